@@ -1,0 +1,205 @@
+"""Benchmark of the GCMe nonbonded hot path on one MI355X.
+
+A step is one pass of the whole path: integrator half-kick/drift/noise, cell
+binning and deterministic sort, excluded-volume pair kernel, smeared-Coulomb
+real-space kernel, B-spline spreading, 3D FFT, Green's-function convolution,
+inverse FFT, force gather and the second half-kick, replayed from a captured
+HIP graph.  Workload: bulk electrolyte, N = 32768 beads at rho = 2.5, 20%
+charged, two species, rc = 3, SPME 64^3 order 5, BAOAB Langevin at dt = 0.02
+(synthetic seeded inputs; see gcme_workloads.config2).
+
+Prints ONE JSON line.  `value` = unordered pairs within the cutoff per step
+x steps per second (pair interactions/s).  ns/day uses tau = 3.18 ps (the
+paper's four-to-one mapping).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+TAU_PS = 3.18
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+# Algorithmic FP operations per unordered pair within the cutoff (both
+# forces by Newton's third law): separation 3, r^2 5, exponent 1, exp 1,
+# prefactor 1, force scale 1, force vector 3, +f_i 3, -f_j 3, energy 1.
+FLOP_PER_GCM_PAIR = 22
+# Charged pair, real-space bracket: separation 3, r^2 5, sqrt 1, 1/r 1, two
+# erfc 2, difference and scale 2, two Gaussians (2 mul + 2 exp) 4, bracket
+# 4, force vector 3, +f_i 3, -f_j 3, z_i z_j lB 2, energy 1.
+FLOP_PER_ELEC_PAIR = 35
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--workload", default="bulk_N32768", choices=["bulk_N32768", "bulk_N2097152"])
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-reps", type=int, default=20)
+    ap.add_argument("--steps-only", action="store_true",
+                    help="only the timed step loop (for profiler runs)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this size and exit (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    if args.copy_calib_mib:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_each_way": n * 4}))
+        return
+
+    import gcme_workloads as W
+    from paper_2403_08148_amd import GCMe, params_from_workload
+
+    w = W.config2() if args.workload == "bulk_N32768" else W.config4()
+    eng = GCMe([w.N], precision=args.precision, seed=12345)
+    eng.set_params(params_from_workload(w))
+    eng.set_state(w.pos, w.type, w.z, w.vel)
+    tuning = eng.tuning() if args.no_autotune else eng.autotune()
+
+    # warm-up (also relaxes the random start a little)
+    eng.step(args.warmup)
+    eng.sync()
+    pairs0 = eng.count_pairs()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    eng.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    eng.sync()
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    pairs1 = eng.count_pairs()
+    pairs = 0.5 * (pairs0 + pairs1)
+    steps_per_s = 1000.0 / ms_step
+    value = pairs * steps_per_s
+    ns_day = steps_per_s * w.dt * TAU_PS * 86400.0 / 1000.0
+    if args.steps_only:
+        print(json.dumps({"ms_per_step": ms_step, "pairs": pairs}))
+        return
+
+    # per-stage device times (HIP events between stages on the engine stream)
+    stages = eng.profile_step(args.profile_reps)
+    eng.sync()
+    nq = int((w.z != 0).sum())
+    obs = eng.step(1, observe=True)
+    eng.sync()
+    E = obs["energy"].cpu().numpy()[0]
+
+    # roofline of the dominant stage
+    dom = max(stages, key=stages.get)
+    t_dom = stages[dom] * 1e-3
+    K = w.grid
+    ngrid = K[0] * K[1] * K[2]
+    nch = K[0] * K[1] * (K[2] // 2 + 1)
+    cs = 16 if args.precision == "fp64" else 8
+    rs = cs // 2
+    peak_alu = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+    alg = {
+        # (bound, algorithmic amount per launch)
+        "pair_gcm": ("alu", FLOP_PER_GCM_PAIR * pairs),
+        "fft_z_r2c": ("hbm", ngrid * 8 + nch * cs),
+        "fft_y": ("hbm", 2 * nch * cs),
+        "fft_x_conv": ("hbm", 2 * nch * cs),
+        "fft_y_inv": ("hbm", 2 * nch * cs),
+        "fft_z_c2r": ("hbm", nch * cs + ngrid * rs),
+        "int_first": ("hbm", w.N * (12 + 24 + 8 + 4 + 4 + 24 + 12 + 24)),
+        "int_last": ("hbm", w.N * (12 + 24 + 4 + 4 + 24 + 12 + 24 + 4 + 4)),
+        "gather": ("hbm", nq * (12 + 4 + 4 + 24)),
+        "spread": ("hbm", nq * (12 + 4)),
+        "sort": ("hbm", w.N * (12 + 4 + 4 + 12 + 24 + 4 + 4)),
+    }
+    bound, amount = alg.get(dom, ("alu", 0.0))
+    if bound == "alu":
+        achieved = amount / t_dom / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak_alu, "unit": "TFLOP/s",
+                "frac": achieved / peak_alu, "traffic": None}
+    else:
+        achieved = amount / t_dom / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    # the excluded-volume pair kernel's own figure is always reported
+    pg = stages["pair_gcm"] * 1e-3
+    gcm_tflops = FLOP_PER_GCM_PAIR * pairs / pg / 1e12
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, pairs)
+
+    out = {
+        "metric": "pair interactions/s (N=32k bulk GCMe, rc=3, SPME 64^3) + ns/day",
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_beads": w.N, "density": 2.5, "charged_fraction": float(nq) / w.N,
+                   "cutoff": w.rc, "beta": w.beta, "pme_grid": list(w.grid), "order": w.order, "dt": w.dt,
+                   "integrator": "BAOAB Langevin", "precision": args.precision, "tuning": tuning},
+        "ns_per_day": ns_day,
+        "steps_per_s": steps_per_s,
+        "pairs_within_cutoff": pairs,
+        "wall_s_timed": wall,
+        "stage_ms": stages,
+        "pair_gcm_tflops": gcm_tflops,
+        "energy_terms_last_step": {k: float(v) for k, v in zip(
+            ["ex", "real", "recip", "corr", "self", "pot", "kin"], E)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    eng.close()
+
+
+def cpu_baseline(w, pairs):
+    """The FP64 oracle (cell-list real space + SPME on the same mesh), one
+    force evaluation of the same workload on the host cores."""
+    from oracle import oracle as O
+    O.build(force=False)
+    p = O.Params(w.box, w.rc, w.beta, w.lB, w.A, w.sigma, w.a)
+    t0 = time.perf_counter()
+    O.forces(w.pos, w.type, w.z, p, recip_mode=O.RECIP_SPME, K=w.grid, order=w.order)
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pair interactions/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"one full force/energy evaluation of {w.name} ({w.N} beads), {dt:.2f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * gcme.h -- C ABI of the MI355X (gfx950) engine for the GCMe nonbonded path:
+ * Gaussian-core excluded volume plus Gaussian-smeared electrostatics with an
+ * Ewald split (cell list -> cutoff pair kernels -> smooth PME).
+ *
+ * Model (reduced units, k_B T = 1; lengths in the bead diameter):
+ *   u_ex(r)   = A_ij (3/(2 pi s_ij^2))^{3/2} exp(-3 r^2/(2 s_ij^2)),
+ *               s_ij^2 = sigma_i^2 + sigma_j^2            (eq. u_ex)
+ *   u_elec(r) = lB z_i z_j erf(sqrt(pi/2) r / a_ij) / r,
+ *               a_ij^2 = a_i^2 + a_j^2                     (eq. u_elec)
+ *   U_elec    = U_real + U_recip + U_corr + U_self         (eq. ewald)
+ *     U_real  = lB sum_{i<j, r<rc} z_i z_j [erf(alpha_ij r) - erf(beta r)]/r,
+ *               alpha_ij = sqrt(pi/2)/a_ij, beta = 1/(sqrt(2) G)
+ *     U_recip = (2 pi lB/V) sum_{k!=0} exp(-k^2/(4 beta^2))/k^2 |S(k)|^2,
+ *               evaluated by smooth particle-mesh Ewald (order p B-splines
+ *               on a K0 x K1 x K2 mesh, tin-foil boundary: k = 0 dropped)
+ *     U_corr  = -lB beta/sqrt(pi) sum z_i^2,  U_self = lB/2 sum z_i^2/a_i
+ *   Forces F_i = -dE/dr_i.  Virial W_ab = sum_pairs r_ij,a f_ij,b plus the
+ *   reciprocal-space tensor (its trace enters eq. pres_virial).
+ *
+ * Conventions for every call:
+ *   - Arrays marked "device" are HIP device pointers on the context's device;
+ *     the caller owns them, the library never frees or keeps them past the
+ *     call.  Arrays marked "host" are read during the call only.
+ *   - Per-bead arrays are replica-concatenated in n_beads order, original
+ *     bead order within a replica.  Coordinates are SoA: [3][N_total]
+ *     (all x, then all y, then all z), float64.
+ *   - Device work is enqueued on the context's stream; outputs are valid
+ *     once that stream has reached the call's end (gcme_sync waits for it).
+ *   - Every call returns a gcme_status.  Validation errors leave all outputs
+ *     and the context unchanged; gcme_last_error() gives a message.
+ *     GCME_EDEVICE means the context is unusable and must be destroyed.
+ *   - One context per host thread; calls on one context are not reentrant.
+ */
+#ifndef GCME_H
+#define GCME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gcme_ctx* gcme_handle;
+
+typedef enum {
+    GCME_OK = 0,
+    GCME_EINVAL = 1,        /* bad argument (NULL, size, range) */
+    GCME_EUNSUPPORTED = 2,  /* grid not 2^a 3^b, order outside 3..8, too many types */
+    GCME_EGEOMETRY = 3,     /* cutoff > L/2, non-positive box */
+    GCME_ENONNEUTRAL = 4,   /* a replica's net charge is not zero */
+    GCME_ESTATE = 5,        /* call order (e.g. forces before params/state) */
+    GCME_EDEVICE = 6,       /* HIP runtime error */
+    GCME_ENOMEM = 7,        /* device allocation failed */
+    GCME_EOVERFLOW = 8      /* fixed-point force/charge accumulator would overflow */
+} gcme_status;
+
+typedef enum {
+    GCME_FP64 = 0,  /* all pair, mesh and FFT arithmetic in float64 */
+    GCME_MIXED = 1  /* pair + mesh + FFT in float32; forces summed in 64-bit
+                       fixed point; energies and virial reduced in float64 */
+} gcme_precision;
+
+/* Energy terms, per replica, in this order (kT units). */
+enum {
+    GCME_E_EX = 0,      /* sum of u_ex over pairs within the cutoff */
+    GCME_E_REAL = 1,    /* U_elec,real */
+    GCME_E_RECIP = 2,   /* U_elec,recip (mesh) */
+    GCME_E_CORR = 3,    /* U_elec,corr (constant) */
+    GCME_E_SELF = 4,    /* U_elec,self (Born, constant) */
+    GCME_E_POT = 5,     /* sum of the five terms above */
+    GCME_E_KIN = 6,     /* kinetic energy (gcme_step observations only, else 0) */
+    GCME_N_TERMS = 7
+};
+
+#define GCME_MAX_TYPES 4
+
+typedef struct {
+    int32_t n_replicas;       /* >= 1 independent periodic boxes */
+    const int32_t* n_beads;   /* host [n_replicas], each >= 2 */
+    int32_t precision;        /* gcme_precision */
+    int32_t device;           /* HIP device ordinal */
+    void* stream;             /* hipStream_t to enqueue on; NULL = a stream the
+                                 library creates and owns */
+    uint64_t seed;            /* Langevin noise seed */
+} gcme_create_info;
+
+typedef struct {
+    double box[3];            /* orthorhombic box edges L0, L1, L2 (> 0) */
+    double cutoff;            /* real-space cutoff rc, rc <= min(L)/2 */
+    double beta;              /* Ewald splitting (erf(beta r)); beta = 1/(sqrt2 G) */
+    int32_t grid[3];          /* mesh K0, K1, K2: each 2^a 3^b, 8 <= K <= 512 */
+    int32_t order;            /* B-spline order p, 3..8, p <= K/2 */
+    double lB;                /* Bjerrum length */
+    int32_t n_types;          /* 1..GCME_MAX_TYPES */
+    const double* A;          /* host [n_types * n_types], symmetric, kT d^3 */
+    const double* sigma;      /* host [n_types] mass smearing radius (> 0) */
+    const double* a;          /* host [n_types] charge smearing radius (> 0) */
+    const double* mass;       /* host [n_types] or NULL (all 1) */
+    double kT;                /* thermostat temperature */
+    double dt;                /* time step */
+    double gamma;             /* Langevin friction; 0 = velocity Verlet (NVE) */
+    uint32_t flags;           /* GCME_FLAG_* */
+} gcme_params;
+
+/* Reject parameters that violate the paper's no-collapse condition
+ * A_ij/(s_ij^3 kT) > 4 pi^{3/2} lB/(3^{3/2} a_ij) for some type pair
+ * (Model and methods, after eq. u_elec).  Without the flag it is not checked. */
+#define GCME_FLAG_STRICT_CONTACT 1u
+
+typedef struct {
+    const double* pos;   /* device [3][N_total] new positions, or NULL = keep state */
+    double* force;       /* device [3][N_total] out, or NULL */
+    double* energy;      /* device [n_replicas][GCME_N_TERMS] out, or NULL */
+    double* virial;      /* device [n_replicas][6] out (xx,yy,zz,xy,xz,yz), or NULL */
+    double* dE_dA;       /* device [n_replicas][MAX_TYPES*MAX_TYPES] out, or NULL:
+                            entry (t,u) = dE/dA_tu of the symmetric parameter */
+    double* dE_dsigma;   /* device [n_replicas][MAX_TYPES] out, or NULL */
+    double* dE_da;       /* device [n_replicas][MAX_TYPES] out, or NULL */
+} gcme_io;
+
+/* Create a context: allocates every device buffer whose size depends only on
+ * bead counts.  *out is set only on GCME_OK. */
+gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out);
+
+/* Set force-field, mesh and integrator parameters of one replica
+ * (replica = -1: all).  Validates geometry and sizes, builds the cell grid,
+ * mesh plans, B-spline moduli and pair tables, and (re)allocates mesh and
+ * cell buffers.  Synchronous with respect to the context's stream. */
+gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p);
+
+/* Load the dynamic state: positions (device [3][N] float64, any real
+ * coordinates; wrapped into the box), velocities (device [3][N] float64 or
+ * NULL = zero), types (device int32 [N], 0..n_types-1) and charge numbers
+ * (device int32 [N], |z| <= 127).  Checks types, and that every replica is
+ * neutral.  Resets the step counter.  Synchronous. */
+gcme_status gcme_set_state(gcme_handle h, const double* pos, const double* vel,
+                           const int32_t* type, const int32_t* z);
+
+/* Copy the state out in original bead order: positions wrapped into
+ * [0, L) (device [3][N] or NULL), velocities (device [3][N] or NULL), and the
+ * number of steps taken since gcme_set_state (host, or NULL). */
+gcme_status gcme_get_state(gcme_handle h, double* pos, double* vel, uint64_t* step);
+
+/* One force/energy evaluation (paper: eqs. u_ex, u_elec, ewald) at the
+ * state's positions, or at io->pos (which then become the state).
+ * Asynchronous on the context's stream. */
+gcme_status gcme_forces_energy(gcme_handle h, const gcme_io* io);
+
+/* Advance n_steps >= 0 (velocity Verlet if gamma == 0, else BAOAB Langevin
+ * with Philox4x64-10 noise keyed by (seed, step, bead id, replica)).  If
+ * observe != NULL its outputs are filled at the final positions (energy
+ * includes GCME_E_KIN).  Steps are replayed from a captured HIP graph.
+ * Asynchronous. */
+gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe);
+
+/* Wait for the context's stream and report device-side status (accumulator
+ * overflow -> GCME_EOVERFLOW, runtime errors -> GCME_EDEVICE). */
+gcme_status gcme_sync(gcme_handle h);
+
+/* Message describing the last error on h (or on creation if h is NULL).
+ * Valid until the next call on h. */
+const char* gcme_last_error(gcme_handle h);
+
+/* Tuning knobs picked by the autotuner (exposed for benchmarks and tests).
+ * Any field < 0 means "leave as is". */
+typedef struct {
+    int32_t cells_per_cutoff;  /* cell edge ~ rc / n (1..4) */
+    int32_t lanes_per_bead;    /* lanes sharing one bead's neighbour scan (1,2,4,8,16) */
+    int32_t lanes_per_charge;  /* same, for the charged-pair kernel */
+} gcme_tuning;
+
+gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t);
+gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t);
+
+/* Time candidate tunings on the current state and keep the fastest.
+ * Tunings change the order of the per-bead floating-point sums, so results
+ * agree across tunings to rounding; for one tuning, reruns on the same
+ * inputs are bit-identical.  Synchronous. */
+gcme_status gcme_autotune(gcme_handle h);
+
+/* Number of unordered pairs with r < rc (all replicas), counted by the pair
+ * kernel's own cutoff test at the state's positions.  Synchronous. */
+gcme_status gcme_count_pairs(gcme_handle h, uint64_t* n_pairs);
+
+/* Device time of each stage of one step, measured with HIP events recorded
+ * between the stages on the context's stream while n_reps >= 1 steps run
+ * eagerly (not from the graph); ms[i] is the mean over the steps (host array
+ * of at least GCME_N_STAGES entries).  Advances the state by n_reps steps.
+ * Synchronous.  gcme_stage_name(i) names stage i (NULL if out of range). */
+#define GCME_N_STAGES 12
+gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms);
+const char* gcme_stage_name(int32_t i);
+
+/* Release all device memory and the owned stream. */
+void gcme_destroy(gcme_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCME_H */

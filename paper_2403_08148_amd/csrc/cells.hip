@@ -1,0 +1,262 @@
+// Cell list: wrap into fixed point, bin, scan, scatter and a deterministic
+// permutation of the state into (cell, previous order) order.
+//
+// Positions are stored as 32-bit fractions of the box edge (u = x/L * 2^32),
+// so the minimum-image separation of two beads is the wrapped 32-bit
+// difference, and drift never leaves the box.  Beads of one cell are kept in
+// their previous relative order (a stable counting sort), which makes every
+// later sum over neighbours run in the same order on every rerun.
+#include "gcme_internal.h"
+
+namespace gcme {
+
+namespace {
+
+__global__ void k_ingest(const double* __restrict__ pos, long long ld, int N, const RepDesc* __restrict__ rep,
+                         StateView A, long long* F0, long long* F1, long long* F2, int nF) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nF) {
+    F0[s] = 0;
+    F1[s] = 0;
+    F2[s] = 0;
+  }
+  if (s >= N) return;
+  int id = A.id[s];
+  const RepDesc& R = rep[param_rep(A.param[s])];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double f = pos[k * ld + id] / R.L[k];
+    f -= floor(f);
+    // round to the nearest 2^-32 fraction; 2^32 wraps to 0
+    unsigned long long u = (unsigned long long)llrint(f * 4294967296.0);
+    A.pos[k][s] = (uint32_t)u;
+  }
+}
+
+template <typename I>
+__global__ void k_fill(I* p, I v, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__device__ inline int cell_of(const RepDesc& R, uint32_t ux, uint32_t uy, uint32_t uz) {
+  int cx = (int)(((unsigned long long)ux * (unsigned)R.nc[0]) >> 32);
+  int cy = (int)(((unsigned long long)uy * (unsigned)R.nc[1]) >> 32);
+  int cz = (int)(((unsigned long long)uz * (unsigned)R.nc[2]) >> 32);
+  return R.cell_off + (cx * R.nc[1] + cy) * R.nc[2] + cz;
+}
+
+__global__ void k_bin(StateView A, const RepDesc* __restrict__ rep, CellView c, int N) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  uint32_t p = A.param[s];
+  const RepDesc& R = rep[param_rep(p)];
+  int cid = cell_of(R, A.pos[0][s], A.pos[1][s], A.pos[2][s]);
+  c.cell[s] = cid;
+  atomicAdd(&c.counts[cid], 1);
+  if (param_z(p) != 0) atomicAdd(&c.qcounts[cid], 1);
+}
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_PER_THREAD = 4;
+constexpr int SCAN_BLOCK = SCAN_THREADS * SCAN_PER_THREAD;
+
+// Inclusive scan of one int per thread over a 256-thread block.
+__device__ inline int block_inclusive_scan(int v, int* sh) {
+  int lane = threadIdx.x & 63;
+  int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  if (lane == 63) sh[wid] = v;
+  __syncthreads();
+  int add = 0;
+  for (int w = 0; w < wid; ++w) add += sh[w];
+  __syncthreads();
+  return v + add;
+}
+
+__global__ void k_scan_reduce(CellView c, int nb) {
+  __shared__ int sh[8];
+  int b = blockIdx.x;
+  int base = b * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
+  int s0 = 0, s1 = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+    int i = base + k;
+    if (i < c.ncells) {
+      s0 += c.counts[i];
+      s1 += c.qcounts[i];
+    }
+  }
+  int t0 = block_inclusive_scan(s0, sh);
+  int t1 = block_inclusive_scan(s1, sh);
+  if (threadIdx.x == SCAN_THREADS - 1) {
+    c.bsum[b] = t0;
+    c.bsum[nb + b] = t1;
+  }
+}
+
+// One block: exclusive scan of the block sums (both arrays).
+__global__ void k_scan_top(CellView c, int nb) {
+  __shared__ int sh[8];
+  for (int arr = 0; arr < 2; ++arr) {
+    int* bs = c.bsum + arr * nb;
+    int carry = 0;
+    for (int base = 0; base < nb; base += SCAN_THREADS) {
+      int i = base + threadIdx.x;
+      int v = i < nb ? bs[i] : 0;
+      int inc = block_inclusive_scan(v, sh);
+      if (i < nb) bs[i] = carry + inc - v;
+      __shared__ int tot;
+      if (threadIdx.x == SCAN_THREADS - 1) tot = inc;
+      __syncthreads();
+      carry += tot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      int* st = arr == 0 ? c.start : c.qstart;
+      st[c.ncells] = carry;
+    }
+  }
+}
+
+__global__ void k_scan_apply(CellView c, int nb) {
+  __shared__ int sh[8];
+  int b = blockIdx.x;
+  int base = b * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
+  for (int arr = 0; arr < 2; ++arr) {
+    const int* cnt = arr == 0 ? c.counts : c.qcounts;
+    int* st = arr == 0 ? c.start : c.qstart;
+    int v[SCAN_PER_THREAD];
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+      int i = base + k;
+      v[k] = i < c.ncells ? cnt[i] : 0;
+      tot += v[k];
+    }
+    int inc = block_inclusive_scan(tot, sh);
+    int run = c.bsum[arr * nb + b] + inc - tot;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+      int i = base + k;
+      if (i < c.ncells) st[i] = run;
+      run += v[k];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_scatter(CellView c, int N) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  int cid = c.cell[s];
+  int slot = atomicAdd(&c.fill[cid], 1);
+  c.tmp[c.start[cid] + slot] = s;
+}
+
+// Position p of the scattered array holds bead s of cell c in arbitrary
+// order; its final slot is start[c] + (number of beads of c with a smaller
+// previous index).  Charged beads get the same rank among charged beads.
+__global__ void k_permute(StateView A, StateView B, CellView c, ChargedView q, int N) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  int s = c.tmp[p];
+  int cid = c.cell[s];
+  int lo = c.start[cid], hi = c.start[cid + 1];
+  uint32_t prm = A.param[s];
+  bool charged = param_z(prm) != 0;
+  int rank = 0, qrank = 0;
+  for (int t = lo; t < hi; ++t) {
+    int o = c.tmp[t];
+    if (o < s) {
+      ++rank;
+      if (charged && param_z(A.param[o]) != 0) ++qrank;
+    }
+  }
+  int n = lo + rank;
+  uint32_t px = A.pos[0][s], py = A.pos[1][s], pz = A.pos[2][s];
+  B.pos[0][n] = px;
+  B.pos[1][n] = py;
+  B.pos[2][n] = pz;
+  B.vel[0][n] = A.vel[0][s];
+  B.vel[1][n] = A.vel[1][s];
+  B.vel[2][n] = A.vel[2][s];
+  B.param[n] = prm;
+  B.id[n] = A.id[s];
+  if (charged) {
+    int qn = c.qstart[cid] + qrank;
+    q.pos[0][qn] = px;
+    q.pos[1][qn] = py;
+    q.pos[2][qn] = pz;
+    q.param[qn] = prm;
+    q.idx[qn] = n;
+  }
+}
+
+__global__ void k_commit(StateView B, StateView A, int N) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A.pos[k][s] = B.pos[k][s];
+    A.vel[k][s] = B.vel[k][s];
+  }
+  A.param[s] = B.param[s];
+  A.id[s] = B.id[s];
+}
+
+inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_ingest(hipStream_t s, const double* pos_soa, int N, long long ld, const RepDesc* rep,
+                   const uint32_t* param, StateView A, long long* F, int nF) {
+  (void)param;
+  int n = N > nF ? N : nF;
+  hipLaunchKernelGGL(k_ingest, dim3(nblk(n, 256)), dim3(256), 0, s, pos_soa, ld, N, rep, A, F, F + nF,
+                     F + 2LL * nF, nF);
+}
+
+void launch_fill_i32(hipStream_t s, int* p, int v, long long n) {
+  if (n <= 0) return;
+  int b = nblk(n, 256);
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_fill<int>, dim3(b), dim3(256), 0, s, p, v, n);
+}
+
+void launch_fill_i64(hipStream_t s, long long* p, long long v, long long n) {
+  if (n <= 0) return;
+  int b = nblk(n, 256);
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_fill<long long>, dim3(b), dim3(256), 0, s, p, v, n);
+}
+
+void launch_bin(hipStream_t s, StateView A, const RepDesc* rep, CellView c, int N) {
+  hipLaunchKernelGGL(k_bin, dim3(nblk(N, 256)), dim3(256), 0, s, A, rep, c, N);
+}
+
+void launch_scan(hipStream_t s, CellView c) {
+  int nb = nblk(c.ncells, SCAN_BLOCK);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, c, nb);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, c, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_THREADS), 0, s, c, nb);
+}
+
+void launch_scatter(hipStream_t s, CellView c, int N) {
+  hipLaunchKernelGGL(k_scatter, dim3(nblk(N, 256)), dim3(256), 0, s, c, N);
+}
+
+void launch_permute(hipStream_t s, StateView A, StateView B, CellView c, ChargedView q, int N) {
+  hipLaunchKernelGGL(k_permute, dim3(nblk(N, 256)), dim3(256), 0, s, A, B, c, q, N);
+}
+
+void launch_commit(hipStream_t s, StateView B, StateView A, int N) {
+  hipLaunchKernelGGL(k_commit, dim3(nblk(N, 256)), dim3(256), 0, s, B, A, N);
+}
+
+}  // namespace gcme

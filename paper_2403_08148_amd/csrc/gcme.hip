@@ -1,0 +1,1232 @@
+// Host side of the GCMe engine: C ABI, validation, device buffers, mesh and
+// cell plans, per-type-pair tables, hipGraph-captured steps and the
+// autotuner.  All arithmetic of the method runs in the kernels of cells.hip,
+// pair.hip, pme.hip and integrate.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gcme.h"
+#include "gcme_internal.h"
+
+using namespace gcme;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (n == 0) n = 64;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+struct HostRep {
+  bool set = false;
+  double box[3] = {0, 0, 0};
+  double rc = 0, beta = 0, lB = 0, kT = 0, dt = 0, gamma = 0;
+  int K[3] = {0, 0, 0};
+  int order = 0;
+  int nt = 0;
+  double A[MAXT * MAXT] = {};
+  double sigma[MAXT] = {};
+  double a[MAXT] = {};
+  double mass[MAXT] = {1, 1, 1, 1};
+  uint32_t flags = 0;
+};
+
+bool smooth(int k) {
+  if (k < 1) return false;
+  while (k % 2 == 0) k /= 2;
+  while (k % 3 == 0) k /= 3;
+  return k == 1;
+}
+
+std::vector<int> radices(int K) {
+  std::vector<int> r;
+  while (K % 4 == 0) {
+    r.push_back(4);
+    K /= 4;
+  }
+  while (K % 2 == 0) {
+    r.push_back(2);
+    K /= 2;
+  }
+  while (K % 3 == 0) {
+    r.push_back(3);
+    K /= 3;
+  }
+  return r;
+}
+
+// Cardinal B-spline M_n(x) on [0, n] (host, for the mesh moduli).
+double bspl(int n, double x) {
+  if (x < 0.0 || x >= (double)n) return 0.0;
+  if (n == 1) return 1.0;
+  return (x * bspl(n - 1, x) + ((double)n - x) * bspl(n - 1, x - 1.0)) / (double)(n - 1);
+}
+
+}  // namespace
+
+struct gcme_ctx {
+  std::string err;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipStream_t cap_stream = nullptr;
+  int R = 0;
+  std::vector<int> nb, boff;
+  int N = 0;
+  bool fp64 = false;
+  uint64_t seed = 0;
+  std::vector<HostRep> hp;
+  // state
+  bool have_state = false;
+  bool forces_valid = false;
+  uint64_t step = 0;
+  std::vector<int> h_type, h_z;
+  std::vector<int> nq, qoff;
+  int NQ = 0;
+  // tuning
+  gcme_tuning tune{2, 4, 4};
+  bool plan_dirty = true;
+  // device buffers
+  DevBuf a_pos[3], a_vel[3], a_param, a_id;
+  DevBuf b_pos[3], b_vel[3], b_param, b_id;
+  DevBuf cell, tmp, counts, qcounts, fill, start, qstart, bsum;
+  DevBuf q_pos[3], q_param, q_idx;
+  DevBuf F;
+  DevBuf Qint, Qc, phi;
+  DevBuf d_rep, d_gcm, d_elec, d_adj;
+  DevBuf d_tw, d_rad, d_bsp, d_freq;
+  DevBuf d_items[3];
+  DevBuf d_tiles_g, d_tiles_q, d_tiles_256;
+  DevBuf part[N_SLOTS], adjp[2];
+  DevBuf d_off[N_SLOTS], d_adj_off[2];
+  DevBuf d_consts, d_Avals, d_dself;
+  DevBuf d_imass, d_c1, d_c2s, d_dt, d_lang;
+  DevBuf d_status, d_step, d_pairs;
+  // plan sizes
+  int ncells = 0;
+  long long grid_total = 0, cgrid_total = 0;
+  int ntiles_g = 0, ntiles_q = 0, ntiles_256 = 0;
+  int nitems[3] = {0, 0, 0};
+  int lb[3] = {0, 0, 0};
+  int maxK[3] = {0, 0, 0};
+  int order = 5;
+  std::vector<RepDesc> rep;
+  // graphs
+  hipGraphExec_t g_plain = nullptr, g_obs = nullptr;
+
+  ~gcme_ctx() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+  void drop_graphs() {
+    if (g_plain) (void)hipGraphExecDestroy(g_plain);
+    if (g_obs) (void)hipGraphExecDestroy(g_obs);
+    g_plain = g_obs = nullptr;
+  }
+  double fscale() const { return std::ldexp(1.0, fp64 ? FSHIFT_FP64 : FSHIFT_MIXED); }
+  double qscale() const { return std::ldexp(1.0, fp64 ? FSHIFT_FP64 : FSHIFT_MIXED); }
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+gcme_status fail(gcme_handle h, gcme_status s, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_create_err = msg;
+  return s;
+}
+
+#define HIPCHK(h, expr)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail(h, e_ == hipErrorOutOfMemory ? GCME_ENOMEM : GCME_EDEVICE,                     \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                            \
+  } while (0)
+
+StateView view(DevBuf* pos, DevBuf* vel, DevBuf& param, DevBuf& id) {
+  StateView v;
+  for (int k = 0; k < 3; ++k) {
+    v.pos[k] = pos[k].as<uint32_t>();
+    v.vel[k] = vel[k].as<double>();
+  }
+  v.param = param.as<uint32_t>();
+  v.id = id.as<int>();
+  return v;
+}
+
+StateView viewA(gcme_handle h) { return view(h->a_pos, h->a_vel, h->a_param, h->a_id); }
+StateView viewB(gcme_handle h) { return view(h->b_pos, h->b_vel, h->b_param, h->b_id); }
+
+CellView cview(gcme_handle h) {
+  CellView c;
+  c.cell = h->cell.as<int>();
+  c.tmp = h->tmp.as<int>();
+  c.counts = h->counts.as<int>();
+  c.qcounts = h->qcounts.as<int>();
+  c.fill = h->fill.as<int>();
+  c.start = h->start.as<int>();
+  c.qstart = h->qstart.as<int>();
+  c.bsum = h->bsum.as<int>();
+  c.ncells = h->ncells;
+  return c;
+}
+
+ChargedView qview(gcme_handle h) {
+  ChargedView q;
+  for (int k = 0; k < 3; ++k) q.pos[k] = h->q_pos[k].as<uint32_t>();
+  q.param = h->q_param.as<uint32_t>();
+  q.idx = h->q_idx.as<int>();
+  return q;
+}
+
+long long* Fk(gcme_handle h, int k) { return h->F.as<long long>() + (size_t)k * h->N; }
+
+template <typename T>
+void upload(std::vector<T>& v, DevBuf& b, hipStream_t s) {
+  (void)b.alloc(v.size() * sizeof(T));
+  (void)hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+std::vector<Tile> make_tiles(const std::vector<int>& off, const std::vector<int>& cnt, int per,
+                             std::vector<int>& tile_off) {
+  std::vector<Tile> t;
+  tile_off.assign(off.size() + 1, 0);
+  for (size_t r = 0; r < off.size(); ++r) {
+    tile_off[r] = (int)t.size();
+    for (int f = 0; f < cnt[r]; f += per) t.push_back(Tile{(int)r, off[r] + f, std::min(per, cnt[r] - f), 0});
+  }
+  tile_off[off.size()] = (int)t.size();
+  return t;
+}
+
+// Series coefficients of phi(r) = [erf(alpha r) - erf(beta r)]/r and
+// g(r) = -(1/r) dphi/dr in powers of r^2, from the Maclaurin series of erf.
+// alpha^k - beta^k is formed as (alpha - beta) sum alpha^i beta^(k-1-i) so
+// that nearly equal alpha and beta lose no digits.
+void erf_series(double al, double be, double* cphi, double* cg) {
+  const double tsp = 2.0 / std::sqrt(M_PI);
+  auto D = [&](int k) {
+    double s = 0;
+    for (int i = 0; i < k; ++i) s += std::pow(al, i) * std::pow(be, k - 1 - i);
+    return (al - be) * s;
+  };
+  double fact = 1.0;  // n!
+  for (int n = 0; n < NSER; ++n) {
+    if (n > 0) fact *= n;
+    double sgn = (n % 2 == 0) ? 1.0 : -1.0;
+    cphi[n] = tsp * sgn * D(2 * n + 1) / (fact * (2 * n + 1));
+    // g: sum_m (-1)^m D(2m+3) 2(m+1) r^{2m} / ((m+1)! (2m+3))
+    cg[n] = tsp * sgn * D(2 * n + 3) * 2.0 * (n + 1) / (fact * (n + 1) * (2 * n + 3));
+  }
+}
+
+template <typename T>
+void build_tables(gcme_handle h, std::vector<GcmPar<T>>& g, std::vector<ElecPar<T>>& e, std::vector<AdjPar<T>>& ad) {
+  const int R = h->R;
+  g.assign((size_t)R * MAXT * MAXT, GcmPar<T>{});
+  e.assign((size_t)R * MAXT * MAXT, ElecPar<T>{});
+  ad.assign((size_t)R * MAXT * MAXT, AdjPar<T>{});
+  const double log2e = 1.4426950408889634;
+  for (int r = 0; r < R; ++r) {
+    const HostRep& p = h->hp[r];
+    for (int t = 0; t < p.nt; ++t)
+      for (int u = 0; u < p.nt; ++u) {
+        size_t q = ((size_t)r * MAXT + t) * MAXT + u;
+        double s2 = p.sigma[t] * p.sigma[t] + p.sigma[u] * p.sigma[u];
+        double b = 3.0 / (2.0 * s2);
+        g[q].C = (T)(p.A[t * p.nt + u] * std::pow(3.0 / (2.0 * M_PI * s2), 1.5));
+        g[q].bl = (T)(b * log2e);
+        g[q].twob = (T)(2.0 * b);
+        double aij = std::sqrt(p.a[t] * p.a[t] + p.a[u] * p.a[u]);
+        double al = std::sqrt(M_PI / 2.0) / aij;
+        e[q].alpha = (T)al;
+        e[q].alpha2 = (T)(al * al);
+        double rs = 0.5 / al;
+        e[q].rs2 = (T)(rs * rs);
+        double cp[NSER], cgv[NSER];
+        erf_series(al, p.beta, cp, cgv);
+        for (int n = 0; n < NSER; ++n) {
+          e[q].cphi[n] = (T)cp[n];
+          e[q].cg[n] = (T)cgv[n];
+        }
+        double s = std::sqrt(s2);
+        ad[q].inv_s2 = (T)(1.0 / s2);
+        ad[q].s_inv = (T)(1.0 / s);
+        ad[q].dsig_i = (T)(p.sigma[t] / s);
+        ad[q].dsig_j = (T)(p.sigma[u] / s);
+        ad[q].daij_i = (T)(p.a[t] / aij);
+        ad[q].daij_j = (T)(p.a[u] / aij);
+        ad[q].ea = (T)(2.0 / std::sqrt(M_PI) * al / aij);
+      }
+  }
+}
+
+template <typename T>
+void build_mesh_tables(gcme_handle h, std::vector<T>& tw, std::vector<T>& bsp, std::vector<T>& frq,
+                       std::vector<int>& rad) {
+  std::map<int, std::pair<int, int>> kmap;  // K -> (tw offset in complex entries, rad offset)
+  tw.clear();
+  bsp.clear();
+  frq.clear();
+  rad.clear();
+  for (int r = 0; r < h->R; ++r) {
+    RepDesc& d = h->rep[r];
+    const HostRep& p = h->hp[r];
+    for (int ax = 0; ax < 3; ++ax) {
+      int K = p.K[ax];
+      auto it = kmap.find(K);
+      if (it == kmap.end()) {
+        int to = (int)(tw.size() / 2);
+        for (int e = 0; e < K; ++e) {
+          double ang = -2.0 * M_PI * (double)e / (double)K;
+          tw.push_back((T)std::cos(ang));
+          tw.push_back((T)std::sin(ang));
+        }
+        int ro = (int)rad.size();
+        for (int x : radices(K)) rad.push_back(x);
+        it = kmap.emplace(K, std::make_pair(to, ro)).first;
+      }
+      d.tw_off[ax] = it->second.first;
+      d.rad_off[ax] = it->second.second;
+      d.nrad[ax] = (int)radices(K).size();
+      // 1/|b(m)|^2 with the odd-order Nyquist zero replaced by the mean of
+      // its neighbours, and the signed frequency m/L
+      std::vector<double> mod(K);
+      for (int m = 0; m < K; ++m) {
+        double re = 0, im = 0;
+        for (int k = 0; k <= p.order - 2; ++k) {
+          double w = bspl(p.order, (double)(k + 1));
+          double ang = 2.0 * M_PI * (double)m * (double)k / (double)K;
+          re += w * std::cos(ang);
+          im += w * std::sin(ang);
+        }
+        mod[m] = re * re + im * im;
+      }
+      for (int m = 0; m < K; ++m)
+        if (mod[m] < 1e-7) mod[m] = 0.5 * (mod[(m - 1 + K) % K] + mod[(m + 1) % K]);
+      d.bsp_off[ax] = (int)bsp.size();
+      for (int m = 0; m < K; ++m) {
+        bsp.push_back((T)(1.0 / mod[m]));
+        int ms = m <= K / 2 ? m : m - K;
+        frq.push_back((T)((double)ms / p.box[ax]));
+      }
+    }
+  }
+}
+
+gcme_status build_plan(gcme_handle h) {
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->drop_graphs();
+  const int R = h->R;
+  h->rep.assign(R, RepDesc{});
+  int cell_off = 0;
+  long long goff = 0, cgoff = 0;
+  h->order = h->hp[0].order;
+  for (int ax = 0; ax < 3; ++ax) h->maxK[ax] = 0;
+  for (int r = 0; r < R; ++r) {
+    const HostRep& p = h->hp[r];
+    RepDesc& d = h->rep[r];
+    for (int k = 0; k < 3; ++k) {
+      d.L[k] = p.box[k];
+      d.scaled[k] = p.box[k] / 4294967296.0;
+      d.scalef[k] = (float)d.scaled[k];
+      int nc = (int)std::floor(p.box[k] * h->tune.cells_per_cutoff / p.rc);
+      nc = std::max(1, std::min(nc, 1024));
+      d.nc[k] = nc;
+      double hcell = p.box[k] / nc;
+      d.hf[k] = (float)hcell;
+      int reach = (int)std::ceil(p.rc / hcell - 1e-9);
+      d.reach[k] = (2 * reach + 1 > nc) ? -1 : reach;
+      d.K[k] = p.K[k];
+    }
+    d.V = p.box[0] * p.box[1] * p.box[2];
+    d.rc = p.rc;
+    d.rc2 = p.rc * p.rc;
+    d.rc2f = (float)d.rc2;
+    d.beta = p.beta;
+    d.betaf = (float)p.beta;
+    d.lB = p.lB;
+    d.lBf = (float)p.lB;
+    d.cell_off = cell_off;
+    cell_off += d.nc[0] * d.nc[1] * d.nc[2];
+    d.bead_off = h->boff[r];
+    d.n = h->nb[r];
+    d.q_off = h->qoff[r];
+    d.nq = h->nq[r];
+    d.K2h = p.K[2] / 2 + 1;
+    d.grid_off = goff;
+    d.cgrid_off = cgoff;
+    goff += (long long)p.K[0] * p.K[1] * p.K[2];
+    cgoff += (long long)p.K[0] * p.K[1] * d.K2h;
+    d.order = p.order;
+    d.nt = p.nt;
+    h->maxK[0] = std::max(h->maxK[0], p.K[2]);  // z pass line length
+    h->maxK[1] = std::max(h->maxK[1], p.K[1]);
+    h->maxK[2] = std::max(h->maxK[2], p.K[0]);
+  }
+  h->ncells = cell_off;
+  h->grid_total = goff;
+  h->cgrid_total = cgoff;
+
+  const size_t cs = h->fp64 ? 16 : 8, rs = h->fp64 ? 8 : 4;
+  // lines per mesh work item: two LDS buffers of LB+1 padded lines stay
+  // below 64 KiB together with the kernels' static reduction buffer
+  const int cap = h->fp64 ? 2048 : 4096;
+  for (int ps = 0; ps < 3; ++ps) h->lb[ps] = std::max(1, std::min(64, cap / h->maxK[ps] - 2));
+
+  // mesh tables
+  std::vector<int> rad;
+  if (h->fp64) {
+    std::vector<double> tw, bsp, frq;
+    build_mesh_tables<double>(h, tw, bsp, frq, rad);
+    upload(tw, h->d_tw, s);
+    upload(bsp, h->d_bsp, s);
+    upload(frq, h->d_freq, s);
+    std::vector<GcmPar<double>> g;
+    std::vector<ElecPar<double>> e;
+    std::vector<AdjPar<double>> ad;
+    build_tables<double>(h, g, e, ad);
+    upload(g, h->d_gcm, s);
+    upload(e, h->d_elec, s);
+    upload(ad, h->d_adj, s);
+    HIPCHK(h, hipStreamSynchronize(s));
+  } else {
+    std::vector<float> tw, bsp, frq;
+    build_mesh_tables<float>(h, tw, bsp, frq, rad);
+    upload(tw, h->d_tw, s);
+    upload(bsp, h->d_bsp, s);
+    upload(frq, h->d_freq, s);
+    std::vector<GcmPar<float>> g;
+    std::vector<ElecPar<float>> e;
+    std::vector<AdjPar<float>> ad;
+    build_tables<float>(h, g, e, ad);
+    upload(g, h->d_gcm, s);
+    upload(e, h->d_elec, s);
+    upload(ad, h->d_adj, s);
+    HIPCHK(h, hipStreamSynchronize(s));
+  }
+  upload(rad, h->d_rad, s);
+
+  // mesh line work items
+  std::vector<LineItem> items[3];
+  std::vector<int> item_off(R + 1, 0);
+  for (int r = 0; r < R; ++r) {
+    const RepDesc& d = h->rep[r];
+    int nlz = d.K[0] * d.K[1];
+    for (int l = 0; l < nlz; l += h->lb[0]) items[0].push_back(LineItem{r, l, std::min(h->lb[0], nlz - l), 0});
+    for (int x = 0; x < d.K[0]; ++x)
+      for (int kz = 0; kz < d.K2h; kz += h->lb[1])
+        items[1].push_back(LineItem{r, x * d.K2h + kz, std::min(h->lb[1], d.K2h - kz), 0});
+    item_off[r] = (int)items[2].size();
+    for (int y = 0; y < d.K[1]; ++y)
+      for (int kz = 0; kz < d.K2h; kz += h->lb[2])
+        items[2].push_back(LineItem{r, y * d.K2h + kz, std::min(h->lb[2], d.K2h - kz), 0});
+  }
+  item_off[R] = (int)items[2].size();
+  for (int ps = 0; ps < 3; ++ps) {
+    h->nitems[ps] = (int)items[ps].size();
+    upload(items[ps], h->d_items[ps], s);
+  }
+
+  // tiles
+  std::vector<int> toff_g, toff_q, toff_256;
+  std::vector<Tile> tg = make_tiles(h->boff, h->nb, 256 / h->tune.lanes_per_bead, toff_g);
+  std::vector<Tile> tq = make_tiles(h->qoff, h->nq, 256 / h->tune.lanes_per_charge, toff_q);
+  std::vector<Tile> t256 = make_tiles(h->boff, h->nb, 256, toff_256);
+  h->ntiles_g = (int)tg.size();
+  h->ntiles_q = (int)tq.size();
+  h->ntiles_256 = (int)t256.size();
+  upload(tg, h->d_tiles_g, s);
+  upload(tq, h->d_tiles_q, s);
+  upload(t256, h->d_tiles_256, s);
+  upload(toff_g, h->d_off[SLOT_GCM], s);
+  upload(toff_q, h->d_off[SLOT_REAL], s);
+  upload(item_off, h->d_off[SLOT_RECIP], s);
+  upload(toff_256, h->d_off[SLOT_KIN], s);
+  upload(toff_g, h->d_adj_off[0], s);
+  upload(toff_q, h->d_adj_off[1], s);
+  HIPCHK(h, h->part[SLOT_GCM].alloc((size_t)std::max(1, h->ntiles_g) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_REAL].alloc((size_t)std::max(1, h->ntiles_q) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_RECIP].alloc((size_t)std::max(1, h->nitems[2]) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_KIN].alloc((size_t)std::max(1, h->ntiles_256) * PART_W * 8));
+  HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->ntiles_g) * (MAXT * MAXT + 2 * MAXT) * 8));
+  HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->ntiles_q) * (MAXT * MAXT + 2 * MAXT) * 8));
+
+  // cells
+  int nbs = (h->ncells + 1023) / 1024;
+  HIPCHK(h, h->counts.alloc((size_t)h->ncells * 4));
+  HIPCHK(h, h->qcounts.alloc((size_t)h->ncells * 4));
+  HIPCHK(h, h->fill.alloc((size_t)h->ncells * 4));
+  HIPCHK(h, h->start.alloc((size_t)(h->ncells + 1) * 4));
+  HIPCHK(h, h->qstart.alloc((size_t)(h->ncells + 1) * 4));
+  HIPCHK(h, h->bsum.alloc((size_t)2 * (nbs + 1) * 4));
+
+  // meshes (Q must start cleared; the z pass clears it after each use)
+  HIPCHK(h, h->Qint.alloc((size_t)h->grid_total * 8));
+  HIPCHK(h, hipMemsetAsync(h->Qint.p, 0, (size_t)h->grid_total * 8, s));
+  HIPCHK(h, h->Qc.alloc((size_t)h->cgrid_total * cs));
+  HIPCHK(h, h->phi.alloc((size_t)h->grid_total * rs));
+
+  // integrator constants, energy constants
+  std::vector<double> imass(R * MAXT, 1.0), c1(R), c2s(R * MAXT, 0.0), dtv(R), consts(2 * R), Av(R * MAXT * MAXT, 0.0),
+      dself(R * MAXT, 0.0);
+  std::vector<int> lang(R);
+  for (int r = 0; r < R; ++r) {
+    const HostRep& p = h->hp[r];
+    double cc = std::exp(-p.gamma * p.dt);
+    c1[r] = cc;
+    dtv[r] = p.dt;
+    lang[r] = p.gamma > 0.0 ? 1 : 0;
+    for (int t = 0; t < p.nt; ++t) {
+      imass[r * MAXT + t] = 1.0 / p.mass[t];
+      c2s[r * MAXT + t] = std::sqrt((1.0 - cc * cc) * p.kT / p.mass[t]);
+      for (int u = 0; u < p.nt; ++u) Av[(size_t)r * MAXT * MAXT + t * MAXT + u] = p.A[t * p.nt + u];
+    }
+    // constants of eq. ewald: U_corr and U_self, and dU_self/da_t
+    double sz2 = 0, sza = 0;
+    for (int i = h->boff[r]; i < h->boff[r] + h->nb[r]; ++i) {
+      double zz = (double)h->h_z[i] * h->h_z[i];
+      int t = h->h_type[i];
+      sz2 += zz;
+      sza += zz / p.a[t];
+      dself[r * MAXT + t] += -0.5 * p.lB * zz / (p.a[t] * p.a[t]);
+    }
+    consts[2 * r] = -p.lB * p.beta / std::sqrt(M_PI) * sz2;
+    consts[2 * r + 1] = 0.5 * p.lB * sza;
+  }
+  upload(imass, h->d_imass, s);
+  upload(c1, h->d_c1, s);
+  upload(c2s, h->d_c2s, s);
+  upload(dtv, h->d_dt, s);
+  upload(lang, h->d_lang, s);
+  upload(consts, h->d_consts, s);
+  upload(Av, h->d_Avals, s);
+  upload(dself, h->d_dself, s);
+  upload(h->rep, h->d_rep, s);
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->plan_dirty = false;
+  return GCME_OK;
+}
+
+PairLaunch pair_args(gcme_handle h, bool charged) {
+  PairLaunch a{};
+  a.rep = h->d_rep.as<RepDesc>();
+  a.gcm = h->d_gcm.p;
+  a.elec = h->d_elec.p;
+  a.adj = h->d_adj.p;
+  for (int k = 0; k < 3; ++k) a.F[k] = Fk(h, k);
+  a.status = h->d_status.as<unsigned>();
+  a.fscale = h->fscale();
+  if (charged) {
+    a.tiles = h->d_tiles_q.as<Tile>();
+    a.ntiles = h->ntiles_q;
+    for (int k = 0; k < 3; ++k) a.pos[k] = h->q_pos[k].as<uint32_t>();
+    a.param = h->q_param.as<uint32_t>();
+    a.start = h->qstart.as<int>();
+    a.qidx = h->q_idx.as<int>();
+    a.part = h->part[SLOT_REAL].as<double>();
+    a.adj_part = h->adjp[1].as<double>();
+  } else {
+    a.tiles = h->d_tiles_g.as<Tile>();
+    a.ntiles = h->ntiles_g;
+    for (int k = 0; k < 3; ++k) a.pos[k] = h->b_pos[k].as<uint32_t>();
+    a.param = h->b_param.as<uint32_t>();
+    a.start = h->start.as<int>();
+    a.part = h->part[SLOT_GCM].as<double>();
+    a.adj_part = h->adjp[0].as<double>();
+  }
+  return a;
+}
+
+PmeLaunch pme_args(gcme_handle h) {
+  PmeLaunch a{};
+  a.rep = h->d_rep.as<RepDesc>();
+  a.nrep = h->R;
+  a.nq = h->NQ;
+  a.order = h->order;
+  for (int k = 0; k < 3; ++k) {
+    a.qpos[k] = h->q_pos[k].as<uint32_t>();
+    a.F[k] = Fk(h, k);
+    a.items[k] = h->d_items[k].as<LineItem>();
+    a.nitems[k] = h->nitems[k];
+    a.lb[k] = h->lb[k];
+    a.maxK[k] = h->maxK[k];
+  }
+  a.qparam = h->q_param.as<uint32_t>();
+  a.qidx = h->q_idx.as<int>();
+  a.Qint = h->Qint.as<long long>();
+  a.Qc = h->Qc.p;
+  a.phi = h->phi.p;
+  a.tw = h->d_tw.p;
+  a.radix = h->d_rad.as<int>();
+  a.bsp = h->d_bsp.p;
+  a.freq = h->d_freq.p;
+  a.part = h->part[SLOT_RECIP].as<double>();
+  a.status = h->d_status.as<unsigned>();
+  a.fscale = h->fscale();
+  a.qscale = h->qscale();
+  return a;
+}
+
+IntLaunch int_args(gcme_handle h) {
+  IntLaunch a{};
+  a.rep = h->d_rep.as<RepDesc>();
+  a.tiles = h->d_tiles_256.as<Tile>();
+  a.ntiles = h->ntiles_256;
+  a.inv_mass = h->d_imass.as<double>();
+  a.c1 = h->d_c1.as<double>();
+  a.c2s = h->d_c2s.as<double>();
+  a.dt = h->d_dt.as<double>();
+  a.langevin = h->d_lang.as<int>();
+  a.nbeads = h->N;
+  a.seed = h->seed;
+  a.step = h->d_step.as<unsigned long long>();
+  a.fscale_inv = 1.0 / h->fscale();
+  a.part = h->part[SLOT_KIN].as<double>();
+  return a;
+}
+
+// Sort the state A into B by cell (and the charged copy), on stream s.
+void enqueue_sort(gcme_handle h, hipStream_t s) {
+  CellView c = cview(h);
+  launch_fill_i32(s, c.counts, 0, h->ncells);
+  launch_fill_i32(s, c.qcounts, 0, h->ncells);
+  launch_fill_i32(s, c.fill, 0, h->ncells);
+  launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
+  launch_scan(s, c);
+  launch_scatter(s, c, h->N);
+  launch_permute(s, viewA(h), viewB(h), c, qview(h), h->N);
+}
+
+// Forces (and partial sums if ev) on the sorted copy B; F must be cleared.
+void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
+  PairLaunch g = pair_args(h, false);
+  launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, ev, adj);
+  if (h->NQ > 0) {
+    PairLaunch q = pair_args(h, true);
+    launch_pair_elec(s, q, h->fp64, h->tune.lanes_per_charge, ev, adj);
+    PmeLaunch p = pme_args(h);
+    launch_spread(s, p, h->fp64);
+    launch_fft_z_r2c(s, p, h->fp64);
+    launch_fft_y(s, p, h->fp64, false);
+    launch_fft_x_conv(s, p, h->fp64, ev);
+    launch_fft_y(s, p, h->fp64, true);
+    launch_fft_z_c2r(s, p, h->fp64);
+    launch_gather(s, p, h->fp64);
+  }
+}
+
+void enqueue_outputs(gcme_handle h, hipStream_t s, const gcme_io* io, bool kin) {
+  long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
+  if (io->force) launch_forces_out(s, viewB(h), F3, io->force, h->N, h->N, 1.0 / h->fscale());
+  bool adj = io->dE_dA || io->dE_dsigma || io->dE_da;
+  if (io->energy || io->virial || adj) {
+    FinalLaunch f{};
+    f.rep = h->d_rep.as<RepDesc>();
+    f.nrep = h->R;
+    for (int sl = 0; sl < N_SLOTS; ++sl) {
+      f.part[sl] = h->part[sl].as<double>();
+      f.slot_off[sl] = h->d_off[sl].as<int>();
+    }
+    if (h->NQ == 0) {
+      // no charged beads: the charged kernels did not run, their slots are empty ranges
+      f.part[SLOT_REAL] = nullptr;
+      f.part[SLOT_RECIP] = nullptr;
+    }
+    f.consts = h->d_consts.as<double>();
+    f.energy = io->energy;
+    f.virial = io->virial;
+    f.have_kin = kin ? 1 : 0;
+    f.adj_part[0] = h->adjp[0].as<double>();
+    f.adj_part[1] = h->NQ > 0 ? h->adjp[1].as<double>() : nullptr;
+    f.adj_off[0] = h->d_adj_off[0].as<int>();
+    f.adj_off[1] = h->d_adj_off[1].as<int>();
+    f.Avals = h->d_Avals.as<double>();
+    f.dself = h->d_dself.as<double>();
+    f.dE_dA = io->dE_dA;
+    f.dE_dsigma = io->dE_dsigma;
+    f.dE_da = io->dE_da;
+    launch_finalize(s, f);
+  }
+}
+
+gcme_status check_ready(gcme_handle h) {
+  if (!h) return GCME_EINVAL;
+  for (int r = 0; r < h->R; ++r)
+    if (!h->hp[r].set) return fail(h, GCME_ESTATE, "parameters not set for replica " + std::to_string(r));
+  if (!h->have_state) return fail(h, GCME_ESTATE, "state not set (gcme_set_state)");
+  if (h->plan_dirty) return build_plan(h);
+  return GCME_OK;
+}
+
+// One full evaluation on stream s: sort, forces, commit B -> A.
+void enqueue_eval(gcme_handle h, hipStream_t s, bool ev, bool adj) {
+  enqueue_sort(h, s);
+  enqueue_forces(h, s, ev, adj);
+}
+
+// One step of the integrator (forces of the current state in F, indexed in
+// the order of A): first half (kick, drift, noise, clears F), sort, forces,
+// second half kick written back to A.
+void enqueue_step(gcme_handle h, hipStream_t s, bool ev) {
+  IntLaunch ia = int_args(h);
+  long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
+  launch_int_first(s, ia, viewA(h), F3);
+  enqueue_sort(h, s);
+  enqueue_forces(h, s, ev, false);
+  launch_int_last(s, ia, viewB(h), viewA(h), F3, ev);
+}
+
+gcme_status capture(gcme_handle h, bool ev, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  enqueue_step(h, h->cap_stream, ev);
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (e != hipSuccess) return fail(h, GCME_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(h, GCME_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return GCME_OK;
+}
+
+gcme_status ensure_forces(gcme_handle h) {
+  if (h->forces_valid) return GCME_OK;
+  launch_fill_i64(h->stream, h->F.as<long long>(), 0, 3LL * h->N);
+  enqueue_eval(h, h->stream, false, false);
+  launch_commit(h->stream, viewB(h), viewA(h), h->N);
+  HIPCHK(h, hipGetLastError());
+  h->forces_valid = true;
+  return GCME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
+  if (!info || !out) return fail(nullptr, GCME_EINVAL, "null argument");
+  if (info->n_replicas < 1 || info->n_replicas > 65535 || !info->n_beads)
+    return fail(nullptr, GCME_EINVAL, "n_replicas must be in 1..65535 with a host n_beads array");
+  if (info->precision != GCME_FP64 && info->precision != GCME_MIXED)
+    return fail(nullptr, GCME_EINVAL, "precision must be GCME_FP64 or GCME_MIXED");
+  long long total = 0;
+  for (int r = 0; r < info->n_replicas; ++r) {
+    if (info->n_beads[r] < 2) return fail(nullptr, GCME_EINVAL, "every replica needs >= 2 beads");
+    total += info->n_beads[r];
+  }
+  if (total > (1LL << 30)) return fail(nullptr, GCME_EINVAL, "too many beads");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, GCME_EDEVICE, "no HIP device");
+  if (info->device < 0 || info->device >= ndev) return fail(nullptr, GCME_EINVAL, "bad device ordinal");
+  gcme_handle h = new gcme_ctx();
+  h->device = info->device;
+  if (hipSetDevice(h->device) != hipSuccess) {
+    delete h;
+    return fail(nullptr, GCME_EDEVICE, "hipSetDevice failed");
+  }
+  h->R = info->n_replicas;
+  h->nb.assign(info->n_beads, info->n_beads + h->R);
+  h->boff.assign(h->R, 0);
+  for (int r = 1; r < h->R; ++r) h->boff[r] = h->boff[r - 1] + h->nb[r - 1];
+  h->N = (int)total;
+  h->fp64 = info->precision == GCME_FP64;
+  h->seed = info->seed;
+  h->hp.assign(h->R, HostRep{});
+  h->nq.assign(h->R, 0);
+  h->qoff.assign(h->R, 0);
+  h->tune.lanes_per_bead = total < 200000 ? 4 : 1;
+  h->tune.lanes_per_charge = total < 200000 ? 4 : 2;
+  h->tune.cells_per_cutoff = 2;
+  if (info->stream) {
+    h->stream = (hipStream_t)info->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return fail(nullptr, GCME_EDEVICE, "stream creation failed");
+    }
+    h->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete h;
+    return fail(nullptr, GCME_EDEVICE, "stream creation failed");
+  }
+  const size_t N = (size_t)h->N;
+  bool ok = true;
+  for (int k = 0; k < 3; ++k) {
+    ok &= h->a_pos[k].alloc(N * 4) == hipSuccess;
+    ok &= h->b_pos[k].alloc(N * 4) == hipSuccess;
+    ok &= h->a_vel[k].alloc(N * 8) == hipSuccess;
+    ok &= h->b_vel[k].alloc(N * 8) == hipSuccess;
+  }
+  ok &= h->a_param.alloc(N * 4) == hipSuccess;
+  ok &= h->b_param.alloc(N * 4) == hipSuccess;
+  ok &= h->a_id.alloc(N * 4) == hipSuccess;
+  ok &= h->b_id.alloc(N * 4) == hipSuccess;
+  ok &= h->cell.alloc(N * 4) == hipSuccess;
+  ok &= h->tmp.alloc(N * 4) == hipSuccess;
+  ok &= h->F.alloc(N * 24) == hipSuccess;
+  ok &= h->d_status.alloc(64) == hipSuccess;
+  ok &= h->d_step.alloc(64) == hipSuccess;
+  ok &= h->d_pairs.alloc(64) == hipSuccess;
+  if (!ok) {
+    delete h;
+    return fail(nullptr, GCME_ENOMEM, "device allocation failed");
+  }
+  (void)hipMemsetAsync(h->d_status.p, 0, 64, h->stream);
+  (void)hipMemsetAsync(h->d_step.p, 0, 64, h->stream);
+  (void)hipMemsetAsync(h->F.p, 0, N * 24, h->stream);
+  (void)hipStreamSynchronize(h->stream);
+  *out = h;
+  return GCME_OK;
+}
+
+gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p) {
+  if (!h || !p) return h ? fail(h, GCME_EINVAL, "null params") : GCME_EINVAL;
+  if (replica < -1 || replica >= h->R) return fail(h, GCME_EINVAL, "replica out of range");
+  for (int k = 0; k < 3; ++k)
+    if (!(p->box[k] > 0.0) || !std::isfinite(p->box[k])) return fail(h, GCME_EGEOMETRY, "box edges must be > 0");
+  if (!(p->cutoff > 0.0)) return fail(h, GCME_EGEOMETRY, "cutoff must be > 0");
+  for (int k = 0; k < 3; ++k)
+    if (p->cutoff > 0.5 * p->box[k] * (1.0 + 1e-12))
+      return fail(h, GCME_EGEOMETRY, "cutoff exceeds half the box edge (minimum image)");
+  if (!(p->beta > 0.0)) return fail(h, GCME_EINVAL, "beta must be > 0");
+  if (!(p->lB >= 0.0)) return fail(h, GCME_EINVAL, "lB must be >= 0");
+  if (p->order < 3 || p->order > 8) return fail(h, GCME_EUNSUPPORTED, "B-spline order must be 3..8");
+  for (int k = 0; k < 3; ++k) {
+    int K = p->grid[k];
+    if (K < 8 || K > 512 || !smooth(K)) return fail(h, GCME_EUNSUPPORTED, "mesh sizes must be 2^a 3^b in 8..512");
+    if (p->order > K / 2) return fail(h, GCME_EUNSUPPORTED, "order must be <= K/2");
+  }
+  if (p->n_types < 1 || p->n_types > MAXT) return fail(h, GCME_EUNSUPPORTED, "n_types must be 1..4");
+  if (!p->A || !p->sigma || !p->a) return fail(h, GCME_EINVAL, "A, sigma and a are required");
+  const int nt = p->n_types;
+  for (int t = 0; t < nt; ++t) {
+    if (!(p->sigma[t] > 0.0) || !(p->a[t] > 0.0)) return fail(h, GCME_EINVAL, "sigma and a must be > 0");
+    if (p->mass && !(p->mass[t] > 0.0)) return fail(h, GCME_EINVAL, "masses must be > 0");
+    for (int u = 0; u < nt; ++u) {
+      double x = p->A[t * nt + u], y = p->A[u * nt + t];
+      if (!std::isfinite(x) || std::fabs(x - y) > 1e-12 * std::max(1.0, std::fabs(x)))
+        return fail(h, GCME_EINVAL, "A must be finite and symmetric");
+    }
+  }
+  if (!(p->kT >= 0.0) || !(p->dt >= 0.0) || !(p->gamma >= 0.0)) return fail(h, GCME_EINVAL, "kT, dt, gamma must be >= 0");
+  if (p->flags & GCME_FLAG_STRICT_CONTACT) {
+    // no-collapse condition between unit charges of opposite sign
+    for (int t = 0; t < nt; ++t)
+      for (int u = 0; u < nt; ++u) {
+        double s2 = p->sigma[t] * p->sigma[t] + p->sigma[u] * p->sigma[u];
+        double aij = std::sqrt(p->a[t] * p->a[t] + p->a[u] * p->a[u]);
+        double lhs = p->A[t * nt + u] / std::pow(s2, 1.5);
+        double rhs = 4.0 * std::pow(M_PI, 1.5) * p->lB / (std::pow(3.0, 1.5) * aij);
+        if (!(lhs > rhs)) return fail(h, GCME_EINVAL, "contact repulsion does not exceed contact attraction");
+      }
+  }
+  int r0 = replica < 0 ? 0 : replica, r1 = replica < 0 ? h->R : replica + 1;
+  for (int r = 0; r < h->R; ++r)
+    if (h->hp[r].set && (r < r0 || r >= r1) && h->hp[r].order != p->order)
+      return fail(h, GCME_EUNSUPPORTED, "all replicas must use the same B-spline order");
+  for (int r = r0; r < r1; ++r) {
+    HostRep& q = h->hp[r];
+    for (int k = 0; k < 3; ++k) {
+      q.box[k] = p->box[k];
+      q.K[k] = p->grid[k];
+    }
+    q.rc = p->cutoff;
+    q.beta = p->beta;
+    q.lB = p->lB;
+    q.kT = p->kT;
+    q.dt = p->dt;
+    q.gamma = p->gamma;
+    q.order = p->order;
+    q.nt = nt;
+    q.flags = p->flags;
+    for (int i = 0; i < nt * nt; ++i) q.A[i] = p->A[i];
+    for (int t = 0; t < nt; ++t) {
+      q.sigma[t] = p->sigma[t];
+      q.a[t] = p->a[t];
+      q.mass[t] = p->mass ? p->mass[t] : 1.0;
+    }
+    q.set = true;
+  }
+  h->plan_dirty = true;
+  h->forces_valid = false;
+  if (h->have_state) {
+    // types must stay within the new type count
+    for (int r = r0; r < r1; ++r)
+      for (int i = h->boff[r]; i < h->boff[r] + h->nb[r]; ++i)
+        if (h->h_type[i] >= h->hp[r].nt) {
+          h->have_state = false;
+          return fail(h, GCME_EINVAL, "state has bead types beyond n_types; set the state again");
+        }
+  }
+  return GCME_OK;
+}
+
+gcme_status gcme_set_state(gcme_handle h, const double* pos, const double* vel, const int32_t* type,
+                           const int32_t* z) {
+  if (!h) return GCME_EINVAL;
+  if (!pos || !type || !z) return fail(h, GCME_EINVAL, "pos, type and z are required");
+  for (int r = 0; r < h->R; ++r)
+    if (!h->hp[r].set) return fail(h, GCME_ESTATE, "set parameters before the state");
+  HIPCHK(h, hipSetDevice(h->device));
+  const int N = h->N;
+  std::vector<int> t(N), zz(N);
+  HIPCHK(h, hipMemcpyAsync(t.data(), type, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(zz.data(), z, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::vector<int> nq(h->R, 0), qoff(h->R, 0);
+  int NQ = 0;
+  for (int r = 0; r < h->R; ++r) {
+    long long net = 0;
+    qoff[r] = NQ;
+    for (int i = h->boff[r]; i < h->boff[r] + h->nb[r]; ++i) {
+      if (t[i] < 0 || t[i] >= h->hp[r].nt) return fail(h, GCME_EINVAL, "bead type out of range");
+      if (zz[i] < -127 || zz[i] > 127) return fail(h, GCME_EINVAL, "charge numbers must be in -127..127");
+      net += zz[i];
+      if (zz[i] != 0) ++nq[r];
+    }
+    if (net != 0) return fail(h, GCME_ENONNEUTRAL, "replica " + std::to_string(r) + " is not neutral");
+    NQ += nq[r];
+  }
+  std::vector<uint32_t> prm(N);
+  std::vector<int> id(N);
+  for (int r = 0; r < h->R; ++r)
+    for (int i = h->boff[r]; i < h->boff[r] + h->nb[r]; ++i) {
+      prm[i] = pack_param(t[i], zz[i], r);
+      id[i] = i;
+    }
+  h->h_type = t;
+  h->h_z = zz;
+  h->nq = nq;
+  h->qoff = qoff;
+  h->NQ = NQ;
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(h, h->q_pos[k].alloc((size_t)std::max(1, NQ) * 4));
+  }
+  HIPCHK(h, h->q_param.alloc((size_t)std::max(1, NQ) * 4));
+  HIPCHK(h, h->q_idx.alloc((size_t)std::max(1, NQ) * 4));
+  HIPCHK(h, hipMemcpyAsync(h->a_param.p, prm.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->a_id.p, id.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+  for (int k = 0; k < 3; ++k) {
+    if (vel)
+      HIPCHK(h, hipMemcpyAsync(h->a_vel[k].p, vel + (size_t)k * N, (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+    else
+      HIPCHK(h, hipMemsetAsync(h->a_vel[k].p, 0, (size_t)N * 8, h->stream));
+  }
+  // the state is new: rebuild the plan (charged ranges, constants)
+  h->plan_dirty = true;
+  h->have_state = true;
+  gcme_status st = build_plan(h);
+  if (st != GCME_OK) return st;
+  launch_ingest(h->stream, pos, N, N, h->d_rep.as<RepDesc>(), nullptr, viewA(h), h->F.as<long long>(), N);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemsetAsync(h->d_step.p, 0, 8, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->step = 0;
+  h->forces_valid = false;
+  return GCME_OK;
+}
+
+gcme_status gcme_get_state(gcme_handle h, double* pos, double* vel, uint64_t* step) {
+  if (!h) return GCME_EINVAL;
+  if (!h->have_state) return fail(h, GCME_ESTATE, "state not set");
+  HIPCHK(h, hipSetDevice(h->device));
+  if (h->plan_dirty) {
+    gcme_status st = build_plan(h);
+    if (st != GCME_OK) return st;
+  }
+  if (pos || vel) launch_state_out(h->stream, viewA(h), h->d_rep.as<RepDesc>(), pos, vel, h->N, h->N);
+  HIPCHK(h, hipGetLastError());
+  if (step) *step = h->step;
+  return GCME_OK;
+}
+
+gcme_status gcme_forces_energy(gcme_handle h, const gcme_io* io) {
+  if (!h) return GCME_EINVAL;
+  if (!io) return fail(h, GCME_EINVAL, "null io");
+  gcme_status st = check_ready(h);
+  if (st != GCME_OK) return st;
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  if (io->pos)
+    launch_ingest(s, io->pos, h->N, h->N, h->d_rep.as<RepDesc>(), nullptr, viewA(h), h->F.as<long long>(), h->N);
+  else
+    launch_fill_i64(s, h->F.as<long long>(), 0, 3LL * h->N);
+  bool adj = io->dE_dA || io->dE_dsigma || io->dE_da;
+  bool ev = io->energy || io->virial || adj;
+  enqueue_eval(h, s, ev, adj);
+  enqueue_outputs(h, s, io, false);
+  launch_commit(s, viewB(h), viewA(h), h->N);
+  HIPCHK(h, hipGetLastError());
+  h->forces_valid = true;
+  return GCME_OK;
+}
+
+gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe) {
+  if (!h) return GCME_EINVAL;
+  if (n_steps < 0) return fail(h, GCME_EINVAL, "n_steps must be >= 0");
+  if (observe && observe->pos) return fail(h, GCME_EINVAL, "observe->pos must be NULL");
+  gcme_status st = check_ready(h);
+  if (st != GCME_OK) return st;
+  HIPCHK(h, hipSetDevice(h->device));
+  st = ensure_forces(h);
+  if (st != GCME_OK) return st;
+  if (n_steps == 0) {
+    if (observe) {
+      // re-evaluate at the current positions to fill the outputs
+      return gcme_forces_energy(h, observe);
+    }
+    return GCME_OK;
+  }
+  bool obs = observe != nullptr;
+  int plain = obs ? n_steps - 1 : n_steps;
+  if (plain > 0 && !h->g_plain) {
+    st = capture(h, false, &h->g_plain);
+    if (st != GCME_OK) return st;
+  }
+  if (obs && !h->g_obs) {
+    st = capture(h, true, &h->g_obs);
+    if (st != GCME_OK) return st;
+  }
+  for (int i = 0; i < plain; ++i) HIPCHK(h, hipGraphLaunch(h->g_plain, h->stream));
+  if (obs) {
+    HIPCHK(h, hipGraphLaunch(h->g_obs, h->stream));
+    // the step left A == B (same order); outputs read B and the partials
+    enqueue_outputs(h, h->stream, observe, true);
+    HIPCHK(h, hipGetLastError());
+  }
+  h->step += (uint64_t)n_steps;
+  return GCME_OK;
+}
+
+gcme_status gcme_sync(gcme_handle h) {
+  if (!h) return GCME_EINVAL;
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  unsigned st = 0;
+  HIPCHK(h, hipMemcpy(&st, h->d_status.p, 4, hipMemcpyDeviceToHost));
+  if (st) {
+    HIPCHK(h, hipMemset(h->d_status.p, 0, 4));
+    return fail(h, GCME_EOVERFLOW, "fixed-point accumulator overflow (forces too large)");
+  }
+  return GCME_OK;
+}
+
+const char* gcme_last_error(gcme_handle h) { return h ? h->err.c_str() : g_create_err.c_str(); }
+
+gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t) {
+  if (!h || !t) return GCME_EINVAL;
+  *t = h->tune;
+  return GCME_OK;
+}
+
+gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
+  if (!h || !t) return GCME_EINVAL;
+  gcme_tuning n = h->tune;
+  if (t->cells_per_cutoff >= 0) {
+    if (t->cells_per_cutoff < 1 || t->cells_per_cutoff > 4) return fail(h, GCME_EINVAL, "cells_per_cutoff in 1..4");
+    n.cells_per_cutoff = t->cells_per_cutoff;
+  }
+  auto okl = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == 16; };
+  if (t->lanes_per_bead >= 0) {
+    if (!okl(t->lanes_per_bead)) return fail(h, GCME_EINVAL, "lanes_per_bead in {1,2,4,8,16}");
+    n.lanes_per_bead = t->lanes_per_bead;
+  }
+  if (t->lanes_per_charge >= 0) {
+    if (!okl(t->lanes_per_charge)) return fail(h, GCME_EINVAL, "lanes_per_charge in {1,2,4,8,16}");
+    n.lanes_per_charge = t->lanes_per_charge;
+  }
+  if (n.cells_per_cutoff != h->tune.cells_per_cutoff || n.lanes_per_bead != h->tune.lanes_per_bead ||
+      n.lanes_per_charge != h->tune.lanes_per_charge) {
+    h->tune = n;
+    h->plan_dirty = true;
+    h->drop_graphs();
+  }
+  return GCME_OK;
+}
+
+gcme_status gcme_count_pairs(gcme_handle h, uint64_t* n_pairs) {
+  if (!h || !n_pairs) return GCME_EINVAL;
+  gcme_status st = check_ready(h);
+  if (st != GCME_OK) return st;
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  enqueue_sort(h, s);
+  HIPCHK(h, hipMemsetAsync(h->d_pairs.p, 0, 8, s));
+  PairLaunch g = pair_args(h, false);
+  g.pair_count = h->d_pairs.as<unsigned long long>();
+  // counting run: forces go to a scratch copy so the state's forces stay valid
+  DevBuf scratch;
+  HIPCHK(h, scratch.alloc((size_t)h->N * 24));
+  for (int k = 0; k < 3; ++k) g.F[k] = scratch.as<long long>() + (size_t)k * h->N;
+  launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, false, false);
+  HIPCHK(h, hipGetLastError());
+  unsigned long long c = 0;
+  HIPCHK(h, hipMemcpyAsync(&c, h->d_pairs.p, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  *n_pairs = c / 2;
+  // sorting B does not disturb A or F
+  return GCME_OK;
+}
+
+gcme_status gcme_autotune(gcme_handle h) {
+  if (!h) return GCME_EINVAL;
+  gcme_status st = check_ready(h);
+  if (st != GCME_OK) return st;
+  HIPCHK(h, hipSetDevice(h->device));
+  st = ensure_forces(h);
+  if (st != GCME_OK) return st;
+  hipStream_t s = h->stream;
+  gcme_tuning best = h->tune;
+  double best_t = 1e30;
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  // time one full evaluation per candidate (forces only), on the current state
+  DevBuf saveF;
+  HIPCHK(h, saveF.alloc((size_t)h->N * 24));
+  HIPCHK(h, hipMemcpyAsync(saveF.p, h->F.p, (size_t)h->N * 24, hipMemcpyDeviceToDevice, s));
+  const int ncc_list[] = {1, 2, 3};
+  const int lpb_list[] = {1, 2, 4, 8};
+  const int lpq_list[] = {1, 2, 4, 8};
+  for (int ncc : ncc_list) {
+    for (int lpb : lpb_list) {
+      for (int lpq : lpq_list) {
+        if (lpq != lpb && lpq != 2 * lpb && 2 * lpq != lpb) continue;
+        gcme_tuning t{ncc, lpb, lpq};
+        if (gcme_set_tuning(h, &t) != GCME_OK) continue;
+        if (build_plan(h) != GCME_OK) continue;
+        float ms = 0;
+        for (int rep = 0; rep < 3; ++rep) {
+          launch_fill_i64(s, h->F.as<long long>(), 0, 3LL * h->N);
+          (void)hipEventRecord(e0, s);
+          enqueue_eval(h, s, false, false);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          float m = 0;
+          (void)hipEventElapsedTime(&m, e0, e1);
+          if (rep > 0) ms += m;
+        }
+        if (ms < best_t) {
+          best_t = ms;
+          best = t;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  gcme_set_tuning(h, &best);
+  st = build_plan(h);
+  if (st != GCME_OK) return st;
+  HIPCHK(h, hipMemcpyAsync(h->F.p, saveF.p, (size_t)h->N * 24, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return GCME_OK;
+}
+
+static const char* kStageNames[GCME_N_STAGES] = {"int_first", "sort",      "pair_gcm",   "pair_elec",
+                                                  "spread",    "fft_z_r2c", "fft_y",      "fft_x_conv",
+                                                  "fft_y_inv", "fft_z_c2r", "gather",     "int_last"};
+
+const char* gcme_stage_name(int32_t i) { return (i >= 0 && i < GCME_N_STAGES) ? kStageNames[i] : nullptr; }
+
+gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
+  if (!h || !ms || n_reps < 1) return h ? fail(h, GCME_EINVAL, "n_reps >= 1 and ms required") : GCME_EINVAL;
+  gcme_status st = check_ready(h);
+  if (st != GCME_OK) return st;
+  HIPCHK(h, hipSetDevice(h->device));
+  st = ensure_forces(h);
+  if (st != GCME_OK) return st;
+  hipStream_t s = h->stream;
+  hipEvent_t ev[GCME_N_STAGES + 1];
+  for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
+  for (int i = 0; i < GCME_N_STAGES; ++i) ms[i] = 0.0;
+  IntLaunch ia = int_args(h);
+  long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
+  for (int rep = 0; rep < n_reps; ++rep) {
+    int k = 0;
+    (void)hipEventRecord(ev[k++], s);
+    launch_int_first(s, ia, viewA(h), F3);
+    (void)hipEventRecord(ev[k++], s);
+    enqueue_sort(h, s);
+    (void)hipEventRecord(ev[k++], s);
+    PairLaunch g = pair_args(h, false);
+    launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, false, false);
+    (void)hipEventRecord(ev[k++], s);
+    PmeLaunch p = pme_args(h);
+    if (h->NQ > 0) {
+      PairLaunch q = pair_args(h, true);
+      launch_pair_elec(s, q, h->fp64, h->tune.lanes_per_charge, false, false);
+      (void)hipEventRecord(ev[k++], s);
+      launch_spread(s, p, h->fp64);
+      (void)hipEventRecord(ev[k++], s);
+      launch_fft_z_r2c(s, p, h->fp64);
+      (void)hipEventRecord(ev[k++], s);
+      launch_fft_y(s, p, h->fp64, false);
+      (void)hipEventRecord(ev[k++], s);
+      launch_fft_x_conv(s, p, h->fp64, false);
+      (void)hipEventRecord(ev[k++], s);
+      launch_fft_y(s, p, h->fp64, true);
+      (void)hipEventRecord(ev[k++], s);
+      launch_fft_z_c2r(s, p, h->fp64);
+      (void)hipEventRecord(ev[k++], s);
+      launch_gather(s, p, h->fp64);
+      (void)hipEventRecord(ev[k++], s);
+    } else {
+      for (int j = 0; j < 8; ++j) (void)hipEventRecord(ev[k++], s);
+    }
+    launch_int_last(s, ia, viewB(h), viewA(h), F3, false);
+    (void)hipEventRecord(ev[k++], s);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipEventSynchronize(ev[GCME_N_STAGES]));
+    for (int i = 0; i < GCME_N_STAGES; ++i) {
+      float m = 0;
+      (void)hipEventElapsedTime(&m, ev[i], ev[i + 1]);
+      ms[i] += m / n_reps;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  h->step += (uint64_t)n_reps;
+  return GCME_OK;
+}
+
+void gcme_destroy(gcme_handle h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+// Internal device structures and kernel launchers of the GCMe engine.
+// Every kernel is hand-written HIP for gfx950 (64-wide wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gcme {
+
+constexpr int MAXT = 4;           // bead types per replica
+constexpr int NSER = 14;          // small-r series terms stored per type pair
+constexpr int TILE = 256;         // beads per tile of the per-bead kernels
+constexpr int FFT_THREADS = 256;  // threads of a mesh-line work item
+
+// Fixed-point scales (log2) of the force and charge-mesh accumulators.
+constexpr int FSHIFT_MIXED = 32;
+constexpr int FSHIFT_FP64 = 40;
+
+// Per-replica geometry and method constants (device resident).
+struct RepDesc {
+  double L[3];
+  double V;
+  double rc, rc2;
+  double beta, lB;
+  double scaled[3];   // L / 2^32: fixed-point unit in length units
+  float scalef[3];
+  float rc2f;
+  float betaf, lBf;
+  float hf[3];        // cell edge
+  int nc[3];          // cells per axis
+  int reach[3];       // stencil half-width in cells; -1 = take the whole axis
+  int cell_off;       // first global cell id
+  int bead_off, n;    // bead range in the concatenated arrays
+  int q_off, nq;      // charged-bead range in the compacted charged arrays
+  int K[3];
+  int K2h;            // K2/2 + 1
+  long long grid_off;   // real mesh offset (K0 K1 K2 entries)
+  long long cgrid_off;  // half-complex mesh offset (K0 K1 K2h entries)
+  int order;
+  int nt;
+  int tw_off[3];      // twiddle table offset for the length of each axis
+  int bsp_off[3];     // offsets of 1/|b(m)|^2 and m/L tables per axis
+  int rad_off[3];     // offset of the radix list of each axis length
+  int nrad[3];
+};
+
+// Pair coefficients of one type pair for the excluded-volume term:
+// u = C exp2(-bl r^2), force/r = twob * u.
+template <typename T>
+struct GcmPar {
+  T C, bl, twob, pad;
+};
+
+// Real-space smeared-Coulomb coefficients of one type pair.
+// phi(r) = [erf(alpha r) - erf(beta r)]/r, g(r) = -(1/r) dphi/dr.
+// For r^2 < rs2 both come from the series in r^2 with coefficients cphi, cg.
+template <typename T>
+struct ElecPar {
+  T alpha, alpha2, rs2, pad;
+  T cphi[NSER];
+  T cg[NSER];
+};
+
+// Adjoint coefficients (derivatives with respect to sigma_ij and a_ij).
+template <typename T>
+struct AdjPar {
+  T inv_s2;     // 1 / s_ij^2
+  T dsig_i;     // sigma_ti / s_ij  (chain factor for d/dsigma_ti)
+  T dsig_j;
+  T s_inv;      // 1 / s_ij
+  T daij_i;     // a_ti / a_ij
+  T daij_j;
+  T ea;         // (2/sqrt(pi)) alpha / a_ij
+  T pad;
+};
+
+// One mesh-line work item: `count` lines of one replica starting at line
+// index `first` of the pass (lines are enumerated per pass, see pme kernels).
+struct LineItem {
+  int rep;
+  int first;
+  int count;
+  int pad;
+};
+
+// Tiles of consecutive beads of one replica (per-bead kernels).
+struct Tile {
+  int rep;
+  int first;   // first bead (concatenated index)
+  int count;   // <= beads per tile
+  int pad;
+};
+
+// Slots of the per-block partial sums (7 doubles: energy, virial[6]).
+enum { SLOT_GCM = 0, SLOT_REAL = 1, SLOT_RECIP = 2, SLOT_KIN = 3, N_SLOTS = 4 };
+constexpr int PART_W = 8;
+
+// Device status bits.
+enum { STATUS_FORCE_OVERFLOW = 1, STATUS_MESH_OVERFLOW = 2 };
+
+// Bead parameter word: bits 0..7 type, 8..15 charge (int8), 16..31 replica.
+__host__ __device__ inline uint32_t pack_param(int t, int z, int rep) {
+  return (uint32_t)(t & 0xff) | ((uint32_t)(z & 0xff) << 8) | ((uint32_t)rep << 16);
+}
+__host__ __device__ inline int param_type(uint32_t p) { return (int)(p & 0xff); }
+__host__ __device__ inline int param_z(uint32_t p) { return (int)(int8_t)((p >> 8) & 0xff); }
+__host__ __device__ inline int param_rep(uint32_t p) { return (int)(p >> 16); }
+
+// Arrays of the dynamic state (SoA).
+struct StateView {
+  uint32_t* pos[3];  // fractional fixed point: x / L * 2^32
+  double* vel[3];
+  uint32_t* param;
+  int* id;           // original (concatenated) bead index
+};
+
+struct CellView {
+  int* cell;         // [N] cell id of each bead of the unsorted array
+  int* tmp;          // [N] bead indices scattered by cell
+  int* counts;       // [Ncells]
+  int* qcounts;      // [Ncells]
+  int* fill;         // [Ncells]
+  int* start;        // [Ncells + 1]
+  int* qstart;       // [Ncells + 1]
+  int* bsum;         // scan block sums [2 * nblocks]
+  int ncells;
+};
+
+struct ChargedView {
+  uint32_t* pos[3];
+  uint32_t* param;
+  int* idx;          // sorted bead index of each charged bead
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the kernel translation units).
+// ---------------------------------------------------------------------------
+
+// cells.hip
+void launch_ingest(hipStream_t s, const double* pos_soa, int N, long long ld, const RepDesc* rep,
+                   const uint32_t* param, StateView A, long long* F, int nF);
+void launch_fill_i32(hipStream_t s, int* p, int v, long long n);
+void launch_fill_i64(hipStream_t s, long long* p, long long v, long long n);
+void launch_bin(hipStream_t s, StateView A, const RepDesc* rep, CellView c, int N);
+void launch_scan(hipStream_t s, CellView c);
+void launch_scatter(hipStream_t s, CellView c, int N);
+void launch_permute(hipStream_t s, StateView A, StateView B, CellView c, ChargedView q, int N);
+void launch_commit(hipStream_t s, StateView B, StateView A, int N);
+
+// pair.hip
+struct PairLaunch {
+  const RepDesc* rep;
+  const Tile* tiles;
+  int ntiles;
+  const void* gcm;     // GcmPar<T>[R][MAXT][MAXT]
+  const void* elec;    // ElecPar<T>[R][MAXT][MAXT]
+  const void* adj;     // AdjPar<T>[R][MAXT][MAXT]
+  const uint32_t* pos[3];
+  const uint32_t* param;
+  const int* start;    // cell start (all beads or charged beads)
+  const int* qidx;     // charged -> sorted bead index (charged kernel)
+  long long* F[3];
+  double* part;        // partial sums of this slot, [ntiles][PART_W]
+  double* adj_part;    // adjoint partials [ntiles][MAXT * MAXT + 2 * MAXT]
+  unsigned long long* pair_count;  // optional counter
+  unsigned int* status;
+  double fscale;       // 2^FSHIFT
+};
+void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, int tpa, bool ev, bool adjoint);
+void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, int tpa, bool ev, bool adjoint);
+
+// pme.hip
+struct PmeLaunch {
+  const RepDesc* rep;
+  int nrep;
+  int nq;             // charged beads, all replicas
+  int order;          // B-spline order (shared by all replicas)
+  const uint32_t* qpos[3];
+  const uint32_t* qparam;
+  const int* qidx;
+  long long* Qint;
+  void* Qc;           // complex<T>
+  void* phi;          // T
+  const void* tw;     // complex<T> twiddles
+  const int* radix;
+  const void* bsp;    // T: 1/|b|^2 per axis entry
+  const void* freq;   // T: signed m / L per axis entry
+  const LineItem* items[3];  // Z, Y, X passes
+  int nitems[3];
+  int lb[3];          // lines per item for each pass
+  int maxK[3];
+  long long* F[3];
+  double* part;       // recip slot partials [nitems X][PART_W]
+  unsigned int* status;
+  double fscale;      // force fixed-point scale
+  double qscale;      // mesh fixed-point scale
+};
+void launch_spread(hipStream_t s, const PmeLaunch& a, bool fp64);
+void launch_fft_z_r2c(hipStream_t s, const PmeLaunch& a, bool fp64);
+void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse);
+void launch_fft_x_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev);
+void launch_fft_z_c2r(hipStream_t s, const PmeLaunch& a, bool fp64);
+void launch_gather(hipStream_t s, const PmeLaunch& a, bool fp64);
+
+// integrate.hip
+struct IntLaunch {
+  const RepDesc* rep;
+  const Tile* tiles;
+  int ntiles;
+  const double* inv_mass;   // [R][MAXT]
+  const double* c1;         // [R] exp(-gamma dt)
+  const double* c2s;        // [R][MAXT] sqrt((1 - c1^2) kT / m)
+  const double* dt;         // [R]
+  const int* langevin;      // [R]
+  int nbeads;
+  unsigned long long seed;
+  unsigned long long* step; // device counter: step being taken (the last
+                            // kernel of a step advances it, so captured
+                            // steps can be replayed)
+  double fscale_inv;
+  double* part;             // kinetic partials [ntiles][PART_W]
+};
+void launch_int_first(hipStream_t s, const IntLaunch& a, StateView A, long long* const F[3]);
+void launch_int_last(hipStream_t s, const IntLaunch& a, StateView B, StateView A,
+                     long long* const F[3], bool kin);
+void launch_forces_out(hipStream_t s, StateView B, long long* const F[3], double* out, long long ld,
+                       int N, double fscale_inv);
+void launch_state_out(hipStream_t s, StateView A, const RepDesc* rep, double* pos, double* vel,
+                      long long ld, int N);
+struct FinalLaunch {
+  const RepDesc* rep;
+  int nrep;
+  const double* part[N_SLOTS];
+  const int* slot_off[N_SLOTS];  // [R+1] partial ranges per replica
+  const double* consts;          // [R][2]: E_corr, E_self
+  double* energy;                // [R][7] or null
+  double* virial;                // [R][6] or null
+  int have_kin;
+  const double* adj_part[2];     // gcm, real adjoint partials
+  const int* adj_off[2];
+  const double* Avals;           // [R][MAXT*MAXT]
+  const double* dself;           // [R][MAXT] d U_self / d a_t
+  double* dE_dA;
+  double* dE_dsigma;
+  double* dE_da;
+};
+void launch_finalize(hipStream_t s, const FinalLaunch& a);
+
+}  // namespace gcme

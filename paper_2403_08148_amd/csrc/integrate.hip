@@ -1,0 +1,275 @@
+// Integrators (velocity Verlet, BAOAB Langevin), output conversion and the
+// fixed-order final reductions.
+//
+// Langevin noise: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+// counter (step, bead id, replica, 0) and key (seed, 0x67636d65); uniforms
+// ((x >> 11) + 1/2) 2^-53; Box-Muller on (u0, u1) and (u2, u3).  Keying by
+// the original bead id makes the noise independent of the cell ordering.
+#include "gcme_internal.h"
+
+namespace gcme {
+
+namespace {
+
+__device__ inline void philox4x64_10(unsigned long long x[4], unsigned long long k0, unsigned long long k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B97F4A7C15ULL;
+      k1 += 0xBB67AE8584CAA73BULL;
+    }
+    const unsigned long long m0 = 0xD2E7470EE14C6C93ULL, m1 = 0xCA5A826395121157ULL;
+    unsigned long long hi0 = __umul64hi(m0, x[0]), lo0 = m0 * x[0];
+    unsigned long long hi1 = __umul64hi(m1, x[2]), lo1 = m1 * x[2];
+    unsigned long long y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0;
+    x[1] = lo1;
+    x[2] = y2;
+    x[3] = lo0;
+  }
+}
+
+__device__ inline void gauss3(unsigned long long seed, unsigned long long step, unsigned long long id,
+                              unsigned long long rep, double g[3]) {
+  unsigned long long x[4] = {step, id, rep, 0ULL};
+  philox4x64_10(x, seed, 0x67636d65ULL);
+  double u[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = ((double)(x[k] >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+  double s1, c1, s3, c3;
+  sincospi(2.0 * u[1], &s1, &c1);
+  sincospi(2.0 * u[3], &s3, &c3);
+  g[0] = r0 * c1;
+  g[1] = r0 * s1;
+  g[2] = r1 * c3;
+}
+
+__device__ inline uint32_t drift(uint32_t u, double dx, double L) {
+  long long du = llrint(dx / L * 4294967296.0);
+  return u + (uint32_t)du;
+}
+
+__global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* F1, long long* F2, int N) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const uint32_t prm = A.param[s];
+  const int r = param_rep(prm), t = param_type(prm);
+  const RepDesc& R = a.rep[r];
+  const double im = a.inv_mass[r * MAXT + t];
+  const double dt = a.dt[r];
+  long long* Fk[3] = {F0, F1, F2};
+  double v[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double f = (double)Fk[k][s] * a.fscale_inv;
+    v[k] = A.vel[k][s] + 0.5 * dt * f * im;
+    Fk[k][s] = 0;
+  }
+  uint32_t u[3] = {A.pos[0][s], A.pos[1][s], A.pos[2][s]};
+  if (a.langevin[r]) {
+    double g[3];
+    gauss3(a.seed, *a.step, (unsigned long long)A.id[s], (unsigned long long)r, g);
+    const double c1 = a.c1[r], c2 = a.c2s[r * MAXT + t];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      u[k] = drift(u[k], 0.5 * dt * v[k], R.L[k]);
+      v[k] = c1 * v[k] + c2 * g[k];
+      u[k] = drift(u[k], 0.5 * dt * v[k], R.L[k]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = drift(u[k], dt * v[k], R.L[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A.pos[k][s] = u[k];
+    A.vel[k][s] = v[k];
+  }
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0) t = ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+  return t;
+}
+
+// Second half kick on the sorted copy B, written back to A (so the state is
+// left in the order the forces are indexed in).  One tile per block.
+template <bool KIN>
+__global__ __launch_bounds__(256) void k_int_last(IntLaunch a, StateView B, StateView A, long long* F0,
+                                                  long long* F1, long long* F2) {
+  __shared__ double sh[4];
+  const Tile tile = a.tiles[blockIdx.x];
+  const bool active = (int)threadIdx.x < tile.count;
+  const int n = tile.first + (active ? (int)threadIdx.x : 0);
+  double ke = 0;
+  if (active) {
+    const uint32_t prm = B.param[n];
+    const int r = tile.rep, t = param_type(prm);
+    const double im = a.inv_mass[r * MAXT + t];
+    const double dt = a.dt[r];
+    long long* Fk[3] = {F0, F1, F2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double v = B.vel[k][n] + 0.5 * dt * (double)Fk[k][n] * a.fscale_inv * im;
+      A.vel[k][n] = v;
+      A.pos[k][n] = B.pos[k][n];
+      ke += 0.5 * v * v / im;
+    }
+    A.param[n] = prm;
+    A.id[n] = B.id[n];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.step += 1ULL;
+  if (KIN) {
+    double t = block_sum(ke, sh);
+    if (threadIdx.x == 0) {
+      a.part[(size_t)blockIdx.x * PART_W + 0] = t;
+      for (int k = 1; k < PART_W; ++k) a.part[(size_t)blockIdx.x * PART_W + k] = 0.0;
+    }
+  }
+}
+
+__global__ void k_forces_out(StateView B, long long* F0, long long* F1, long long* F2, double* out, long long ld,
+                             int N, double sc) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  int id = B.id[n];
+  out[id] = (double)F0[n] * sc;
+  out[ld + id] = (double)F1[n] * sc;
+  out[2 * ld + id] = (double)F2[n] * sc;
+}
+
+__global__ void k_state_out(StateView A, const RepDesc* rep, double* pos, double* vel, long long ld, int N) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  int id = A.id[s];
+  const RepDesc& R = rep[param_rep(A.param[s])];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (pos) pos[k * ld + id] = (double)A.pos[k][s] * R.scaled[k];
+    if (vel) vel[k * ld + id] = A.vel[k][s];
+  }
+}
+
+// Fixed-order sum of the partial-sum rows [lo, hi) of one slot: thread t
+// takes rows lo + t, lo + t + 256, ... in order, then a fixed tree.
+__device__ inline double slot_sum(const double* part, int lo, int hi, int col, double* sh) {
+  double v = 0;
+  for (int r = lo + (int)threadIdx.x; r < hi; r += blockDim.x) v += part[(size_t)r * PART_W + col];
+  return block_sum(v, sh);
+}
+
+__device__ inline double adj_sum(const double* part, int lo, int hi, int col, double* sh) {
+  constexpr int W = MAXT * MAXT + 2 * MAXT;
+  double v = 0;
+  for (int r = lo + (int)threadIdx.x; r < hi; r += blockDim.x) v += part[(size_t)r * W + col];
+  return block_sum(v, sh);
+}
+
+__global__ __launch_bounds__(256) void k_finalize(FinalLaunch a) {
+  __shared__ double sh[4];
+  __shared__ double res[N_SLOTS][7];
+  const int r = blockIdx.x;
+  for (int sl = 0; sl < N_SLOTS; ++sl) {
+    for (int col = 0; col < 7; ++col) {
+      double t = 0;
+      if (a.part[sl] && (sl != SLOT_KIN || a.have_kin)) {
+        t = slot_sum(a.part[sl], a.slot_off[sl][r], a.slot_off[sl][r + 1], col, sh);
+      } else {
+        __syncthreads();
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) res[sl][col] = t;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double ec = a.consts[2 * r], es = a.consts[2 * r + 1];
+    if (a.energy) {
+      double* E = a.energy + (size_t)r * 7;
+      E[0] = res[SLOT_GCM][0];
+      E[1] = res[SLOT_REAL][0];
+      E[2] = res[SLOT_RECIP][0];
+      E[3] = ec;
+      E[4] = es;
+      E[5] = ((E[0] + E[1]) + (E[2] + E[3])) + E[4];
+      E[6] = a.have_kin ? res[SLOT_KIN][0] : 0.0;
+    }
+    if (a.virial) {
+      for (int k = 0; k < 6; ++k)
+        a.virial[(size_t)r * 6 + k] = (res[SLOT_GCM][1 + k] + res[SLOT_REAL][1 + k]) + res[SLOT_RECIP][1 + k];
+    }
+  }
+  if (a.dE_dA || a.dE_dsigma || a.dE_da) {
+    __shared__ double ett[MAXT * MAXT], dsg[MAXT], dea[MAXT];
+    for (int q = 0; q < MAXT * MAXT; ++q) {
+      double t = adj_sum(a.adj_part[0], a.adj_off[0][r], a.adj_off[0][r + 1], q, sh);
+      if (threadIdx.x == 0) ett[q] = t;
+    }
+    for (int t2 = 0; t2 < MAXT; ++t2) {
+      double t = adj_sum(a.adj_part[0], a.adj_off[0][r], a.adj_off[0][r + 1], MAXT * MAXT + t2, sh);
+      if (threadIdx.x == 0) dsg[t2] = t;
+    }
+    for (int t2 = 0; t2 < MAXT; ++t2) {
+      double t = 0;
+      if (a.adj_part[1])
+        t = adj_sum(a.adj_part[1], a.adj_off[1][r], a.adj_off[1][r + 1], MAXT * MAXT + MAXT + t2, sh);
+      else {
+        __syncthreads();
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) dea[t2] = t;
+    }
+    if (threadIdx.x == 0) {
+      for (int t = 0; t < MAXT; ++t) {
+        for (int u = 0; u < MAXT; ++u) {
+          // unordered type-pair energy: both visiting orders
+          double E = t == u ? ett[t * MAXT + t] : ett[t * MAXT + u] + ett[u * MAXT + t];
+          double A = a.Avals[(size_t)r * MAXT * MAXT + t * MAXT + u];
+          if (a.dE_dA) a.dE_dA[(size_t)r * MAXT * MAXT + t * MAXT + u] = A != 0.0 ? E / A : 0.0;
+        }
+        if (a.dE_dsigma) a.dE_dsigma[(size_t)r * MAXT + t] = dsg[t];
+        if (a.dE_da) a.dE_da[(size_t)r * MAXT + t] = dea[t] + a.dself[(size_t)r * MAXT + t];
+      }
+    }
+  }
+}
+
+inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_int_first(hipStream_t s, const IntLaunch& a, StateView A, long long* const F[3]) {
+  hipLaunchKernelGGL(k_int_first, dim3(nblk(a.nbeads, 256)), dim3(256), 0, s, a, A, F[0], F[1], F[2], a.nbeads);
+}
+
+void launch_int_last(hipStream_t s, const IntLaunch& a, StateView B, StateView A, long long* const F[3], bool kin) {
+  if (kin)
+    hipLaunchKernelGGL(k_int_last<true>, dim3(a.ntiles), dim3(256), 0, s, a, B, A, F[0], F[1], F[2]);
+  else
+    hipLaunchKernelGGL(k_int_last<false>, dim3(a.ntiles), dim3(256), 0, s, a, B, A, F[0], F[1], F[2]);
+}
+
+void launch_forces_out(hipStream_t s, StateView B, long long* const F[3], double* out, long long ld, int N,
+                       double fscale_inv) {
+  hipLaunchKernelGGL(k_forces_out, dim3(nblk(N, 256)), dim3(256), 0, s, B, F[0], F[1], F[2], out, ld, N,
+                     fscale_inv);
+}
+
+void launch_state_out(hipStream_t s, StateView A, const RepDesc* rep, double* pos, double* vel, long long ld,
+                      int N) {
+  hipLaunchKernelGGL(k_state_out, dim3(nblk(N, 256)), dim3(256), 0, s, A, rep, pos, vel, ld, N);
+}
+
+void launch_finalize(hipStream_t s, const FinalLaunch& a) {
+  hipLaunchKernelGGL(k_finalize, dim3(a.nrep), dim3(256), 0, s, a);
+}
+
+}  // namespace gcme

@@ -1,0 +1,54 @@
+"""Helpers shared by the GPU tests: run the HIP engine and the FP64 oracle on
+the same seeded inputs and compare.  (Not collected by pytest.)"""
+import numpy as np
+
+from oracle import oracle as O
+
+
+def make_engine(ws, precision, seed=1, tuning=None):
+    from paper_2403_08148_amd import GCMe, params_from_workload
+    eng = GCMe([w.N for w in ws], precision=precision, seed=seed)
+    for r, w in enumerate(ws):
+        eng.set_params(params_from_workload(w), replica=r)
+    if tuning:
+        eng.set_tuning(**tuning)
+    pos = np.concatenate([w.pos for w in ws])
+    typ = np.concatenate([w.type for w in ws])
+    z = np.concatenate([w.z for w in ws])
+    vel = np.concatenate([w.vel for w in ws])
+    eng.set_state(pos, typ, z, vel)
+    return eng
+
+
+def gpu_eval(eng, adjoint=False, pos=None):
+    out = eng.forces_energy(pos=pos, adjoint=adjoint)
+    eng.sync()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res["force"] = res["force"].T.copy()
+    return res
+
+
+def oracle_params(w, **over):
+    d = dict(box=w.box, rc=w.rc, beta=w.beta, lB=w.lB, A=w.A, sigma=w.sigma, a=w.a)
+    d.update(over)
+    return O.Params(**d)
+
+
+def oracle_eval(w, adjoint=False):
+    p = oracle_params(w)
+    ref = O.forces(w.pos, w.type, w.z, p, recip_mode=O.RECIP_SPME, K=w.grid, order=w.order)
+    if adjoint:
+        rs = O.real_space(w.pos, w.type, w.z, p, adjoint=True)
+        c = O.constants(w.type, w.z, p)
+        ref["Eex_tt"] = rs["Eex_tt"]
+        ref["dE_dsigma"] = rs["dE_dsigma"]
+        ref["dE_da"] = rs["dE_da"] + c["dE_da_self"]
+    return ref
+
+
+def rel_rms(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def rel(a, b, floor=1e-12):
+    return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), floor)
