@@ -7,7 +7,9 @@ FP64 oracle (tests) and the HIP library (tests, bench) are fed from here.
 Workload recipe (reduced units, kT = 1, lengths in the bead diameter d):
   * number density 2.5 d^-3, the coarse-graining level the paper settles on
     (Parametrization section), so L = (N / 2.5)^(1/3) for cubic boxes;
-  * positions uniform in [0, L)^3 (numpy PCG64 ``default_rng(seed)``);
+  * positions uniform in [0, L)^3 (numpy PCG64 ``default_rng(seed)``), drawn
+    on the 2^-32 L lattice of each edge (the engine's fixed-point grid) unless
+    on_lattice=False;
   * charged beads chosen by permutation, exactly half +1 and half -1 (neutral);
   * species assigned by permutation in equal shares;
   * the mass radius sigma_t is tied to the charge radius a_t (one radius per
@@ -102,12 +104,22 @@ def _sym_uniform(rng, nt, lo, hi):
     return np.triu(m) + np.triu(m, 1).T
 
 
+def lattice_positions(frac, box):
+    """Positions x = (u / 2^32) L for integer u = floor(frac 2^32): the
+    2^-32 L lattice on which the engine stores coordinates, so an input drawn
+    here reaches both the oracle and the engine without rounding."""
+    u = np.floor(np.asarray(frac, dtype=np.float64) * 4294967296.0)
+    u = np.minimum(u, 4294967295.0)
+    return u / 4294967296.0 * np.asarray(box, dtype=np.float64)
+
+
 def bulk(name, N, seed, charged_frac, a_types, A, rc, beta, grid, order=5, lB=1.0,
-         dt=0.02, gamma=1.0, kT=1.0, kmax=0.0, box=None):
+         dt=0.02, gamma=1.0, kT=1.0, kmax=0.0, box=None, on_lattice=True):
     rng = np.random.default_rng(seed)
     L = (N / DENSITY) ** (1.0 / 3.0) if box is None else None
     box = (L, L, L) if box is None else tuple(float(b) for b in box)
-    pos = rng.uniform(0.0, 1.0, size=(N, 3)) * np.asarray(box)
+    frac = rng.uniform(0.0, 1.0, size=(N, 3))
+    pos = lattice_positions(frac, box) if on_lattice else frac * np.asarray(box)
     nt = len(a_types)
     typ = _species(rng, N, nt)
     z = _charges(rng, N, charged_frac)

@@ -168,6 +168,8 @@ typedef struct {
     int32_t cells_per_cutoff;  /* cell edge ~ rc / n (1..4) */
     int32_t lanes_per_bead;    /* lanes sharing one bead's neighbour scan (1,2,4,8,16) */
     int32_t lanes_per_charge;  /* same, for the charged-pair kernel */
+    int32_t beads_per_brick;   /* target home beads per pair workgroup (0 = 256/lanes) */
+    int32_t charges_per_brick; /* same, for the charged-pair kernel */
 } gcme_tuning;
 
 gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t);
@@ -183,11 +185,13 @@ gcme_status gcme_autotune(gcme_handle h);
  * kernel's own cutoff test at the state's positions.  Synchronous. */
 gcme_status gcme_count_pairs(gcme_handle h, uint64_t* n_pairs);
 
-/* Device time of each stage of one step, measured with HIP events recorded
- * between the stages on the context's stream while n_reps >= 1 steps run
- * eagerly (not from the graph); ms[i] is the mean over the steps (host array
- * of at least GCME_N_STAGES entries).  Advances the state by n_reps steps.
- * Synchronous.  gcme_stage_name(i) names stage i (NULL if out of range). */
+/* Device time of each stage of a step: the kernels of stage i are captured
+ * n_reps >= 1 times back to back into a HIP graph, which is replayed between
+ * two HIP events on the context's stream; ms[i] = elapsed / n_reps (host
+ * array of at least GCME_N_STAGES entries).  The state, forces and mesh are
+ * saved before and restored after, so the call leaves the simulation as it
+ * found it.  Synchronous.  gcme_stage_name(i) names stage i (NULL if out of
+ * range). */
 #define GCME_N_STAGES 12
 gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms);
 const char* gcme_stage_name(int32_t i);

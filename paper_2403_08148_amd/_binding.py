@@ -45,7 +45,8 @@ class gcme_io(C.Structure):
 
 
 class gcme_tuning(C.Structure):
-    _fields_ = [("cells_per_cutoff", C.c_int32), ("lanes_per_bead", C.c_int32), ("lanes_per_charge", C.c_int32)]
+    _fields_ = [("cells_per_cutoff", C.c_int32), ("lanes_per_bead", C.c_int32), ("lanes_per_charge", C.c_int32),
+                ("beads_per_brick", C.c_int32), ("charges_per_brick", C.c_int32)]
 
 
 class GCMeError(RuntimeError):

@@ -62,7 +62,8 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PER_THREAD = 4;
 constexpr int SCAN_BLOCK = SCAN_THREADS * SCAN_PER_THREAD;
 
-// Inclusive scan of one int per thread over a 256-thread block.
+// Inclusive scan of one int per thread over the block (blockDim.x a
+// multiple of 64, at most 1024).
 __device__ inline int block_inclusive_scan(int v, int* sh) {
   int lane = threadIdx.x & 63;
   int wid = threadIdx.x >> 6;
@@ -71,12 +72,52 @@ __device__ inline int block_inclusive_scan(int v, int* sh) {
     int t = __shfl_up(v, o, 64);
     if (lane >= o) v += t;
   }
+  __syncthreads();
   if (lane == 63) sh[wid] = v;
   __syncthreads();
   int add = 0;
   for (int w = 0; w < wid; ++w) add += sh[w];
-  __syncthreads();
   return v + add;
+}
+
+// Whole scan in one block for grids of up to SINGLE_SCAN_MAX cells: each
+// thread sums a contiguous chunk, one block scan, then each thread writes its
+// chunk.  Produces start (exclusive), the scatter cursor fill = start, and
+// the same for the charged counts.
+constexpr int SINGLE_SCAN_THREADS = 1024;
+constexpr int SINGLE_SCAN_MAX = 15872;
+
+// The counts pass through LDS: coalesced, independent global loads and
+// stores, and each thread's serial chunk runs at LDS latency.
+__global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c) {
+  __shared__ int sh[16];
+  __shared__ int buf[SINGLE_SCAN_MAX];
+  const int n = c.ncells;
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per, hi = min(lo + per, n);
+  for (int arr = 0; arr < 2; ++arr) {
+    const int* cnt = arr == 0 ? c.counts : c.qcounts;
+    int* st = arr == 0 ? c.start : c.qstart;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = cnt[i];
+    __syncthreads();
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += buf[i];
+    int inc = block_inclusive_scan(s, sh);
+    int run = inc - s;
+    for (int i = lo; i < hi; ++i) {
+      int v = buf[i];
+      buf[i] = run;
+      run += v;
+    }
+    if (threadIdx.x == blockDim.x - 1) st[n] = inc;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int v = buf[i];
+      st[i] = v;
+      if (arr == 0) c.fill[i] = v;
+    }
+    __syncthreads();
+  }
 }
 
 __global__ void k_scan_reduce(CellView c, int nb) {
@@ -144,7 +185,10 @@ __global__ void k_scan_apply(CellView c, int nb) {
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k) {
       int i = base + k;
-      if (i < c.ncells) st[i] = run;
+      if (i < c.ncells) {
+        st[i] = run;
+        if (arr == 0) c.fill[i] = run;
+      }
       run += v[k];
     }
     __syncthreads();
@@ -154,9 +198,8 @@ __global__ void k_scan_apply(CellView c, int nb) {
 __global__ void k_scatter(CellView c, int N) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N) return;
-  int cid = c.cell[s];
-  int slot = atomicAdd(&c.fill[cid], 1);
-  c.tmp[c.start[cid] + slot] = s;
+  // fill holds the cell's next free slot (initialised to start by the scan)
+  c.tmp[atomicAdd(&c.fill[c.cell[s]], 1)] = s;
 }
 
 // Position p of the scattered array holds bead s of cell c in arbitrary
@@ -164,6 +207,11 @@ __global__ void k_scatter(CellView c, int N) {
 // previous index).  Charged beads get the same rank among charged beads.
 __global__ void k_permute(StateView A, StateView B, CellView c, ChargedView q, int N) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
+  // the counts were consumed by the scan: clear them for the next binning
+  for (int k = p; k < c.ncells; k += gridDim.x * blockDim.x) {
+    c.counts[k] = 0;
+    c.qcounts[k] = 0;
+  }
   if (p >= N) return;
   int s = c.tmp[p];
   int cid = c.cell[s];
@@ -241,6 +289,10 @@ void launch_bin(hipStream_t s, StateView A, const RepDesc* rep, CellView c, int 
 }
 
 void launch_scan(hipStream_t s, CellView c) {
+  if (c.ncells <= SINGLE_SCAN_MAX) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SINGLE_SCAN_THREADS), 0, s, c);
+    return;
+  }
   int nb = nblk(c.ncells, SCAN_BLOCK);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, c, nb);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, c, nb);

@@ -95,6 +95,8 @@ struct gcme_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipStream_t cap_stream = nullptr;
+  hipStream_t aux[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int R = 0;
   std::vector<int> nb, boff;
   int N = 0;
@@ -109,7 +111,7 @@ struct gcme_ctx {
   std::vector<int> nq, qoff;
   int NQ = 0;
   // tuning
-  gcme_tuning tune{2, 4, 4};
+  gcme_tuning tune{2, 4, 4, 0, 0};
   bool plan_dirty = true;
   // device buffers
   DevBuf a_pos[3], a_vel[3], a_param, a_id;
@@ -121,7 +123,7 @@ struct gcme_ctx {
   DevBuf d_rep, d_gcm, d_elec, d_adj;
   DevBuf d_tw, d_rad, d_bsp, d_freq;
   DevBuf d_items[3];
-  DevBuf d_tiles_g, d_tiles_q, d_tiles_256;
+  DevBuf d_bricks_g, d_bricks_q, d_tiles_256;
   DevBuf part[N_SLOTS], adjp[2];
   DevBuf d_off[N_SLOTS], d_adj_off[2];
   DevBuf d_consts, d_Avals, d_dself;
@@ -130,7 +132,10 @@ struct gcme_ctx {
   // plan sizes
   int ncells = 0;
   long long grid_total = 0, cgrid_total = 0;
-  int ntiles_g = 0, ntiles_q = 0, ntiles_256 = 0;
+  int nbricks_g = 0, nbricks_q = 0, ntiles_256 = 0;
+  int lds_cap_g = 0, lds_cap_q = 0, lds_tab_g = 0, lds_tab_q = 0;
+  int thr_g = 256, thr_q = 256, colr_g = 0, colr_q = 0, ncol_max = 1;
+  int lds_budget = 61440;  // dynamic LDS per pair workgroup (device limit less static use)
   int nitems[3] = {0, 0, 0};
   int lb[3] = {0, 0, 0};
   int maxK[3] = {0, 0, 0};
@@ -141,6 +146,11 @@ struct gcme_ctx {
 
   ~gcme_ctx() {
     drop_graphs();
+    for (auto& e : ev_join)
+      if (e) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (auto& a : aux)
+      if (a) (void)hipStreamDestroy(a);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
@@ -344,6 +354,80 @@ void build_mesh_tables(gcme_handle h, std::vector<T>& tw, std::vector<T>& bsp, s
   }
 }
 
+// Split each replica's cell grid into bricks (one pair-kernel workgroup
+// each, or several for a brick much larger than the target).  The brick
+// shape aims at `target` home beads with the smallest staged neighbourhood
+// (brick plus reach on every side) per home cell, within the LDS budget.
+
+void plan_bricks(gcme_handle h, bool charged, int target, int colr_bytes, std::vector<Brick>& out, std::vector<int>& off,
+                 int& tab_bytes, int& cap) {
+  const size_t sb = pair_stage_bytes(h->fp64);
+  out.clear();
+  off.assign(h->R + 1, 0);
+  int max_ncn = 1;
+  double max_exp = 0.0;  // expected staged beads of the largest neighbourhood
+  for (int r = 0; r < h->R; ++r) {
+    const RepDesc& d = h->rep[r];
+    off[r] = (int)out.size();
+    const int n_r = charged ? h->nq[r] : h->nb[r];
+    if (n_r == 0) continue;
+    const double per_cell = (double)n_r / ((double)d.nc[0] * d.nc[1] * d.nc[2]);
+    int best[3] = {1, 1, 1};
+    double best_score = 1e300;
+    for (int bx = 1; bx <= std::min(8, d.nc[0]); ++bx)
+      for (int by = 1; by <= std::min(8, d.nc[1]); ++by) {
+        if (bx * by > 64) continue;
+        for (int bz = 1; bz <= std::min(16, d.nc[2]); ++bz) {
+          double nbr_cells = (double)(bx + 2 * d.nreach[0]) * (by + 2 * d.nreach[1]) * (bz + 2 * d.nreach[2]);
+          double home = bx * by * bz * per_cell;
+          double need = 16.0 * std::ceil((nbr_cells + 1) * 4 / 16.0) + (nbr_cells * per_cell * 1.5 + 64) * sb + colr_bytes;
+          if (need > h->lds_budget) continue;
+          // staging cost per home bead, plus a penalty for missing the target size
+          double score = nbr_cells / (bx * by * bz) + 4.0 * std::fabs(std::log2(std::max(home, 1e-3) / target));
+          if (score < best_score) {
+            best_score = score;
+            best[0] = bx;
+            best[1] = by;
+            best[2] = bz;
+          }
+        }
+      }
+    int ncn = (best[0] + 2 * d.nreach[0]) * (best[1] + 2 * d.nreach[1]) * (best[2] + 2 * d.nreach[2]);
+    max_ncn = std::max(max_ncn, ncn);
+    max_exp = std::max(max_exp, ncn * per_cell);
+    for (int x = 0; x < d.nc[0]; x += best[0])
+      for (int y = 0; y < d.nc[1]; y += best[1])
+        for (int z = 0; z < d.nc[2]; z += best[2]) {
+          Brick b{};
+          b.rep = r;
+          b.c0[0] = x;
+          b.c0[1] = y;
+          b.c0[2] = z;
+          b.nb[0] = std::min(best[0], d.nc[0] - x);
+          b.nb[1] = std::min(best[1], d.nc[1] - y);
+          b.nb[2] = std::min(best[2], d.nc[2] - z);
+          // a brick much larger than the target is shared by several
+          // workgroups, one slice of its home beads each
+          const double home = (double)b.nb[0] * b.nb[1] * b.nb[2] * per_cell;
+          const int S = std::max(1, (int)std::lround(home / target));
+          const int per = (int)std::ceil(home / S);
+          for (int s = 0; s < S; ++s) {
+            b.h0 = s * per;
+            b.hn = s == S - 1 ? (1 << 30) : per;
+            out.push_back(b);
+          }
+        }
+  }
+  off[h->R] = (int)out.size();
+  tab_bytes = 16 * (((max_ncn + 1) * 4 + 15) / 16);
+  // room for 1.5x the expected neighbourhood (many standard deviations of
+  // the bead count; a fuller brick takes the global-memory path), within the
+  // LDS budget: smaller footprints let more workgroups share a CU
+  const int fit = (int)((h->lds_budget - tab_bytes - colr_bytes) / (long long)sb);
+  cap = std::max(64, std::min(fit, (int)std::ceil(1.5 * max_exp + 64)));
+  cap = (cap + 3) & ~3;
+}
+
 gcme_status build_plan(gcme_handle h) {
   hipStream_t s = h->stream;
   HIPCHK(h, hipSetDevice(h->device));
@@ -369,6 +453,7 @@ gcme_status build_plan(gcme_handle h) {
       d.hf[k] = (float)hcell;
       int reach = (int)std::ceil(p.rc / hcell - 1e-9);
       d.reach[k] = (2 * reach + 1 > nc) ? -1 : reach;
+      d.nreach[k] = std::max(1, reach);
       d.K[k] = p.K[k];
     }
     d.V = p.box[0] * p.box[1] * p.box[2];
@@ -404,7 +489,13 @@ gcme_status build_plan(gcme_handle h) {
   // lines per mesh work item: two LDS buffers of LB+1 padded lines stay
   // below 64 KiB together with the kernels' static reduction buffer
   const int cap = h->fp64 ? 2048 : 4096;
-  for (int ps = 0; ps < 3; ++ps) h->lb[ps] = std::max(1, std::min(64, cap / h->maxK[ps] - 2));
+  // z lines are contiguous: about 1024 points per work item; strided y/x
+  // lines are batched along z (at least 8 adjacent lines for coalescing)
+  for (int ps = 0; ps < 3; ++ps) {
+    int want = ps == 0 ? std::max(1, 1024 / h->maxK[ps]) : std::max(8, 1024 / h->maxK[ps]);
+    int fit = cap / h->maxK[ps] - 2;
+    h->lb[ps] = std::max(1, std::min(64, std::min(want, fit)));
+  }
 
   // mesh tables
   std::vector<int> rad;
@@ -446,13 +537,16 @@ gcme_status build_plan(gcme_handle h) {
     const RepDesc& d = h->rep[r];
     int nlz = d.K[0] * d.K[1];
     for (int l = 0; l < nlz; l += h->lb[0]) items[0].push_back(LineItem{r, l, std::min(h->lb[0], nlz - l), 0});
+    // balanced batches of the K2/2+1 strided lines
+    int c1 = (d.K2h + h->lb[1] - 1) / h->lb[1], b1 = (d.K2h + c1 - 1) / c1;
+    int c2 = (d.K2h + h->lb[2] - 1) / h->lb[2], b2 = (d.K2h + c2 - 1) / c2;
     for (int x = 0; x < d.K[0]; ++x)
-      for (int kz = 0; kz < d.K2h; kz += h->lb[1])
-        items[1].push_back(LineItem{r, x * d.K2h + kz, std::min(h->lb[1], d.K2h - kz), 0});
+      for (int kz = 0; kz < d.K2h; kz += b1)
+        items[1].push_back(LineItem{r, x * d.K2h + kz, std::min(b1, d.K2h - kz), 0});
     item_off[r] = (int)items[2].size();
     for (int y = 0; y < d.K[1]; ++y)
-      for (int kz = 0; kz < d.K2h; kz += h->lb[2])
-        items[2].push_back(LineItem{r, y * d.K2h + kz, std::min(h->lb[2], d.K2h - kz), 0});
+      for (int kz = 0; kz < d.K2h; kz += b2)
+        items[2].push_back(LineItem{r, y * d.K2h + kz, std::min(b2, d.K2h - kz), 0});
   }
   item_off[R] = (int)items[2].size();
   for (int ps = 0; ps < 3; ++ps) {
@@ -462,14 +556,29 @@ gcme_status build_plan(gcme_handle h) {
 
   // tiles
   std::vector<int> toff_g, toff_q, toff_256;
-  std::vector<Tile> tg = make_tiles(h->boff, h->nb, 256 / h->tune.lanes_per_bead, toff_g);
-  std::vector<Tile> tq = make_tiles(h->qoff, h->nq, 256 / h->tune.lanes_per_charge, toff_q);
+  std::vector<Brick> bg, bq;
+  // workgroup: 64 home beads per pass for several lanes per bead (up to 1024
+  // threads), 256 threads otherwise; the column-range list holds one entry per
+  // neighbourhood column for every bead of a pass
+  h->ncol_max = 1;
+  for (const RepDesc& d : h->rep) h->ncol_max = std::max(h->ncol_max, (2 * d.nreach[0] + 1) * (2 * d.nreach[1] + 1));
+  auto threads_for = [](int tpa) { return std::min(1024, std::max(256, 128 * tpa)); };
+  h->thr_g = threads_for(h->tune.lanes_per_bead);
+  h->thr_q = threads_for(h->tune.lanes_per_charge);
+  const int pass_g = h->thr_g / h->tune.lanes_per_bead, pass_q = h->thr_q / h->tune.lanes_per_charge;
+  // column lists plus the per-lane hit queues
+  h->colr_g = (h->tune.lanes_per_bead > 1 ? pass_g * h->ncol_max * 4 : 0) + pair_queue_bytes(h->thr_g);
+  h->colr_q = (h->tune.lanes_per_charge > 1 ? pass_q * h->ncol_max * 4 : 0) + pair_queue_bytes(h->thr_q);
+  int tgt_g = h->tune.beads_per_brick > 0 ? h->tune.beads_per_brick : pass_g;
+  int tgt_q = h->tune.charges_per_brick > 0 ? h->tune.charges_per_brick : pass_q;
+  plan_bricks(h, false, tgt_g, h->colr_g, bg, toff_g, h->lds_tab_g, h->lds_cap_g);
+  plan_bricks(h, true, tgt_q, h->colr_q, bq, toff_q, h->lds_tab_q, h->lds_cap_q);
   std::vector<Tile> t256 = make_tiles(h->boff, h->nb, 256, toff_256);
-  h->ntiles_g = (int)tg.size();
-  h->ntiles_q = (int)tq.size();
+  h->nbricks_g = (int)bg.size();
+  h->nbricks_q = (int)bq.size();
   h->ntiles_256 = (int)t256.size();
-  upload(tg, h->d_tiles_g, s);
-  upload(tq, h->d_tiles_q, s);
+  upload(bg, h->d_bricks_g, s);
+  upload(bq, h->d_bricks_q, s);
   upload(t256, h->d_tiles_256, s);
   upload(toff_g, h->d_off[SLOT_GCM], s);
   upload(toff_q, h->d_off[SLOT_REAL], s);
@@ -477,12 +586,12 @@ gcme_status build_plan(gcme_handle h) {
   upload(toff_256, h->d_off[SLOT_KIN], s);
   upload(toff_g, h->d_adj_off[0], s);
   upload(toff_q, h->d_adj_off[1], s);
-  HIPCHK(h, h->part[SLOT_GCM].alloc((size_t)std::max(1, h->ntiles_g) * PART_W * 8));
-  HIPCHK(h, h->part[SLOT_REAL].alloc((size_t)std::max(1, h->ntiles_q) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_GCM].alloc((size_t)std::max(1, h->nbricks_g) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_REAL].alloc((size_t)std::max(1, h->nbricks_q) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_RECIP].alloc((size_t)std::max(1, h->nitems[2]) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_KIN].alloc((size_t)std::max(1, h->ntiles_256) * PART_W * 8));
-  HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->ntiles_g) * (MAXT * MAXT + 2 * MAXT) * 8));
-  HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->ntiles_q) * (MAXT * MAXT + 2 * MAXT) * 8));
+  HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->nbricks_g) * (MAXT * MAXT + 2 * MAXT) * 8));
+  HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->nbricks_q) * (MAXT * MAXT + 2 * MAXT) * 8));
 
   // cells
   int nbs = (h->ncells + 1023) / 1024;
@@ -492,6 +601,8 @@ gcme_status build_plan(gcme_handle h) {
   HIPCHK(h, h->start.alloc((size_t)(h->ncells + 1) * 4));
   HIPCHK(h, h->qstart.alloc((size_t)(h->ncells + 1) * 4));
   HIPCHK(h, h->bsum.alloc((size_t)2 * (nbs + 1) * 4));
+  HIPCHK(h, hipMemsetAsync(h->counts.p, 0, (size_t)h->ncells * 4, s));
+  HIPCHK(h, hipMemsetAsync(h->qcounts.p, 0, (size_t)h->ncells * 4, s));
 
   // meshes (Q must start cleared; the z pass clears it after each use)
   HIPCHK(h, h->Qint.alloc((size_t)h->grid_total * 8));
@@ -549,9 +660,16 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
   for (int k = 0; k < 3; ++k) a.F[k] = Fk(h, k);
   a.status = h->d_status.as<unsigned>();
   a.fscale = h->fscale();
+  const size_t sb = pair_stage_bytes(h->fp64);
   if (charged) {
-    a.tiles = h->d_tiles_q.as<Tile>();
-    a.ntiles = h->ntiles_q;
+    a.bricks = h->d_bricks_q.as<Brick>();
+    a.nbricks = h->nbricks_q;
+    a.lds_cap = h->lds_cap_q;
+    a.lds_tab_bytes = h->lds_tab_q;
+    a.lds_bytes = (size_t)h->lds_tab_q + (size_t)h->lds_cap_q * sb + (size_t)h->colr_q;
+    a.threads = h->thr_q;
+    a.ncol_max = h->ncol_max;
+    a.lds_q_off = (int)(a.lds_bytes - pair_queue_bytes(h->thr_q));
     for (int k = 0; k < 3; ++k) a.pos[k] = h->q_pos[k].as<uint32_t>();
     a.param = h->q_param.as<uint32_t>();
     a.start = h->qstart.as<int>();
@@ -559,8 +677,14 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.part = h->part[SLOT_REAL].as<double>();
     a.adj_part = h->adjp[1].as<double>();
   } else {
-    a.tiles = h->d_tiles_g.as<Tile>();
-    a.ntiles = h->ntiles_g;
+    a.bricks = h->d_bricks_g.as<Brick>();
+    a.nbricks = h->nbricks_g;
+    a.lds_cap = h->lds_cap_g;
+    a.lds_tab_bytes = h->lds_tab_g;
+    a.lds_bytes = (size_t)h->lds_tab_g + (size_t)h->lds_cap_g * sb + (size_t)h->colr_g;
+    a.threads = h->thr_g;
+    a.ncol_max = h->ncol_max;
+    a.lds_q_off = (int)(a.lds_bytes - pair_queue_bytes(h->thr_g));
     for (int k = 0; k < 3; ++k) a.pos[k] = h->b_pos[k].as<uint32_t>();
     a.param = h->b_param.as<uint32_t>();
     a.start = h->start.as<int>();
@@ -620,10 +744,8 @@ IntLaunch int_args(gcme_handle h) {
 
 // Sort the state A into B by cell (and the charged copy), on stream s.
 void enqueue_sort(gcme_handle h, hipStream_t s) {
+  // counts are left cleared by the previous permute (and at plan build)
   CellView c = cview(h);
-  launch_fill_i32(s, c.counts, 0, h->ncells);
-  launch_fill_i32(s, c.qcounts, 0, h->ncells);
-  launch_fill_i32(s, c.fill, 0, h->ncells);
   launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
   launch_scan(s, c);
   launch_scatter(s, c, h->N);
@@ -631,21 +753,34 @@ void enqueue_sort(gcme_handle h, hipStream_t s) {
 }
 
 // Forces (and partial sums if ev) on the sorted copy B; F must be cleared.
+// The excluded-volume kernel, the charged real-space kernel and the mesh
+// chain are independent and all add into the integer force accumulator, so
+// they run as three concurrent branches (fork/join with events; captured as
+// parallel graph branches).
 void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   PairLaunch g = pair_args(h, false);
-  launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, ev, adj);
-  if (h->NQ > 0) {
-    PairLaunch q = pair_args(h, true);
-    launch_pair_elec(s, q, h->fp64, h->tune.lanes_per_charge, ev, adj);
-    PmeLaunch p = pme_args(h);
-    launch_spread(s, p, h->fp64);
-    launch_fft_z_r2c(s, p, h->fp64);
-    launch_fft_y(s, p, h->fp64, false);
-    launch_fft_x_conv(s, p, h->fp64, ev);
-    launch_fft_y(s, p, h->fp64, true);
-    launch_fft_z_c2r(s, p, h->fp64);
-    launch_gather(s, p, h->fp64);
+  if (h->NQ == 0) {
+    launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, ev, adj);
+    return;
   }
+  (void)hipEventRecord(h->ev_fork, s);
+  (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
+  (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
+  PmeLaunch p = pme_args(h);
+  launch_spread(h->aux[1], p, h->fp64);
+  launch_fft_z_r2c(h->aux[1], p, h->fp64);
+  launch_fft_y(h->aux[1], p, h->fp64, false);
+  launch_fft_x_conv(h->aux[1], p, h->fp64, ev);
+  launch_fft_y(h->aux[1], p, h->fp64, true);
+  launch_fft_z_c2r(h->aux[1], p, h->fp64);
+  launch_gather(h->aux[1], p, h->fp64);
+  PairLaunch q = pair_args(h, true);
+  launch_pair_elec(h->aux[0], q, h->fp64, h->tune.lanes_per_charge, ev, adj);
+  launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, ev, adj);
+  (void)hipEventRecord(h->ev_join[0], h->aux[0]);
+  (void)hipEventRecord(h->ev_join[1], h->aux[1]);
+  (void)hipStreamWaitEvent(s, h->ev_join[0], 0);
+  (void)hipStreamWaitEvent(s, h->ev_join[1], 0);
 }
 
 void enqueue_outputs(gcme_handle h, hipStream_t s, const gcme_io* io, bool kin) {
@@ -769,6 +904,11 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   h->tune.lanes_per_bead = total < 200000 ? 4 : 1;
   h->tune.lanes_per_charge = total < 200000 ? 4 : 2;
   h->tune.cells_per_cutoff = 2;
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lds > 0)
+      h->lds_budget = std::max(16384, lds - 4096);
+  }
   if (info->stream) {
     h->stream = (hipStream_t)info->stream;
   } else {
@@ -778,9 +918,13 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
     }
     h->own_stream = true;
   }
-  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  bool sok = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) == hipSuccess;
+  for (auto& a : h->aux) sok &= hipStreamCreateWithFlags(&a, hipStreamNonBlocking) == hipSuccess;
+  sok &= hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (auto& e : h->ev_join) sok &= hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!sok) {
     delete h;
-    return fail(nullptr, GCME_EDEVICE, "stream creation failed");
+    return fail(nullptr, GCME_EDEVICE, "stream/event creation failed");
   }
   const size_t N = (size_t)h->N;
   bool ok = true;
@@ -1068,8 +1212,17 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
     if (!okl(t->lanes_per_charge)) return fail(h, GCME_EINVAL, "lanes_per_charge in {1,2,4,8,16}");
     n.lanes_per_charge = t->lanes_per_charge;
   }
+  if (t->beads_per_brick >= 0) {
+    if (t->beads_per_brick > 4096) return fail(h, GCME_EINVAL, "beads_per_brick in 0..4096");
+    n.beads_per_brick = t->beads_per_brick;
+  }
+  if (t->charges_per_brick >= 0) {
+    if (t->charges_per_brick > 4096) return fail(h, GCME_EINVAL, "charges_per_brick in 0..4096");
+    n.charges_per_brick = t->charges_per_brick;
+  }
   if (n.cells_per_cutoff != h->tune.cells_per_cutoff || n.lanes_per_bead != h->tune.lanes_per_bead ||
-      n.lanes_per_charge != h->tune.lanes_per_charge) {
+      n.lanes_per_charge != h->tune.lanes_per_charge || n.beads_per_brick != h->tune.beads_per_brick ||
+      n.charges_per_brick != h->tune.charges_per_brick) {
     h->tune = n;
     h->plan_dirty = true;
     h->drop_graphs();
@@ -1125,7 +1278,7 @@ gcme_status gcme_autotune(gcme_handle h) {
     for (int lpb : lpb_list) {
       for (int lpq : lpq_list) {
         if (lpq != lpb && lpq != 2 * lpb && 2 * lpq != lpb) continue;
-        gcme_tuning t{ncc, lpb, lpq};
+        gcme_tuning t{ncc, lpb, lpq, 0, 0};
         if (gcme_set_tuning(h, &t) != GCME_OK) continue;
         if (build_plan(h) != GCME_OK) continue;
         float ms = 0;
@@ -1170,55 +1323,75 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
   st = ensure_forces(h);
   if (st != GCME_OK) return st;
   hipStream_t s = h->stream;
-  hipEvent_t ev[GCME_N_STAGES + 1];
-  for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
-  for (int i = 0; i < GCME_N_STAGES; ++i) ms[i] = 0.0;
+  const size_t N = (size_t)h->N;
+  // save what the repeated stages disturb
+  DevBuf sp[3], sv[3], sF;
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(h, sp[k].alloc(N * 4));
+    HIPCHK(h, sv[k].alloc(N * 8));
+    HIPCHK(h, hipMemcpyAsync(sp[k].p, h->a_pos[k].p, N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(sv[k].p, h->a_vel[k].p, N * 8, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(h, sF.alloc(N * 24));
+  HIPCHK(h, hipMemcpyAsync(sF.p, h->F.p, N * 24, hipMemcpyDeviceToDevice, s));
+  enqueue_sort(h, s);
   IntLaunch ia = int_args(h);
   long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
-  for (int rep = 0; rep < n_reps; ++rep) {
-    int k = 0;
-    (void)hipEventRecord(ev[k++], s);
-    launch_int_first(s, ia, viewA(h), F3);
-    (void)hipEventRecord(ev[k++], s);
-    enqueue_sort(h, s);
-    (void)hipEventRecord(ev[k++], s);
-    PairLaunch g = pair_args(h, false);
-    launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, false, false);
-    (void)hipEventRecord(ev[k++], s);
-    PmeLaunch p = pme_args(h);
-    if (h->NQ > 0) {
-      PairLaunch q = pair_args(h, true);
-      launch_pair_elec(s, q, h->fp64, h->tune.lanes_per_charge, false, false);
-      (void)hipEventRecord(ev[k++], s);
-      launch_spread(s, p, h->fp64);
-      (void)hipEventRecord(ev[k++], s);
-      launch_fft_z_r2c(s, p, h->fp64);
-      (void)hipEventRecord(ev[k++], s);
-      launch_fft_y(s, p, h->fp64, false);
-      (void)hipEventRecord(ev[k++], s);
-      launch_fft_x_conv(s, p, h->fp64, false);
-      (void)hipEventRecord(ev[k++], s);
-      launch_fft_y(s, p, h->fp64, true);
-      (void)hipEventRecord(ev[k++], s);
-      launch_fft_z_c2r(s, p, h->fp64);
-      (void)hipEventRecord(ev[k++], s);
-      launch_gather(s, p, h->fp64);
-      (void)hipEventRecord(ev[k++], s);
-    } else {
-      for (int j = 0; j < 8; ++j) (void)hipEventRecord(ev[k++], s);
+  PairLaunch g = pair_args(h, false);
+  PairLaunch q = pair_args(h, true);
+  PmeLaunch p = pme_args(h);
+  auto stage = [&](int i, hipStream_t st2) {
+    switch (i) {
+      case 0: launch_int_first(st2, ia, viewA(h), F3); break;
+      case 1: enqueue_sort(h, st2); break;
+      case 2: launch_pair_gcm(st2, g, h->fp64, h->tune.lanes_per_bead, false, false); break;
+      case 3: launch_pair_elec(st2, q, h->fp64, h->tune.lanes_per_charge, false, false); break;
+      case 4: launch_spread(st2, p, h->fp64); break;
+      case 5: launch_fft_z_r2c(st2, p, h->fp64); break;
+      case 6: launch_fft_y(st2, p, h->fp64, false); break;
+      case 7: launch_fft_x_conv(st2, p, h->fp64, false); break;
+      case 8: launch_fft_y(st2, p, h->fp64, true); break;
+      case 9: launch_fft_z_c2r(st2, p, h->fp64); break;
+      case 10: launch_gather(st2, p, h->fp64); break;
+      default: launch_int_last(st2, ia, viewB(h), viewA(h), F3, false); break;
     }
-    launch_int_last(s, ia, viewB(h), viewA(h), F3, false);
-    (void)hipEventRecord(ev[k++], s);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipEventSynchronize(ev[GCME_N_STAGES]));
-    for (int i = 0; i < GCME_N_STAGES; ++i) {
-      float m = 0;
-      (void)hipEventElapsedTime(&m, ev[i], ev[i + 1]);
-      ms[i] += m / n_reps;
-    }
+  };
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  for (int i = 0; i < GCME_N_STAGES; ++i) {
+    ms[i] = 0.0;
+    if (h->NQ == 0 && i >= 3 && i <= 10) continue;
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ex = nullptr;
+    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < n_reps; ++r) stage(i, h->cap_stream);
+    HIPCHK(h, hipStreamEndCapture(h->cap_stream, &gr));
+    HIPCHK(h, hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(gr);
+    HIPCHK(h, hipGraphLaunch(ex, s));
+    HIPCHK(h, hipEventRecord(e0, s));
+    HIPCHK(h, hipGraphLaunch(ex, s));
+    HIPCHK(h, hipEventRecord(e1, s));
+    HIPCHK(h, hipEventSynchronize(e1));
+    float m = 0;
+    HIPCHK(h, hipEventElapsedTime(&m, e0, e1));
+    ms[i] = (double)m / n_reps;
+    (void)hipGraphExecDestroy(ex);
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
-  h->step += (uint64_t)n_reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // restore
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(h, hipMemcpyAsync(h->a_pos[k].p, sp[k].p, N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->a_vel[k].p, sv[k].p, N * 8, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(h, hipMemcpyAsync(h->F.p, sF.p, N * 24, hipMemcpyDeviceToDevice, s));
+  launch_fill_i64(s, h->Qint.as<long long>(), 0, h->grid_total);
+  unsigned long long stepv = h->step;
+  HIPCHK(h, hipMemcpyAsync(h->d_step.p, &stepv, 8, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemsetAsync(h->d_status.p, 0, 4, s));
+  HIPCHK(h, hipStreamSynchronize(s));
   return GCME_OK;
 }
 

@@ -29,6 +29,7 @@ struct RepDesc {
   float hf[3];        // cell edge
   int nc[3];          // cells per axis
   int reach[3];       // stencil half-width in cells; -1 = take the whole axis
+  int nreach[3];      // ceil(rc / cell edge): neighbourhood half-width of a brick
   int cell_off;       // first global cell id
   int bead_off, n;    // bead range in the concatenated arrays
   int q_off, nq;      // charged-bead range in the compacted charged arrays
@@ -81,6 +82,18 @@ struct LineItem {
   int first;
   int count;
   int pad;
+};
+
+// A brick of cells and a range of its home beads (one workgroup of the
+// pair kernels; a large brick is shared by several workgroups, each staging
+// the same neighbourhood and taking its own slice of the home beads).
+struct Brick {
+  int rep;
+  int c0[3];   // first cell per axis
+  int nb[3];   // cells per axis
+  int h0;      // first home bead of this workgroup (in the brick's home order)
+  int hn;      // home beads of this workgroup (the last slice takes the rest)
+  int pad[3];
 };
 
 // Tiles of consecutive beads of one replica (per-bead kernels).
@@ -150,8 +163,14 @@ void launch_commit(hipStream_t s, StateView B, StateView A, int N);
 // pair.hip
 struct PairLaunch {
   const RepDesc* rep;
-  const Tile* tiles;
-  int ntiles;
+  const Brick* bricks;
+  int nbricks;
+  int lds_cap;         // staged beads per brick
+  int lds_tab_bytes;   // LDS bytes of the cell prefix table (16-aligned)
+  size_t lds_bytes;    // dynamic LDS per workgroup
+  int threads;         // workgroup size
+  int ncol_max;        // column-range list entries per bead (lanes_per_bead > 1)
+  int lds_q_off;       // byte offset of the per-lane hit queues
   const void* gcm;     // GcmPar<T>[R][MAXT][MAXT]
   const void* elec;    // ElecPar<T>[R][MAXT][MAXT]
   const void* adj;     // AdjPar<T>[R][MAXT][MAXT]
@@ -168,6 +187,8 @@ struct PairLaunch {
 };
 void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, int tpa, bool ev, bool adjoint);
 void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, int tpa, bool ev, bool adjoint);
+size_t pair_stage_bytes(bool fp64);  // LDS bytes per staged bead
+int pair_queue_bytes(int threads);    // LDS bytes of the per-lane hit queues
 
 // pme.hip
 struct PmeLaunch {

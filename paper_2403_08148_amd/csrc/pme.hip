@@ -65,10 +65,14 @@ __device__ inline void mesh_coord(uint32_t u, int K, int& k, T& t) {
   t = (T)((double)(uint32_t)(p & 0xffffffffu) * 2.3283064365386963e-10);
 }
 
+// Eight lanes per charged bead: lane j0 < P of the group handles the
+// x-slab j0 of the P^3 stencil (the others idle), which gives the small
+// charged sets enough lanes to hide the atomics' latency.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_spread(PmeLaunch a, int nq) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = t >> 3, j0 = t & 7;
+  if (q >= nq || j0 >= P) return;
   uint32_t prm = a.qparam[q];
   const RepDesc& R = a.rep[param_rep(prm)];
   T w[3][P], dw[P];
@@ -88,7 +92,7 @@ __global__ __launch_bounds__(256) void k_spread(PmeLaunch a, int nq) {
     int g = k0[2] - j;
     g2s[j] = g < 0 ? g + K2 : g;
   }
-  for (int j0 = 0; j0 < P; ++j0) {
+  {
     int g0 = k0[0] - j0;
     g0 += g0 < 0 ? K0 : 0;
     T a0 = z * w[0][j0];
@@ -325,10 +329,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_c2r(PmeLaunch a) {
   }
 }
 
+// Eight lanes per charged bead (x-slab j0 per lane), partial gradients
+// combined with xor shuffles in a fixed order.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_gather(PmeLaunch a, int nq) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q0 = t >> 3, j0 = t & 7;
+  const bool active = q0 < nq && j0 < P;
+  const int q = q0 < nq ? q0 : nq - 1;
   uint32_t prm = a.qparam[q];
   const RepDesc& R = a.rep[param_rep(prm)];
   T w[3][P], dw[3][P];
@@ -348,7 +356,7 @@ __global__ __launch_bounds__(256) void k_gather(PmeLaunch a, int nq) {
     g2s[j] = g < 0 ? g + K2 : g;
   }
   T gx = 0, gy = 0, gz = 0;
-  for (int j0 = 0; j0 < P; ++j0) {
+  if (active) {
     int g0 = k0[0] - j0;
     g0 += g0 < 0 ? K0 : 0;
     for (int j1 = 0; j1 < P; ++j1) {
@@ -367,6 +375,13 @@ __global__ __launch_bounds__(256) void k_gather(PmeLaunch a, int nq) {
       gz += w[0][j0] * w[1][j1] * s2;
     }
   }
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) {
+    gx += __shfl_xor(gx, o, 64);
+    gy += __shfl_xor(gy, o, 64);
+    gz += __shfl_xor(gz, o, 64);
+  }
+  if (q0 >= nq || j0 != 0) return;
   const double c = -R.lB * (double)param_z(prm);
   const int bi = a.qidx[q];
   double f[3] = {c * (double)gx * K0 / R.L[0], c * (double)gy * K1 / R.L[1], c * (double)gz * K2 / R.L[2]};
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(256) void k_gather(PmeLaunch a, int nq) {
 
 template <typename T>
 void spread_p(hipStream_t s, const PmeLaunch& a, int p, int nq) {
-  dim3 g((nq + 255) / 256), b(256);
+  dim3 g((8 * nq + 255) / 256), b(256);
   switch (p) {
     case 3: hipLaunchKernelGGL((k_spread<T, 3>), g, b, 0, s, a, nq); break;
     case 4: hipLaunchKernelGGL((k_spread<T, 4>), g, b, 0, s, a, nq); break;
@@ -397,7 +412,7 @@ void spread_p(hipStream_t s, const PmeLaunch& a, int p, int nq) {
 
 template <typename T>
 void gather_p(hipStream_t s, const PmeLaunch& a, int p, int nq) {
-  dim3 g((nq + 255) / 256), b(256);
+  dim3 g((8 * nq + 255) / 256), b(256);
   switch (p) {
     case 3: hipLaunchKernelGGL((k_gather<T, 3>), g, b, 0, s, a, nq); break;
     case 4: hipLaunchKernelGGL((k_gather<T, 4>), g, b, 0, s, a, nq); break;

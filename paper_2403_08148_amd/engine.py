@@ -54,8 +54,10 @@ class GCMe:
         self.N = sum(self.n_beads)
         self.device = torch.device("cuda", device)
         self.precision = precision
-        if stream is None:
-            stream = torch.cuda.current_stream(self.device)
+        if stream is None or stream.cuda_stream == 0:
+            # a dedicated (non-default) torch stream: handle 0 would mean
+            # "library-owned stream" to the C ABI, invisible to torch events
+            stream = torch.cuda.Stream(device=self.device)
         self.stream = stream
         nb = (C.c_int32 * self.R)(*self.n_beads)
         info = B.gcme_create_info(self.R, C.cast(nb, C.POINTER(C.c_int32)),
@@ -119,12 +121,18 @@ class GCMe:
 
     # -- evaluation -------------------------------------------------------
     def _io(self, pos=None, force=True, energy=True, virial=True, adjoint=False):
+        with self.torch.cuda.stream(self.stream):
+            return self._io_on_stream(pos, force, energy, virial, adjoint)
+
+    def _io_on_stream(self, pos, force, energy, virial, adjoint):
         torch = self.torch
         out = {}
         keep = []
         io = B.gcme_io()
         if pos is not None:
             p = self._soa(pos)
+            # the engine reads it asynchronously on its stream
+            p.record_stream(self.stream)
             keep.append(p)
             io.pos = p.data_ptr()
         if force:
@@ -171,15 +179,18 @@ class GCMe:
         t = B.gcme_tuning()
         B.check(self.h, self.lib.gcme_get_tuning(self.h, C.byref(t)))
         return dict(cells_per_cutoff=t.cells_per_cutoff, lanes_per_bead=t.lanes_per_bead,
-                    lanes_per_charge=t.lanes_per_charge)
+                    lanes_per_charge=t.lanes_per_charge, beads_per_brick=t.beads_per_brick,
+                    charges_per_brick=t.charges_per_brick)
 
-    def set_tuning(self, cells_per_cutoff=-1, lanes_per_bead=-1, lanes_per_charge=-1):
-        t = B.gcme_tuning(cells_per_cutoff, lanes_per_bead, lanes_per_charge)
+    def set_tuning(self, cells_per_cutoff=-1, lanes_per_bead=-1, lanes_per_charge=-1, beads_per_brick=-1,
+                   charges_per_brick=-1):
+        t = B.gcme_tuning(cells_per_cutoff, lanes_per_bead, lanes_per_charge, beads_per_brick, charges_per_brick)
         B.check(self.h, self.lib.gcme_set_tuning(self.h, C.byref(t)))
 
     def profile_step(self, n_reps: int = 10) -> dict:
-        """Mean device time (ms) of each stage of a step, HIP events between
-        stages on the engine's stream (advances the state by n_reps steps)."""
+        """Device time (ms) of each stage of a step: the stage's kernels are
+        replayed n_reps times back to back from a HIP graph between two HIP
+        events on the engine's stream (state, forces and mesh restored)."""
         ms = (C.c_double * B.GCME_N_STAGES)()
         B.check(self.h, self.lib.gcme_profile_step(self.h, int(n_reps), ms))
         return {self.lib.gcme_stage_name(i).decode(): ms[i] for i in range(B.GCME_N_STAGES)}

@@ -52,3 +52,16 @@ def rel_rms(a, b):
 
 def rel(a, b, floor=1e-12):
     return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), floor)
+
+
+def energy_errors(got5, ref5):
+    """Errors of [E_ex, E_real, E_recip, E_corr, E_self]: relative per term,
+    except E_real, which is a sum of nearly cancelling signed pair terms and
+    is measured on the electrostatic energy scale |E_real| + |E_recip| +
+    |E_corr| + |E_self| (the magnitudes that make up U_elec)."""
+    got5, ref5 = np.asarray(got5, dtype=float), np.asarray(ref5, dtype=float)
+    err = rel(got5, ref5)
+    scale = np.abs(ref5[1:5]).sum()
+    if scale > 0:
+        err[1] = abs(got5[1] - ref5[1]) / scale
+    return err
