@@ -163,13 +163,13 @@ gcme_status gcme_sync(gcme_handle h);
 const char* gcme_last_error(gcme_handle h);
 
 /* Tuning knobs picked by the autotuner (exposed for benchmarks and tests).
- * Any field < 0 means "leave as is". */
+ * Any field < 0 means "leave as is".  The pair kernels work on clusters of
+ * consecutive cell-sorted beads with one neighbour list per cluster. */
 typedef struct {
-    int32_t cells_per_cutoff;  /* cell edge ~ rc / n (1..4) */
-    int32_t lanes_per_bead;    /* lanes sharing one bead's neighbour scan (1,2,4,8,16) */
-    int32_t lanes_per_charge;  /* same, for the charged-pair kernel */
-    int32_t beads_per_brick;   /* target home beads per pair workgroup (0 = 256/lanes) */
-    int32_t charges_per_brick; /* same, for the charged-pair kernel */
+    int32_t cells_per_cutoff;    /* cell edge ~ rc / n (1..4) */
+    int32_t beads_per_cluster;   /* excluded-volume cluster size (2, 4, 8) */
+    int32_t charges_per_cluster; /* real-space electrostatics cluster size (2, 4, 8) */
+    int32_t list_slack_pct;      /* list capacity above the density estimate, % (0..1000) */
 } gcme_tuning;
 
 gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t);
@@ -192,7 +192,7 @@ gcme_status gcme_count_pairs(gcme_handle h, uint64_t* n_pairs);
  * saved before and restored after, so the call leaves the simulation as it
  * found it.  Synchronous.  gcme_stage_name(i) names stage i (NULL if out of
  * range). */
-#define GCME_N_STAGES 12
+#define GCME_N_STAGES 14
 gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms);
 const char* gcme_stage_name(int32_t i);
 

@@ -111,7 +111,7 @@ struct gcme_ctx {
   std::vector<int> nq, qoff;
   int NQ = 0;
   // tuning
-  gcme_tuning tune{2, 4, 4, 0, 0};
+  gcme_tuning tune{3, 4, 4, 50};
   bool plan_dirty = true;
   // device buffers
   DevBuf a_pos[3], a_vel[3], a_param, a_id;
@@ -123,7 +123,8 @@ struct gcme_ctx {
   DevBuf d_rep, d_gcm, d_elec, d_adj;
   DevBuf d_tw, d_rad, d_bsp, d_freq;
   DevBuf d_items[3];
-  DevBuf d_bricks_g, d_bricks_q, d_tiles_256;
+  DevBuf d_cl_g, d_cl_q, d_tiles_g, d_tiles_q, d_tiles_256;
+  DevBuf list_g, list_q, cnt_g, cnt_q;
   DevBuf part[N_SLOTS], adjp[2];
   DevBuf d_off[N_SLOTS], d_adj_off[2];
   DevBuf d_consts, d_Avals, d_dself;
@@ -132,10 +133,8 @@ struct gcme_ctx {
   // plan sizes
   int ncells = 0;
   long long grid_total = 0, cgrid_total = 0;
-  int nbricks_g = 0, nbricks_q = 0, ntiles_256 = 0;
-  int lds_cap_g = 0, lds_cap_q = 0, lds_tab_g = 0, lds_tab_q = 0;
-  int thr_g = 256, thr_q = 256, colr_g = 0, colr_q = 0, ncol_max = 1;
-  int lds_budget = 61440;  // dynamic LDS per pair workgroup (device limit less static use)
+  int ncl_g = 0, ncl_q = 0, ntiles_g = 0, ntiles_q = 0, ntiles_256 = 0;
+  int cap_g = 64, cap_q = 64;
   int nitems[3] = {0, 0, 0};
   int lb[3] = {0, 0, 0};
   int maxK[3] = {0, 0, 0};
@@ -354,78 +353,48 @@ void build_mesh_tables(gcme_handle h, std::vector<T>& tw, std::vector<T>& bsp, s
   }
 }
 
-// Split each replica's cell grid into bricks (one pair-kernel workgroup
-// each, or several for a brick much larger than the target).  The brick
-// shape aims at `target` home beads with the smallest staged neighbourhood
-// (brick plus reach on every side) per home cell, within the LDS budget.
-
-void plan_bricks(gcme_handle h, bool charged, int target, int colr_bytes, std::vector<Brick>& out, std::vector<int>& off,
-                 int& tab_bytes, int& cap) {
-  const size_t sb = pair_stage_bytes(h->fp64);
-  out.clear();
-  off.assign(h->R + 1, 0);
-  int max_ncn = 1;
-  double max_exp = 0.0;  // expected staged beads of the largest neighbourhood
+// Clusters of `ci` consecutive beads of each replica's sorted population
+// (all beads, or the compacted charged beads), tiled in groups of
+// pair_waves_per_block() clusters of one replica (one pair-kernel workgroup
+// each, one partial-sum row per workgroup).  The list capacity per cluster is
+// bounded from the population density: a cluster fills its cell column over
+// roughly ci / (rho h^2) (plus up to two cells, since beads within a cell are
+// not ordered in z), and its list is at most the population inside the
+// cutoff shell of that box; the slack covers density fluctuations, and a
+// list that still overflows is reported as GCME_EOVERFLOW.
+void plan_clusters(gcme_handle h, bool charged, int ci, std::vector<int2>& cl, std::vector<Tile>& tiles,
+                   std::vector<int>& toff, int& cap) {
+  const int wpb = pair_waves_per_block();
+  cl.clear();
+  tiles.clear();
+  toff.assign(h->R + 1, 0);
+  double cmax = 64.0;
   for (int r = 0; r < h->R; ++r) {
     const RepDesc& d = h->rep[r];
-    off[r] = (int)out.size();
-    const int n_r = charged ? h->nq[r] : h->nb[r];
-    if (n_r == 0) continue;
-    const double per_cell = (double)n_r / ((double)d.nc[0] * d.nc[1] * d.nc[2]);
-    int best[3] = {1, 1, 1};
-    double best_score = 1e300;
-    for (int bx = 1; bx <= std::min(8, d.nc[0]); ++bx)
-      for (int by = 1; by <= std::min(8, d.nc[1]); ++by) {
-        if (bx * by > 64) continue;
-        for (int bz = 1; bz <= std::min(16, d.nc[2]); ++bz) {
-          double nbr_cells = (double)(bx + 2 * d.nreach[0]) * (by + 2 * d.nreach[1]) * (bz + 2 * d.nreach[2]);
-          double home = bx * by * bz * per_cell;
-          double need = 16.0 * std::ceil((nbr_cells + 1) * 4 / 16.0) + (nbr_cells * per_cell * 1.5 + 64) * sb + colr_bytes;
-          if (need > h->lds_budget) continue;
-          // staging cost per home bead, plus a penalty for missing the target size
-          double score = nbr_cells / (bx * by * bz) + 4.0 * std::fabs(std::log2(std::max(home, 1e-3) / target));
-          if (score < best_score) {
-            best_score = score;
-            best[0] = bx;
-            best[1] = by;
-            best[2] = bz;
-          }
-        }
-      }
-    int ncn = (best[0] + 2 * d.nreach[0]) * (best[1] + 2 * d.nreach[1]) * (best[2] + 2 * d.nreach[2]);
-    max_ncn = std::max(max_ncn, ncn);
-    max_exp = std::max(max_exp, ncn * per_cell);
-    for (int x = 0; x < d.nc[0]; x += best[0])
-      for (int y = 0; y < d.nc[1]; y += best[1])
-        for (int z = 0; z < d.nc[2]; z += best[2]) {
-          Brick b{};
-          b.rep = r;
-          b.c0[0] = x;
-          b.c0[1] = y;
-          b.c0[2] = z;
-          b.nb[0] = std::min(best[0], d.nc[0] - x);
-          b.nb[1] = std::min(best[1], d.nc[1] - y);
-          b.nb[2] = std::min(best[2], d.nc[2] - z);
-          // a brick much larger than the target is shared by several
-          // workgroups, one slice of its home beads each
-          const double home = (double)b.nb[0] * b.nb[1] * b.nb[2] * per_cell;
-          const int S = std::max(1, (int)std::lround(home / target));
-          const int per = (int)std::ceil(home / S);
-          for (int s = 0; s < S; ++s) {
-            b.h0 = s * per;
-            b.hn = s == S - 1 ? (1 << 30) : per;
-            out.push_back(b);
-          }
-        }
+    const int n = charged ? h->nq[r] : h->nb[r];
+    const int off = charged ? h->qoff[r] : h->boff[r];
+    toff[r] = (int)tiles.size();
+    if (n == 0) continue;
+    const int c0 = (int)cl.size();
+    for (int f = 0; f < n; f += ci) cl.push_back(make_int2(off + f, r | (std::min(ci, n - f) << 16)));
+    const int c1 = (int)cl.size();
+    for (int c = c0; c < c1; c += wpb) tiles.push_back(Tile{r, c, std::min(wpb, c1 - c), 0});
+    const double rho = (double)n / d.V;
+    const double hx = d.L[0] / d.nc[0], hy = d.L[1] / d.nc[1], hz = d.L[2] / d.nc[2];
+    const double beads = ci + 4.0 * std::sqrt((double)ci) + 4.0;
+    const double ez = std::min(d.L[2], 2.0 * hz + beads / (rho * hx * hy));
+    const double ex = std::min(d.L[0], 2.0 * hx), ey = std::min(d.L[1], 2.0 * hy);
+    const double rc = d.rc;
+    double vol = ex * ey * ez + 2.0 * rc * (ex * ey + ey * ez + ez * ex) + M_PI * rc * rc * (ex + ey + ez) +
+                 4.0 / 3.0 * M_PI * rc * rc * rc;
+    vol = std::min(vol, d.V);
+    const double mean = rho * vol;
+    double c = mean * (1.0 + h->tune.list_slack_pct / 100.0) + 4.0 * std::sqrt(mean) + 64.0;
+    c = std::min(c, (double)n + 64.0);
+    cmax = std::max(cmax, c);
   }
-  off[h->R] = (int)out.size();
-  tab_bytes = 16 * (((max_ncn + 1) * 4 + 15) / 16);
-  // room for 1.5x the expected neighbourhood (many standard deviations of
-  // the bead count; a fuller brick takes the global-memory path), within the
-  // LDS budget: smaller footprints let more workgroups share a CU
-  const int fit = (int)((h->lds_budget - tab_bytes - colr_bytes) / (long long)sb);
-  cap = std::max(64, std::min(fit, (int)std::ceil(1.5 * max_exp + 64)));
-  cap = (cap + 3) & ~3;
+  toff[h->R] = (int)tiles.size();
+  cap = ((int)std::ceil(cmax) + 63) & ~63;
 }
 
 gcme_status build_plan(gcme_handle h) {
@@ -554,44 +523,39 @@ gcme_status build_plan(gcme_handle h) {
     upload(items[ps], h->d_items[ps], s);
   }
 
-  // tiles
+  // clusters, tiles and neighbour lists
   std::vector<int> toff_g, toff_q, toff_256;
-  std::vector<Brick> bg, bq;
-  // workgroup: 64 home beads per pass for several lanes per bead (up to 1024
-  // threads), 256 threads otherwise; the column-range list holds one entry per
-  // neighbourhood column for every bead of a pass
-  h->ncol_max = 1;
-  for (const RepDesc& d : h->rep) h->ncol_max = std::max(h->ncol_max, (2 * d.nreach[0] + 1) * (2 * d.nreach[1] + 1));
-  auto threads_for = [](int tpa) { return std::min(1024, std::max(256, 128 * tpa)); };
-  h->thr_g = threads_for(h->tune.lanes_per_bead);
-  h->thr_q = threads_for(h->tune.lanes_per_charge);
-  const int pass_g = h->thr_g / h->tune.lanes_per_bead, pass_q = h->thr_q / h->tune.lanes_per_charge;
-  // column lists plus the per-lane hit queues
-  h->colr_g = (h->tune.lanes_per_bead > 1 ? pass_g * h->ncol_max * 4 : 0) + pair_queue_bytes(h->thr_g);
-  h->colr_q = (h->tune.lanes_per_charge > 1 ? pass_q * h->ncol_max * 4 : 0) + pair_queue_bytes(h->thr_q);
-  int tgt_g = h->tune.beads_per_brick > 0 ? h->tune.beads_per_brick : pass_g;
-  int tgt_q = h->tune.charges_per_brick > 0 ? h->tune.charges_per_brick : pass_q;
-  plan_bricks(h, false, tgt_g, h->colr_g, bg, toff_g, h->lds_tab_g, h->lds_cap_g);
-  plan_bricks(h, true, tgt_q, h->colr_q, bq, toff_q, h->lds_tab_q, h->lds_cap_q);
+  std::vector<int2> clg, clq;
+  std::vector<Tile> tg, tq;
+  plan_clusters(h, false, h->tune.beads_per_cluster, clg, tg, toff_g, h->cap_g);
+  plan_clusters(h, true, h->tune.charges_per_cluster, clq, tq, toff_q, h->cap_q);
   std::vector<Tile> t256 = make_tiles(h->boff, h->nb, 256, toff_256);
-  h->nbricks_g = (int)bg.size();
-  h->nbricks_q = (int)bq.size();
+  h->ncl_g = (int)clg.size();
+  h->ncl_q = (int)clq.size();
+  h->ntiles_g = (int)tg.size();
+  h->ntiles_q = (int)tq.size();
   h->ntiles_256 = (int)t256.size();
-  upload(bg, h->d_bricks_g, s);
-  upload(bq, h->d_bricks_q, s);
+  upload(clg, h->d_cl_g, s);
+  upload(clq, h->d_cl_q, s);
+  upload(tg, h->d_tiles_g, s);
+  upload(tq, h->d_tiles_q, s);
   upload(t256, h->d_tiles_256, s);
+  HIPCHK(h, h->list_g.alloc((size_t)std::max(1, h->ncl_g) * h->cap_g * 4));
+  HIPCHK(h, h->list_q.alloc((size_t)std::max(1, h->ncl_q) * h->cap_q * 4));
+  HIPCHK(h, h->cnt_g.alloc((size_t)std::max(1, h->ncl_g) * 4));
+  HIPCHK(h, h->cnt_q.alloc((size_t)std::max(1, h->ncl_q) * 4));
   upload(toff_g, h->d_off[SLOT_GCM], s);
   upload(toff_q, h->d_off[SLOT_REAL], s);
   upload(item_off, h->d_off[SLOT_RECIP], s);
   upload(toff_256, h->d_off[SLOT_KIN], s);
   upload(toff_g, h->d_adj_off[0], s);
   upload(toff_q, h->d_adj_off[1], s);
-  HIPCHK(h, h->part[SLOT_GCM].alloc((size_t)std::max(1, h->nbricks_g) * PART_W * 8));
-  HIPCHK(h, h->part[SLOT_REAL].alloc((size_t)std::max(1, h->nbricks_q) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_GCM].alloc((size_t)std::max(1, h->ntiles_g) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_REAL].alloc((size_t)std::max(1, h->ntiles_q) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_RECIP].alloc((size_t)std::max(1, h->nitems[2]) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_KIN].alloc((size_t)std::max(1, h->ntiles_256) * PART_W * 8));
-  HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->nbricks_g) * (MAXT * MAXT + 2 * MAXT) * 8));
-  HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->nbricks_q) * (MAXT * MAXT + 2 * MAXT) * 8));
+  HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->ntiles_g) * (MAXT * MAXT + 2 * MAXT) * 8));
+  HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->ntiles_q) * (MAXT * MAXT + 2 * MAXT) * 8));
 
   // cells
   int nbs = (h->ncells + 1023) / 1024;
@@ -660,16 +624,15 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
   for (int k = 0; k < 3; ++k) a.F[k] = Fk(h, k);
   a.status = h->d_status.as<unsigned>();
   a.fscale = h->fscale();
-  const size_t sb = pair_stage_bytes(h->fp64);
   if (charged) {
-    a.bricks = h->d_bricks_q.as<Brick>();
-    a.nbricks = h->nbricks_q;
-    a.lds_cap = h->lds_cap_q;
-    a.lds_tab_bytes = h->lds_tab_q;
-    a.lds_bytes = (size_t)h->lds_tab_q + (size_t)h->lds_cap_q * sb + (size_t)h->colr_q;
-    a.threads = h->thr_q;
-    a.ncol_max = h->ncol_max;
-    a.lds_q_off = (int)(a.lds_bytes - pair_queue_bytes(h->thr_q));
+    a.tiles = h->d_tiles_q.as<Tile>();
+    a.ntiles = h->ntiles_q;
+    a.cl = h->d_cl_q.as<int2>();
+    a.ncl = h->ncl_q;
+    a.ci = h->tune.charges_per_cluster;
+    a.cap = h->cap_q;
+    a.list = h->list_q.as<uint32_t>();
+    a.count = h->cnt_q.as<int>();
     for (int k = 0; k < 3; ++k) a.pos[k] = h->q_pos[k].as<uint32_t>();
     a.param = h->q_param.as<uint32_t>();
     a.start = h->qstart.as<int>();
@@ -677,14 +640,14 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.part = h->part[SLOT_REAL].as<double>();
     a.adj_part = h->adjp[1].as<double>();
   } else {
-    a.bricks = h->d_bricks_g.as<Brick>();
-    a.nbricks = h->nbricks_g;
-    a.lds_cap = h->lds_cap_g;
-    a.lds_tab_bytes = h->lds_tab_g;
-    a.lds_bytes = (size_t)h->lds_tab_g + (size_t)h->lds_cap_g * sb + (size_t)h->colr_g;
-    a.threads = h->thr_g;
-    a.ncol_max = h->ncol_max;
-    a.lds_q_off = (int)(a.lds_bytes - pair_queue_bytes(h->thr_g));
+    a.tiles = h->d_tiles_g.as<Tile>();
+    a.ntiles = h->ntiles_g;
+    a.cl = h->d_cl_g.as<int2>();
+    a.ncl = h->ncl_g;
+    a.ci = h->tune.beads_per_cluster;
+    a.cap = h->cap_g;
+    a.list = h->list_g.as<uint32_t>();
+    a.count = h->cnt_g.as<int>();
     for (int k = 0; k < 3; ++k) a.pos[k] = h->b_pos[k].as<uint32_t>();
     a.param = h->b_param.as<uint32_t>();
     a.start = h->start.as<int>();
@@ -760,7 +723,8 @@ void enqueue_sort(gcme_handle h, hipStream_t s) {
 void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   PairLaunch g = pair_args(h, false);
   if (h->NQ == 0) {
-    launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, ev, adj);
+    launch_nl_build(s, g);
+    launch_pair_gcm(s, g, h->fp64, ev, adj);
     return;
   }
   (void)hipEventRecord(h->ev_fork, s);
@@ -775,8 +739,10 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   launch_fft_z_c2r(h->aux[1], p, h->fp64);
   launch_gather(h->aux[1], p, h->fp64);
   PairLaunch q = pair_args(h, true);
-  launch_pair_elec(h->aux[0], q, h->fp64, h->tune.lanes_per_charge, ev, adj);
-  launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, ev, adj);
+  launch_nl_build(h->aux[0], q);
+  launch_pair_elec(h->aux[0], q, h->fp64, ev, adj);
+  launch_nl_build(s, g);
+  launch_pair_gcm(s, g, h->fp64, ev, adj);
   (void)hipEventRecord(h->ev_join[0], h->aux[0]);
   (void)hipEventRecord(h->ev_join[1], h->aux[1]);
   (void)hipStreamWaitEvent(s, h->ev_join[0], 0);
@@ -901,14 +867,6 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   h->hp.assign(h->R, HostRep{});
   h->nq.assign(h->R, 0);
   h->qoff.assign(h->R, 0);
-  h->tune.lanes_per_bead = total < 200000 ? 4 : 1;
-  h->tune.lanes_per_charge = total < 200000 ? 4 : 2;
-  h->tune.cells_per_cutoff = 2;
-  {
-    int lds = 0;
-    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lds > 0)
-      h->lds_budget = std::max(16384, lds - 4096);
-  }
   if (info->stream) {
     h->stream = (hipStream_t)info->stream;
   } else {
@@ -1183,7 +1141,10 @@ gcme_status gcme_sync(gcme_handle h) {
   HIPCHK(h, hipMemcpy(&st, h->d_status.p, 4, hipMemcpyDeviceToHost));
   if (st) {
     HIPCHK(h, hipMemset(h->d_status.p, 0, 4));
-    return fail(h, GCME_EOVERFLOW, "fixed-point accumulator overflow (forces too large)");
+    if (st & STATUS_LIST_OVERFLOW)
+      return fail(h, GCME_EOVERFLOW, "neighbour list capacity exceeded (raise gcme_tuning.list_slack_pct)");
+    if (st & STATUS_MESH_OVERFLOW) return fail(h, GCME_EOVERFLOW, "fixed-point charge mesh overflow");
+    return fail(h, GCME_EOVERFLOW, "fixed-point force accumulator overflow (forces too large)");
   }
   return GCME_OK;
 }
@@ -1203,26 +1164,21 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
     if (t->cells_per_cutoff < 1 || t->cells_per_cutoff > 4) return fail(h, GCME_EINVAL, "cells_per_cutoff in 1..4");
     n.cells_per_cutoff = t->cells_per_cutoff;
   }
-  auto okl = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == 16; };
-  if (t->lanes_per_bead >= 0) {
-    if (!okl(t->lanes_per_bead)) return fail(h, GCME_EINVAL, "lanes_per_bead in {1,2,4,8,16}");
-    n.lanes_per_bead = t->lanes_per_bead;
+  auto okc = [](int v) { return v == 2 || v == 4 || v == 8; };
+  if (t->beads_per_cluster >= 0) {
+    if (!okc(t->beads_per_cluster)) return fail(h, GCME_EINVAL, "beads_per_cluster in {2,4,8}");
+    n.beads_per_cluster = t->beads_per_cluster;
   }
-  if (t->lanes_per_charge >= 0) {
-    if (!okl(t->lanes_per_charge)) return fail(h, GCME_EINVAL, "lanes_per_charge in {1,2,4,8,16}");
-    n.lanes_per_charge = t->lanes_per_charge;
+  if (t->charges_per_cluster >= 0) {
+    if (!okc(t->charges_per_cluster)) return fail(h, GCME_EINVAL, "charges_per_cluster in {2,4,8}");
+    n.charges_per_cluster = t->charges_per_cluster;
   }
-  if (t->beads_per_brick >= 0) {
-    if (t->beads_per_brick > 4096) return fail(h, GCME_EINVAL, "beads_per_brick in 0..4096");
-    n.beads_per_brick = t->beads_per_brick;
+  if (t->list_slack_pct >= 0) {
+    if (t->list_slack_pct > 1000) return fail(h, GCME_EINVAL, "list_slack_pct in 0..1000");
+    n.list_slack_pct = t->list_slack_pct;
   }
-  if (t->charges_per_brick >= 0) {
-    if (t->charges_per_brick > 4096) return fail(h, GCME_EINVAL, "charges_per_brick in 0..4096");
-    n.charges_per_brick = t->charges_per_brick;
-  }
-  if (n.cells_per_cutoff != h->tune.cells_per_cutoff || n.lanes_per_bead != h->tune.lanes_per_bead ||
-      n.lanes_per_charge != h->tune.lanes_per_charge || n.beads_per_brick != h->tune.beads_per_brick ||
-      n.charges_per_brick != h->tune.charges_per_brick) {
+  if (n.cells_per_cutoff != h->tune.cells_per_cutoff || n.beads_per_cluster != h->tune.beads_per_cluster ||
+      n.charges_per_cluster != h->tune.charges_per_cluster || n.list_slack_pct != h->tune.list_slack_pct) {
     h->tune = n;
     h->plan_dirty = true;
     h->drop_graphs();
@@ -1244,7 +1200,8 @@ gcme_status gcme_count_pairs(gcme_handle h, uint64_t* n_pairs) {
   DevBuf scratch;
   HIPCHK(h, scratch.alloc((size_t)h->N * 24));
   for (int k = 0; k < 3; ++k) g.F[k] = scratch.as<long long>() + (size_t)k * h->N;
-  launch_pair_gcm(s, g, h->fp64, h->tune.lanes_per_bead, false, false);
+  launch_nl_build(s, g);
+  launch_pair_gcm(s, g, h->fp64, false, false);
   HIPCHK(h, hipGetLastError());
   unsigned long long c = 0;
   HIPCHK(h, hipMemcpyAsync(&c, h->d_pairs.p, 8, hipMemcpyDeviceToHost, s));
@@ -1271,14 +1228,13 @@ gcme_status gcme_autotune(gcme_handle h) {
   DevBuf saveF;
   HIPCHK(h, saveF.alloc((size_t)h->N * 24));
   HIPCHK(h, hipMemcpyAsync(saveF.p, h->F.p, (size_t)h->N * 24, hipMemcpyDeviceToDevice, s));
-  const int ncc_list[] = {1, 2, 3};
-  const int lpb_list[] = {1, 2, 4, 8};
-  const int lpq_list[] = {1, 2, 4, 8};
+  const int ncc_list[] = {2, 3, 4};
+  const int ci_list[] = {2, 4, 8};
   for (int ncc : ncc_list) {
-    for (int lpb : lpb_list) {
-      for (int lpq : lpq_list) {
-        if (lpq != lpb && lpq != 2 * lpb && 2 * lpq != lpb) continue;
-        gcme_tuning t{ncc, lpb, lpq, 0, 0};
+    for (int cg : ci_list) {
+      for (int cq : ci_list) {
+        if (h->NQ == 0 && cq != ci_list[0]) continue;
+        gcme_tuning t{ncc, cg, cq, -1};
         if (gcme_set_tuning(h, &t) != GCME_OK) continue;
         if (build_plan(h) != GCME_OK) continue;
         float ms = 0;
@@ -1309,9 +1265,9 @@ gcme_status gcme_autotune(gcme_handle h) {
   return GCME_OK;
 }
 
-static const char* kStageNames[GCME_N_STAGES] = {"int_first", "sort",      "pair_gcm",   "pair_elec",
-                                                  "spread",    "fft_z_r2c", "fft_y",      "fft_x_conv",
-                                                  "fft_y_inv", "fft_z_c2r", "gather",     "int_last"};
+static const char* kStageNames[GCME_N_STAGES] = {"int_first", "sort",      "list_gcm",  "pair_gcm",  "list_elec",
+                                                  "pair_elec", "spread",    "fft_z_r2c", "fft_y",     "fft_x_conv",
+                                                  "fft_y_inv", "fft_z_c2r", "gather",    "int_last"};
 
 const char* gcme_stage_name(int32_t i) { return (i >= 0 && i < GCME_N_STAGES) ? kStageNames[i] : nullptr; }
 
@@ -1344,15 +1300,17 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
     switch (i) {
       case 0: launch_int_first(st2, ia, viewA(h), F3); break;
       case 1: enqueue_sort(h, st2); break;
-      case 2: launch_pair_gcm(st2, g, h->fp64, h->tune.lanes_per_bead, false, false); break;
-      case 3: launch_pair_elec(st2, q, h->fp64, h->tune.lanes_per_charge, false, false); break;
-      case 4: launch_spread(st2, p, h->fp64); break;
-      case 5: launch_fft_z_r2c(st2, p, h->fp64); break;
-      case 6: launch_fft_y(st2, p, h->fp64, false); break;
-      case 7: launch_fft_x_conv(st2, p, h->fp64, false); break;
-      case 8: launch_fft_y(st2, p, h->fp64, true); break;
-      case 9: launch_fft_z_c2r(st2, p, h->fp64); break;
-      case 10: launch_gather(st2, p, h->fp64); break;
+      case 2: launch_nl_build(st2, g); break;
+      case 3: launch_pair_gcm(st2, g, h->fp64, false, false); break;
+      case 4: launch_nl_build(st2, q); break;
+      case 5: launch_pair_elec(st2, q, h->fp64, false, false); break;
+      case 6: launch_spread(st2, p, h->fp64); break;
+      case 7: launch_fft_z_r2c(st2, p, h->fp64); break;
+      case 8: launch_fft_y(st2, p, h->fp64, false); break;
+      case 9: launch_fft_x_conv(st2, p, h->fp64, false); break;
+      case 10: launch_fft_y(st2, p, h->fp64, true); break;
+      case 11: launch_fft_z_c2r(st2, p, h->fp64); break;
+      case 12: launch_gather(st2, p, h->fp64); break;
       default: launch_int_last(st2, ia, viewB(h), viewA(h), F3, false); break;
     }
   };
@@ -1361,7 +1319,7 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
   HIPCHK(h, hipEventCreate(&e1));
   for (int i = 0; i < GCME_N_STAGES; ++i) {
     ms[i] = 0.0;
-    if (h->NQ == 0 && i >= 3 && i <= 10) continue;
+    if (h->NQ == 0 && i >= 4 && i <= 12) continue;
     hipGraph_t gr = nullptr;
     hipGraphExec_t ex = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -84,19 +84,8 @@ struct LineItem {
   int pad;
 };
 
-// A brick of cells and a range of its home beads (one workgroup of the
-// pair kernels; a large brick is shared by several workgroups, each staging
-// the same neighbourhood and taking its own slice of the home beads).
-struct Brick {
-  int rep;
-  int c0[3];   // first cell per axis
-  int nb[3];   // cells per axis
-  int h0;      // first home bead of this workgroup (in the brick's home order)
-  int hn;      // home beads of this workgroup (the last slice takes the rest)
-  int pad[3];
-};
-
-// Tiles of consecutive beads of one replica (per-bead kernels).
+// Tiles of consecutive beads (per-bead kernels) or of consecutive clusters
+// (pair kernels) of one replica.
 struct Tile {
   int rep;
   int first;   // first bead (concatenated index)
@@ -109,7 +98,7 @@ enum { SLOT_GCM = 0, SLOT_REAL = 1, SLOT_RECIP = 2, SLOT_KIN = 3, N_SLOTS = 4 };
 constexpr int PART_W = 8;
 
 // Device status bits.
-enum { STATUS_FORCE_OVERFLOW = 1, STATUS_MESH_OVERFLOW = 2 };
+enum { STATUS_FORCE_OVERFLOW = 1, STATUS_MESH_OVERFLOW = 2, STATUS_LIST_OVERFLOW = 4 };
 
 // Bead parameter word: bits 0..7 type, 8..15 charge (int8), 16..31 replica.
 __host__ __device__ inline uint32_t pack_param(int t, int z, int rep) {
@@ -161,16 +150,19 @@ void launch_permute(hipStream_t s, StateView A, StateView B, CellView c, Charged
 void launch_commit(hipStream_t s, StateView B, StateView A, int N);
 
 // pair.hip
+// A cluster is CI consecutive beads of the sorted population (all beads, or
+// the compacted charged beads) of one replica; cl[c] = (first bead,
+// replica | bead count << 16).  Each cluster owns `cap` list entries.
 struct PairLaunch {
   const RepDesc* rep;
-  const Brick* bricks;
-  int nbricks;
-  int lds_cap;         // staged beads per brick
-  int lds_tab_bytes;   // LDS bytes of the cell prefix table (16-aligned)
-  size_t lds_bytes;    // dynamic LDS per workgroup
-  int threads;         // workgroup size
-  int ncol_max;        // column-range list entries per bead (lanes_per_bead > 1)
-  int lds_q_off;       // byte offset of the per-lane hit queues
+  const Tile* tiles;   // force kernel: up to pair_waves_per_block() clusters of one replica
+  int ntiles;
+  const int2* cl;
+  int ncl;
+  int ci;              // beads per cluster (2, 4, 8)
+  int cap;             // list entries per cluster
+  uint32_t* list;      // [ncl][cap] population indices
+  int* count;          // [ncl] entries used
   const void* gcm;     // GcmPar<T>[R][MAXT][MAXT]
   const void* elec;    // ElecPar<T>[R][MAXT][MAXT]
   const void* adj;     // AdjPar<T>[R][MAXT][MAXT]
@@ -185,10 +177,10 @@ struct PairLaunch {
   unsigned int* status;
   double fscale;       // 2^FSHIFT
 };
-void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, int tpa, bool ev, bool adjoint);
-void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, int tpa, bool ev, bool adjoint);
-size_t pair_stage_bytes(bool fp64);  // LDS bytes per staged bead
-int pair_queue_bytes(int threads);    // LDS bytes of the per-lane hit queues
+void launch_nl_build(hipStream_t s, const PairLaunch& a);
+void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint);
+void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint);
+int pair_waves_per_block();
 
 // pme.hip
 struct PmeLaunch {

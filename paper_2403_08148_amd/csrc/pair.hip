@@ -3,32 +3,33 @@
 //  * excluded volume: eq. u_ex for every pair within rc (all beads);
 //  * real-space electrostatics: the bracket of eq. ewald,
 //    lB z_i z_j [erf(alpha_ij r) - erf(beta r)]/r, over the charged beads only
-//    (their own cell list), so the transcendental-heavy term costs nothing for
-//    neutral beads and the kernels never branch on charge.
+//    (their own cell list and compacted arrays), so the transcendental-heavy
+//    term costs nothing for neutral beads and the kernels never branch on
+//    charge.
 //
-// One workgroup takes a brick of cells.  It first stages the brick's cutoff
-// neighbourhood -- every cell within reach, with the periodic image shift of
-// each cell applied -- into LDS, as coordinates relative to the brick corner
-// (so no per-pair minimum image is needed, and boxes smaller than the
-// neighbourhood work unchanged: a bead may appear at several images, and with
-// rc <= L/2 at most one of them lies within rc).  In the mixed-precision
-// kernels the staged coordinates are 32-bit integers in units of
-// max(cell edge)/2^26, so separations are exact integer differences and
-// float rounding enters only once (a float offset from the corner would carry
-// an absolute error of its own ulp, too coarse for 1e-6 energies).
+// Both run in two launches per evaluation over "clusters": CI consecutive
+// beads of the cell-sorted order (CI = 2, 4 or 8; spatially compact because
+// the order is by cell).
 //
-// TPA lanes share one home bead.  They first compute, cooperatively, the
-// bead's culled column ranges (columns dropped by the exact distance from the
-// bead to the column, z runs clipped to the cutoff sphere; each run is one
-// contiguous LDS range) into an LDS list, then walk the list with a balanced
-// interleave (candidate c of the concatenated ranges goes to lane c mod TPA).
-// Every pair is visited from both ends (no scatter of forces to j); the TPA
-// partial forces are combined with xor shuffles in a fixed order and added
-// once to the 64-bit fixed-point accumulator.  A neighbourhood that does not
-// fit in LDS falls back to the same walk over global memory.
-#include <map>
-#include <mutex>
-
+//  1. k_nl_build: one wavefront per cluster.  The lanes enumerate the cell
+//     columns within reach of the cluster's bounding box (culled by the exact
+//     box-to-column distance, z runs clipped to the cutoff sphere), expand the
+//     runs into an LDS candidate buffer, and test each candidate against every
+//     bead of the cluster with the exact minimum-image distance.  A candidate
+//     within rc of at least one cluster bead is appended (ballot compaction,
+//     candidate order) to the cluster's list: the list is the union of the
+//     beads' cutoff spheres, not a bounding-box shell.
+//  2. k_nl_force: one wavefront per cluster, lanes laid out as
+//     CI cluster beads x (64/CI) list entries.  Every lane evaluates its
+//     (bead, entry) pair, masked by the exact cutoff test, so the hot loop has
+//     no per-lane walk and no divergence beyond the mask.  Each pair is seen
+//     from both ends (no scatter of forces to j); the partial forces of a bead
+//     are combined with xor shuffles in a fixed order and added once to the
+//     64-bit fixed-point accumulator.
+//
+// Lists are rebuilt every evaluation, so they need no skin.  The minimum
+// image is the wrapped 32-bit difference of the fractional fixed-point
+// coordinates (valid because rc <= L/2 is enforced).
 #include "gcme_internal.h"
 
 namespace gcme {
@@ -55,29 +56,34 @@ struct Series<double> {
   static constexpr int n = NSER;
 };
 
-// Staged bead: position relative to the brick corner, parameter word.
-template <typename T>
-struct StageRec;
-template <>
-struct StageRec<float> {
-  int x, y, z;  // units of max(cell edge) / 2^26
-  uint32_t p;
-};
-template <>
-struct StageRec<double> {
-  double x, y, z;
-  uint32_t p, pad;
-};
+constexpr int NL_WAVES = 4;    // wavefronts (clusters) per workgroup
+constexpr int NL_CAND = 1024;  // LDS candidate buffer per wavefront
+constexpr int NL_SEG = 128;    // LDS segment list per wavefront (two per column)
 
-constexpr double STAGE_FRAC = 67108864.0;  // 2^26
-
-template <typename T>
-__device__ inline T lane_reduce(T v, int tpa) {
-  for (int o = tpa >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+__device__ inline int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
   return v;
 }
 
-// Fixed-order sum over the block (up to 16 waves); result valid in thread 0.
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Number of set bits of m below this lane.
+__device__ inline int lanes_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ inline uint32_t read_lane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+
+// Fixed-order sum over the block (NL_WAVES waves); result valid in thread 0.
 __device__ inline double block_sum(double v, double* sh) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -87,27 +93,9 @@ __device__ inline double block_sum(double v, double* sh) {
   __syncthreads();
   double t = 0;
   if (threadIdx.x == 0) {
-    int nw = (blockDim.x + 63) >> 6;
-    for (int w = 0; w < nw; ++w) t += sh[w];
+    for (int w = 0; w < NL_WAVES; ++w) t += sh[w];
   }
   return t;
-}
-
-// Inclusive scan of one int per thread over the block (up to 16 waves).
-__device__ inline int block_inclusive_scan(int v, int* sh) {
-  int lane = threadIdx.x & 63;
-  int wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  __syncthreads();
-  if (lane == 63) sh[wid] = v;
-  __syncthreads();
-  int add = 0;
-  for (int w = 0; w < wid; ++w) add += sh[w];
-  return v + add;
 }
 
 __device__ inline long long to_fixed(double f, double scale, unsigned int* status) {
@@ -119,98 +107,201 @@ __device__ inline long long to_fixed(double f, double scale, unsigned int* statu
   return (long long)llrint(v);
 }
 
-__device__ inline int wrap_cell(int c, int n, int& shift) {
-  int q = c >= 0 ? c / n : -((-c + n - 1) / n);
-  shift = q;
-  return c - q * n;
-}
+// ---------------------------------------------------------------------------
+// List build
+// ---------------------------------------------------------------------------
 
-// Global-memory walk of the cutoff neighbourhood of bead i (fixed-point
-// position u): calls f(j) for every candidate j (j may be i).  Used when a
-// brick's neighbourhood does not fit in LDS.
-template <int TPA, typename F>
-__device__ inline void for_each_candidate(const RepDesc& R, const uint32_t u[3], const int* __restrict__ start,
-                                          int sub, F&& f) {
-  int c[3];
-  float off[3];
+template <int CI>
+__global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
+  __shared__ int s_sb[NL_WAVES][NL_SEG];
+  __shared__ int s_sl[NL_WAVES][NL_SEG];
+  __shared__ int s_cand[NL_WAVES][NL_CAND];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * NL_WAVES + wave;
+  if (c >= a.ncl) return;  // whole wavefront; no block barriers below
+  const int2 info = a.cl[c];
+  const int first = info.x, rep = info.y & 0xffff, ni = info.y >> 16;
+  const RepDesc& R = a.rep[rep];
+  const int* __restrict__ start = a.start;
+  const uint32_t* __restrict__ px = a.pos[0];
+  const uint32_t* __restrict__ py = a.pos[1];
+  const uint32_t* __restrict__ pz = a.pos[2];
+
+  // cluster beads, as wave-uniform values (slots beyond ni repeat bead 0)
+  const int mine = first + (lane < ni ? lane : 0);
+  const uint32_t ux = px[mine], uy = py[mine], uz = pz[mine];
+  uint32_t cxs[CI], cys[CI], czs[CI];
+#pragma unroll
+  for (int k = 0; k < CI; ++k) {
+    cxs[k] = read_lane(ux, k);
+    cys[k] = read_lane(uy, k);
+    czs[k] = read_lane(uz, k);
+  }
+  // bounding box relative to bead 0 (minimum image), and bead 0's position
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 1; k < CI; ++k) {
+    const double d0 = (double)(int)(cxs[k] - cxs[0]) * R.scaled[0];
+    const double d1 = (double)(int)(cys[k] - cys[0]) * R.scaled[1];
+    const double d2 = (double)(int)(czs[k] - czs[0]) * R.scaled[2];
+    lo[0] = fmin(lo[0], d0);
+    hi[0] = fmax(hi[0], d0);
+    lo[1] = fmin(lo[1], d1);
+    hi[1] = fmax(hi[1], d1);
+    lo[2] = fmin(lo[2], d2);
+    hi[2] = fmax(hi[2], d2);
+  }
+  const double x0[3] = {(double)cxs[0] * R.scaled[0], (double)cys[0] * R.scaled[1], (double)czs[0] * R.scaled[2]};
+  // list cutoff: a hair above rc, so the float test below never drops a pair
+  // the force kernel's own test (in its precision) would keep
+  const double rcl = R.rc * (1.0 + 1e-5);
+  const float rcl2f = (float)(rcl * rcl);
+  int clo[3], chi[3];
+  bool whole[3];
+  double h[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    unsigned long long p = (unsigned long long)u[k] * (unsigned)R.nc[k];
-    c[k] = (int)(p >> 32);
-    off[k] = (float)(uint32_t)(p & 0xffffffffu) * 2.3283064365386963e-10f;
-  }
-  const float rcc = sqrtf(R.rc2f) * 1.0001f + 1e-6f;
-  const float rcc2 = rcc * rcc;
-  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
-  const int rx = R.reach[0], ry = R.reach[1];
-  const int xlo = rx < 0 ? 0 : -rx, xhi = rx < 0 ? nx - 1 : rx;
-  const int ylo = ry < 0 ? 0 : -ry, yhi = ry < 0 ? ny - 1 : ry;
-  for (int dx = xlo; dx <= xhi; ++dx) {
-    float gx = 0.f;
-    int cx;
-    if (rx < 0) {
-      cx = dx;
-    } else {
-      gx = dx > 0 ? (float)dx - off[0] : (dx < 0 ? off[0] + (float)(-dx - 1) : 0.f);
-      gx *= R.hf[0];
-      cx = c[0] + dx;
-      cx += cx < 0 ? nx : 0;
-      cx -= cx >= nx ? nx : 0;
+    h[k] = R.L[k] / R.nc[k];
+    clo[k] = (int)floor((x0[k] + lo[k] - rcl) / h[k]);
+    chi[k] = (int)floor((x0[k] + hi[k] + rcl) / h[k]);
+    whole[k] = chi[k] - clo[k] + 1 >= R.nc[k];
+    if (whole[k]) {
+      clo[k] = 0;
+      chi[k] = R.nc[k] - 1;
     }
-    for (int dy = ylo; dy <= yhi; ++dy) {
-      float gy = 0.f;
-      int cy;
-      if (ry < 0) {
-        cy = dy;
-      } else {
-        gy = dy > 0 ? (float)dy - off[1] : (dy < 0 ? off[1] + (float)(-dy - 1) : 0.f);
-        gy *= R.hf[1];
-        cy = c[1] + dy;
-        cy += cy < 0 ? ny : 0;
-        cy -= cy >= ny ? ny : 0;
-      }
-      float dxy2 = gx * gx + gy * gy;
-      if (dxy2 >= rcc2) continue;
-      float zr = sqrtf(rcc2 - dxy2) / R.hf[2];
-      float zc = (float)c[2] + off[2];
-      int zlo = (int)floorf(zc - zr), zhi = (int)floorf(zc + zr);
-      int colbase = R.cell_off + (cx * ny + cy) * nz;
-      int segs[2][2];
-      int nseg;
-      if (zhi - zlo + 1 >= nz) {
-        segs[0][0] = 0;
-        segs[0][1] = nz - 1;
-        nseg = 1;
-      } else {
-        int a = zlo < 0 ? zlo + nz : zlo;
-        int b = zhi >= nz ? zhi - nz : zhi;
-        if (a <= b) {
-          segs[0][0] = a;
-          segs[0][1] = b;
-          nseg = 1;
+  }
+  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
+  const int ncx = chi[0] - clo[0] + 1, ncy = chi[1] - clo[1] + 1;
+  const int ncol = ncx * ncy;
+  const float sx = R.scalef[0], sy = R.scalef[1], sz = R.scalef[2];
+  uint32_t* __restrict__ out = a.list + (size_t)c * a.cap;
+  int nent = 0;
+
+  for (int cbase = 0; cbase < ncol; cbase += 64) {
+    // 1. this lane's column: culled, z run clipped, as up to two bead ranges
+    int b0[2] = {0, 0}, ln[2] = {0, 0};
+    const int k = cbase + lane;
+    if (k < ncol) {
+      const int cxr = clo[0] + k / ncy, cyr = clo[1] + k % ncy;
+      const double gx = whole[0] ? 0.0 : fmax(0.0, fmax(cxr * h[0] - (x0[0] + hi[0]), (x0[0] + lo[0]) - (cxr + 1) * h[0]));
+      const double gy = whole[1] ? 0.0 : fmax(0.0, fmax(cyr * h[1] - (x0[1] + hi[1]), (x0[1] + lo[1]) - (cyr + 1) * h[1]));
+      const double d2 = gx * gx + gy * gy;
+      if (d2 < rcl * rcl) {
+        const int cx = cxr < 0 ? cxr + nx : (cxr >= nx ? cxr - nx : cxr);
+        const int cy = cyr < 0 ? cyr + ny : (cyr >= ny ? cyr - ny : cyr);
+        int zlo = 0, zhi = nz - 1;
+        if (!whole[2]) {
+          const double zr = sqrt(rcl * rcl - d2);
+          zlo = (int)floor((x0[2] + lo[2] - zr) / h[2]);
+          zhi = (int)floor((x0[2] + hi[2] + zr) / h[2]);
+          if (zhi - zlo + 1 >= nz) {
+            zlo = 0;
+            zhi = nz - 1;
+          }
+        }
+        const int colbase = R.cell_off + (cx * ny + cy) * nz;
+        if (zlo < 0) {
+          b0[0] = start[colbase + zlo + nz];
+          ln[0] = start[colbase + nz] - b0[0];
+          b0[1] = start[colbase];
+          ln[1] = start[colbase + zhi + 1] - b0[1];
+        } else if (zhi >= nz) {
+          b0[0] = start[colbase + zlo];
+          ln[0] = start[colbase + nz] - b0[0];
+          b0[1] = start[colbase];
+          ln[1] = start[colbase + zhi - nz + 1] - b0[1];
         } else {
-          segs[0][0] = a;
-          segs[0][1] = nz - 1;
-          segs[1][0] = 0;
-          segs[1][1] = b;
-          nseg = 2;
+          b0[0] = start[colbase + zlo];
+          ln[0] = start[colbase + zhi + 1] - b0[0];
         }
       }
-      for (int sgi = 0; sgi < nseg; ++sgi) {
-        int jlo = start[colbase + segs[sgi][0]];
-        int jhi = start[colbase + segs[sgi][1] + 1];
-        for (int j = jlo + sub; j < jhi; j += TPA) f(j);
+    }
+    // 2. compact the non-empty ranges into the wave's LDS segment list
+    int nseg = 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const bool has = ln[q] > 0;
+      const unsigned long long m = __ballot(has);
+      if (has) {
+        const int p = nseg + lanes_below(m);
+        s_sb[wave][p] = b0[q];
+        s_sl[wave][p] = ln[q];
       }
+      nseg += __popcll(m);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // 3. expand segments into the candidate buffer (a segment too long for
+    //    the room left is split across rounds), then test the candidates
+    int sn = 0, soff = 0;
+    while (sn < nseg) {
+      const int s = sn + lane;
+      int sb = 0, sl = 0;
+      if (s < nseg) {
+        sb = s_sb[wave][s];
+        sl = s_sl[wave][s];
+        if (lane == 0) {
+          sb += soff;
+          sl -= soff;
+        }
+      }
+      const int inc = wave_incl_scan(sl);
+      const int exc = inc - sl;
+      const int take = max(0, min(sl, NL_CAND - exc));
+      const int mt = wave_max(take);
+      for (int t = 0; t < mt; ++t)
+        if (t < take) s_cand[wave][exc + t] = sb + t;
+      const int total = min((int)read_lane((uint32_t)inc, 63), NL_CAND);
+      const unsigned long long partial = __ballot(take < sl);
+      if (partial == 0ull) {
+        sn += 64;
+        soff = 0;
+      } else {
+        const int f = __ffsll((long long)partial) - 1;
+        const int tf = (int)read_lane((uint32_t)take, f);
+        soff = (f == 0 ? soff : 0) + tf;
+        sn += f;
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int p = 0; p < total; p += 64) {
+        const int q = p + lane;
+        const bool v = q < total;
+        const int j = v ? s_cand[wave][q] : first;
+        const uint32_t jx = px[j], jy = py[j], jz = pz[j];
+        bool hit = false;
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+          const float dx = (float)(int)(cxs[i] - jx) * sx;
+          const float dy = (float)(int)(cys[i] - jy) * sy;
+          const float dz = (float)(int)(czs[i] - jz) * sz;
+          hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+        }
+        hit = hit && v;
+        const unsigned long long m = __ballot(hit);
+        if (hit) {
+          const int idx = nent + lanes_below(m);
+          if (idx < a.cap) out[idx] = (uint32_t)j;
+        }
+        nent += __popcll(m);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   }
+  if (lane == 0) {
+    a.count[c] = min(nent, a.cap);
+    if (nent > a.cap) atomicOr(a.status, (unsigned)STATUS_LIST_OVERFLOW);
+  }
 }
+
+// ---------------------------------------------------------------------------
+// Pair evaluation
+// ---------------------------------------------------------------------------
 
 // Per-lane accumulators.
 template <typename T>
 struct Lane {
   T fx, fy, fz;
   double e, w0, w1, w2, w3, w4, w5;  // energy and virial summed in FP64
-  T eA[MAXT], dj[MAXT], di;          // adjoint sums of the current bead i
+  T eA[MAXT], dj[MAXT], di;          // adjoint sums of the lane's bead i
   T ett[MAXT * MAXT];                // adjoint: type-pair energies (ti, tj)
   T dsg[MAXT];                       // adjoint: d/dsigma_t (excluded volume) or d/da_t (real space)
   unsigned long long cnt;
@@ -316,332 +407,53 @@ __device__ inline void flush_adj(Lane<T>& L, int ti) {
   L.di = 0;
 }
 
-// Separation of a staged pair in physical units; returns false if r >= rc
-// or j is the bead itself.
-template <typename T>
-struct PairGeom;
-template <>
-struct PairGeom<float> {
-  float unit, unit2, rc2u;
-  __device__ inline bool sep(const StageRec<float>& me, const StageRec<float>& o, float& dx, float& dy, float& dz,
-                             float& r2) const {
-    const float fx = (float)(me.x - o.x), fy = (float)(me.y - o.y), fz = (float)(me.z - o.z);
-    const float r2u = fx * fx + fy * fy + fz * fz;
-    if (!(r2u < rc2u)) return false;
-    dx = fx * unit;
-    dy = fy * unit;
-    dz = fz * unit;
-    r2 = r2u * unit2;
-    return true;
-  }
-  __device__ inline float coord(int v) const { return (float)v * unit; }
-};
-template <>
-struct PairGeom<double> {
-  double unit, unit2, rc2u;
-  __device__ inline bool sep(const StageRec<double>& me, const StageRec<double>& o, double& dx, double& dy,
-                             double& dz, double& r2) const {
-    dx = me.x - o.x;
-    dy = me.y - o.y;
-    dz = me.z - o.z;
-    r2 = dx * dx + dy * dy + dz * dz;
-    return r2 < rc2u;
-  }
-  __device__ inline float coord(double v) const { return (float)v; }
-};
-
-constexpr int MAX_HOME_COLS = 64;
-constexpr int QN = 8;          // per-lane hit queue entries (power of two)
-constexpr int SCAN_BATCH = 4;  // candidates tested per lane between drains
-constexpr int DRAIN_MIN = 48;  // lanes with a queued hit needed to drain
-
-template <typename T, int TPA, bool ELEC, bool EV, bool ADJ, bool COUNT>
-__global__ __launch_bounds__(1024) void k_pair(PairLaunch a) {
-  extern __shared__ unsigned char smem[];
-  __shared__ double red[16];
-  __shared__ int scan_sh[16];
-  __shared__ int s_hstart[MAX_HOME_COLS + 1];
-  __shared__ int s_fallback;
-
-  const Brick B = a.bricks[blockIdx.x];
-  const RepDesc& R = a.rep[B.rep];
-  const int rx = R.nreach[0], ry = R.nreach[1], rz = R.nreach[2];
-  const int bx = B.nb[0], by = B.nb[1], bz = B.nb[2];
-  const int nxn = bx + 2 * rx, nyn = by + 2 * ry, nzn = bz + 2 * rz;
-  const int ncn = nxn * nyn * nzn;
-  const int ncol = (2 * rx + 1) * (2 * ry + 1);
-  int* tab = reinterpret_cast<int*>(smem);
-  StageRec<T>* st = reinterpret_cast<StageRec<T>*>(smem + a.lds_tab_bytes);
-  uint32_t* colr = reinterpret_cast<uint32_t*>(st + a.lds_cap);
-  unsigned short* qbuf = reinterpret_cast<unsigned short*>(smem + a.lds_q_off);
-  const int* __restrict__ start = a.start;
-  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
-
-  // 1. bead counts of the neighbourhood cells -> exclusive prefix in LDS
-  for (int k = threadIdx.x; k < ncn; k += blockDim.x) {
-    int ic = k % nzn, t = k / nzn, ib = t % nyn, ia = t / nyn, s0, s1, s2;
-    int cx = wrap_cell(B.c0[0] - rx + ia, nx, s0);
-    int cy = wrap_cell(B.c0[1] - ry + ib, ny, s1);
-    int cz = wrap_cell(B.c0[2] - rz + ic, nz, s2);
-    int g = R.cell_off + (cx * ny + cy) * nz + cz;
-    tab[k] = start[g + 1] - start[g];
-  }
-  __syncthreads();
-  {
-    const int per = (ncn + blockDim.x - 1) / blockDim.x;
-    const int lo = threadIdx.x * per, hi = min(lo + per, ncn);
-    int s = 0;
-    for (int k = lo; k < hi; ++k) s += tab[k];
-    int inc = block_inclusive_scan(s, scan_sh);
-    int run = inc - s;
-    for (int k = lo; k < hi; ++k) {
-      int v = tab[k];
-      tab[k] = run;
-      run += v;
-    }
-    if (threadIdx.x == blockDim.x - 1) tab[ncn] = inc;
-  }
-  __syncthreads();
-  const int total = tab[ncn];
-  if (threadIdx.x == 0) {
-    s_fallback = total > a.lds_cap ? 1 : 0;
-    int acc = 0;
-    for (int hc = 0; hc < bx * by; ++hc) {
-      int hx = hc / by, hy = hc % by;
-      int col = ((hx + rx) * nyn + (hy + ry)) * nzn;
-      s_hstart[hc] = acc;
-      acc += tab[col + rz + bz] - tab[col + rz];
-    }
-    s_hstart[bx * by] = acc;
-  }
-  __syncthreads();
-  const bool fallback = s_fallback != 0;
-  const int ni = s_hstart[bx * by];
-  const double h0 = R.L[0] / nx, h1 = R.L[1] / ny, h2 = R.L[2] / nz;
-  const double hmax = fmax(h0, fmax(h1, h2));
-  PairGeom<T> geo;
-  if (sizeof(T) == 4) {
-    geo.unit = (T)(hmax / STAGE_FRAC);
-    geo.unit2 = geo.unit * geo.unit;
-    geo.rc2u = (T)(R.rc2 / ((hmax / STAGE_FRAC) * (hmax / STAGE_FRAC)));
-  } else {
-    geo.unit = (T)1;
-    geo.unit2 = (T)1;
-    geo.rc2u = (T)R.rc2;
-  }
-
-  // 2. stage positions relative to the brick corner, images applied
-  if (!fallback) {
-    const double ox = B.c0[0] * h0, oy = B.c0[1] * h1, oz = B.c0[2] * h2;
-    const double inv_unit = STAGE_FRAC / hmax;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      int lo = 0, hi = ncn - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (tab[mid] <= e)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      const int k = lo;
-      int ic = k % nzn, t = k / nzn, ib = t % nyn, ia = t / nyn, s0, s1, s2;
-      int cx = wrap_cell(B.c0[0] - rx + ia, nx, s0);
-      int cy = wrap_cell(B.c0[1] - ry + ib, ny, s1);
-      int cz = wrap_cell(B.c0[2] - rz + ic, nz, s2);
-      int g = R.cell_off + (cx * ny + cy) * nz + cz;
-      int j = start[g] + (e - tab[k]);
-      const double xr = (double)a.pos[0][j] * R.scaled[0] + s0 * R.L[0] - ox;
-      const double yr = (double)a.pos[1][j] * R.scaled[1] + s1 * R.L[1] - oy;
-      const double zr = (double)a.pos[2][j] * R.scaled[2] + s2 * R.L[2] - oz;
-      StageRec<T> r;
-      if constexpr (sizeof(T) == 4) {
-        r.x = (int)llrint(xr * inv_unit);
-        r.y = (int)llrint(yr * inv_unit);
-        r.z = (int)llrint(zr * inv_unit);
-      } else {
-        r.x = xr;
-        r.y = yr;
-        r.z = zr;
-      }
-      r.p = a.param[j];
-      st[e] = r;
-    }
-  }
-  __syncthreads();
-
-  const GcmPar<T>* gtab = reinterpret_cast<const GcmPar<T>*>(a.gcm);
-  const ElecPar<T>* etab = reinterpret_cast<const ElecPar<T>*>(a.elec);
-  const AdjPar<T>* atab = reinterpret_cast<const AdjPar<T>*>(a.adj);
-  const T sx = (T)R.scaled[0], sy = (T)R.scaled[1], sz = (T)R.scaled[2];
-  const T rc2 = (T)R.rc2;
-  const T beta = (T)R.beta, beta2 = (T)(R.beta * R.beta), lB = (T)R.lB;
-  const float rcc = sqrtf(R.rc2f) * 1.0001f + 1e-6f;
-  const float rcc2 = rcc * rcc;
-  const float hf0 = (float)h0, hf1 = (float)h1, hf2 = (float)h2;
-  const int ncy = 2 * ry + 1;
-
+template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
+__global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
+  constexpr int CJ = 64 / CI;
+  __shared__ double red[NL_WAVES];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const Tile tl = a.tiles[blockIdx.x];
+  const RepDesc& R = a.rep[tl.rep];
+  const int il = lane / CJ, jl = lane % CJ;
   Lane<T> L;
   lane_zero(L);
-  const int per_pass = blockDim.x / TPA;
-  const int sub = threadIdx.x % TPA;
-  const int lb = threadIdx.x / TPA;  // bead slot of this lane group within the pass
-  // this workgroup's slice of the brick's home beads
-  const int i_lo = B.h0, i_hi = min(ni, B.h0 + B.hn);
-  for (int base = i_lo; base < i_hi; base += per_pass) {
-    const int ibd = base + lb;
-    const bool active = ibd < i_hi;
-    int gi = 0, ti = 0;
-    L.fx = L.fy = L.fz = 0;
-    int hx = 0, hy = 0, hz = 0, slot = 0, col = 0;
-    if (active) {
-      int hc = 0;
-      while (hc + 1 < bx * by && s_hstart[hc + 1] <= ibd) ++hc;
-      hx = hc / by;
-      hy = hc % by;
-      col = ((hx + rx) * nyn + (hy + ry)) * nzn;
-      slot = tab[col + rz] + (ibd - s_hstart[hc]);
-      while (hz + 1 < bz && tab[col + rz + hz + 1] <= slot) ++hz;
+  if (wave < tl.count) {
+    const int c = tl.first + wave;
+    const int2 info = a.cl[c];
+    const int first = info.x, ni = info.y >> 16;
+    const bool vi = il < ni;
+    const int i = first + (vi ? il : 0);
+    const uint32_t uix = a.pos[0][i], uiy = a.pos[1][i], uiz = a.pos[2][i];
+    const uint32_t pi = a.param[i];
+    const int ti = param_type(pi);
+    const T zi = (T)param_z(pi);
+    const GcmPar<T>* grow = reinterpret_cast<const GcmPar<T>*>(a.gcm) + ((size_t)tl.rep * MAXT + ti) * MAXT;
+    const ElecPar<T>* erow = reinterpret_cast<const ElecPar<T>*>(a.elec) + ((size_t)tl.rep * MAXT + ti) * MAXT;
+    const AdjPar<T>* arow = reinterpret_cast<const AdjPar<T>*>(a.adj) + ((size_t)tl.rep * MAXT + ti) * MAXT;
+    const T sx = (T)R.scaled[0], sy = (T)R.scaled[1], sz = (T)R.scaled[2];
+    const T rc2 = (T)R.rc2;
+    const T beta = (T)R.beta, beta2 = (T)(R.beta * R.beta), lB = (T)R.lB;
+    const int cnt = a.count[c];
+    const uint32_t* __restrict__ lst = a.list + (size_t)c * a.cap;
+    for (int e = jl; e < cnt; e += CJ) {
+      const int j = (int)lst[e];
+      const T dx = (T)(int)(uix - a.pos[0][j]) * sx;
+      const T dy = (T)(int)(uiy - a.pos[1][j]) * sy;
+      const T dz = (T)(int)(uiz - a.pos[2][j]) * sz;
+      const T r2 = dx * dx + dy * dy + dz * dz;
+      if (vi && r2 < rc2 && j != i)
+        interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, a.param[j], grow, erow, arow, zi, beta, beta2, lB);
     }
-    if (!fallback) {
-      StageRec<T> me{};
-      float xf = 0.f, yf = 0.f, zf = 0.f;
-      if (active) {
-        me = st[slot];
-        xf = geo.coord(me.x);
-        yf = geo.coord(me.y);
-        zf = geo.coord(me.z);
-      }
-      // LDS range [lo, hi) of column k of this bead's culled neighbourhood,
-      // packed lo | hi << 16 (empty if the column is beyond rc)
-      auto col_range = [&](int k) -> uint32_t {
-        const int dxc = k / ncy - rx, dyc = k % ncy - ry;
-        const int cxn = hx + dxc, cyn = hy + dyc;
-        const float gx = fmaxf(0.f, fmaxf((float)cxn * hf0 - xf, xf - (float)(cxn + 1) * hf0));
-        const float gy = fmaxf(0.f, fmaxf((float)cyn * hf1 - yf, yf - (float)(cyn + 1) * hf1));
-        const float d2 = gx * gx + gy * gy;
-        if (!(d2 < rcc2)) return 0u;
-        const float zr = sqrtf(rcc2 - d2);
-        int zlo = (int)floorf((zf - zr) / hf2), zhi = (int)floorf((zf + zr) / hf2);
-        zlo = max(zlo, hz - rz);
-        zhi = min(zhi, hz + rz);
-        const int cb = ((cxn + rx) * nyn + (cyn + ry)) * nzn + rz;
-        return (uint32_t)tab[cb + zlo] | ((uint32_t)tab[cb + zhi + 1] << 16);
-      };
-      // with several lanes per bead the ranges are computed once, by the
-      // bead's lanes together, into an LDS list
-      uint32_t* myr = colr + (size_t)lb * a.ncol_max;
-      if (TPA > 1) {
-        if (active)
-          for (int k = sub; k < ncol; k += TPA) myr[k] = col_range(k);
-        __syncthreads();
-      }
-      {
-        if (active) {
-          ti = param_type(me.p);
-          // sorted index of the home bead: its cell's start + rank in the cell
-          const int kc = col + rz + hz;
-          int s0, s1, s2;
-          const int gx = wrap_cell(B.c0[0] + hx, nx, s0), gy = wrap_cell(B.c0[1] + hy, ny, s1);
-          const int gz = wrap_cell(B.c0[2] + hz, nz, s2);
-          gi = start[R.cell_off + (gx * ny + gy) * nz + gz] + (slot - tab[kc]);
-        }
-        const T zi = (T)param_z(me.p);
-        const GcmPar<T>* grow = gtab + ((size_t)B.rep * MAXT + ti) * MAXT;
-        const ElecPar<T>* erow = etab + ((size_t)B.rep * MAXT + ti) * MAXT;
-        const AdjPar<T>* arow = atab + ((size_t)B.rep * MAXT + ti) * MAXT;
-        // Walk the concatenated column ranges: candidate c (c = sub, sub +
-        // TPA, ...) of the bead lies in column k at LDS slot jlo + c - P.
-        // Hits go to this lane's LDS queue; queued hits are evaluated only
-        // while at least 3/4 of the wave has one, so the costly interaction
-        // runs with dense lanes.  Each lane keeps its own hits in order, so
-        // every force is still a fixed-order private sum.
-        unsigned short* q = qbuf + (size_t)threadIdx.x * QN;
-        int qh = 0, qt = 0;
-        int k = -1, P = 0, jlo = 0, n = 0;
-        int c = sub;
-        bool more = active;
-        auto advance = [&]() {
-          while (more && c >= P + n) {
-            P += n;
-            ++k;
-            if (k >= ncol) {
-              more = false;
-              break;
-            }
-            const uint32_t v = TPA > 1 ? myr[k] : col_range(k);
-            jlo = (int)(v & 0xffffu);
-            n = (int)(v >> 16) - jlo;
-          }
-        };
-        auto drain_one = [&]() {
-          const int j = q[qh & (QN - 1)];
-          ++qh;
-          T ddx, ddy, ddz, r2;
-          const StageRec<T> o = st[j];
-          geo.sep(me, o, ddx, ddy, ddz, r2);
-          interact<T, ELEC, EV, ADJ, COUNT>(L, ddx, ddy, ddz, r2, o.p, grow, erow, arow, zi, beta, beta2, lB);
-        };
-        advance();
-        while (__any(more)) {
-#pragma unroll
-          for (int s = 0; s < SCAN_BATCH; ++s) {
-            if (more && qt - qh < QN) {
-              const int j = jlo + (c - P);
-              T ddx, ddy, ddz, r2;
-              if (geo.sep(me, st[j], ddx, ddy, ddz, r2) && j != slot) {
-                q[qt & (QN - 1)] = (unsigned short)j;
-                ++qt;
-              }
-              c += TPA;
-              advance();
-            }
-          }
-          while (true) {
-            const bool blocked = more && qt - qh == QN;
-            if (__popcll(__ballot(qt > qh)) < DRAIN_MIN && !__any(blocked)) break;
-            if (qt > qh) drain_one();
-          }
-        }
-        while (__any(qt > qh)) {
-          if (qt > qh) drain_one();
-        }
-      }
-      if (TPA > 1) __syncthreads();
-    } else if (active) {
-      // global-memory walk for a neighbourhood too large for LDS
-      const int kc = col + rz + hz;
-      int ic = kc % nzn, t = kc / nzn, ib = t % nyn, ia = t / nyn, s0, s1, s2;
-      int cx = wrap_cell(B.c0[0] - rx + ia, nx, s0);
-      int cy = wrap_cell(B.c0[1] - ry + ib, ny, s1);
-      int cz = wrap_cell(B.c0[2] - rz + ic, nz, s2);
-      int g = R.cell_off + (cx * ny + cy) * nz + cz;
-      gi = start[g] + (slot - tab[kc]);
-      const uint32_t u[3] = {a.pos[0][gi], a.pos[1][gi], a.pos[2][gi]};
-      const uint32_t pi = a.param[gi];
-      ti = param_type(pi);
-      const T zi = (T)param_z(pi);
-      const GcmPar<T>* grow = gtab + ((size_t)B.rep * MAXT + ti) * MAXT;
-      const ElecPar<T>* erow = etab + ((size_t)B.rep * MAXT + ti) * MAXT;
-      const AdjPar<T>* arow = atab + ((size_t)B.rep * MAXT + ti) * MAXT;
-      const int me = gi;
-      for_each_candidate<TPA>(R, u, start, sub, [&](int j) {
-        T ddx = (T)(int)(u[0] - a.pos[0][j]) * sx;
-        T ddy = (T)(int)(u[1] - a.pos[1][j]) * sy;
-        T ddz = (T)(int)(u[2] - a.pos[2][j]) * sz;
-        T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-        if (r2 < rc2 && j != me)
-          interact<T, ELEC, EV, ADJ, COUNT>(L, ddx, ddy, ddz, r2, a.param[j], grow, erow, arow, zi, beta, beta2, lB);
-      });
-    }
-    if (ADJ && active) flush_adj<T, ELEC>(L, ti);
+    if (ADJ && vi) flush_adj<T, ELEC>(L, ti);
     T fx = L.fx, fy = L.fy, fz = L.fz;
-    if (TPA > 1) {
-      fx = lane_reduce(fx, TPA);
-      fy = lane_reduce(fy, TPA);
-      fz = lane_reduce(fz, TPA);
+#pragma unroll
+    for (int o = CJ >> 1; o > 0; o >>= 1) {
+      fx += __shfl_xor(fx, o, 64);
+      fy += __shfl_xor(fy, o, 64);
+      fz += __shfl_xor(fz, o, 64);
     }
-    if (active && sub == 0) {
-      const int fi = ELEC ? a.qidx[gi] : gi;
+    if (vi && jl == 0) {
+      const int fi = ELEC ? a.qidx[i] : i;
       atomicAdd((unsigned long long*)&a.F[0][fi], (unsigned long long)to_fixed((double)fx, a.fscale, a.status));
       atomicAdd((unsigned long long*)&a.F[1][fi], (unsigned long long)to_fixed((double)fy, a.fscale, a.status));
       atomicAdd((unsigned long long*)&a.F[2][fi], (unsigned long long)to_fixed((double)fz, a.fscale, a.status));
@@ -649,9 +461,9 @@ __global__ __launch_bounds__(1024) void k_pair(PairLaunch a) {
   }
 
   if (COUNT) {
-    unsigned long long c = L.cnt;
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(a.pair_count, c);
+    unsigned long long cc = L.cnt;
+    for (int o = 32; o > 0; o >>= 1) cc += __shfl_xor(cc, o, 64);
+    if (lane == 0 && cc) atomicAdd(a.pair_count, cc);
   }
   if (EV) {
     double v[7] = {L.e, L.w0, L.w1, L.w2, L.w3, L.w4, L.w5};
@@ -676,69 +488,57 @@ __global__ __launch_bounds__(1024) void k_pair(PairLaunch a) {
   }
 }
 
-// Workgroups may use more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per
-// CU): raise each kernel's limit once to what it is launched with.
-void allow_lds(const void* fn, size_t bytes) {
-  static std::mutex mu;
-  static std::map<const void*, size_t> done;
-  if (bytes <= 65536) return;
-  std::lock_guard<std::mutex> lk(mu);
-  size_t& d = done[fn];
-  if (d >= bytes) return;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess) d = bytes;
-}
-
-template <typename T, int TPA, bool ELEC, bool EV, bool ADJ, bool COUNT>
-void launch_one(hipStream_t s, const PairLaunch& a) {
-  auto fn = k_pair<T, TPA, ELEC, EV, ADJ, COUNT>;
-  allow_lds((const void*)fn, a.lds_bytes);
-  hipLaunchKernelGGL(fn, dim3(a.nbricks), dim3(a.threads), a.lds_bytes, s, a);
-}
-
-template <typename T, int TPA, bool ELEC>
+template <typename T, int CI, bool ELEC>
 void dispatch_mode(hipStream_t s, const PairLaunch& a, bool ev, bool adj, bool count) {
+  dim3 g(a.ntiles), b(NL_WAVES * 64);
   if (count)
-    launch_one<T, TPA, ELEC, false, false, true>(s, a);
+    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, false, false, true>), g, b, 0, s, a);
   else if (adj)
-    launch_one<T, TPA, ELEC, true, true, false>(s, a);
+    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, true, true, false>), g, b, 0, s, a);
   else if (ev)
-    launch_one<T, TPA, ELEC, true, false, false>(s, a);
+    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, true, false, false>), g, b, 0, s, a);
   else
-    launch_one<T, TPA, ELEC, false, false, false>(s, a);
+    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, false, false, false>), g, b, 0, s, a);
 }
 
 template <typename T, bool ELEC>
-void dispatch_tpa(hipStream_t s, const PairLaunch& a, int tpa, bool ev, bool adj, bool count) {
-  switch (tpa) {
-    case 1: dispatch_mode<T, 1, ELEC>(s, a, ev, adj, count); break;
+void dispatch_ci(hipStream_t s, const PairLaunch& a, bool ev, bool adj, bool count) {
+  switch (a.ci) {
     case 2: dispatch_mode<T, 2, ELEC>(s, a, ev, adj, count); break;
-    case 4: dispatch_mode<T, 4, ELEC>(s, a, ev, adj, count); break;
     case 8: dispatch_mode<T, 8, ELEC>(s, a, ev, adj, count); break;
-    default: dispatch_mode<T, 16, ELEC>(s, a, ev, adj, count); break;
+    default: dispatch_mode<T, 4, ELEC>(s, a, ev, adj, count); break;
   }
 }
 
 }  // namespace
 
-void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, int tpa, bool ev, bool adjoint) {
-  if (a.nbricks <= 0) return;
+void launch_nl_build(hipStream_t s, const PairLaunch& a) {
+  if (a.ncl <= 0) return;
+  dim3 g((a.ncl + NL_WAVES - 1) / NL_WAVES), b(NL_WAVES * 64);
+  switch (a.ci) {
+    case 2: hipLaunchKernelGGL(k_nl_build<2>, g, b, 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_nl_build<8>, g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_nl_build<4>, g, b, 0, s, a); break;
+  }
+}
+
+void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint) {
+  if (a.ntiles <= 0) return;
   bool count = a.pair_count != nullptr;
   if (fp64)
-    dispatch_tpa<double, false>(s, a, tpa, ev, adjoint, count);
+    dispatch_ci<double, false>(s, a, ev, adjoint, count);
   else
-    dispatch_tpa<float, false>(s, a, tpa, ev, adjoint, count);
+    dispatch_ci<float, false>(s, a, ev, adjoint, count);
 }
 
-void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, int tpa, bool ev, bool adjoint) {
-  if (a.nbricks <= 0) return;
+void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint) {
+  if (a.ntiles <= 0) return;
   if (fp64)
-    dispatch_tpa<double, true>(s, a, tpa, ev, adjoint, false);
+    dispatch_ci<double, true>(s, a, ev, adjoint, false);
   else
-    dispatch_tpa<float, true>(s, a, tpa, ev, adjoint, false);
+    dispatch_ci<float, true>(s, a, ev, adjoint, false);
 }
 
-size_t pair_stage_bytes(bool fp64) { return fp64 ? sizeof(StageRec<double>) : sizeof(StageRec<float>); }
-
-int pair_queue_bytes(int threads) { return threads * QN * 2; }
+int pair_waves_per_block() { return NL_WAVES; }
 
 }  // namespace gcme

@@ -178,13 +178,11 @@ class GCMe:
     def tuning(self):
         t = B.gcme_tuning()
         B.check(self.h, self.lib.gcme_get_tuning(self.h, C.byref(t)))
-        return dict(cells_per_cutoff=t.cells_per_cutoff, lanes_per_bead=t.lanes_per_bead,
-                    lanes_per_charge=t.lanes_per_charge, beads_per_brick=t.beads_per_brick,
-                    charges_per_brick=t.charges_per_brick)
+        return dict(cells_per_cutoff=t.cells_per_cutoff, beads_per_cluster=t.beads_per_cluster,
+                    charges_per_cluster=t.charges_per_cluster, list_slack_pct=t.list_slack_pct)
 
-    def set_tuning(self, cells_per_cutoff=-1, lanes_per_bead=-1, lanes_per_charge=-1, beads_per_brick=-1,
-                   charges_per_brick=-1):
-        t = B.gcme_tuning(cells_per_cutoff, lanes_per_bead, lanes_per_charge, beads_per_brick, charges_per_brick)
+    def set_tuning(self, cells_per_cutoff=-1, beads_per_cluster=-1, charges_per_cluster=-1, list_slack_pct=-1):
+        t = B.gcme_tuning(cells_per_cutoff, beads_per_cluster, charges_per_cluster, list_slack_pct)
         B.check(self.h, self.lib.gcme_set_tuning(self.h, C.byref(t)))
 
     def profile_step(self, n_reps: int = 10) -> dict:
