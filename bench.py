@@ -129,15 +129,13 @@ def main():
     alg = {
         # (bound, algorithmic amount per launch)
         "pair_gcm": ("alu", FLOP_PER_GCM_PAIR * pairs),
-        "fft_z_r2c": ("hbm", ngrid * 8 + nch * cs),
+        "spread_z": ("hbm", nq * 16 + nch * cs),
         "fft_y": ("hbm", 2 * nch * cs),
         "fft_x_conv": ("hbm", 2 * nch * cs),
         "fft_y_inv": ("hbm", 2 * nch * cs),
-        "fft_z_c2r": ("hbm", nch * cs + ngrid * rs),
+        "z_gather": ("hbm", nch * cs + nq * (16 + 4 + 24)),
         "int_first": ("hbm", w.N * (12 + 24 + 8 + 4 + 4 + 24 + 12 + 24)),
         "int_last": ("hbm", w.N * (12 + 24 + 4 + 4 + 24 + 12 + 24 + 4 + 4)),
-        "gather": ("hbm", nq * (12 + 4 + 4 + 24)),
-        "spread": ("hbm", nq * (12 + 4)),
         "sort": ("hbm", w.N * (12 + 4 + 4 + 12 + 24 + 4 + 4)),
     }
     bound, amount = alg.get(dom, ("alu", 0.0))

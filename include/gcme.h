@@ -192,7 +192,7 @@ gcme_status gcme_count_pairs(gcme_handle h, uint64_t* n_pairs);
  * saved before and restored after, so the call leaves the simulation as it
  * found it.  Synchronous.  gcme_stage_name(i) names stage i (NULL if out of
  * range). */
-#define GCME_N_STAGES 14
+#define GCME_N_STAGES 12
 gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms);
 const char* gcme_stage_name(int32_t i);
 

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "GCME_OK", 1: "GCME_EINVAL", 2: "GCME_EUNSUPPORTED", 3: "GCME
 EXPORTED = ["gcme_create", "gcme_set_params", "gcme_set_state", "gcme_get_state", "gcme_forces_energy",
             "gcme_step", "gcme_sync", "gcme_last_error", "gcme_get_tuning", "gcme_set_tuning",
             "gcme_autotune", "gcme_count_pairs", "gcme_profile_step", "gcme_stage_name", "gcme_destroy"]
-GCME_N_STAGES = 14
+GCME_N_STAGES = 12
 
 
 class gcme_create_info(C.Structure):

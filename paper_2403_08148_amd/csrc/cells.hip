@@ -205,7 +205,7 @@ __global__ void k_scatter(CellView c, int N) {
 // Position p of the scattered array holds bead s of cell c in arbitrary
 // order; its final slot is start[c] + (number of beads of c with a smaller
 // previous index).  Charged beads get the same rank among charged beads.
-__global__ void k_permute(StateView A, StateView B, CellView c, ChargedView q, int N) {
+__global__ void k_permute(StateView A, StateView B, uint4* __restrict__ bpk, CellView c, ChargedView q, int N) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   // the counts were consumed by the scan: clear them for the next binning
   for (int k = p; k < c.ncells; k += gridDim.x * blockDim.x) {
@@ -236,12 +236,11 @@ __global__ void k_permute(StateView A, StateView B, CellView c, ChargedView q, i
   B.vel[2][n] = A.vel[2][s];
   B.param[n] = prm;
   B.id[n] = A.id[s];
+  const uint4 rec = make_uint4(px, py, pz, prm);
+  bpk[n] = rec;
   if (charged) {
     int qn = c.qstart[cid] + qrank;
-    q.pos[0][qn] = px;
-    q.pos[1][qn] = py;
-    q.pos[2][qn] = pz;
-    q.param[qn] = prm;
+    q.pk[qn] = rec;
     q.idx[qn] = n;
   }
 }
@@ -303,8 +302,8 @@ void launch_scatter(hipStream_t s, CellView c, int N) {
   hipLaunchKernelGGL(k_scatter, dim3(nblk(N, 256)), dim3(256), 0, s, c, N);
 }
 
-void launch_permute(hipStream_t s, StateView A, StateView B, CellView c, ChargedView q, int N) {
-  hipLaunchKernelGGL(k_permute, dim3(nblk(N, 256)), dim3(256), 0, s, A, B, c, q, N);
+void launch_permute(hipStream_t s, StateView A, StateView B, uint4* bpk, CellView c, ChargedView q, int N) {
+  hipLaunchKernelGGL(k_permute, dim3(nblk(N, 256)), dim3(256), 0, s, A, B, bpk, c, q, N);
 }
 
 void launch_commit(hipStream_t s, StateView B, StateView A, int N) {

@@ -117,9 +117,9 @@ struct gcme_ctx {
   DevBuf a_pos[3], a_vel[3], a_param, a_id;
   DevBuf b_pos[3], b_vel[3], b_param, b_id;
   DevBuf cell, tmp, counts, qcounts, fill, start, qstart, bsum;
-  DevBuf q_pos[3], q_param, q_idx;
+  DevBuf b_pk, q_pk, q_idx;
   DevBuf F;
-  DevBuf Qint, Qc, phi;
+  DevBuf Qc, d_mtiles;
   DevBuf d_rep, d_gcm, d_elec, d_adj;
   DevBuf d_tw, d_rad, d_bsp, d_freq;
   DevBuf d_items[3];
@@ -135,6 +135,8 @@ struct gcme_ctx {
   long long grid_total = 0, cgrid_total = 0;
   int ncl_g = 0, ncl_q = 0, ntiles_g = 0, ntiles_q = 0, ntiles_256 = 0;
   int cap_g = 64, cap_q = 64;
+  int nmtiles = 0, mtx = 4, mty = 4;
+  int lds_max = 65536;  // dynamic LDS a workgroup may use
   int nitems[3] = {0, 0, 0};
   int lb[3] = {0, 0, 0};
   int maxK[3] = {0, 0, 0};
@@ -212,8 +214,7 @@ CellView cview(gcme_handle h) {
 
 ChargedView qview(gcme_handle h) {
   ChargedView q;
-  for (int k = 0; k < 3; ++k) q.pos[k] = h->q_pos[k].as<uint32_t>();
-  q.param = h->q_param.as<uint32_t>();
+  q.pk = h->q_pk.as<uint4>();
   q.idx = h->q_idx.as<int>();
   return q;
 }
@@ -454,7 +455,7 @@ gcme_status build_plan(gcme_handle h) {
   h->grid_total = goff;
   h->cgrid_total = cgoff;
 
-  const size_t cs = h->fp64 ? 16 : 8, rs = h->fp64 ? 8 : 4;
+  const size_t cs = h->fp64 ? 16 : 8;
   // lines per mesh work item: two LDS buffers of LB+1 padded lines stay
   // below 64 KiB together with the kernels' static reduction buffer
   const int cap = h->fp64 ? 2048 : 4096;
@@ -505,7 +506,7 @@ gcme_status build_plan(gcme_handle h) {
   for (int r = 0; r < R; ++r) {
     const RepDesc& d = h->rep[r];
     int nlz = d.K[0] * d.K[1];
-    for (int l = 0; l < nlz; l += h->lb[0]) items[0].push_back(LineItem{r, l, std::min(h->lb[0], nlz - l), 0});
+    (void)nlz;
     // balanced batches of the K2/2+1 strided lines
     int c1 = (d.K2h + h->lb[1] - 1) / h->lb[1], b1 = (d.K2h + c1 - 1) / c1;
     int c2 = (d.K2h + h->lb[2] - 1) / h->lb[2], b2 = (d.K2h + c2 - 1) / c2;
@@ -518,6 +519,27 @@ gcme_status build_plan(gcme_handle h) {
         items[2].push_back(LineItem{r, y * d.K2h + kz, std::min(b2, d.K2h - kz), 0});
   }
   item_off[R] = (int)items[2].size();
+  // mesh tiles of the fused spread / gather passes: 4 x 4 z lines, fewer if
+  // the two LDS line buffers would not fit
+  h->mtx = 4;
+  h->mty = 4;
+  while (h->mtx * h->mty > 1 && pme_tile_lds_bytes(h->maxK[0], h->mtx, h->mty, h->fp64) > (size_t)h->lds_max) {
+    if (h->mtx >= h->mty)
+      h->mtx /= 2;
+    else
+      h->mty /= 2;
+  }
+  if (pme_tile_lds_bytes(h->maxK[0], h->mtx, h->mty, h->fp64) > (size_t)h->lds_max)
+    return fail(h, GCME_EUNSUPPORTED, "mesh z length too large for the LDS of one workgroup");
+  std::vector<MeshTile> mtiles;
+  for (int r = 0; r < R; ++r) {
+    const RepDesc& d = h->rep[r];
+    for (int x = 0; x < d.K[0]; x += h->mtx)
+      for (int y = 0; y < d.K[1]; y += h->mty)
+        mtiles.push_back(MeshTile{r, x, y, std::min(h->mtx, d.K[0] - x) | (std::min(h->mty, d.K[1] - y) << 16)});
+  }
+  h->nmtiles = h->NQ > 0 ? (int)mtiles.size() : 0;
+  upload(mtiles, h->d_mtiles, s);
   for (int ps = 0; ps < 3; ++ps) {
     h->nitems[ps] = (int)items[ps].size();
     upload(items[ps], h->d_items[ps], s);
@@ -568,11 +590,8 @@ gcme_status build_plan(gcme_handle h) {
   HIPCHK(h, hipMemsetAsync(h->counts.p, 0, (size_t)h->ncells * 4, s));
   HIPCHK(h, hipMemsetAsync(h->qcounts.p, 0, (size_t)h->ncells * 4, s));
 
-  // meshes (Q must start cleared; the z pass clears it after each use)
-  HIPCHK(h, h->Qint.alloc((size_t)h->grid_total * 8));
-  HIPCHK(h, hipMemsetAsync(h->Qint.p, 0, (size_t)h->grid_total * 8, s));
+  // half-complex mesh
   HIPCHK(h, h->Qc.alloc((size_t)h->cgrid_total * cs));
-  HIPCHK(h, h->phi.alloc((size_t)h->grid_total * rs));
 
   // integrator constants, energy constants
   std::vector<double> imass(R * MAXT, 1.0), c1(R), c2s(R * MAXT, 0.0), dtv(R), consts(2 * R), Av(R * MAXT * MAXT, 0.0),
@@ -633,8 +652,7 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.cap = h->cap_q;
     a.list = h->list_q.as<uint32_t>();
     a.count = h->cnt_q.as<int>();
-    for (int k = 0; k < 3; ++k) a.pos[k] = h->q_pos[k].as<uint32_t>();
-    a.param = h->q_param.as<uint32_t>();
+    a.pk = h->q_pk.as<uint4>();
     a.start = h->qstart.as<int>();
     a.qidx = h->q_idx.as<int>();
     a.part = h->part[SLOT_REAL].as<double>();
@@ -648,8 +666,7 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.cap = h->cap_g;
     a.list = h->list_g.as<uint32_t>();
     a.count = h->cnt_g.as<int>();
-    for (int k = 0; k < 3; ++k) a.pos[k] = h->b_pos[k].as<uint32_t>();
-    a.param = h->b_param.as<uint32_t>();
+    a.pk = h->b_pk.as<uint4>();
     a.start = h->start.as<int>();
     a.part = h->part[SLOT_GCM].as<double>();
     a.adj_part = h->adjp[0].as<double>();
@@ -663,19 +680,21 @@ PmeLaunch pme_args(gcme_handle h) {
   a.nrep = h->R;
   a.nq = h->NQ;
   a.order = h->order;
+  a.qpk = h->q_pk.as<uint4>();
   for (int k = 0; k < 3; ++k) {
-    a.qpos[k] = h->q_pos[k].as<uint32_t>();
     a.F[k] = Fk(h, k);
     a.items[k] = h->d_items[k].as<LineItem>();
     a.nitems[k] = h->nitems[k];
     a.lb[k] = h->lb[k];
     a.maxK[k] = h->maxK[k];
   }
-  a.qparam = h->q_param.as<uint32_t>();
   a.qidx = h->q_idx.as<int>();
-  a.Qint = h->Qint.as<long long>();
+  a.qstart = h->qstart.as<int>();
+  a.tiles = h->d_mtiles.as<MeshTile>();
+  a.ntiles = h->nmtiles;
+  a.tx = h->mtx;
+  a.ty = h->mty;
   a.Qc = h->Qc.p;
-  a.phi = h->phi.p;
   a.tw = h->d_tw.p;
   a.radix = h->d_rad.as<int>();
   a.bsp = h->d_bsp.p;
@@ -712,7 +731,7 @@ void enqueue_sort(gcme_handle h, hipStream_t s) {
   launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
   launch_scan(s, c);
   launch_scatter(s, c, h->N);
-  launch_permute(s, viewA(h), viewB(h), c, qview(h), h->N);
+  launch_permute(s, viewA(h), viewB(h), h->b_pk.as<uint4>(), c, qview(h), h->N);
 }
 
 // Forces (and partial sums if ev) on the sorted copy B; F must be cleared.
@@ -731,13 +750,11 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
   (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
   PmeLaunch p = pme_args(h);
-  launch_spread(h->aux[1], p, h->fp64);
-  launch_fft_z_r2c(h->aux[1], p, h->fp64);
+  launch_spread_z(h->aux[1], p, h->fp64);
   launch_fft_y(h->aux[1], p, h->fp64, false);
   launch_fft_x_conv(h->aux[1], p, h->fp64, ev);
   launch_fft_y(h->aux[1], p, h->fp64, true);
-  launch_fft_z_c2r(h->aux[1], p, h->fp64);
-  launch_gather(h->aux[1], p, h->fp64);
+  launch_z_gather(h->aux[1], p, h->fp64);
   PairLaunch q = pair_args(h, true);
   launch_nl_build(h->aux[0], q);
   launch_pair_elec(h->aux[0], q, h->fp64, ev, adj);
@@ -864,6 +881,11 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   h->N = (int)total;
   h->fp64 = info->precision == GCME_FP64;
   h->seed = info->seed;
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lds > 0)
+      h->lds_max = lds - 4096;  // less the kernels' static LDS
+  }
   h->hp.assign(h->R, HostRep{});
   h->nq.assign(h->R, 0);
   h->qoff.assign(h->R, 0);
@@ -895,6 +917,7 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   ok &= h->a_param.alloc(N * 4) == hipSuccess;
   ok &= h->b_param.alloc(N * 4) == hipSuccess;
   ok &= h->a_id.alloc(N * 4) == hipSuccess;
+  ok &= h->b_pk.alloc(N * 16) == hipSuccess;
   ok &= h->b_id.alloc(N * 4) == hipSuccess;
   ok &= h->cell.alloc(N * 4) == hipSuccess;
   ok &= h->tmp.alloc(N * 4) == hipSuccess;
@@ -1034,10 +1057,7 @@ gcme_status gcme_set_state(gcme_handle h, const double* pos, const double* vel, 
   h->nq = nq;
   h->qoff = qoff;
   h->NQ = NQ;
-  for (int k = 0; k < 3; ++k) {
-    HIPCHK(h, h->q_pos[k].alloc((size_t)std::max(1, NQ) * 4));
-  }
-  HIPCHK(h, h->q_param.alloc((size_t)std::max(1, NQ) * 4));
+  HIPCHK(h, h->q_pk.alloc((size_t)std::max(1, NQ) * 16));
   HIPCHK(h, h->q_idx.alloc((size_t)std::max(1, NQ) * 4));
   HIPCHK(h, hipMemcpyAsync(h->a_param.p, prm.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(h->a_id.p, id.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
@@ -1265,9 +1285,9 @@ gcme_status gcme_autotune(gcme_handle h) {
   return GCME_OK;
 }
 
-static const char* kStageNames[GCME_N_STAGES] = {"int_first", "sort",      "list_gcm",  "pair_gcm",  "list_elec",
-                                                  "pair_elec", "spread",    "fft_z_r2c", "fft_y",     "fft_x_conv",
-                                                  "fft_y_inv", "fft_z_c2r", "gather",    "int_last"};
+static const char* kStageNames[GCME_N_STAGES] = {"int_first", "sort",       "list_gcm",  "pair_gcm",
+                                                  "list_elec", "pair_elec",  "spread_z",  "fft_y",
+                                                  "fft_x_conv", "fft_y_inv", "z_gather",  "int_last"};
 
 const char* gcme_stage_name(int32_t i) { return (i >= 0 && i < GCME_N_STAGES) ? kStageNames[i] : nullptr; }
 
@@ -1304,13 +1324,11 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
       case 3: launch_pair_gcm(st2, g, h->fp64, false, false); break;
       case 4: launch_nl_build(st2, q); break;
       case 5: launch_pair_elec(st2, q, h->fp64, false, false); break;
-      case 6: launch_spread(st2, p, h->fp64); break;
-      case 7: launch_fft_z_r2c(st2, p, h->fp64); break;
-      case 8: launch_fft_y(st2, p, h->fp64, false); break;
-      case 9: launch_fft_x_conv(st2, p, h->fp64, false); break;
-      case 10: launch_fft_y(st2, p, h->fp64, true); break;
-      case 11: launch_fft_z_c2r(st2, p, h->fp64); break;
-      case 12: launch_gather(st2, p, h->fp64); break;
+      case 6: launch_spread_z(st2, p, h->fp64); break;
+      case 7: launch_fft_y(st2, p, h->fp64, false); break;
+      case 8: launch_fft_x_conv(st2, p, h->fp64, false); break;
+      case 9: launch_fft_y(st2, p, h->fp64, true); break;
+      case 10: launch_z_gather(st2, p, h->fp64); break;
       default: launch_int_last(st2, ia, viewB(h), viewA(h), F3, false); break;
     }
   };
@@ -1319,7 +1337,7 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
   HIPCHK(h, hipEventCreate(&e1));
   for (int i = 0; i < GCME_N_STAGES; ++i) {
     ms[i] = 0.0;
-    if (h->NQ == 0 && i >= 4 && i <= 12) continue;
+    if (h->NQ == 0 && i >= 4 && i <= 10) continue;
     hipGraph_t gr = nullptr;
     hipGraphExec_t ex = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1345,7 +1363,6 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
     HIPCHK(h, hipMemcpyAsync(h->a_vel[k].p, sv[k].p, N * 8, hipMemcpyDeviceToDevice, s));
   }
   HIPCHK(h, hipMemcpyAsync(h->F.p, sF.p, N * 24, hipMemcpyDeviceToDevice, s));
-  launch_fill_i64(s, h->Qint.as<long long>(), 0, h->grid_total);
   unsigned long long stepv = h->step;
   HIPCHK(h, hipMemcpyAsync(h->d_step.p, &stepv, 8, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemsetAsync(h->d_status.p, 0, 4, s));

@@ -84,6 +84,14 @@ struct LineItem {
   int pad;
 };
 
+// A tile of the mesh for the fused spread / gather passes: the z lines
+// x0 <= x < x0 + nx, y0 <= y < y0 + ny of one replica (nxy = nx | ny << 16).
+struct MeshTile {
+  int rep;
+  int x0, y0;
+  int nxy;
+};
+
 // Tiles of consecutive beads (per-bead kernels) or of consecutive clusters
 // (pair kernels) of one replica.
 struct Tile {
@@ -128,9 +136,9 @@ struct CellView {
   int ncells;
 };
 
+// Packed copy of a sorted bead: x, y, z (fractional fixed point), param.
 struct ChargedView {
-  uint32_t* pos[3];
-  uint32_t* param;
+  uint4* pk;         // charged beads in cell order
   int* idx;          // sorted bead index of each charged bead
 };
 
@@ -146,7 +154,7 @@ void launch_fill_i64(hipStream_t s, long long* p, long long v, long long n);
 void launch_bin(hipStream_t s, StateView A, const RepDesc* rep, CellView c, int N);
 void launch_scan(hipStream_t s, CellView c);
 void launch_scatter(hipStream_t s, CellView c, int N);
-void launch_permute(hipStream_t s, StateView A, StateView B, CellView c, ChargedView q, int N);
+void launch_permute(hipStream_t s, StateView A, StateView B, uint4* bpk, CellView c, ChargedView q, int N);
 void launch_commit(hipStream_t s, StateView B, StateView A, int N);
 
 // pair.hip
@@ -166,8 +174,7 @@ struct PairLaunch {
   const void* gcm;     // GcmPar<T>[R][MAXT][MAXT]
   const void* elec;    // ElecPar<T>[R][MAXT][MAXT]
   const void* adj;     // AdjPar<T>[R][MAXT][MAXT]
-  const uint32_t* pos[3];
-  const uint32_t* param;
+  const uint4* pk;     // packed sorted population
   const int* start;    // cell start (all beads or charged beads)
   const int* qidx;     // charged -> sorted bead index (charged kernel)
   long long* F[3];
@@ -188,32 +195,32 @@ struct PmeLaunch {
   int nrep;
   int nq;             // charged beads, all replicas
   int order;          // B-spline order (shared by all replicas)
-  const uint32_t* qpos[3];
-  const uint32_t* qparam;
-  const int* qidx;
-  long long* Qint;
-  void* Qc;           // complex<T>
-  void* phi;          // T
+  const uint4* qpk;   // packed charged beads (cell order)
+  const int* qidx;    // charged -> sorted bead index
+  const int* qstart;  // charged cell list
+  const MeshTile* tiles;  // fused spread + z / z + gather passes
+  int ntiles;
+  int tx, ty;         // tile shape (z lines per axis)
+  void* Qc;           // complex<T> half-complex mesh
   const void* tw;     // complex<T> twiddles
   const int* radix;
   const void* bsp;    // T: 1/|b|^2 per axis entry
   const void* freq;   // T: signed m / L per axis entry
-  const LineItem* items[3];  // Z, Y, X passes
+  const LineItem* items[3];  // (unused), Y, X passes
   int nitems[3];
   int lb[3];          // lines per item for each pass
-  int maxK[3];
+  int maxK[3];        // longest z, y, x line
   long long* F[3];
   double* part;       // recip slot partials [nitems X][PART_W]
   unsigned int* status;
   double fscale;      // force fixed-point scale
   double qscale;      // mesh fixed-point scale
 };
-void launch_spread(hipStream_t s, const PmeLaunch& a, bool fp64);
-void launch_fft_z_r2c(hipStream_t s, const PmeLaunch& a, bool fp64);
+void launch_spread_z(hipStream_t s, const PmeLaunch& a, bool fp64);
 void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse);
 void launch_fft_x_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev);
-void launch_fft_z_c2r(hipStream_t s, const PmeLaunch& a, bool fp64);
-void launch_gather(hipStream_t s, const PmeLaunch& a, bool fp64);
+void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64);
+size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64);
 
 // integrate.hip
 struct IntLaunch {

@@ -123,13 +123,12 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
   const int first = info.x, rep = info.y & 0xffff, ni = info.y >> 16;
   const RepDesc& R = a.rep[rep];
   const int* __restrict__ start = a.start;
-  const uint32_t* __restrict__ px = a.pos[0];
-  const uint32_t* __restrict__ py = a.pos[1];
-  const uint32_t* __restrict__ pz = a.pos[2];
+  const uint4* __restrict__ pk = a.pk;
 
   // cluster beads, as wave-uniform values (slots beyond ni repeat bead 0)
   const int mine = first + (lane < ni ? lane : 0);
-  const uint32_t ux = px[mine], uy = py[mine], uz = pz[mine];
+  const uint4 me = pk[mine];
+  const uint32_t ux = me.x, uy = me.y, uz = me.z;
   uint32_t cxs[CI], cys[CI], czs[CI];
 #pragma unroll
   for (int k = 0; k < CI; ++k) {
@@ -266,7 +265,8 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
         const int q = p + lane;
         const bool v = q < total;
         const int j = v ? s_cand[wave][q] : first;
-        const uint32_t jx = px[j], jy = py[j], jz = pz[j];
+        const uint4 pj = pk[j];
+        const uint32_t jx = pj.x, jy = pj.y, jz = pj.z;
         bool hit = false;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
@@ -411,9 +411,20 @@ template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
 __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
   constexpr int CJ = 64 / CI;
   __shared__ double red[NL_WAVES];
+  // the replica's type-pair tables, staged once per workgroup
+  __shared__ GcmPar<T> s_g[ELEC ? 1 : MAXT * MAXT];
+  __shared__ ElecPar<T> s_e[ELEC ? MAXT * MAXT : 1];
+  __shared__ AdjPar<T> s_a[ADJ ? MAXT * MAXT : 1];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Tile tl = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[tl.rep];
+  {
+    const size_t tb = (size_t)tl.rep * MAXT * MAXT;
+    if (!ELEC && threadIdx.x < MAXT * MAXT) s_g[threadIdx.x] = reinterpret_cast<const GcmPar<T>*>(a.gcm)[tb + threadIdx.x];
+    if (ELEC && threadIdx.x < MAXT * MAXT) s_e[threadIdx.x] = reinterpret_cast<const ElecPar<T>*>(a.elec)[tb + threadIdx.x];
+    if (ADJ && threadIdx.x < MAXT * MAXT) s_a[threadIdx.x] = reinterpret_cast<const AdjPar<T>*>(a.adj)[tb + threadIdx.x];
+    __syncthreads();
+  }
   const int il = lane / CJ, jl = lane % CJ;
   Lane<T> L;
   lane_zero(L);
@@ -423,26 +434,28 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
     const int first = info.x, ni = info.y >> 16;
     const bool vi = il < ni;
     const int i = first + (vi ? il : 0);
-    const uint32_t uix = a.pos[0][i], uiy = a.pos[1][i], uiz = a.pos[2][i];
-    const uint32_t pi = a.param[i];
+    const uint4 mi = a.pk[i];
+    const uint32_t pi = mi.w;
     const int ti = param_type(pi);
     const T zi = (T)param_z(pi);
-    const GcmPar<T>* grow = reinterpret_cast<const GcmPar<T>*>(a.gcm) + ((size_t)tl.rep * MAXT + ti) * MAXT;
-    const ElecPar<T>* erow = reinterpret_cast<const ElecPar<T>*>(a.elec) + ((size_t)tl.rep * MAXT + ti) * MAXT;
-    const AdjPar<T>* arow = reinterpret_cast<const AdjPar<T>*>(a.adj) + ((size_t)tl.rep * MAXT + ti) * MAXT;
+    const GcmPar<T>* grow = s_g + (ELEC ? 0 : ti * MAXT);
+    const ElecPar<T>* erow = s_e + (ELEC ? ti * MAXT : 0);
+    const AdjPar<T>* arow = s_a + (ADJ ? ti * MAXT : 0);
     const T sx = (T)R.scaled[0], sy = (T)R.scaled[1], sz = (T)R.scaled[2];
     const T rc2 = (T)R.rc2;
     const T beta = (T)R.beta, beta2 = (T)(R.beta * R.beta), lB = (T)R.lB;
     const int cnt = a.count[c];
     const uint32_t* __restrict__ lst = a.list + (size_t)c * a.cap;
+    const uint4* __restrict__ pk = a.pk;
     for (int e = jl; e < cnt; e += CJ) {
       const int j = (int)lst[e];
-      const T dx = (T)(int)(uix - a.pos[0][j]) * sx;
-      const T dy = (T)(int)(uiy - a.pos[1][j]) * sy;
-      const T dz = (T)(int)(uiz - a.pos[2][j]) * sz;
+      const uint4 pj = pk[j];
+      const T dx = (T)(int)(mi.x - pj.x) * sx;
+      const T dy = (T)(int)(mi.y - pj.y) * sy;
+      const T dz = (T)(int)(mi.z - pj.z) * sz;
       const T r2 = dx * dx + dy * dy + dz * dz;
       if (vi && r2 < rc2 && j != i)
-        interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, a.param[j], grow, erow, arow, zi, beta, beta2, lB);
+        interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pj.w, grow, erow, arow, zi, beta, beta2, lB);
     }
     if (ADJ && vi) flush_adj<T, ELEC>(L, ti);
     T fx = L.fx, fy = L.fy, fz = L.fz;

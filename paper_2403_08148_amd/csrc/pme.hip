@@ -1,19 +1,26 @@
 // Smooth particle-mesh Ewald for U_recip of eq. ewald (the paper evaluates
 // the reciprocal sum with the particle-mesh Ewald method it cites):
 //
-//   spread   Q(k) = sum_i z_i prod_a M_p(u_ia - k_a)   (fixed-point atomics)
-//   z pass   real-to-complex transform of each z line (and clears Q)
-//   y pass   complex transform of each y line
-//   x pass   transform x lines, multiply by G(m) = B(m) exp(-pi^2 m^2/beta^2)
-//            / (pi V m^2) while summing E = lB/2 sum G |Q^|^2 and the virial,
-//            inverse-transform the lines (one kernel, lines stay in LDS)
-//   y pass   inverse
-//   z pass   complex-to-real inverse -> potential phi(k)
-//   gather   F_i = -lB z_i sum_k grad W_i(k) phi(k)
+//   spread+z  per tile of TX x TY z lines: every charged bead whose B-spline
+//             stencil meets the tile adds z_i prod_a M_p(u_ia - k_a) to the
+//             tile's points (64-bit fixed-point LDS atomics, so the sum is
+//             exact and order-free), then the real-to-complex transform of
+//             the tile's lines; the charge mesh never goes to HBM
+//   y pass    complex transform of each y line
+//   x pass    transform x lines, multiply by G(m) = B(m) exp(-pi^2 m^2/beta^2)
+//             / (pi V m^2) while summing E = lB/2 sum G |Q^|^2 and the virial,
+//             inverse-transform the lines (one kernel, lines stay in LDS)
+//   y pass    inverse
+//   z+gather  per tile: complex-to-real inverse of the tile's lines, then
+//             every bead whose stencil meets the tile adds its share of
+//             F_i = -lB z_i sum_k grad W_i(k) phi(k) (64-bit fixed point)
 //
 // The mesh transforms are Stockham radix-4/2/3 FFTs on batches of lines held
 // in LDS; batches of strided lines are loaded so that consecutive threads
-// touch consecutive addresses.
+// touch consecutive addresses.  The beads of a tile are found through the
+// charged beads' cell list (whole cell columns along z).
+#include <algorithm>
+
 #include "gcme_internal.h"
 
 namespace gcme {
@@ -63,51 +70,6 @@ __device__ inline void mesh_coord(uint32_t u, int K, int& k, T& t) {
   unsigned long long p = (unsigned long long)u * (unsigned)K;
   k = (int)(p >> 32);
   t = (T)((double)(uint32_t)(p & 0xffffffffu) * 2.3283064365386963e-10);
-}
-
-// Eight lanes per charged bead: lane j0 < P of the group handles the
-// x-slab j0 of the P^3 stencil (the others idle), which gives the small
-// charged sets enough lanes to hide the atomics' latency.
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_spread(PmeLaunch a, int nq) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = t >> 3, j0 = t & 7;
-  if (q >= nq || j0 >= P) return;
-  uint32_t prm = a.qparam[q];
-  const RepDesc& R = a.rep[param_rep(prm)];
-  T w[3][P], dw[P];
-  int k0[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T t;
-    mesh_coord<T>(a.qpos[d][q], R.K[d], k0[d], t);
-    bspline<T, P>(t, w[d], dw);
-  }
-  const T z = (T)param_z(prm);
-  const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2];
-  long long* Q = a.Qint + R.grid_off;
-  int g2s[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    int g = k0[2] - j;
-    g2s[j] = g < 0 ? g + K2 : g;
-  }
-  {
-    int g0 = k0[0] - j0;
-    g0 += g0 < 0 ? K0 : 0;
-    T a0 = z * w[0][j0];
-    for (int j1 = 0; j1 < P; ++j1) {
-      int g1 = k0[1] - j1;
-      g1 += g1 < 0 ? K1 : 0;
-      T a01 = a0 * w[1][j1];
-      long long* row = Q + ((long long)g0 * K1 + g1) * K2;
-#pragma unroll
-      for (int j2 = 0; j2 < P; ++j2) {
-        double v = (double)(a01 * w[2][j2]) * a.qscale;
-        atomicAdd((unsigned long long*)&row[g2s[j2]], (unsigned long long)(long long)llrint(v));
-      }
-    }
-  }
 }
 
 // In-LDS Stockham FFT of nl lines of length K (element (k, l) at k*LBP + l).
@@ -173,34 +135,8 @@ __device__ cplx<T>* fft_lines(cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, co
 }
 
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_z_r2c(PmeLaunch a) {
-  extern __shared__ unsigned char smem[];
-  const LineItem it = a.items[0][blockIdx.x];
-  const RepDesc& R = a.rep[it.rep];
-  const int K = R.K[2], K2h = R.K2h, nl = it.count, LBP = a.lb[0] + 1;
-  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
-  long long* Q = a.Qint + R.grid_off + (long long)it.first * K;
-  const double inv_qs = 1.0 / a.qscale;
-  for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
-    int l = e / K, k = e % K;
-    long long v = Q[(long long)l * K + k];
-    Q[(long long)l * K + k] = 0;  // leave the mesh cleared for the next spread
-    A[k * LBP + l] = {(T)((double)v * inv_qs), (T)0};
-  }
-  __syncthreads();
-  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[2];
-  cplx<T>* res = fft_lines<T>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[2], R.nrad[2], false);
-  cplx<T>* out = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)it.first * K2h;
-  for (int e = threadIdx.x; e < nl * K2h; e += blockDim.x) {
-    int l = e / K2h, m = e % K2h;
-    out[(long long)l * K2h + m] = res[m * LBP + l];
-  }
-}
-
-template <typename T>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   const LineItem it = a.items[1][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
   const int K = R.K[1], K2h = R.K2h, nl = it.count, LBP = a.lb[1] + 1;
@@ -235,7 +171,7 @@ __device__ inline double block_sum_fft(double v, double* sh) {
 
 template <typename T, bool EV>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[4];
   const LineItem it = a.items[2][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
@@ -302,125 +238,282 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_z_c2r(PmeLaunch a) {
-  extern __shared__ unsigned char smem[];
-  const LineItem it = a.items[0][blockIdx.x];
-  const RepDesc& R = a.rep[it.rep];
-  const int K = R.K[2], K2h = R.K2h, nl = it.count, LBP = a.lb[0] + 1;
+// Inclusive scan of one int per thread over the block (FFT_THREADS).
+__device__ inline int block_scan_incl(int v, int* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  __syncthreads();
+  if (lane == 63) sh[wid] = v;
+  __syncthreads();
+  int add = 0;
+  for (int w = 0; w < wid; ++w) add += sh[w];
+  return v + add;
+}
+
+// Charged beads whose order-P stencil can meet a mesh tile: whole cell
+// columns (all z) of the charged cell list over the cell range that holds
+// the stencil base points k0 in [t0, t0 + n + P - 2] (mod K) on x and y.
+struct TileCols {
+  int lo[2], n[2];
+};
+__device__ inline TileCols tile_columns(const RepDesc& R, const MeshTile& mt, int P) {
+  TileCols tc;
+  const int t0[2] = {mt.x0, mt.y0};
+  const int nt[2] = {mt.nxy & 0xffff, mt.nxy >> 16};
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const long long nc = R.nc[d], K = R.K[d];
+    const int lo = (int)((t0[d] * nc) / K);
+    const int hi = (int)(((long long)(t0[d] + nt[d] + P - 1) * nc) / K);
+    if (hi - lo + 1 >= nc) {
+      tc.lo[d] = 0;
+      tc.n[d] = (int)nc;
+    } else {
+      tc.lo[d] = lo;
+      tc.n[d] = hi - lo + 1;
+    }
+  }
+  return tc;
+}
+
+// Calls f(q) for every charged bead q in the tile's columns (every thread of
+// the block must call this; f runs on the thread that owns q).
+template <typename F>
+__device__ inline void for_tile_beads(const RepDesc& R, const TileCols& tc, const int* __restrict__ qstart, int* s_cs,
+                                      int* s_cp, int* s_tot, int* scan_sh, F&& f) {
+  const int ncol = tc.n[0] * tc.n[1];
+  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
+  for (int cb = 0; cb < ncol; cb += blockDim.x) {
+    const int c = cb + threadIdx.x;
+    int st = 0, n = 0;
+    if (c < ncol) {
+      int cx = tc.lo[0] + c / tc.n[1], cy = tc.lo[1] + c % tc.n[1];
+      cx -= cx >= nx ? nx : 0;
+      cy -= cy >= ny ? ny : 0;
+      const int base = R.cell_off + (cx * ny + cy) * nz;
+      st = qstart[base];
+      n = qstart[base + nz] - st;
+    }
+    const int inc = block_scan_incl(n, scan_sh);
+    s_cs[threadIdx.x] = st;
+    s_cp[threadIdx.x] = inc - n;
+    if (threadIdx.x == blockDim.x - 1) *s_tot = inc;
+    __syncthreads();
+    const int tot = *s_tot;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+      // the last column whose prefix is <= e holds candidate e
+      int lo = 0, hi = (int)blockDim.x - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_cp[mid] <= e)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      f(s_cs[lo] + (e - s_cp[lo]));
+    }
+    __syncthreads();
+  }
+}
+
+// Offset of a stencil base point from the tile origin (mod K); the bead
+// meets the tile iff it is at most n + P - 2.
+__device__ inline int tile_off(int k0, int t0, int K) {
+  int o = k0 - t0;
+  return o < 0 ? o + K : o;
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_cs[FFT_THREADS], s_cp[FFT_THREADS], s_tot, scan_sh[FFT_THREADS / 64];
+  const MeshTile mt = a.tiles[blockIdx.x];
+  const RepDesc& R = a.rep[mt.rep];
+  const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h;
+  const int TY = a.ty, NL = a.tx * a.ty, LBP = NL + 1;
+  const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
-  const cplx<T>* in = reinterpret_cast<const cplx<T>*>(a.Qc) + R.cgrid_off + (long long)it.first * K2h;
-  for (int e = threadIdx.x; e < nl * K2h; e += blockDim.x) {
-    int l = e / K2h, m = e % K2h;
-    cplx<T> v = in[(long long)l * K2h + m];
-    A[m * LBP + l] = v;
-    // Hermitian partner of a real field
-    int mc = K - m;
-    if (m > 0 && mc > m && mc < K) A[mc * LBP + l] = {v.x, -v.y};
+  // integer accumulators of the tile, line l = lx * TY + ly, point l * K2 + z
+  // (they live in B, which the transform first writes after they are read)
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(B);
+  for (int e = threadIdx.x; e < NL * K2; e += blockDim.x) acc[e] = 0ull;
+  __syncthreads();
+  const TileCols tc = tile_columns(R, mt, P);
+  const double qs = a.qscale;
+  for_tile_beads(R, tc, a.qstart, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
+    const uint4 rec = a.qpk[q];
+    int k0[3];
+    T t[3];
+    mesh_coord<T>(rec.x, K0, k0[0], t[0]);
+    mesh_coord<T>(rec.y, K1, k0[1], t[1]);
+    mesh_coord<T>(rec.z, K2, k0[2], t[2]);
+    const int ox = tile_off(k0[0], mt.x0, K0), oy = tile_off(k0[1], mt.y0, K1);
+    if (ox > nxt + P - 2 || oy > nyt + P - 2) return;
+    T w[3][P], dw[P];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) bspline<T, P>(t[d], w[d], dw);
+    const T z = (T)param_z(rec.w);
+    int g2s[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int g = k0[2] - j;
+      g2s[j] = g < 0 ? g + K2 : g;
+    }
+    for (int jx = 0; jx < P; ++jx) {
+      int lx = ox - jx;
+      lx += lx < 0 ? K0 : 0;
+      if (lx >= nxt) continue;
+      const T ax = z * w[0][jx];
+      for (int jy = 0; jy < P; ++jy) {
+        int ly = oy - jy;
+        ly += ly < 0 ? K1 : 0;
+        if (ly >= nyt) continue;
+        const T axy = ax * w[1][jy];
+        unsigned long long* row = acc + (size_t)(lx * TY + ly) * K2;
+#pragma unroll
+        for (int jz = 0; jz < P; ++jz) {
+          const double v = (double)(axy * w[2][jz]) * qs;
+          atomicAdd(&row[g2s[jz]], (unsigned long long)(long long)llrint(v));
+        }
+      }
+    }
+  });
+  // integer mesh -> complex lines (k, l) at A[k * LBP + l]
+  const double inv_qs = 1.0 / qs;
+  for (int e = threadIdx.x; e < NL * K2; e += blockDim.x) {
+    const int l = e / K2, k = e % K2;
+    A[k * LBP + l] = {(T)((double)(long long)acc[e] * inv_qs), (T)0};
   }
   __syncthreads();
   const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[2];
-  cplx<T>* res = fft_lines<T>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[2], R.nrad[2], true);
-  T* phi = reinterpret_cast<T*>(a.phi) + R.grid_off + (long long)it.first * K;
-  for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
-    int l = e / K, k = e % K;
-    phi[(long long)l * K + k] = res[k * LBP + l].x;
+  cplx<T>* res = fft_lines<T>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], false);
+  cplx<T>* out = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off;
+  for (int e = threadIdx.x; e < NL * K2h; e += blockDim.x) {
+    const int l = e / K2h, m = e % K2h;
+    const int lx = l / TY, ly = l % TY;
+    if (lx < nxt && ly < nyt)
+      out[((long long)(mt.x0 + lx) * K1 + (mt.y0 + ly)) * K2h + m] = res[m * LBP + l];
   }
 }
 
-// Eight lanes per charged bead (x-slab j0 per lane), partial gradients
-// combined with xor shuffles in a fixed order.
 template <typename T, int P>
-__global__ __launch_bounds__(256) void k_gather(PmeLaunch a, int nq) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q0 = t >> 3, j0 = t & 7;
-  const bool active = q0 < nq && j0 < P;
-  const int q = q0 < nq ? q0 : nq - 1;
-  uint32_t prm = a.qparam[q];
-  const RepDesc& R = a.rep[param_rep(prm)];
-  T w[3][P], dw[3][P];
-  int k0[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T t;
-    mesh_coord<T>(a.qpos[d][q], R.K[d], k0[d], t);
-    bspline<T, P>(t, w[d], dw[d]);
+__global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_cs[FFT_THREADS], s_cp[FFT_THREADS], s_tot, scan_sh[FFT_THREADS / 64];
+  const MeshTile mt = a.tiles[blockIdx.x];
+  const RepDesc& R = a.rep[mt.rep];
+  const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h;
+  const int TY = a.ty, NL = a.tx * a.ty, LBP = NL + 1;
+  const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
+  const cplx<T>* in = reinterpret_cast<const cplx<T>*>(a.Qc) + R.cgrid_off;
+  for (int e = threadIdx.x; e < NL * K2h; e += blockDim.x) {
+    const int l = e / K2h, m = e % K2h;
+    const int lx = l / TY, ly = l % TY;
+    cplx<T> v = {(T)0, (T)0};
+    if (lx < nxt && ly < nyt) v = in[((long long)(mt.x0 + lx) * K1 + (mt.y0 + ly)) * K2h + m];
+    A[m * LBP + l] = v;
+    // Hermitian partner of a real field
+    const int mc = K2 - m;
+    if (m > 0 && mc > m && mc < K2) A[mc * LBP + l] = {v.x, -v.y};
   }
-  const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2];
-  const T* phi = reinterpret_cast<const T*>(a.phi) + R.grid_off;
-  int g2s[P];
+  __syncthreads();
+  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[2];
+  const cplx<T>* phi = fft_lines<T>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], true);
+  const TileCols tc = tile_columns(R, mt, P);
+  const double fx = -R.lB * K0 / R.L[0], fy = -R.lB * K1 / R.L[1], fz = -R.lB * K2 / R.L[2];
+  for_tile_beads(R, tc, a.qstart, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
+    const uint4 rec = a.qpk[q];
+    int k0[3];
+    T t[3];
+    mesh_coord<T>(rec.x, K0, k0[0], t[0]);
+    mesh_coord<T>(rec.y, K1, k0[1], t[1]);
+    mesh_coord<T>(rec.z, K2, k0[2], t[2]);
+    const int ox = tile_off(k0[0], mt.x0, K0), oy = tile_off(k0[1], mt.y0, K1);
+    if (ox > nxt + P - 2 || oy > nyt + P - 2) return;
+    T w[3][P], dw[3][P];
 #pragma unroll
-  for (int j = 0; j < P; ++j) {
-    int g = k0[2] - j;
-    g2s[j] = g < 0 ? g + K2 : g;
-  }
-  T gx = 0, gy = 0, gz = 0;
-  if (active) {
-    int g0 = k0[0] - j0;
-    g0 += g0 < 0 ? K0 : 0;
-    for (int j1 = 0; j1 < P; ++j1) {
-      int g1 = k0[1] - j1;
-      g1 += g1 < 0 ? K1 : 0;
-      const T* row = phi + ((long long)g0 * K1 + g1) * K2;
-      T s0 = 0, s2 = 0;
+    for (int d = 0; d < 3; ++d) bspline<T, P>(t[d], w[d], dw[d]);
+    int g2s[P];
 #pragma unroll
-      for (int j2 = 0; j2 < P; ++j2) {
-        T ph = row[g2s[j2]];
-        s0 += w[2][j2] * ph;
-        s2 += dw[2][j2] * ph;
-      }
-      gx += dw[0][j0] * w[1][j1] * s0;
-      gy += w[0][j0] * dw[1][j1] * s0;
-      gz += w[0][j0] * w[1][j1] * s2;
+    for (int j = 0; j < P; ++j) {
+      const int g = k0[2] - j;
+      g2s[j] = g < 0 ? g + K2 : g;
     }
-  }
+    T gx = 0, gy = 0, gz = 0;
+    for (int jx = 0; jx < P; ++jx) {
+      int lx = ox - jx;
+      lx += lx < 0 ? K0 : 0;
+      if (lx >= nxt) continue;
+      for (int jy = 0; jy < P; ++jy) {
+        int ly = oy - jy;
+        ly += ly < 0 ? K1 : 0;
+        if (ly >= nyt) continue;
+        const int l = lx * TY + ly;
+        T s0 = 0, s2 = 0;
 #pragma unroll
-  for (int o = 4; o > 0; o >>= 1) {
-    gx += __shfl_xor(gx, o, 64);
-    gy += __shfl_xor(gy, o, 64);
-    gz += __shfl_xor(gz, o, 64);
-  }
-  if (q0 >= nq || j0 != 0) return;
-  const double c = -R.lB * (double)param_z(prm);
-  const int bi = a.qidx[q];
-  double f[3] = {c * (double)gx * K0 / R.L[0], c * (double)gy * K1 / R.L[1], c * (double)gz * K2 / R.L[2]};
+        for (int jz = 0; jz < P; ++jz) {
+          const T ph = phi[g2s[jz] * LBP + l].x;
+          s0 += w[2][jz] * ph;
+          s2 += dw[2][jz] * ph;
+        }
+        gx += dw[0][jx] * w[1][jy] * s0;
+        gy += w[0][jx] * dw[1][jy] * s0;
+        gz += w[0][jx] * w[1][jy] * s2;
+      }
+    }
+    const double z = (double)param_z(rec.w);
+    const double f[3] = {z * fx * (double)gx, z * fy * (double)gy, z * fz * (double)gz};
+    const int bi = a.qidx[q];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double v = f[d] * a.fscale;
-    long long iv = 0;
-    if (fabs(v) < 4.0e18)
-      iv = (long long)llrint(v);
-    else
-      atomicOr(a.status, (unsigned)STATUS_FORCE_OVERFLOW);
-    atomicAdd((unsigned long long*)&a.F[d][bi], (unsigned long long)iv);
+    for (int d = 0; d < 3; ++d) {
+      const double v = f[d] * a.fscale;
+      long long iv = 0;
+      if (fabs(v) < 4.0e18)
+        iv = (long long)llrint(v);
+      else
+        atomicOr(a.status, (unsigned)STATUS_FORCE_OVERFLOW);
+      atomicAdd((unsigned long long*)&a.F[d][bi], (unsigned long long)iv);
+    }
+  });
+}
+
+template <typename T>
+void spread_z_p(hipStream_t s, const PmeLaunch& a, size_t sh) {
+  dim3 g(a.ntiles), b(FFT_THREADS);
+  switch (a.order) {
+    case 3: hipLaunchKernelGGL((k_spread_z<T, 3>), g, b, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((k_spread_z<T, 4>), g, b, sh, s, a); break;
+    case 5: hipLaunchKernelGGL((k_spread_z<T, 5>), g, b, sh, s, a); break;
+    case 6: hipLaunchKernelGGL((k_spread_z<T, 6>), g, b, sh, s, a); break;
+    case 7: hipLaunchKernelGGL((k_spread_z<T, 7>), g, b, sh, s, a); break;
+    default: hipLaunchKernelGGL((k_spread_z<T, 8>), g, b, sh, s, a); break;
   }
 }
 
 template <typename T>
-void spread_p(hipStream_t s, const PmeLaunch& a, int p, int nq) {
-  dim3 g((8 * nq + 255) / 256), b(256);
-  switch (p) {
-    case 3: hipLaunchKernelGGL((k_spread<T, 3>), g, b, 0, s, a, nq); break;
-    case 4: hipLaunchKernelGGL((k_spread<T, 4>), g, b, 0, s, a, nq); break;
-    case 5: hipLaunchKernelGGL((k_spread<T, 5>), g, b, 0, s, a, nq); break;
-    case 6: hipLaunchKernelGGL((k_spread<T, 6>), g, b, 0, s, a, nq); break;
-    case 7: hipLaunchKernelGGL((k_spread<T, 7>), g, b, 0, s, a, nq); break;
-    default: hipLaunchKernelGGL((k_spread<T, 8>), g, b, 0, s, a, nq); break;
+void z_gather_p(hipStream_t s, const PmeLaunch& a, size_t sh) {
+  dim3 g(a.ntiles), b(FFT_THREADS);
+  switch (a.order) {
+    case 3: hipLaunchKernelGGL((k_z_gather<T, 3>), g, b, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((k_z_gather<T, 4>), g, b, sh, s, a); break;
+    case 5: hipLaunchKernelGGL((k_z_gather<T, 5>), g, b, sh, s, a); break;
+    case 6: hipLaunchKernelGGL((k_z_gather<T, 6>), g, b, sh, s, a); break;
+    case 7: hipLaunchKernelGGL((k_z_gather<T, 7>), g, b, sh, s, a); break;
+    default: hipLaunchKernelGGL((k_z_gather<T, 8>), g, b, sh, s, a); break;
   }
 }
 
-template <typename T>
-void gather_p(hipStream_t s, const PmeLaunch& a, int p, int nq) {
-  dim3 g((8 * nq + 255) / 256), b(256);
-  switch (p) {
-    case 3: hipLaunchKernelGGL((k_gather<T, 3>), g, b, 0, s, a, nq); break;
-    case 4: hipLaunchKernelGGL((k_gather<T, 4>), g, b, 0, s, a, nq); break;
-    case 5: hipLaunchKernelGGL((k_gather<T, 5>), g, b, 0, s, a, nq); break;
-    case 6: hipLaunchKernelGGL((k_gather<T, 6>), g, b, 0, s, a, nq); break;
-    case 7: hipLaunchKernelGGL((k_gather<T, 7>), g, b, 0, s, a, nq); break;
-    default: hipLaunchKernelGGL((k_gather<T, 8>), g, b, 0, s, a, nq); break;
-  }
+// Workgroups may use more than 64 KiB of dynamic LDS: raise a kernel's
+// limit to what it is launched with.
+void allow_lds(const void* fn, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 inline size_t lds_bytes(const PmeLaunch& a, int pass, bool fp64) {
@@ -429,31 +522,46 @@ inline size_t lds_bytes(const PmeLaunch& a, int pass, bool fp64) {
 
 }  // namespace
 
-void launch_spread(hipStream_t s, const PmeLaunch& a, bool fp64) {
-  int nq = a.nq, p = a.order;
-  if (nq <= 0) return;
-  if (fp64)
-    spread_p<double>(s, a, p, nq);
-  else
-    spread_p<float>(s, a, p, nq);
+size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64) {
+  return 2 * (size_t)maxK2 * (size_t)(tx * ty + 1) * (fp64 ? 16 : 8);
 }
 
-void launch_gather(hipStream_t s, const PmeLaunch& a, bool fp64) {
-  int nq = a.nq, p = a.order;
-  if (nq <= 0) return;
-  if (fp64)
-    gather_p<double>(s, a, p, nq);
-  else
-    gather_p<float>(s, a, p, nq);
+void launch_spread_z(hipStream_t s, const PmeLaunch& a, bool fp64) {
+  if (a.ntiles <= 0) return;
+  const size_t sh = pme_tile_lds_bytes(a.maxK[0], a.tx, a.ty, fp64);
+  const int o = std::min(std::max(a.order, 3), 8) - 3;
+  if (fp64) {
+    static const void* fns[6] = {(const void*)k_spread_z<double, 3>, (const void*)k_spread_z<double, 4>,
+                                 (const void*)k_spread_z<double, 5>, (const void*)k_spread_z<double, 6>,
+                                 (const void*)k_spread_z<double, 7>, (const void*)k_spread_z<double, 8>};
+    allow_lds(fns[o], sh);
+    spread_z_p<double>(s, a, sh);
+  } else {
+    static const void* fns[6] = {(const void*)k_spread_z<float, 3>, (const void*)k_spread_z<float, 4>,
+                                 (const void*)k_spread_z<float, 5>, (const void*)k_spread_z<float, 6>,
+                                 (const void*)k_spread_z<float, 7>, (const void*)k_spread_z<float, 8>};
+    allow_lds(fns[o], sh);
+    spread_z_p<float>(s, a, sh);
+  }
 }
 
-void launch_fft_z_r2c(hipStream_t s, const PmeLaunch& a, bool fp64) {
-  if (a.nitems[0] <= 0) return;
-  size_t sh = lds_bytes(a, 0, fp64);
-  if (fp64)
-    hipLaunchKernelGGL(k_fft_z_r2c<double>, dim3(a.nitems[0]), dim3(FFT_THREADS), sh, s, a);
-  else
-    hipLaunchKernelGGL(k_fft_z_r2c<float>, dim3(a.nitems[0]), dim3(FFT_THREADS), sh, s, a);
+void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64) {
+  if (a.ntiles <= 0) return;
+  const size_t sh = pme_tile_lds_bytes(a.maxK[0], a.tx, a.ty, fp64);
+  const int o = std::min(std::max(a.order, 3), 8) - 3;
+  if (fp64) {
+    static const void* fns[6] = {(const void*)k_z_gather<double, 3>, (const void*)k_z_gather<double, 4>,
+                                 (const void*)k_z_gather<double, 5>, (const void*)k_z_gather<double, 6>,
+                                 (const void*)k_z_gather<double, 7>, (const void*)k_z_gather<double, 8>};
+    allow_lds(fns[o], sh);
+    z_gather_p<double>(s, a, sh);
+  } else {
+    static const void* fns[6] = {(const void*)k_z_gather<float, 3>, (const void*)k_z_gather<float, 4>,
+                                 (const void*)k_z_gather<float, 5>, (const void*)k_z_gather<float, 6>,
+                                 (const void*)k_z_gather<float, 7>, (const void*)k_z_gather<float, 8>};
+    allow_lds(fns[o], sh);
+    z_gather_p<float>(s, a, sh);
+  }
 }
 
 void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse) {
@@ -480,15 +588,6 @@ void launch_fft_x_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev) {
     else
       hipLaunchKernelGGL((k_fft_x_conv<float, false>), g, b, sh, s, a);
   }
-}
-
-void launch_fft_z_c2r(hipStream_t s, const PmeLaunch& a, bool fp64) {
-  if (a.nitems[0] <= 0) return;
-  size_t sh = lds_bytes(a, 0, fp64);
-  if (fp64)
-    hipLaunchKernelGGL(k_fft_z_c2r<double>, dim3(a.nitems[0]), dim3(FFT_THREADS), sh, s, a);
-  else
-    hipLaunchKernelGGL(k_fft_z_c2r<float>, dim3(a.nitems[0]), dim3(FFT_THREADS), sh, s, a);
 }
 
 }  // namespace gcme
