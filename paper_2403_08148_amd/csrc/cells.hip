@@ -80,10 +80,11 @@ __device__ inline int block_inclusive_scan(int v, int* sh) {
   return v + add;
 }
 
-// Whole scan in one block for grids of up to SINGLE_SCAN_MAX cells: each
-// thread sums a contiguous chunk, one block scan, then each thread writes its
-// chunk.  Produces start (exclusive), the scatter cursor fill = start, and
-// the same for the charged counts.
+// Whole scan in one block per array (block 0: all beads, block 1: charged
+// beads) for grids of up to SINGLE_SCAN_MAX cells: each thread sums a
+// contiguous chunk, one block scan, then each thread writes its chunk.
+// Produces start (exclusive) and, for all beads, the scatter cursor
+// fill = start.
 constexpr int SINGLE_SCAN_THREADS = 1024;
 constexpr int SINGLE_SCAN_MAX = 15872;
 
@@ -95,28 +96,26 @@ __global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c)
   const int n = c.ncells;
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per, hi = min(lo + per, n);
-  for (int arr = 0; arr < 2; ++arr) {
-    const int* cnt = arr == 0 ? c.counts : c.qcounts;
-    int* st = arr == 0 ? c.start : c.qstart;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = cnt[i];
-    __syncthreads();
-    int s = 0;
-    for (int i = lo; i < hi; ++i) s += buf[i];
-    int inc = block_inclusive_scan(s, sh);
-    int run = inc - s;
-    for (int i = lo; i < hi; ++i) {
-      int v = buf[i];
-      buf[i] = run;
-      run += v;
-    }
-    if (threadIdx.x == blockDim.x - 1) st[n] = inc;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int v = buf[i];
-      st[i] = v;
-      if (arr == 0) c.fill[i] = v;
-    }
-    __syncthreads();
+  const int arr = blockIdx.x;
+  const int* cnt = arr == 0 ? c.counts : c.qcounts;
+  int* st = arr == 0 ? c.start : c.qstart;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = cnt[i];
+  __syncthreads();
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += buf[i];
+  int inc = block_inclusive_scan(s, sh);
+  int run = inc - s;
+  for (int i = lo; i < hi; ++i) {
+    int v = buf[i];
+    buf[i] = run;
+    run += v;
+  }
+  if (threadIdx.x == blockDim.x - 1) st[n] = inc;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int v = buf[i];
+    st[i] = v;
+    if (arr == 0) c.fill[i] = v;
   }
 }
 
@@ -289,7 +288,7 @@ void launch_bin(hipStream_t s, StateView A, const RepDesc* rep, CellView c, int 
 
 void launch_scan(hipStream_t s, CellView c) {
   if (c.ncells <= SINGLE_SCAN_MAX) {
-    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SINGLE_SCAN_THREADS), 0, s, c);
+    hipLaunchKernelGGL(k_scan_single, dim3(2), dim3(SINGLE_SCAN_THREADS), 0, s, c);
     return;
   }
   int nb = nblk(c.ncells, SCAN_BLOCK);

@@ -136,6 +136,8 @@ struct gcme_ctx {
   int ncl_g = 0, ncl_q = 0, ntiles_g = 0, ntiles_q = 0, ntiles_256 = 0;
   int cap_g = 64, cap_q = 64;
   int nmtiles = 0, mtx = 4, mty = 4;
+  bool yx_fused = false;  // y and x passes in one LDS plane kernel
+  int plane_elems = 0;
   int lds_max = 65536;  // dynamic LDS a workgroup may use
   int nitems[3] = {0, 0, 0};
   int lb[3] = {0, 0, 0};
@@ -344,11 +346,14 @@ void build_mesh_tables(gcme_handle h, std::vector<T>& tw, std::vector<T>& bsp, s
       }
       for (int m = 0; m < K; ++m)
         if (mod[m] < 1e-7) mod[m] = 0.5 * (mod[(m - 1 + K) % K] + mod[(m + 1) % K]);
+      // Green's function factor of the axis: the Gaussian of eq. ewald's
+      // reciprocal sum factorises over the axes
       d.bsp_off[ax] = (int)bsp.size();
       for (int m = 0; m < K; ++m) {
-        bsp.push_back((T)(1.0 / mod[m]));
         int ms = m <= K / 2 ? m : m - K;
-        frq.push_back((T)((double)ms / p.box[ax]));
+        const double f = (double)ms / p.box[ax];
+        bsp.push_back((T)(std::exp(-M_PI * M_PI * f * f / (p.beta * p.beta)) / mod[m]));
+        frq.push_back((T)f);
       }
     }
   }
@@ -519,6 +524,17 @@ gcme_status build_plan(gcme_handle h) {
         items[2].push_back(LineItem{r, y * d.K2h + kz, std::min(b2, d.K2h - kz), 0});
   }
   item_off[R] = (int)items[2].size();
+  // one kz plane per work item when a K0 x K1 plane fits twice in LDS
+  h->plane_elems = 0;
+  for (int r = 0; r < R; ++r) h->plane_elems = std::max(h->plane_elems, (h->rep[r].K[0] + 1) * (h->rep[r].K[1] + 1));
+  h->yx_fused = pme_plane_lds_bytes(h->plane_elems, h->maxK[2], h->maxK[1], h->maxK[0], h->fp64) <= (size_t)h->lds_max;
+  if (h->yx_fused) {
+    for (int r = 0; r < R; ++r) {
+      item_off[r] = (int)items[0].size();
+      for (int kz = 0; kz < h->rep[r].K2h; ++kz) items[0].push_back(LineItem{r, kz, 1, 0});
+    }
+    item_off[R] = (int)items[0].size();
+  }
   // mesh tiles of the fused spread / gather passes: 4 x 4 z lines, fewer if
   // the two LDS line buffers would not fit
   h->mtx = 4;
@@ -574,7 +590,7 @@ gcme_status build_plan(gcme_handle h) {
   upload(toff_q, h->d_adj_off[1], s);
   HIPCHK(h, h->part[SLOT_GCM].alloc((size_t)std::max(1, h->ntiles_g) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_REAL].alloc((size_t)std::max(1, h->ntiles_q) * PART_W * 8));
-  HIPCHK(h, h->part[SLOT_RECIP].alloc((size_t)std::max(1, h->nitems[2]) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_RECIP].alloc((size_t)std::max(1, std::max(h->nitems[0], h->nitems[2])) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_KIN].alloc((size_t)std::max(1, h->ntiles_256) * PART_W * 8));
   HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->ntiles_g) * (MAXT * MAXT + 2 * MAXT) * 8));
   HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->ntiles_q) * (MAXT * MAXT + 2 * MAXT) * 8));
@@ -695,6 +711,7 @@ PmeLaunch pme_args(gcme_handle h) {
   a.tx = h->mtx;
   a.ty = h->mty;
   a.Qc = h->Qc.p;
+  a.plane_elems = h->plane_elems;
   a.tw = h->d_tw.p;
   a.radix = h->d_rad.as<int>();
   a.bsp = h->d_bsp.p;
@@ -751,9 +768,13 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
   PmeLaunch p = pme_args(h);
   launch_spread_z(h->aux[1], p, h->fp64);
-  launch_fft_y(h->aux[1], p, h->fp64, false);
-  launch_fft_x_conv(h->aux[1], p, h->fp64, ev);
-  launch_fft_y(h->aux[1], p, h->fp64, true);
+  if (h->yx_fused) {
+    launch_fft_yx_conv(h->aux[1], p, h->fp64, ev);
+  } else {
+    launch_fft_y(h->aux[1], p, h->fp64, false);
+    launch_fft_x_conv(h->aux[1], p, h->fp64, ev);
+    launch_fft_y(h->aux[1], p, h->fp64, true);
+  }
   launch_z_gather(h->aux[1], p, h->fp64);
   PairLaunch q = pair_args(h, true);
   launch_nl_build(h->aux[0], q);
@@ -1287,7 +1308,7 @@ gcme_status gcme_autotune(gcme_handle h) {
 
 static const char* kStageNames[GCME_N_STAGES] = {"int_first", "sort",       "list_gcm",  "pair_gcm",
                                                   "list_elec", "pair_elec",  "spread_z",  "fft_y",
-                                                  "fft_x_conv", "fft_y_inv", "z_gather",  "int_last"};
+                                                  "fft_conv",  "fft_y_inv",  "z_gather",  "int_last"};
 
 const char* gcme_stage_name(int32_t i) { return (i >= 0 && i < GCME_N_STAGES) ? kStageNames[i] : nullptr; }
 
@@ -1325,9 +1346,18 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
       case 4: launch_nl_build(st2, q); break;
       case 5: launch_pair_elec(st2, q, h->fp64, false, false); break;
       case 6: launch_spread_z(st2, p, h->fp64); break;
-      case 7: launch_fft_y(st2, p, h->fp64, false); break;
-      case 8: launch_fft_x_conv(st2, p, h->fp64, false); break;
-      case 9: launch_fft_y(st2, p, h->fp64, true); break;
+      case 7:
+        if (!h->yx_fused) launch_fft_y(st2, p, h->fp64, false);
+        break;
+      case 8:
+        if (h->yx_fused)
+          launch_fft_yx_conv(st2, p, h->fp64, false);
+        else
+          launch_fft_x_conv(st2, p, h->fp64, false);
+        break;
+      case 9:
+        if (!h->yx_fused) launch_fft_y(st2, p, h->fp64, true);
+        break;
       case 10: launch_z_gather(st2, p, h->fp64); break;
       default: launch_int_last(st2, ia, viewB(h), viewA(h), F3, false); break;
     }
@@ -1338,6 +1368,7 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
   for (int i = 0; i < GCME_N_STAGES; ++i) {
     ms[i] = 0.0;
     if (h->NQ == 0 && i >= 4 && i <= 10) continue;
+    if (h->yx_fused && (i == 7 || i == 9)) continue;
     hipGraph_t gr = nullptr;
     hipGraphExec_t ex = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -11,6 +11,7 @@ constexpr int MAXT = 4;           // bead types per replica
 constexpr int NSER = 14;          // small-r series terms stored per type pair
 constexpr int TILE = 256;         // beads per tile of the per-bead kernels
 constexpr int FFT_THREADS = 256;  // threads of a mesh-line work item
+constexpr int YX_THREADS = 1024;  // threads of a fused y/x plane work item
 
 // Fixed-point scales (log2) of the force and charge-mesh accumulators.
 constexpr int FSHIFT_MIXED = 32;
@@ -40,7 +41,7 @@ struct RepDesc {
   int order;
   int nt;
   int tw_off[3];      // twiddle table offset for the length of each axis
-  int bsp_off[3];     // offsets of 1/|b(m)|^2 and m/L tables per axis
+  int bsp_off[3];     // offsets of the Green factor and m/L tables per axis
   int rad_off[3];     // offset of the radix list of each axis length
   int nrad[3];
 };
@@ -204,9 +205,10 @@ struct PmeLaunch {
   void* Qc;           // complex<T> half-complex mesh
   const void* tw;     // complex<T> twiddles
   const int* radix;
-  const void* bsp;    // T: 1/|b|^2 per axis entry
+  const void* bsp;    // T: exp(-pi^2 (m/L)^2/beta^2) / |b(m)|^2 per axis entry
   const void* freq;   // T: signed m / L per axis entry
-  const LineItem* items[3];  // (unused), Y, X passes
+  const LineItem* items[3];  // fused y/x planes (rep, kz), Y lines, X lines
+  int plane_elems;    // complex entries of one LDS plane buffer (fused y/x pass)
   int nitems[3];
   int lb[3];          // lines per item for each pass
   int maxK[3];        // longest z, y, x line
@@ -219,6 +221,8 @@ struct PmeLaunch {
 void launch_spread_z(hipStream_t s, const PmeLaunch& a, bool fp64);
 void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse);
 void launch_fft_x_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev);
+void launch_fft_yx_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev);
+size_t pme_plane_lds_bytes(int plane_elems, int maxK0, int maxK1, int maxK2, bool fp64);
 void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64);
 size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64);
 

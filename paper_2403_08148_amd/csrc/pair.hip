@@ -261,18 +261,15 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
         sn += f;
       }
       __builtin_amdgcn_wave_barrier();
-      for (int p = 0; p < total; p += 64) {
-        const int q = p + lane;
-        const bool v = q < total;
-        const int j = v ? s_cand[wave][q] : first;
-        const uint4 pj = pk[j];
-        const uint32_t jx = pj.x, jy = pj.y, jz = pj.z;
+      // test one candidate per lane against every cluster bead; hits are
+      // appended in candidate order
+      auto test = [&](const uint4 pj, bool v, int j) {
         bool hit = false;
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
-          const float dx = (float)(int)(cxs[i] - jx) * sx;
-          const float dy = (float)(int)(cys[i] - jy) * sy;
-          const float dz = (float)(int)(czs[i] - jz) * sz;
+          const float dx = (float)(int)(cxs[i] - pj.x) * sx;
+          const float dy = (float)(int)(cys[i] - pj.y) * sy;
+          const float dz = (float)(int)(czs[i] - pj.z) * sz;
           hit |= dx * dx + dy * dy + dz * dz < rcl2f;
         }
         hit = hit && v;
@@ -282,6 +279,17 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
           if (idx < a.cap) out[idx] = (uint32_t)j;
         }
         nent += __popcll(m);
+      };
+      // two chunks per round, their loads issued together
+      for (int p = 0; p < total; p += 128) {
+        const int q0 = p + lane, q1 = p + 64 + lane;
+        const bool v0 = q0 < total, v1 = q1 < total;
+        const int j0 = v0 ? s_cand[wave][q0] : first;
+        const int j1 = v1 ? s_cand[wave][q1] : first;
+        const uint4 p0 = pk[j0];
+        const uint4 p1 = pk[j1];
+        test(p0, v0, j0);
+        if (p + 64 < total) test(p1, v1, j1);
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -447,15 +455,30 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
     const int cnt = a.count[c];
     const uint32_t* __restrict__ lst = a.list + (size_t)c * a.cap;
     const uint4* __restrict__ pk = a.pk;
-    for (int e = jl; e < cnt; e += CJ) {
-      const int j = (int)lst[e];
-      const uint4 pj = pk[j];
-      const T dx = (T)(int)(mi.x - pj.x) * sx;
-      const T dy = (T)(int)(mi.y - pj.y) * sy;
-      const T dz = (T)(int)(mi.z - pj.z) * sz;
-      const T r2 = dx * dx + dy * dy + dz * dz;
-      if (vi && r2 < rc2 && j != i)
-        interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pj.w, grow, erow, arow, zi, beta, beta2, lB);
+    // NU entries per lane per round: the list loads, then the dependent
+    // bead-record loads, are issued back to back so one memory latency
+    // covers NU pairs
+    constexpr int NU = 4;
+    for (int e0 = jl; e0 < cnt; e0 += NU * CJ) {
+      int jj[NU];
+      uint4 pp[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int e = e0 + u * CJ;
+        jj[u] = e < cnt ? (int)lst[e] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < NU; ++u) pp[u] = pk[jj[u] < 0 ? i : jj[u]];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const uint4 pj = pp[u];
+        const T dx = (T)(int)(mi.x - pj.x) * sx;
+        const T dy = (T)(int)(mi.y - pj.y) * sy;
+        const T dz = (T)(int)(mi.z - pj.z) * sz;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (vi && jj[u] >= 0 && r2 < rc2 && jj[u] != i)
+          interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pj.w, grow, erow, arow, zi, beta, beta2, lB);
+      }
     }
     if (ADJ && vi) flush_adj<T, ELEC>(L, ti);
     T fx = L.fx, fy = L.fy, fz = L.fz;

@@ -72,59 +72,93 @@ __device__ inline void mesh_coord(uint32_t u, int K, int& k, T& t) {
   t = (T)((double)(uint32_t)(p & 0xffffffffu) * 2.3283064365386963e-10);
 }
 
+// Quotient of n / d for 0 <= n < 2^22, d >= 1: float reciprocal estimate
+// (off by at most one in that range) and one exact integer correction --
+// a handful of instructions instead of a full integer division.
+struct FDiv {
+  int d;
+  float r;
+  __device__ explicit FDiv(int dd) : d(dd), r(1.0f / (float)dd) {}
+  __device__ inline int div(int n) const {
+    int q = (int)((float)n * r);
+    const int rem = n - q * d;
+    q += (rem >= d) - (rem < 0);
+    return q;
+  }
+};
+
+// One radix-RR Stockham stage over nl lines of length K held in LDS
+// (element (k, l) at k*LBP + l), A -> B.  The radix is a template parameter
+// so the butterfly operands stay in registers.
+template <typename T, int RR>
+__device__ inline void fft_stage(const cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, int Ns,
+                                 const cplx<T>* __restrict__ tw, bool inverse) {
+  const T sgn = inverse ? (T)1 : (T)-1;
+  const int nb = K / RR;
+  const int tstride = K / (Ns * RR);
+  const FDiv dnl(nl), dns(Ns);
+  for (int b = threadIdx.x; b < nb * nl; b += blockDim.x) {
+    const int j = dnl.div(b);
+    const int l = b - j * nl;
+    const int jn = dns.div(j);
+    const int k = j - jn * Ns;
+    cplx<T> v[RR];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) v[r] = A[(j + r * nb) * LBP + l];
+#pragma unroll
+    for (int r = 1; r < RR; ++r) {
+      cplx<T> w = tw[k * r * tstride];
+      if (inverse) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    cplx<T> o[RR];
+    if constexpr (RR == 2) {
+      o[0] = {v[0].x + v[1].x, v[0].y + v[1].y};
+      o[1] = {v[0].x - v[1].x, v[0].y - v[1].y};
+    } else if constexpr (RR == 4) {
+      // X_q = sum_s v_s exp(sgn 2 pi i s q / 4); exp(sgn pi i/2) = sgn i
+      cplx<T> a0 = {v[0].x + v[2].x, v[0].y + v[2].y};
+      cplx<T> a1 = {v[0].x - v[2].x, v[0].y - v[2].y};
+      cplx<T> b0 = {v[1].x + v[3].x, v[1].y + v[3].y};
+      cplx<T> b1 = {v[1].x - v[3].x, v[1].y - v[3].y};
+      // sgn i * b1
+      cplx<T> ib1 = {-sgn * b1.y, sgn * b1.x};
+      o[0] = {a0.x + b0.x, a0.y + b0.y};
+      o[2] = {a0.x - b0.x, a0.y - b0.y};
+      o[1] = {a1.x + ib1.x, a1.y + ib1.y};
+      o[3] = {a1.x - ib1.x, a1.y - ib1.y};
+    } else {
+      // radix 3: w = exp(sgn 2 pi i / 3) = -1/2 + sgn i sqrt(3)/2
+      const T h = (T)0.86602540378443864676;
+      cplx<T> s = {v[1].x + v[2].x, v[1].y + v[2].y};
+      cplx<T> d = {v[1].x - v[2].x, v[1].y - v[2].y};
+      o[0] = {v[0].x + s.x, v[0].y + s.y};
+      cplx<T> m = {v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y};
+      // sgn i h d
+      cplx<T> id = {-sgn * h * d.y, sgn * h * d.x};
+      o[1] = {m.x + id.x, m.y + id.y};
+      o[2] = {m.x - id.x, m.y - id.y};
+    }
+    const int idxD = jn * Ns * RR + k;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) B[(idxD + r * Ns) * LBP + l] = o[r];
+  }
+}
+
 // In-LDS Stockham FFT of nl lines of length K (element (k, l) at k*LBP + l).
 // Returns the buffer holding the result (A or B).
 template <typename T>
 __device__ cplx<T>* fft_lines(cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, const cplx<T>* __restrict__ tw,
                               const int* __restrict__ rad, int nrad, bool inverse) {
-  const T sgn = inverse ? (T)1 : (T)-1;
   int Ns = 1;
   for (int s = 0; s < nrad; ++s) {
     const int Rr = rad[s];
-    const int nb = K / Rr;
-    const int tstride = K / (Ns * Rr);
-    for (int b = threadIdx.x; b < nb * nl; b += blockDim.x) {
-      const int l = b % nl;
-      const int j = b / nl;
-      const int k = j % Ns;
-      cplx<T> v[4];
-      for (int r = 0; r < Rr; ++r) v[r] = A[(j + r * nb) * LBP + l];
-      for (int r = 1; r < Rr; ++r) {
-        cplx<T> w = tw[k * r * tstride];
-        if (inverse) w.y = -w.y;
-        v[r] = cmul(v[r], w);
-      }
-      cplx<T> o[4];
-      if (Rr == 2) {
-        o[0] = {v[0].x + v[1].x, v[0].y + v[1].y};
-        o[1] = {v[0].x - v[1].x, v[0].y - v[1].y};
-      } else if (Rr == 4) {
-        // X_q = sum_s v_s exp(sgn 2 pi i s q / 4); exp(sgn pi i/2) = sgn i
-        cplx<T> a0 = {v[0].x + v[2].x, v[0].y + v[2].y};
-        cplx<T> a1 = {v[0].x - v[2].x, v[0].y - v[2].y};
-        cplx<T> b0 = {v[1].x + v[3].x, v[1].y + v[3].y};
-        cplx<T> b1 = {v[1].x - v[3].x, v[1].y - v[3].y};
-        // sgn i * b1
-        cplx<T> ib1 = {-sgn * b1.y, sgn * b1.x};
-        o[0] = {a0.x + b0.x, a0.y + b0.y};
-        o[2] = {a0.x - b0.x, a0.y - b0.y};
-        o[1] = {a1.x + ib1.x, a1.y + ib1.y};
-        o[3] = {a1.x - ib1.x, a1.y - ib1.y};
-      } else {
-        // radix 3: w = exp(sgn 2 pi i / 3) = -1/2 + sgn i sqrt(3)/2
-        const T h = (T)0.86602540378443864676;
-        cplx<T> s = {v[1].x + v[2].x, v[1].y + v[2].y};
-        cplx<T> d = {v[1].x - v[2].x, v[1].y - v[2].y};
-        o[0] = {v[0].x + s.x, v[0].y + s.y};
-        cplx<T> m = {v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y};
-        // sgn i h d
-        cplx<T> id = {-sgn * h * d.y, sgn * h * d.x};
-        o[1] = {m.x + id.x, m.y + id.y};
-        o[2] = {m.x - id.x, m.y - id.y};
-      }
-      const int idxD = (j / Ns) * Ns * Rr + k;
-      for (int r = 0; r < Rr; ++r) B[(idxD + r * Ns) * LBP + l] = o[r];
-    }
+    if (Rr == 4)
+      fft_stage<T, 4>(A, B, K, LBP, nl, Ns, tw, inverse);
+    else if (Rr == 2)
+      fft_stage<T, 2>(A, B, K, LBP, nl, Ns, tw, inverse);
+    else
+      fft_stage<T, 3>(A, B, K, LBP, nl, Ns, tw, inverse);
     __syncthreads();
     cplx<T>* t = A;
     A = B;
@@ -132,6 +166,16 @@ __device__ cplx<T>* fft_lines(cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, co
     Ns *= Rr;
   }
   return A;
+}
+
+// Copies the K twiddles of one axis into LDS (whole block; the caller's
+// next __syncthreads publishes them).  The FFT stages then read twiddles at
+// LDS latency instead of waiting on global loads once per stage.
+template <typename T>
+__device__ inline const cplx<T>* stage_twiddles(cplx<T>* dst, const PmeLaunch& a, int off, int K) {
+  const cplx<T>* src = reinterpret_cast<const cplx<T>*>(a.tw) + off;
+  for (int e = threadIdx.x; e < K; e += blockDim.x) dst[e] = src[e];
+  return dst;
 }
 
 template <typename T>
@@ -142,17 +186,18 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse)
   const int K = R.K[1], K2h = R.K2h, nl = it.count, LBP = a.lb[1] + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[1] * LBP;
+  const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[1] * LBP, a, R.tw_off[1], K);
   const int x = it.first / K2h, kz0 = it.first % K2h;
   cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)x * R.K[1] * K2h + kz0;
+  const FDiv dnl(nl);
   for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
-    int k = e / nl, l = e % nl;
+    const int k = dnl.div(e), l = e - k * nl;
     A[k * LBP + l] = base[(long long)k * K2h + l];
   }
   __syncthreads();
-  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[1];
   cplx<T>* res = fft_lines<T>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[1], R.nrad[1], inverse != 0);
   for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
-    int k = e / nl, l = e % nl;
+    const int k = dnl.div(e), l = e - k * nl;
     base[(long long)k * K2h + l] = res[k * LBP + l];
   }
 }
@@ -165,8 +210,48 @@ __device__ inline double block_sum_fft(double v, double* sh) {
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   double t = 0;
-  if (threadIdx.x == 0) t = ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+  if (threadIdx.x == 0) {
+    const int nw = (int)blockDim.x >> 6;
+    for (int w = 0; w < nw; ++w) t += sh[w];
+  }
   return t;
+}
+
+struct RecipSums {
+  double e;
+  double w[6];
+};
+
+// Multiply the transformed charge at mesh frequency (mx, my, mz) (mz of the
+// half-complex axis) by G(m) = B(m) exp(-pi^2 m^2/beta^2) / (pi V m^2) of
+// eq. ewald, and add its energy lB/2 G |Q^|^2 (doubled for the mz lines
+// that stand for their conjugates) and virial to the sums.  The Gaussian
+// factorises over the axes, so gf_a(m) = exp(-pi^2 (m/L_a)^2/beta^2)/|b_a(m)|^2
+// comes from per-axis tables and fr_a(m) = m/L_a is the signed frequency.
+template <typename T, bool EV>
+__device__ inline cplx<T> green_apply(const RepDesc& R, const T* gf0, const T* gf1, const T* gf2, const T* fr0,
+                                      const T* fr1, const T* fr2, int mx, int my, int mz, cplx<T> v, RecipSums& acc) {
+  const T f0 = fr0[mx], f1 = fr1[my], f2 = fr2[mz];
+  const T mm = f0 * f0 + f1 * f1 + f2 * f2;
+  T G = 0;
+  if (mm > (T)0) {
+    G = gf0[mx] * gf1[my] * gf2[mz] / ((T)(3.141592653589793 * R.V) * mm);
+    if (EV) {
+      const double pi2b2 = 9.869604401089358 / (R.beta * R.beta);
+      const double wgt = (mz == 0 || 2 * mz == R.K[2]) ? 1.0 : 2.0;
+      const double em = 0.5 * R.lB * wgt * (double)G * ((double)v.x * v.x + (double)v.y * v.y);
+      const double c = 2.0 * (1.0 + pi2b2 * (double)mm) / (double)mm;
+      const double m0 = f0, m1 = f1, m2 = f2;
+      acc.e += em;
+      acc.w[0] += em * (1.0 - c * m0 * m0);
+      acc.w[1] += em * (1.0 - c * m1 * m1);
+      acc.w[2] += em * (1.0 - c * m2 * m2);
+      acc.w[3] -= em * c * m0 * m1;
+      acc.w[4] -= em * c * m0 * m2;
+      acc.w[5] -= em * c * m1 * m2;
+    }
+  }
+  return {v.x * G, v.y * G};
 }
 
 template <typename T, bool EV>
@@ -175,61 +260,127 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
   __shared__ double sh[4];
   const LineItem it = a.items[2][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
-  const int K = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h, nl = it.count, LBP = a.lb[2] + 1;
+  const int K = R.K[0], K1 = R.K[1], K2h = R.K2h, nl = it.count, LBP = a.lb[2] + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[2] * LBP;
+  const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[2] * LBP, a, R.tw_off[0], K);
   const int y = it.first / K2h, kz0 = it.first % K2h;
   const long long xstride = (long long)K1 * K2h;
   cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)y * K2h + kz0;
+  const FDiv dnl(nl);
   for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
-    int k = e / nl, l = e % nl;
+    const int k = dnl.div(e), l = e - k * nl;
     A[k * LBP + l] = base[(long long)k * xstride + l];
   }
   __syncthreads();
-  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[0];
   cplx<T>* res = fft_lines<T>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], false);
   cplx<T>* other = res == A ? B : A;
   // Green's function, energy and virial
-  const T* bsp = reinterpret_cast<const T*>(a.bsp);
-  const T* frq = reinterpret_cast<const T*>(a.freq);
-  const T b0y = bsp[R.bsp_off[1] + y], f1 = frq[R.bsp_off[1] + y];
-  const double pi2b2 = 9.869604401089358 / (R.beta * R.beta);
-  const double piV = 3.141592653589793 * R.V;
-  double e = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
+  const T* gf = reinterpret_cast<const T*>(a.bsp);
+  const T* fr = reinterpret_cast<const T*>(a.freq);
+  RecipSums acc{};
   for (int q = threadIdx.x; q < nl * K; q += blockDim.x) {
-    int k = q / nl, l = q % nl;
-    int m2 = kz0 + l;
-    T f0 = frq[R.bsp_off[0] + k];
-    T f2 = frq[R.bsp_off[2] + m2];
-    T mm = f0 * f0 + f1 * f1 + f2 * f2;
-    cplx<T> v = res[k * LBP + l];
-    T G = 0;
-    if (mm > (T)0) {
-      G = (T)(exp(-pi2b2 * (double)mm) / (piV * (double)mm)) * bsp[R.bsp_off[0] + k] * b0y * bsp[R.bsp_off[2] + m2];
-      if (EV) {
-        double wgt = (m2 == 0 || 2 * m2 == K2) ? 1.0 : 2.0;
-        double em = 0.5 * R.lB * wgt * (double)G * ((double)v.x * v.x + (double)v.y * v.y);
-        double c = 2.0 * (1.0 + pi2b2 * (double)mm) / (double)mm;
-        double m0 = f0, m1 = f1, m2d = f2;
-        e += em;
-        w0 += em * (1.0 - c * m0 * m0);
-        w1 += em * (1.0 - c * m1 * m1);
-        w2 += em * (1.0 - c * m2d * m2d);
-        w3 -= em * c * m0 * m1;
-        w4 -= em * c * m0 * m2d;
-        w5 -= em * c * m1 * m2d;
-      }
-    }
-    res[k * LBP + l] = {v.x * G, v.y * G};
+    const int k = dnl.div(q), l = q - k * nl;
+    res[k * LBP + l] = green_apply<T, EV>(R, gf + R.bsp_off[0], gf + R.bsp_off[1], gf + R.bsp_off[2], fr + R.bsp_off[0],
+                                          fr + R.bsp_off[1], fr + R.bsp_off[2], k, y, kz0 + l, res[k * LBP + l], acc);
   }
   __syncthreads();
   cplx<T>* fin = fft_lines<T>(res, other, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], true);
   for (int e2 = threadIdx.x; e2 < nl * K; e2 += blockDim.x) {
-    int k = e2 / nl, l = e2 % nl;
+    const int k = dnl.div(e2), l = e2 - k * nl;
     base[(long long)k * xstride + l] = fin[k * LBP + l];
   }
   if (EV) {
-    double v[7] = {e, w0, w1, w2, w3, w4, w5};
+    double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      double t = block_sum_fft(v[k], sh);
+      if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
+    }
+  }
+}
+
+// y transform, x transform, Green's function (energy, virial), inverse x,
+// inverse y of one kz plane of the half-complex mesh, all in LDS (for meshes
+// whose K0 x K1 plane fits twice in a workgroup's LDS).  Layouts: y-major
+// (y, x) at y*LY + x for the y lines, x-major (x, y) at x*LX + y for the x
+// lines; the transposes between them are LDS-to-LDS copies.
+template <typename T, bool EV>
+__global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sh[YX_THREADS / 64];
+  const LineItem it = a.items[0][blockIdx.x];
+  const RepDesc& R = a.rep[it.rep];
+  const int K0 = R.K[0], K1 = R.K[1], K2h = R.K2h;
+  const int kz = it.first;
+  const int LY = K0 + 1, LX = K1 + 1;
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* B = A + (size_t)a.plane_elems;
+  const cplx<T>* twx = stage_twiddles(B + (size_t)a.plane_elems, a, R.tw_off[0], K0);
+  const cplx<T>* twy = stage_twiddles(B + (size_t)a.plane_elems + a.maxK[2], a, R.tw_off[1], K1);
+  // per-axis Green's function factors and frequencies of this replica
+  T* tabs = reinterpret_cast<T*>(B + (size_t)a.plane_elems + a.maxK[2] + a.maxK[1]);
+  T* gf0 = tabs;
+  T* gf1 = gf0 + K0;
+  T* gf2 = gf1 + K1;
+  T* fr0 = gf2 + K2h;
+  T* fr1 = fr0 + K0;
+  T* fr2 = fr1 + K1;
+  {
+    const T* gf = reinterpret_cast<const T*>(a.bsp);
+    const T* fr = reinterpret_cast<const T*>(a.freq);
+    for (int e = threadIdx.x; e < K0; e += blockDim.x) {
+      gf0[e] = gf[R.bsp_off[0] + e];
+      fr0[e] = fr[R.bsp_off[0] + e];
+    }
+    for (int e = threadIdx.x; e < K1; e += blockDim.x) {
+      gf1[e] = gf[R.bsp_off[1] + e];
+      fr1[e] = fr[R.bsp_off[1] + e];
+    }
+    for (int e = threadIdx.x; e < K2h; e += blockDim.x) {
+      gf2[e] = gf[R.bsp_off[2] + e];
+      fr2[e] = fr[R.bsp_off[2] + e];
+    }
+  }
+  cplx<T>* Q = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + kz;
+  const int n = K0 * K1;
+  const FDiv dk0(K0), dk1(K1);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int x = dk1.div(e), y = e - x * K1;
+    A[y * LY + x] = Q[(long long)e * K2h];
+  }
+  __syncthreads();
+  const int* radx = a.radix + R.rad_off[0];
+  const int* rady = a.radix + R.rad_off[1];
+  cplx<T>* r1 = fft_lines<T>(A, B, K1, LY, K0, twy, rady, R.nrad[1], false);
+  cplx<T>* o1 = r1 == A ? B : A;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int y = dk0.div(e), x = e - y * K0;
+    o1[x * LX + y] = r1[y * LY + x];
+  }
+  __syncthreads();
+  cplx<T>* r2 = fft_lines<T>(o1, r1, K0, LX, K1, twx, radx, R.nrad[0], false);
+  cplx<T>* o2 = r2 == o1 ? r1 : o1;
+  RecipSums acc{};
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int x = dk1.div(e), y = e - x * K1;
+    r2[x * LX + y] = green_apply<T, EV>(R, gf0, gf1, gf2, fr0, fr1, fr2, x, y, kz, r2[x * LX + y], acc);
+  }
+  __syncthreads();
+  cplx<T>* r3 = fft_lines<T>(r2, o2, K0, LX, K1, twx, radx, R.nrad[0], true);
+  cplx<T>* o3 = r3 == r2 ? o2 : r2;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int x = dk1.div(e), y = e - x * K1;
+    o3[y * LY + x] = r3[x * LX + y];
+  }
+  __syncthreads();
+  cplx<T>* r4 = fft_lines<T>(o3, r3, K1, LY, K0, twy, rady, R.nrad[1], true);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int x = dk1.div(e), y = e - x * K1;
+    Q[(long long)e * K2h] = r4[y * LY + x];
+  }
+  if (EV) {
+    double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
       double t = block_sum_fft(v[k], sh);
@@ -338,6 +489,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
+  const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
   // integer accumulators of the tile, line l = lx * TY + ly, point l * K2 + z
   // (they live in B, which the transform first writes after they are read)
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(B);
@@ -364,38 +516,41 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
       const int g = k0[2] - j;
       g2s[j] = g < 0 ? g + K2 : g;
     }
+    // stencil loops unrolled so the weights stay in registers
+#pragma unroll
     for (int jx = 0; jx < P; ++jx) {
       int lx = ox - jx;
       lx += lx < 0 ? K0 : 0;
-      if (lx >= nxt) continue;
       const T ax = z * w[0][jx];
+#pragma unroll
       for (int jy = 0; jy < P; ++jy) {
         int ly = oy - jy;
         ly += ly < 0 ? K1 : 0;
-        if (ly >= nyt) continue;
-        const T axy = ax * w[1][jy];
-        unsigned long long* row = acc + (size_t)(lx * TY + ly) * K2;
+        if (lx < nxt && ly < nyt) {
+          const T axy = ax * w[1][jy];
+          unsigned long long* row = acc + (size_t)(lx * TY + ly) * K2;
 #pragma unroll
-        for (int jz = 0; jz < P; ++jz) {
-          const double v = (double)(axy * w[2][jz]) * qs;
-          atomicAdd(&row[g2s[jz]], (unsigned long long)(long long)llrint(v));
+          for (int jz = 0; jz < P; ++jz) {
+            const double v = (double)(axy * w[2][jz]) * qs;
+            atomicAdd(&row[g2s[jz]], (unsigned long long)(long long)llrint(v));
+          }
         }
       }
     }
   });
   // integer mesh -> complex lines (k, l) at A[k * LBP + l]
   const double inv_qs = 1.0 / qs;
+  const FDiv dk2(K2), dk2h(K2h);
   for (int e = threadIdx.x; e < NL * K2; e += blockDim.x) {
-    const int l = e / K2, k = e % K2;
+    const int l = dk2.div(e), k = e - l * K2;
     A[k * LBP + l] = {(T)((double)(long long)acc[e] * inv_qs), (T)0};
   }
   __syncthreads();
-  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[2];
   cplx<T>* res = fft_lines<T>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], false);
   cplx<T>* out = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off;
   for (int e = threadIdx.x; e < NL * K2h; e += blockDim.x) {
-    const int l = e / K2h, m = e % K2h;
-    const int lx = l / TY, ly = l % TY;
+    const int l = dk2h.div(e), m = e - l * K2h;
+    const int lx = l / TY, ly = l - lx * TY;
     if (lx < nxt && ly < nyt)
       out[((long long)(mt.x0 + lx) * K1 + (mt.y0 + ly)) * K2h + m] = res[m * LBP + l];
   }
@@ -412,10 +567,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
+  const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
   const cplx<T>* in = reinterpret_cast<const cplx<T>*>(a.Qc) + R.cgrid_off;
+  const FDiv dk2h(K2h);
   for (int e = threadIdx.x; e < NL * K2h; e += blockDim.x) {
-    const int l = e / K2h, m = e % K2h;
-    const int lx = l / TY, ly = l % TY;
+    const int l = dk2h.div(e), m = e - l * K2h;
+    const int lx = l / TY, ly = l - lx * TY;
     cplx<T> v = {(T)0, (T)0};
     if (lx < nxt && ly < nyt) v = in[((long long)(mt.x0 + lx) * K1 + (mt.y0 + ly)) * K2h + m];
     A[m * LBP + l] = v;
@@ -424,7 +581,6 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
     if (m > 0 && mc > m && mc < K2) A[mc * LBP + l] = {v.x, -v.y};
   }
   __syncthreads();
-  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[2];
   const cplx<T>* phi = fft_lines<T>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], true);
   const TileCols tc = tile_columns(R, mt, P);
   const double fx = -R.lB * K0 / R.L[0], fy = -R.lB * K1 / R.L[1], fz = -R.lB * K2 / R.L[2];
@@ -447,40 +603,46 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
       g2s[j] = g < 0 ? g + K2 : g;
     }
     T gx = 0, gy = 0, gz = 0;
+    // stencil loops unrolled so the weights stay in registers
+#pragma unroll
     for (int jx = 0; jx < P; ++jx) {
       int lx = ox - jx;
       lx += lx < 0 ? K0 : 0;
-      if (lx >= nxt) continue;
+#pragma unroll
       for (int jy = 0; jy < P; ++jy) {
         int ly = oy - jy;
         ly += ly < 0 ? K1 : 0;
-        if (ly >= nyt) continue;
-        const int l = lx * TY + ly;
-        T s0 = 0, s2 = 0;
+        if (lx < nxt && ly < nyt) {
+          const int l = lx * TY + ly;
+          T s0 = 0, s2 = 0;
 #pragma unroll
-        for (int jz = 0; jz < P; ++jz) {
-          const T ph = phi[g2s[jz] * LBP + l].x;
-          s0 += w[2][jz] * ph;
-          s2 += dw[2][jz] * ph;
+          for (int jz = 0; jz < P; ++jz) {
+            const T ph = phi[g2s[jz] * LBP + l].x;
+            s0 += w[2][jz] * ph;
+            s2 += dw[2][jz] * ph;
+          }
+          gx += dw[0][jx] * w[1][jy] * s0;
+          gy += w[0][jx] * dw[1][jy] * s0;
+          gz += w[0][jx] * w[1][jy] * s2;
         }
-        gx += dw[0][jx] * w[1][jy] * s0;
-        gy += w[0][jx] * dw[1][jy] * s0;
-        gz += w[0][jx] * w[1][jy] * s2;
       }
     }
     const double z = (double)param_z(rec.w);
     const double f[3] = {z * fx * (double)gx, z * fy * (double)gy, z * fz * (double)gz};
     const int bi = a.qidx[q];
+    long long iv[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double v = f[d] * a.fscale;
-      long long iv = 0;
+      iv[d] = 0;
       if (fabs(v) < 4.0e18)
-        iv = (long long)llrint(v);
+        iv[d] = (long long)llrint(v);
       else
         atomicOr(a.status, (unsigned)STATUS_FORCE_OVERFLOW);
-      atomicAdd((unsigned long long*)&a.F[d][bi], (unsigned long long)iv);
     }
+    atomicAdd((unsigned long long*)&a.F[0][bi], (unsigned long long)iv[0]);
+    atomicAdd((unsigned long long*)&a.F[1][bi], (unsigned long long)iv[1]);
+    atomicAdd((unsigned long long*)&a.F[2][bi], (unsigned long long)iv[2]);
   });
 }
 
@@ -517,13 +679,13 @@ void allow_lds(const void* fn, size_t bytes) {
 }
 
 inline size_t lds_bytes(const PmeLaunch& a, int pass, bool fp64) {
-  return 2 * (size_t)a.maxK[pass] * (size_t)(a.lb[pass] + 1) * (fp64 ? 16 : 8);
+  return (2 * (size_t)a.maxK[pass] * (size_t)(a.lb[pass] + 1) + a.maxK[pass]) * (fp64 ? 16 : 8);
 }
 
 }  // namespace
 
 size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64) {
-  return 2 * (size_t)maxK2 * (size_t)(tx * ty + 1) * (fp64 ? 16 : 8);
+  return (2 * (size_t)maxK2 * (size_t)(tx * ty + 1) + maxK2) * (fp64 ? 16 : 8);
 }
 
 void launch_spread_z(hipStream_t s, const PmeLaunch& a, bool fp64) {
@@ -567,10 +729,41 @@ void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64) {
 void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse) {
   if (a.nitems[1] <= 0) return;
   size_t sh = lds_bytes(a, 1, fp64);
-  if (fp64)
+  if (fp64) {
+    allow_lds((const void*)k_fft_y<double>, sh);
     hipLaunchKernelGGL(k_fft_y<double>, dim3(a.nitems[1]), dim3(FFT_THREADS), sh, s, a, (int)inverse);
-  else
+  } else {
+    allow_lds((const void*)k_fft_y<float>, sh);
     hipLaunchKernelGGL(k_fft_y<float>, dim3(a.nitems[1]), dim3(FFT_THREADS), sh, s, a, (int)inverse);
+  }
+}
+
+size_t pme_plane_lds_bytes(int plane_elems, int maxK0, int maxK1, int maxK2, bool fp64) {
+  // two plane buffers, x and y twiddles, then six per-axis real tables
+  return (2 * (size_t)plane_elems + maxK0 + maxK1) * (fp64 ? 16 : 8) + 2 * (size_t)(maxK0 + maxK1 + maxK2) * (fp64 ? 8 : 4);
+}
+
+void launch_fft_yx_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev) {
+  if (a.nitems[0] <= 0) return;
+  const size_t sh = pme_plane_lds_bytes(a.plane_elems, a.maxK[2], a.maxK[1], a.maxK[0], fp64);
+  dim3 g(a.nitems[0]), b(YX_THREADS);
+  if (fp64) {
+    if (ev) {
+      allow_lds((const void*)k_fft_yx_conv<double, true>, sh);
+      hipLaunchKernelGGL((k_fft_yx_conv<double, true>), g, b, sh, s, a);
+    } else {
+      allow_lds((const void*)k_fft_yx_conv<double, false>, sh);
+      hipLaunchKernelGGL((k_fft_yx_conv<double, false>), g, b, sh, s, a);
+    }
+  } else {
+    if (ev) {
+      allow_lds((const void*)k_fft_yx_conv<float, true>, sh);
+      hipLaunchKernelGGL((k_fft_yx_conv<float, true>), g, b, sh, s, a);
+    } else {
+      allow_lds((const void*)k_fft_yx_conv<float, false>, sh);
+      hipLaunchKernelGGL((k_fft_yx_conv<float, false>), g, b, sh, s, a);
+    }
+  }
 }
 
 void launch_fft_x_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev) {
@@ -578,15 +771,21 @@ void launch_fft_x_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev) {
   size_t sh = lds_bytes(a, 2, fp64);
   dim3 g(a.nitems[2]), b(FFT_THREADS);
   if (fp64) {
-    if (ev)
+    if (ev) {
+      allow_lds((const void*)k_fft_x_conv<double, true>, sh);
       hipLaunchKernelGGL((k_fft_x_conv<double, true>), g, b, sh, s, a);
-    else
+    } else {
+      allow_lds((const void*)k_fft_x_conv<double, false>, sh);
       hipLaunchKernelGGL((k_fft_x_conv<double, false>), g, b, sh, s, a);
+    }
   } else {
-    if (ev)
+    if (ev) {
+      allow_lds((const void*)k_fft_x_conv<float, true>, sh);
       hipLaunchKernelGGL((k_fft_x_conv<float, true>), g, b, sh, s, a);
-    else
+    } else {
+      allow_lds((const void*)k_fft_x_conv<float, false>, sh);
       hipLaunchKernelGGL((k_fft_x_conv<float, false>), g, b, sh, s, a);
+    }
   }
 }
 
