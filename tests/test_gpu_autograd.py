@@ -1,0 +1,132 @@
+"""The differentiable energy (torch.autograd.Function over the engine's
+adjoint kernels) against central finite differences of the GPU energy in
+FP64: dE/dA per type pair, dE/da per type (sigma tied to a, and free), and
+dE/dr = -F for sampled position components."""
+import numpy as np
+import pytest
+
+import gcme_workloads as W
+from tests.gpu_common import make_engine
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(seed=9):
+    import torch
+    from paper_2403_08148_amd import params_from_workload
+    w = W.small_bulk(N=700, seed=seed, charged_frac=0.3, a_types=(0.4, 0.6), box=(7.0, 7.2, 6.8), rc=2.5,
+                     grid=(24, 24, 24))
+    eng = make_engine([w], "fp64")
+    p = params_from_workload(w)
+    pos = torch.tensor(w.pos, dtype=torch.float64, device="cuda")
+    return torch, w, eng, p, pos
+
+
+def test_dE_dA_and_da_tied_match_finite_differences():
+    torch, w, eng, p, pos = _setup()
+    from paper_2403_08148_amd import gcme_energy
+    nt = w.nt
+    A = torch.tensor(np.asarray(w.A, dtype=np.float64).reshape(1, nt, nt), requires_grad=True)
+    a = torch.tensor(np.asarray(w.a, dtype=np.float64).reshape(1, nt), requires_grad=True)
+    E = gcme_energy(eng, [p], pos, A, a)
+    gA, ga = torch.autograd.grad(E.sum(), [A, a])
+
+    def energy(Av, av):
+        with torch.no_grad():
+            return float(gcme_energy(eng, [p], pos, Av, av)[0])
+
+    A0, a0 = A.detach().clone(), a.detach().clone()
+    for t in range(nt):
+        for u in range(t, nt):
+            h = 1e-3 * float(A0[0, t, u])
+            d = torch.zeros_like(A0)
+            d[0, t, u] += h
+            d[0, u, t] += h if u != t else 0.0
+            fd = (energy(A0 + d, a0) - energy(A0 - d, a0)) / (2 * h)
+            got = float(gA[0, t, u] + (gA[0, u, t] if u != t else 0.0))
+            print(f"dE/dA[{t},{u}] autograd {got:.10e} fd {fd:.10e}", flush=True)
+            assert abs(got - fd) <= 1e-7 * abs(fd) + 1e-9
+    for t in range(nt):
+        h = 1e-4 * float(a0[0, t])
+        d = torch.zeros_like(a0)
+        d[0, t] = h
+        fd = (energy(A0, a0 + d) - energy(A0, a0 - d)) / (2 * h)
+        got = float(ga[0, t])
+        print(f"dE/da[{t}] (tied) autograd {got:.10e} fd {fd:.10e}", flush=True)
+        assert abs(got - fd) <= 1e-6 * abs(fd) + 1e-6
+    eng.close()
+
+
+def test_dE_dsigma_free_matches_finite_differences():
+    torch, w, eng, p, pos = _setup(seed=10)
+    from paper_2403_08148_amd import gcme_energy
+    nt = w.nt
+    A = torch.tensor(np.asarray(w.A, dtype=np.float64).reshape(1, nt, nt))
+    a = torch.tensor(np.asarray(w.a, dtype=np.float64).reshape(1, nt), requires_grad=True)
+    s = torch.tensor(np.asarray(w.sigma, dtype=np.float64).reshape(1, nt) * 1.1, requires_grad=True)
+    E = gcme_energy(eng, [p], pos, A, a, s)
+    ga, gs = torch.autograd.grad(E.sum(), [a, s])
+
+    def energy(av, sv):
+        with torch.no_grad():
+            return float(gcme_energy(eng, [p], pos, A, av, sv)[0])
+
+    a0, s0 = a.detach().clone(), s.detach().clone()
+    for t in range(nt):
+        h = 1e-4 * float(s0[0, t])
+        d = torch.zeros_like(s0)
+        d[0, t] = h
+        fd_s = (energy(a0, s0 + d) - energy(a0, s0 - d)) / (2 * h)
+        h2 = 1e-4 * float(a0[0, t])
+        d2 = torch.zeros_like(a0)
+        d2[0, t] = h2
+        fd_a = (energy(a0 + d2, s0) - energy(a0 - d2, s0)) / (2 * h2)
+        print(f"type {t}: dE/dsigma {float(gs[0, t]):.10e} fd {fd_s:.10e}; dE/da {float(ga[0, t]):.10e} "
+              f"fd {fd_a:.10e}", flush=True)
+        assert abs(float(gs[0, t]) - fd_s) <= 1e-6 * abs(fd_s) + 1e-6
+        assert abs(float(ga[0, t]) - fd_a) <= 1e-6 * abs(fd_a) + 1e-6
+    eng.close()
+
+
+def test_position_gradient_is_minus_force():
+    torch, w, eng, p, pos = _setup(seed=11)
+    from paper_2403_08148_amd import gcme_energy
+    nt = w.nt
+    A = torch.tensor(np.asarray(w.A, dtype=np.float64).reshape(1, nt, nt))
+    a = torch.tensor(np.asarray(w.a, dtype=np.float64).reshape(1, nt))
+    x = pos.clone().requires_grad_(True)
+    E = gcme_energy(eng, [p], x, A, a)
+    (g,) = torch.autograd.grad(E.sum(), [x])
+    rng = np.random.default_rng(3)
+    # positions live on a 2^-32 L lattice (~1.6e-9), so the steps stay large
+    # (1e-3, 2e-3) and Richardson extrapolation removes the h^2 term of the
+    # central difference, which is large at the steep GCM contacts
+    def d_central(i, k, h):
+        xp = pos.clone()
+        xm = pos.clone()
+        xp[i, k] += h
+        xm[i, k] -= h
+        with torch.no_grad():
+            return (float(gcme_energy(eng, [p], xp, A, a)[0]) - float(gcme_energy(eng, [p], xm, A, a)[0])) / (2 * h)
+
+    # the potential is truncated at rc (not shifted), so E jumps where a pair
+    # crosses the cutoff: test beads with no neighbour within 5e-3 of rc
+    L = np.asarray(w.box)
+    cand = []
+    for i in rng.permutation(w.N):
+        d = w.pos - w.pos[i]
+        d -= L * np.round(d / L)
+        r = np.sqrt((d * d).sum(1))
+        if np.all(np.abs(r - w.rc) > 5e-3):
+            cand.append(i)
+        if len(cand) == 4:
+            break
+    assert len(cand) == 4
+    for i in cand:
+        for k in range(3):
+            d1, d2 = d_central(i, k, 2e-3), d_central(i, k, 1e-3)
+            fd = (4.0 * d2 - d1) / 3.0
+            got = float(g[i, k])
+            print(f"bead {i} axis {k}: dE/dr {got:.8e} fd {fd:.8e}", flush=True)
+            assert abs(got - fd) <= 1e-5 * max(1.0, abs(fd))
+    eng.close()
