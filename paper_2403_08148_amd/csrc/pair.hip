@@ -169,6 +169,20 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
       chi[k] = R.nc[k] - 1;
     }
   }
+  // In the frame of bead 0, separations equal the per-pair minimum image for
+  // every pair within rc as long as each cluster bead lies within L/2 - rc of
+  // bead 0 on each axis (then |d| < rc cannot wrap); otherwise the test
+  // takes the minimum image of each pair.
+  bool frame = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) frame = frame && fmax(-lo[k], hi[k]) < 0.5 * R.L[k] - rcl;
+  float rfx[CI], rfy[CI], rfz[CI];
+#pragma unroll
+  for (int k = 0; k < CI; ++k) {
+    rfx[k] = (float)(int)(cxs[k] - cxs[0]) * R.scalef[0];
+    rfy[k] = (float)(int)(cys[k] - cys[0]) * R.scalef[1];
+    rfz[k] = (float)(int)(czs[k] - czs[0]) * R.scalef[2];
+  }
   const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
   const int ncx = chi[0] - clo[0] + 1, ncy = chi[1] - clo[1] + 1;
   const int ncol = ncx * ncy;
@@ -265,12 +279,24 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
       // appended in candidate order
       auto test = [&](const uint4 pj, bool v, int j) {
         bool hit = false;
+        if (frame) {
+          // candidate relative to bead 0 once, then one subtraction per bead
+          const float Dx = (float)(int)(pj.x - cxs[0]) * sx;
+          const float Dy = (float)(int)(pj.y - cys[0]) * sy;
+          const float Dz = (float)(int)(pj.z - czs[0]) * sz;
 #pragma unroll
-        for (int i = 0; i < CI; ++i) {
-          const float dx = (float)(int)(cxs[i] - pj.x) * sx;
-          const float dy = (float)(int)(cys[i] - pj.y) * sy;
-          const float dz = (float)(int)(czs[i] - pj.z) * sz;
-          hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+          for (int i = 0; i < CI; ++i) {
+            const float dx = Dx - rfx[i], dy = Dy - rfy[i], dz = Dz - rfz[i];
+            hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < CI; ++i) {
+            const float dx = (float)(int)(cxs[i] - pj.x) * sx;
+            const float dy = (float)(int)(cys[i] - pj.y) * sy;
+            const float dz = (float)(int)(czs[i] - pj.z) * sz;
+            hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+          }
         }
         hit = hit && v;
         const unsigned long long m = __ballot(hit);
