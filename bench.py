@@ -32,6 +32,9 @@ PEAK_FP64_TFLOPS = 78.6
 # forces by Newton's third law): separation 3, r^2 5, exponent 1, exp 1,
 # prefactor 1, force scale 1, force vector 3, +f_i 3, -f_j 3, energy 1.
 FLOP_PER_GCM_PAIR = 22
+# Distance test a neighbour search needs for each in-range pair it keeps:
+# separation 3, r^2 5.
+FLOP_PER_DISTANCE_TEST = 8
 # Charged pair, real-space bracket: separation 3, r^2 5, sqrt 1, 1/r 1, two
 # erfc 2, difference and scale 2, two Gaussians (2 mul + 2 exp) 4, bracket
 # 4, force vector 3, +f_i 3, -f_j 3, z_i z_j lB 2, energy 1.
@@ -46,6 +49,8 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--workload", default="bulk_N32768", choices=["bulk_N32768", "bulk_N2097152"])
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default="",
+                    help="cells_per_cutoff,beads_per_cluster,charges_per_cluster (implies --no-autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--steps-only", action="store_true",
@@ -81,7 +86,12 @@ def main():
     eng = GCMe([w.N], precision=args.precision, seed=12345)
     eng.set_params(params_from_workload(w))
     eng.set_state(w.pos, w.type, w.z, w.vel)
-    tuning = eng.tuning() if args.no_autotune else eng.autotune()
+    if args.tuning:
+        c, g, q = (int(x) for x in args.tuning.split(","))
+        eng.set_tuning(cells_per_cutoff=c, beads_per_cluster=g, charges_per_cluster=q)
+        tuning = eng.tuning()
+    else:
+        tuning = eng.tuning() if args.no_autotune else eng.autotune()
 
     # warm-up (also relaxes the random start a little)
     eng.step(args.warmup)
@@ -117,39 +127,51 @@ def main():
     eng.sync()
     E = obs["energy"].cpu().numpy()[0]
 
-    # roofline of the dominant stage
-    dom = max(stages, key=stages.get)
-    t_dom = stages[dom] * 1e-3
+    # charged pairs within the cutoff at the final positions (for the
+    # charged-pair stages' algorithmic counts)
+    cc_pairs = charged_pairs(eng, w)
+
+    # algorithmic work per launch of each stage: (bound, amount); alu amounts
+    # are FLOP, hbm amounts bytes (kernels table)
     K = w.grid
-    ngrid = K[0] * K[1] * K[2]
     nch = K[0] * K[1] * (K[2] // 2 + 1)
     cs = 16 if args.precision == "fp64" else 8
-    rs = cs // 2
     peak_alu = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
     alg = {
-        # (bound, algorithmic amount per launch)
+        "int_first": ("hbm", w.N * (12 + 24 + 24 + 12 + 24 + 24)),
+        "sort": ("hbm", w.N * (12 + 4 + 4 + 12 + 24 + 4 + 4 + 12 + 24 + 4 + 4 + 16)),
+        "list_gcm": ("alu", FLOP_PER_DISTANCE_TEST * pairs),
         "pair_gcm": ("alu", FLOP_PER_GCM_PAIR * pairs),
+        "list_elec": ("alu", FLOP_PER_DISTANCE_TEST * cc_pairs),
+        "pair_elec": ("alu", FLOP_PER_ELEC_PAIR * cc_pairs),
         "spread_z": ("hbm", nq * 16 + nch * cs),
         "fft_y": ("hbm", 2 * nch * cs),
-        "fft_x_conv": ("hbm", 2 * nch * cs),
+        "fft_conv": ("hbm", 2 * nch * cs),
         "fft_y_inv": ("hbm", 2 * nch * cs),
         "z_gather": ("hbm", nch * cs + nq * (16 + 4 + 24)),
-        "int_first": ("hbm", w.N * (12 + 24 + 8 + 4 + 4 + 24 + 12 + 24)),
-        "int_last": ("hbm", w.N * (12 + 24 + 4 + 4 + 24 + 12 + 24 + 4 + 4)),
-        "sort": ("hbm", w.N * (12 + 4 + 4 + 12 + 24 + 4 + 4)),
+        "int_last": ("hbm", w.N * (12 + 24 + 24 + 12 + 24 + 4)),
     }
-    bound, amount = alg.get(dom, ("alu", 0.0))
-    if bound == "alu":
-        achieved = amount / t_dom / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak_alu, "unit": "TFLOP/s",
-                "frac": achieved / peak_alu, "traffic": None}
-    else:
-        achieved = amount / t_dom / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+
+    def roof_of(name):
+        bound, amount = alg[name]
+        t = stages[name] * 1e-3
+        if t <= 0:
+            return None
+        if bound == "alu":
+            ach = amount / t / 1e12
+            return {"bound": "alu", "kernel": name, "achieved": ach, "peak": peak_alu, "unit": "TFLOP/s",
+                    "frac": ach / peak_alu}
+        ach = amount / t / 1e9
+        return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS}
+
+    stage_roof = {k: roof_of(k) for k in stages if k in alg and stages[k] > 0}
+    dom = max(stage_roof, key=lambda k: stages[k])
+    roof = dict(stage_roof[dom])
+    roof["launch_us"] = stages[dom] * 1e3
+    roof["traffic"] = measured_traffic(dom)
     # the excluded-volume pair kernel's own figure is always reported
-    pg = stages["pair_gcm"] * 1e-3
-    gcm_tflops = FLOP_PER_GCM_PAIR * pairs / pg / 1e12
+    gcm_tflops = stage_roof["pair_gcm"]["achieved"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -177,6 +199,8 @@ def main():
         "wall_s_timed": wall,
         "stage_ms": stages,
         "pair_gcm_tflops": gcm_tflops,
+        "charged_pairs_within_cutoff": cc_pairs,
+        "stage_roofline": stage_roof,
         "energy_terms_last_step": {k: float(v) for k, v in zip(
             ["ex", "real", "recip", "corr", "self", "pot", "kin"], E)},
         "roofline": roof,
@@ -184,6 +208,40 @@ def main():
     }
     print(json.dumps(out), flush=True)
     eng.close()
+
+
+def charged_pairs(eng, w):
+    """Unordered charged pairs with r < rc at the engine's current positions
+    (scipy KD tree on the host)."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    pos, _, _ = eng.get_state()
+    eng.sync()
+    p = pos.t().cpu().numpy()
+    q = np.mod(p[w.z != 0], w.box)
+    return int(len(cKDTree(q, boxsize=w.box).query_pairs(w.rc)))
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of a stage from committed rocprofv3 counter runs
+    (profiles/traffic_<stage>.json: FETCH_SIZE and WRITE_SIZE in KiB per
+    dispatch, each scaled by what the counter reads for a plain device copy of
+    known size), or None when no run exists or the kernel source changed
+    since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    src = os.path.join(ROOT, t["source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+            return None
+    cb = float(t["copy_bytes"])
+    fetch = t["fetch_kib"] * 1024.0 * cb / (t["copy_fetch_kib"] * 1024.0)
+    write = t["write_kib"] * 1024.0 * cb / (t["copy_write_kib"] * 1024.0)
+    return fetch + write
 
 
 def cpu_baseline(w, pairs, budget_s=15.0):
