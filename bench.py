@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--steps-only", action="store_true",
                     help="only the timed step loop (for profiler runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64, 2M-bead and batched-replica measurements")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this size and exit (HBM counter calibration)")
     return ap.parse_args()
@@ -173,6 +175,13 @@ def main():
     # the excluded-volume pair kernel's own figure is always reported
     gcm_tflops = stage_roof["pair_gcm"]["achieved"]
 
+    # mixed-precision forces against the plain FP64 GPU form at the same state
+    # (the initial positions), then the other workloads
+    extras = None
+    if not args.no_extras:
+        eng.close()
+        extras = extra_workloads(w)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, pairs)
@@ -205,9 +214,98 @@ def main():
             ["ex", "real", "recip", "corr", "self", "pot", "kin"], E)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "extra": extras,
     }
     print(json.dumps(out), flush=True)
+    if args.no_extras:
+        eng.close()
+
+
+def time_steps(eng, steps, warmup):
+    """ms per graph-replayed step on the engine's stream (HIP events)."""
+    import torch
+    eng.step(warmup)
+    eng.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(eng.stream)
+    eng.step(steps)
+    e1.record(eng.stream)
+    eng.sync()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def engine_for(ws, precision, tune=True):
+    from paper_2403_08148_amd import GCMe, params_from_workload
+    import numpy as np
+    eng = GCMe([x.N for x in ws], precision=precision, seed=12345)
+    for r, x in enumerate(ws):
+        eng.set_params(params_from_workload(x), replica=r)
+    eng.set_state(np.concatenate([x.pos for x in ws]), np.concatenate([x.type for x in ws]),
+                  np.concatenate([x.z for x in ws]), np.concatenate([x.vel for x in ws]))
+    tuning = eng.autotune() if tune else eng.tuning()
+    return eng, tuning
+
+
+def extra_workloads(w):
+    """The plain FP64 form of the same workload, the 2,097,152-bead bulk
+    system (mixed and FP64) and 256 batched replicas against one engine per
+    replica called in sequence."""
+    import numpy as np
+    import gcme_workloads as W
+    out = {}
+
+    def forces(eng):
+        f = eng.forces_energy(energy=False, virial=False)["force"]
+        eng.sync()
+        return f.double().cpu().numpy()
+
+    # 1. same workload, plain FP64 GPU form; mixed force error against it
+    res = {}
+    fr = {}
+    for prec in ("mixed", "fp64"):
+        eng, tun = engine_for([w], prec)
+        fr[prec] = forces(eng)
+        ms = time_steps(eng, 200, 20)
+        res[prec] = {"ms_per_step": ms, "tuning": tun}
+        eng.close()
+    res["mixed_force_rel_rms_vs_fp64"] = float(np.linalg.norm(fr["mixed"] - fr["fp64"]) / np.linalg.norm(fr["fp64"]))
+    out[w.name] = res
+
+    # 2. N = 2,097,152 bulk, mixed and FP64
+    w4 = W.config4()
+    res = {}
+    fr = {}
+    for prec in ("mixed", "fp64"):
+        eng, tun = engine_for([w4], prec)
+        fr[prec] = forces(eng)
+        ms = time_steps(eng, 10, 3)
+        pairs = eng.count_pairs()
+        res[prec] = {"ms_per_step": ms, "pair_interactions_per_s": pairs * 1000.0 / ms,
+                     "ns_per_day": 1000.0 / ms * w4.dt * TAU_PS * 86400.0 / 1000.0, "pairs_within_cutoff": pairs,
+                     "tuning": tun}
+        eng.close()
+    res["mixed_force_rel_rms_vs_fp64"] = float(np.linalg.norm(fr["mixed"] - fr["fp64"]) / np.linalg.norm(fr["fp64"]))
+    out[w4.name] = res
+
+    # 3. 256 batched replicas (one engine, one graph per step) against the
+    #    same replicas each in its own engine, stepped one after another
+    ws = W.config5()
+    eng, tun = engine_for(ws, "mixed")
+    ms_b = time_steps(eng, 100, 10)
+    pairs = eng.count_pairs()
     eng.close()
+    ms_seq = 0.0
+    for x in ws:
+        e1, _ = engine_for([x], "mixed", tune=False)
+        ms_seq += time_steps(e1, 20, 3)
+        e1.close()
+    out["batched_256_replicas"] = {"n_beads": int(sum(x.N for x in ws)), "ms_per_step": ms_b,
+                                   "pair_interactions_per_s": pairs * 1000.0 / ms_b,
+                                   "sequential_ms_per_step": ms_seq, "speedup_vs_sequential": ms_seq / ms_b,
+                                   "tuning": tun}
+    return out
 
 
 def charged_pairs(eng, w):

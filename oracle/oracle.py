@@ -140,11 +140,12 @@ def phi_real(r, alpha, beta):
     return lib().gco_phi_real(float(r), float(alpha), float(beta))
 
 
-def real_space(pos, type_, z, p: Params, use_cells=True, sample=None, adjoint=False):
+def real_space(pos, type_, z, p: Params, use_cells=True, sample=None, adjoint=False, energies=True):
     """Min-image real space (GCM + smeared-Coulomb bracket), r < rc.
     Returns dict with F (forces on all beads, or on ``sample``), E_ex, E_real,
     W[6] (xx,yy,zz,xy,xz,yz), and with adjoint: Eex_tt [nt,nt], dE_dsigma,
-    dE_da (real-space part)."""
+    dE_da (real-space part).  energies=False (with a sample) computes only the
+    sampled forces, visiting only the sampled beads."""
     pos, type_, z = _prep(pos, type_, z)
     N = len(pos)
     pc = p._c()
@@ -154,8 +155,8 @@ def real_space(pos, type_, z, p: Params, use_cells=True, sample=None, adjoint=Fa
         F = np.zeros((len(sample), 3))
     else:
         F = np.zeros((N, 3))
-    E2 = np.zeros(2)
-    W = np.zeros(6)
+    E2 = np.zeros(2) if energies else None
+    W = np.zeros(6) if energies else None
     ett = np.zeros(nt * nt) if adjoint else None
     dsg = np.zeros(nt) if adjoint else None
     dea = np.zeros(nt) if adjoint else None
@@ -164,7 +165,9 @@ def real_space(pos, type_, z, p: Params, use_cells=True, sample=None, adjoint=Fa
                               _d(F), _d(E2), _d(W), _d(ett), _d(dsg), _d(dea))
     if rc != 0:
         raise ValueError("oracle real_space: rc must be <= L/2")
-    out = dict(F=F, E_ex=E2[0], E_real=E2[1], W=W)
+    out = dict(F=F)
+    if energies:
+        out.update(E_ex=E2[0], E_real=E2[1], W=W)
     if adjoint:
         out.update(Eex_tt=ett.reshape(nt, nt), dE_dsigma=dsg, dE_da=dea)
     return out

@@ -86,13 +86,13 @@ __device__ inline int block_inclusive_scan(int v, int* sh) {
 // Produces start (exclusive) and, for all beads, the scatter cursor
 // fill = start.
 constexpr int SINGLE_SCAN_THREADS = 1024;
-constexpr int SINGLE_SCAN_MAX = 15872;
+constexpr int SINGLE_SCAN_MAX = 38912;  // counts staged in up to 152 KiB of LDS
 
 // The counts pass through LDS: coalesced, independent global loads and
 // stores, and each thread's serial chunk runs at LDS latency.
 __global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c) {
   __shared__ int sh[16];
-  __shared__ int buf[SINGLE_SCAN_MAX];
+  extern __shared__ __align__(16) int buf[];  // ncells entries
   const int n = c.ncells;
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per, hi = min(lo + per, n);
@@ -288,7 +288,9 @@ void launch_bin(hipStream_t s, StateView A, const RepDesc* rep, CellView c, int 
 
 void launch_scan(hipStream_t s, CellView c) {
   if (c.ncells <= SINGLE_SCAN_MAX) {
-    hipLaunchKernelGGL(k_scan_single, dim3(2), dim3(SINGLE_SCAN_THREADS), 0, s, c);
+    const size_t sh = (size_t)c.ncells * 4;
+    if (sh > 65536) (void)hipFuncSetAttribute((const void*)k_scan_single, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL(k_scan_single, dim3(2), dim3(SINGLE_SCAN_THREADS), sh, s, c);
     return;
   }
   int nb = nblk(c.ncells, SCAN_BLOCK);

@@ -136,33 +136,49 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
     cys[k] = read_lane(uy, k);
     czs[k] = read_lane(uz, k);
   }
-  // bounding box relative to bead 0 (minimum image), and bead 0's position
-  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  // Cluster geometry in float, relative to the lower corner of bead 0's cell:
+  // every value is a few cells at most, so float carries it to ~1e-7 of a
+  // cell, and the margin dl keeps each cell range conservative.
+  float rfx[CI], rfy[CI], rfz[CI];
+#pragma unroll
+  for (int k = 0; k < CI; ++k) {
+    rfx[k] = (float)(int)(cxs[k] - cxs[0]) * R.scalef[0];
+    rfy[k] = (float)(int)(cys[k] - cys[0]) * R.scalef[1];
+    rfz[k] = (float)(int)(czs[k] - czs[0]) * R.scalef[2];
+  }
+  float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 1; k < CI; ++k) {
-    const double d0 = (double)(int)(cxs[k] - cxs[0]) * R.scaled[0];
-    const double d1 = (double)(int)(cys[k] - cys[0]) * R.scaled[1];
-    const double d2 = (double)(int)(czs[k] - czs[0]) * R.scaled[2];
-    lo[0] = fmin(lo[0], d0);
-    hi[0] = fmax(hi[0], d0);
-    lo[1] = fmin(lo[1], d1);
-    hi[1] = fmax(hi[1], d1);
-    lo[2] = fmin(lo[2], d2);
-    hi[2] = fmax(hi[2], d2);
+    lo[0] = fminf(lo[0], rfx[k]);
+    hi[0] = fmaxf(hi[0], rfx[k]);
+    lo[1] = fminf(lo[1], rfy[k]);
+    hi[1] = fmaxf(hi[1], rfy[k]);
+    lo[2] = fminf(lo[2], rfz[k]);
+    hi[2] = fmaxf(hi[2], rfz[k]);
   }
-  const double x0[3] = {(double)cxs[0] * R.scaled[0], (double)cys[0] * R.scaled[1], (double)czs[0] * R.scaled[2]};
-  // list cutoff: a hair above rc, so the float test below never drops a pair
-  // the force kernel's own test (in its precision) would keep
-  const double rcl = R.rc * (1.0 + 1e-5);
-  const float rcl2f = (float)(rcl * rcl);
-  int clo[3], chi[3];
-  bool whole[3];
-  double h[3];
+  const uint32_t u0[3] = {cxs[0], cys[0], czs[0]};
+  int c0[3];
+  float p0[3], h[3], ih[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    h[k] = R.L[k] / R.nc[k];
-    clo[k] = (int)floor((x0[k] + lo[k] - rcl) / h[k]);
-    chi[k] = (int)floor((x0[k] + hi[k] + rcl) / h[k]);
+    const unsigned long long pp = (unsigned long long)u0[k] * (unsigned)R.nc[k];
+    c0[k] = (int)(pp >> 32);
+    h[k] = R.hf[k];
+    ih[k] = 1.0f / h[k];
+    p0[k] = (float)(uint32_t)(pp & 0xffffffffu) * 2.3283064365386963e-10f * h[k];
+  }
+  // list cutoff: a hair above rc, so the float test below never drops a pair
+  // the force kernel's own test (in its precision) would keep
+  const float rcl = (float)(R.rc * (1.0 + 1e-5));
+  const float rcl2f = rcl * rcl;
+  const float dl = 1e-4f * fmaxf(h[0], fmaxf(h[1], h[2]));
+  const float rclm = rcl + dl;
+  int clo[3], chi[3];  // cell ranges relative to c0 (absolute when whole)
+  bool whole[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    clo[k] = (int)floorf((p0[k] + lo[k] - rclm) * ih[k]);
+    chi[k] = (int)floorf((p0[k] + hi[k] + rclm) * ih[k]);
     whole[k] = chi[k] - clo[k] + 1 >= R.nc[k];
     if (whole[k]) {
       clo[k] = 0;
@@ -175,14 +191,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
   // takes the minimum image of each pair.
   bool frame = true;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) frame = frame && fmax(-lo[k], hi[k]) < 0.5 * R.L[k] - rcl;
-  float rfx[CI], rfy[CI], rfz[CI];
-#pragma unroll
-  for (int k = 0; k < CI; ++k) {
-    rfx[k] = (float)(int)(cxs[k] - cxs[0]) * R.scalef[0];
-    rfy[k] = (float)(int)(cys[k] - cys[0]) * R.scalef[1];
-    rfz[k] = (float)(int)(czs[k] - czs[0]) * R.scalef[2];
-  }
+  for (int k = 0; k < 3; ++k) frame = frame && fmaxf(-lo[k], hi[k]) < 0.5f * (float)R.L[k] - rclm;
   const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
   const int ncx = chi[0] - clo[0] + 1, ncy = chi[1] - clo[1] + 1;
   const int ncol = ncx * ncy;
@@ -195,18 +204,21 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
     int b0[2] = {0, 0}, ln[2] = {0, 0};
     const int k = cbase + lane;
     if (k < ncol) {
-      const int cxr = clo[0] + k / ncy, cyr = clo[1] + k % ncy;
-      const double gx = whole[0] ? 0.0 : fmax(0.0, fmax(cxr * h[0] - (x0[0] + hi[0]), (x0[0] + lo[0]) - (cxr + 1) * h[0]));
-      const double gy = whole[1] ? 0.0 : fmax(0.0, fmax(cyr * h[1] - (x0[1] + hi[1]), (x0[1] + lo[1]) - (cyr + 1) * h[1]));
-      const double d2 = gx * gx + gy * gy;
-      if (d2 < rcl * rcl) {
-        const int cx = cxr < 0 ? cxr + nx : (cxr >= nx ? cxr - nx : cxr);
-        const int cy = cyr < 0 ? cyr + ny : (cyr >= ny ? cyr - ny : cyr);
+      const int rx = clo[0] + k / ncy, ry = clo[1] + k % ncy;
+      // distance from the column to the bounding box in x and y
+      const float gx = whole[0] ? 0.f : fmaxf(0.f, fmaxf(rx * h[0] - (p0[0] + hi[0]), (p0[0] + lo[0]) - (rx + 1) * h[0]));
+      const float gy = whole[1] ? 0.f : fmaxf(0.f, fmaxf(ry * h[1] - (p0[1] + hi[1]), (p0[1] + lo[1]) - (ry + 1) * h[1]));
+      const float d2 = gx * gx + gy * gy;
+      if (d2 < rclm * rclm) {
+        int cx = whole[0] ? rx : c0[0] + rx;
+        int cy = whole[1] ? ry : c0[1] + ry;
+        cx += cx < 0 ? nx : (cx >= nx ? -nx : 0);
+        cy += cy < 0 ? ny : (cy >= ny ? -ny : 0);
         int zlo = 0, zhi = nz - 1;
         if (!whole[2]) {
-          const double zr = sqrt(rcl * rcl - d2);
-          zlo = (int)floor((x0[2] + lo[2] - zr) / h[2]);
-          zhi = (int)floor((x0[2] + hi[2] + zr) / h[2]);
+          const float zr = sqrtf(rclm * rclm - d2);
+          zlo = c0[2] + (int)floorf((p0[2] + lo[2] - zr) * ih[2]);
+          zhi = c0[2] + (int)floorf((p0[2] + hi[2] + zr) * ih[2]);
           if (zhi - zlo + 1 >= nz) {
             zlo = 0;
             zhi = nz - 1;
