@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--workload", default="bulk_N32768", choices=["bulk_N32768", "bulk_N2097152"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default="",
-                    help="cells_per_cutoff,beads_per_cluster,charges_per_cluster (implies --no-autotune)")
+                    help="cells_per_cutoff,beads_per_cluster,charges_per_cluster[,direct_pairs] "
+                         "(implies --no-autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--steps-only", action="store_true",
@@ -89,8 +90,9 @@ def main():
     eng.set_params(params_from_workload(w))
     eng.set_state(w.pos, w.type, w.z, w.vel)
     if args.tuning:
-        c, g, q = (int(x) for x in args.tuning.split(","))
-        eng.set_tuning(cells_per_cutoff=c, beads_per_cluster=g, charges_per_cluster=q)
+        v = [int(x) for x in args.tuning.split(",")]
+        eng.set_tuning(cells_per_cutoff=v[0], beads_per_cluster=v[1], charges_per_cluster=v[2],
+                       direct_pairs=v[3] if len(v) > 3 else -1)
         tuning = eng.tuning()
     else:
         tuning = eng.tuning() if args.no_autotune else eng.autotune()

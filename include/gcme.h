@@ -164,12 +164,17 @@ const char* gcme_last_error(gcme_handle h);
 
 /* Tuning knobs picked by the autotuner (exposed for benchmarks and tests).
  * Any field < 0 means "leave as is".  The pair kernels work on clusters of
- * consecutive cell-sorted beads with one neighbour list per cluster. */
+ * consecutive cell-sorted beads, either with one neighbour list per cluster
+ * (built each evaluation) or list-free (each cluster evaluates the beads of
+ * its cell columns directly).  Both visit the same pairs with the same
+ * cutoff test; they differ in the order of the per-bead sums. */
 typedef struct {
     int32_t cells_per_cutoff;    /* cell edge ~ rc / n (1..4) */
     int32_t beads_per_cluster;   /* excluded-volume cluster size (2, 4, 8) */
     int32_t charges_per_cluster; /* real-space electrostatics cluster size (2, 4, 8) */
     int32_t list_slack_pct;      /* list capacity above the density estimate, % (0..1000) */
+    int32_t direct_pairs;        /* list-free kernels: bit 0 excluded volume,
+                                    bit 1 real-space electrostatics (0..3) */
 } gcme_tuning;
 
 gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t);

@@ -111,7 +111,7 @@ struct gcme_ctx {
   std::vector<int> nq, qoff;
   int NQ = 0;
   // tuning
-  gcme_tuning tune{3, 4, 4, 50};
+  gcme_tuning tune{3, 4, 4, 50, 0};
   bool plan_dirty = true;
   // device buffers
   DevBuf a_pos[3], a_vel[3], a_param, a_id;
@@ -578,8 +578,10 @@ gcme_status build_plan(gcme_handle h) {
   upload(tg, h->d_tiles_g, s);
   upload(tq, h->d_tiles_q, s);
   upload(t256, h->d_tiles_256, s);
-  HIPCHK(h, h->list_g.alloc((size_t)std::max(1, h->ncl_g) * h->cap_g * 4));
-  HIPCHK(h, h->list_q.alloc((size_t)std::max(1, h->ncl_q) * h->cap_q * 4));
+  // the list-free kernels read no list
+  const bool dg = h->tune.direct_pairs & 1, dq = (h->tune.direct_pairs >> 1) & 1;
+  HIPCHK(h, h->list_g.alloc(dg ? 64 : (size_t)std::max(1, h->ncl_g) * h->cap_g * 4));
+  HIPCHK(h, h->list_q.alloc(dq ? 64 : (size_t)std::max(1, h->ncl_q) * h->cap_q * 4));
   HIPCHK(h, h->cnt_g.alloc((size_t)std::max(1, h->ncl_g) * 4));
   HIPCHK(h, h->cnt_q.alloc((size_t)std::max(1, h->ncl_q) * 4));
   upload(toff_g, h->d_off[SLOT_GCM], s);
@@ -665,6 +667,7 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.cl = h->d_cl_q.as<int2>();
     a.ncl = h->ncl_q;
     a.ci = h->tune.charges_per_cluster;
+    a.direct = (h->tune.direct_pairs >> 1) & 1;
     a.cap = h->cap_q;
     a.list = h->list_q.as<uint32_t>();
     a.count = h->cnt_q.as<int>();
@@ -679,6 +682,7 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.cl = h->d_cl_g.as<int2>();
     a.ncl = h->ncl_g;
     a.ci = h->tune.beads_per_cluster;
+    a.direct = h->tune.direct_pairs & 1;
     a.cap = h->cap_g;
     a.list = h->list_g.as<uint32_t>();
     a.count = h->cnt_g.as<int>();
@@ -1218,8 +1222,13 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
     if (t->list_slack_pct > 1000) return fail(h, GCME_EINVAL, "list_slack_pct in 0..1000");
     n.list_slack_pct = t->list_slack_pct;
   }
+  if (t->direct_pairs >= 0) {
+    if (t->direct_pairs > 3) return fail(h, GCME_EINVAL, "direct_pairs in 0..3");
+    n.direct_pairs = t->direct_pairs;
+  }
   if (n.cells_per_cutoff != h->tune.cells_per_cutoff || n.beads_per_cluster != h->tune.beads_per_cluster ||
-      n.charges_per_cluster != h->tune.charges_per_cluster || n.list_slack_pct != h->tune.list_slack_pct) {
+      n.charges_per_cluster != h->tune.charges_per_cluster || n.list_slack_pct != h->tune.list_slack_pct ||
+      n.direct_pairs != h->tune.direct_pairs) {
     h->tune = n;
     h->plan_dirty = true;
     h->drop_graphs();
@@ -1271,31 +1280,30 @@ gcme_status gcme_autotune(gcme_handle h) {
   HIPCHK(h, hipMemcpyAsync(saveF.p, h->F.p, (size_t)h->N * 24, hipMemcpyDeviceToDevice, s));
   const int ncc_list[] = {2, 3, 4};
   const int ci_list[] = {2, 4, 8};
-  for (int ncc : ncc_list) {
-    for (int cg : ci_list) {
-      for (int cq : ci_list) {
-        if (h->NQ == 0 && cq != ci_list[0]) continue;
-        gcme_tuning t{ncc, cg, cq, -1};
-        if (gcme_set_tuning(h, &t) != GCME_OK) continue;
-        if (build_plan(h) != GCME_OK) continue;
-        float ms = 0;
-        for (int rep = 0; rep < 3; ++rep) {
-          launch_fill_i64(s, h->F.as<long long>(), 0, 3LL * h->N);
-          (void)hipEventRecord(e0, s);
-          enqueue_eval(h, s, false, false);
-          (void)hipEventRecord(e1, s);
-          (void)hipEventSynchronize(e1);
-          float m = 0;
-          (void)hipEventElapsedTime(&m, e0, e1);
-          if (rep > 0) ms += m;
+  for (int ncc : ncc_list)
+    for (int cg : ci_list)
+      for (int cq : ci_list)
+        for (int dp = 0; dp < 4; ++dp) {
+          if (h->NQ == 0 && (cq != ci_list[0] || dp > 1)) continue;
+          gcme_tuning t{ncc, cg, cq, -1, dp};
+          if (gcme_set_tuning(h, &t) != GCME_OK) continue;
+          if (build_plan(h) != GCME_OK) continue;
+          float ms = 0;
+          for (int rep = 0; rep < 3; ++rep) {
+            launch_fill_i64(s, h->F.as<long long>(), 0, 3LL * h->N);
+            (void)hipEventRecord(e0, s);
+            enqueue_eval(h, s, false, false);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float m = 0;
+            (void)hipEventElapsedTime(&m, e0, e1);
+            if (rep > 0) ms += m;
+          }
+          if (ms < best_t) {
+            best_t = ms;
+            best = t;
+          }
         }
-        if (ms < best_t) {
-          best_t = ms;
-          best = t;
-        }
-      }
-    }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   gcme_set_tuning(h, &best);

@@ -169,6 +169,7 @@ struct PairLaunch {
   const int2* cl;
   int ncl;
   int ci;              // beads per cluster (2, 4, 8)
+  int direct;          // 1: list-free kernel (no list build, no list)
   int cap;             // list entries per cluster
   uint32_t* list;      // [ncl][cap] population indices
   int* count;          // [ncl] entries used

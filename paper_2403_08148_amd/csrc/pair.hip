@@ -108,117 +108,117 @@ __device__ inline long long to_fixed(double f, double scale, unsigned int* statu
 }
 
 // ---------------------------------------------------------------------------
-// List build
+// Candidate enumeration, shared by the list build and the list-free kernel
 // ---------------------------------------------------------------------------
 
+// A cluster as wave-uniform values.  Its geometry is kept in float relative
+// to the lower corner of bead 0's cell: every value is a few cells at most,
+// so float carries it to ~1e-7 of a cell, and the margin in rclm keeps each
+// cell range conservative.
 template <int CI>
-__global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
-  __shared__ int s_sb[NL_WAVES][NL_SEG];
-  __shared__ int s_sl[NL_WAVES][NL_SEG];
-  __shared__ int s_cand[NL_WAVES][NL_CAND];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * NL_WAVES + wave;
-  if (c >= a.ncl) return;  // whole wavefront; no block barriers below
-  const int2 info = a.cl[c];
-  const int first = info.x, rep = info.y & 0xffff, ni = info.y >> 16;
-  const RepDesc& R = a.rep[rep];
-  const int* __restrict__ start = a.start;
-  const uint4* __restrict__ pk = a.pk;
+struct Cluster {
+  uint32_t ux[CI], uy[CI], uz[CI];  // fixed-point positions (slots beyond ni repeat bead 0)
+  float rx[CI], ry[CI], rz[CI];     // positions relative to bead 0
+  float lo[3], hi[3];               // bounding box relative to bead 0
+  int c0[3];                        // cell of bead 0
+  float p0[3];                      // bead 0 within its cell
+  float h[3], ih[3];                // cell edges and their inverses
+  float rcl;                        // list cutoff, a hair above rc
+  float rclm;                       // enumeration radius: rcl plus a margin
+  int clo[3], chi[3];               // cell ranges relative to c0 (absolute when whole)
+  bool whole[3];                    // the range spans the whole axis
+};
 
-  // cluster beads, as wave-uniform values (slots beyond ni repeat bead 0)
-  const int mine = first + (lane < ni ? lane : 0);
-  const uint4 me = pk[mine];
-  const uint32_t ux = me.x, uy = me.y, uz = me.z;
-  uint32_t cxs[CI], cys[CI], czs[CI];
+template <int CI>
+__device__ inline void load_cluster(Cluster<CI>& K, const uint4* __restrict__ pk, int first, int ni,
+                                    const RepDesc& R) {
+  const int lane = threadIdx.x & 63;
+  const uint4 me = pk[first + (lane < ni ? lane : 0)];
 #pragma unroll
   for (int k = 0; k < CI; ++k) {
-    cxs[k] = read_lane(ux, k);
-    cys[k] = read_lane(uy, k);
-    czs[k] = read_lane(uz, k);
+    K.ux[k] = read_lane(me.x, k);
+    K.uy[k] = read_lane(me.y, k);
+    K.uz[k] = read_lane(me.z, k);
   }
-  // Cluster geometry in float, relative to the lower corner of bead 0's cell:
-  // every value is a few cells at most, so float carries it to ~1e-7 of a
-  // cell, and the margin dl keeps each cell range conservative.
-  float rfx[CI], rfy[CI], rfz[CI];
 #pragma unroll
   for (int k = 0; k < CI; ++k) {
-    rfx[k] = (float)(int)(cxs[k] - cxs[0]) * R.scalef[0];
-    rfy[k] = (float)(int)(cys[k] - cys[0]) * R.scalef[1];
-    rfz[k] = (float)(int)(czs[k] - czs[0]) * R.scalef[2];
+    K.rx[k] = (float)(int)(K.ux[k] - K.ux[0]) * R.scalef[0];
+    K.ry[k] = (float)(int)(K.uy[k] - K.uy[0]) * R.scalef[1];
+    K.rz[k] = (float)(int)(K.uz[k] - K.uz[0]) * R.scalef[2];
   }
-  float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) K.lo[k] = K.hi[k] = 0.f;
 #pragma unroll
   for (int k = 1; k < CI; ++k) {
-    lo[0] = fminf(lo[0], rfx[k]);
-    hi[0] = fmaxf(hi[0], rfx[k]);
-    lo[1] = fminf(lo[1], rfy[k]);
-    hi[1] = fmaxf(hi[1], rfy[k]);
-    lo[2] = fminf(lo[2], rfz[k]);
-    hi[2] = fmaxf(hi[2], rfz[k]);
+    K.lo[0] = fminf(K.lo[0], K.rx[k]);
+    K.hi[0] = fmaxf(K.hi[0], K.rx[k]);
+    K.lo[1] = fminf(K.lo[1], K.ry[k]);
+    K.hi[1] = fmaxf(K.hi[1], K.ry[k]);
+    K.lo[2] = fminf(K.lo[2], K.rz[k]);
+    K.hi[2] = fmaxf(K.hi[2], K.rz[k]);
   }
-  const uint32_t u0[3] = {cxs[0], cys[0], czs[0]};
-  int c0[3];
-  float p0[3], h[3], ih[3];
+  const uint32_t u0[3] = {K.ux[0], K.uy[0], K.uz[0]};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const unsigned long long pp = (unsigned long long)u0[k] * (unsigned)R.nc[k];
-    c0[k] = (int)(pp >> 32);
-    h[k] = R.hf[k];
-    ih[k] = 1.0f / h[k];
-    p0[k] = (float)(uint32_t)(pp & 0xffffffffu) * 2.3283064365386963e-10f * h[k];
+    K.c0[k] = (int)(pp >> 32);
+    K.h[k] = R.hf[k];
+    K.ih[k] = 1.0f / K.h[k];
+    K.p0[k] = (float)(uint32_t)(pp & 0xffffffffu) * 2.3283064365386963e-10f * K.h[k];
   }
-  // list cutoff: a hair above rc, so the float test below never drops a pair
-  // the force kernel's own test (in its precision) would keep
-  const float rcl = (float)(R.rc * (1.0 + 1e-5));
-  const float rcl2f = rcl * rcl;
-  const float dl = 1e-4f * fmaxf(h[0], fmaxf(h[1], h[2]));
-  const float rclm = rcl + dl;
-  int clo[3], chi[3];  // cell ranges relative to c0 (absolute when whole)
-  bool whole[3];
+  // the float list test with rcl never drops a pair that the pair kernels'
+  // own test (in their precision) keeps
+  K.rcl = (float)(R.rc * (1.0 + 1e-5));
+  K.rclm = K.rcl + 1e-4f * fmaxf(K.h[0], fmaxf(K.h[1], K.h[2]));
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    clo[k] = (int)floorf((p0[k] + lo[k] - rclm) * ih[k]);
-    chi[k] = (int)floorf((p0[k] + hi[k] + rclm) * ih[k]);
-    whole[k] = chi[k] - clo[k] + 1 >= R.nc[k];
-    if (whole[k]) {
-      clo[k] = 0;
-      chi[k] = R.nc[k] - 1;
+    K.clo[k] = (int)floorf((K.p0[k] + K.lo[k] - K.rclm) * K.ih[k]);
+    K.chi[k] = (int)floorf((K.p0[k] + K.hi[k] + K.rclm) * K.ih[k]);
+    K.whole[k] = K.chi[k] - K.clo[k] + 1 >= R.nc[k];
+    if (K.whole[k]) {
+      K.clo[k] = 0;
+      K.chi[k] = R.nc[k] - 1;
     }
   }
-  // In the frame of bead 0, separations equal the per-pair minimum image for
-  // every pair within rc as long as each cluster bead lies within L/2 - rc of
-  // bead 0 on each axis (then |d| < rc cannot wrap); otherwise the test
-  // takes the minimum image of each pair.
-  bool frame = true;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) frame = frame && fmaxf(-lo[k], hi[k]) < 0.5f * (float)R.L[k] - rclm;
-  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
-  const int ncx = chi[0] - clo[0] + 1, ncy = chi[1] - clo[1] + 1;
-  const int ncol = ncx * ncy;
-  const float sx = R.scalef[0], sy = R.scalef[1], sz = R.scalef[2];
-  uint32_t* __restrict__ out = a.list + (size_t)c * a.cap;
-  int nent = 0;
+}
 
+// Every bead of the cells within reach of the cluster: the columns whose
+// distance to the cluster's box is below rclm, each with its z run clipped to
+// the sphere of radius rclm around the box.  The beads are handed over in
+// rounds: a round leaves up to NL_CAND bead indices in cand[0, total) and
+// calls visit(total).  Wavefront-level only (no block barriers); seg_b and
+// seg_l are the wavefront's NL_SEG-entry segment scratch.
+template <int CI, class V>
+__device__ inline void for_candidates(const Cluster<CI>& K, const RepDesc& R, const int* __restrict__ start,
+                                      int* seg_b, int* seg_l, int* cand, V&& visit) {
+  const int lane = threadIdx.x & 63;
+  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
+  const int ncx = K.chi[0] - K.clo[0] + 1, ncy = K.chi[1] - K.clo[1] + 1;
+  const int ncol = ncx * ncy;
+  const float rclm2 = K.rclm * K.rclm;
   for (int cbase = 0; cbase < ncol; cbase += 64) {
     // 1. this lane's column: culled, z run clipped, as up to two bead ranges
     int b0[2] = {0, 0}, ln[2] = {0, 0};
     const int k = cbase + lane;
     if (k < ncol) {
-      const int rx = clo[0] + k / ncy, ry = clo[1] + k % ncy;
-      // distance from the column to the bounding box in x and y
-      const float gx = whole[0] ? 0.f : fmaxf(0.f, fmaxf(rx * h[0] - (p0[0] + hi[0]), (p0[0] + lo[0]) - (rx + 1) * h[0]));
-      const float gy = whole[1] ? 0.f : fmaxf(0.f, fmaxf(ry * h[1] - (p0[1] + hi[1]), (p0[1] + lo[1]) - (ry + 1) * h[1]));
+      const int rx = K.clo[0] + k / ncy, ry = K.clo[1] + k % ncy;
+      const float gx = K.whole[0] ? 0.f
+                                  : fmaxf(0.f, fmaxf(rx * K.h[0] - (K.p0[0] + K.hi[0]),
+                                                     (K.p0[0] + K.lo[0]) - (rx + 1) * K.h[0]));
+      const float gy = K.whole[1] ? 0.f
+                                  : fmaxf(0.f, fmaxf(ry * K.h[1] - (K.p0[1] + K.hi[1]),
+                                                     (K.p0[1] + K.lo[1]) - (ry + 1) * K.h[1]));
       const float d2 = gx * gx + gy * gy;
-      if (d2 < rclm * rclm) {
-        int cx = whole[0] ? rx : c0[0] + rx;
-        int cy = whole[1] ? ry : c0[1] + ry;
+      if (d2 < rclm2) {
+        int cx = K.whole[0] ? rx : K.c0[0] + rx;
+        int cy = K.whole[1] ? ry : K.c0[1] + ry;
         cx += cx < 0 ? nx : (cx >= nx ? -nx : 0);
         cy += cy < 0 ? ny : (cy >= ny ? -ny : 0);
         int zlo = 0, zhi = nz - 1;
-        if (!whole[2]) {
-          const float zr = sqrtf(rclm * rclm - d2);
-          zlo = c0[2] + (int)floorf((p0[2] + lo[2] - zr) * ih[2]);
-          zhi = c0[2] + (int)floorf((p0[2] + hi[2] + zr) * ih[2]);
+        if (!K.whole[2]) {
+          const float zr = sqrtf(rclm2 - d2);
+          zlo = K.c0[2] + (int)floorf((K.p0[2] + K.lo[2] - zr) * K.ih[2]);
+          zhi = K.c0[2] + (int)floorf((K.p0[2] + K.hi[2] + zr) * K.ih[2]);
           if (zhi - zlo + 1 >= nz) {
             zlo = 0;
             zhi = nz - 1;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
         }
       }
     }
-    // 2. compact the non-empty ranges into the wave's LDS segment list
+    // 2. compact the non-empty ranges into the segment list
     int nseg = 0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -249,21 +249,21 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
       const unsigned long long m = __ballot(has);
       if (has) {
         const int p = nseg + lanes_below(m);
-        s_sb[wave][p] = b0[q];
-        s_sl[wave][p] = ln[q];
+        seg_b[p] = b0[q];
+        seg_l[p] = ln[q];
       }
       nseg += __popcll(m);
     }
     __builtin_amdgcn_wave_barrier();
     // 3. expand segments into the candidate buffer (a segment too long for
-    //    the room left is split across rounds), then test the candidates
+    //    the room left is split across rounds), then visit the round
     int sn = 0, soff = 0;
     while (sn < nseg) {
       const int s = sn + lane;
       int sb = 0, sl = 0;
       if (s < nseg) {
-        sb = s_sb[wave][s];
-        sl = s_sl[wave][s];
+        sb = seg_b[s];
+        sl = seg_l[s];
         if (lane == 0) {
           sb += soff;
           sl -= soff;
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
       const int take = max(0, min(sl, NL_CAND - exc));
       const int mt = wave_max(take);
       for (int t = 0; t < mt; ++t)
-        if (t < take) s_cand[wave][exc + t] = sb + t;
+        if (t < take) cand[exc + t] = sb + t;
       const int total = min((int)read_lane((uint32_t)inc, 63), NL_CAND);
       const unsigned long long partial = __ballot(take < sl);
       if (partial == 0ull) {
@@ -287,51 +287,86 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
         sn += f;
       }
       __builtin_amdgcn_wave_barrier();
-      // test one candidate per lane against every cluster bead; hits are
-      // appended in candidate order
-      auto test = [&](const uint4 pj, bool v, int j) {
-        bool hit = false;
-        if (frame) {
-          // candidate relative to bead 0 once, then one subtraction per bead
-          const float Dx = (float)(int)(pj.x - cxs[0]) * sx;
-          const float Dy = (float)(int)(pj.y - cys[0]) * sy;
-          const float Dz = (float)(int)(pj.z - czs[0]) * sz;
-#pragma unroll
-          for (int i = 0; i < CI; ++i) {
-            const float dx = Dx - rfx[i], dy = Dy - rfy[i], dz = Dz - rfz[i];
-            hit |= dx * dx + dy * dy + dz * dz < rcl2f;
-          }
-        } else {
-#pragma unroll
-          for (int i = 0; i < CI; ++i) {
-            const float dx = (float)(int)(cxs[i] - pj.x) * sx;
-            const float dy = (float)(int)(cys[i] - pj.y) * sy;
-            const float dz = (float)(int)(czs[i] - pj.z) * sz;
-            hit |= dx * dx + dy * dy + dz * dz < rcl2f;
-          }
-        }
-        hit = hit && v;
-        const unsigned long long m = __ballot(hit);
-        if (hit) {
-          const int idx = nent + lanes_below(m);
-          if (idx < a.cap) out[idx] = (uint32_t)j;
-        }
-        nent += __popcll(m);
-      };
-      // two chunks per round, their loads issued together
-      for (int p = 0; p < total; p += 128) {
-        const int q0 = p + lane, q1 = p + 64 + lane;
-        const bool v0 = q0 < total, v1 = q1 < total;
-        const int j0 = v0 ? s_cand[wave][q0] : first;
-        const int j1 = v1 ? s_cand[wave][q1] : first;
-        const uint4 p0 = pk[j0];
-        const uint4 p1 = pk[j1];
-        test(p0, v0, j0);
-        if (p + 64 < total) test(p1, v1, j1);
-      }
+      visit(total);
       __builtin_amdgcn_wave_barrier();
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// List build
+// ---------------------------------------------------------------------------
+
+template <int CI>
+__global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
+  __shared__ int s_sb[NL_WAVES][NL_SEG];
+  __shared__ int s_sl[NL_WAVES][NL_SEG];
+  __shared__ int s_cand[NL_WAVES][NL_CAND];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * NL_WAVES + wave;
+  if (c >= a.ncl) return;  // whole wavefront; no block barriers below
+  const int2 info = a.cl[c];
+  const int first = info.x, rep = info.y & 0xffff, ni = info.y >> 16;
+  const RepDesc& R = a.rep[rep];
+  const uint4* __restrict__ pk = a.pk;
+  Cluster<CI> K;
+  load_cluster(K, pk, first, ni, R);
+  const float rcl2f = K.rcl * K.rcl;
+  // In the frame of bead 0, separations equal the per-pair minimum image for
+  // every pair within rc as long as each cluster bead lies within L/2 - rc of
+  // bead 0 on each axis (then |d| < rc cannot wrap); otherwise the test
+  // takes the minimum image of each pair.
+  bool frame = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) frame = frame && fmaxf(-K.lo[k], K.hi[k]) < 0.5f * (float)R.L[k] - K.rclm;
+  const float sx = R.scalef[0], sy = R.scalef[1], sz = R.scalef[2];
+  uint32_t* __restrict__ out = a.list + (size_t)c * a.cap;
+  int nent = 0;
+  // test one candidate per lane against every cluster bead; hits are
+  // appended in candidate order
+  auto test = [&](const uint4 pj, bool v, int j) {
+    bool hit = false;
+    if (frame) {
+      // candidate relative to bead 0 once, then one subtraction per bead
+      const float Dx = (float)(int)(pj.x - K.ux[0]) * sx;
+      const float Dy = (float)(int)(pj.y - K.uy[0]) * sy;
+      const float Dz = (float)(int)(pj.z - K.uz[0]) * sz;
+#pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        const float dx = Dx - K.rx[i], dy = Dy - K.ry[i], dz = Dz - K.rz[i];
+        hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        const float dx = (float)(int)(K.ux[i] - pj.x) * sx;
+        const float dy = (float)(int)(K.uy[i] - pj.y) * sy;
+        const float dz = (float)(int)(K.uz[i] - pj.z) * sz;
+        hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+      }
+    }
+    hit = hit && v;
+    const unsigned long long m = __ballot(hit);
+    if (hit) {
+      const int idx = nent + lanes_below(m);
+      if (idx < a.cap) out[idx] = (uint32_t)j;
+    }
+    nent += __popcll(m);
+  };
+  const int* cand = s_cand[wave];
+  for_candidates(K, R, a.start, s_sb[wave], s_sl[wave], s_cand[wave], [&](int total) {
+    // two chunks per pass, their loads issued together
+    for (int p = 0; p < total; p += 128) {
+      const int q0 = p + lane, q1 = p + 64 + lane;
+      const bool v0 = q0 < total, v1 = q1 < total;
+      const int j0 = v0 ? cand[q0] : first;
+      const int j1 = v1 ? cand[q1] : first;
+      const uint4 p0 = pk[j0];
+      const uint4 p1 = pk[j1];
+      test(p0, v0, j0);
+      if (p + 64 < total) test(p1, v1, j1);
+    }
+  });
   if (lane == 0) {
     a.count[c] = min(nent, a.cap);
     if (nent > a.cap) atomicOr(a.status, (unsigned)STATUS_LIST_OVERFLOW);
@@ -453,87 +488,89 @@ __device__ inline void flush_adj(Lane<T>& L, int ti) {
   L.di = 0;
 }
 
-template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
-__global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
-  constexpr int CJ = 64 / CI;
-  __shared__ double red[NL_WAVES];
-  // the replica's type-pair tables, staged once per workgroup
-  __shared__ GcmPar<T> s_g[ELEC ? 1 : MAXT * MAXT];
-  __shared__ ElecPar<T> s_e[ELEC ? MAXT * MAXT : 1];
-  __shared__ AdjPar<T> s_a[ADJ ? MAXT * MAXT : 1];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const Tile tl = a.tiles[blockIdx.x];
-  const RepDesc& R = a.rep[tl.rep];
-  {
-    const size_t tb = (size_t)tl.rep * MAXT * MAXT;
-    if (!ELEC && threadIdx.x < MAXT * MAXT) s_g[threadIdx.x] = reinterpret_cast<const GcmPar<T>*>(a.gcm)[tb + threadIdx.x];
-    if (ELEC && threadIdx.x < MAXT * MAXT) s_e[threadIdx.x] = reinterpret_cast<const ElecPar<T>*>(a.elec)[tb + threadIdx.x];
-    if (ADJ && threadIdx.x < MAXT * MAXT) s_a[threadIdx.x] = reinterpret_cast<const AdjPar<T>*>(a.adj)[tb + threadIdx.x];
-    __syncthreads();
-  }
-  const int il = lane / CJ, jl = lane % CJ;
-  Lane<T> L;
-  lane_zero(L);
-  if (wave < tl.count) {
-    const int c = tl.first + wave;
-    const int2 info = a.cl[c];
-    const int first = info.x, ni = info.y >> 16;
-    const bool vi = il < ni;
-    const int i = first + (vi ? il : 0);
-    const uint4 mi = a.pk[i];
-    const uint32_t pi = mi.w;
-    const int ti = param_type(pi);
-    const T zi = (T)param_z(pi);
-    const GcmPar<T>* grow = s_g + (ELEC ? 0 : ti * MAXT);
-    const ElecPar<T>* erow = s_e + (ELEC ? ti * MAXT : 0);
-    const AdjPar<T>* arow = s_a + (ADJ ? ti * MAXT : 0);
-    const T sx = (T)R.scaled[0], sy = (T)R.scaled[1], sz = (T)R.scaled[2];
-    const T rc2 = (T)R.rc2;
-    const T beta = (T)R.beta, beta2 = (T)(R.beta * R.beta), lB = (T)R.lB;
-    const int cnt = a.count[c];
-    const uint32_t* __restrict__ lst = a.list + (size_t)c * a.cap;
-    const uint4* __restrict__ pk = a.pk;
-    // NU entries per lane per round: the list loads, then the dependent
-    // bead-record loads, are issued back to back so one memory latency
-    // covers NU pairs
-    constexpr int NU = 4;
-    for (int e0 = jl; e0 < cnt; e0 += NU * CJ) {
-      int jj[NU];
-      uint4 pp[NU];
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int e = e0 + u * CJ;
-        jj[u] = e < cnt ? (int)lst[e] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < NU; ++u) pp[u] = pk[jj[u] < 0 ? i : jj[u]];
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const uint4 pj = pp[u];
-        const T dx = (T)(int)(mi.x - pj.x) * sx;
-        const T dy = (T)(int)(mi.y - pj.y) * sy;
-        const T dz = (T)(int)(mi.z - pj.z) * sz;
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        if (vi && jj[u] >= 0 && r2 < rc2 && jj[u] != i)
-          interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pj.w, grow, erow, arow, zi, beta, beta2, lB);
-      }
-    }
-    if (ADJ && vi) flush_adj<T, ELEC>(L, ti);
-    T fx = L.fx, fy = L.fy, fz = L.fz;
-#pragma unroll
-    for (int o = CJ >> 1; o > 0; o >>= 1) {
-      fx += __shfl_xor(fx, o, 64);
-      fy += __shfl_xor(fy, o, 64);
-      fz += __shfl_xor(fz, o, 64);
-    }
-    if (vi && jl == 0) {
-      const int fi = ELEC ? a.qidx[i] : i;
-      atomicAdd((unsigned long long*)&a.F[0][fi], (unsigned long long)to_fixed((double)fx, a.fscale, a.status));
-      atomicAdd((unsigned long long*)&a.F[1][fi], (unsigned long long)to_fixed((double)fy, a.fscale, a.status));
-      atomicAdd((unsigned long long*)&a.F[2][fi], (unsigned long long)to_fixed((double)fz, a.fscale, a.status));
-    }
-  }
+// What a lane needs to evaluate the pairs of its bead i.
+template <typename T>
+struct PairCtx {
+  T sx, sy, sz, rc2, beta, beta2, lB, zi;
+  const GcmPar<T>* grow;
+  const ElecPar<T>* erow;
+  const AdjPar<T>* arow;
+};
 
+// The replica's type-pair tables, staged once per workgroup.
+template <typename T, bool ELEC, bool ADJ>
+struct Tables {
+  GcmPar<T> g[ELEC ? 1 : MAXT * MAXT];
+  ElecPar<T> e[ELEC ? MAXT * MAXT : 1];
+  AdjPar<T> a[ADJ ? MAXT * MAXT : 1];
+};
+
+template <typename T, bool ELEC, bool ADJ>
+__device__ inline void stage_tables(Tables<T, ELEC, ADJ>& S, const PairLaunch& a, int rep) {
+  const size_t tb = (size_t)rep * MAXT * MAXT;
+  if (!ELEC && threadIdx.x < MAXT * MAXT) S.g[threadIdx.x] = reinterpret_cast<const GcmPar<T>*>(a.gcm)[tb + threadIdx.x];
+  if (ELEC && threadIdx.x < MAXT * MAXT) S.e[threadIdx.x] = reinterpret_cast<const ElecPar<T>*>(a.elec)[tb + threadIdx.x];
+  if (ADJ && threadIdx.x < MAXT * MAXT) S.a[threadIdx.x] = reinterpret_cast<const AdjPar<T>*>(a.adj)[tb + threadIdx.x];
+  __syncthreads();
+}
+
+template <typename T, bool ELEC, bool ADJ>
+__device__ inline PairCtx<T> make_ctx(const Tables<T, ELEC, ADJ>& S, const RepDesc& R, uint32_t pi) {
+  const int ti = param_type(pi);
+  PairCtx<T> P;
+  P.sx = (T)R.scaled[0];
+  P.sy = (T)R.scaled[1];
+  P.sz = (T)R.scaled[2];
+  P.rc2 = (T)R.rc2;
+  P.beta = (T)R.beta;
+  P.beta2 = (T)(R.beta * R.beta);
+  P.lB = (T)R.lB;
+  P.zi = (T)param_z(pi);
+  P.grow = S.g + (ELEC ? 0 : ti * MAXT);
+  P.erow = S.e + (ELEC ? ti * MAXT : 0);
+  P.arow = S.a + (ADJ ? ti * MAXT : 0);
+  return P;
+}
+
+// Pair (i, j) when ok (j a real bead other than i) and r < rc: separation by
+// the exact minimum image in T, the one cutoff test of the method's sums.
+template <typename T, bool ELEC, bool EV, bool ADJ, bool COUNT>
+__device__ inline void try_pair(Lane<T>& L, const PairCtx<T>& P, const uint4& mi, const uint4& pj, bool ok) {
+  const T dx = (T)(int)(mi.x - pj.x) * P.sx;
+  const T dy = (T)(int)(mi.y - pj.y) * P.sy;
+  const T dz = (T)(int)(mi.z - pj.z) * P.sz;
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  if (ok && r2 < P.rc2)
+    interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pj.w, P.grow, P.erow, P.arow, P.zi, P.beta, P.beta2, P.lB);
+}
+
+// Combine the partial forces of bead i over its CJ lanes (xor shuffles, fixed
+// order) and add them once to the fixed-point accumulator.
+template <typename T, int CI, bool ELEC, bool ADJ>
+__device__ inline void flush_bead(const PairLaunch& a, Lane<T>& L, bool vi, int i, int ti) {
+  constexpr int CJ = 64 / CI;
+  const int jl = (threadIdx.x & 63) % CJ;
+  if (ADJ && vi) flush_adj<T, ELEC>(L, ti);
+  T fx = L.fx, fy = L.fy, fz = L.fz;
+#pragma unroll
+  for (int o = CJ >> 1; o > 0; o >>= 1) {
+    fx += __shfl_xor(fx, o, 64);
+    fy += __shfl_xor(fy, o, 64);
+    fz += __shfl_xor(fz, o, 64);
+  }
+  if (vi && jl == 0) {
+    const int fi = ELEC ? a.qidx[i] : i;
+    atomicAdd((unsigned long long*)&a.F[0][fi], (unsigned long long)to_fixed((double)fx, a.fscale, a.status));
+    atomicAdd((unsigned long long*)&a.F[1][fi], (unsigned long long)to_fixed((double)fy, a.fscale, a.status));
+    atomicAdd((unsigned long long*)&a.F[2][fi], (unsigned long long)to_fixed((double)fz, a.fscale, a.status));
+  }
+}
+
+// Workgroup partial sums (every pair was seen from both ends: halved).
+// Reached by every thread of the workgroup.
+template <typename T, bool ELEC, bool EV, bool ADJ, bool COUNT>
+__device__ inline void block_outputs(const PairLaunch& a, const Lane<T>& L, double* red) {
+  const int lane = threadIdx.x & 63;
   if (COUNT) {
     unsigned long long cc = L.cnt;
     for (int o = 32; o > 0; o >>= 1) cc += __shfl_xor(cc, o, 64);
@@ -562,17 +599,127 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
   }
 }
 
+// List-driven pairs: one wavefront per cluster, lanes = CI beads x 64/CI
+// list entries.
+template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
+__global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
+  constexpr int CJ = 64 / CI;
+  __shared__ double red[NL_WAVES];
+  __shared__ Tables<T, ELEC, ADJ> S;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const Tile tl = a.tiles[blockIdx.x];
+  const RepDesc& R = a.rep[tl.rep];
+  stage_tables(S, a, tl.rep);
+  const int il = lane / CJ, jl = lane % CJ;
+  Lane<T> L;
+  lane_zero(L);
+  if (wave < tl.count) {
+    const int c = tl.first + wave;
+    const int2 info = a.cl[c];
+    const int first = info.x, ni = info.y >> 16;
+    const bool vi = il < ni;
+    const int i = first + (vi ? il : 0);
+    const uint4 mi = a.pk[i];
+    const PairCtx<T> P = make_ctx(S, R, mi.w);
+    const int cnt = a.count[c];
+    const uint32_t* __restrict__ lst = a.list + (size_t)c * a.cap;
+    const uint4* __restrict__ pk = a.pk;
+    // NU entries per lane per round: the list loads, then the dependent
+    // bead-record loads, are issued back to back so one memory latency
+    // covers NU pairs
+    constexpr int NU = 4;
+    for (int e0 = jl; e0 < cnt; e0 += NU * CJ) {
+      int jj[NU];
+      uint4 pp[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int e = e0 + u * CJ;
+        jj[u] = e < cnt ? (int)lst[e] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < NU; ++u) pp[u] = pk[jj[u] < 0 ? i : jj[u]];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[u], vi && jj[u] >= 0 && jj[u] != i);
+    }
+    flush_bead<T, CI, ELEC, ADJ>(a, L, vi, i, param_type(mi.w));
+  }
+  block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red);
+}
+
+// List-free pairs: one wavefront per cluster enumerates the candidates of
+// its cells (as the list build does) and evaluates them at once, lanes = CI
+// beads x 64/CI candidates.  Same pairs and cutoff test as the list path; no
+// list written or read, at the price of evaluating the pair test for every
+// candidate of the cluster's cell columns instead of the union of its
+// beads' cutoff spheres.
+template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
+__global__ __launch_bounds__(NL_WAVES * 64) void k_pair_direct(PairLaunch a) {
+  constexpr int CJ = 64 / CI;
+  __shared__ double red[NL_WAVES];
+  __shared__ Tables<T, ELEC, ADJ> S;
+  __shared__ int s_sb[NL_WAVES][NL_SEG];
+  __shared__ int s_sl[NL_WAVES][NL_SEG];
+  __shared__ int s_cand[NL_WAVES][NL_CAND];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const Tile tl = a.tiles[blockIdx.x];
+  const RepDesc& R = a.rep[tl.rep];
+  stage_tables(S, a, tl.rep);
+  const int il = lane / CJ, jl = lane % CJ;
+  Lane<T> L;
+  lane_zero(L);
+  if (wave < tl.count) {
+    const int c = tl.first + wave;
+    const int2 info = a.cl[c];
+    const int first = info.x, ni = info.y >> 16;
+    const uint4* __restrict__ pk = a.pk;
+    Cluster<CI> K;
+    load_cluster(K, pk, first, ni, R);
+    const bool vi = il < ni;
+    const int i = first + (vi ? il : 0);
+    const uint4 mi = pk[i];
+    const PairCtx<T> P = make_ctx(S, R, mi.w);
+    const int* cand = s_cand[wave];
+    for_candidates(K, R, a.start, s_sb[wave], s_sl[wave], s_cand[wave], [&](int total) {
+      constexpr int NU = 4;
+      for (int q0 = jl; q0 < total; q0 += NU * CJ) {
+        int jj[NU];
+        uint4 pp[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int q = q0 + u * CJ;
+          jj[u] = q < total ? cand[q] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) pp[u] = pk[jj[u] < 0 ? i : jj[u]];
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+          try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[u], vi && jj[u] >= 0 && jj[u] != i);
+      }
+    });
+    flush_bead<T, CI, ELEC, ADJ>(a, L, vi, i, param_type(mi.w));
+  }
+  block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red);
+}
+
+template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
+void launch_one(hipStream_t s, const PairLaunch& a) {
+  dim3 g(a.ntiles), b(NL_WAVES * 64);
+  if (a.direct)
+    hipLaunchKernelGGL((k_pair_direct<T, CI, ELEC, EV, ADJ, COUNT>), g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, EV, ADJ, COUNT>), g, b, 0, s, a);
+}
+
 template <typename T, int CI, bool ELEC>
 void dispatch_mode(hipStream_t s, const PairLaunch& a, bool ev, bool adj, bool count) {
-  dim3 g(a.ntiles), b(NL_WAVES * 64);
   if (count)
-    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, false, false, true>), g, b, 0, s, a);
+    launch_one<T, CI, ELEC, false, false, true>(s, a);
   else if (adj)
-    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, true, true, false>), g, b, 0, s, a);
+    launch_one<T, CI, ELEC, true, true, false>(s, a);
   else if (ev)
-    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, true, false, false>), g, b, 0, s, a);
+    launch_one<T, CI, ELEC, true, false, false>(s, a);
   else
-    hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, false, false, false>), g, b, 0, s, a);
+    launch_one<T, CI, ELEC, false, false, false>(s, a);
 }
 
 template <typename T, bool ELEC>
@@ -587,7 +734,7 @@ void dispatch_ci(hipStream_t s, const PairLaunch& a, bool ev, bool adj, bool cou
 }  // namespace
 
 void launch_nl_build(hipStream_t s, const PairLaunch& a) {
-  if (a.ncl <= 0) return;
+  if (a.ncl <= 0 || a.direct) return;
   dim3 g((a.ncl + NL_WAVES - 1) / NL_WAVES), b(NL_WAVES * 64);
   switch (a.ci) {
     case 2: hipLaunchKernelGGL(k_nl_build<2>, g, b, 0, s, a); break;

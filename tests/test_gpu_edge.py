@@ -25,12 +25,13 @@ def _cmp(got_F, got_E, got_W, ref, ftol, etol):
     assert werr < 10 * max(ftol, etol)
 
 
+@pytest.mark.parametrize("direct", [0, 3])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_small_box_images(precision):
+def test_small_box_images(precision, direct):
     # L = 5.2 with rc = 2.5: the cell stencil wraps onto itself
     w = W.small_bulk(N=350, seed=13, charged_frac=0.4, box=(5.2, 5.3, 5.05), rc=2.5, grid=(16, 16, 16))
-    print(f"case small box {w.box} prec={precision}", flush=True)
-    eng = make_engine([w], precision, tuning=dict(cells_per_cutoff=3))
+    print(f"case small box {w.box} prec={precision} direct_pairs={direct}", flush=True)
+    eng = make_engine([w], precision, tuning=dict(cells_per_cutoff=3, direct_pairs=direct))
     got = gpu_eval(eng)
     eng.close()
     tol = (1e-9, 1e-10) if precision == "fp64" else (1e-5, 1e-6)
@@ -72,6 +73,30 @@ def test_batched_equals_single():
         off += w.N
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_list_free_equals_lists(precision):
+    # Both pair paths visit the same pairs with the same cutoff test; only the
+    # order of the per-bead sums differs.
+    w = W.config2()
+    print(f"case list vs list-free {w.name} N={w.N} prec={precision}", flush=True)
+    got = {}
+    for d in (0, 3):
+        eng = make_engine([w], precision, tuning=dict(cells_per_cutoff=3, beads_per_cluster=4,
+                                                       charges_per_cluster=4, direct_pairs=d))
+        got[d] = gpu_eval(eng)
+        if precision == "mixed":
+            got[d]["pairs"] = eng.count_pairs()
+        eng.close()
+    ftol = 1e-12 if precision == "fp64" else 1e-6
+    ferr = rel_rms(got[3]["force"], got[0]["force"])
+    eerr = np.abs(got[3]["energy"][0, :5] - got[0]["energy"][0, :5]) / np.abs(got[0]["energy"][0, :5]).max()
+    print(f"  list-free vs list: force {ferr:.2e} energy {eerr.max():.2e}", flush=True)
+    assert ferr < ftol
+    assert eerr.max() < ftol
+    if precision == "mixed":
+        assert got[3]["pairs"] == got[0]["pairs"]
+
+
 def test_two_beads():
     w = W.small_bulk(N=2, seed=1, charged_frac=1.0, a_types=(0.5,), box=(6.0, 6.0, 6.0), rc=2.9,
                      grid=(16, 16, 16))
@@ -82,10 +107,12 @@ def test_two_beads():
     _cmp(got["force"], got["energy"][0], got["virial"][0], oracle_eval(w), 1e-9, 1e-10)
 
 
-def test_pair_count_matches_kdtree():
+@pytest.mark.parametrize("direct", [0, 1])
+def test_pair_count_matches_kdtree(direct):
     from scipy.spatial import cKDTree
     w = W.small_bulk(N=3000, seed=21, charged_frac=0.2, box=(10.6, 10.6, 10.7), rc=2.7, grid=(32, 32, 32))
-    eng = make_engine([w], "mixed")
+    print(f"case pair count direct_pairs={direct}", flush=True)
+    eng = make_engine([w], "mixed", tuning=dict(direct_pairs=direct))
     n = eng.count_pairs()
     eng.close()
     tree = cKDTree(np.mod(w.pos, w.box), boxsize=w.box)
@@ -165,11 +192,13 @@ def test_langevin_temperature():
     assert abs(np.mean(Ts) - 1.0) < 0.02
 
 
+@pytest.mark.parametrize("direct", [0, 3])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_adjoint_matches_oracle(precision):
+def test_adjoint_matches_oracle(precision, direct):
     w = W.small_bulk(N=900, seed=7, charged_frac=0.3, a_types=(0.35, 0.55, 0.65), box=(7.1, 7.3, 6.9),
                      rc=2.5, grid=(24, 24, 24))
-    eng = make_engine([w], precision)
+    print(f"case adjoint prec={precision} direct_pairs={direct}", flush=True)
+    eng = make_engine([w], precision, tuning=dict(direct_pairs=direct))
     got = gpu_eval(eng, adjoint=True)
     eng.close()
     ref = oracle_eval(w, adjoint=True)
