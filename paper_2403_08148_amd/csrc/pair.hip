@@ -36,7 +36,9 @@ namespace gcme {
 
 namespace {
 
-__device__ inline float gexp2(float x) { return exp2f(x); }
+// hardware 2^x (1 ulp; results below the smallest normal flush to zero,
+// far below anything the single-precision sums resolve)
+__device__ inline float gexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline double gexp2(double x) { return exp2(x); }
 __device__ inline float gexp(float x) { return expf(x); }
 __device__ inline double gexp(double x) { return exp(x); }
@@ -297,6 +299,47 @@ __device__ inline void for_candidates(const Cluster<CI>& K, const RepDesc& R, co
 // List build
 // ---------------------------------------------------------------------------
 
+// In the frame of bead 0, separations equal the per-pair minimum image for
+// every pair within rc as long as each cluster bead lies within L/2 - rc of
+// bead 0 on each axis (then |d| < rc cannot wrap).
+template <int CI>
+__device__ inline bool in_frame(const Cluster<CI>& K, const RepDesc& R) {
+  bool frame = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) frame = frame && fmaxf(-K.lo[k], K.hi[k]) < 0.5f * (float)R.L[k] - K.rclm;
+  return frame;
+}
+
+// Whether bead record pj lies within the list cutoff of at least one bead of
+// the cluster (float): in bead 0's frame when `frame`, otherwise by the
+// minimum image of each pair.
+template <int CI>
+__device__ inline bool near_cluster(const Cluster<CI>& K, bool frame, const uint4& pj, const RepDesc& R) {
+  const float rcl2f = K.rcl * K.rcl;
+  const float sx = R.scalef[0], sy = R.scalef[1], sz = R.scalef[2];
+  bool hit = false;
+  if (frame) {
+    // candidate relative to bead 0 once, then one subtraction per bead
+    const float Dx = (float)(int)(pj.x - K.ux[0]) * sx;
+    const float Dy = (float)(int)(pj.y - K.uy[0]) * sy;
+    const float Dz = (float)(int)(pj.z - K.uz[0]) * sz;
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+      const float dx = Dx - K.rx[i], dy = Dy - K.ry[i], dz = Dz - K.rz[i];
+      hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+      const float dx = (float)(int)(K.ux[i] - pj.x) * sx;
+      const float dy = (float)(int)(K.uy[i] - pj.y) * sy;
+      const float dz = (float)(int)(K.uz[i] - pj.z) * sz;
+      hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+    }
+  }
+  return hit;
+}
+
 template <int CI>
 __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
   __shared__ int s_sb[NL_WAVES][NL_SEG];
@@ -311,41 +354,12 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
   const uint4* __restrict__ pk = a.pk;
   Cluster<CI> K;
   load_cluster(K, pk, first, ni, R);
-  const float rcl2f = K.rcl * K.rcl;
-  // In the frame of bead 0, separations equal the per-pair minimum image for
-  // every pair within rc as long as each cluster bead lies within L/2 - rc of
-  // bead 0 on each axis (then |d| < rc cannot wrap); otherwise the test
-  // takes the minimum image of each pair.
-  bool frame = true;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) frame = frame && fmaxf(-K.lo[k], K.hi[k]) < 0.5f * (float)R.L[k] - K.rclm;
-  const float sx = R.scalef[0], sy = R.scalef[1], sz = R.scalef[2];
+  const bool frame = in_frame(K, R);
   uint32_t* __restrict__ out = a.list + (size_t)c * a.cap;
   int nent = 0;
-  // test one candidate per lane against every cluster bead; hits are
-  // appended in candidate order
+  // one candidate per lane; hits are appended in candidate order
   auto test = [&](const uint4 pj, bool v, int j) {
-    bool hit = false;
-    if (frame) {
-      // candidate relative to bead 0 once, then one subtraction per bead
-      const float Dx = (float)(int)(pj.x - K.ux[0]) * sx;
-      const float Dy = (float)(int)(pj.y - K.uy[0]) * sy;
-      const float Dz = (float)(int)(pj.z - K.uz[0]) * sz;
-#pragma unroll
-      for (int i = 0; i < CI; ++i) {
-        const float dx = Dx - K.rx[i], dy = Dy - K.ry[i], dz = Dz - K.rz[i];
-        hit |= dx * dx + dy * dy + dz * dz < rcl2f;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < CI; ++i) {
-        const float dx = (float)(int)(K.ux[i] - pj.x) * sx;
-        const float dy = (float)(int)(K.uy[i] - pj.y) * sy;
-        const float dz = (float)(int)(K.uz[i] - pj.z) * sz;
-        hit |= dx * dx + dy * dy + dz * dz < rcl2f;
-      }
-    }
-    hit = hit && v;
+    const bool hit = near_cluster(K, frame, pj, R) && v;
     const unsigned long long m = __ballot(hit);
     if (hit) {
       const int idx = nent + lanes_below(m);
@@ -540,8 +554,32 @@ __device__ inline void try_pair(Lane<T>& L, const PairCtx<T>& P, const uint4& mi
   const T dy = (T)(int)(mi.y - pj.y) * P.sy;
   const T dz = (T)(int)(mi.z - pj.z) * P.sz;
   const T r2 = dx * dx + dy * dy + dz * dz;
-  if (ok && r2 < P.rc2)
+  const bool in = ok && r2 < P.rc2;
+  if (!ELEC && !ADJ && !COUNT) {
+    // excluded volume: cheap enough to evaluate for every lane and mask,
+    // which keeps the unrolled pairs free of branches
+    // (a multiplicative mask: a select of the exponential would be turned
+    // back into a branch around it)
+    const GcmPar<T> g = P.grow[param_type(pj.w)];
+    const T msk = in ? (T)1 : (T)0;
+    const T en = g.C * gexp2(-g.bl * r2) * msk;
+    const T fs = g.twob * en;
+    L.fx += fs * dx;
+    L.fy += fs * dy;
+    L.fz += fs * dz;
+    if (EV) {
+      const double fxd = (double)(fs * dx), fyd = (double)(fs * dy), fzd = (double)(fs * dz);
+      L.e += (double)en;
+      L.w0 += fxd * (double)dx;
+      L.w1 += fyd * (double)dy;
+      L.w2 += fzd * (double)dz;
+      L.w3 += fxd * (double)dy;
+      L.w4 += fxd * (double)dz;
+      L.w5 += fyd * (double)dz;
+    }
+  } else if (in) {
     interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pj.w, P.grow, P.erow, P.arow, P.zi, P.beta, P.beta2, P.lB);
+  }
 }
 
 // Combine the partial forces of bead i over its CJ lanes (xor shuffles, fixed
@@ -647,19 +685,23 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
 }
 
 // List-free pairs: one wavefront per cluster enumerates the candidates of
-// its cells (as the list build does) and evaluates them at once, lanes = CI
-// beads x 64/CI candidates.  Same pairs and cutoff test as the list path; no
-// list written or read, at the price of evaluating the pair test for every
-// candidate of the cluster's cell columns instead of the union of its
-// beads' cutoff spheres.
+// its cell columns (as the list build does), keeps those within the list
+// cutoff of some cluster bead (the list build's test), and evaluates them at
+// once from an LDS ring of pending pairs: whenever 64 are pending they are
+// taken by the lanes laid out as CI beads x 64/CI entries.  The same pairs
+// and cutoff test as the list path, with no list in HBM.
+constexpr int RING = 128;  // pending-pair ring per wavefront (entries)
+static_assert(RING == 128, "the drain relies on a ring of exactly two 64-entry halves");
+
 template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
-__global__ __launch_bounds__(NL_WAVES * 64) void k_pair_direct(PairLaunch a) {
+__global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
   constexpr int CJ = 64 / CI;
   __shared__ double red[NL_WAVES];
   __shared__ Tables<T, ELEC, ADJ> S;
   __shared__ int s_sb[NL_WAVES][NL_SEG];
   __shared__ int s_sl[NL_WAVES][NL_SEG];
   __shared__ int s_cand[NL_WAVES][NL_CAND];
+  __shared__ uint4 s_ring[NL_WAVES][RING];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Tile tl = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[tl.rep];
@@ -674,28 +716,56 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_direct(PairLaunch a) {
     const uint4* __restrict__ pk = a.pk;
     Cluster<CI> K;
     load_cluster(K, pk, first, ni, R);
+    const bool frame = in_frame(K, R);
     const bool vi = il < ni;
     const int i = first + (vi ? il : 0);
     const uint4 mi = pk[i];
     const PairCtx<T> P = make_ctx(S, R, mi.w);
+    // ring records carry, in place of the replica bits, 1 + the cluster slot
+    // of a candidate that is itself a cluster bead (0 otherwise)
+    const uint32_t self = (uint32_t)(il + 1);
+    uint4* ring = s_ring[wave];
+    int head = 0, tail = 0;  // wave-uniform: pairs evaluated / appended
+    // evaluate the n <= 64 pending entries from head: lane (il, jl) takes
+    // entries jl + k CJ, k < CI.  head is a multiple of 64 here (every drain
+    // but the last takes exactly 64), so the entries do not wrap.
+    auto drain = [&](int n) {
+      const uint4* base = ring + (head & 64) + jl;
+      uint4 pp[CI];
+#pragma unroll
+      for (int k = 0; k < CI; ++k) pp[k] = base[k * CJ];
+#pragma unroll
+      for (int k = 0; k < CI; ++k)
+        try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[k], vi && jl + k * CJ < n && (pp[k].w >> 16) != self);
+      head += n;
+    };
+    auto filter = [&](const uint4 pj, bool v, int j) {
+      const bool hit = near_cluster(K, frame, pj, R) && v;
+      const unsigned long long m = __ballot(hit);
+      if (hit) {
+        const uint32_t d = (uint32_t)(j - first);
+        const uint4 r = make_uint4(pj.x, pj.y, pj.z, (pj.w & 0xffffu) | ((d < (uint32_t)ni ? d + 1u : 0u) << 16));
+        ring[(tail + lanes_below(m)) & (RING - 1)] = r;
+      }
+      tail += __popcll(m);
+      __builtin_amdgcn_wave_barrier();
+      if (tail - head >= 64) drain(64);
+    };
     const int* cand = s_cand[wave];
     for_candidates(K, R, a.start, s_sb[wave], s_sl[wave], s_cand[wave], [&](int total) {
-      constexpr int NU = 4;
-      for (int q0 = jl; q0 < total; q0 += NU * CJ) {
-        int jj[NU];
-        uint4 pp[NU];
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int q = q0 + u * CJ;
-          jj[u] = q < total ? cand[q] : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < NU; ++u) pp[u] = pk[jj[u] < 0 ? i : jj[u]];
-#pragma unroll
-        for (int u = 0; u < NU; ++u)
-          try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[u], vi && jj[u] >= 0 && jj[u] != i);
+      // two chunks per pass, their loads issued together
+      for (int p = 0; p < total; p += 128) {
+        const int q0 = p + lane, q1 = p + 64 + lane;
+        const bool v0 = q0 < total, v1 = q1 < total;
+        const int j0 = v0 ? cand[q0] : first;
+        const int j1 = v1 ? cand[q1] : first;
+        const uint4 p0 = pk[j0];
+        const uint4 p1 = pk[j1];
+        filter(p0, v0, j0);
+        if (p + 64 < total) filter(p1, v1, j1);
       }
     });
+    if (tail > head) drain(tail - head);
     flush_bead<T, CI, ELEC, ADJ>(a, L, vi, i, param_type(mi.w));
   }
   block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red);
@@ -705,7 +775,7 @@ template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
 void launch_one(hipStream_t s, const PairLaunch& a) {
   dim3 g(a.ntiles), b(NL_WAVES * 64);
   if (a.direct)
-    hipLaunchKernelGGL((k_pair_direct<T, CI, ELEC, EV, ADJ, COUNT>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_pair_fused<T, CI, ELEC, EV, ADJ, COUNT>), g, b, 0, s, a);
   else
     hipLaunchKernelGGL((k_nl_force<T, CI, ELEC, EV, ADJ, COUNT>), g, b, 0, s, a);
 }
