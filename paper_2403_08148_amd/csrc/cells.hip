@@ -40,22 +40,12 @@ __global__ void k_fill(I* p, I v, long long n) {
   for (; i < n; i += stride) p[i] = v;
 }
 
-__device__ inline int cell_of(const RepDesc& R, uint32_t ux, uint32_t uy, uint32_t uz) {
-  int cx = (int)(((unsigned long long)ux * (unsigned)R.nc[0]) >> 32);
-  int cy = (int)(((unsigned long long)uy * (unsigned)R.nc[1]) >> 32);
-  int cz = (int)(((unsigned long long)uz * (unsigned)R.nc[2]) >> 32);
-  return R.cell_off + (cx * R.nc[1] + cy) * R.nc[2] + cz;
-}
-
 __global__ void k_bin(StateView A, const RepDesc* __restrict__ rep, CellView c, int N) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N) return;
   uint32_t p = A.param[s];
   const RepDesc& R = rep[param_rep(p)];
-  int cid = cell_of(R, A.pos[0][s], A.pos[1][s], A.pos[2][s]);
-  c.cell[s] = cid;
-  atomicAdd(&c.counts[cid], 1);
-  if (param_z(p) != 0) atomicAdd(&c.qcounts[cid], 1);
+  bin_bead(c, R, A.pos[0][s], A.pos[1][s], A.pos[2][s], p, s);
 }
 
 constexpr int SCAN_THREADS = 256;

@@ -145,7 +145,11 @@ struct gcme_ctx {
   int order = 5;
   std::vector<RepDesc> rep;
   // graphs
-  hipGraphExec_t g_plain = nullptr, g_obs = nullptr;
+  //   g_mid: a step after the first half (sort, forces, then the second half
+  //          fused with the next step's first half and binning)
+  //   g_last / g_obs: the same, ending with the plain second half (g_obs also
+  //          accumulates the energy, virial and kinetic partials)
+  hipGraphExec_t g_mid = nullptr, g_last = nullptr, g_obs = nullptr;
 
   ~gcme_ctx() {
     drop_graphs();
@@ -158,9 +162,10 @@ struct gcme_ctx {
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
   void drop_graphs() {
-    if (g_plain) (void)hipGraphExecDestroy(g_plain);
+    if (g_mid) (void)hipGraphExecDestroy(g_mid);
+    if (g_last) (void)hipGraphExecDestroy(g_last);
     if (g_obs) (void)hipGraphExecDestroy(g_obs);
-    g_plain = g_obs = nullptr;
+    g_mid = g_last = g_obs = nullptr;
   }
   double fscale() const { return std::ldexp(1.0, fp64 ? FSHIFT_FP64 : FSHIFT_MIXED); }
   double qscale() const { return std::ldexp(1.0, fp64 ? FSHIFT_FP64 : FSHIFT_MIXED); }
@@ -740,16 +745,18 @@ IntLaunch int_args(gcme_handle h) {
   a.nbeads = h->N;
   a.seed = h->seed;
   a.step = h->d_step.as<unsigned long long>();
+  a.done = reinterpret_cast<unsigned*>(h->d_step.as<char>() + 8);
   a.fscale_inv = 1.0 / h->fscale();
   a.part = h->part[SLOT_KIN].as<double>();
   return a;
 }
 
-// Sort the state A into B by cell (and the charged copy), on stream s.
-void enqueue_sort(gcme_handle h, hipStream_t s) {
+// Sort the state A into B by cell (and the charged copy), on stream s;
+// bin = false when the integrator has already binned A.
+void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
   // counts are left cleared by the previous permute (and at plan build)
   CellView c = cview(h);
-  launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
+  if (bin) launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
   launch_scan(s, c);
   launch_scatter(s, c, h->N);
   launch_permute(s, viewA(h), viewB(h), h->b_pk.as<uint4>(), c, qview(h), h->N);
@@ -770,8 +777,16 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   (void)hipEventRecord(h->ev_fork, s);
   (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
   (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
+  // issue order: the longest single kernels first, so that in a captured
+  // graph (whose nodes are submitted in this order) each branch's first
+  // kernel is queued before the others' later ones
+  launch_nl_build(s, g);
+  launch_pair_gcm(s, g, h->fp64, ev, adj);
+  PairLaunch q = pair_args(h, true);
+  launch_nl_build(h->aux[0], q);
   PmeLaunch p = pme_args(h);
   launch_spread_z(h->aux[1], p, h->fp64);
+  launch_pair_elec(h->aux[0], q, h->fp64, ev, adj);
   if (h->yx_fused) {
     launch_fft_yx_conv(h->aux[1], p, h->fp64, ev);
   } else {
@@ -780,11 +795,6 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
     launch_fft_y(h->aux[1], p, h->fp64, true);
   }
   launch_z_gather(h->aux[1], p, h->fp64);
-  PairLaunch q = pair_args(h, true);
-  launch_nl_build(h->aux[0], q);
-  launch_pair_elec(h->aux[0], q, h->fp64, ev, adj);
-  launch_nl_build(s, g);
-  launch_pair_gcm(s, g, h->fp64, ev, adj);
   (void)hipEventRecord(h->ev_join[0], h->aux[0]);
   (void)hipEventRecord(h->ev_join[1], h->aux[1]);
   (void)hipStreamWaitEvent(s, h->ev_join[0], 0);
@@ -840,22 +850,28 @@ void enqueue_eval(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   enqueue_forces(h, s, ev, adj);
 }
 
-// One step of the integrator (forces of the current state in F, indexed in
-// the order of A): first half (kick, drift, noise, clears F), sort, forces,
-// second half kick written back to A.
-void enqueue_step(gcme_handle h, hipStream_t s, bool ev) {
+// n steps of the integrator (forces of the current state in F, indexed in
+// the order of A) are: the first half of step 1 with the binning of its new
+// positions (kick, drift, noise; clears F), then per step the rest of the
+// sort and the forces, and between steps the second half kick fused with the
+// next first half and binning; the last step ends with the plain second half
+// kick, written back to A.  enqueue_step_rest enqueues all of a step but its
+// first half: `between` selects the fused ending.
+void enqueue_step_rest(gcme_handle h, hipStream_t s, bool between, bool ev) {
   IntLaunch ia = int_args(h);
   long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
-  launch_int_first(s, ia, viewA(h), F3);
-  enqueue_sort(h, s);
+  enqueue_sort(h, s, false);
   enqueue_forces(h, s, ev, false);
-  launch_int_last(s, ia, viewB(h), viewA(h), F3, ev);
+  if (between)
+    launch_int_between(s, ia, viewB(h), viewA(h), F3, cview(h));
+  else
+    launch_int_last(s, ia, viewB(h), viewA(h), F3, ev);
 }
 
-gcme_status capture(gcme_handle h, bool ev, hipGraphExec_t* out) {
+gcme_status capture(gcme_handle h, bool between, bool ev, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-  enqueue_step(h, h->cap_stream, ev);
+  enqueue_step_rest(h, h->cap_stream, between, ev);
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (e != hipSuccess) return fail(h, GCME_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -1158,18 +1174,24 @@ gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe) {
     return GCME_OK;
   }
   bool obs = observe != nullptr;
-  int plain = obs ? n_steps - 1 : n_steps;
-  if (plain > 0 && !h->g_plain) {
-    st = capture(h, false, &h->g_plain);
+  if (n_steps > 1 && !h->g_mid) {
+    st = capture(h, true, false, &h->g_mid);
     if (st != GCME_OK) return st;
   }
-  if (obs && !h->g_obs) {
-    st = capture(h, true, &h->g_obs);
+  hipGraphExec_t* last = obs ? &h->g_obs : &h->g_last;
+  if (!*last) {
+    st = capture(h, false, obs, last);
     if (st != GCME_OK) return st;
   }
-  for (int i = 0; i < plain; ++i) HIPCHK(h, hipGraphLaunch(h->g_plain, h->stream));
+  {
+    IntLaunch ia = int_args(h);
+    long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
+    CellView c = cview(h);
+    launch_int_first(h->stream, ia, viewA(h), F3, &c);
+  }
+  for (int i = 0; i < n_steps - 1; ++i) HIPCHK(h, hipGraphLaunch(h->g_mid, h->stream));
+  HIPCHK(h, hipGraphLaunch(*last, h->stream));
   if (obs) {
-    HIPCHK(h, hipGraphLaunch(h->g_obs, h->stream));
     // the step left A == B (same order); outputs read B and the partials
     enqueue_outputs(h, h->stream, observe, true);
     HIPCHK(h, hipGetLastError());

@@ -137,6 +137,23 @@ struct CellView {
   int ncells;
 };
 
+// Global cell of a position (x-major, then y, then z within a replica).
+__device__ inline int cell_of(const RepDesc& R, uint32_t ux, uint32_t uy, uint32_t uz) {
+  int cx = (int)(((unsigned long long)ux * (unsigned)R.nc[0]) >> 32);
+  int cy = (int)(((unsigned long long)uy * (unsigned)R.nc[1]) >> 32);
+  int cz = (int)(((unsigned long long)uz * (unsigned)R.nc[2]) >> 32);
+  return R.cell_off + (cx * R.nc[1] + cy) * R.nc[2] + cz;
+}
+
+// Record bead s's cell and count it (and, if charged, among the charged).
+__device__ inline void bin_bead(const CellView& c, const RepDesc& R, uint32_t ux, uint32_t uy, uint32_t uz,
+                                uint32_t prm, int s) {
+  const int cid = cell_of(R, ux, uy, uz);
+  c.cell[s] = cid;
+  atomicAdd(&c.counts[cid], 1);
+  if (param_z(prm) != 0) atomicAdd(&c.qcounts[cid], 1);
+}
+
 // Packed copy of a sorted bead: x, y, z (fractional fixed point), param.
 struct ChargedView {
   uint4* pk;         // charged beads in cell order
@@ -242,10 +259,19 @@ struct IntLaunch {
   unsigned long long* step; // device counter: step being taken (the last
                             // kernel of a step advances it, so captured
                             // steps can be replayed)
+  unsigned* done;           // blocks finished (the fused between-steps kernel), left 0
   double fscale_inv;
   double* part;             // kinetic partials [ntiles][PART_W]
 };
-void launch_int_first(hipStream_t s, const IntLaunch& a, StateView A, long long* const F[3]);
+// First half of a step on A (kick, drift, noise; clears F); with bin != NULL
+// also the binning of the new positions (as launch_bin).
+void launch_int_first(hipStream_t s, const IntLaunch& a, StateView A, long long* const F[3],
+                      const CellView* bin = nullptr);
+// Second half kick of a step on B written back to A, then the first half of
+// the next step and its binning: the same arithmetic as launch_int_last,
+// launch_int_first and launch_bin in turn, in one pass.
+void launch_int_between(hipStream_t s, const IntLaunch& a, StateView B, StateView A, long long* const F[3],
+                        const CellView& bin);
 void launch_int_last(hipStream_t s, const IntLaunch& a, StateView B, StateView A,
                      long long* const F[3], bool kin);
 void launch_forces_out(hipStream_t s, StateView B, long long* const F[3], double* out, long long ld,

@@ -50,26 +50,18 @@ __device__ inline uint32_t drift(uint32_t u, double dx, double L) {
   return u + (uint32_t)du;
 }
 
-__global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* F1, long long* F2, int N) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= N) return;
-  const uint32_t prm = A.param[s];
-  const int r = param_rep(prm), t = param_type(prm);
-  const RepDesc& R = a.rep[r];
+// First half of a step for one bead, from velocity v, position u and force
+// f (already in force units): kick, then drift (velocity Verlet) or drift,
+// Ornstein-Uhlenbeck noise, drift (BAOAB), with the noise of `step`.
+__device__ inline void first_half(const IntLaunch& a, const RepDesc& R, int r, int t, unsigned long long step,
+                                  int id, const double f[3], double v[3], uint32_t u[3]) {
   const double im = a.inv_mass[r * MAXT + t];
   const double dt = a.dt[r];
-  long long* Fk[3] = {F0, F1, F2};
-  double v[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    double f = (double)Fk[k][s] * a.fscale_inv;
-    v[k] = A.vel[k][s] + 0.5 * dt * f * im;
-    Fk[k][s] = 0;
-  }
-  uint32_t u[3] = {A.pos[0][s], A.pos[1][s], A.pos[2][s]};
+  for (int k = 0; k < 3; ++k) v[k] = v[k] + 0.5 * dt * f[k] * im;
   if (a.langevin[r]) {
     double g[3];
-    gauss3(a.seed, *a.step, (unsigned long long)A.id[s], (unsigned long long)r, g);
+    gauss3(a.seed, step, (unsigned long long)id, (unsigned long long)r, g);
     const double c1 = a.c1[r], c2 = a.c2s[r * MAXT + t];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -81,10 +73,81 @@ __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* 
 #pragma unroll
     for (int k = 0; k < 3; ++k) u[k] = drift(u[k], dt * v[k], R.L[k]);
   }
+}
+
+template <bool BIN>
+__global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* F1, long long* F2, CellView c,
+                            int N) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const uint32_t prm = A.param[s];
+  const int r = param_rep(prm), t = param_type(prm);
+  const RepDesc& R = a.rep[r];
+  long long* Fk[3] = {F0, F1, F2};
+  double f[3], v[3];
+  uint32_t u[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f[k] = (double)Fk[k][s] * a.fscale_inv;
+    Fk[k][s] = 0;
+    v[k] = A.vel[k][s];
+    u[k] = A.pos[k][s];
+  }
+  first_half(a, R, r, t, *a.step, A.id[s], f, v, u);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     A.pos[k][s] = u[k];
     A.vel[k][s] = v[k];
+  }
+  if (BIN) bin_bead(c, R, u[0], u[1], u[2], prm, s);
+}
+
+// The second half kick of the step just completed (as k_int_last, on the
+// sorted copy B), then the first half of the next step (as k_int_first) and
+// its binning, written to A.  The step counter advances once every block has
+// read it.
+__global__ __launch_bounds__(256) void k_int_between(IntLaunch a, StateView B, StateView A, long long* F0,
+                                                     long long* F1, long long* F2, CellView c, int N) {
+  __shared__ int last;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned long long step = *a.step;
+  if (s < N) {
+    const uint32_t prm = B.param[s];
+    const int r = param_rep(prm), t = param_type(prm);
+    const RepDesc& R = a.rep[r];
+    const double im = a.inv_mass[r * MAXT + t];
+    const double dt = a.dt[r];
+    long long* Fk[3] = {F0, F1, F2};
+    double f[3], v[3];
+    uint32_t u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const long long fi = Fk[k][s];
+      v[k] = B.vel[k][s] + 0.5 * dt * (double)fi * a.fscale_inv * im;
+      f[k] = (double)fi * a.fscale_inv;
+      Fk[k][s] = 0;
+      u[k] = B.pos[k][s];
+    }
+    const int id = B.id[s];
+    first_half(a, R, r, t, step + 1ULL, id, f, v, u);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      A.pos[k][s] = u[k];
+      A.vel[k][s] = v[k];
+    }
+    A.param[s] = prm;
+    A.id[s] = id;
+    bin_bead(c, R, u[0], u[1], u[2], prm, s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(a.done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    atomicAdd(a.step, 1ULL);
+    atomicExch(a.done, 0u);
   }
 }
 
@@ -246,8 +309,19 @@ inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_int_first(hipStream_t s, const IntLaunch& a, StateView A, long long* const F[3]) {
-  hipLaunchKernelGGL(k_int_first, dim3(nblk(a.nbeads, 256)), dim3(256), 0, s, a, A, F[0], F[1], F[2], a.nbeads);
+void launch_int_first(hipStream_t s, const IntLaunch& a, StateView A, long long* const F[3], const CellView* bin) {
+  if (bin)
+    hipLaunchKernelGGL(k_int_first<true>, dim3(nblk(a.nbeads, 256)), dim3(256), 0, s, a, A, F[0], F[1], F[2], *bin,
+                       a.nbeads);
+  else
+    hipLaunchKernelGGL(k_int_first<false>, dim3(nblk(a.nbeads, 256)), dim3(256), 0, s, a, A, F[0], F[1], F[2],
+                       CellView{}, a.nbeads);
+}
+
+void launch_int_between(hipStream_t s, const IntLaunch& a, StateView B, StateView A, long long* const F[3],
+                        const CellView& bin) {
+  hipLaunchKernelGGL(k_int_between, dim3(nblk(a.nbeads, 256)), dim3(256), 0, s, a, B, A, F[0], F[1], F[2], bin,
+                     a.nbeads);
 }
 
 void launch_int_last(hipStream_t s, const IntLaunch& a, StateView B, StateView A, long long* const F[3], bool kin) {

@@ -30,6 +30,8 @@
 // Lists are rebuilt every evaluation, so they need no skin.  The minimum
 // image is the wrapped 32-bit difference of the fractional fixed-point
 // coordinates (valid because rc <= L/2 is enforced).
+#include <type_traits>
+
 #include "gcme_internal.h"
 
 namespace gcme {
@@ -311,33 +313,43 @@ __device__ inline bool in_frame(const Cluster<CI>& K, const RepDesc& R) {
 }
 
 // Whether bead record pj lies within the list cutoff of at least one bead of
-// the cluster (float): in bead 0's frame when `frame`, otherwise by the
-// minimum image of each pair.
+// the cluster (float), in bead 0's frame; D receives pj's position relative
+// to bead 0.
 template <int CI>
-__device__ inline bool near_cluster(const Cluster<CI>& K, bool frame, const uint4& pj, const RepDesc& R) {
+__device__ inline bool near_frame(const Cluster<CI>& K, const uint4& pj, const RepDesc& R, float& Dx, float& Dy,
+                                  float& Dz) {
   const float rcl2f = K.rcl * K.rcl;
-  const float sx = R.scalef[0], sy = R.scalef[1], sz = R.scalef[2];
+  Dx = (float)(int)(pj.x - K.ux[0]) * R.scalef[0];
+  Dy = (float)(int)(pj.y - K.uy[0]) * R.scalef[1];
+  Dz = (float)(int)(pj.z - K.uz[0]) * R.scalef[2];
   bool hit = false;
-  if (frame) {
-    // candidate relative to bead 0 once, then one subtraction per bead
-    const float Dx = (float)(int)(pj.x - K.ux[0]) * sx;
-    const float Dy = (float)(int)(pj.y - K.uy[0]) * sy;
-    const float Dz = (float)(int)(pj.z - K.uz[0]) * sz;
 #pragma unroll
-    for (int i = 0; i < CI; ++i) {
-      const float dx = Dx - K.rx[i], dy = Dy - K.ry[i], dz = Dz - K.rz[i];
-      hit |= dx * dx + dy * dy + dz * dz < rcl2f;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < CI; ++i) {
-      const float dx = (float)(int)(K.ux[i] - pj.x) * sx;
-      const float dy = (float)(int)(K.uy[i] - pj.y) * sy;
-      const float dz = (float)(int)(K.uz[i] - pj.z) * sz;
-      hit |= dx * dx + dy * dy + dz * dz < rcl2f;
-    }
+  for (int i = 0; i < CI; ++i) {
+    const float dx = Dx - K.rx[i], dy = Dy - K.ry[i], dz = Dz - K.rz[i];
+    hit |= dx * dx + dy * dy + dz * dz < rcl2f;
   }
   return hit;
+}
+
+// The same test by the minimum image of each pair (any cluster).
+template <int CI>
+__device__ inline bool near_exact(const Cluster<CI>& K, const uint4& pj, const RepDesc& R) {
+  const float rcl2f = K.rcl * K.rcl;
+  bool hit = false;
+#pragma unroll
+  for (int i = 0; i < CI; ++i) {
+    const float dx = (float)(int)(K.ux[i] - pj.x) * R.scalef[0];
+    const float dy = (float)(int)(K.uy[i] - pj.y) * R.scalef[1];
+    const float dz = (float)(int)(K.uz[i] - pj.z) * R.scalef[2];
+    hit |= dx * dx + dy * dy + dz * dz < rcl2f;
+  }
+  return hit;
+}
+
+template <int CI>
+__device__ inline bool near_cluster(const Cluster<CI>& K, bool frame, const uint4& pj, const RepDesc& R) {
+  float Dx, Dy, Dz;
+  return frame ? near_frame(K, pj, R, Dx, Dy, Dz) : near_exact(K, pj, R);
 }
 
 template <int CI>
@@ -549,10 +561,7 @@ __device__ inline PairCtx<T> make_ctx(const Tables<T, ELEC, ADJ>& S, const RepDe
 // Pair (i, j) when ok (j a real bead other than i) and r < rc: separation by
 // the exact minimum image in T, the one cutoff test of the method's sums.
 template <typename T, bool ELEC, bool EV, bool ADJ, bool COUNT>
-__device__ inline void try_pair(Lane<T>& L, const PairCtx<T>& P, const uint4& mi, const uint4& pj, bool ok) {
-  const T dx = (T)(int)(mi.x - pj.x) * P.sx;
-  const T dy = (T)(int)(mi.y - pj.y) * P.sy;
-  const T dz = (T)(int)(mi.z - pj.z) * P.sz;
+__device__ inline void pair_at(Lane<T>& L, const PairCtx<T>& P, T dx, T dy, T dz, uint32_t pw, bool ok) {
   const T r2 = dx * dx + dy * dy + dz * dz;
   const bool in = ok && r2 < P.rc2;
   if (!ELEC && !ADJ && !COUNT) {
@@ -560,7 +569,7 @@ __device__ inline void try_pair(Lane<T>& L, const PairCtx<T>& P, const uint4& mi
     // which keeps the unrolled pairs free of branches
     // (a multiplicative mask: a select of the exponential would be turned
     // back into a branch around it)
-    const GcmPar<T> g = P.grow[param_type(pj.w)];
+    const GcmPar<T> g = P.grow[param_type(pw)];
     const T msk = in ? (T)1 : (T)0;
     const T en = g.C * gexp2(-g.bl * r2) * msk;
     const T fs = g.twob * en;
@@ -578,8 +587,16 @@ __device__ inline void try_pair(Lane<T>& L, const PairCtx<T>& P, const uint4& mi
       L.w5 += fyd * (double)dz;
     }
   } else if (in) {
-    interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pj.w, P.grow, P.erow, P.arow, P.zi, P.beta, P.beta2, P.lB);
+    interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pw, P.grow, P.erow, P.arow, P.zi, P.beta, P.beta2, P.lB);
   }
+}
+
+template <typename T, bool ELEC, bool EV, bool ADJ, bool COUNT>
+__device__ inline void try_pair(Lane<T>& L, const PairCtx<T>& P, const uint4& mi, const uint4& pj, bool ok) {
+  const T dx = (T)(int)(mi.x - pj.x) * P.sx;
+  const T dy = (T)(int)(mi.y - pj.y) * P.sy;
+  const T dz = (T)(int)(mi.z - pj.z) * P.sz;
+  pair_at<T, ELEC, EV, ADJ, COUNT>(L, P, dx, dy, dz, pj.w, ok);
 }
 
 // Combine the partial forces of bead i over its CJ lanes (xor shuffles, fixed
@@ -721,8 +738,18 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
     const int i = first + (vi ? il : 0);
     const uint4 mi = pk[i];
     const PairCtx<T> P = make_ctx(S, R, mi.w);
-    // ring records carry, in place of the replica bits, 1 + the cluster slot
-    // of a candidate that is itself a cluster bead (0 otherwise)
+    // Ring records carry, in place of the replica bits, 1 + the cluster slot
+    // of a candidate that is itself a cluster bead (0 otherwise).  In single
+    // precision with the cluster in bead 0's frame they hold the candidate's
+    // position relative to bead 0 as floats (computed once, by the filter),
+    // so a pair costs one subtraction per axis; otherwise the fixed-point
+    // record, and each pair takes its own minimum image.  (Not for the
+    // electrostatics, whose pair cost that would hardly change.)
+    constexpr bool REL = std::is_same<T, float>::value && !ELEC && !COUNT;
+    const bool rel = REL && frame;
+    const float rxi = (float)(int)(mi.x - K.ux[0]) * R.scalef[0];
+    const float ryi = (float)(int)(mi.y - K.uy[0]) * R.scalef[1];
+    const float rzi = (float)(int)(mi.z - K.uz[0]) * R.scalef[2];
     const uint32_t self = (uint32_t)(il + 1);
     uint4* ring = s_ring[wave];
     int head = 0, tail = 0;  // wave-uniform: pairs evaluated / appended
@@ -734,18 +761,33 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
       uint4 pp[CI];
 #pragma unroll
       for (int k = 0; k < CI; ++k) pp[k] = base[k * CJ];
+      if (rel) {
 #pragma unroll
-      for (int k = 0; k < CI; ++k)
-        try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[k], vi && jl + k * CJ < n && (pp[k].w >> 16) != self);
+        for (int k = 0; k < CI; ++k) {
+          const T dx = (T)(rxi - __uint_as_float(pp[k].x));
+          const T dy = (T)(ryi - __uint_as_float(pp[k].y));
+          const T dz = (T)(rzi - __uint_as_float(pp[k].z));
+          pair_at<T, ELEC, EV, ADJ, COUNT>(L, P, dx, dy, dz, pp[k].w,
+                                           vi && jl + k * CJ < n && (pp[k].w >> 16) != self);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < CI; ++k)
+          try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[k], vi && jl + k * CJ < n && (pp[k].w >> 16) != self);
+      }
       head += n;
     };
     auto filter = [&](const uint4 pj, bool v, int j) {
-      const bool hit = near_cluster(K, frame, pj, R) && v;
+      float Dx = 0.f, Dy = 0.f, Dz = 0.f;
+      const bool near = frame ? near_frame(K, pj, R, Dx, Dy, Dz) : near_exact(K, pj, R);
+      const bool hit = near && v;
       const unsigned long long m = __ballot(hit);
       if (hit) {
         const uint32_t d = (uint32_t)(j - first);
-        const uint4 r = make_uint4(pj.x, pj.y, pj.z, (pj.w & 0xffffu) | ((d < (uint32_t)ni ? d + 1u : 0u) << 16));
-        ring[(tail + lanes_below(m)) & (RING - 1)] = r;
+        const uint32_t w = (pj.w & 0xffffu) | ((d < (uint32_t)ni ? d + 1u : 0u) << 16);
+        ring[(tail + lanes_below(m)) & (RING - 1)] =
+            rel ? make_uint4(__float_as_uint(Dx), __float_as_uint(Dy), __float_as_uint(Dz), w)
+                : make_uint4(pj.x, pj.y, pj.z, w);
       }
       tail += __popcll(m);
       __builtin_amdgcn_wave_barrier();

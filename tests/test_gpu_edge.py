@@ -158,6 +158,34 @@ def test_velocity_verlet_trajectory_fp64():
     assert gpu_drift < 2.0 * ora_drift + 1e-9 * abs(gtot[1])
 
 
+@pytest.mark.parametrize("gamma", [0.0, 1.0])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_steps_equal_single_steps(precision, gamma):
+    # A run of n steps fuses each step's second half kick with the next
+    # step's first half and binning; n runs of one step do not.  The
+    # arithmetic is the same, so the trajectories agree bit for bit.
+    w = W.small_bulk(N=900, seed=8, charged_frac=0.3, box=(7.1, 7.3, 6.9), rc=2.5, grid=(24, 24, 24))
+    w.gamma = gamma
+    print(f"case fused steps prec={precision} gamma={gamma}", flush=True)
+    runs = []
+    for split in (False, True):
+        eng = make_engine([w], precision, seed=5)
+        if split:
+            for _ in range(12):
+                eng.step(1)
+        else:
+            eng.step(12)
+        obs = eng.step(1, observe=True)
+        eng.sync()
+        pos, vel, step = eng.get_state()
+        runs.append((pos.cpu().numpy(), vel.cpu().numpy(), step, obs["energy"].cpu().numpy()))
+        eng.close()
+    assert runs[0][2] == runs[1][2] == 13
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    np.testing.assert_array_equal(runs[0][3], runs[1][3])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_langevin_trajectory_short(precision):
     from oracle import oracle as O
