@@ -281,9 +281,11 @@ void build_tables(gcme_handle h, std::vector<GcmPar<T>>& g, std::vector<ElecPar<
         size_t q = ((size_t)r * MAXT + t) * MAXT + u;
         double s2 = p.sigma[t] * p.sigma[t] + p.sigma[u] * p.sigma[u];
         double b = 3.0 / (2.0 * s2);
-        g[q].C = (T)(p.A[t * p.nt + u] * std::pow(3.0 / (2.0 * M_PI * s2), 1.5));
+        const double C = p.A[t * p.nt + u] * std::pow(3.0 / (2.0 * M_PI * s2), 1.5);
+        g[q].C = (T)C;
         g[q].bl = (T)(b * log2e);
         g[q].twob = (T)(2.0 * b);
+        g[q].fC = (T)(2.0 * b * C);
         double aij = std::sqrt(p.a[t] * p.a[t] + p.a[u] * p.a[u]);
         double al = std::sqrt(M_PI / 2.0) / aij;
         e[q].alpha = (T)al;
@@ -389,7 +391,7 @@ void plan_clusters(gcme_handle h, bool charged, int ci, std::vector<int2>& cl, s
     const int c0 = (int)cl.size();
     for (int f = 0; f < n; f += ci) cl.push_back(make_int2(off + f, r | (std::min(ci, n - f) << 16)));
     const int c1 = (int)cl.size();
-    for (int c = c0; c < c1; c += wpb) tiles.push_back(Tile{r, c, std::min(wpb, c1 - c), 0});
+    for (int c = c0; c < c1; c += wpb) tiles.push_back(Tile{r, c, std::min(wpb, c1 - c), off + (c - c0) * ci});
     const double rho = (double)n / d.V;
     const double hx = d.L[0] / d.nc[0], hy = d.L[1] / d.nc[1], hz = d.L[2] / d.nc[2];
     const double beads = ci + 4.0 * std::sqrt((double)ci) + 4.0;

@@ -50,7 +50,8 @@ struct RepDesc {
 // u = C exp2(-bl r^2), force/r = twob * u.
 template <typename T>
 struct GcmPar {
-  T C, bl, twob, pad;
+  T C, bl, twob;
+  T fC;  // twob C: force/r = fC exp2(-bl r^2)
 };
 
 // Real-space smeared-Coulomb coefficients of one type pair.
@@ -97,9 +98,10 @@ struct MeshTile {
 // (pair kernels) of one replica.
 struct Tile {
   int rep;
-  int first;   // first bead (concatenated index)
-  int count;   // <= beads per tile
-  int pad;
+  int first;   // first bead (concatenated index); pair tiles: first cluster
+  int count;   // <= beads per tile; pair tiles: clusters
+  int bead0;   // pair tiles: first bead of the first cluster (clusters of a
+               // replica are consecutive runs of CI beads, the last one short)
 };
 
 // Slots of the per-block partial sums (7 doubles: energy, virial[6]).

@@ -87,6 +87,10 @@ __device__ inline int lanes_below(unsigned long long m) {
 
 __device__ inline uint32_t read_lane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
 
+// A wave-uniform float kept in a scalar register (the VALU reads it as an
+// operand, so it costs no vector register).
+__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
 // Fixed-order sum over the block (NL_WAVES waves); result valid in thread 0.
 __device__ inline double block_sum(double v, double* sh) {
 #pragma unroll
@@ -122,44 +126,46 @@ __device__ inline long long to_fixed(double f, double scale, unsigned int* statu
 template <int CI>
 struct Cluster {
   uint32_t ux[CI], uy[CI], uz[CI];  // fixed-point positions (slots beyond ni repeat bead 0)
-  float rx[CI], ry[CI], rz[CI];     // positions relative to bead 0
   float lo[3], hi[3];               // bounding box relative to bead 0
   int c0[3];                        // cell of bead 0
   float p0[3];                      // bead 0 within its cell
   float h[3], ih[3];                // cell edges and their inverses
+  float qx[CI], qy[CI], qz[CI];     // -2 x (positions relative to bead 0)
+  float nn[CI];                     // squared distances from bead 0
+  bool compact;                     // every bead within 3 rcl of bead 0
   float rcl;                        // list cutoff, a hair above rc
   float rclm;                       // enumeration radius: rcl plus a margin
   int clo[3], chi[3];               // cell ranges relative to c0 (absolute when whole)
   bool whole[3];                    // the range spans the whole axis
 };
 
+// The cluster's geometry from its bead records (lane k < ni holds bead k's
+// record in `me`; slots beyond ni repeat bead 0).
 template <int CI>
-__device__ inline void load_cluster(Cluster<CI>& K, const uint4* __restrict__ pk, int first, int ni,
-                                    const RepDesc& R) {
-  const int lane = threadIdx.x & 63;
-  const uint4 me = pk[first + (lane < ni ? lane : 0)];
+__device__ inline void make_cluster(Cluster<CI>& K, const uint4 me, const RepDesc& R) {
 #pragma unroll
   for (int k = 0; k < CI; ++k) {
     K.ux[k] = read_lane(me.x, k);
     K.uy[k] = read_lane(me.y, k);
     K.uz[k] = read_lane(me.z, k);
   }
+  float rx[CI], ry[CI], rz[CI];  // positions relative to bead 0
 #pragma unroll
   for (int k = 0; k < CI; ++k) {
-    K.rx[k] = (float)(int)(K.ux[k] - K.ux[0]) * R.scalef[0];
-    K.ry[k] = (float)(int)(K.uy[k] - K.uy[0]) * R.scalef[1];
-    K.rz[k] = (float)(int)(K.uz[k] - K.uz[0]) * R.scalef[2];
+    rx[k] = (float)(int)(K.ux[k] - K.ux[0]) * R.scalef[0];
+    ry[k] = (float)(int)(K.uy[k] - K.uy[0]) * R.scalef[1];
+    rz[k] = (float)(int)(K.uz[k] - K.uz[0]) * R.scalef[2];
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) K.lo[k] = K.hi[k] = 0.f;
 #pragma unroll
   for (int k = 1; k < CI; ++k) {
-    K.lo[0] = fminf(K.lo[0], K.rx[k]);
-    K.hi[0] = fmaxf(K.hi[0], K.rx[k]);
-    K.lo[1] = fminf(K.lo[1], K.ry[k]);
-    K.hi[1] = fmaxf(K.hi[1], K.ry[k]);
-    K.lo[2] = fminf(K.lo[2], K.rz[k]);
-    K.hi[2] = fmaxf(K.hi[2], K.rz[k]);
+    K.lo[0] = fminf(K.lo[0], rx[k]);
+    K.hi[0] = fmaxf(K.hi[0], rx[k]);
+    K.lo[1] = fminf(K.lo[1], ry[k]);
+    K.hi[1] = fmaxf(K.hi[1], ry[k]);
+    K.lo[2] = fminf(K.lo[2], rz[k]);
+    K.hi[2] = fmaxf(K.hi[2], rz[k]);
   }
   const uint32_t u0[3] = {K.ux[0], K.uy[0], K.uz[0]};
 #pragma unroll
@@ -174,6 +180,16 @@ __device__ inline void load_cluster(Cluster<CI>& K, const uint4* __restrict__ pk
   // own test (in their precision) keeps
   K.rcl = (float)(R.rc * (1.0 + 1e-5));
   K.rclm = K.rcl + 1e-4f * fmaxf(K.h[0], fmaxf(K.h[1], K.h[2]));
+  float nmax = 0.f;
+#pragma unroll
+  for (int k = 0; k < CI; ++k) {
+    K.qx[k] = uni(-2.f * rx[k]);
+    K.qy[k] = uni(-2.f * ry[k]);
+    K.qz[k] = uni(-2.f * rz[k]);
+    K.nn[k] = uni(rx[k] * rx[k] + ry[k] * ry[k] + rz[k] * rz[k]);
+    nmax = fmaxf(nmax, K.nn[k]);
+  }
+  K.compact = nmax <= 9.f * K.rcl * K.rcl;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     K.clo[k] = (int)floorf((K.p0[k] + K.lo[k] - K.rclm) * K.ih[k]);
@@ -184,6 +200,13 @@ __device__ inline void load_cluster(Cluster<CI>& K, const uint4* __restrict__ pk
       K.chi[k] = R.nc[k] - 1;
     }
   }
+}
+
+template <int CI>
+__device__ inline void load_cluster(Cluster<CI>& K, const uint4* __restrict__ pk, int first, int ni,
+                                    const RepDesc& R) {
+  const int lane = threadIdx.x & 63;
+  make_cluster(K, pk[first + (lane < ni ? lane : 0)], R);
 }
 
 // Every bead of the cells within reach of the cluster: the columns whose
@@ -297,37 +320,62 @@ __device__ inline void for_candidates(const Cluster<CI>& K, const RepDesc& R, co
   }
 }
 
+// The candidates cand[0, total) in chunks of 64, one per lane: the index and
+// bead-record loads of NCH chunks are issued together (one memory latency
+// covers them), then f(record, valid, index) runs per chunk in order.
+template <int NCH, class F>
+__device__ inline void for_chunks(const int* cand, int total, const uint4* __restrict__ pk, int fallback, F&& f) {
+  const int lane = threadIdx.x & 63;
+  for (int p = 0; p < total; p += 64 * NCH) {
+    int jj[NCH];
+    uint4 rr[NCH];
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+      const int q = p + 64 * u + lane;
+      jj[u] = q < total ? cand[q] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) rr[u] = pk[jj[u] < 0 ? fallback : jj[u]];
+#pragma unroll
+    for (int u = 0; u < NCH; ++u)
+      if (u == 0 || p + 64 * u < total) f(rr[u], jj[u] >= 0, jj[u] < 0 ? fallback : jj[u]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // List build
 // ---------------------------------------------------------------------------
 
-// In the frame of bead 0, separations equal the per-pair minimum image for
-// every pair within rc as long as each cluster bead lies within L/2 - rc of
-// bead 0 on each axis (then |d| < rc cannot wrap).
+// Whether the cluster takes the fast path: in the frame of bead 0,
+// separations equal the per-pair minimum image for every pair within rc as
+// long as each cluster bead lies within L/2 - rc of bead 0 on each axis (then
+// |d| < rc cannot wrap); and the cluster is compact (every bead within 3 rcl
+// of bead 0), which bounds the rounding of the frame-relative arithmetic.
 template <int CI>
 __device__ inline bool in_frame(const Cluster<CI>& K, const RepDesc& R) {
-  bool frame = true;
+  bool frame = K.compact;
 #pragma unroll
   for (int k = 0; k < 3; ++k) frame = frame && fmaxf(-K.lo[k], K.hi[k]) < 0.5f * (float)R.L[k] - K.rclm;
   return frame;
 }
 
 // Whether bead record pj lies within the list cutoff of at least one bead of
-// the cluster (float), in bead 0's frame; D receives pj's position relative
-// to bead 0.
+// the cluster (float), for a compact cluster in bead 0's frame; D receives
+// pj's position relative to bead 0.  |D - r_i|^2 < rcl^2 is tested as
+// |r_i|^2 - 2 D.r_i < rcl^2 - |D|^2: three fused multiply-adds per bead.  The
+// candidates that can pass lie within 4 rcl of bead 0, so the rounding of the
+// expanded form stays below 1e-5 rcl^2, inside the margin of rcl over rc: no
+// pair within rc is dropped.
 template <int CI>
 __device__ inline bool near_frame(const Cluster<CI>& K, const uint4& pj, const RepDesc& R, float& Dx, float& Dy,
                                   float& Dz) {
-  const float rcl2f = K.rcl * K.rcl;
   Dx = (float)(int)(pj.x - K.ux[0]) * R.scalef[0];
   Dy = (float)(int)(pj.y - K.uy[0]) * R.scalef[1];
   Dz = (float)(int)(pj.z - K.uz[0]) * R.scalef[2];
+  const float thr = K.rcl * K.rcl - (Dx * Dx + Dy * Dy + Dz * Dz);
   bool hit = false;
 #pragma unroll
-  for (int i = 0; i < CI; ++i) {
-    const float dx = Dx - K.rx[i], dy = Dy - K.ry[i], dz = Dz - K.rz[i];
-    hit |= dx * dx + dy * dy + dz * dz < rcl2f;
-  }
+  for (int i = 0; i < CI; ++i) hit |= fmaf(K.qx[i], Dx, fmaf(K.qy[i], Dy, fmaf(K.qz[i], Dz, K.nn[i]))) < thr;
   return hit;
 }
 
@@ -347,9 +395,9 @@ __device__ inline bool near_exact(const Cluster<CI>& K, const uint4& pj, const R
 }
 
 template <int CI>
-__device__ inline bool near_cluster(const Cluster<CI>& K, bool frame, const uint4& pj, const RepDesc& R) {
+__device__ inline bool near_cluster(const Cluster<CI>& K, bool fast, const uint4& pj, const RepDesc& R) {
   float Dx, Dy, Dz;
-  return frame ? near_frame(K, pj, R, Dx, Dy, Dz) : near_exact(K, pj, R);
+  return fast ? near_frame(K, pj, R, Dx, Dy, Dz) : near_exact(K, pj, R);
 }
 
 template <int CI>
@@ -381,17 +429,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
   };
   const int* cand = s_cand[wave];
   for_candidates(K, R, a.start, s_sb[wave], s_sl[wave], s_cand[wave], [&](int total) {
-    // two chunks per pass, their loads issued together
-    for (int p = 0; p < total; p += 128) {
-      const int q0 = p + lane, q1 = p + 64 + lane;
-      const bool v0 = q0 < total, v1 = q1 < total;
-      const int j0 = v0 ? cand[q0] : first;
-      const int j1 = v1 ? cand[q1] : first;
-      const uint4 p0 = pk[j0];
-      const uint4 p1 = pk[j1];
-      test(p0, v0, j0);
-      if (p + 64 < total) test(p1, v1, j1);
-    }
+    for_chunks<2>(cand, total, pk, first, test);
   });
   if (lane == 0) {
     a.count[c] = min(nent, a.cap);
@@ -565,18 +603,17 @@ __device__ inline void pair_at(Lane<T>& L, const PairCtx<T>& P, T dx, T dy, T dz
   const T r2 = dx * dx + dy * dy + dz * dz;
   const bool in = ok && r2 < P.rc2;
   if (!ELEC && !ADJ && !COUNT) {
-    // excluded volume: cheap enough to evaluate for every lane and mask,
-    // which keeps the unrolled pairs free of branches
-    // (a multiplicative mask: a select of the exponential would be turned
-    // back into a branch around it)
+    // excluded volume: cheap enough to evaluate for every lane, which keeps
+    // the unrolled pairs free of branches; a pair that does not count gets
+    // the exponent -inf, hence exactly zero
     const GcmPar<T> g = P.grow[param_type(pw)];
-    const T msk = in ? (T)1 : (T)0;
-    const T en = g.C * gexp2(-g.bl * r2) * msk;
-    const T fs = g.twob * en;
+    const T ex = gexp2(in ? -g.bl * r2 : -(T)INFINITY);
+    const T fs = g.fC * ex;
     L.fx += fs * dx;
     L.fy += fs * dy;
     L.fz += fs * dz;
     if (EV) {
+      const T en = g.C * ex;
       const double fxd = (double)(fs * dx), fyd = (double)(fs * dy), fzd = (double)(fs * dz);
       L.e += (double)en;
       L.w0 += fxd * (double)dx;
@@ -722,21 +759,28 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Tile tl = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[tl.rep];
-  stage_tables(S, a, tl.rep);
   const int il = lane / CJ, jl = lane % CJ;
+  const uint4* __restrict__ pk = a.pk;
+  // this wave's cluster: CI consecutive beads from bead0 + wave CI (the
+  // replica's last cluster may be short).  Its records are requested before
+  // the tables are staged, so the two loads overlap.
+  const bool active = wave < tl.count;
+  const int first = tl.bead0 + wave * CI;
+  const int ni = active ? min(CI, (ELEC ? R.q_off + R.nq : R.bead_off + R.n) - first) : 1;
+  const bool vi = il < ni;
+  const int i = first + (vi ? il : 0);
+  uint4 me = make_uint4(0u, 0u, 0u, 0u), mi = me;
+  if (active) {
+    me = pk[first + (lane < ni ? lane : 0)];
+    mi = pk[i];
+  }
+  stage_tables(S, a, tl.rep);
   Lane<T> L;
   lane_zero(L);
-  if (wave < tl.count) {
-    const int c = tl.first + wave;
-    const int2 info = a.cl[c];
-    const int first = info.x, ni = info.y >> 16;
-    const uint4* __restrict__ pk = a.pk;
+  if (active) {
     Cluster<CI> K;
-    load_cluster(K, pk, first, ni, R);
+    make_cluster(K, me, R);
     const bool frame = in_frame(K, R);
-    const bool vi = il < ni;
-    const int i = first + (vi ? il : 0);
-    const uint4 mi = pk[i];
     const PairCtx<T> P = make_ctx(S, R, mi.w);
     // Ring records carry, in place of the replica bits, 1 + the cluster slot
     // of a candidate that is itself a cluster bead (0 otherwise).  In single
@@ -756,11 +800,22 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
     // evaluate the n <= 64 pending entries from head: lane (il, jl) takes
     // entries jl + k CJ, k < CI.  head is a multiple of 64 here (every drain
     // but the last takes exactly 64), so the entries do not wrap.
+    //
+    // Forces alone (BARE) need no per-pair validity test in that mode: a bead
+    // paired with itself has zero separation, so zero force; lanes of
+    // missing cluster beads (vi false) are never flushed; and the slots past
+    // the last entry of the final drain are filled with a record 1e18 away.
+    constexpr bool BARE = REL && !EV && !ADJ;
     auto drain = [&](int n) {
-      const uint4* base = ring + (head & 64) + jl;
+      uint4* base = ring + (head & 64);
+      if (BARE && rel && n < 64) {
+        const uint32_t far = __float_as_uint(1e18f);
+        if (lane >= n) base[lane] = make_uint4(far, far, far, 0u);
+        __builtin_amdgcn_wave_barrier();
+      }
       uint4 pp[CI];
 #pragma unroll
-      for (int k = 0; k < CI; ++k) pp[k] = base[k * CJ];
+      for (int k = 0; k < CI; ++k) pp[k] = base[jl + k * CJ];
       if (rel) {
 #pragma unroll
         for (int k = 0; k < CI; ++k) {
@@ -768,7 +823,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
           const T dy = (T)(ryi - __uint_as_float(pp[k].y));
           const T dz = (T)(rzi - __uint_as_float(pp[k].z));
           pair_at<T, ELEC, EV, ADJ, COUNT>(L, P, dx, dy, dz, pp[k].w,
-                                           vi && jl + k * CJ < n && (pp[k].w >> 16) != self);
+                                           BARE || (vi && jl + k * CJ < n && (pp[k].w >> 16) != self));
         }
       } else {
 #pragma unroll
@@ -795,17 +850,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
     };
     const int* cand = s_cand[wave];
     for_candidates(K, R, a.start, s_sb[wave], s_sl[wave], s_cand[wave], [&](int total) {
-      // two chunks per pass, their loads issued together
-      for (int p = 0; p < total; p += 128) {
-        const int q0 = p + lane, q1 = p + 64 + lane;
-        const bool v0 = q0 < total, v1 = q1 < total;
-        const int j0 = v0 ? cand[q0] : first;
-        const int j1 = v1 ? cand[q1] : first;
-        const uint4 p0 = pk[j0];
-        const uint4 p1 = pk[j1];
-        filter(p0, v0, j0);
-        if (p + 64 < total) filter(p1, v1, j1);
-      }
+      for_chunks<2>(cand, total, pk, first, filter);
     });
     if (tail > head) drain(tail - head);
     flush_bead<T, CI, ELEC, ADJ>(a, L, vi, i, param_type(mi.w));
