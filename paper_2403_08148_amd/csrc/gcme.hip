@@ -722,6 +722,7 @@ PmeLaunch pme_args(gcme_handle h) {
   a.tx = h->mtx;
   a.ty = h->mty;
   a.Qc = h->Qc.p;
+  a.plane_major = h->yx_fused ? 1 : 0;
   a.plane_elems = h->plane_elems;
   a.tw = h->d_tw.p;
   a.radix = h->d_rad.as<int>();

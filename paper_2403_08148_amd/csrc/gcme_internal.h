@@ -222,7 +222,10 @@ struct PmeLaunch {
   const MeshTile* tiles;  // fused spread + z / z + gather passes
   int ntiles;
   int tx, ty;         // tile shape (z lines per axis)
-  void* Qc;           // complex<T> half-complex mesh
+  void* Qc;           // complex<T> half-complex mesh, per replica at cgrid_off:
+                      //   plane_major: (m, x, y) at (m K0 + x) K1 + y
+                      //   otherwise:   (x, y, m) at (x K1 + y) K2h + m
+  int plane_major;    // the layout of the fused y/x plane pass
   const void* tw;     // complex<T> twiddles
   const int* radix;
   const void* bsp;    // T: exp(-pi^2 (m/L)^2/beta^2) / |b(m)|^2 per axis entry

@@ -87,6 +87,12 @@ struct FDiv {
   }
 };
 
+// Offset of half-complex mesh point (x, y, m) within a replica's mesh, in
+// the layout the launch uses.
+__device__ inline long long mesh_index(const PmeLaunch& a, const RepDesc& R, int x, int y, int m) {
+  return a.plane_major ? ((long long)m * R.K[0] + x) * R.K[1] + y : ((long long)x * R.K[1] + y) * R.K2h + m;
+}
+
 // One radix-RR Stockham stage over nl lines of length K held in LDS
 // (element (k, l) at k*LBP + l), A -> B.  The radix is a template parameter
 // so the butterfly operands stay in registers.
@@ -342,12 +348,13 @@ __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
       fr2[e] = fr[R.bsp_off[2] + e];
     }
   }
-  cplx<T>* Q = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + kz;
+  // the plane is contiguous in the plane-major mesh layout
   const int n = K0 * K1;
+  cplx<T>* Q = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)kz * n;
   const FDiv dk0(K0), dk1(K1);
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int x = dk1.div(e), y = e - x * K1;
-    A[y * LY + x] = Q[(long long)e * K2h];
+    A[y * LY + x] = Q[e];
   }
   __syncthreads();
   const int* radx = a.radix + R.rad_off[0];
@@ -377,7 +384,7 @@ __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
   cplx<T>* r4 = fft_lines<T>(o3, r3, K1, LY, K0, twy, rady, R.nrad[1], true);
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int x = dk1.div(e), y = e - x * K1;
-    Q[(long long)e * K2h] = r4[y * LY + x];
+    Q[e] = r4[y * LY + x];
   }
   if (EV) {
     double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
@@ -548,11 +555,19 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   __syncthreads();
   cplx<T>* res = fft_lines<T>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], false);
   cplx<T>* out = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off;
+  const FDiv dnl(NL), dty(TY);
   for (int e = threadIdx.x; e < NL * K2h; e += blockDim.x) {
-    const int l = dk2h.div(e), m = e - l * K2h;
-    const int lx = l / TY, ly = l - lx * TY;
-    if (lx < nxt && ly < nyt)
-      out[((long long)(mt.x0 + lx) * K1 + (mt.y0 + ly)) * K2h + m] = res[m * LBP + l];
+    // consecutive threads take consecutive addresses of either layout
+    int l, m;
+    if (a.plane_major) {
+      m = dnl.div(e);
+      l = e - m * NL;
+    } else {
+      l = dk2h.div(e);
+      m = e - l * K2h;
+    }
+    const int lx = dty.div(l), ly = l - lx * TY;
+    if (lx < nxt && ly < nyt) out[mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m)] = res[m * LBP + l];
   }
 }
 
@@ -569,12 +584,20 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
   const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
   const cplx<T>* in = reinterpret_cast<const cplx<T>*>(a.Qc) + R.cgrid_off;
-  const FDiv dk2h(K2h);
+  const FDiv dk2h(K2h), dnl(NL), dty(TY);
   for (int e = threadIdx.x; e < NL * K2h; e += blockDim.x) {
-    const int l = dk2h.div(e), m = e - l * K2h;
-    const int lx = l / TY, ly = l - lx * TY;
+    // consecutive threads take consecutive addresses of either layout
+    int l, m;
+    if (a.plane_major) {
+      m = dnl.div(e);
+      l = e - m * NL;
+    } else {
+      l = dk2h.div(e);
+      m = e - l * K2h;
+    }
+    const int lx = dty.div(l), ly = l - lx * TY;
     cplx<T> v = {(T)0, (T)0};
-    if (lx < nxt && ly < nyt) v = in[((long long)(mt.x0 + lx) * K1 + (mt.y0 + ly)) * K2h + m];
+    if (lx < nxt && ly < nyt) v = in[mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m)];
     A[m * LBP + l] = v;
     // Hermitian partner of a real field
     const int mc = K2 - m;
