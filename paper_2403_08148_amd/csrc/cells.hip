@@ -76,6 +76,7 @@ __device__ inline int block_inclusive_scan(int v, int* sh) {
 // Produces start (exclusive) and, for all beads, the scatter cursor
 // fill = start.
 constexpr int SINGLE_SCAN_THREADS = 1024;
+constexpr int SCAN_UNROLL = 8;
 constexpr int SINGLE_SCAN_MAX = 38912;  // counts staged in up to 152 KiB of LDS
 
 // The counts pass through LDS: coalesced, independent global loads and
@@ -89,16 +90,41 @@ __global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c)
   const int arr = blockIdx.x;
   const int* cnt = arr == 0 ? c.counts : c.qcounts;
   int* st = arr == 0 ? c.start : c.qstart;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = cnt[i];
+  // loads of SCAN_UNROLL rounds are issued before any is stored, so one
+  // memory latency covers them
+  for (int i0 = threadIdx.x; i0 < n; i0 += SCAN_UNROLL * blockDim.x) {
+    int v[SCAN_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SCAN_UNROLL; ++u) {
+      const int i = i0 + u * blockDim.x;
+      v[u] = i < n ? cnt[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_UNROLL; ++u) {
+      const int i = i0 + u * blockDim.x;
+      if (i < n) buf[i] = v[u];
+    }
+  }
   __syncthreads();
+  // each thread's contiguous chunk, four LDS reads in flight at a time
   int s = 0;
-  for (int i = lo; i < hi; ++i) s += buf[i];
+  for (int i = lo; i < hi; i += 4) {
+    int v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = i + u < hi ? buf[i + u] : 0;
+    s += (v[0] + v[1]) + (v[2] + v[3]);
+  }
   int inc = block_inclusive_scan(s, sh);
   int run = inc - s;
-  for (int i = lo; i < hi; ++i) {
-    int v = buf[i];
-    buf[i] = run;
-    run += v;
+  for (int i = lo; i < hi; i += 4) {
+    int v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = i + u < hi ? buf[i + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i + u < hi) buf[i + u] = run;
+      run += v[u];
+    }
   }
   if (threadIdx.x == blockDim.x - 1) st[n] = inc;
   __syncthreads();

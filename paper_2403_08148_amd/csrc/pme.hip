@@ -94,23 +94,33 @@ __device__ inline long long mesh_index(const PmeLaunch& a, const RepDesc& R, int
 }
 
 // One radix-RR Stockham stage over nl lines of length K held in LDS
-// (element (k, l) at k*LBP + l), A -> B.  The radix is a template parameter
-// so the butterfly operands stay in registers.
+// (element (k, l) at k*SK + l*SL), A -> B.  The radix is a template
+// parameter so the butterfly operands stay in registers.  Consecutive
+// threads take consecutive lines when the lines are interleaved (SL = 1) and
+// consecutive butterflies of one line when its points are (SK = 1), so LDS
+// accesses stay on consecutive banks.
 template <typename T, int RR>
-__device__ inline void fft_stage(const cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, int Ns,
+__device__ inline void fft_stage(const cplx<T>* A, cplx<T>* B, int K, int SK, int SL, int nl, int Ns,
                                  const cplx<T>* __restrict__ tw, bool inverse) {
   const T sgn = inverse ? (T)1 : (T)-1;
   const int nb = K / RR;
   const int tstride = K / (Ns * RR);
-  const FDiv dnl(nl), dns(Ns);
+  const FDiv dnl(nl), dnb(nb), dns(Ns);
+  const bool kfast = SK == 1 && SL != 1;
   for (int b = threadIdx.x; b < nb * nl; b += blockDim.x) {
-    const int j = dnl.div(b);
-    const int l = b - j * nl;
+    int j, l;
+    if (kfast) {
+      l = dnb.div(b);
+      j = b - l * nb;
+    } else {
+      j = dnl.div(b);
+      l = b - j * nl;
+    }
     const int jn = dns.div(j);
     const int k = j - jn * Ns;
     cplx<T> v[RR];
 #pragma unroll
-    for (int r = 0; r < RR; ++r) v[r] = A[(j + r * nb) * LBP + l];
+    for (int r = 0; r < RR; ++r) v[r] = A[(j + r * nb) * SK + l * SL];
 #pragma unroll
     for (int r = 1; r < RR; ++r) {
       cplx<T> w = tw[k * r * tstride];
@@ -147,24 +157,25 @@ __device__ inline void fft_stage(const cplx<T>* A, cplx<T>* B, int K, int LBP, i
     }
     const int idxD = jn * Ns * RR + k;
 #pragma unroll
-    for (int r = 0; r < RR; ++r) B[(idxD + r * Ns) * LBP + l] = o[r];
+    for (int r = 0; r < RR; ++r) B[(idxD + r * Ns) * SK + l * SL] = o[r];
   }
 }
 
-// In-LDS Stockham FFT of nl lines of length K (element (k, l) at k*LBP + l).
-// Returns the buffer holding the result (A or B).
+// In-LDS Stockham FFT of nl lines of length K (element (k, l) at
+// k*SK + l*SL).  Returns the buffer holding the result (A or B).
 template <typename T>
-__device__ cplx<T>* fft_lines(cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, const cplx<T>* __restrict__ tw,
-                              const int* __restrict__ rad, int nrad, bool inverse) {
+__device__ cplx<T>* fft_lines_s(cplx<T>* A, cplx<T>* B, int K, int SK, int SL, int nl,
+                                const cplx<T>* __restrict__ tw, const int* __restrict__ rad, int nrad,
+                                bool inverse) {
   int Ns = 1;
   for (int s = 0; s < nrad; ++s) {
     const int Rr = rad[s];
     if (Rr == 4)
-      fft_stage<T, 4>(A, B, K, LBP, nl, Ns, tw, inverse);
+      fft_stage<T, 4>(A, B, K, SK, SL, nl, Ns, tw, inverse);
     else if (Rr == 2)
-      fft_stage<T, 2>(A, B, K, LBP, nl, Ns, tw, inverse);
+      fft_stage<T, 2>(A, B, K, SK, SL, nl, Ns, tw, inverse);
     else
-      fft_stage<T, 3>(A, B, K, LBP, nl, Ns, tw, inverse);
+      fft_stage<T, 3>(A, B, K, SK, SL, nl, Ns, tw, inverse);
     __syncthreads();
     cplx<T>* t = A;
     A = B;
@@ -172,6 +183,13 @@ __device__ cplx<T>* fft_lines(cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, co
     Ns *= Rr;
   }
   return A;
+}
+
+// Lines interleaved: element (k, l) at k*LBP + l.
+template <typename T>
+__device__ cplx<T>* fft_lines(cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, const cplx<T>* __restrict__ tw,
+                              const int* __restrict__ rad, int nrad, bool inverse) {
+  return fft_lines_s<T>(A, B, K, LBP, 1, nl, tw, rad, nrad, inverse);
 }
 
 // Copies the K twiddles of one axis into LDS (whole block; the caller's
@@ -308,9 +326,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
 
 // y transform, x transform, Green's function (energy, virial), inverse x,
 // inverse y of one kz plane of the half-complex mesh, all in LDS (for meshes
-// whose K0 x K1 plane fits twice in a workgroup's LDS).  Layouts: y-major
-// (y, x) at y*LY + x for the y lines, x-major (x, y) at x*LX + y for the x
-// lines; the transposes between them are LDS-to-LDS copies.
+// whose K0 x K1 plane fits twice in a workgroup's LDS).  The plane stays in
+// one layout, (y, x) at y*LY + x (LY = K0 + 1): the y lines are transformed
+// with x interleaved, the x lines with their points consecutive.
 template <typename T, bool EV>
 __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -319,7 +337,7 @@ __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
   const RepDesc& R = a.rep[it.rep];
   const int K0 = R.K[0], K1 = R.K[1], K2h = R.K2h;
   const int kz = it.first;
-  const int LY = K0 + 1, LX = K1 + 1;
+  const int LY = K0 + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.plane_elems;
   const cplx<T>* twx = stage_twiddles(B + (size_t)a.plane_elems, a, R.tw_off[0], K0);
@@ -359,29 +377,21 @@ __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
   __syncthreads();
   const int* radx = a.radix + R.rad_off[0];
   const int* rady = a.radix + R.rad_off[1];
-  cplx<T>* r1 = fft_lines<T>(A, B, K1, LY, K0, twy, rady, R.nrad[1], false);
+  // y lines (x interleaved), then x lines in place in the same layout
+  // (points of a line consecutive, lines LY apart): no transposes
+  cplx<T>* r1 = fft_lines_s<T>(A, B, K1, LY, 1, K0, twy, rady, R.nrad[1], false);
   cplx<T>* o1 = r1 == A ? B : A;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int y = dk0.div(e), x = e - y * K0;
-    o1[x * LX + y] = r1[y * LY + x];
-  }
-  __syncthreads();
-  cplx<T>* r2 = fft_lines<T>(o1, r1, K0, LX, K1, twx, radx, R.nrad[0], false);
-  cplx<T>* o2 = r2 == o1 ? r1 : o1;
+  cplx<T>* r2 = fft_lines_s<T>(r1, o1, K0, 1, LY, K1, twx, radx, R.nrad[0], false);
+  cplx<T>* o2 = r2 == r1 ? o1 : r1;
   RecipSums acc{};
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int x = dk1.div(e), y = e - x * K1;
-    r2[x * LX + y] = green_apply<T, EV>(R, gf0, gf1, gf2, fr0, fr1, fr2, x, y, kz, r2[x * LX + y], acc);
+    const int y = dk0.div(e), x = e - y * K0;
+    r2[y * LY + x] = green_apply<T, EV>(R, gf0, gf1, gf2, fr0, fr1, fr2, x, y, kz, r2[y * LY + x], acc);
   }
   __syncthreads();
-  cplx<T>* r3 = fft_lines<T>(r2, o2, K0, LX, K1, twx, radx, R.nrad[0], true);
+  cplx<T>* r3 = fft_lines_s<T>(r2, o2, K0, 1, LY, K1, twx, radx, R.nrad[0], true);
   cplx<T>* o3 = r3 == r2 ? o2 : r2;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int x = dk1.div(e), y = e - x * K1;
-    o3[y * LY + x] = r3[x * LX + y];
-  }
-  __syncthreads();
-  cplx<T>* r4 = fft_lines<T>(o3, r3, K1, LY, K0, twy, rady, R.nrad[1], true);
+  cplx<T>* r4 = fft_lines_s<T>(r3, o3, K1, LY, 1, K0, twy, rady, R.nrad[1], true);
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int x = dk1.div(e), y = e - x * K1;
     Q[e] = r4[y * LY + x];
