@@ -141,13 +141,18 @@ def main():
     nch = K[0] * K[1] * (K[2] // 2 + 1)
     cs = 16 if args.precision == "fp64" else 8
     peak_alu = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+    # a list-free pair kernel does its neighbour search itself: its stage
+    # carries the distance tests too (and the list stage is empty)
+    direct = tuning.get("direct_pairs", 0)
+    gcm_flop = FLOP_PER_GCM_PAIR + (FLOP_PER_DISTANCE_TEST if direct & 1 else 0)
+    elec_flop = FLOP_PER_ELEC_PAIR + (FLOP_PER_DISTANCE_TEST if direct & 2 else 0)
     alg = {
         "int_first": ("hbm", w.N * (12 + 24 + 24 + 12 + 24 + 24)),
         "sort": ("hbm", w.N * (12 + 4 + 4 + 12 + 24 + 4 + 4 + 12 + 24 + 4 + 4 + 16)),
         "list_gcm": ("alu", FLOP_PER_DISTANCE_TEST * pairs),
-        "pair_gcm": ("alu", FLOP_PER_GCM_PAIR * pairs),
+        "pair_gcm": ("alu", gcm_flop * pairs),
         "list_elec": ("alu", FLOP_PER_DISTANCE_TEST * cc_pairs),
-        "pair_elec": ("alu", FLOP_PER_ELEC_PAIR * cc_pairs),
+        "pair_elec": ("alu", elec_flop * cc_pairs),
         "spread_z": ("hbm", nq * 16 + nch * cs),
         "fft_y": ("hbm", 2 * nch * cs),
         "fft_conv": ("hbm", 2 * nch * cs),
@@ -169,7 +174,9 @@ def main():
         return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS}
 
-    stage_roof = {k: roof_of(k) for k in stages if k in alg and stages[k] > 0}
+    skip = {"list_gcm"} if direct & 1 else set()
+    skip |= {"list_elec"} if direct & 2 else set()
+    stage_roof = {k: roof_of(k) for k in stages if k in alg and stages[k] > 0 and k not in skip}
     dom = max(stage_roof, key=lambda k: stages[k])
     roof = dict(stage_roof[dom])
     roof["launch_us"] = stages[dom] * 1e3
