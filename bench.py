@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--workload", default="bulk_N32768", choices=["bulk_N32768", "bulk_N2097152"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default="",
-                    help="cells_per_cutoff,beads_per_cluster,charges_per_cluster[,direct_pairs] "
+                    help="cells_per_cutoff,beads_per_cluster,charges_per_cluster[,direct_pairs[,stream_layout]] "
                          "(implies --no-autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=20)
@@ -92,7 +92,7 @@ def main():
     if args.tuning:
         v = [int(x) for x in args.tuning.split(",")]
         eng.set_tuning(cells_per_cutoff=v[0], beads_per_cluster=v[1], charges_per_cluster=v[2],
-                       direct_pairs=v[3] if len(v) > 3 else -1)
+                       direct_pairs=v[3] if len(v) > 3 else -1, stream_layout=v[4] if len(v) > 4 else -1)
         tuning = eng.tuning()
     else:
         tuning = eng.tuning() if args.no_autotune else eng.autotune()

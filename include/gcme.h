@@ -175,12 +175,25 @@ typedef struct {
     int32_t list_slack_pct;      /* list capacity above the density estimate, % (0..1000) */
     int32_t direct_pairs;        /* list-free kernels: bit 0 excluded volume,
                                     bit 1 real-space electrostatics (0..3) */
+    int32_t stream_layout;       /* how the three independent parts of a force
+                                    evaluation (excluded-volume pairs, charged
+                                    pairs, mesh chain) share streams (0..3):
+                                    0: each on its own stream;
+                                    1: the pairs on the context's stream, the
+                                       mesh chain on a second one;
+                                    2: the mesh chain on the context's stream,
+                                       charged then excluded-volume pairs on a
+                                       second one;
+                                    3: as 2, excluded-volume pairs first */
 } gcme_tuning;
 
 gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t);
 gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t);
 
-/* Time candidate tunings on the current state and keep the fastest.
+/* Time candidate tunings on the current state and keep the fastest: every
+ * cluster size, cell size and list choice as a stream-launched evaluation,
+ * then the stream layouts of the best few as replays of a captured
+ * evaluation graph (the form a step runs in).
  * Tunings change the order of the per-bead floating-point sums, so results
  * agree across tunings to rounding; for one tuning, reruns on the same
  * inputs are bit-identical.  Synchronous. */

@@ -299,7 +299,7 @@ void launch_fill_i64(hipStream_t s, long long* p, long long v, long long n) {
 }
 
 void launch_bin(hipStream_t s, StateView A, const RepDesc* rep, CellView c, int N) {
-  hipLaunchKernelGGL(k_bin, dim3(nblk(N, 256)), dim3(256), 0, s, A, rep, c, N);
+  hipLaunchKernelGGL(k_bin, dim3(nblk(N, BEAD_THREADS)), dim3(BEAD_THREADS), 0, s, A, rep, c, N);
 }
 
 void launch_scan(hipStream_t s, CellView c) {
@@ -316,11 +316,11 @@ void launch_scan(hipStream_t s, CellView c) {
 }
 
 void launch_scatter(hipStream_t s, CellView c, int N) {
-  hipLaunchKernelGGL(k_scatter, dim3(nblk(N, 256)), dim3(256), 0, s, c, N);
+  hipLaunchKernelGGL(k_scatter, dim3(nblk(N, BEAD_THREADS)), dim3(BEAD_THREADS), 0, s, c, N);
 }
 
 void launch_permute(hipStream_t s, StateView A, StateView B, uint4* bpk, CellView c, ChargedView q, int N) {
-  hipLaunchKernelGGL(k_permute, dim3(nblk(N, 256)), dim3(256), 0, s, A, B, bpk, c, q, N);
+  hipLaunchKernelGGL(k_permute, dim3(nblk(N, BEAD_THREADS)), dim3(BEAD_THREADS), 0, s, A, B, bpk, c, q, N);
 }
 
 void launch_commit(hipStream_t s, StateView B, StateView A, int N) {

@@ -111,7 +111,7 @@ struct gcme_ctx {
   std::vector<int> nq, qoff;
   int NQ = 0;
   // tuning
-  gcme_tuning tune{3, 4, 4, 50, 0};
+  gcme_tuning tune{3, 4, 4, 50, 0, 0};
   bool plan_dirty = true;
   // device buffers
   DevBuf a_pos[3], a_vel[3], a_param, a_id;
@@ -777,31 +777,61 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
     launch_pair_gcm(s, g, h->fp64, ev, adj);
     return;
   }
-  (void)hipEventRecord(h->ev_fork, s);
-  (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
-  (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
-  // issue order: the longest single kernels first, so that in a captured
-  // graph (whose nodes are submitted in this order) each branch's first
-  // kernel is queued before the others' later ones
-  launch_nl_build(s, g);
-  launch_pair_gcm(s, g, h->fp64, ev, adj);
-  PairLaunch q = pair_args(h, true);
-  launch_nl_build(h->aux[0], q);
-  PmeLaunch p = pme_args(h);
-  launch_spread_z(h->aux[1], p, h->fp64);
-  launch_pair_elec(h->aux[0], q, h->fp64, ev, adj);
-  if (h->yx_fused) {
-    launch_fft_yx_conv(h->aux[1], p, h->fp64, ev);
-  } else {
-    launch_fft_y(h->aux[1], p, h->fp64, false);
-    launch_fft_x_conv(h->aux[1], p, h->fp64, ev);
-    launch_fft_y(h->aux[1], p, h->fp64, true);
+  // Stream of each part by layout (gcme_tuning.stream_layout).  A
+  // dependency between streams costs several microseconds in a captured
+  // graph, against about two within one, so fewer branches can win even
+  // though the parts then overlap less.  Parts are issued in the order
+  // listed (a captured graph submits its nodes in that order).
+  const int lay = h->tune.stream_layout;
+  hipStream_t sg = s, sq = h->aux[0], sp = h->aux[1];
+  if (lay == 1) {
+    sq = s;
+  } else if (lay >= 2) {
+    sp = s;
+    sg = h->aux[0];
+    sq = h->aux[0];
   }
-  launch_z_gather(h->aux[1], p, h->fp64);
-  (void)hipEventRecord(h->ev_join[0], h->aux[0]);
-  (void)hipEventRecord(h->ev_join[1], h->aux[1]);
-  (void)hipStreamWaitEvent(s, h->ev_join[0], 0);
-  (void)hipStreamWaitEvent(s, h->ev_join[1], 0);
+  (void)hipEventRecord(h->ev_fork, s);
+  if (sq != s || sg != s) (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
+  if (sp != s) (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
+  PairLaunch q = pair_args(h, true);
+  PmeLaunch p = pme_args(h);
+  auto gcm = [&]() {
+    launch_nl_build(sg, g);
+    launch_pair_gcm(sg, g, h->fp64, ev, adj);
+  };
+  auto elec = [&]() {
+    launch_nl_build(sq, q);
+    launch_pair_elec(sq, q, h->fp64, ev, adj);
+  };
+  auto mesh = [&]() {
+    launch_spread_z(sp, p, h->fp64);
+    if (h->yx_fused) {
+      launch_fft_yx_conv(sp, p, h->fp64, ev);
+    } else {
+      launch_fft_y(sp, p, h->fp64, false);
+      launch_fft_x_conv(sp, p, h->fp64, ev);
+      launch_fft_y(sp, p, h->fp64, true);
+    }
+    launch_z_gather(sp, p, h->fp64);
+  };
+  if (lay == 2) {
+    mesh();
+    elec();
+    gcm();
+  } else {
+    gcm();
+    elec();
+    mesh();
+  }
+  if (sq != s || sg != s) {
+    (void)hipEventRecord(h->ev_join[0], h->aux[0]);
+    (void)hipStreamWaitEvent(s, h->ev_join[0], 0);
+  }
+  if (sp != s) {
+    (void)hipEventRecord(h->ev_join[1], h->aux[1]);
+    (void)hipStreamWaitEvent(s, h->ev_join[1], 0);
+  }
 }
 
 void enqueue_outputs(gcme_handle h, hipStream_t s, const gcme_io* io, bool kin) {
@@ -1251,6 +1281,12 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
     if (t->direct_pairs > 3) return fail(h, GCME_EINVAL, "direct_pairs in 0..3");
     n.direct_pairs = t->direct_pairs;
   }
+  if (t->stream_layout >= 0) {
+    if (t->stream_layout > 3) return fail(h, GCME_EINVAL, "stream_layout in 0..3");
+    if (t->stream_layout != h->tune.stream_layout) h->drop_graphs();  // no new plan needed
+    n.stream_layout = t->stream_layout;
+    h->tune.stream_layout = n.stream_layout;
+  }
   if (n.cells_per_cutoff != h->tune.cells_per_cutoff || n.beads_per_cluster != h->tune.beads_per_cluster ||
       n.charges_per_cluster != h->tune.charges_per_cluster || n.list_slack_pct != h->tune.list_slack_pct ||
       n.direct_pairs != h->tune.direct_pairs) {
@@ -1294,15 +1330,17 @@ gcme_status gcme_autotune(gcme_handle h) {
   st = ensure_forces(h);
   if (st != GCME_OK) return st;
   hipStream_t s = h->stream;
-  gcme_tuning best = h->tune;
-  double best_t = 1e30;
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
-  // time one full evaluation per candidate (forces only), on the current state
+  // every candidate is timed on the current state (forces only); the forces
+  // are restored afterwards
   DevBuf saveF;
   HIPCHK(h, saveF.alloc((size_t)h->N * 24));
   HIPCHK(h, hipMemcpyAsync(saveF.p, h->F.p, (size_t)h->N * 24, hipMemcpyDeviceToDevice, s));
+  const int keep_layout = h->tune.stream_layout;
+  // 1. stream-launched evaluations over cell size, cluster sizes and lists
+  std::vector<std::pair<float, gcme_tuning>> cands;
   const int ncc_list[] = {2, 3, 4};
   const int ci_list[] = {2, 4, 8};
   for (int ncc : ncc_list)
@@ -1310,7 +1348,7 @@ gcme_status gcme_autotune(gcme_handle h) {
       for (int cq : ci_list)
         for (int dp = 0; dp < 4; ++dp) {
           if (h->NQ == 0 && (cq != ci_list[0] || dp > 1)) continue;
-          gcme_tuning t{ncc, cg, cq, -1, dp};
+          gcme_tuning t{ncc, cg, cq, -1, dp, keep_layout};
           if (gcme_set_tuning(h, &t) != GCME_OK) continue;
           if (build_plan(h) != GCME_OK) continue;
           float ms = 0;
@@ -1324,11 +1362,47 @@ gcme_status gcme_autotune(gcme_handle h) {
             (void)hipEventElapsedTime(&m, e0, e1);
             if (rep > 0) ms += m;
           }
-          if (ms < best_t) {
-            best_t = ms;
-            best = t;
-          }
+          cands.push_back({ms, t});
         }
+  std::sort(cands.begin(), cands.end(),
+            [](const std::pair<float, gcme_tuning>& x, const std::pair<float, gcme_tuning>& y) { return x.first < y.first; });
+  gcme_tuning best = cands.empty() ? h->tune : cands[0].second;
+  // 2. the best few in every stream layout, as replays of a captured
+  //    evaluation graph (stream dependencies cost differently there)
+  if (h->NQ > 0) {
+    float best_t = 1e30f;
+    const size_t top = std::min<size_t>(cands.size(), 6);
+    for (size_t c = 0; c < top; ++c) {
+      for (int lay = 0; lay < 4; ++lay) {
+        gcme_tuning t = cands[c].second;
+        t.stream_layout = lay;
+        if (gcme_set_tuning(h, &t) != GCME_OK) continue;
+        if (build_plan(h) != GCME_OK) continue;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) continue;
+        launch_fill_i64(h->cap_stream, h->F.as<long long>(), 0, 3LL * h->N);
+        enqueue_eval(h, h->cap_stream, false, false);
+        if (hipStreamEndCapture(h->cap_stream, &g) != hipSuccess) continue;
+        const bool ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipGraphDestroy(g);
+        if (!ok) continue;
+        constexpr int WARM = 3, REPS = 10;
+        for (int r = 0; r < WARM; ++r) (void)hipGraphLaunch(ex, s);
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < REPS; ++r) (void)hipGraphLaunch(ex, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float m = 0;
+        (void)hipEventElapsedTime(&m, e0, e1);
+        (void)hipGraphExecDestroy(ex);
+        if (m < best_t) {
+          best_t = m;
+          best = t;
+        }
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   gcme_set_tuning(h, &best);
@@ -1336,6 +1410,7 @@ gcme_status gcme_autotune(gcme_handle h) {
   if (st != GCME_OK) return st;
   HIPCHK(h, hipMemcpyAsync(h->F.p, saveF.p, (size_t)h->N * 24, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  HIPCHK(h, hipGetLastError());
   return GCME_OK;
 }
 

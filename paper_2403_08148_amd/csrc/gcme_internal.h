@@ -104,6 +104,11 @@ struct Tile {
                // replica are consecutive runs of CI beads, the last one short)
 };
 
+// Workgroup size of the one-thread-per-bead kernels (binning, scatter,
+// permute, integrator halves): one wavefront, so that even the 32,768-bead
+// workloads spread over every compute unit.
+constexpr int BEAD_THREADS = 256;
+
 // Slots of the per-block partial sums (7 doubles: energy, virial[6]).
 enum { SLOT_GCM = 0, SLOT_REAL = 1, SLOT_RECIP = 2, SLOT_KIN = 3, N_SLOTS = 4 };
 constexpr int PART_W = 8;

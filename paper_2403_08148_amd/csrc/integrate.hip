@@ -106,7 +106,7 @@ __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* 
 // sorted copy B), then the first half of the next step (as k_int_first) and
 // its binning, written to A.  The step counter advances once every block has
 // read it.
-__global__ __launch_bounds__(256) void k_int_between(IntLaunch a, StateView B, StateView A, long long* F0,
+__global__ __launch_bounds__(BEAD_THREADS) void k_int_between(IntLaunch a, StateView B, StateView A, long long* F0,
                                                      long long* F1, long long* F2, CellView c, int N) {
   __shared__ int last;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,16 +311,16 @@ inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
 
 void launch_int_first(hipStream_t s, const IntLaunch& a, StateView A, long long* const F[3], const CellView* bin) {
   if (bin)
-    hipLaunchKernelGGL(k_int_first<true>, dim3(nblk(a.nbeads, 256)), dim3(256), 0, s, a, A, F[0], F[1], F[2], *bin,
+    hipLaunchKernelGGL(k_int_first<true>, dim3(nblk(a.nbeads, BEAD_THREADS)), dim3(BEAD_THREADS), 0, s, a, A, F[0], F[1], F[2], *bin,
                        a.nbeads);
   else
-    hipLaunchKernelGGL(k_int_first<false>, dim3(nblk(a.nbeads, 256)), dim3(256), 0, s, a, A, F[0], F[1], F[2],
+    hipLaunchKernelGGL(k_int_first<false>, dim3(nblk(a.nbeads, BEAD_THREADS)), dim3(BEAD_THREADS), 0, s, a, A, F[0], F[1], F[2],
                        CellView{}, a.nbeads);
 }
 
 void launch_int_between(hipStream_t s, const IntLaunch& a, StateView B, StateView A, long long* const F[3],
                         const CellView& bin) {
-  hipLaunchKernelGGL(k_int_between, dim3(nblk(a.nbeads, 256)), dim3(256), 0, s, a, B, A, F[0], F[1], F[2], bin,
+  hipLaunchKernelGGL(k_int_between, dim3(nblk(a.nbeads, BEAD_THREADS)), dim3(BEAD_THREADS), 0, s, a, B, A, F[0], F[1], F[2], bin,
                      a.nbeads);
 }
 

@@ -813,22 +813,31 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
         if (lane >= n) base[lane] = make_uint4(far, far, far, 0u);
         __builtin_amdgcn_wave_barrier();
       }
-      uint4 pp[CI];
+      // the lane's CI entries in groups of at most four (the records of a
+      // group are read together; fewer live registers for CI = 8)
+      constexpr int G = CI < 4 ? CI : 4;
 #pragma unroll
-      for (int k = 0; k < CI; ++k) pp[k] = base[jl + k * CJ];
-      if (rel) {
+      for (int k0 = 0; k0 < CI; k0 += G) {
+        uint4 pp[G];
 #pragma unroll
-        for (int k = 0; k < CI; ++k) {
-          const T dx = (T)(rxi - __uint_as_float(pp[k].x));
-          const T dy = (T)(ryi - __uint_as_float(pp[k].y));
-          const T dz = (T)(rzi - __uint_as_float(pp[k].z));
-          pair_at<T, ELEC, EV, ADJ, COUNT>(L, P, dx, dy, dz, pp[k].w,
-                                           BARE || (vi && jl + k * CJ < n && (pp[k].w >> 16) != self));
+        for (int g = 0; g < G; ++g) pp[g] = base[jl + (k0 + g) * CJ];
+        if (rel) {
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int k = k0 + g;
+            const T dx = (T)(rxi - __uint_as_float(pp[g].x));
+            const T dy = (T)(ryi - __uint_as_float(pp[g].y));
+            const T dz = (T)(rzi - __uint_as_float(pp[g].z));
+            pair_at<T, ELEC, EV, ADJ, COUNT>(L, P, dx, dy, dz, pp[g].w,
+                                             BARE || (vi && jl + k * CJ < n && (pp[g].w >> 16) != self));
+          }
+        } else {
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int k = k0 + g;
+            try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[g], vi && jl + k * CJ < n && (pp[g].w >> 16) != self);
+          }
         }
-      } else {
-#pragma unroll
-        for (int k = 0; k < CI; ++k)
-          try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[k], vi && jl + k * CJ < n && (pp[k].w >> 16) != self);
       }
       head += n;
     };

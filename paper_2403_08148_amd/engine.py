@@ -180,11 +180,12 @@ class GCMe:
         B.check(self.h, self.lib.gcme_get_tuning(self.h, C.byref(t)))
         return dict(cells_per_cutoff=t.cells_per_cutoff, beads_per_cluster=t.beads_per_cluster,
                     charges_per_cluster=t.charges_per_cluster, list_slack_pct=t.list_slack_pct,
-                    direct_pairs=t.direct_pairs)
+                    direct_pairs=t.direct_pairs, stream_layout=t.stream_layout)
 
     def set_tuning(self, cells_per_cutoff=-1, beads_per_cluster=-1, charges_per_cluster=-1, list_slack_pct=-1,
-                   direct_pairs=-1):
-        t = B.gcme_tuning(cells_per_cutoff, beads_per_cluster, charges_per_cluster, list_slack_pct, direct_pairs)
+                   direct_pairs=-1, stream_layout=-1):
+        t = B.gcme_tuning(cells_per_cutoff, beads_per_cluster, charges_per_cluster, list_slack_pct, direct_pairs,
+                          stream_layout)
         B.check(self.h, self.lib.gcme_set_tuning(self.h, C.byref(t)))
 
     def profile_step(self, n_reps: int = 10) -> dict:

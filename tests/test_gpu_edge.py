@@ -158,18 +158,19 @@ def test_velocity_verlet_trajectory_fp64():
     assert gpu_drift < 2.0 * ora_drift + 1e-9 * abs(gtot[1])
 
 
+@pytest.mark.parametrize("layout", [0, 2])
 @pytest.mark.parametrize("gamma", [0.0, 1.0])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_fused_steps_equal_single_steps(precision, gamma):
+def test_fused_steps_equal_single_steps(precision, gamma, layout):
     # A run of n steps fuses each step's second half kick with the next
     # step's first half and binning; n runs of one step do not.  The
     # arithmetic is the same, so the trajectories agree bit for bit.
     w = W.small_bulk(N=900, seed=8, charged_frac=0.3, box=(7.1, 7.3, 6.9), rc=2.5, grid=(24, 24, 24))
     w.gamma = gamma
-    print(f"case fused steps prec={precision} gamma={gamma}", flush=True)
+    print(f"case fused steps prec={precision} gamma={gamma} layout={layout}", flush=True)
     runs = []
     for split in (False, True):
-        eng = make_engine([w], precision, seed=5)
+        eng = make_engine([w], precision, seed=5, tuning=dict(stream_layout=layout))
         if split:
             for _ in range(12):
                 eng.step(1)
