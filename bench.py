@@ -180,7 +180,7 @@ def main():
     dom = max(stage_roof, key=lambda k: stages[k])
     roof = dict(stage_roof[dom])
     roof["launch_us"] = stages[dom] * 1e3
-    roof["traffic"] = measured_traffic(dom)
+    roof["traffic"] = measured_traffic(dom, tuning) if args.precision == "mixed" else None
     # the excluded-volume pair kernel's own figure is always reported
     gcm_tflops = stage_roof["pair_gcm"]["achieved"]
 
@@ -329,12 +329,12 @@ def charged_pairs(eng, w):
     return int(len(cKDTree(q, boxsize=w.box).query_pairs(w.rc)))
 
 
-def measured_traffic(stage):
+def measured_traffic(stage, tuning):
     """HBM bytes per launch of a stage from committed rocprofv3 counter runs
     (profiles/traffic_<stage>.json: FETCH_SIZE and WRITE_SIZE in KiB per
-    dispatch, each scaled by what the counter reads for a plain device copy of
-    known size), or None when no run exists or the kernel source changed
-    since it was taken."""
+    dispatch for the kernel under each measured tuning, each scaled by what the
+    counter reads for a plain device copy of known size), or None when no run
+    matches the tuning or the kernel source changed since the runs."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{stage}.json")
     if not os.path.exists(path):
@@ -345,9 +345,15 @@ def measured_traffic(stage):
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
+    # the excluded-volume pair kernel is set by the cell size, the cluster
+    # size and the list choice
+    key = f"{tuning['cells_per_cutoff']},{tuning['beads_per_cluster']},{tuning.get('direct_pairs', 0) & 1}"
+    run = next((r for r in t["runs"] if r["key"] == key), None)
+    if run is None:
+        return None
     cb = float(t["copy_bytes"])
-    fetch = t["fetch_kib"] * 1024.0 * cb / (t["copy_fetch_kib"] * 1024.0)
-    write = t["write_kib"] * 1024.0 * cb / (t["copy_write_kib"] * 1024.0)
+    fetch = run["fetch_kib"] * 1024.0 * cb / (t["copy_fetch_kib"] * 1024.0)
+    write = run["write_kib"] * 1024.0 * cb / (t["copy_write_kib"] * 1024.0)
     return fetch + write
 
 
