@@ -1367,14 +1367,27 @@ gcme_status gcme_autotune(gcme_handle h) {
   std::sort(cands.begin(), cands.end(),
             [](const std::pair<float, gcme_tuning>& x, const std::pair<float, gcme_tuning>& y) { return x.first < y.first; });
   gcme_tuning best = cands.empty() ? h->tune : cands[0].second;
-  // 2. the best few in every stream layout, as replays of a captured
-  //    evaluation graph (stream dependencies cost differently there)
+  // 2. the best few, with every charged-cluster size and stream layout, as
+  //    replays of a captured evaluation graph (stream dependencies cost
+  //    differently there, and a layout that runs the two pair kernels one
+  //    after the other exposes the charged kernel's own time)
   if (h->NQ > 0) {
     float best_t = 1e30f;
-    const size_t top = std::min<size_t>(cands.size(), 6);
-    for (size_t c = 0; c < top; ++c) {
-      for (int lay = 0; lay < 4; ++lay) {
+    std::vector<gcme_tuning> second;
+    for (size_t c = 0; c < cands.size() && second.size() < 4 * 3; ++c) {
+      for (int cq : ci_list) {
         gcme_tuning t = cands[c].second;
+        t.charges_per_cluster = cq;
+        bool dup = false;
+        for (const gcme_tuning& u : second)
+          dup = dup || (u.cells_per_cutoff == t.cells_per_cutoff && u.beads_per_cluster == t.beads_per_cluster &&
+                        u.charges_per_cluster == t.charges_per_cluster && u.direct_pairs == t.direct_pairs);
+        if (!dup) second.push_back(t);
+      }
+    }
+    for (const gcme_tuning& base : second) {
+      for (int lay = 0; lay < 4; ++lay) {
+        gcme_tuning t = base;
         t.stream_layout = lay;
         if (gcme_set_tuning(h, &t) != GCME_OK) continue;
         if (build_plan(h) != GCME_OK) continue;
