@@ -329,21 +329,32 @@ def charged_pairs(eng, w):
     return int(len(cKDTree(q, boxsize=w.box).query_pairs(w.rc)))
 
 
+def code_digest(text):
+    """sha256 of source text without // comments, blank lines and repeated
+    whitespace: changes when the code changes, not when a comment does."""
+    import hashlib
+    import re
+    lines = []
+    for line in text.split("\n"):
+        line = re.sub(r"//.*", "", line).strip()
+        if line:
+            lines.append(" ".join(line.split()))
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def measured_traffic(stage, tuning):
     """HBM bytes per launch of a stage from committed rocprofv3 counter runs
     (profiles/traffic_<stage>.json: FETCH_SIZE and WRITE_SIZE in KiB per
     dispatch for the kernel under each measured tuning, each scaled by what the
     counter reads for a plain device copy of known size), or None when no run
     matches the tuning or the kernel source changed since the runs."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{stage}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    src = os.path.join(ROOT, t["source"])
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+    with open(os.path.join(ROOT, t["source"])) as f:
+        if code_digest(f.read()) != t["source_code_sha256"]:
             return None
     # the excluded-volume pair kernel is set by the cell size, the cluster
     # size and the list choice

@@ -7,9 +7,10 @@
 //    term costs nothing for neutral beads and the kernels never branch on
 //    charge.
 //
-// Both run in two launches per evaluation over "clusters": CI consecutive
-// beads of the cell-sorted order (CI = 2, 4 or 8; spatially compact because
-// the order is by cell).
+// Both work on "clusters": CI consecutive beads of the cell-sorted order
+// (CI = 2, 4 or 8; spatially compact because the order is by cell), one
+// wavefront per cluster, either with a neighbour list in HBM (two launches)
+// or list-free (one launch, k_pair_fused):
 //
 //  1. k_nl_build: one wavefront per cluster.  The lanes enumerate the cell
 //     columns within reach of the cluster's bounding box (culled by the exact
@@ -26,6 +27,10 @@
 //     from both ends (no scatter of forces to j); the partial forces of a bead
 //     are combined with xor shuffles in a fixed order and added once to the
 //     64-bit fixed-point accumulator.
+//
+//  k_pair_fused does both in one pass: the candidates that pass the list
+//  test go to a small LDS ring instead of HBM, and every 64 of them are
+//  evaluated at once with the force pass's lane layout.
 //
 // Lists are rebuilt every evaluation, so they need no skin.  The minimum
 // image is the wrapped 32-bit difference of the fractional fixed-point
