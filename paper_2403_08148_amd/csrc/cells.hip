@@ -41,11 +41,12 @@ __global__ void k_fill(I* p, I v, long long n) {
 }
 
 __global__ void k_bin(StateView A, const RepDesc* __restrict__ rep, CellView c, int N) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= N) return;
-  uint32_t p = A.param[s];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = s < N;
+  const int si = active ? s : 0;
+  const uint32_t p = A.param[si];
   const RepDesc& R = rep[param_rep(p)];
-  bin_bead(c, R, A.pos[0][s], A.pos[1][s], A.pos[2][s], p, s);
+  bin_bead(c, R, A.pos[0][si], A.pos[1][si], A.pos[2][si], p, s, active);
 }
 
 constexpr int SCAN_THREADS = 256;
@@ -211,10 +212,12 @@ __global__ void k_scan_apply(CellView c, int nb) {
 }
 
 __global__ void k_scatter(CellView c, int N) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= N) return;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = s < N;
+  const int cid = active ? c.cell[s] : 0;
   // fill holds the cell's next free slot (initialised to start by the scan)
-  c.tmp[atomicAdd(&c.fill[c.cell[s]], 1)] = s;
+  const int slot = run_atomic_add(c.fill, cid, active);
+  if (active) c.tmp[slot] = s;
 }
 
 // Position p of the scattered array holds bead s of cell c in arbitrary

@@ -152,13 +152,36 @@ __device__ inline int cell_of(const RepDesc& R, uint32_t ux, uint32_t uy, uint32
   return R.cell_off + (cx * R.nc[1] + cy) * R.nc[2] + cz;
 }
 
+// counts[key] += 1 for every lane with `active`, as one atomic per run of
+// consecutive lanes with the same key (beads kept in cell order put runs of
+// one cell in consecutive lanes; same-address atomics would serialise).
+// Returns the counter's value before this lane's share, lanes of a run
+// taking consecutive values in lane order.  Every lane of the wavefront must
+// call it.
+__device__ inline int run_atomic_add(int* counts, int key, bool active) {
+  const int lane = threadIdx.x & 63;
+  const int k = active ? key : -1 - lane;  // inactive lanes never join a run
+  const int prev = __shfl_up(k, 1, 64);
+  const bool head = lane == 0 || prev != k;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int start = 63 - __clzll((long long)(heads & upto));
+  const unsigned long long above = heads & ~upto;
+  const int end = above ? __ffsll((long long)above) - 1 : 64;
+  int old = 0;
+  if (head && active) old = atomicAdd(&counts[key], end - start);
+  old = __shfl(old, start, 64);
+  return old + (lane - start);
+}
+
 // Record bead s's cell and count it (and, if charged, among the charged).
+// Every lane of the wavefront must call it (inactive lanes: active false).
 __device__ inline void bin_bead(const CellView& c, const RepDesc& R, uint32_t ux, uint32_t uy, uint32_t uz,
-                                uint32_t prm, int s) {
-  const int cid = cell_of(R, ux, uy, uz);
-  c.cell[s] = cid;
-  atomicAdd(&c.counts[cid], 1);
-  if (param_z(prm) != 0) atomicAdd(&c.qcounts[cid], 1);
+                                uint32_t prm, int s, bool active) {
+  const int cid = active ? cell_of(R, ux, uy, uz) : 0;
+  if (active) c.cell[s] = cid;
+  (void)run_atomic_add(c.counts, cid, active);
+  (void)run_atomic_add(c.qcounts, cid, active && param_z(prm) != 0);
 }
 
 // Packed copy of a sorted bead: x, y, z (fractional fixed point), param.

@@ -78,8 +78,10 @@ __device__ inline void first_half(const IntLaunch& a, const RepDesc& R, int r, i
 template <bool BIN>
 __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* F1, long long* F2, CellView c,
                             int N) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= N) return;
+  const int s0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = s0 < N;
+  if (!BIN && !active) return;
+  const int s = active ? s0 : 0;  // inactive lanes of the last wavefront only take part in the binning
   const uint32_t prm = A.param[s];
   const int r = param_rep(prm), t = param_type(prm);
   const RepDesc& R = a.rep[r];
@@ -89,17 +91,19 @@ __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* 
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     f[k] = (double)Fk[k][s] * a.fscale_inv;
-    Fk[k][s] = 0;
+    if (active) Fk[k][s] = 0;
     v[k] = A.vel[k][s];
     u[k] = A.pos[k][s];
   }
   first_half(a, R, r, t, *a.step, A.id[s], f, v, u);
+  if (active) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    A.pos[k][s] = u[k];
-    A.vel[k][s] = v[k];
+    for (int k = 0; k < 3; ++k) {
+      A.pos[k][s] = u[k];
+      A.vel[k][s] = v[k];
+    }
   }
-  if (BIN) bin_bead(c, R, u[0], u[1], u[2], prm, s);
+  if (BIN) bin_bead(c, R, u[0], u[1], u[2], prm, s, active);
 }
 
 // The second half kick of the step just completed (as k_int_last, on the
@@ -111,8 +115,11 @@ __global__ __launch_bounds__(BEAD_THREADS) void k_int_between(IntLaunch a, State
   __shared__ int last;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned long long step = *a.step;
-  if (s < N) {
-    const uint32_t prm = B.param[s];
+  const bool active = s < N;
+  int cid = 0;
+  uint32_t prm = 0;
+  if (active) {
+    prm = B.param[s];
     const int r = param_rep(prm), t = param_type(prm);
     const RepDesc& R = a.rep[r];
     const double im = a.inv_mass[r * MAXT + t];
@@ -137,8 +144,12 @@ __global__ __launch_bounds__(BEAD_THREADS) void k_int_between(IntLaunch a, State
     }
     A.param[s] = prm;
     A.id[s] = id;
-    bin_bead(c, R, u[0], u[1], u[2], prm, s);
+    cid = cell_of(R, u[0], u[1], u[2]);
+    c.cell[s] = cid;
   }
+  // the binning's counts, one atomic per run of equal cells in the wavefront
+  (void)run_atomic_add(c.counts, cid, active);
+  (void)run_atomic_add(c.qcounts, cid, active && param_z(prm) != 0);
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
