@@ -23,10 +23,11 @@ def big():
     print(f"case {w.name} N={w.N} grid={w.grid}", flush=True)
     got = {}
     for prec in ("mixed", "fp64"):
-        eng = make_engine([w], prec)
-        got[prec] = gpu_eval(eng)
-        eng.close()
-        print(f"  gpu {prec} done", flush=True)
+        for direct in (3, 0):  # list-free pair kernels, neighbour lists
+            eng = make_engine([w], prec, tuning=dict(direct_pairs=direct))
+            got[(prec, direct)] = gpu_eval(eng)
+            eng.close()
+            print(f"  gpu {prec} direct_pairs={direct} done", flush=True)
     p = oracle_params(w)
     idx = np.sort(np.random.default_rng(404).choice(w.N, 600, replace=False))
     rs = O.real_space(w.pos, w.type, w.z, p, sample=idx, energies=False)
@@ -44,16 +45,17 @@ def big():
     return w, got, idx, F_ref, E_ref, W_ref
 
 
+@pytest.mark.parametrize("direct", [3, 0])
 @pytest.mark.parametrize("precision,ftol,etol", [("fp64", 1e-9, 1e-10), ("mixed", 1e-5, 1e-6)])
-def test_two_million_beads_against_oracle(big, precision, ftol, etol):
+def test_two_million_beads_against_oracle(big, precision, ftol, etol, direct):
     w, got, idx, F_ref, E_ref, W_ref = big
-    g = got[precision]
+    g = got[(precision, direct)]
     ferr = rel_rms(g["force"][idx], F_ref)
     eerr = energy_errors(g["energy"][0][:5], E_ref)
     wscale = np.linalg.norm(W_ref) + np.abs(E_ref[:3]).sum()
     werr = np.linalg.norm(g["virial"][0] - W_ref) / wscale
-    print(f"  {precision}: sampled force {ferr:.2e} energies {np.array2string(eerr, precision=2)} virial {werr:.2e}",
-          flush=True)
+    print(f"  {precision} direct_pairs={direct}: sampled force {ferr:.2e} energies "
+          f"{np.array2string(eerr, precision=2)} virial {werr:.2e}", flush=True)
     assert ferr < ftol
     assert np.all(eerr < etol), eerr
     assert werr < 10 * max(ftol, etol)
@@ -61,9 +63,14 @@ def test_two_million_beads_against_oracle(big, precision, ftol, etol):
 
 def test_two_million_beads_mixed_against_fp64(big):
     w, got, idx, F_ref, E_ref, W_ref = big
-    ferr = rel_rms(got["mixed"]["force"], got["fp64"]["force"])
-    print(f"  mixed vs fp64 GPU, all {w.N} beads: force {ferr:.2e}", flush=True)
-    assert ferr < 1e-5
+    for direct in (3, 0):
+        ferr = rel_rms(got[("mixed", direct)]["force"], got[("fp64", direct)]["force"])
+        print(f"  mixed vs fp64 GPU, all {w.N} beads, direct_pairs={direct}: force {ferr:.2e}", flush=True)
+        assert ferr < 1e-5
+    # both pair paths in FP64: the same pairs, sums in another order
+    ferr = rel_rms(got[("fp64", 3)]["force"], got[("fp64", 0)]["force"])
+    print(f"  list-free vs lists, FP64, all beads: force {ferr:.2e}", flush=True)
+    assert ferr < 1e-12
 
 
 @pytest.mark.parametrize("precision,ftol,etol", [("fp64", 1e-9, 1e-10), ("mixed", 1e-5, 1e-6)])

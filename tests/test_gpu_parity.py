@@ -44,9 +44,12 @@ def test_small_box_parity(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("tuning", [dict(cells_per_cutoff=1, beads_per_cluster=2, charges_per_cluster=8),
-                                    dict(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=2),
-                                    dict(cells_per_cutoff=4, beads_per_cluster=4, charges_per_cluster=4),
+@pytest.mark.parametrize("tuning", [dict(cells_per_cutoff=1, beads_per_cluster=2, charges_per_cluster=8,
+                                         direct_pairs=0, stream_layout=0),
+                                    dict(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=2,
+                                         direct_pairs=0, stream_layout=0),
+                                    dict(cells_per_cutoff=4, beads_per_cluster=4, charges_per_cluster=4,
+                                         direct_pairs=0, stream_layout=0),
                                     dict(cells_per_cutoff=1, beads_per_cluster=8, charges_per_cluster=2,
                                          direct_pairs=3),
                                     dict(cells_per_cutoff=2, beads_per_cluster=2, charges_per_cluster=4,
