@@ -177,14 +177,20 @@ typedef struct {
                                     bit 1 real-space electrostatics (0..3) */
     int32_t stream_layout;       /* how the three independent parts of a force
                                     evaluation (excluded-volume pairs, charged
-                                    pairs, mesh chain) share streams (0..3):
+                                    pairs, mesh chain) share streams (0..5):
                                     0: each on its own stream;
                                     1: the pairs on the context's stream, the
                                        mesh chain on a second one;
                                     2: the mesh chain on the context's stream,
                                        charged then excluded-volume pairs on a
                                        second one;
-                                    3: as 2, excluded-volume pairs first */
+                                    3: as 2, excluded-volume pairs first;
+                                    4: excluded-volume pairs on the context's
+                                       stream, the mesh chain then the charged
+                                       pairs on a second one;
+                                    5: the mesh chain then the charged pairs on
+                                       the context's stream, the
+                                       excluded-volume pairs on a second one */
 } gcme_tuning;
 
 gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t);

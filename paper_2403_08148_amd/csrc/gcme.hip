@@ -782,18 +782,21 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   // graph, against about two within one, so fewer branches can win even
   // though the parts then overlap less.  Parts are issued in the order
   // listed (a captured graph submits its nodes in that order).
-  const int lay = h->tune.stream_layout;
-  hipStream_t sg = s, sq = h->aux[0], sp = h->aux[1];
-  if (lay == 1) {
-    sq = s;
-  } else if (lay >= 2) {
-    sp = s;
-    sg = h->aux[0];
-    sq = h->aux[0];
-  }
+  //   layout: excluded-volume pairs, charged pairs, mesh chain (0 = the
+  //   context's stream, 1 and 2 = the second and third), issue order
+  struct Layout {
+    int g, q, p;
+    char order[4];
+  };
+  static const Layout kLayouts[6] = {{0, 1, 2, "gqp"}, {0, 0, 2, "gqp"}, {1, 1, 0, "pqg"},
+                                     {1, 1, 0, "gqp"}, {0, 1, 1, "gpq"}, {1, 0, 0, "gpq"}};
+  const Layout& L = kLayouts[h->tune.stream_layout];
+  hipStream_t st3[3] = {s, h->aux[0], h->aux[1]};
+  hipStream_t sg = st3[L.g], sq = st3[L.q], sp = st3[L.p];
+  const bool use1 = L.g == 1 || L.q == 1 || L.p == 1, use2 = L.g == 2 || L.q == 2 || L.p == 2;
   (void)hipEventRecord(h->ev_fork, s);
-  if (sq != s || sg != s) (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
-  if (sp != s) (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
+  if (use1) (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
+  if (use2) (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
   PairLaunch q = pair_args(h, true);
   PmeLaunch p = pme_args(h);
   auto gcm = [&]() {
@@ -815,20 +818,16 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
     }
     launch_z_gather(sp, p, h->fp64);
   };
-  if (lay == 2) {
-    mesh();
-    elec();
-    gcm();
-  } else {
-    gcm();
-    elec();
-    mesh();
+  for (int k = 0; k < 3; ++k) {
+    if (L.order[k] == 'g') gcm();
+    if (L.order[k] == 'q') elec();
+    if (L.order[k] == 'p') mesh();
   }
-  if (sq != s || sg != s) {
+  if (use1) {
     (void)hipEventRecord(h->ev_join[0], h->aux[0]);
     (void)hipStreamWaitEvent(s, h->ev_join[0], 0);
   }
-  if (sp != s) {
+  if (use2) {
     (void)hipEventRecord(h->ev_join[1], h->aux[1]);
     (void)hipStreamWaitEvent(s, h->ev_join[1], 0);
   }
@@ -1282,7 +1281,7 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
     n.direct_pairs = t->direct_pairs;
   }
   if (t->stream_layout >= 0) {
-    if (t->stream_layout > 3) return fail(h, GCME_EINVAL, "stream_layout in 0..3");
+    if (t->stream_layout > 5) return fail(h, GCME_EINVAL, "stream_layout in 0..5");
     if (t->stream_layout != h->tune.stream_layout) h->drop_graphs();  // no new plan needed
     n.stream_layout = t->stream_layout;
     h->tune.stream_layout = n.stream_layout;
@@ -1386,7 +1385,7 @@ gcme_status gcme_autotune(gcme_handle h) {
       }
     }
     for (const gcme_tuning& base : second) {
-      for (int lay = 0; lay < 4; ++lay) {
+      for (int lay = 0; lay < 6; ++lay) {
         gcme_tuning t = base;
         t.stream_layout = lay;
         if (gcme_set_tuning(h, &t) != GCME_OK) continue;

@@ -61,7 +61,11 @@ def test_small_box_parity(precision):
                                     dict(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=4,
                                          direct_pairs=1, stream_layout=2),
                                     dict(cells_per_cutoff=2, beads_per_cluster=4, charges_per_cluster=4,
-                                         direct_pairs=0, stream_layout=3)])
+                                         direct_pairs=0, stream_layout=3),
+                                    dict(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=2,
+                                         direct_pairs=2, stream_layout=4),
+                                    dict(cells_per_cutoff=4, beads_per_cluster=2, charges_per_cluster=4,
+                                         direct_pairs=3, stream_layout=5)])
 def test_tunings_parity(precision, tuning):
     w = W.small_bulk(N=1001, seed=4, charged_frac=0.25, a_types=(0.3, 0.5, 0.7), box=(7.7, 8.3, 6.5),
                      rc=2.6, grid=(27, 36, 24), order=4)
