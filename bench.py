@@ -27,6 +27,9 @@ TAU_PS = 3.18
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+# VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes per cycle)
+PEAK_VALU_GINSTR = 256 * 4 * 2.4 / 4 * 1000.0
 
 # Algorithmic FP operations per unordered pair within the cutoff (both
 # forces by Newton's third law): separation 3, r^2 5, exponent 1, exp 1,
@@ -181,6 +184,11 @@ def main():
     roof = dict(stage_roof[dom])
     roof["launch_us"] = stages[dom] * 1e3
     roof["traffic"] = measured_traffic(dom, tuning) if args.precision == "mixed" else None
+    vi = measured_valu(dom, tuning) if args.precision == "mixed" else None
+    if vi is not None:
+        ach = vi / (stages[dom] * 1e-3) / 1e9
+        roof["valu_issue"] = {"instr_per_launch": vi, "achieved": ach, "peak": PEAK_VALU_GINSTR,
+                              "unit": "G wave-instr/s", "frac": ach / PEAK_VALU_GINSTR}
     # the excluded-volume pair kernel's own figure is always reported
     gcm_tflops = stage_roof["pair_gcm"]["achieved"]
 
@@ -366,6 +374,23 @@ def measured_traffic(stage, tuning):
     fetch = run["fetch_kib"] * 1024.0 * cb / (t["copy_fetch_kib"] * 1024.0)
     write = run["write_kib"] * 1024.0 * cb / (t["copy_write_kib"] * 1024.0)
     return fetch + write
+
+
+def measured_valu(stage, tuning):
+    """VALU wavefront instructions per launch of a stage's kernel from the
+    committed counter runs (profiles/valu_<stage>.json), or None when no run
+    matches the tuning or the kernel source changed since the runs."""
+    path = os.path.join(ROOT, "profiles", f"valu_{stage}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    with open(os.path.join(ROOT, t["source"])) as f:
+        if code_digest(f.read()) != t["source_code_sha256"]:
+            return None
+    key = f"{tuning['cells_per_cutoff']},{tuning['beads_per_cluster']},{tuning.get('direct_pairs', 0) & 1}"
+    run = next((r for r in t["runs"] if r["key"] == key), None)
+    return None if run is None else float(run["valu_instr"])
 
 
 def cpu_baseline(w, pairs, budget_s=15.0):
