@@ -29,7 +29,7 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 # VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD
 # every 4 cycles (16 lanes per cycle)
-PEAK_VALU_GINSTR = 256 * 4 * 2.4 / 4 * 1000.0
+PEAK_VALU_GINSTR = 256 * 4 * 2.4 / 4  # = 614.4
 
 # Algorithmic FP operations per unordered pair within the cutoff (both
 # forces by Newton's third law): separation 3, r^2 5, exponent 1, exp 1,
