@@ -20,6 +20,7 @@
 // touch consecutive addresses.  The beads of a tile are found through the
 // charged beads' cell list (whole cell columns along z).
 #include <algorithm>
+#include <type_traits>
 
 #include "gcme_internal.h"
 
@@ -62,6 +63,23 @@ __device__ inline void bspline(T t, T* w, T* dw) {
 #pragma unroll
   for (int j = 0; j < P; ++j) w[j] = m[j];
 }
+
+// Integer form of the charge mesh while a tile is spread.  Single precision:
+// 32-bit integers at 2^-24 of a unit charge, so a point holds up to 128 unit
+// charges' worth (one bead adds z w_x w_y w_z, at most 0.42 |z|); 32-bit LDS
+// atomics and no double arithmetic, at a rounding of 3e-8 per contribution.
+// Double precision: 64-bit integers at the launch's qscale.
+template <typename T>
+struct MeshInt;
+template <>
+struct MeshInt<float> {
+  using U = unsigned int;
+  static constexpr float scale = 16777216.0f;  // 2^24
+};
+template <>
+struct MeshInt<double> {
+  using U = unsigned long long;
+};
 
 // Mesh coordinate of a fixed-point fractional position: integer cell and
 // fractional offset, exact up to the final rounding of the offset.
@@ -509,8 +527,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
   // integer accumulators of the tile, line l = lx * TY + ly, point l * K2 + z
   // (they live in B, which the transform first writes after they are read)
-  unsigned long long* acc = reinterpret_cast<unsigned long long*>(B);
-  for (int e = threadIdx.x; e < NL * K2; e += blockDim.x) acc[e] = 0ull;
+  using U = typename MeshInt<T>::U;
+  U* acc = reinterpret_cast<U*>(B);
+  for (int e = threadIdx.x; e < NL * K2; e += blockDim.x) acc[e] = 0;
   __syncthreads();
   const TileCols tc = tile_columns(R, mt, P);
   const double qs = a.qscale;
@@ -545,11 +564,17 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
         ly += ly < 0 ? K1 : 0;
         if (lx < nxt && ly < nyt) {
           const T axy = ax * w[1][jy];
-          unsigned long long* row = acc + (size_t)(lx * TY + ly) * K2;
+          U* row = acc + (size_t)(lx * TY + ly) * K2;
+          if constexpr (std::is_same<T, float>::value) {
+            const float axs = axy * MeshInt<float>::scale;  // exact: a power of two
 #pragma unroll
-          for (int jz = 0; jz < P; ++jz) {
-            const double v = (double)(axy * w[2][jz]) * qs;
-            atomicAdd(&row[g2s[jz]], (unsigned long long)(long long)llrint(v));
+            for (int jz = 0; jz < P; ++jz) atomicAdd(&row[g2s[jz]], (unsigned)(int)rintf(axs * w[2][jz]));
+          } else {
+#pragma unroll
+            for (int jz = 0; jz < P; ++jz) {
+              const double v = (double)(axy * w[2][jz]) * qs;
+              atomicAdd(&row[g2s[jz]], (unsigned long long)(long long)llrint(v));
+            }
           }
         }
       }
@@ -560,7 +585,10 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   const FDiv dk2(K2), dk2h(K2h);
   for (int e = threadIdx.x; e < NL * K2; e += blockDim.x) {
     const int l = dk2.div(e), k = e - l * K2;
-    A[k * LBP + l] = {(T)((double)(long long)acc[e] * inv_qs), (T)0};
+    if constexpr (std::is_same<T, float>::value)
+      A[k * LBP + l] = {(float)(int)acc[e] * (1.0f / MeshInt<float>::scale), 0.0f};
+    else
+      A[k * LBP + l] = {(T)((double)(long long)acc[e] * inv_qs), (T)0};
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], false);
