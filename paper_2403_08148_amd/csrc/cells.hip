@@ -77,7 +77,7 @@ __device__ inline int block_inclusive_scan(int v, int* sh) {
 // Produces start (exclusive) and, for all beads, the scatter cursor
 // fill = start.
 constexpr int SINGLE_SCAN_THREADS = 1024;
-constexpr int SCAN_UNROLL = 8;
+constexpr int SCAN_UNROLL = 16;
 constexpr int SINGLE_SCAN_MAX = 38912;  // counts staged in up to 152 KiB of LDS
 
 // The counts pass through LDS: coalesced, independent global loads and

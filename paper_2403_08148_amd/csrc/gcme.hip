@@ -724,6 +724,9 @@ PmeLaunch pme_args(gcme_handle h) {
   a.Qc = h->Qc.p;
   a.plane_major = h->yx_fused ? 1 : 0;
   a.plane_elems = h->plane_elems;
+  a.plane_k = h->rep[0].K[0] == h->rep[0].K[1] ? h->rep[0].K[0] : 0;
+  for (int r = 1; r < h->R; ++r)
+    if (h->rep[r].K[0] != a.plane_k || h->rep[r].K[1] != a.plane_k) a.plane_k = 0;
   a.tw = h->d_tw.p;
   a.radix = h->d_rad.as<int>();
   a.bsp = h->d_bsp.p;

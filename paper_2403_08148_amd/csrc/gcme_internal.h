@@ -260,6 +260,7 @@ struct PmeLaunch {
   const void* freq;   // T: signed m / L per axis entry
   const LineItem* items[3];  // fused y/x planes (rep, kz), Y lines, X lines
   int plane_elems;    // complex entries of one LDS plane buffer (fused y/x pass)
+  int plane_k;        // K0 = K1 shared by every replica's mesh, else 0
   int nitems[3];
   int lb[3];          // lines per item for each pass
   int maxK[3];        // longest z, y, x line

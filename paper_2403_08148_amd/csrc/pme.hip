@@ -105,10 +105,57 @@ struct FDiv {
   }
 };
 
+// Quotient by a divisor fixed at compile time (D > 0: a shift or a
+// multiply) or at run time (D == 0: FDiv).
+template <int D>
+struct QDiv {
+  FDiv f;
+  __device__ explicit QDiv(int d) : f(D > 0 ? D : d) {}
+  __device__ inline int div(int n) const {
+    if constexpr (D > 0)
+      return (int)((unsigned)n / (unsigned)D);
+    else
+      return f.div(n);
+  }
+};
+
 // Offset of half-complex mesh point (x, y, m) within a replica's mesh, in
 // the layout the launch uses.
 __device__ inline long long mesh_index(const PmeLaunch& a, const RepDesc& R, int x, int y, int m) {
   return a.plane_major ? ((long long)m * R.K[0] + x) * R.K[1] + y : ((long long)x * R.K[1] + y) * R.K2h + m;
+}
+
+// Radix-RR DFT of v (twiddles already applied): o_q = sum_s v_s
+// exp(sgn 2 pi i s q / RR), sgn = -1 forward, +1 inverse.
+template <typename T, int RR>
+__device__ inline void butterfly(const cplx<T>* v, cplx<T>* o, T sgn) {
+  if constexpr (RR == 2) {
+    o[0] = {v[0].x + v[1].x, v[0].y + v[1].y};
+    o[1] = {v[0].x - v[1].x, v[0].y - v[1].y};
+  } else if constexpr (RR == 4) {
+    // exp(sgn pi i/2) = sgn i
+    cplx<T> a0 = {v[0].x + v[2].x, v[0].y + v[2].y};
+    cplx<T> a1 = {v[0].x - v[2].x, v[0].y - v[2].y};
+    cplx<T> b0 = {v[1].x + v[3].x, v[1].y + v[3].y};
+    cplx<T> b1 = {v[1].x - v[3].x, v[1].y - v[3].y};
+    // sgn i * b1
+    cplx<T> ib1 = {-sgn * b1.y, sgn * b1.x};
+    o[0] = {a0.x + b0.x, a0.y + b0.y};
+    o[2] = {a0.x - b0.x, a0.y - b0.y};
+    o[1] = {a1.x + ib1.x, a1.y + ib1.y};
+    o[3] = {a1.x - ib1.x, a1.y - ib1.y};
+  } else {
+    // radix 3: w = exp(sgn 2 pi i / 3) = -1/2 + sgn i sqrt(3)/2
+    const T h = (T)0.86602540378443864676;
+    cplx<T> s = {v[1].x + v[2].x, v[1].y + v[2].y};
+    cplx<T> d = {v[1].x - v[2].x, v[1].y - v[2].y};
+    o[0] = {v[0].x + s.x, v[0].y + s.y};
+    cplx<T> m = {v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y};
+    // sgn i h d
+    cplx<T> id = {-sgn * h * d.y, sgn * h * d.x};
+    o[1] = {m.x + id.x, m.y + id.y};
+    o[2] = {m.x - id.x, m.y - id.y};
+  }
 }
 
 // One radix-RR Stockham stage over nl lines of length K held in LDS
@@ -116,8 +163,10 @@ __device__ inline long long mesh_index(const PmeLaunch& a, const RepDesc& R, int
 // parameter so the butterfly operands stay in registers.  Consecutive
 // threads take consecutive lines when the lines are interleaved (SL = 1) and
 // consecutive butterflies of one line when its points are (SK = 1), so LDS
-// accesses stay on consecutive banks.
-template <typename T, int RR>
+// accesses stay on consecutive banks.  NT is the block's thread count (a
+// compile-time stride: blockDim would be reloaded from the dispatch packet
+// with a memory round trip in every stage).
+template <typename T, int RR, int NT>
 __device__ inline void fft_stage(const cplx<T>* A, cplx<T>* B, int K, int SK, int SL, int nl, int Ns,
                                  const cplx<T>* __restrict__ tw, bool inverse) {
   const T sgn = inverse ? (T)1 : (T)-1;
@@ -125,7 +174,7 @@ __device__ inline void fft_stage(const cplx<T>* A, cplx<T>* B, int K, int SK, in
   const int tstride = K / (Ns * RR);
   const FDiv dnl(nl), dnb(nb), dns(Ns);
   const bool kfast = SK == 1 && SL != 1;
-  for (int b = threadIdx.x; b < nb * nl; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nb * nl; b += NT) {
     int j, l;
     if (kfast) {
       l = dnb.div(b);
@@ -146,42 +195,91 @@ __device__ inline void fft_stage(const cplx<T>* A, cplx<T>* B, int K, int SK, in
       v[r] = cmul(v[r], w);
     }
     cplx<T> o[RR];
-    if constexpr (RR == 2) {
-      o[0] = {v[0].x + v[1].x, v[0].y + v[1].y};
-      o[1] = {v[0].x - v[1].x, v[0].y - v[1].y};
-    } else if constexpr (RR == 4) {
-      // X_q = sum_s v_s exp(sgn 2 pi i s q / 4); exp(sgn pi i/2) = sgn i
-      cplx<T> a0 = {v[0].x + v[2].x, v[0].y + v[2].y};
-      cplx<T> a1 = {v[0].x - v[2].x, v[0].y - v[2].y};
-      cplx<T> b0 = {v[1].x + v[3].x, v[1].y + v[3].y};
-      cplx<T> b1 = {v[1].x - v[3].x, v[1].y - v[3].y};
-      // sgn i * b1
-      cplx<T> ib1 = {-sgn * b1.y, sgn * b1.x};
-      o[0] = {a0.x + b0.x, a0.y + b0.y};
-      o[2] = {a0.x - b0.x, a0.y - b0.y};
-      o[1] = {a1.x + ib1.x, a1.y + ib1.y};
-      o[3] = {a1.x - ib1.x, a1.y - ib1.y};
-    } else {
-      // radix 3: w = exp(sgn 2 pi i / 3) = -1/2 + sgn i sqrt(3)/2
-      const T h = (T)0.86602540378443864676;
-      cplx<T> s = {v[1].x + v[2].x, v[1].y + v[2].y};
-      cplx<T> d = {v[1].x - v[2].x, v[1].y - v[2].y};
-      o[0] = {v[0].x + s.x, v[0].y + s.y};
-      cplx<T> m = {v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y};
-      // sgn i h d
-      cplx<T> id = {-sgn * h * d.y, sgn * h * d.x};
-      o[1] = {m.x + id.x, m.y + id.y};
-      o[2] = {m.x - id.x, m.y - id.y};
-    }
+    butterfly<T, RR>(v, o, sgn);
     const int idxD = jn * Ns * RR + k;
 #pragma unroll
     for (int r = 0; r < RR; ++r) B[(idxD + r * Ns) * SK + l * SL] = o[r];
   }
 }
 
+// The host's radix plan of a K-point transform (radix-4 stages, then 2,
+// then 3) at compile time: its length and its stage s.
+constexpr int plan_len(int K) {
+  int n = 0;
+  while (K % 4 == 0) K /= 4, ++n;
+  while (K % 2 == 0) K /= 2, ++n;
+  while (K % 3 == 0) K /= 3, ++n;
+  return n;
+}
+constexpr int plan_radix(int K, int s) {
+  while (K % 4 == 0) {
+    if (s-- == 0) return 4;
+    K /= 4;
+  }
+  while (K % 2 == 0) {
+    if (s-- == 0) return 2;
+    K /= 2;
+  }
+  return 3;
+}
+
+// fft_stage with the line length, layout, line count and stage (NS = product
+// of the earlier radices) known at compile time: the butterfly's indices
+// are shifts and its LDS offsets immediates.
+template <typename T, int K, int NT, int SK, int SL, int NL, int RR, int NS>
+__device__ inline void fft_stage_c(const cplx<T>* A, cplx<T>* B, const cplx<T>* __restrict__ tw, bool inverse) {
+  constexpr int NB = K / RR, TS = K / (NS * RR), NBUT = NB * NL;
+  constexpr bool kfast = SK == 1 && SL != 1;
+  const T sgn = inverse ? (T)1 : (T)-1;
+#pragma unroll
+  for (int b0 = 0; b0 < NBUT; b0 += NT) {
+    const unsigned b = b0 + threadIdx.x;
+    if (NBUT % NT == 0 || b < (unsigned)NBUT) {
+      unsigned j, l;
+      if constexpr (kfast) {
+        l = b / NB;
+        j = b % NB;
+      } else {
+        j = b / NL;
+        l = b % NL;
+      }
+      const unsigned jn = j / NS, k = j % NS;
+      const cplx<T>* src = A + j * SK + l * SL;
+      cplx<T> v[RR];
+#pragma unroll
+      for (int r = 0; r < RR; ++r) v[r] = src[r * NB * SK];
+#pragma unroll
+      for (int r = 1; r < RR; ++r) {
+        cplx<T> w = tw[k * r * TS];
+        if (inverse) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+      cplx<T> o[RR];
+      butterfly<T, RR>(v, o, sgn);
+      cplx<T>* dst = B + (jn * NS * RR + k) * SK + l * SL;
+#pragma unroll
+      for (int r = 0; r < RR; ++r) dst[r * NS * SK] = o[r];
+    }
+  }
+}
+
+// All stages of fft_stage_c from stage S on, A -> B -> A ...; returns the
+// buffer holding the result.
+template <typename T, int K, int NT, int SK, int SL, int NL, int S = 0, int NS = 1>
+__device__ inline cplx<T>* fft_lines_c(cplx<T>* A, cplx<T>* B, const cplx<T>* __restrict__ tw, bool inverse) {
+  if constexpr (S == plan_len(K)) {
+    return A;
+  } else {
+    constexpr int RR = plan_radix(K, S);
+    fft_stage_c<T, K, NT, SK, SL, NL, RR, NS>(A, B, tw, inverse);
+    __syncthreads();
+    return fft_lines_c<T, K, NT, SK, SL, NL, S + 1, NS * RR>(B, A, tw, inverse);
+  }
+}
+
 // In-LDS Stockham FFT of nl lines of length K (element (k, l) at
 // k*SK + l*SL).  Returns the buffer holding the result (A or B).
-template <typename T>
+template <typename T, int NT>
 __device__ cplx<T>* fft_lines_s(cplx<T>* A, cplx<T>* B, int K, int SK, int SL, int nl,
                                 const cplx<T>* __restrict__ tw, const int* __restrict__ rad, int nrad,
                                 bool inverse) {
@@ -189,11 +287,11 @@ __device__ cplx<T>* fft_lines_s(cplx<T>* A, cplx<T>* B, int K, int SK, int SL, i
   for (int s = 0; s < nrad; ++s) {
     const int Rr = rad[s];
     if (Rr == 4)
-      fft_stage<T, 4>(A, B, K, SK, SL, nl, Ns, tw, inverse);
+      fft_stage<T, 4, NT>(A, B, K, SK, SL, nl, Ns, tw, inverse);
     else if (Rr == 2)
-      fft_stage<T, 2>(A, B, K, SK, SL, nl, Ns, tw, inverse);
+      fft_stage<T, 2, NT>(A, B, K, SK, SL, nl, Ns, tw, inverse);
     else
-      fft_stage<T, 3>(A, B, K, SK, SL, nl, Ns, tw, inverse);
+      fft_stage<T, 3, NT>(A, B, K, SK, SL, nl, Ns, tw, inverse);
     __syncthreads();
     cplx<T>* t = A;
     A = B;
@@ -204,19 +302,19 @@ __device__ cplx<T>* fft_lines_s(cplx<T>* A, cplx<T>* B, int K, int SK, int SL, i
 }
 
 // Lines interleaved: element (k, l) at k*LBP + l.
-template <typename T>
+template <typename T, int NT>
 __device__ cplx<T>* fft_lines(cplx<T>* A, cplx<T>* B, int K, int LBP, int nl, const cplx<T>* __restrict__ tw,
                               const int* __restrict__ rad, int nrad, bool inverse) {
-  return fft_lines_s<T>(A, B, K, LBP, 1, nl, tw, rad, nrad, inverse);
+  return fft_lines_s<T, NT>(A, B, K, LBP, 1, nl, tw, rad, nrad, inverse);
 }
 
 // Copies the K twiddles of one axis into LDS (whole block; the caller's
 // next __syncthreads publishes them).  The FFT stages then read twiddles at
 // LDS latency instead of waiting on global loads once per stage.
-template <typename T>
+template <typename T, int NT>
 __device__ inline const cplx<T>* stage_twiddles(cplx<T>* dst, const PmeLaunch& a, int off, int K) {
   const cplx<T>* src = reinterpret_cast<const cplx<T>*>(a.tw) + off;
-  for (int e = threadIdx.x; e < K; e += blockDim.x) dst[e] = src[e];
+  for (int e = threadIdx.x; e < K; e += NT) dst[e] = src[e];
   return dst;
 }
 
@@ -228,22 +326,23 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse)
   const int K = R.K[1], K2h = R.K2h, nl = it.count, LBP = a.lb[1] + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[1] * LBP;
-  const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[1] * LBP, a, R.tw_off[1], K);
+  const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[1] * LBP, a, R.tw_off[1], K);
   const int x = it.first / K2h, kz0 = it.first % K2h;
   cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)x * R.K[1] * K2h + kz0;
   const FDiv dnl(nl);
-  for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
+  for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
     const int k = dnl.div(e), l = e - k * nl;
     A[k * LBP + l] = base[(long long)k * K2h + l];
   }
   __syncthreads();
-  cplx<T>* res = fft_lines<T>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[1], R.nrad[1], inverse != 0);
-  for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
+  cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[1], R.nrad[1], inverse != 0);
+  for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
     const int k = dnl.div(e), l = e - k * nl;
     base[(long long)k * K2h + l] = res[k * LBP + l];
   }
 }
 
+template <int NT>
 __device__ inline double block_sum_fft(double v, double* sh) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -253,7 +352,7 @@ __device__ inline double block_sum_fft(double v, double* sh) {
   __syncthreads();
   double t = 0;
   if (threadIdx.x == 0) {
-    const int nw = (int)blockDim.x >> 6;
+    const int nw = NT >> 6;
     for (int w = 0; w < nw; ++w) t += sh[w];
   }
   return t;
@@ -305,30 +404,30 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
   const int K = R.K[0], K1 = R.K[1], K2h = R.K2h, nl = it.count, LBP = a.lb[2] + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[2] * LBP;
-  const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[2] * LBP, a, R.tw_off[0], K);
+  const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[2] * LBP, a, R.tw_off[0], K);
   const int y = it.first / K2h, kz0 = it.first % K2h;
   const long long xstride = (long long)K1 * K2h;
   cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)y * K2h + kz0;
   const FDiv dnl(nl);
-  for (int e = threadIdx.x; e < nl * K; e += blockDim.x) {
+  for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
     const int k = dnl.div(e), l = e - k * nl;
     A[k * LBP + l] = base[(long long)k * xstride + l];
   }
   __syncthreads();
-  cplx<T>* res = fft_lines<T>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], false);
+  cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], false);
   cplx<T>* other = res == A ? B : A;
   // Green's function, energy and virial
   const T* gf = reinterpret_cast<const T*>(a.bsp);
   const T* fr = reinterpret_cast<const T*>(a.freq);
   RecipSums acc{};
-  for (int q = threadIdx.x; q < nl * K; q += blockDim.x) {
+  for (int q = threadIdx.x; q < nl * K; q += FFT_THREADS) {
     const int k = dnl.div(q), l = q - k * nl;
     res[k * LBP + l] = green_apply<T, EV>(R, gf + R.bsp_off[0], gf + R.bsp_off[1], gf + R.bsp_off[2], fr + R.bsp_off[0],
                                           fr + R.bsp_off[1], fr + R.bsp_off[2], k, y, kz0 + l, res[k * LBP + l], acc);
   }
   __syncthreads();
-  cplx<T>* fin = fft_lines<T>(res, other, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], true);
-  for (int e2 = threadIdx.x; e2 < nl * K; e2 += blockDim.x) {
+  cplx<T>* fin = fft_lines<T, FFT_THREADS>(res, other, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], true);
+  for (int e2 = threadIdx.x; e2 < nl * K; e2 += FFT_THREADS) {
     const int k = dnl.div(e2), l = e2 - k * nl;
     base[(long long)k * xstride + l] = fin[k * LBP + l];
   }
@@ -336,7 +435,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
     double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
-      double t = block_sum_fft(v[k], sh);
+      double t = block_sum_fft<FFT_THREADS>(v[k], sh);
       if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
     }
   }
@@ -347,70 +446,137 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
 // whose K0 x K1 plane fits twice in a workgroup's LDS).  The plane stays in
 // one layout, (y, x) at y*LY + x (LY = K0 + 1): the y lines are transformed
 // with x interleaved, the x lines with their points consecutive.
-template <typename T, bool EV>
+template <typename T, bool EV, int KC>
 __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[YX_THREADS / 64];
   const LineItem it = a.items[0][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
-  const int K0 = R.K[0], K1 = R.K[1], K2h = R.K2h;
+  // KC > 0: every replica's plane is KC x KC (compile-time transforms)
+  const int K0 = KC > 0 ? KC : R.K[0], K1 = KC > 0 ? KC : R.K[1], K2h = R.K2h;
   const int kz = it.first;
   const int LY = K0 + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.plane_elems;
-  const cplx<T>* twx = stage_twiddles(B + (size_t)a.plane_elems, a, R.tw_off[0], K0);
-  const cplx<T>* twy = stage_twiddles(B + (size_t)a.plane_elems + a.maxK[2], a, R.tw_off[1], K1);
+  constexpr int NT = YX_THREADS;
+  cplx<T>* twx = B + (size_t)a.plane_elems;
+  cplx<T>* twy = twx + a.maxK[2];
   // per-axis Green's function factors and frequencies of this replica
-  T* tabs = reinterpret_cast<T*>(B + (size_t)a.plane_elems + a.maxK[2] + a.maxK[1]);
+  T* tabs = reinterpret_cast<T*>(twy + a.maxK[1]);
   T* gf0 = tabs;
   T* gf1 = gf0 + K0;
   T* gf2 = gf1 + K1;
   T* fr0 = gf2 + K2h;
   T* fr1 = fr0 + K0;
   T* fr2 = fr1 + K1;
-  {
-    const T* gf = reinterpret_cast<const T*>(a.bsp);
-    const T* fr = reinterpret_cast<const T*>(a.freq);
-    for (int e = threadIdx.x; e < K0; e += blockDim.x) {
-      gf0[e] = gf[R.bsp_off[0] + e];
-      fr0[e] = fr[R.bsp_off[0] + e];
-    }
-    for (int e = threadIdx.x; e < K1; e += blockDim.x) {
-      gf1[e] = gf[R.bsp_off[1] + e];
-      fr1[e] = fr[R.bsp_off[1] + e];
-    }
-    for (int e = threadIdx.x; e < K2h; e += blockDim.x) {
-      gf2[e] = gf[R.bsp_off[2] + e];
-      fr2[e] = fr[R.bsp_off[2] + e];
-    }
-  }
   // the plane is contiguous in the plane-major mesh layout
   const int n = K0 * K1;
   cplx<T>* Q = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)kz * n;
-  const FDiv dk0(K0), dk1(K1);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int x = dk1.div(e), y = e - x * K1;
-    A[y * LY + x] = Q[e];
+  const QDiv<KC> dk0(K0), dk1(K1);
+  {
+    // Every load of the first NT table entries and PL plane points per
+    // thread is issued before the first LDS store, so the block waits for
+    // one memory latency rather than one per table and per plane row.
+    const int t = threadIdx.x;
+    const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw);
+    const T* gf = reinterpret_cast<const T*>(a.bsp);
+    const T* fr = reinterpret_cast<const T*>(a.freq);
+    constexpr int PL = 4;
+    cplx<T> v[PL], wx = {}, wy = {};
+    T g[3] = {}, f[3] = {};
+#pragma unroll
+    for (int u = 0; u < PL; ++u) v[u] = t + u * NT < n ? Q[t + u * NT] : cplx<T>{};
+    if (t < K0) {
+      wx = tw[R.tw_off[0] + t];
+      g[0] = gf[R.bsp_off[0] + t];
+      f[0] = fr[R.bsp_off[0] + t];
+    }
+    if (t < K1) {
+      wy = tw[R.tw_off[1] + t];
+      g[1] = gf[R.bsp_off[1] + t];
+      f[1] = fr[R.bsp_off[1] + t];
+    }
+    if (t < K2h) {
+      g[2] = gf[R.bsp_off[2] + t];
+      f[2] = fr[R.bsp_off[2] + t];
+    }
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int e = t + u * NT;
+      if (e < n) {
+        const int x = dk1.div(e), y = e - x * K1;
+        A[y * LY + x] = v[u];
+      }
+    }
+    if (t < K0) {
+      twx[t] = wx;
+      gf0[t] = g[0];
+      fr0[t] = f[0];
+    }
+    if (t < K1) {
+      twy[t] = wy;
+      gf1[t] = g[1];
+      fr1[t] = f[1];
+    }
+    if (t < K2h) {
+      gf2[t] = g[2];
+      fr2[t] = f[2];
+    }
+    // the rest, for meshes with more points than that
+    for (int e = t + NT; e < K0; e += NT) {
+      twx[e] = tw[R.tw_off[0] + e];
+      gf0[e] = gf[R.bsp_off[0] + e];
+      fr0[e] = fr[R.bsp_off[0] + e];
+    }
+    for (int e = t + NT; e < K1; e += NT) {
+      twy[e] = tw[R.tw_off[1] + e];
+      gf1[e] = gf[R.bsp_off[1] + e];
+      fr1[e] = fr[R.bsp_off[1] + e];
+    }
+    for (int e = t + NT; e < K2h; e += NT) {
+      gf2[e] = gf[R.bsp_off[2] + e];
+      fr2[e] = fr[R.bsp_off[2] + e];
+    }
+    for (int e = t + PL * NT; e < n; e += NT) {
+      const int x = dk1.div(e), y = e - x * K1;
+      A[y * LY + x] = Q[e];
+    }
   }
   __syncthreads();
   const int* radx = a.radix + R.rad_off[0];
   const int* rady = a.radix + R.rad_off[1];
   // y lines (x interleaved), then x lines in place in the same layout
   // (points of a line consecutive, lines LY apart): no transposes
-  cplx<T>* r1 = fft_lines_s<T>(A, B, K1, LY, 1, K0, twy, rady, R.nrad[1], false);
+  cplx<T>* r1;
+  if constexpr (KC > 0)
+    r1 = fft_lines_c<T, KC, NT, KC + 1, 1, KC>(A, B, twy, false);
+  else
+    r1 = fft_lines_s<T, NT>(A, B, K1, LY, 1, K0, twy, rady, R.nrad[1], false);
   cplx<T>* o1 = r1 == A ? B : A;
-  cplx<T>* r2 = fft_lines_s<T>(r1, o1, K0, 1, LY, K1, twx, radx, R.nrad[0], false);
+  cplx<T>* r2;
+  if constexpr (KC > 0)
+    r2 = fft_lines_c<T, KC, NT, 1, KC + 1, KC>(r1, o1, twx, false);
+  else
+    r2 = fft_lines_s<T, NT>(r1, o1, K0, 1, LY, K1, twx, radx, R.nrad[0], false);
   cplx<T>* o2 = r2 == r1 ? o1 : r1;
   RecipSums acc{};
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+  for (int e = threadIdx.x; e < n; e += NT) {
     const int y = dk0.div(e), x = e - y * K0;
     r2[y * LY + x] = green_apply<T, EV>(R, gf0, gf1, gf2, fr0, fr1, fr2, x, y, kz, r2[y * LY + x], acc);
   }
   __syncthreads();
-  cplx<T>* r3 = fft_lines_s<T>(r2, o2, K0, 1, LY, K1, twx, radx, R.nrad[0], true);
+  cplx<T>* r3;
+  if constexpr (KC > 0)
+    r3 = fft_lines_c<T, KC, NT, 1, KC + 1, KC>(r2, o2, twx, true);
+  else
+    r3 = fft_lines_s<T, NT>(r2, o2, K0, 1, LY, K1, twx, radx, R.nrad[0], true);
   cplx<T>* o3 = r3 == r2 ? o2 : r2;
-  cplx<T>* r4 = fft_lines_s<T>(r3, o3, K1, LY, 1, K0, twy, rady, R.nrad[1], true);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+  cplx<T>* r4;
+  if constexpr (KC > 0)
+    r4 = fft_lines_c<T, KC, NT, KC + 1, 1, KC>(r3, o3, twy, true);
+  else
+    r4 = fft_lines_s<T, NT>(r3, o3, K1, LY, 1, K0, twy, rady, R.nrad[1], true);
+  for (int e = threadIdx.x; e < n; e += NT) {
     const int x = dk1.div(e), y = e - x * K1;
     Q[e] = r4[y * LY + x];
   }
@@ -418,7 +584,7 @@ __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
     double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
-      double t = block_sum_fft(v[k], sh);
+      double t = block_sum_fft<NT>(v[k], sh);
       if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
     }
   }
@@ -466,33 +632,46 @@ __device__ inline TileCols tile_columns(const RepDesc& R, const MeshTile& mt, in
   return tc;
 }
 
+// Start and count of this thread's column of the tile's columns cb.. (zero
+// past the last column).
+struct ColRun {
+  int st, n;
+};
+template <int NT>
+__device__ inline ColRun tile_column(const RepDesc& R, const TileCols& tc, const int* __restrict__ qstart, int cb) {
+  const int c = cb + threadIdx.x;
+  ColRun r{0, 0};
+  if (c < tc.n[0] * tc.n[1]) {
+    const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
+    int cx = tc.lo[0] + c / tc.n[1], cy = tc.lo[1] + c % tc.n[1];
+    cx -= cx >= nx ? nx : 0;
+    cy -= cy >= ny ? ny : 0;
+    const int base = R.cell_off + (cx * ny + cy) * nz;
+    r.st = qstart[base];
+    r.n = qstart[base + nz] - r.st;
+  }
+  return r;
+}
+
 // Calls f(q) for every charged bead q in the tile's columns (every thread of
-// the block must call this; f runs on the thread that owns q).
-template <typename F>
-__device__ inline void for_tile_beads(const RepDesc& R, const TileCols& tc, const int* __restrict__ qstart, int* s_cs,
-                                      int* s_cp, int* s_tot, int* scan_sh, F&& f) {
+// the block must call this; f runs on the thread that owns q).  first is
+// tile_column(.., 0), which callers load early so that its latency overlaps
+// other work.
+template <int NT, typename F>
+__device__ inline void for_tile_beads(const RepDesc& R, const TileCols& tc, const int* __restrict__ qstart,
+                                      ColRun first, int* s_cs, int* s_cp, int* s_tot, int* scan_sh, F&& f) {
   const int ncol = tc.n[0] * tc.n[1];
-  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
-  for (int cb = 0; cb < ncol; cb += blockDim.x) {
-    const int c = cb + threadIdx.x;
-    int st = 0, n = 0;
-    if (c < ncol) {
-      int cx = tc.lo[0] + c / tc.n[1], cy = tc.lo[1] + c % tc.n[1];
-      cx -= cx >= nx ? nx : 0;
-      cy -= cy >= ny ? ny : 0;
-      const int base = R.cell_off + (cx * ny + cy) * nz;
-      st = qstart[base];
-      n = qstart[base + nz] - st;
-    }
-    const int inc = block_scan_incl(n, scan_sh);
-    s_cs[threadIdx.x] = st;
-    s_cp[threadIdx.x] = inc - n;
-    if (threadIdx.x == blockDim.x - 1) *s_tot = inc;
+  for (int cb = 0; cb < ncol; cb += NT) {
+    const ColRun cr = cb == 0 ? first : tile_column<NT>(R, tc, qstart, cb);
+    const int inc = block_scan_incl(cr.n, scan_sh);
+    s_cs[threadIdx.x] = cr.st;
+    s_cp[threadIdx.x] = inc - cr.n;
+    if (threadIdx.x == NT - 1) *s_tot = inc;
     __syncthreads();
     const int tot = *s_tot;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    for (int e = threadIdx.x; e < tot; e += NT) {
       // the last column whose prefix is <= e holds candidate e
-      int lo = 0, hi = (int)blockDim.x - 1;
+      int lo = 0, hi = NT - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_cp[mid] <= e)
@@ -524,16 +703,22 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
-  const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
+  // the tile's first column run and this thread's twiddle are loaded first;
+  // the twiddles go to LDS after the spread, so neither latency is waited
+  // for on its own
+  const TileCols tc = tile_columns(R, mt, P);
+  const ColRun first = tile_column<FFT_THREADS>(R, tc, a.qstart, 0);
+  cplx<T>* tw = B + (size_t)a.maxK[0] * LBP;
+  const cplx<T>* tws = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[2];
+  const cplx<T> tw0 = threadIdx.x < K2 ? tws[threadIdx.x] : cplx<T>{};
   // integer accumulators of the tile, line l = lx * TY + ly, point l * K2 + z
   // (they live in B, which the transform first writes after they are read)
   using U = typename MeshInt<T>::U;
   U* acc = reinterpret_cast<U*>(B);
-  for (int e = threadIdx.x; e < NL * K2; e += blockDim.x) acc[e] = 0;
+  for (int e = threadIdx.x; e < NL * K2; e += FFT_THREADS) acc[e] = 0;
   __syncthreads();
-  const TileCols tc = tile_columns(R, mt, P);
   const double qs = a.qscale;
-  for_tile_beads(R, tc, a.qstart, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
+  for_tile_beads<FFT_THREADS>(R, tc, a.qstart, first, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
     const uint4 rec = a.qpk[q];
     int k0[3];
     T t[3];
@@ -580,10 +765,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
       }
     }
   });
+  if (threadIdx.x < K2) tw[threadIdx.x] = tw0;
+  for (int e = threadIdx.x + FFT_THREADS; e < K2; e += FFT_THREADS) tw[e] = tws[e];
   // integer mesh -> complex lines (k, l) at A[k * LBP + l]
   const double inv_qs = 1.0 / qs;
   const FDiv dk2(K2), dk2h(K2h);
-  for (int e = threadIdx.x; e < NL * K2; e += blockDim.x) {
+  for (int e = threadIdx.x; e < NL * K2; e += FFT_THREADS) {
     const int l = dk2.div(e), k = e - l * K2;
     if constexpr (std::is_same<T, float>::value)
       A[k * LBP + l] = {(float)(int)acc[e] * (1.0f / MeshInt<float>::scale), 0.0f};
@@ -591,10 +778,10 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
       A[k * LBP + l] = {(T)((double)(long long)acc[e] * inv_qs), (T)0};
   }
   __syncthreads();
-  cplx<T>* res = fft_lines<T>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], false);
+  cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], false);
   cplx<T>* out = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off;
   const FDiv dnl(NL), dty(TY);
-  for (int e = threadIdx.x; e < NL * K2h; e += blockDim.x) {
+  for (int e = threadIdx.x; e < NL * K2h; e += FFT_THREADS) {
     // consecutive threads take consecutive addresses of either layout
     int l, m;
     if (a.plane_major) {
@@ -620,12 +807,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
-  const cplx<T>* tw = stage_twiddles(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
+  const TileCols tc = tile_columns(R, mt, P);
+  const ColRun first = tile_column<FFT_THREADS>(R, tc, a.qstart, 0);
   const cplx<T>* in = reinterpret_cast<const cplx<T>*>(a.Qc) + R.cgrid_off;
   const FDiv dk2h(K2h), dnl(NL), dty(TY);
-  for (int e = threadIdx.x; e < NL * K2h; e += blockDim.x) {
-    // consecutive threads take consecutive addresses of either layout
-    int l, m;
+  // point e of the tile's half-complex lines: line l, frequency m, and its
+  // mesh offset (negative outside the tile); consecutive e take consecutive
+  // addresses of either layout
+  auto point = [&](int e, int& l, int& m) -> long long {
     if (a.plane_major) {
       m = dnl.div(e);
       l = e - m * NL;
@@ -634,19 +823,44 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
       m = e - l * K2h;
     }
     const int lx = dty.div(l), ly = l - lx * TY;
-    cplx<T> v = {(T)0, (T)0};
-    if (lx < nxt && ly < nyt) v = in[mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m)];
+    return lx < nxt && ly < nyt ? mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m) : -1;
+  };
+  auto put = [&](int l, int m, cplx<T> v) {
     A[m * LBP + l] = v;
     // Hermitian partner of a real field
     const int mc = K2 - m;
     if (m > 0 && mc > m && mc < K2) A[mc * LBP + l] = {v.x, -v.y};
+  };
+  const int ne = NL * K2h;
+  // the first PL points per thread are loaded together (one memory latency)
+  constexpr int PL = 4;
+  cplx<T> v[PL];
+  int vl[PL], vm[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int e = threadIdx.x + u * FFT_THREADS;
+    v[u] = cplx<T>{};
+    vl[u] = vm[u] = 0;
+    if (e < ne) {
+      const long long o = point(e, vl[u], vm[u]);
+      if (o >= 0) v[u] = in[o];
+    }
+  }
+  const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
+#pragma unroll
+  for (int u = 0; u < PL; ++u)
+    if (threadIdx.x + u * FFT_THREADS < ne) put(vl[u], vm[u], v[u]);
+  for (int e = threadIdx.x + PL * FFT_THREADS; e < ne; e += FFT_THREADS) {
+    int l, m;
+    const long long o = point(e, l, m);
+    put(l, m, o >= 0 ? in[o] : cplx<T>{});
   }
   __syncthreads();
-  const cplx<T>* phi = fft_lines<T>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], true);
-  const TileCols tc = tile_columns(R, mt, P);
+  const cplx<T>* phi = fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], true);
   const double fx = -R.lB * K0 / R.L[0], fy = -R.lB * K1 / R.L[1], fz = -R.lB * K2 / R.L[2];
-  for_tile_beads(R, tc, a.qstart, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
+  for_tile_beads<FFT_THREADS>(R, tc, a.qstart, first, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
     const uint4 rec = a.qpk[q];
+    const int bi = a.qidx[q];
     int k0[3];
     T t[3];
     mesh_coord<T>(rec.x, K0, k0[0], t[0]);
@@ -690,7 +904,6 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
     }
     const double z = (double)param_z(rec.w);
     const double f[3] = {z * fx * (double)gx, z * fy * (double)gy, z * fz * (double)gz};
-    const int bi = a.qidx[q];
     long long iv[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -804,26 +1017,35 @@ size_t pme_plane_lds_bytes(int plane_elems, int maxK0, int maxK1, int maxK2, boo
   return (2 * (size_t)plane_elems + maxK0 + maxK1) * (fp64 ? 16 : 8) + 2 * (size_t)(maxK0 + maxK1 + maxK2) * (fp64 ? 8 : 4);
 }
 
+template <typename T, bool EV, int KC>
+void fft_yx_conv_k(hipStream_t s, const PmeLaunch& a, size_t sh) {
+  allow_lds((const void*)k_fft_yx_conv<T, EV, KC>, sh);
+  hipLaunchKernelGGL((k_fft_yx_conv<T, EV, KC>), dim3(a.nitems[0]), dim3(YX_THREADS), sh, s, a);
+}
+
+template <typename T, bool EV>
+void fft_yx_conv_t(hipStream_t s, const PmeLaunch& a, size_t sh) {
+  if (a.plane_k == 64)
+    fft_yx_conv_k<T, EV, 64>(s, a, sh);
+  else if (a.plane_k == 32)
+    fft_yx_conv_k<T, EV, 32>(s, a, sh);
+  else
+    fft_yx_conv_k<T, EV, 0>(s, a, sh);
+}
+
 void launch_fft_yx_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev) {
   if (a.nitems[0] <= 0) return;
   const size_t sh = pme_plane_lds_bytes(a.plane_elems, a.maxK[2], a.maxK[1], a.maxK[0], fp64);
-  dim3 g(a.nitems[0]), b(YX_THREADS);
   if (fp64) {
-    if (ev) {
-      allow_lds((const void*)k_fft_yx_conv<double, true>, sh);
-      hipLaunchKernelGGL((k_fft_yx_conv<double, true>), g, b, sh, s, a);
-    } else {
-      allow_lds((const void*)k_fft_yx_conv<double, false>, sh);
-      hipLaunchKernelGGL((k_fft_yx_conv<double, false>), g, b, sh, s, a);
-    }
+    if (ev)
+      fft_yx_conv_t<double, true>(s, a, sh);
+    else
+      fft_yx_conv_t<double, false>(s, a, sh);
   } else {
-    if (ev) {
-      allow_lds((const void*)k_fft_yx_conv<float, true>, sh);
-      hipLaunchKernelGGL((k_fft_yx_conv<float, true>), g, b, sh, s, a);
-    } else {
-      allow_lds((const void*)k_fft_yx_conv<float, false>, sh);
-      hipLaunchKernelGGL((k_fft_yx_conv<float, false>), g, b, sh, s, a);
-    }
+    if (ev)
+      fft_yx_conv_t<float, true>(s, a, sh);
+    else
+      fft_yx_conv_t<float, false>(s, a, sh);
   }
 }
 
