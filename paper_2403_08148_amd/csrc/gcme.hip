@@ -1370,10 +1370,38 @@ gcme_status gcme_autotune(gcme_handle h) {
             [](const std::pair<float, gcme_tuning>& x, const std::pair<float, gcme_tuning>& y) { return x.first < y.first; });
   gcme_tuning best = cands.empty() ? h->tune : cands[0].second;
   // 2. the best few, with every charged-cluster size and stream layout, as
-  //    replays of a captured evaluation graph (stream dependencies cost
-  //    differently there, and a layout that runs the two pair kernels one
-  //    after the other exposes the charged kernel's own time)
+  //    replays of the captured step graph from the saved state: stream
+  //    dependencies cost differently in a graph, and only whole steps show
+  //    how the branches overlap the sort and the integrator.  The state
+  //    (order, positions, velocities, forces, step counter) is restored
+  //    before each candidate and at the end.
   if (h->NQ > 0) {
+    const size_t N = (size_t)h->N;
+    DevBuf sp[3], sv[3], sprm, sid, sstep;
+    for (int k = 0; k < 3; ++k) {
+      HIPCHK(h, sp[k].alloc(N * 4));
+      HIPCHK(h, sv[k].alloc(N * 8));
+      HIPCHK(h, hipMemcpyAsync(sp[k].p, h->a_pos[k].p, N * 4, hipMemcpyDeviceToDevice, s));
+      HIPCHK(h, hipMemcpyAsync(sv[k].p, h->a_vel[k].p, N * 8, hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(h, sprm.alloc(N * 4));
+    HIPCHK(h, sid.alloc(N * 4));
+    HIPCHK(h, sstep.alloc(8));
+    HIPCHK(h, hipMemcpyAsync(sprm.p, h->a_param.p, N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(sid.p, h->a_id.p, N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(sstep.p, h->d_step.p, 8, hipMemcpyDeviceToDevice, s));
+    auto restore = [&]() -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        e = hipMemcpyAsync(h->a_pos[k].p, sp[k].p, N * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->a_vel[k].p, sv[k].p, N * 8, hipMemcpyDeviceToDevice, s);
+      }
+      if (e == hipSuccess) e = hipMemcpyAsync(h->a_param.p, sprm.p, N * 4, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(h->a_id.p, sid.p, N * 4, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(h->d_step.p, sstep.p, 8, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(h->F.p, saveF.p, N * 24, hipMemcpyDeviceToDevice, s);
+      return e;
+    };
     float best_t = 1e30f;
     std::vector<gcme_tuning> second;
     for (size_t c = 0; c < cands.size() && second.size() < 4 * 3; ++c) {
@@ -1392,17 +1420,17 @@ gcme_status gcme_autotune(gcme_handle h) {
         gcme_tuning t = base;
         t.stream_layout = lay;
         if (gcme_set_tuning(h, &t) != GCME_OK) continue;
-        if (build_plan(h) != GCME_OK) continue;
-        hipGraph_t g = nullptr;
+        if (build_plan(h) != GCME_OK) continue;  // also clears the cell counts
         hipGraphExec_t ex = nullptr;
-        if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) continue;
-        launch_fill_i64(h->cap_stream, h->F.as<long long>(), 0, 3LL * h->N);
-        enqueue_eval(h, h->cap_stream, false, false);
-        if (hipStreamEndCapture(h->cap_stream, &g) != hipSuccess) continue;
-        const bool ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
-        (void)hipGraphDestroy(g);
-        if (!ok) continue;
-        constexpr int WARM = 3, REPS = 10;
+        if (capture(h, true, false, &ex) != GCME_OK) continue;
+        HIPCHK(h, restore());
+        {
+          IntLaunch ia = int_args(h);
+          long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
+          CellView c = cview(h);
+          launch_int_first(s, ia, viewA(h), F3, &c);
+        }
+        constexpr int WARM = 5, REPS = 20;
         for (int r = 0; r < WARM; ++r) (void)hipGraphLaunch(ex, s);
         (void)hipEventRecord(e0, s);
         for (int r = 0; r < REPS; ++r) (void)hipGraphLaunch(ex, s);
@@ -1417,6 +1445,9 @@ gcme_status gcme_autotune(gcme_handle h) {
         }
       }
     }
+    HIPCHK(h, restore());
+    HIPCHK(h, hipMemsetAsync(h->d_status.p, 0, 4, s));
+    HIPCHK(h, hipStreamSynchronize(s));
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

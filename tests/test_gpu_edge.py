@@ -188,6 +188,41 @@ def test_fused_steps_equal_single_steps(precision, gamma, layout):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_leaves_state_unchanged(precision):
+    # The autotuner times whole steps from the current state and restores
+    # it (order, positions, velocities, forces, step counter): a run after
+    # it equals, bit for bit, the same run of an engine switched to the
+    # tuning it picked at that point.
+    w = W.small_bulk(N=900, seed=9, charged_frac=0.3, box=(7.1, 7.3, 6.9), rc=2.5, grid=(24, 24, 24))
+    print(f"case autotune restore prec={precision}", flush=True)
+    eng = make_engine([w], precision, seed=5)
+    eng.step(3)
+    eng.sync()
+    before = [x.cpu().numpy() for x in eng.get_state()[:2]] + [eng.get_state()[2]]
+    tun = eng.autotune()
+    after = [x.cpu().numpy() for x in eng.get_state()[:2]] + [eng.get_state()[2]]
+    np.testing.assert_array_equal(before[0], after[0])
+    np.testing.assert_array_equal(before[1], after[1])
+    assert before[2] == after[2] == 3
+    runs = []
+    for e in (eng, None):
+        if e is None:
+            e = make_engine([w], precision, seed=5)
+            e.step(3)
+            e.set_tuning(**tun)
+        e.step(7)
+        obs = e.step(1, observe=True)
+        e.sync()
+        pos, vel, step = e.get_state()
+        runs.append((pos.cpu().numpy(), vel.cpu().numpy(), step, obs["energy"].cpu().numpy(),
+                     obs["force"].cpu().numpy()))
+        e.close()
+    assert runs[0][2] == runs[1][2] == 11
+    for k in (0, 1, 3, 4):
+        np.testing.assert_array_equal(runs[0][k], runs[1][k])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_langevin_trajectory_short(precision):
     from oracle import oracle as O
     from tests.gpu_common import oracle_params
