@@ -53,14 +53,14 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PER_THREAD = 4;
 constexpr int SCAN_BLOCK = SCAN_THREADS * SCAN_PER_THREAD;
 
-// Inclusive scan of one int per thread over the block (blockDim.x a
-// multiple of 64, at most 1024).
-__device__ inline int block_inclusive_scan(int v, int* sh) {
-  int lane = threadIdx.x & 63;
-  int wid = threadIdx.x >> 6;
+// Inclusive scan of one int per thread over a block of NT threads (a
+// multiple of 64, at most 1024); sh holds NT / 64 ints.
+template <int NT>
+__device__ inline int block_incl_scan(int v, int* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(v, o, 64);
+    const int t = __shfl_up(v, o, 64);
     if (lane >= o) v += t;
   }
   __syncthreads();
@@ -71,43 +71,24 @@ __device__ inline int block_inclusive_scan(int v, int* sh) {
   return v + add;
 }
 
-// Whole scan in one block per array (block 0: all beads, block 1: charged
-// beads) for grids of up to SINGLE_SCAN_MAX cells: each thread sums a
-// contiguous chunk, one block scan, then each thread writes its chunk.
-// Produces start (exclusive) and, for all beads, the scatter cursor
-// fill = start.
-constexpr int SINGLE_SCAN_THREADS = 1024;
-constexpr int SCAN_UNROLL = 16;
-constexpr int SINGLE_SCAN_MAX = 38912;  // counts staged in up to 152 KiB of LDS
-
-// The counts pass through LDS: coalesced, independent global loads and
-// stores, and each thread's serial chunk runs at LDS latency.
-__global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c) {
-  __shared__ int sh[16];
-  extern __shared__ __align__(16) int buf[];  // ncells entries
-  const int n = c.ncells;
-  const int per = (n + blockDim.x - 1) / blockDim.x;
-  const int lo = threadIdx.x * per, hi = min(lo + per, n);
-  const int arr = blockIdx.x;
-  const int* cnt = arr == 0 ? c.counts : c.qcounts;
-  int* st = arr == 0 ? c.start : c.qstart;
-  // loads of SCAN_UNROLL rounds are issued before any is stored, so one
-  // memory latency covers them
-  for (int i0 = threadIdx.x; i0 < n; i0 += SCAN_UNROLL * blockDim.x) {
-    int v[SCAN_UNROLL];
+// Exclusive scan of the n cell counts cnt into st (st[n] = the total) and,
+// with fill, a copy of st in fill (the scatter's cursors).  One block of NT
+// threads: the counts pass through buf (n ints of LDS), each thread sums a
+// contiguous chunk, one block scan, then each thread writes its chunk.  The
+// loads of U rounds are issued before any is stored.
+template <int NT, int U>
+__device__ inline void block_scan_counts(const int* cnt, int* st, int* fill, int n, int* buf, int* sh) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * NT) {
+    int v[U];
 #pragma unroll
-    for (int u = 0; u < SCAN_UNROLL; ++u) {
-      const int i = i0 + u * blockDim.x;
-      v[u] = i < n ? cnt[i] : 0;
-    }
+    for (int u = 0; u < U; ++u) v[u] = i0 + u * NT < n ? cnt[i0 + u * NT] : 0;
 #pragma unroll
-    for (int u = 0; u < SCAN_UNROLL; ++u) {
-      const int i = i0 + u * blockDim.x;
-      if (i < n) buf[i] = v[u];
-    }
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * NT < n) buf[i0 + u * NT] = v[u];
   }
   __syncthreads();
-  // each thread's contiguous chunk, four LDS reads in flight at a time
+  const int per = (n + NT - 1) / NT;
+  const int lo = threadIdx.x * per, hi = min(lo + per, n);
   int s = 0;
   for (int i = lo; i < hi; i += 4) {
     int v[4];
@@ -115,7 +96,7 @@ __global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c)
     for (int u = 0; u < 4; ++u) v[u] = i + u < hi ? buf[i + u] : 0;
     s += (v[0] + v[1]) + (v[2] + v[3]);
   }
-  int inc = block_inclusive_scan(s, sh);
+  const int inc = block_incl_scan<NT>(s, sh);
   int run = inc - s;
   for (int i = lo; i < hi; i += 4) {
     int v[4];
@@ -127,13 +108,32 @@ __global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c)
       run += v[u];
     }
   }
-  if (threadIdx.x == blockDim.x - 1) st[n] = inc;
+  if (threadIdx.x == NT - 1) st[n] = inc;
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = threadIdx.x; i < n; i += NT) {
     const int v = buf[i];
     st[i] = v;
-    if (arr == 0) c.fill[i] = v;
+    if (fill) fill[i] = v;
   }
+  __syncthreads();  // buf may be reused at once
+}
+
+// Whole scan in one block per array (block 0: all beads, block 1: charged
+// beads) for grids of up to SINGLE_SCAN_MAX cells: each thread sums a
+// contiguous chunk, one block scan, then each thread writes its chunk.
+// Produces start (exclusive) and, for all beads, the scatter cursor
+// fill = start.
+constexpr int SINGLE_SCAN_THREADS = 1024;
+constexpr int SCAN_UNROLL = 16;
+constexpr int SINGLE_SCAN_MAX = 38912;  // counts staged in up to 152 KiB of LDS
+
+__global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c) {
+  __shared__ int sh[SINGLE_SCAN_THREADS / 64];
+  extern __shared__ __align__(16) int buf[];  // ncells entries
+  if (blockIdx.x == 0)
+    block_scan_counts<SINGLE_SCAN_THREADS, SCAN_UNROLL>(c.counts, c.start, c.fill, c.ncells, buf, sh);
+  else
+    block_scan_counts<SINGLE_SCAN_THREADS, SCAN_UNROLL>(c.qcounts, c.qstart, nullptr, c.ncells, buf, sh);
 }
 
 __global__ void k_scan_reduce(CellView c, int nb) {
@@ -149,8 +149,8 @@ __global__ void k_scan_reduce(CellView c, int nb) {
       s1 += c.qcounts[i];
     }
   }
-  int t0 = block_inclusive_scan(s0, sh);
-  int t1 = block_inclusive_scan(s1, sh);
+  int t0 = block_incl_scan<SCAN_THREADS>(s0, sh);
+  int t1 = block_incl_scan<SCAN_THREADS>(s1, sh);
   if (threadIdx.x == SCAN_THREADS - 1) {
     c.bsum[b] = t0;
     c.bsum[nb + b] = t1;
@@ -166,7 +166,7 @@ __global__ void k_scan_top(CellView c, int nb) {
     for (int base = 0; base < nb; base += SCAN_THREADS) {
       int i = base + threadIdx.x;
       int v = i < nb ? bs[i] : 0;
-      int inc = block_inclusive_scan(v, sh);
+      int inc = block_incl_scan<SCAN_THREADS>(v, sh);
       if (i < nb) bs[i] = carry + inc - v;
       __shared__ int tot;
       if (threadIdx.x == SCAN_THREADS - 1) tot = inc;
@@ -196,7 +196,7 @@ __global__ void k_scan_apply(CellView c, int nb) {
       v[k] = i < c.ncells ? cnt[i] : 0;
       tot += v[k];
     }
-    int inc = block_inclusive_scan(tot, sh);
+    int inc = block_incl_scan<SCAN_THREADS>(tot, sh);
     int run = c.bsum[arr * nb + b] + inc - tot;
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k) {
@@ -217,7 +217,9 @@ __global__ void k_scatter(CellView c, int N) {
   const int cid = active ? c.cell[s] : 0;
   // fill holds the cell's next free slot (initialised to start by the scan)
   const int slot = run_atomic_add(c.fill, cid, active);
-  if (active) c.tmp[slot] = s;
+  // (slots outside the population cannot come from consistent counts; they
+  // are dropped rather than written out of bounds)
+  if (active && (unsigned)slot < (unsigned)N) c.tmp[slot] = s;
 }
 
 // Position p of the scattered array holds bead s of cell c in arbitrary
@@ -231,35 +233,53 @@ __global__ void k_permute(StateView A, StateView B, uint4* __restrict__ bpk, Cel
     c.qcounts[k] = 0;
   }
   if (p >= N) return;
-  int s = c.tmp[p];
-  int cid = c.cell[s];
-  int lo = c.start[cid], hi = c.start[cid + 1];
-  uint32_t prm = A.param[s];
-  bool charged = param_z(prm) != 0;
+  const int s = c.tmp[p];
+  // bead s's own data is requested as soon as s is known, beside its cell
+  const int cid = c.cell[s];
+  const uint32_t prm = A.param[s];
+  const uint32_t px = A.pos[0][s], py = A.pos[1][s], pz = A.pos[2][s];
+  const double vx = A.vel[0][s], vy = A.vel[1][s], vz = A.vel[2][s];
+  const int id = A.id[s];
+  // (clamped to the population, so inconsistent counts cannot send an
+  // access out of bounds)
+  const int lo = max(0, c.start[cid]), hi = min(N, c.start[cid + 1]);
+  const bool charged = param_z(prm) != 0;
+  // the rank among the cell's beads: their indices PB at a time, then the
+  // parameters of those before s (charged beads only), each batch of loads
+  // issued together
+  constexpr int PB = 8;
   int rank = 0, qrank = 0;
-  for (int t = lo; t < hi; ++t) {
-    int o = c.tmp[t];
-    if (o < s) {
-      ++rank;
-      if (charged && param_z(A.param[o]) != 0) ++qrank;
+  for (int t0 = lo; t0 < hi; t0 += PB) {
+    int o[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) o[u] = t0 + u < hi ? c.tmp[t0 + u] : N;
+    uint32_t po[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) po[u] = charged && o[u] < s ? A.param[o[u]] : 0u;
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      rank += o[u] < s;
+      qrank += param_z(po[u]) != 0;
     }
   }
-  int n = lo + rank;
-  uint32_t px = A.pos[0][s], py = A.pos[1][s], pz = A.pos[2][s];
+  const int n = lo + rank;
+  if (n >= N) return;
   B.pos[0][n] = px;
   B.pos[1][n] = py;
   B.pos[2][n] = pz;
-  B.vel[0][n] = A.vel[0][s];
-  B.vel[1][n] = A.vel[1][s];
-  B.vel[2][n] = A.vel[2][s];
+  B.vel[0][n] = vx;
+  B.vel[1][n] = vy;
+  B.vel[2][n] = vz;
   B.param[n] = prm;
-  B.id[n] = A.id[s];
+  B.id[n] = id;
   const uint4 rec = make_uint4(px, py, pz, prm);
   bpk[n] = rec;
   if (charged) {
-    int qn = c.qstart[cid] + qrank;
-    q.pk[qn] = rec;
-    q.idx[qn] = n;
+    const int qn = c.qstart[cid] + qrank;
+    if ((unsigned)qn < (unsigned)c.qstart[c.ncells]) {
+      q.pk[qn] = rec;
+      q.idx[qn] = n;
+    }
   }
 }
 
