@@ -198,8 +198,10 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t);
 
 /* Time candidate tunings on the current state and keep the fastest: every
  * cluster size, cell size and list choice as a stream-launched evaluation,
- * then the stream layouts of the best few as replays of a captured
- * evaluation graph (the form a step runs in).
+ * then the charged-cluster sizes and stream layouts of the best few as
+ * replays of the captured step graph (the form a run of steps takes), each
+ * from the saved state.  The state (bead order, positions, velocities,
+ * forces, step counter) is restored exactly afterwards.
  * Tunings change the order of the per-bead floating-point sums, so results
  * agree across tunings to rounding; for one tuning, reruns on the same
  * inputs are bit-identical.  Synchronous. */

@@ -111,7 +111,7 @@ struct gcme_ctx {
   std::vector<int> nq, qoff;
   int NQ = 0;
   // tuning
-  gcme_tuning tune{3, 4, 4, 50, 3, 1};  // list-free pairs, two stream branches
+  gcme_tuning tune{3, 8, 4, 50, 3, 0};  // list-free pairs, three stream branches
   bool plan_dirty = true;
   // device buffers
   DevBuf a_pos[3], a_vel[3], a_param, a_id;

@@ -806,14 +806,18 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
     // entries jl + k CJ, k < CI.  head is a multiple of 64 here (every drain
     // but the last takes exactly 64), so the entries do not wrap.
     //
-    // Forces alone (BARE) need no per-pair validity test in that mode: a bead
-    // paired with itself has zero separation, so zero force; lanes of
-    // missing cluster beads (vi false) are never flushed; and the slots past
-    // the last entry of the final drain are filled with a record 1e18 away.
+    // In the frame, the slots past the last entry of the final drain are
+    // filled with a record 1e18 away: the branch-free excluded-volume pair
+    // multiplies every lane's separation by its (zero) force factor, so no
+    // slot may hold a stale or never-written LDS value (NaN or inf times zero
+    // is NaN).  Forces alone (BARE) then need no per-pair validity test: a
+    // bead paired with itself has zero separation, so zero force; lanes of
+    // missing cluster beads (vi false) are never flushed; and the padding
+    // lies beyond the cutoff.
     constexpr bool BARE = REL && !EV && !ADJ;
     auto drain = [&](int n) {
       uint4* base = ring + (head & 64);
-      if (BARE && rel && n < 64) {
+      if (rel && n < 64) {
         const uint32_t far = __float_as_uint(1e18f);
         if (lane >= n) base[lane] = make_uint4(far, far, far, 0u);
         __builtin_amdgcn_wave_barrier();
