@@ -89,8 +89,10 @@ typedef struct {
     double box[3];            /* orthorhombic box edges L0, L1, L2 (> 0) */
     double cutoff;            /* real-space cutoff rc, rc <= min(L)/2 */
     double beta;              /* Ewald splitting (erf(beta r)); beta = 1/(sqrt2 G) */
-    int32_t grid[3];          /* mesh K0, K1, K2: each 2^a 3^b, 8 <= K <= 512 */
-    int32_t order;            /* B-spline order p, 3..8, p <= K/2 */
+    int32_t grid[3];          /* mesh K0, K1, K2: each 2^a 3^b, 8 <= K <= 512
+                                 (ignored when kmax > 0) */
+    int32_t order;            /* B-spline order p, 3..8, p <= K/2; the same for
+                                 every replica */
     double lB;                /* Bjerrum length */
     int32_t n_types;          /* 1..GCME_MAX_TYPES */
     const double* A;          /* host [n_types * n_types], symmetric, kT d^3 */
@@ -101,6 +103,12 @@ typedef struct {
     double dt;                /* time step */
     double gamma;             /* Langevin friction; 0 = velocity Verlet (NVE) */
     uint32_t flags;           /* GCME_FLAG_* */
+    double kmax;              /* 0: the reciprocal term of eq. ewald by smooth PME
+                                 on the mesh.  > 0: that term summed exactly over
+                                 the wave vectors k = 2 pi (n0/L0, n1/L1, n2/L2),
+                                 0 < |k| <= kmax (no mesh; for small replicas,
+                                 where the sum is cheap and has no mesh error);
+                                 kmax L / (2 pi) <= 64 on every axis */
 } gcme_params;
 
 /* Reject parameters that violate the paper's no-collapse condition

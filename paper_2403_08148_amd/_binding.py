@@ -36,7 +36,7 @@ class gcme_params(C.Structure):
                 ("grid", C.c_int32 * 3), ("order", C.c_int32), ("lB", C.c_double), ("n_types", C.c_int32),
                 ("A", C.POINTER(C.c_double)), ("sigma", C.POINTER(C.c_double)), ("a", C.POINTER(C.c_double)),
                 ("mass", C.POINTER(C.c_double)), ("kT", C.c_double), ("dt", C.c_double), ("gamma", C.c_double),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("kmax", C.c_double)]
 
 
 class gcme_io(C.Structure):

@@ -48,6 +48,7 @@ struct HostRep {
   double rc = 0, beta = 0, lB = 0, kT = 0, dt = 0, gamma = 0;
   int K[3] = {0, 0, 0};
   int order = 0;
+  double kmax = 0;  // > 0: exact reciprocal sum over |k| <= kmax, no mesh
   int nt = 0;
   double A[MAXT * MAXT] = {};
   double sigma[MAXT] = {};
@@ -130,6 +131,8 @@ struct gcme_ctx {
   DevBuf d_consts, d_Avals, d_dself;
   DevBuf d_imass, d_c1, d_c2s, d_dt, d_lang;
   DevBuf d_status, d_step, d_pairs;
+  DevBuf d_ewk, d_ew_items_s, d_ew_items_f, ew_sp;  // exact reciprocal sums
+  int nitems_ew_s = 0, nitems_ew_f = 0;
   // plan sizes
   int ncells = 0;
   long long grid_total = 0, cgrid_total = 0;
@@ -321,6 +324,7 @@ void build_mesh_tables(gcme_handle h, std::vector<T>& tw, std::vector<T>& bsp, s
   for (int r = 0; r < h->R; ++r) {
     RepDesc& d = h->rep[r];
     const HostRep& p = h->hp[r];
+    if (p.kmax > 0) continue;  // exact reciprocal sum: no mesh
     for (int ax = 0; ax < 3; ++ax) {
       int K = p.K[ax];
       auto it = kmap.find(K);
@@ -452,7 +456,7 @@ gcme_status build_plan(gcme_handle h) {
     d.n = h->nb[r];
     d.q_off = h->qoff[r];
     d.nq = h->nq[r];
-    d.K2h = p.K[2] / 2 + 1;
+    d.K2h = p.K[2] > 0 ? p.K[2] / 2 + 1 : 0;  // no mesh: exact reciprocal sum
     d.grid_off = goff;
     d.cgrid_off = cgoff;
     goff += (long long)p.K[0] * p.K[1] * p.K[2];
@@ -474,8 +478,9 @@ gcme_status build_plan(gcme_handle h) {
   // z lines are contiguous: about 1024 points per work item; strided y/x
   // lines are batched along z (at least 8 adjacent lines for coalescing)
   for (int ps = 0; ps < 3; ++ps) {
-    int want = ps == 0 ? std::max(1, 1024 / h->maxK[ps]) : std::max(8, 1024 / h->maxK[ps]);
-    int fit = cap / h->maxK[ps] - 2;
+    const int mk = std::max(1, h->maxK[ps]);  // 0 when no replica has a mesh
+    int want = ps == 0 ? std::max(1, 1024 / mk) : std::max(8, 1024 / mk);
+    int fit = cap / mk - 2;
     h->lb[ps] = std::max(1, std::min(64, std::min(want, fit)));
   }
 
@@ -517,15 +522,14 @@ gcme_status build_plan(gcme_handle h) {
   std::vector<int> item_off(R + 1, 0);
   for (int r = 0; r < R; ++r) {
     const RepDesc& d = h->rep[r];
-    int nlz = d.K[0] * d.K[1];
-    (void)nlz;
+    item_off[r] = (int)items[2].size();
+    if (d.K2h == 0) continue;  // no mesh (exact reciprocal sum)
     // balanced batches of the K2/2+1 strided lines
     int c1 = (d.K2h + h->lb[1] - 1) / h->lb[1], b1 = (d.K2h + c1 - 1) / c1;
     int c2 = (d.K2h + h->lb[2] - 1) / h->lb[2], b2 = (d.K2h + c2 - 1) / c2;
     for (int x = 0; x < d.K[0]; ++x)
       for (int kz = 0; kz < d.K2h; kz += b1)
         items[1].push_back(LineItem{r, x * d.K2h + kz, std::min(b1, d.K2h - kz), 0});
-    item_off[r] = (int)items[2].size();
     for (int y = 0; y < d.K[1]; ++y)
       for (int kz = 0; kz < d.K2h; kz += b2)
         items[2].push_back(LineItem{r, y * d.K2h + kz, std::min(b2, d.K2h - kz), 0});
@@ -568,6 +572,62 @@ gcme_status build_plan(gcme_handle h) {
     upload(items[ps], h->d_items[ps], s);
   }
 
+  // exact reciprocal sums: the half-space wave vectors of each replica with
+  // kmax > 0 (|k| <= kmax, the same enumeration and test as the definition
+  // of the sum), its tiles, and room for the partial structure factors
+  std::vector<EwaldK> ewk;
+  std::vector<EwaldItem> ews, ewf;
+  std::vector<int> ew_off(R + 1, 0);
+  long long sp_total = 0;
+  for (int r = 0; r < R; ++r) {
+    RepDesc& d = h->rep[r];
+    const HostRep& p = h->hp[r];
+    d.ek_off = (int)ewk.size();
+    d.ek_n = 0;
+    d.sp_off = sp_total;
+    ew_off[r] = (int)ewf.size();
+    if (!(p.kmax > 0)) continue;
+    int nmax[3];
+    for (int k = 0; k < 3; ++k) nmax[k] = (int)std::floor(p.kmax * p.box[k] / (2.0 * M_PI));
+    const double V = p.box[0] * p.box[1] * p.box[2];
+    for (int n0 = 0; n0 <= nmax[0]; ++n0)
+      for (int n1 = -nmax[1]; n1 <= nmax[1]; ++n1)
+        for (int n2 = -nmax[2]; n2 <= nmax[2]; ++n2) {
+          if (n0 == 0 && (n1 < 0 || (n1 == 0 && n2 <= 0))) continue;
+          const double k0 = 2.0 * M_PI * n0 / p.box[0], k1 = 2.0 * M_PI * n1 / p.box[1],
+                       k2 = 2.0 * M_PI * n2 / p.box[2];
+          const double kk = k0 * k0 + k1 * k1 + k2 * k2;
+          if (kk > p.kmax * p.kmax) continue;
+          EwaldK e{};
+          e.n[0] = n0;
+          e.n[1] = n1;
+          e.n[2] = n2;
+          e.rep = r;
+          const double x = kk / (4.0 * p.beta * p.beta);
+          e.ek = 2.0 * (2.0 * M_PI * p.lB / V) * std::exp(-x) / kk;
+          e.c = 2.0 * (1.0 + x) / kk;
+          e.k[0] = k0;
+          e.k[1] = k1;
+          e.k[2] = k2;
+          ewk.push_back(e);
+        }
+    d.ek_n = (int)ewk.size() - d.ek_off;
+    const int nq = h->nq[r];
+    if (nq == 0 || d.ek_n == 0) continue;
+    for (int k0 = 0; k0 < d.ek_n; k0 += EW_SK_K)
+      for (int q0 = 0; q0 < nq; q0 += EW_SK_Q) ews.push_back(EwaldItem{r, k0, q0, 0});
+    for (int k0 = 0; k0 < d.ek_n; k0 += EW_F_K)
+      for (int q0 = 0; q0 < nq; q0 += EW_F_Q) ewf.push_back(EwaldItem{r, k0, q0, 0});
+    sp_total += (long long)((nq + EW_SK_Q - 1) / EW_SK_Q) * d.ek_n;
+  }
+  ew_off[R] = (int)ewf.size();
+  h->nitems_ew_s = (int)ews.size();
+  h->nitems_ew_f = (int)ewf.size();
+  upload(ewk, h->d_ewk, s);
+  upload(ews, h->d_ew_items_s, s);
+  upload(ewf, h->d_ew_items_f, s);
+  HIPCHK(h, h->ew_sp.alloc((size_t)std::max(1LL, sp_total) * 16));
+
   // clusters, tiles and neighbour lists
   std::vector<int> toff_g, toff_q, toff_256;
   std::vector<int2> clg, clq;
@@ -595,12 +655,14 @@ gcme_status build_plan(gcme_handle h) {
   upload(toff_q, h->d_off[SLOT_REAL], s);
   upload(item_off, h->d_off[SLOT_RECIP], s);
   upload(toff_256, h->d_off[SLOT_KIN], s);
+  upload(ew_off, h->d_off[SLOT_EWALD], s);
   upload(toff_g, h->d_adj_off[0], s);
   upload(toff_q, h->d_adj_off[1], s);
   HIPCHK(h, h->part[SLOT_GCM].alloc((size_t)std::max(1, h->ntiles_g) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_REAL].alloc((size_t)std::max(1, h->ntiles_q) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_RECIP].alloc((size_t)std::max(1, std::max(h->nitems[0], h->nitems[2])) * PART_W * 8));
   HIPCHK(h, h->part[SLOT_KIN].alloc((size_t)std::max(1, h->ntiles_256) * PART_W * 8));
+  HIPCHK(h, h->part[SLOT_EWALD].alloc((size_t)std::max(1, h->nitems_ew_f) * PART_W * 8));
   HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->ntiles_g) * (MAXT * MAXT + 2 * MAXT) * 8));
   HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->ntiles_q) * (MAXT * MAXT + 2 * MAXT) * 8));
 
@@ -701,6 +763,24 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
   return a;
 }
 
+EwaldLaunch ewald_args(gcme_handle h) {
+  EwaldLaunch a{};
+  a.rep = h->d_rep.as<RepDesc>();
+  a.kv = h->d_ewk.as<EwaldK>();
+  a.items_s = h->d_ew_items_s.as<EwaldItem>();
+  a.nitems_s = h->nitems_ew_s;
+  a.items_f = h->d_ew_items_f.as<EwaldItem>();
+  a.nitems_f = h->nitems_ew_f;
+  a.sp = h->ew_sp.as<double>();
+  a.qpk = h->q_pk.as<uint4>();
+  a.qidx = h->q_idx.as<int>();
+  for (int k = 0; k < 3; ++k) a.F[k] = Fk(h, k);
+  a.part = h->part[SLOT_EWALD].as<double>();
+  a.status = h->d_status.as<unsigned>();
+  a.fscale = h->fscale();
+  return a;
+}
+
 PmeLaunch pme_args(gcme_handle h) {
   PmeLaunch a{};
   a.rep = h->d_rep.as<RepDesc>();
@@ -724,9 +804,14 @@ PmeLaunch pme_args(gcme_handle h) {
   a.Qc = h->Qc.p;
   a.plane_major = h->yx_fused ? 1 : 0;
   a.plane_elems = h->plane_elems;
-  a.plane_k = h->rep[0].K[0] == h->rep[0].K[1] ? h->rep[0].K[0] : 0;
-  for (int r = 1; r < h->R; ++r)
-    if (h->rep[r].K[0] != a.plane_k || h->rep[r].K[1] != a.plane_k) a.plane_k = 0;
+  a.plane_k = -1;  // K0 = K1 of every replica with a mesh, else 0
+  for (int r = 0; r < h->R; ++r) {
+    const int k0 = h->rep[r].K[0], k1 = h->rep[r].K[1];
+    if (k0 == 0) continue;
+    if (a.plane_k < 0) a.plane_k = k0 == k1 ? k0 : 0;
+    if (k0 != a.plane_k || k1 != a.plane_k) a.plane_k = 0;
+  }
+  if (a.plane_k < 0) a.plane_k = 0;
   a.tw = h->d_tw.p;
   a.radix = h->d_rad.as<int>();
   a.bsp = h->d_bsp.p;
@@ -820,6 +905,8 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
       launch_fft_y(sp, p, h->fp64, true);
     }
     launch_z_gather(sp, p, h->fp64);
+    // replicas with the exact reciprocal sum instead of a mesh
+    launch_ewald(sp, ewald_args(h), h->fp64, ev);
   };
   for (int k = 0; k < 3; ++k) {
     if (L.order[k] == 'g') gcm();
@@ -852,6 +939,7 @@ void enqueue_outputs(gcme_handle h, hipStream_t s, const gcme_io* io, bool kin) 
       // no charged beads: the charged kernels did not run, their slots are empty ranges
       f.part[SLOT_REAL] = nullptr;
       f.part[SLOT_RECIP] = nullptr;
+      f.part[SLOT_EWALD] = nullptr;
     }
     f.consts = h->d_consts.as<double>();
     f.energy = io->energy;
@@ -1025,10 +1113,18 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
   if (!(p->beta > 0.0)) return fail(h, GCME_EINVAL, "beta must be > 0");
   if (!(p->lB >= 0.0)) return fail(h, GCME_EINVAL, "lB must be >= 0");
   if (p->order < 3 || p->order > 8) return fail(h, GCME_EUNSUPPORTED, "B-spline order must be 3..8");
-  for (int k = 0; k < 3; ++k) {
-    int K = p->grid[k];
-    if (K < 8 || K > 512 || !smooth(K)) return fail(h, GCME_EUNSUPPORTED, "mesh sizes must be 2^a 3^b in 8..512");
-    if (p->order > K / 2) return fail(h, GCME_EUNSUPPORTED, "order must be <= K/2");
+  if (!(p->kmax >= 0.0) || !std::isfinite(p->kmax)) return fail(h, GCME_EINVAL, "kmax must be >= 0");
+  if (p->kmax > 0.0) {
+    // exact reciprocal sum: the integer wave vectors per axis stay bounded
+    for (int k = 0; k < 3; ++k)
+      if (p->kmax * p->box[k] / (2.0 * M_PI) > (double)EW_NMAX)
+        return fail(h, GCME_EUNSUPPORTED, "kmax L / (2 pi) must be <= 64 on every axis");
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      int K = p->grid[k];
+      if (K < 8 || K > 512 || !smooth(K)) return fail(h, GCME_EUNSUPPORTED, "mesh sizes must be 2^a 3^b in 8..512");
+      if (p->order > K / 2) return fail(h, GCME_EUNSUPPORTED, "order must be <= K/2");
+    }
   }
   if (p->n_types < 1 || p->n_types > MAXT) return fail(h, GCME_EUNSUPPORTED, "n_types must be 1..4");
   if (!p->A || !p->sigma || !p->a) return fail(h, GCME_EINVAL, "A, sigma and a are required");
@@ -1062,8 +1158,9 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
     HostRep& q = h->hp[r];
     for (int k = 0; k < 3; ++k) {
       q.box[k] = p->box[k];
-      q.K[k] = p->grid[k];
+      q.K[k] = p->kmax > 0.0 ? 0 : p->grid[k];  // no mesh with the exact sum
     }
+    q.kmax = p->kmax;
     q.rc = p->cutoff;
     q.beta = p->beta;
     q.lB = p->lB;

@@ -44,6 +44,9 @@ struct RepDesc {
   int bsp_off[3];     // offsets of the Green factor and m/L tables per axis
   int rad_off[3];     // offset of the radix list of each axis length
   int nrad[3];
+  // exact reciprocal sum (replicas with kmax > 0, which have no mesh: K = 0)
+  int ek_off, ek_n;   // the replica's wave vectors in the k table
+  long long sp_off;   // its partial structure factors, [charged chunk][ek_n]
 };
 
 // Pair coefficients of one type pair for the excluded-volume term:
@@ -110,7 +113,7 @@ struct Tile {
 constexpr int BEAD_THREADS = 256;
 
 // Slots of the per-block partial sums (7 doubles: energy, virial[6]).
-enum { SLOT_GCM = 0, SLOT_REAL = 1, SLOT_RECIP = 2, SLOT_KIN = 3, N_SLOTS = 4 };
+enum { SLOT_GCM = 0, SLOT_REAL = 1, SLOT_RECIP = 2, SLOT_KIN = 3, SLOT_EWALD = 4, N_SLOTS = 5 };
 constexpr int PART_W = 8;
 
 // Device status bits.
@@ -277,6 +280,42 @@ void launch_fft_yx_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev);
 size_t pme_plane_lds_bytes(int plane_elems, int maxK0, int maxK1, int maxK2, bool fp64);
 void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64);
 size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64);
+
+// ewald.hip: the reciprocal term of eq. ewald summed exactly over the wave
+// vectors k = 2 pi (n0/L0, n1/L1, n2/L2) != 0 with |k| <= kmax, for the
+// replicas that ask for it instead of the mesh.
+struct EwaldK {
+  int n[3];     // integer wave vector of the half space (n0 > 0; or n0 = 0, n1 > 0;
+                // or n0 = n1 = 0, n2 > 0); -k is counted through ek
+  int rep;
+  double ek;    // 2 (2 pi lB / V) exp(-k^2 / (4 beta^2)) / k^2: energy per |S(k)|^2
+  double c;     // 2 (1 + k^2 / (4 beta^2)) / k^2 (virial)
+  double k[3];  // the wave vector (1 / length)
+};
+// Work tile of the exact sum: wave vectors k0 .. k0 + KCH - 1 of a replica
+// against its charged beads q0 .. q0 + QCH - 1 (replica-relative).
+struct EwaldItem {
+  int rep, k0, q0, pad;
+};
+constexpr int EW_SK_K = 64, EW_SK_Q = 256;  // structure-factor tiles (k x charged)
+constexpr int EW_F_K = 256, EW_F_Q = 64;    // force tiles
+constexpr int EW_NMAX = 64;                 // largest |n_a| of a wave vector
+struct EwaldLaunch {
+  const RepDesc* rep;
+  const EwaldK* kv;
+  const EwaldItem* items_s;
+  int nitems_s;
+  const EwaldItem* items_f;
+  int nitems_f;
+  double* sp;           // partial structure factors (re, im) per replica at sp_off
+  const uint4* qpk;     // packed charged beads (cell order)
+  const int* qidx;      // charged -> sorted bead index
+  long long* F[3];
+  double* part;         // SLOT_EWALD partials [nitems_f][PART_W]
+  unsigned int* status;
+  double fscale;
+};
+void launch_ewald(hipStream_t s, const EwaldLaunch& a, bool fp64, bool ev);
 
 // integrate.hip
 struct IntLaunch {

@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinalLaunch a) {
       double* E = a.energy + (size_t)r * 7;
       E[0] = res[SLOT_GCM][0];
       E[1] = res[SLOT_REAL][0];
-      E[2] = res[SLOT_RECIP][0];
+      E[2] = res[SLOT_RECIP][0] + res[SLOT_EWALD][0];  // a replica has one of the two
       E[3] = ec;
       E[4] = es;
       E[5] = ((E[0] + E[1]) + (E[2] + E[3])) + E[4];
@@ -278,7 +278,8 @@ __global__ __launch_bounds__(256) void k_finalize(FinalLaunch a) {
     }
     if (a.virial) {
       for (int k = 0; k < 6; ++k)
-        a.virial[(size_t)r * 6 + k] = (res[SLOT_GCM][1 + k] + res[SLOT_REAL][1 + k]) + res[SLOT_RECIP][1 + k];
+        a.virial[(size_t)r * 6 + k] =
+            (res[SLOT_GCM][1 + k] + res[SLOT_REAL][1 + k]) + (res[SLOT_RECIP][1 + k] + res[SLOT_EWALD][1 + k]);
     }
   }
   if (a.dE_dA || a.dE_dsigma || a.dE_da) {

@@ -28,6 +28,7 @@ class ReplicaParams:
     dt: float = 0.02
     gamma: float = 1.0
     flags: int = 0
+    kmax: float = 0.0  # > 0: exact reciprocal sum over |k| <= kmax instead of the mesh
 
 
 def _ptr(t):
@@ -92,7 +93,7 @@ class GCMe:
                            (C.c_int32 * 3)(*[int(k) for k in p.grid]), int(p.order), float(p.lB), nt,
                            A.ctypes.data_as(dp), s.ctypes.data_as(dp), a.ctypes.data_as(dp),
                            m.ctypes.data_as(dp) if m is not None else None, float(p.kT), float(p.dt),
-                           float(p.gamma), int(p.flags))
+                           float(p.gamma), int(p.flags), float(p.kmax))
         B.check(self.h, self.lib.gcme_set_params(self.h, int(replica), C.byref(cp)))
         for r in (range(self.R) if replica < 0 else [replica]):
             self.params[r] = p

@@ -5,11 +5,14 @@ import numpy as np
 from oracle import oracle as O
 
 
-def make_engine(ws, precision, seed=1, tuning=None):
+def make_engine(ws, precision, seed=1, tuning=None, kmax=None):
+    """kmax: None (every replica on its mesh) or one value per replica (> 0:
+    that replica's reciprocal sum taken exactly over |k| <= kmax)."""
     from paper_2403_08148_amd import GCMe, params_from_workload
     eng = GCMe([w.N for w in ws], precision=precision, seed=seed)
     for r, w in enumerate(ws):
-        eng.set_params(params_from_workload(w), replica=r)
+        over = {} if kmax is None else dict(kmax=float(kmax[r]))
+        eng.set_params(params_from_workload(w, **over), replica=r)
     if tuning:
         eng.set_tuning(**tuning)
     pos = np.concatenate([w.pos for w in ws])
@@ -34,9 +37,14 @@ def oracle_params(w, **over):
     return O.Params(**d)
 
 
-def oracle_eval(w, adjoint=False):
+def oracle_eval(w, adjoint=False, kmax=0.0):
+    """The oracle's forces, energy terms and virial: SPME on the workload's
+    mesh, or with kmax > 0 the exact reciprocal sum over |k| <= kmax."""
     p = oracle_params(w)
-    ref = O.forces(w.pos, w.type, w.z, p, recip_mode=O.RECIP_SPME, K=w.grid, order=w.order)
+    if kmax > 0:
+        ref = O.forces(w.pos, w.type, w.z, p, recip_mode=O.RECIP_EWALD, kmax=kmax)
+    else:
+        ref = O.forces(w.pos, w.type, w.z, p, recip_mode=O.RECIP_SPME, K=w.grid, order=w.order)
     if adjoint:
         rs = O.real_space(w.pos, w.type, w.z, p, adjoint=True)
         c = O.constants(w.type, w.z, p)
