@@ -253,12 +253,14 @@ def time_steps(eng, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def engine_for(ws, precision, tune=True):
+def engine_for(ws, precision, tune=True, kmax=0.0):
+    """An engine over the workloads (kmax > 0: the exact reciprocal sum over
+    |k| <= kmax in place of the mesh)."""
     from paper_2403_08148_amd import GCMe, params_from_workload
     import numpy as np
     eng = GCMe([x.N for x in ws], precision=precision, seed=12345)
     for r, x in enumerate(ws):
-        eng.set_params(params_from_workload(x), replica=r)
+        eng.set_params(params_from_workload(x, kmax=kmax), replica=r)
     eng.set_state(np.concatenate([x.pos for x in ws]), np.concatenate([x.type for x in ws]),
                   np.concatenate([x.z for x in ws]), np.concatenate([x.vel for x in ws]))
     tuning = eng.autotune() if tune else eng.tuning()
@@ -267,8 +269,9 @@ def engine_for(ws, precision, tune=True):
 
 def extra_workloads(w):
     """The plain FP64 form of the same workload, the 2,097,152-bead bulk
-    system (mixed and FP64) and 256 batched replicas against one engine per
-    replica called in sequence."""
+    system (mixed and FP64), 256 batched replicas against one engine per
+    replica called in sequence, and the 1,536-bead plain-method system with
+    the exact reciprocal sum against its mesh form."""
     import numpy as np
     import gcme_workloads as W
     out = {}
@@ -322,6 +325,24 @@ def extra_workloads(w):
                                    "pair_interactions_per_s": pairs * 1000.0 / ms_b,
                                    "sequential_ms_per_step": ms_seq, "speedup_vs_sequential": ms_seq / ms_b,
                                    "tuning": tun}
+
+    # 4. the plain-method configuration (N = 1536) with the reciprocal sum
+    #    taken exactly over |k| <= 8, against the same system on its 32^3 mesh
+    w1 = W.config1()
+    res = {}
+    fr = {}
+    for prec in ("fp64", "mixed"):
+        for mode, km in (("exact_k_sum", w1.kmax), ("spme_32", 0.0)):
+            eng, tun = engine_for([w1], prec, kmax=km)
+            fr[(prec, mode)] = forces(eng)
+            res[f"{prec}_{mode}"] = {"ms_per_step": time_steps(eng, 200, 20), "tuning": tun}
+            eng.close()
+    fx = fr[("fp64", "exact_k_sum")]
+    res["mixed_force_rel_rms_vs_fp64_exact"] = float(np.linalg.norm(fr[("mixed", "exact_k_sum")] - fx) /
+                                                     np.linalg.norm(fx))
+    res["spme_force_rel_rms_vs_exact_fp64"] = float(np.linalg.norm(fr[("fp64", "spme_32")] - fx) / np.linalg.norm(fx))
+    res["kmax"] = w1.kmax
+    out[w1.name] = res
     return out
 
 
