@@ -101,3 +101,25 @@ def test_exact_sum_in_steps(precision):
     w.pos = pos.cpu().numpy().T.copy()
     ref = oracle_eval(w, kmax=6.5)
     _cmp(again["force"], again["energy"][0], again["virial"][0], ref, *TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_all_reciprocal_limit(precision):
+    # Every bead with the same smearing radius a: beta = alpha = sqrt(pi)/(2a)
+    # (G = a/sqrt(pi)) makes the real-space bracket vanish (up to the
+    # rounding of alpha against beta), and
+    # the whole smeared Coulomb energy sits in the reciprocal sum (here exact,
+    # |k| <= 17: exp(-k^2/(4 beta^2)) < 1e-20 beyond it).
+    a = 0.5
+    beta = np.sqrt(np.pi) / (2.0 * a)
+    w = W.small_bulk(N=420, seed=26, charged_frac=0.3, a_types=(a,), box=(6.0, 6.2, 5.8), rc=2.5,
+                     beta=beta, grid=(24, 24, 24))
+    print(f"case all-reciprocal beta = alpha = {beta:.6f} prec={precision}", flush=True)
+    eng = make_engine([w], precision, kmax=[17.0])
+    got = gpu_eval(eng)
+    eng.close()
+    # E_real: zero up to the rounding of alpha against beta
+    scale = np.abs(got["energy"][0][2:5]).sum()
+    assert abs(got["energy"][0][1]) < 1e-12 * scale
+    ref = oracle_eval(w, kmax=17.0)
+    _cmp(got["force"], got["energy"][0], got["virial"][0], ref, *TOL[precision])
