@@ -116,6 +116,17 @@ typedef struct {
  * (Model and methods, after eq. u_elec).  Without the flag it is not checked. */
 #define GCME_FLAG_STRICT_CONTACT 1u
 
+/* All-reciprocal splitting: G = a/sqrt(pi), i.e. beta = alpha = sqrt(pi)/(2a),
+ * the choice under which the real-space bracket of eq. ewald vanishes for
+ * equal smearing radii (Model and methods, on the choice of G): the smeared
+ * Coulomb interaction lies wholly in the reciprocal sum, whose Gaussian is
+ * then the smearing itself.  Requires one charge radius a for every type
+ * (GCME_EINVAL otherwise); `beta` is ignored and the real-space electrostatic
+ * pairs are not evaluated (U_real = 0).  The reciprocal sum needs a mesh (or
+ * kmax) fine enough for that beta.  dE/da is not provided for such a replica
+ * (GCME_EUNSUPPORTED when requested), since beta then depends on a. */
+#define GCME_FLAG_ALL_RECIPROCAL 2u
+
 typedef struct {
     const double* pos;   /* device [3][N_total] new positions, or NULL = keep state */
     double* force;       /* device [3][N_total] out, or NULL */

@@ -15,6 +15,7 @@ GCME_FP64, GCME_MIXED = 0, 1
 GCME_E_EX, GCME_E_REAL, GCME_E_RECIP, GCME_E_CORR, GCME_E_SELF, GCME_E_POT, GCME_E_KIN, GCME_N_TERMS = range(8)
 GCME_MAX_TYPES = 4
 GCME_FLAG_STRICT_CONTACT = 1
+GCME_FLAG_ALL_RECIPROCAL = 2
 
 STATUS_NAMES = {0: "GCME_OK", 1: "GCME_EINVAL", 2: "GCME_EUNSUPPORTED", 3: "GCME_EGEOMETRY",
                 4: "GCME_ENONNEUTRAL", 5: "GCME_ESTATE", 6: "GCME_EDEVICE", 7: "GCME_ENOMEM",

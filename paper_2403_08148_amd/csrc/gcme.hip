@@ -388,7 +388,9 @@ void plan_clusters(gcme_handle h, bool charged, int ci, std::vector<int2>& cl, s
   double cmax = 64.0;
   for (int r = 0; r < h->R; ++r) {
     const RepDesc& d = h->rep[r];
-    const int n = charged ? h->nq[r] : h->nb[r];
+    // an all-reciprocal replica has no real-space electrostatic pairs
+    const bool skip = charged && (h->hp[r].flags & GCME_FLAG_ALL_RECIPROCAL);
+    const int n = skip ? 0 : charged ? h->nq[r] : h->nb[r];
     const int off = charged ? h->qoff[r] : h->boff[r];
     toff[r] = (int)tiles.size();
     if (n == 0) continue;
@@ -1139,6 +1141,14 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
     }
   }
   if (!(p->kT >= 0.0) || !(p->dt >= 0.0) || !(p->gamma >= 0.0)) return fail(h, GCME_EINVAL, "kT, dt, gamma must be >= 0");
+  double beta = p->beta;
+  if (p->flags & GCME_FLAG_ALL_RECIPROCAL) {
+    // beta = alpha_ij = sqrt(pi/2)/a_ij with a_ij = sqrt(2) a: one radius for all
+    for (int t = 1; t < nt; ++t)
+      if (std::fabs(p->a[t] - p->a[0]) > 1e-12 * p->a[0])
+        return fail(h, GCME_EINVAL, "the all-reciprocal splitting needs one charge radius a for every type");
+    beta = std::sqrt(M_PI) / (2.0 * p->a[0]);
+  }
   if (p->flags & GCME_FLAG_STRICT_CONTACT) {
     // no-collapse condition between unit charges of opposite sign
     for (int t = 0; t < nt; ++t)
@@ -1162,7 +1172,7 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
     }
     q.kmax = p->kmax;
     q.rc = p->cutoff;
-    q.beta = p->beta;
+    q.beta = beta;
     q.lB = p->lB;
     q.kT = p->kT;
     q.dt = p->dt;
@@ -1273,6 +1283,10 @@ gcme_status gcme_forces_energy(gcme_handle h, const gcme_io* io) {
   if (!io) return fail(h, GCME_EINVAL, "null io");
   gcme_status st = check_ready(h);
   if (st != GCME_OK) return st;
+  if (io->dE_da)
+    for (int r = 0; r < h->R; ++r)
+      if (h->hp[r].flags & GCME_FLAG_ALL_RECIPROCAL)
+        return fail(h, GCME_EUNSUPPORTED, "dE/da is not provided with the all-reciprocal splitting");
   HIPCHK(h, hipSetDevice(h->device));
   hipStream_t s = h->stream;
   if (io->pos)

@@ -123,3 +123,38 @@ def test_all_reciprocal_limit(precision):
     assert abs(got["energy"][0][1]) < 1e-12 * scale
     ref = oracle_eval(w, kmax=17.0)
     _cmp(got["force"], got["energy"][0], got["virial"][0], ref, *TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_all_reciprocal_flag(precision):
+    # GCME_FLAG_ALL_RECIPROCAL sets beta = sqrt(pi)/(2a) itself and skips the
+    # real-space electrostatic pairs: E_real is exactly zero, and forces and
+    # energies agree with the explicit beta = alpha run (whose real-space
+    # term is the rounding of alpha - beta) and with the oracle.
+    from paper_2403_08148_amd import GCMe, params_from_workload
+    from paper_2403_08148_amd._binding import GCMeError, GCME_FLAG_ALL_RECIPROCAL
+    a = 0.5
+    beta = np.sqrt(np.pi) / (2.0 * a)
+    w = W.small_bulk(N=420, seed=26, charged_frac=0.3, a_types=(a,), box=(6.0, 6.2, 5.8), rc=2.5,
+                     beta=beta, grid=(24, 24, 24))
+    print(f"case all-reciprocal flag prec={precision}", flush=True)
+    eng = make_engine([w], precision, kmax=[17.0])
+    ref_gpu = gpu_eval(eng)
+    eng.set_params(params_from_workload(w, beta=3.0, kmax=17.0, flags=GCME_FLAG_ALL_RECIPROCAL))
+    got = gpu_eval(eng)
+    assert got["energy"][0][1] == 0.0
+    ferr = rel_rms(got["force"], ref_gpu["force"])
+    print(f"  flag vs explicit beta = alpha: force {ferr:.2e}", flush=True)
+    assert ferr < (1e-13 if precision == "fp64" else 1e-6)
+    np.testing.assert_allclose(got["energy"][0][2:5], ref_gpu["energy"][0][2:5], rtol=1e-12)
+    _cmp(got["force"], got["energy"][0], got["virial"][0], oracle_eval(w, kmax=17.0), *TOL[precision])
+    # dE/da is not provided under the flag; unequal radii are rejected
+    with pytest.raises(GCMeError):
+        eng.forces_energy(adjoint=True)
+    eng.close()
+    w2 = W.small_bulk(N=300, seed=27, charged_frac=0.3, a_types=(0.4, 0.6), box=(6.0, 6.0, 6.0), rc=2.5,
+                      grid=(24, 24, 24))
+    e2 = GCMe([w2.N], precision=precision)
+    with pytest.raises(GCMeError):
+        e2.set_params(params_from_workload(w2, flags=GCME_FLAG_ALL_RECIPROCAL))
+    e2.close()
