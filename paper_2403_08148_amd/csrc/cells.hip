@@ -130,6 +130,7 @@ constexpr int SINGLE_SCAN_MAX = 38912;  // counts staged in up to 152 KiB of LDS
 __global__ __launch_bounds__(SINGLE_SCAN_THREADS) void k_scan_single(CellView c) {
   __shared__ int sh[SINGLE_SCAN_THREADS / 64];
   extern __shared__ __align__(16) int buf[];  // ncells entries
+  if (c.step && blockIdx.x == 0 && threadIdx.x == 0) *c.step += 1ULL;
   if (blockIdx.x == 0)
     block_scan_counts<SINGLE_SCAN_THREADS, SCAN_UNROLL>(c.counts, c.start, c.fill, c.ncells, buf, sh);
   else
@@ -160,6 +161,7 @@ __global__ void k_scan_reduce(CellView c, int nb) {
 // One block: exclusive scan of the block sums (both arrays).
 __global__ void k_scan_top(CellView c, int nb) {
   __shared__ int sh[8];
+  if (c.step && threadIdx.x == 0) *c.step += 1ULL;
   for (int arr = 0; arr < 2; ++arr) {
     int* bs = c.bsum + arr * nb;
     int carry = 0;

@@ -218,6 +218,7 @@ CellView cview(gcme_handle h) {
   c.start = h->start.as<int>();
   c.qstart = h->qstart.as<int>();
   c.bsum = h->bsum.as<int>();
+  c.step = nullptr;
   c.ncells = h->ncells;
   return c;
 }
@@ -838,7 +839,6 @@ IntLaunch int_args(gcme_handle h) {
   a.nbeads = h->N;
   a.seed = h->seed;
   a.step = h->d_step.as<unsigned long long>();
-  a.done = reinterpret_cast<unsigned*>(h->d_step.as<char>() + 8);
   a.fscale_inv = 1.0 / h->fscale();
   a.part = h->part[SLOT_KIN].as<double>();
   return a;
@@ -849,6 +849,9 @@ IntLaunch int_args(gcme_handle h) {
 void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
   // counts are left cleared by the previous permute (and at plan build)
   CellView c = cview(h);
+  // a step's sort (after the integrator's binning) starts the next step:
+  // its scan advances the step counter
+  if (!bin) c.step = h->d_step.as<unsigned long long>();
   if (bin) launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
   launch_scan(s, c);
   launch_scatter(s, c, h->N);

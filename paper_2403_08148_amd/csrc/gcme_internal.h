@@ -144,6 +144,8 @@ struct CellView {
   int* start;        // [Ncells + 1]
   int* qstart;       // [Ncells + 1]
   int* bsum;         // scan block sums [2 * nblocks]
+  unsigned long long* step;  // with a step's sort: the step counter, which the
+                             // scan advances by one (one thread); else null
   int ncells;
 };
 
@@ -329,10 +331,10 @@ struct IntLaunch {
   const int* langevin;      // [R]
   int nbeads;
   unsigned long long seed;
-  unsigned long long* step; // device counter: step being taken (the last
-                            // kernel of a step advances it, so captured
-                            // steps can be replayed)
-  unsigned* done;           // blocks finished (the fused between-steps kernel), left 0
+  unsigned long long* step; // device counter: step being taken (advanced by
+                            // the scan of each step's sort, before the
+                            // integrator of the next first half reads it,
+                            // so captured steps can be replayed)
   double fscale_inv;
   double* part;             // kinetic partials [ntiles][PART_W]
 };
