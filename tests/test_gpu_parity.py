@@ -109,3 +109,41 @@ def test_deterministic_reruns():
     np.testing.assert_array_equal(a["force"], b["force"])
     np.testing.assert_array_equal(a["energy"], b["energy"])
     np.testing.assert_array_equal(a["virial"], b["virial"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("tuning", [dict(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=4, direct_pairs=3),
+                                    dict(cells_per_cutoff=2, beads_per_cluster=4, charges_per_cluster=2, direct_pairs=3),
+                                    dict(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=4, direct_pairs=0)])
+def test_forces_only_pass_parity(precision, tuning):
+    # The pass a step runs (forces, no energy or virial) has kernels of its
+    # own (no per-pair validity test in the list-free excluded-volume kernel,
+    # a padded final drain): its forces against the oracle at full size.
+    w = W.config2()
+    print(f"case forces-only {w.name} prec={precision} tuning={tuning}", flush=True)
+    eng = make_engine([w], precision, tuning=tuning)
+    F = eng.forces_energy(energy=False, virial=False)["force"]
+    eng.sync()
+    F = F.cpu().numpy().T
+    eng.close()
+    ref = oracle_eval(w)
+    ferr = rel_rms(F, ref["F"])
+    print(f"  force {ferr:.2e}", flush=True)
+    assert ferr < TOL[precision][0]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_forces_only_small_boxes(precision):
+    # clusters outside the first-bead frame (boxes near 2 rc) in the forces-only pass
+    for w in (W.small_bulk(N=350, seed=13, charged_frac=0.4, box=(5.2, 5.3, 5.05), rc=2.5, grid=(16, 16, 16)),
+              W.small_bulk(N=1001, seed=4, charged_frac=0.25, a_types=(0.3, 0.5, 0.7), box=(7.7, 8.3, 6.5),
+                           rc=2.6, grid=(27, 36, 24), order=4)):
+        for ci in (2, 4, 8):
+            eng = make_engine([w], precision, tuning=dict(cells_per_cutoff=3, beads_per_cluster=ci, direct_pairs=3))
+            F = eng.forces_energy(energy=False, virial=False)["force"]
+            eng.sync()
+            F = F.cpu().numpy().T
+            eng.close()
+            ferr = rel_rms(F, oracle_eval(w)["F"])
+            print(f"case forces-only {w.name} box={w.box} CI={ci} prec={precision}: force {ferr:.2e}", flush=True)
+            assert ferr < TOL[precision][0]
