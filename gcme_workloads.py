@@ -146,6 +146,17 @@ def config2():
     return bulk("bulk_N32768_mixed", 32768, 2, 0.2, [0.4, 0.6], A, 3.0, 1.1, (64, 64, 64))
 
 
+def config3():
+    """The polyelectrolyte-slab workload's composition and mesh as a periodic
+    bulk box (its chains' bonds, the electrodes and the image charges are not
+    part of the nonbonded path): N = 200,000 in 40 x 40 x 50 (rho = 2.5),
+    50,000 beads at +1 (the charged chain monomers) and 50,000 at -1 (the
+    counterions), the rest neutral; one species a = sigma = 0.5, A = 25,
+    rc = 3, beta = 1.1, SPME 96 x 96 x 128 order 5."""
+    return bulk("bulk_N200000_slab_shape", 200000, 3, 0.5, [0.5], [[25.0]], 3.0, 1.1, (96, 96, 128),
+                box=(40.0, 40.0, 50.0))
+
+
 def config4():
     """Large bulk: N = 2^21, three species a = 0.3/0.5/0.7, A ~ U(15, 35)
     symmetric (seeded), 15% charged, rc = 2.5, beta = 1.2, SPME 256^3."""

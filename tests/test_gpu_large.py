@@ -6,6 +6,9 @@
   mixed-precision run against the plain FP64 GPU run on all beads.
 * 256 batched replicas of uneven size and parameters: every replica's forces
   and energies against the oracle run on that replica alone.
+* N = 200,000 with the polyelectrolyte workload's composition, box and mesh
+  (50% charged, 40 x 40 x 50, SPME 96 x 96 x 128) as a periodic bulk box:
+  sampled forces and every energy term against the oracle.
 """
 import numpy as np
 import pytest
@@ -71,6 +74,44 @@ def test_two_million_beads_mixed_against_fp64(big):
     ferr = rel_rms(got[("fp64", 3)]["force"], got[("fp64", 0)]["force"])
     print(f"  list-free vs lists, FP64, all beads: force {ferr:.2e}", flush=True)
     assert ferr < 1e-12
+
+
+@pytest.fixture(scope="module")
+def slab_shape():
+    w = W.config3()
+    print(f"case {w.name} N={w.N} box={w.box} grid={w.grid}", flush=True)
+    got = {}
+    for prec in ("mixed", "fp64"):
+        eng = make_engine([w], prec)
+        got[prec] = gpu_eval(eng)
+        eng.close()
+        print(f"  gpu {prec} done", flush=True)
+    p = oracle_params(w)
+    idx = np.sort(np.random.default_rng(303).choice(w.N, 600, replace=False))
+    rs = O.real_space(w.pos, w.type, w.z, p, sample=idx, energies=False)
+    q = np.flatnonzero(w.z != 0)
+    rec = O.spme_recip(w.pos[q], w.z[q], w.box, w.beta, w.lB, w.grid, w.order)
+    Frec = np.zeros((w.N, 3))
+    Frec[q] = rec["F"]
+    full = O.real_space(w.pos, w.type, w.z, p)
+    c = O.constants(w.type, w.z, p)
+    E_ref = np.array([full["E_ex"], full["E_real"], rec["E_recip"], c["E_corr"], c["E_self"]])
+    print("  oracle done", flush=True)
+    return w, got, idx, rs["F"] + Frec[idx], E_ref
+
+
+@pytest.mark.parametrize("precision,ftol,etol", [("fp64", 1e-9, 1e-10), ("mixed", 1e-5, 1e-6)])
+def test_slab_shaped_bulk_against_oracle(slab_shape, precision, ftol, etol):
+    # the polyelectrolyte workload's composition (50% charged), box 40 x 40 x 50
+    # and 96 x 96 x 128 mesh, as a periodic bulk box
+    w, got, idx, F_ref, E_ref = slab_shape
+    g = got[precision]
+    ferr = rel_rms(g["force"][idx], F_ref)
+    eerr = energy_errors(g["energy"][0][:5], E_ref)
+    print(f"  {precision}: sampled force {ferr:.2e} energies {np.array2string(eerr, precision=2)}", flush=True)
+    assert ferr < ftol
+    assert np.all(eerr < etol), eerr
+    assert rel_rms(got["mixed"]["force"], got["fp64"]["force"]) < 1e-5
 
 
 @pytest.mark.parametrize("precision,ftol,etol", [("fp64", 1e-9, 1e-10), ("mixed", 1e-5, 1e-6)])
