@@ -309,13 +309,6 @@ void launch_ingest(hipStream_t s, const double* pos_soa, int N, long long ld, co
                      F + 2LL * nF, nF);
 }
 
-void launch_fill_i32(hipStream_t s, int* p, int v, long long n) {
-  if (n <= 0) return;
-  int b = nblk(n, 256);
-  if (b > 4096) b = 4096;
-  hipLaunchKernelGGL(k_fill<int>, dim3(b), dim3(256), 0, s, p, v, n);
-}
-
 void launch_fill_i64(hipStream_t s, long long* p, long long v, long long n) {
   if (n <= 0) return;
   int b = nblk(n, 256);

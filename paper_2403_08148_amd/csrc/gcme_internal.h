@@ -202,7 +202,6 @@ struct ChargedView {
 // cells.hip
 void launch_ingest(hipStream_t s, const double* pos_soa, int N, long long ld, const RepDesc* rep,
                    const uint32_t* param, StateView A, long long* F, int nF);
-void launch_fill_i32(hipStream_t s, int* p, int v, long long n);
 void launch_fill_i64(hipStream_t s, long long* p, long long v, long long n);
 void launch_bin(hipStream_t s, StateView A, const RepDesc* rep, CellView c, int N);
 void launch_scan(hipStream_t s, CellView c);
