@@ -152,7 +152,8 @@ struct gcme_ctx {
   //          fused with the next step's first half and binning)
   //   g_last / g_obs: the same, ending with the plain second half (g_obs also
   //          accumulates the energy, virial and kinetic partials)
-  hipGraphExec_t g_mid = nullptr, g_last = nullptr, g_obs = nullptr;
+  //   g_midn: MID_BATCH consecutive g_mid steps in one graph (one launch)
+  hipGraphExec_t g_mid = nullptr, g_midn = nullptr, g_last = nullptr, g_obs = nullptr;
 
   ~gcme_ctx() {
     drop_graphs();
@@ -166,15 +167,18 @@ struct gcme_ctx {
   }
   void drop_graphs() {
     if (g_mid) (void)hipGraphExecDestroy(g_mid);
+    if (g_midn) (void)hipGraphExecDestroy(g_midn);
     if (g_last) (void)hipGraphExecDestroy(g_last);
     if (g_obs) (void)hipGraphExecDestroy(g_obs);
-    g_mid = g_last = g_obs = nullptr;
+    g_mid = g_midn = g_last = g_obs = nullptr;
   }
   double fscale() const { return std::ldexp(1.0, fp64 ? FSHIFT_FP64 : FSHIFT_MIXED); }
   double qscale() const { return std::ldexp(1.0, fp64 ? FSHIFT_FP64 : FSHIFT_MIXED); }
 };
 
 namespace {
+
+constexpr int MID_BATCH = 8;  // steps per graph launch in long runs
 
 thread_local std::string g_create_err;
 
@@ -996,10 +1000,10 @@ void enqueue_step_rest(gcme_handle h, hipStream_t s, bool between, bool ev) {
     launch_int_last(s, ia, viewB(h), viewA(h), F3, ev);
 }
 
-gcme_status capture(gcme_handle h, bool between, bool ev, hipGraphExec_t* out) {
+gcme_status capture(gcme_handle h, bool between, bool ev, hipGraphExec_t* out, int repeat = 1) {
   hipGraph_t g = nullptr;
   HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-  enqueue_step_rest(h, h->cap_stream, between, ev);
+  for (int k = 0; k < repeat; ++k) enqueue_step_rest(h, h->cap_stream, between, ev);
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (e != hipSuccess) return fail(h, GCME_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -1338,7 +1342,17 @@ gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe) {
     CellView c = cview(h);
     launch_int_first(h->stream, ia, viewA(h), F3, &c);
   }
-  for (int i = 0; i < n_steps - 1; ++i) HIPCHK(h, hipGraphLaunch(h->g_mid, h->stream));
+  // long runs replay MID_BATCH steps per graph launch: the host-side cost of a
+  // launch (tens of microseconds) is paid once per batch
+  int rest = n_steps - 1;
+  if (rest >= MID_BATCH) {
+    if (!h->g_midn) {
+      st = capture(h, true, false, &h->g_midn, MID_BATCH);
+      if (st != GCME_OK) return st;
+    }
+    for (; rest >= MID_BATCH; rest -= MID_BATCH) HIPCHK(h, hipGraphLaunch(h->g_midn, h->stream));
+  }
+  for (int i = 0; i < rest; ++i) HIPCHK(h, hipGraphLaunch(h->g_mid, h->stream));
   HIPCHK(h, hipGraphLaunch(*last, h->stream));
   if (obs) {
     // the step left A == B (same order); outputs read B and the partials
