@@ -20,6 +20,11 @@
  *   - Forces F = -dE/dr, the virial tensor sum r_ij (x) f_ij (eq. pres_virial
  *     uses its trace) plus the reciprocal-space virial.
  *   - Parameter derivatives dE/dA (per type pair), dE/dsigma_t, dE/da_t.
+ *   - The slab correction for a slab in a box with a vacuum gap along z
+ *     (nonmetal electrodes; section "Image charge effects on polyelectrolyte
+ *     adsorption", with the Yeh--Berkowitz reference it cites):
+ *     E = 2 pi lB M_z^2 / V, M_z = sum z_i z-coordinate_i.
+ *   - Harmonic bonds u = k/2 (r - b)^2 (the bond potential of that section).
  *   - Velocity-Verlet and BAOAB Langevin steps (the paper integrates the
  *     Langevin equation; the splitting is this oracle's reading), with
  *     Philox4x64-10 (Salmon et al., SC'11) Gaussian noise keyed by
@@ -771,19 +776,105 @@ int gco_forces(int N, const double* pos, const int* type, const int* z, const gc
     return 0;
 }
 
+/* Terms beyond the nonbonded force field, used by the slab systems of the
+ * section on polyelectrolyte adsorption at electrodes. */
+typedef struct {
+    int slab;            /* 1: add the slab correction (gco_slab) */
+    int nbonds;          /* harmonic bonds */
+    const int* bonds;    /* [nbonds][2] bead indices */
+    double bond_k, bond_b;
+} gco_extra;
+
+/* Slab correction for a slab that is periodic in x and y and separated from
+ * its periodic images along z by vacuum (the nonmetal-electrode systems,
+ * whose box is tripled along z for it; the correction of Yeh and Berkowitz,
+ * which the paper cites): the Ewald sum of such a box counts the
+ * interaction of every slab with the dipoles of the others, and the term
+ *   E = 2 pi lB M_z^2 / V,   M_z = sum_i z_i zeta_i
+ * (zeta_i the z coordinate in [0, Lz)) corrects the tin-foil sum of eq.
+ * ewald to the sum over a two-dimensionally periodic slab.  Forces
+ * F_iz = -dE/dzeta_i = -4 pi lB z_i M_z / V.  Virial (-dE/d strain, the
+ * convention of the reciprocal virial, for diagonal strains, under which
+ * M_z scales with the zz strain and V with the trace): diag(E, E, -E).
+ * Adds to F (AoS) and W (xx,yy,zz,xy,xz,yz); returns E. */
+double gco_slab(int N, const double* pos, const int* z, const double box[3], double lB, double* F,
+                double* W) {
+    const double V = box[0] * box[1] * box[2];
+    double Mz = 0.0;
+    for (int i = 0; i < N; ++i) Mz += z[i] * wrapd(pos[3 * i + 2], box[2]);
+    const double E = 2.0 * M_PI * lB * Mz * Mz / V;
+    for (int i = 0; i < N; ++i) F[3 * i + 2] += -4.0 * M_PI * lB * z[i] * Mz / V;
+    if (W) {
+        W[0] += E;
+        W[1] += E;
+        W[2] -= E;
+    }
+    return E;
+}
+
+/* Harmonic bonds, u = k/2 (r - b)^2 over the minimum-image separation of
+ * each listed pair (the polyanion backbone of the adsorption study, with
+ * k = 100 and b = 0.8).  Bonded pairs keep their nonbonded terms (the paper
+ * lists no exclusions).  Adds to F and W (sum over bonds of r_ij (x) f_ij);
+ * returns E. */
+double gco_bonds(int N, const double* pos, const double box[3], int nb, const int* bonds, double k,
+                 double b, double* F, double* W) {
+    (void)N;
+    double E = 0.0;
+    for (int m = 0; m < nb; ++m) {
+        const int i = bonds[2 * m], j = bonds[2 * m + 1];
+        double d[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = min_image(pos[3 * i + a] - pos[3 * j + a], box[a]);
+            r2 += d[a] * d[a];
+        }
+        const double r = sqrt(r2);
+        E += 0.5 * k * (r - b) * (r - b);
+        /* force on i: -k (r - b) d / r */
+        const double g = r > 0.0 ? -k * (r - b) / r : 0.0;
+        for (int a = 0; a < 3; ++a) {
+            F[3 * i + a] += g * d[a];
+            F[3 * j + a] -= g * d[a];
+        }
+        if (W) {
+            W[0] += d[0] * g * d[0];
+            W[1] += d[1] * g * d[1];
+            W[2] += d[2] * g * d[2];
+            W[3] += d[0] * g * d[1];
+            W[4] += d[0] * g * d[2];
+            W[5] += d[1] * g * d[2];
+        }
+    }
+    return E;
+}
+
+/* gco_forces plus the extra terms: E[7] = {ex, real, recip, corr, self,
+ * slab, bond}. */
+int gco_forces_ext(int N, const double* pos, const int* type, const int* z, const gco_params* p,
+                   const gco_recip* rec, const gco_extra* ex, double* F, double* E, double* W) {
+    int rc = gco_forces(N, pos, type, z, p, rec, F, E, W);
+    if (rc) return rc;
+    E[5] = E[6] = 0.0;
+    if (ex && ex->slab) E[5] = gco_slab(N, pos, z, p->box, p->lB, F, W);
+    if (ex && ex->nbonds > 0) E[6] = gco_bonds(N, pos, p->box, ex->nbonds, ex->bonds, ex->bond_k, ex->bond_b, F, W);
+    return 0;
+}
+
 /* n_steps of velocity Verlet (gamma == 0) or BAOAB Langevin (gamma > 0).
  * State: pos, vel AoS [N][3]; F must hold the forces at pos on entry and
  * holds the forces at the final positions on exit.  mass per type.  Step s
  * (0-based within this call) draws noise with step counter step0 + s.
- * Positions are wrapped into [0, L) after each drift.
+ * Positions are wrapped into [0, L) after each drift.  A type of infinite
+ * mass is held fixed (the electrode lattices of the slab systems): no kick,
+ * no noise, no kinetic energy; its beads must start at rest.  ex may be NULL.
  * Per-step potential + kinetic energies go to Elog[n_steps][2] if non-NULL. */
 int gco_md(int N, double* pos, double* vel, double* F, const int* type, const int* z,
-           const int* id, const gco_params* p, const gco_recip* rec, const double* mass,
-           double dt, double gamma, double kT, uint64_t seed, uint64_t replica,
+           const int* id, const gco_params* p, const gco_recip* rec, const gco_extra* ex,
+           const double* mass, double dt, double gamma, double kT, uint64_t seed, uint64_t replica,
            uint64_t step0, int n_steps, double* Elog) {
     double c1 = exp(-gamma * dt);
     double c2 = sqrt(1.0 - c1 * c1);
-    double E[5];
+    double E[7];
     for (int s = 0; s < n_steps; ++s) {
         for (int i = 0; i < N; ++i) {
             double m = mass[type[i]];
@@ -801,18 +892,19 @@ int gco_md(int N, double* pos, double* vel, double* F, const int* type, const in
             }
             for (int k = 0; k < 3; ++k) pos[3 * i + k] = wrapd(pos[3 * i + k], p->box[k]);
         }
-        int rc = gco_forces(N, pos, type, z, p, rec, F, E, NULL);
+        int rc = gco_forces_ext(N, pos, type, z, p, rec, ex, F, E, NULL);
         if (rc) return rc;
         double ke = 0;
         for (int i = 0; i < N; ++i) {
             double m = mass[type[i]];
+            if (isinf(m)) continue;
             for (int k = 0; k < 3; ++k) {
                 vel[3 * i + k] += 0.5 * dt * F[3 * i + k] / m;
                 ke += 0.5 * m * vel[3 * i + k] * vel[3 * i + k];
             }
         }
         if (Elog) {
-            Elog[2 * s] = E[0] + E[1] + E[2] + E[3] + E[4];
+            Elog[2 * s] = E[0] + E[1] + E[2] + E[3] + E[4] + E[5] + E[6];
             Elog[2 * s + 1] = ke;
         }
     }

@@ -48,6 +48,11 @@ class _Recip(C.Structure):
     _fields_ = [("mode", C.c_int), ("kmax", C.c_double), ("K", C.c_int * 3), ("order", C.c_int)]
 
 
+class _Extra(C.Structure):
+    _fields_ = [("slab", C.c_int), ("nbonds", C.c_int), ("bonds", C.POINTER(C.c_int)),
+                ("bond_k", C.c_double), ("bond_b", C.c_double)]
+
+
 RECIP_NONE, RECIP_EWALD, RECIP_SPME = 0, 1, 2
 
 _lib = None
@@ -82,9 +87,15 @@ def lib():
         L.gco_philox4x64_10.argtypes = [u64p, u64p, u64p]
         L.gco_gauss3.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, dp]
         L.gco_forces.argtypes = [C.c_int, dp, ip, ip, C.POINTER(_Params), C.POINTER(_Recip), dp, dp, dp]
-        L.gco_md.argtypes = [C.c_int, dp, dp, dp, ip, ip, ip, C.POINTER(_Params), C.POINTER(_Recip), dp,
-                             C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint64, C.c_uint64,
-                             C.c_int, dp]
+        L.gco_forces_ext.argtypes = [C.c_int, dp, ip, ip, C.POINTER(_Params), C.POINTER(_Recip),
+                                     C.POINTER(_Extra), dp, dp, dp]
+        L.gco_slab.restype = C.c_double
+        L.gco_slab.argtypes = [C.c_int, dp, ip, dp, C.c_double, dp, dp]
+        L.gco_bonds.restype = C.c_double
+        L.gco_bonds.argtypes = [C.c_int, dp, dp, C.c_int, ip, C.c_double, C.c_double, dp, dp]
+        L.gco_md.argtypes = [C.c_int, dp, dp, dp, ip, ip, ip, C.POINTER(_Params), C.POINTER(_Recip),
+                             C.POINTER(_Extra), dp, C.c_double, C.c_double, C.c_double, C.c_uint64,
+                             C.c_uint64, C.c_uint64, C.c_int, dp]
         L.gco_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -280,10 +291,67 @@ def forces(pos, type_, z, p: Params, recip_mode=RECIP_SPME, kmax=0.0, K=(0, 0, 0
     return dict(F=F, E=E, W=W)
 
 
+def slab(pos, z, box, lB):
+    """Slab correction of a slab with a vacuum gap along z (see gco_slab):
+    energy, forces [N, 3] and virial of that term alone."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    z = np.ascontiguousarray(z, dtype=np.int32)
+    F = np.zeros_like(pos)
+    W = np.zeros(6)
+    b = np.ascontiguousarray(box, dtype=np.float64)
+    E = lib().gco_slab(len(pos), _d(pos), _i(z), _d(b), float(lB), _d(F), _d(W))
+    return dict(E=E, F=F, W=W)
+
+
+def bonds(pos, box, pairs, k, b):
+    """Harmonic bonds k/2 (r - b)^2 over the minimum image (see gco_bonds):
+    energy, forces [N, 3] and virial of that term alone."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    F = np.zeros_like(pos)
+    W = np.zeros(6)
+    bx = np.ascontiguousarray(box, dtype=np.float64)
+    E = lib().gco_bonds(len(pos), _d(pos), _d(bx), len(pairs), _i(pairs), float(k), float(b), _d(F), _d(W))
+    return dict(E=E, F=F, W=W)
+
+
+class Extra:
+    """Terms beyond the nonbonded force field: the slab correction and
+    harmonic bonds (bead-index pairs)."""
+
+    def __init__(self, slab=False, pairs=None, bond_k=0.0, bond_b=0.0):
+        self.pairs = np.ascontiguousarray(pairs if pairs is not None else np.zeros((0, 2)),
+                                          dtype=np.int32).reshape(-1, 2)
+        self.c = _Extra()
+        self.c.slab = 1 if slab else 0
+        self.c.nbonds = len(self.pairs)
+        self.c.bonds = _i(self.pairs)
+        self.c.bond_k, self.c.bond_b = float(bond_k), float(bond_b)
+
+
+def forces_ext(pos, type_, z, p: Params, extra: Extra, recip_mode=RECIP_SPME, kmax=0.0, K=(0, 0, 0),
+               order=5):
+    """forces() plus the extra terms: E = [E_ex, E_real, E_recip, E_corr,
+    E_self, E_slab, E_bond]."""
+    pos, type_, z = _prep(pos, type_, z)
+    N = len(pos)
+    pc = p._c()
+    rec = _recip(recip_mode, kmax, K, order)
+    F = np.zeros((N, 3))
+    E = np.zeros(7)
+    W = np.zeros(6)
+    rc = lib().gco_forces_ext(N, _d(pos), _i(type_), _i(z), C.byref(pc), C.byref(rec), C.byref(extra.c),
+                              _d(F), _d(E), _d(W))
+    if rc != 0:
+        raise ValueError("oracle forces: rc must be <= L/2")
+    return dict(F=F, E=E, W=W)
+
+
 def md(pos, vel, type_, z, ids, p: Params, mass, dt, gamma, kT, seed, replica, step0, n_steps,
-       recip_mode=RECIP_SPME, kmax=0.0, K=(0, 0, 0), order=5):
+       recip_mode=RECIP_SPME, kmax=0.0, K=(0, 0, 0), order=5, extra: Extra | None = None):
     """n_steps of velocity Verlet (gamma == 0) or BAOAB Langevin; returns
-    (pos, vel, F, Elog[n_steps, 2] = (potential, kinetic))."""
+    (pos, vel, F, Elog[n_steps, 2] = (potential, kinetic)).  A type of
+    infinite mass stays fixed (its beads must start at rest)."""
     pos, type_, z = _prep(pos, type_, z)
     pos = pos.copy()
     vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3).copy()
@@ -292,11 +360,12 @@ def md(pos, vel, type_, z, ids, p: Params, mass, dt, gamma, kT, seed, replica, s
     N = len(pos)
     pc = p._c()
     rec = _recip(recip_mode, kmax, K, order)
-    F = forces(pos, type_, z, p, recip_mode, kmax, K, order)["F"].copy()
+    ex = extra if extra is not None else Extra()
+    F = forces_ext(pos, type_, z, p, ex, recip_mode, kmax, K, order)["F"].copy()
     Elog = np.zeros((n_steps, 2))
     rc = lib().gco_md(N, _d(pos), _d(vel), _d(F), _i(type_), _i(z), _i(ids), C.byref(pc), C.byref(rec),
-                      _d(mass), float(dt), float(gamma), float(kT), C.c_uint64(seed), C.c_uint64(replica),
-                      C.c_uint64(step0), int(n_steps), _d(Elog))
+                      C.byref(ex.c), _d(mass), float(dt), float(gamma), float(kT), C.c_uint64(seed),
+                      C.c_uint64(replica), C.c_uint64(step0), int(n_steps), _d(Elog))
     if rc != 0:
         raise ValueError("oracle md failed")
     return pos, vel, F, Elog
