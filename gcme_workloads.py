@@ -157,6 +157,75 @@ def config3():
                 box=(40.0, 40.0, 50.0))
 
 
+def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, beta=1.2, grid=(24, 24, 64),
+                order=5, gap_factor=3.0, lB=1.0, A=25.0, dt=0.02, gamma=1.0, kT=1.0, name=None):
+    """The nonmetal-electrode slab of the polyelectrolyte adsorption study,
+    at a chosen size.  Electrodes: two planes of fixed beads (type 1, half
+    the electrolyte radius, infinite mass, neutral) on a triangular lattice
+    of spacing 0.5 (nx sites per row, ny rows: Lx = 0.5 nx, Ly = 0.5 ny
+    sqrt(3)/2; the paper's 25 x 25.11 is nx = 50, ny = 58), at z = 0.5 and
+    z = h + 0.5.  Electrolyte (type 0, a = sigma = 0.5) at rho = 2.5 between
+    them: polyanion chains of chain_len monomers at -1 and as many +1
+    counterions (each an ion fraction x_p), the rest neutral solvent; chains
+    are random walks of step 0.8 kept inside the slab.  The box is
+    gap_factor h long in z (tripled for the slab correction).  Bonds k = 100,
+    b = 0.8 join consecutive monomers (extra["bonds"], concatenated indices)."""
+    rng = np.random.default_rng(seed)
+    sp = 0.5
+    Lx, Ly = sp * nx, sp * ny * math.sqrt(3.0) / 2.0
+    Lz = gap_factor * (h + 1.0)
+    box = (Lx, Ly, Lz)
+    # electrode lattices
+    ex, ey = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    ex = (ex + 0.5 * (ey % 2)) * sp
+    ey = ey * sp * math.sqrt(3.0) / 2.0
+    plane = np.c_[ex.ravel(), ey.ravel()]
+    elec = np.vstack([np.c_[plane, np.full(len(plane), 0.5)], np.c_[plane, np.full(len(plane), h + 0.5)]])
+    # electrolyte
+    zlo, zhi = 0.8, h + 0.2
+    n_e = int(round(DENSITY * Lx * Ly * h))
+    n_chain = max(1, int(round(x_p * n_e / chain_len)))
+    n_mono = n_chain * chain_len
+    n_ci = n_mono
+    n_sol = n_e - n_mono - n_ci
+    assert n_sol >= 0, "ion fraction too high for this slab"
+    mono = np.empty((n_mono, 3))
+    for c in range(n_chain):
+        x = np.array([rng.uniform(0, Lx), rng.uniform(0, Ly), rng.uniform(zlo, zhi)])
+        for m in range(chain_len):
+            if m:
+                d = rng.standard_normal(3)
+                x = x + 0.8 * d / np.linalg.norm(d)
+                if x[2] < zlo:
+                    x[2] = 2 * zlo - x[2]
+                if x[2] > zhi:
+                    x[2] = 2 * zhi - x[2]
+            mono[c * chain_len + m] = x
+    free = np.c_[rng.uniform(0, Lx, n_ci + n_sol), rng.uniform(0, Ly, n_ci + n_sol),
+                 rng.uniform(zlo, zhi, n_ci + n_sol)]
+    pos = np.vstack([mono, free, elec])
+    pos[:, 0] %= Lx
+    pos[:, 1] %= Ly
+    pos = lattice_positions(pos / np.asarray(box), box)
+    N = len(pos)
+    typ = np.zeros(N, dtype=np.int32)
+    typ[n_mono + n_ci + n_sol:] = 1
+    z = np.zeros(N, dtype=np.int32)
+    z[:n_mono] = -1
+    z[n_mono:n_mono + n_ci] = 1
+    mass = np.array([1.0, np.inf])
+    vel = np.zeros((N, 3))
+    mob = typ == 0
+    vel[mob] = _velocities(rng, int(mob.sum()), np.ones(int(mob.sum())), kT)
+    bonds = np.array([[c * chain_len + m, c * chain_len + m + 1] for c in range(n_chain) for m in range(chain_len - 1)],
+                     dtype=np.int32).reshape(-1, 2)
+    a = np.array([0.5, 0.25])
+    Am = np.full((2, 2), float(A))
+    return Workload(name or f"slab_N{N}", pos, typ, z, vel, box, rc, beta, lB, Am, a.copy(), a.copy(),
+                    tuple(grid), order, dt, gamma, kT, mass, seed,
+                    extra=dict(bonds=bonds, bond_k=100.0, bond_b=0.8, slab=True, fixed_type=1))
+
+
 def config4():
     """Large bulk: N = 2^21, three species a = 0.3/0.5/0.7, A ~ U(15, 35)
     symmetric (seeded), 15% charged, rc = 2.5, beta = 1.2, SPME 256^3."""

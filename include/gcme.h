@@ -68,9 +68,12 @@ enum {
     GCME_E_RECIP = 2,   /* U_elec,recip (mesh) */
     GCME_E_CORR = 3,    /* U_elec,corr (constant) */
     GCME_E_SELF = 4,    /* U_elec,self (Born, constant) */
-    GCME_E_POT = 5,     /* sum of the five terms above */
+    GCME_E_POT = 5,     /* sum of the potential terms: 0..4, GCME_E_SLAB and
+                           GCME_E_BOND */
     GCME_E_KIN = 6,     /* kinetic energy (gcme_step observations only, else 0) */
-    GCME_N_TERMS = 7
+    GCME_E_SLAB = 7,    /* slab correction (GCME_FLAG_SLAB_CORRECTION, else 0) */
+    GCME_E_BOND = 8,    /* harmonic bonds (gcme_set_bonds, else 0) */
+    GCME_N_TERMS = 9
 };
 
 #define GCME_MAX_TYPES 4
@@ -98,7 +101,11 @@ typedef struct {
     const double* A;          /* host [n_types * n_types], symmetric, kT d^3 */
     const double* sigma;      /* host [n_types] mass smearing radius (> 0) */
     const double* a;          /* host [n_types] charge smearing radius (> 0) */
-    const double* mass;       /* host [n_types] or NULL (all 1) */
+    const double* mass;       /* host [n_types] or NULL (all 1).  INFINITY holds
+                                 the type's beads fixed (no kick, no noise, zero
+                                 velocity, no kinetic energy): the electrode
+                                 lattices of the slab systems (section on
+                                 polyelectrolyte adsorption at electrodes) */
     double kT;                /* thermostat temperature */
     double dt;                /* time step */
     double gamma;             /* Langevin friction; 0 = velocity Verlet (NVE) */
@@ -109,6 +116,9 @@ typedef struct {
                                  0 < |k| <= kmax (no mesh; for small replicas,
                                  where the sum is cheap and has no mesh error);
                                  kmax L / (2 pi) <= 64 on every axis */
+    double bond_k;            /* harmonic bonds u = bond_k/2 (r - bond_b)^2 of the  */
+    double bond_b;            /* pairs given to gcme_set_bonds (polyanion chains of
+                                 the adsorption study: k = 100, b = 0.8); >= 0 */
 } gcme_params;
 
 /* Reject parameters that violate the paper's no-collapse condition
@@ -126,6 +136,17 @@ typedef struct {
  * kmax) fine enough for that beta.  dE/da is not provided for such a replica
  * (GCME_EUNSUPPORTED when requested), since beta then depends on a. */
 #define GCME_FLAG_ALL_RECIPROCAL 2u
+
+/* Slab correction for a slab that is periodic in x and y and separated from
+ * its periodic images along z by a vacuum gap (the nonmetal-electrode
+ * systems of the adsorption study, whose box is tripled along z; the
+ * correction of Yeh and Berkowitz that the paper cites): adds
+ * E = 2 pi lB M_z^2 / V, M_z = sum_i z_i zeta_i with zeta_i the z coordinate
+ * in [0, L2), and its forces F_iz = -4 pi lB z_i M_z / V, to the tin-foil
+ * sum of eq. ewald.  Virial diag(E, E, -E) (minus its derivative under
+ * diagonal strains).  The beads must stay inside the slab (walls of fixed
+ * beads, see gcme_params.mass): M_z uses the wrapped coordinate. */
+#define GCME_FLAG_SLAB_CORRECTION 4u
 
 typedef struct {
     const double* pos;   /* device [3][N_total] new positions, or NULL = keep state */
@@ -147,6 +168,16 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out);
  * mesh plans, B-spline moduli and pair tables, and (re)allocates mesh and
  * cell buffers.  Synchronous with respect to the context's stream. */
 gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p);
+
+/* Harmonic bonds (the chain connectivity of the adsorption study):
+ * pairs is host [n_bonds][2] of concatenated bead indices, both beads of a
+ * bond in the same replica, each bond u = bond_k/2 (r - bond_b)^2 with its
+ * replica's bond_k and bond_b, over the minimum-image separation.  Bonded
+ * beads keep their nonbonded terms.  Replaces the previous list
+ * (n_bonds = 0 removes every bond); the pairs are copied.  GCME_EINVAL on an
+ * index out of range, a bead bonded to itself or a bond across replicas.
+ * The bond forces enter every later evaluation and step. */
+gcme_status gcme_set_bonds(gcme_handle h, int64_t n_bonds, const int32_t* pairs);
 
 /* Load the dynamic state: positions (device [3][N] float64, any real
  * coordinates; wrapped into the box), velocities (device [3][N] float64 or

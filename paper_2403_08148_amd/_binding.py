@@ -12,16 +12,18 @@ LIB_PATH = os.path.join(_HERE, "libgcme.so")
 GCME_OK, GCME_EINVAL, GCME_EUNSUPPORTED, GCME_EGEOMETRY, GCME_ENONNEUTRAL, GCME_ESTATE, \
     GCME_EDEVICE, GCME_ENOMEM, GCME_EOVERFLOW = range(9)
 GCME_FP64, GCME_MIXED = 0, 1
-GCME_E_EX, GCME_E_REAL, GCME_E_RECIP, GCME_E_CORR, GCME_E_SELF, GCME_E_POT, GCME_E_KIN, GCME_N_TERMS = range(8)
+GCME_E_EX, GCME_E_REAL, GCME_E_RECIP, GCME_E_CORR, GCME_E_SELF, GCME_E_POT, GCME_E_KIN, GCME_E_SLAB, \
+    GCME_E_BOND, GCME_N_TERMS = range(10)
 GCME_MAX_TYPES = 4
 GCME_FLAG_STRICT_CONTACT = 1
 GCME_FLAG_ALL_RECIPROCAL = 2
+GCME_FLAG_SLAB_CORRECTION = 4
 
 STATUS_NAMES = {0: "GCME_OK", 1: "GCME_EINVAL", 2: "GCME_EUNSUPPORTED", 3: "GCME_EGEOMETRY",
                 4: "GCME_ENONNEUTRAL", 5: "GCME_ESTATE", 6: "GCME_EDEVICE", 7: "GCME_ENOMEM",
                 8: "GCME_EOVERFLOW"}
 
-EXPORTED = ["gcme_create", "gcme_set_params", "gcme_set_state", "gcme_get_state", "gcme_forces_energy",
+EXPORTED = ["gcme_create", "gcme_set_params", "gcme_set_bonds", "gcme_set_state", "gcme_get_state", "gcme_forces_energy",
             "gcme_step", "gcme_sync", "gcme_last_error", "gcme_get_tuning", "gcme_set_tuning",
             "gcme_autotune", "gcme_count_pairs", "gcme_profile_step", "gcme_stage_name", "gcme_destroy"]
 GCME_N_STAGES = 12
@@ -37,7 +39,7 @@ class gcme_params(C.Structure):
                 ("grid", C.c_int32 * 3), ("order", C.c_int32), ("lB", C.c_double), ("n_types", C.c_int32),
                 ("A", C.POINTER(C.c_double)), ("sigma", C.POINTER(C.c_double)), ("a", C.POINTER(C.c_double)),
                 ("mass", C.POINTER(C.c_double)), ("kT", C.c_double), ("dt", C.c_double), ("gamma", C.c_double),
-                ("flags", C.c_uint32), ("kmax", C.c_double)]
+                ("flags", C.c_uint32), ("kmax", C.c_double), ("bond_k", C.c_double), ("bond_b", C.c_double)]
 
 
 class gcme_io(C.Structure):
@@ -72,6 +74,7 @@ def load():
     H = C.c_void_p
     L.gcme_create.argtypes = [C.POINTER(gcme_create_info), C.POINTER(H)]
     L.gcme_set_params.argtypes = [H, C.c_int32, C.POINTER(gcme_params)]
+    L.gcme_set_bonds.argtypes = [H, C.c_int64, C.POINTER(C.c_int32)]
     L.gcme_set_state.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.gcme_get_state.argtypes = [H, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]
     L.gcme_forces_energy.argtypes = [H, C.POINTER(gcme_io)]

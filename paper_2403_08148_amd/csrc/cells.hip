@@ -274,6 +274,7 @@ __global__ void k_permute(StateView A, StateView B, uint4* __restrict__ bpk, Cel
   B.vel[2][n] = vz;
   B.param[n] = prm;
   B.id[n] = id;
+  if (c.slot_of && (unsigned)id < (unsigned)N) c.slot_of[id] = n;
   const uint4 rec = make_uint4(px, py, pz, prm);
   bpk[n] = rec;
   if (charged) {

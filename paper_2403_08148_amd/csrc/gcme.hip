@@ -18,6 +18,8 @@
 
 using namespace gcme;
 
+static_assert(GCME_N_TERMS == N_TERMS, "energy row width");
+
 namespace {
 
 struct DevBuf {
@@ -55,6 +57,7 @@ struct HostRep {
   double a[MAXT] = {};
   double mass[MAXT] = {1, 1, 1, 1};
   uint32_t flags = 0;
+  double bond_k = 0, bond_b = 0;  // harmonic bonds k/2 (r - b)^2
 };
 
 bool smooth(int k) {
@@ -133,6 +136,12 @@ struct gcme_ctx {
   DevBuf d_status, d_step, d_pairs;
   DevBuf d_ewk, d_ew_items_s, d_ew_items_f, ew_sp;  // exact reciprocal sums
   int nitems_ew_s = 0, nitems_ew_f = 0;
+  // slab correction and bonds
+  DevBuf d_slab_on, slab_mz, d_bond_kb, d_bonds, d_btiles, slot_of;
+  bool any_slab = false;
+  int ntiles_b = 0;
+  std::vector<std::vector<int2>> bonds;  // per replica, original bead indices
+  long long nbonds = 0;
   // plan sizes
   int ncells = 0;
   long long grid_total = 0, cgrid_total = 0;
@@ -223,6 +232,7 @@ CellView cview(gcme_handle h) {
   c.qstart = h->qstart.as<int>();
   c.bsum = h->bsum.as<int>();
   c.step = nullptr;
+  c.slot_of = h->nbonds > 0 ? h->slot_of.as<int>() : nullptr;
   c.ncells = h->ncells;
   return c;
 }
@@ -673,6 +683,40 @@ gcme_status build_plan(gcme_handle h) {
   HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->ntiles_g) * (MAXT * MAXT + 2 * MAXT) * 8));
   HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->ntiles_q) * (MAXT * MAXT + 2 * MAXT) * 8));
 
+  // slab correction (per 256-bead tile) and bonds (per 256-bond tile)
+  {
+    std::vector<int> on(R, 0);
+    std::vector<double> kb(2 * R, 0.0);
+    h->any_slab = false;
+    for (int r = 0; r < R; ++r) {
+      on[r] = (h->hp[r].flags & GCME_FLAG_SLAB_CORRECTION) && h->nq[r] > 0 ? 1 : 0;
+      h->any_slab |= on[r] != 0;
+      kb[r] = h->hp[r].bond_k;
+      kb[R + r] = h->hp[r].bond_b;
+    }
+    upload(on, h->d_slab_on, s);
+    upload(kb, h->d_bond_kb, s);
+    HIPCHK(h, h->slab_mz.alloc((size_t)std::max(1, h->ntiles_256) * 8));
+    HIPCHK(h, h->part[SLOT_SLAB].alloc((size_t)std::max(1, h->ntiles_256) * PART_W * 8));
+    upload(toff_256, h->d_off[SLOT_SLAB], s);
+    std::vector<int2> bl;
+    std::vector<int> bcnt(R), bfirst(R), toff_b;
+    for (int r = 0; r < R; ++r) {
+      bfirst[r] = (int)bl.size();
+      bcnt[r] = (int)h->bonds[r].size();
+      bl.insert(bl.end(), h->bonds[r].begin(), h->bonds[r].end());
+    }
+    std::vector<Tile> tb = make_tiles(bfirst, bcnt, 256, toff_b);
+    h->ntiles_b = (int)tb.size();
+    h->nbonds = (long long)bl.size();
+    if (bl.empty()) bl.push_back(int2{0, 0});
+    if (tb.empty()) tb.push_back(Tile{0, 0, 0, 0});
+    upload(bl, h->d_bonds, s);
+    upload(tb, h->d_btiles, s);
+    upload(toff_b, h->d_off[SLOT_BOND], s);
+    HIPCHK(h, h->part[SLOT_BOND].alloc((size_t)std::max(1, h->ntiles_b) * PART_W * 8));
+  }
+
   // cells
   int nbs = (h->ncells + 1023) / 1024;
   HIPCHK(h, h->counts.alloc((size_t)h->ncells * 4));
@@ -788,6 +832,38 @@ EwaldLaunch ewald_args(gcme_handle h) {
   return a;
 }
 
+SlabLaunch slab_args(gcme_handle h) {
+  SlabLaunch a{};
+  a.rep = h->d_rep.as<RepDesc>();
+  a.tiles = h->d_tiles_256.as<Tile>();
+  a.ntiles = h->any_slab ? h->ntiles_256 : 0;
+  a.tile_off = h->d_off[SLOT_SLAB].as<int>();
+  a.on = h->d_slab_on.as<int>();
+  a.mz = h->slab_mz.as<long long>();
+  for (int k = 0; k < 3; ++k) a.F[k] = Fk(h, k);
+  a.fscale = h->fscale();
+  a.status = h->d_status.as<unsigned>();
+  a.part = h->part[SLOT_SLAB].as<double>();
+  return a;
+}
+
+BondLaunch bond_args(gcme_handle h) {
+  BondLaunch a{};
+  a.rep = h->d_rep.as<RepDesc>();
+  a.tiles = h->d_btiles.as<Tile>();
+  a.ntiles = h->ntiles_b;
+  a.bonds = h->d_bonds.as<int2>();
+  a.slot_of = h->slot_of.as<int>();
+  a.nbeads = h->N;
+  a.k = h->d_bond_kb.as<double>();
+  a.b = a.k + h->R;
+  for (int k = 0; k < 3; ++k) a.F[k] = Fk(h, k);
+  a.fscale = h->fscale();
+  a.status = h->d_status.as<unsigned>();
+  a.part = h->part[SLOT_BOND].as<double>();
+  return a;
+}
+
 PmeLaunch pme_args(gcme_handle h) {
   PmeLaunch a{};
   a.rep = h->d_rep.as<RepDesc>();
@@ -872,6 +948,7 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   if (h->NQ == 0) {
     launch_nl_build(s, g);
     launch_pair_gcm(s, g, h->fp64, ev, adj);
+    launch_bonds(s, bond_args(h), viewB(h));
     return;
   }
   // Stream of each part by layout (gcme_tuning.stream_layout).  A
@@ -916,6 +993,9 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
     launch_z_gather(sp, p, h->fp64);
     // replicas with the exact reciprocal sum instead of a mesh
     launch_ewald(sp, ewald_args(h), h->fp64, ev);
+    // the slab systems' extra terms (none in bulk)
+    launch_slab(sp, slab_args(h), viewB(h));
+    launch_bonds(sp, bond_args(h), viewB(h));
   };
   for (int k = 0; k < 3; ++k) {
     if (L.order[k] == 'g') gcm();
@@ -950,6 +1030,8 @@ void enqueue_outputs(gcme_handle h, hipStream_t s, const gcme_io* io, bool kin) 
       f.part[SLOT_RECIP] = nullptr;
       f.part[SLOT_EWALD] = nullptr;
     }
+    if (!h->any_slab) f.part[SLOT_SLAB] = nullptr;
+    if (h->ntiles_b == 0) f.part[SLOT_BOND] = nullptr;
     f.consts = h->d_consts.as<double>();
     f.energy = io->energy;
     f.virial = io->virial;
@@ -1060,6 +1142,7 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
       h->lds_max = lds - 4096;  // less the kernels' static LDS
   }
   h->hp.assign(h->R, HostRep{});
+  h->bonds.assign(h->R, {});
   h->nq.assign(h->R, 0);
   h->qoff.assign(h->R, 0);
   if (info->stream) {
@@ -1094,6 +1177,7 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   ok &= h->b_id.alloc(N * 4) == hipSuccess;
   ok &= h->cell.alloc(N * 4) == hipSuccess;
   ok &= h->tmp.alloc(N * 4) == hipSuccess;
+  ok &= h->slot_of.alloc(N * 4) == hipSuccess;
   ok &= h->F.alloc(N * 24) == hipSuccess;
   ok &= h->d_status.alloc(64) == hipSuccess;
   ok &= h->d_step.alloc(64) == hipSuccess;
@@ -1105,6 +1189,7 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   (void)hipMemsetAsync(h->d_status.p, 0, 64, h->stream);
   (void)hipMemsetAsync(h->d_step.p, 0, 64, h->stream);
   (void)hipMemsetAsync(h->F.p, 0, N * 24, h->stream);
+  (void)hipMemsetAsync(h->slot_of.p, 0, N * 4, h->stream);
   (void)hipStreamSynchronize(h->stream);
   *out = h;
   return GCME_OK;
@@ -1148,6 +1233,10 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
     }
   }
   if (!(p->kT >= 0.0) || !(p->dt >= 0.0) || !(p->gamma >= 0.0)) return fail(h, GCME_EINVAL, "kT, dt, gamma must be >= 0");
+  if (!(p->bond_k >= 0.0) || !std::isfinite(p->bond_k) || !(p->bond_b >= 0.0) || !std::isfinite(p->bond_b))
+    return fail(h, GCME_EINVAL, "bond_k and bond_b must be finite and >= 0");
+  if (p->flags & ~(GCME_FLAG_STRICT_CONTACT | GCME_FLAG_ALL_RECIPROCAL | GCME_FLAG_SLAB_CORRECTION))
+    return fail(h, GCME_EINVAL, "unknown flag");
   double beta = p->beta;
   if (p->flags & GCME_FLAG_ALL_RECIPROCAL) {
     // beta = alpha_ij = sqrt(pi/2)/a_ij with a_ij = sqrt(2) a: one radius for all
@@ -1187,6 +1276,8 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
     q.order = p->order;
     q.nt = nt;
     q.flags = p->flags;
+    q.bond_k = p->bond_k;
+    q.bond_b = p->bond_b;
     for (int i = 0; i < nt * nt; ++i) q.A[i] = p->A[i];
     for (int t = 0; t < nt; ++t) {
       q.sigma[t] = p->sigma[t];
@@ -1206,6 +1297,26 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
           return fail(h, GCME_EINVAL, "state has bead types beyond n_types; set the state again");
         }
   }
+  return GCME_OK;
+}
+
+gcme_status gcme_set_bonds(gcme_handle h, int64_t n_bonds, const int32_t* pairs) {
+  if (!h) return GCME_EINVAL;
+  if (n_bonds < 0 || (n_bonds > 0 && !pairs)) return fail(h, GCME_EINVAL, "n_bonds must be >= 0, pairs non-null");
+  if (n_bonds > (int64_t)1 << 30) return fail(h, GCME_EUNSUPPORTED, "at most 2^30 bonds");
+  std::vector<std::vector<int2>> by(h->R);
+  for (int64_t m = 0; m < n_bonds; ++m) {
+    const int i = pairs[2 * m], j = pairs[2 * m + 1];
+    if (i < 0 || j < 0 || i >= h->N || j >= h->N || i == j)
+      return fail(h, GCME_EINVAL, "bond indices must be distinct beads in 0..N-1");
+    // the replica of bead i (replicas are consecutive index ranges)
+    const int r = (int)(std::upper_bound(h->boff.begin(), h->boff.begin() + h->R, i) - h->boff.begin()) - 1;
+    if (j < h->boff[r] || j >= h->boff[r] + h->nb[r]) return fail(h, GCME_EINVAL, "a bond joins two replicas");
+    by[r].push_back(int2{i, j});
+  }
+  h->bonds.swap(by);
+  h->plan_dirty = true;
+  h->forces_valid = false;
   return GCME_OK;
 }
 

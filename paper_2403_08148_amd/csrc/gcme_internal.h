@@ -113,8 +113,20 @@ struct Tile {
 constexpr int BEAD_THREADS = 256;
 
 // Slots of the per-block partial sums (7 doubles: energy, virial[6]).
-enum { SLOT_GCM = 0, SLOT_REAL = 1, SLOT_RECIP = 2, SLOT_KIN = 3, SLOT_EWALD = 4, N_SLOTS = 5 };
+enum {
+  SLOT_GCM = 0,
+  SLOT_REAL = 1,
+  SLOT_RECIP = 2,
+  SLOT_KIN = 3,
+  SLOT_EWALD = 4,
+  SLOT_SLAB = 5,
+  SLOT_BOND = 6,
+  N_SLOTS = 7
+};
 constexpr int PART_W = 8;
+// Width of a replica's energy row: ex, real, recip, corr, self, potential,
+// kinetic, slab, bond.
+constexpr int N_TERMS = 9;
 
 // Device status bits.
 enum { STATUS_FORCE_OVERFLOW = 1, STATUS_MESH_OVERFLOW = 2, STATUS_LIST_OVERFLOW = 4 };
@@ -146,6 +158,8 @@ struct CellView {
   int* bsum;         // scan block sums [2 * nblocks]
   unsigned long long* step;  // with a step's sort: the step counter, which the
                              // scan advances by one (one thread); else null
+  int* slot_of;      // [N] sorted index of each original bead index, written
+                     // by the permute; null when nothing reads it (no bonds)
   int ncells;
 };
 
@@ -194,6 +208,36 @@ struct ChargedView {
   uint4* pk;         // charged beads in cell order
   int* idx;          // sorted bead index of each charged bead
 };
+
+// extra.hip: the slab correction and harmonic bonds, both added to F.
+struct SlabLaunch {
+  const RepDesc* rep;
+  const Tile* tiles;        // 256-bead tiles of every replica
+  int ntiles;
+  const int* tile_off;      // [R+1] each replica's tiles
+  const int* on;            // [R] correction switched on
+  long long* mz;            // [ntiles] z_i u_iz summed per tile (exact)
+  long long* F[3];
+  double fscale;
+  unsigned int* status;
+  double* part;             // SLOT_SLAB partials [ntiles][PART_W]
+};
+struct BondLaunch {
+  const RepDesc* rep;
+  const Tile* tiles;        // 256-bond tiles (first = first bond)
+  int ntiles;
+  const int2* bonds;        // original bead indices, grouped by replica
+  const int* slot_of;       // [N] sorted index of each original bead index
+  int nbeads;               // N
+  const double* k;          // [R] force constant
+  const double* b;          // [R] rest length
+  long long* F[3];
+  double fscale;
+  unsigned int* status;
+  double* part;             // SLOT_BOND partials [ntiles][PART_W]
+};
+void launch_slab(hipStream_t s, const SlabLaunch& a, StateView B);
+void launch_bonds(hipStream_t s, const BondLaunch& a, StateView B);
 
 // ---------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).

@@ -52,13 +52,14 @@ __device__ inline uint32_t drift(uint32_t u, double dx, double L) {
 
 // First half of a step for one bead, from velocity v, position u and force
 // f (already in force units): kick, then drift (velocity Verlet) or drift,
-// Ornstein-Uhlenbeck noise, drift (BAOAB), with the noise of `step`.
+// Ornstein-Uhlenbeck noise, drift (BAOAB), with the noise of `step`.  A type
+// of infinite mass (inverse mass 0, no noise amplitude) is held at rest.
 __device__ inline void first_half(const IntLaunch& a, const RepDesc& R, int r, int t, unsigned long long step,
                                   int id, const double f[3], double v[3], uint32_t u[3]) {
   const double im = a.inv_mass[r * MAXT + t];
   const double dt = a.dt[r];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) v[k] = v[k] + 0.5 * dt * f[k] * im;
+  for (int k = 0; k < 3; ++k) v[k] = im == 0.0 ? 0.0 : v[k] + 0.5 * dt * f[k] * im;
   if (a.langevin[r]) {
     double g[3];
     gauss3(a.seed, step, (unsigned long long)id, (unsigned long long)r, g);
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(256) void k_int_last(IntLaunch a, StateView B, Stat
       double v = B.vel[k][n] + 0.5 * dt * (double)Fk[k][n] * a.fscale_inv * im;
       A.vel[k][n] = v;
       A.pos[k][n] = B.pos[k][n];
-      ke += 0.5 * v * v / im;
+      ke += im == 0.0 ? 0.0 : 0.5 * v * v / im;
     }
     A.param[n] = prm;
     A.id[n] = B.id[n];
@@ -257,19 +258,22 @@ __global__ __launch_bounds__(256) void k_finalize(FinalLaunch a) {
   if (threadIdx.x == 0) {
     const double ec = a.consts[2 * r], es = a.consts[2 * r + 1];
     if (a.energy) {
-      double* E = a.energy + (size_t)r * 7;
+      double* E = a.energy + (size_t)r * N_TERMS;
       E[0] = res[SLOT_GCM][0];
       E[1] = res[SLOT_REAL][0];
       E[2] = res[SLOT_RECIP][0] + res[SLOT_EWALD][0];  // a replica has one of the two
       E[3] = ec;
       E[4] = es;
-      E[5] = ((E[0] + E[1]) + (E[2] + E[3])) + E[4];
+      E[7] = res[SLOT_SLAB][0];
+      E[8] = res[SLOT_BOND][0];
+      E[5] = (((E[0] + E[1]) + (E[2] + E[3])) + E[4]) + (E[7] + E[8]);
       E[6] = a.have_kin ? res[SLOT_KIN][0] : 0.0;
     }
     if (a.virial) {
       for (int k = 0; k < 6; ++k)
         a.virial[(size_t)r * 6 + k] =
-            (res[SLOT_GCM][1 + k] + res[SLOT_REAL][1 + k]) + (res[SLOT_RECIP][1 + k] + res[SLOT_EWALD][1 + k]);
+            ((res[SLOT_GCM][1 + k] + res[SLOT_REAL][1 + k]) + (res[SLOT_RECIP][1 + k] + res[SLOT_EWALD][1 + k])) +
+            (res[SLOT_SLAB][1 + k] + res[SLOT_BOND][1 + k]);
     }
   }
   if (a.dE_dA || a.dE_dsigma || a.dE_da) {

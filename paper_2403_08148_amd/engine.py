@@ -29,6 +29,8 @@ class ReplicaParams:
     gamma: float = 1.0
     flags: int = 0
     kmax: float = 0.0  # > 0: exact reciprocal sum over |k| <= kmax instead of the mesh
+    bond_k: float = 0.0  # harmonic bonds bond_k/2 (r - bond_b)^2 (set_bonds)
+    bond_b: float = 0.0
 
 
 def _ptr(t):
@@ -93,10 +95,16 @@ class GCMe:
                            (C.c_int32 * 3)(*[int(k) for k in p.grid]), int(p.order), float(p.lB), nt,
                            A.ctypes.data_as(dp), s.ctypes.data_as(dp), a.ctypes.data_as(dp),
                            m.ctypes.data_as(dp) if m is not None else None, float(p.kT), float(p.dt),
-                           float(p.gamma), int(p.flags), float(p.kmax))
+                           float(p.gamma), int(p.flags), float(p.kmax), float(p.bond_k), float(p.bond_b))
         B.check(self.h, self.lib.gcme_set_params(self.h, int(replica), C.byref(cp)))
         for r in (range(self.R) if replica < 0 else [replica]):
             self.params[r] = p
+
+    def set_bonds(self, pairs):
+        """Harmonic bonds between concatenated bead indices ([n, 2], both
+        beads of a bond in one replica); replaces the previous list."""
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        B.check(self.h, self.lib.gcme_set_bonds(self.h, len(pr), pr.ctypes.data_as(C.POINTER(C.c_int32))))
 
     def _soa(self, x):
         t = self.torch.as_tensor(x, dtype=self.torch.float64, device=self.device)

@@ -1,0 +1,187 @@
+"""GPU parity of the slab systems' terms (section on polyelectrolyte
+adsorption at electrodes): the slab correction, harmonic bonds and fixed
+electrode beads, against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import gcme_workloads as W
+from oracle import oracle as O
+from tests.gpu_common import energy_errors, gpu_eval, oracle_params, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-9, 1e-10), "mixed": (1e-5, 1e-6)}
+
+
+def _engine(ws, precision, seed=1, slab=True, bonds=True, tuning=None):
+    from paper_2403_08148_amd import GCMe, params_from_workload
+    from paper_2403_08148_amd import _binding as B
+    eng = GCMe([w.N for w in ws], precision=precision, seed=seed)
+    off, pairs = 0, []
+    for r, w in enumerate(ws):
+        ex = w.extra
+        over = dict(flags=B.GCME_FLAG_SLAB_CORRECTION if slab and ex.get("slab") else 0,
+                    bond_k=ex.get("bond_k", 0.0), bond_b=ex.get("bond_b", 0.0))
+        eng.set_params(params_from_workload(w, **over), replica=r)
+        if bonds and "bonds" in ex:
+            pairs.append(ex["bonds"] + off)
+        off += w.N
+    if tuning:
+        eng.set_tuning(**tuning)
+    if pairs:
+        eng.set_bonds(np.concatenate(pairs))
+    eng.set_state(np.concatenate([w.pos for w in ws]), np.concatenate([w.type for w in ws]),
+                  np.concatenate([w.z for w in ws]), np.concatenate([w.vel for w in ws]))
+    return eng
+
+
+def _extra(w, slab=True, bonds=True):
+    ex = w.extra
+    return O.Extra(slab=slab and ex.get("slab", False), pairs=ex.get("bonds") if bonds else None,
+                   bond_k=ex.get("bond_k", 0.0), bond_b=ex.get("bond_b", 0.0))
+
+
+def _oracle(w, pos=None, slab=True, bonds=True):
+    return O.forces_ext(w.pos if pos is None else pos, w.type, w.z, oracle_params(w), _extra(w, slab, bonds),
+                        recip_mode=O.RECIP_SPME, K=w.grid, order=w.order)
+
+
+def _compare(E, F, Wv, ref, precision, tag):
+    ftol, et = TOL[precision]
+    ferr = rel_rms(F, ref["F"])
+    eerr = energy_errors(E[:5], ref["E"][:5])
+    es = abs(E[7] - ref["E"][5]) / max(abs(ref["E"][5]), 1e-300)
+    eb = abs(E[8] - ref["E"][6]) / max(abs(ref["E"][6]), 1e-300)
+    werr = rel_rms(Wv, ref["W"])
+    print(f"  {tag}: force {ferr:.2e} energies {eerr.max():.2e} slab {es:.2e} bond {eb:.2e} virial {werr:.2e}",
+          flush=True)
+    assert ferr < ftol
+    assert np.all(eerr < et), eerr
+    # both terms are summed in float64 from the fixed-point positions in
+    # either precision
+    assert es < 1e-12 and eb < 1e-12
+    assert werr < max(ftol, et) * 10
+    assert E[5] == pytest.approx(E[:5].sum() + E[7] + E[8], rel=1e-14)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_slab_system_parity(precision):
+    w = W.slab_system()
+    print(f"case slab_system N={w.N} prec={precision}", flush=True)
+    eng = _engine([w], precision)
+    got = gpu_eval(eng)
+    eng.close()
+    _compare(got["energy"][0], got["force"], got["virial"][0], _oracle(w), precision, "slab+bonds")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_slab_and_bond_forces_alone(precision):
+    """The two terms' forces isolated: the difference of evaluations with and
+    without them (forces are summed exactly in fixed point, so the rest
+    cancels) against the oracle's terms alone, which the GCM forces would
+    otherwise mask."""
+    w = W.slab_system(seed=22)
+    print(f"case slab_terms_alone N={w.N} prec={precision}", flush=True)
+    outs = []
+    for on in (True, False):
+        eng = _engine([w], precision, slab=on, bonds=on)
+        outs.append(gpu_eval(eng)["force"])
+        eng.close()
+    d = outs[0] - outs[1]
+    ref = O.slab(w.pos, w.z, w.box, w.lB)["F"] + O.bonds(w.pos, w.box, w.extra["bonds"], 100.0, 0.8)["F"]
+    err = rel_rms(d, ref)
+    print(f"  slab + bond forces alone: {err:.2e}", flush=True)
+    assert err < (1e-11 if precision == "fp64" else 1e-6)
+
+
+def test_bonds_follow_the_sort():
+    """After steps (each re-sorting the beads) the bond forces still join the
+    right beads: a fresh evaluation against the oracle at the engine's
+    positions."""
+    w = W.slab_system(seed=23)
+    print(f"case bonds_after_steps N={w.N}", flush=True)
+    eng = _engine([w], "fp64")
+    eng.step(7)
+    eng.sync()
+    pos, _, _ = eng.get_state()
+    pos = pos.cpu().numpy().T.copy()
+    got = gpu_eval(eng)
+    eng.close()
+    _compare(got["energy"][0], got["force"], got["virial"][0], _oracle(w, pos=pos), "fp64", "after 7 steps")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fixed_electrodes_do_not_move(precision):
+    w = W.slab_system(seed=24)
+    print(f"case fixed_electrodes N={w.N} prec={precision}", flush=True)
+    eng = _engine([w], precision)
+    p0, _, _ = eng.get_state()
+    o = eng.step(20, observe=True)
+    eng.sync()
+    p1, v1, _ = eng.get_state()
+    E = o["energy"][0].cpu().numpy()
+    eng.close()
+    p0, p1, v1 = p0.cpu().numpy().T, p1.cpu().numpy().T, v1.cpu().numpy().T
+    fixed = w.type == 1
+    np.testing.assert_array_equal(p1[fixed], p0[fixed])
+    assert np.all(v1[fixed] == 0.0)
+    assert np.abs(p1[~fixed] - p0[~fixed]).max() > 1e-3
+    assert np.isfinite(E).all()
+    # the kinetic energy is that of the mobile beads
+    assert E[6] == pytest.approx(0.5 * (v1[~fixed] ** 2).sum(), rel=1e-12)
+
+
+def test_slab_trajectory_short():
+    """Ten BAOAB steps with the slab correction, bonds and fixed electrodes
+    against the oracle's steps with the same noise."""
+    w = W.slab_system(seed=25)
+    print(f"case slab_trajectory N={w.N}", flush=True)
+    eng = _engine([w], "fp64", seed=99)
+    eng.step(10)
+    eng.sync()
+    pos, vel, _ = eng.get_state()
+    eng.close()
+    opos, ovel, _, _ = O.md(w.pos, w.vel, w.type, w.z, np.arange(w.N, dtype=np.int32), oracle_params(w), w.mass,
+                            w.dt, w.gamma, w.kT, 99, 0, 0, 10, recip_mode=O.RECIP_SPME, K=w.grid, order=w.order,
+                            extra=_extra(w))
+    dv = rel_rms(vel.cpu().numpy().T, ovel)
+    print(f"  10 steps velocity rel diff {dv:.2e}", flush=True)
+    assert dv < 1e-7
+    fixed = w.type == 1
+    np.testing.assert_array_equal(opos[fixed], w.pos[fixed])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_slab_and_bulk(precision):
+    """A slab replica beside a bulk one (no slab correction, no bonds): each
+    against its own oracle."""
+    ws = [W.small_bulk(N=700, seed=26, charged_frac=0.3, box=(6.5, 6.5, 6.6), rc=2.5, grid=(24, 24, 24)),
+          W.slab_system(seed=27)]
+    print(f"case batched_slab_bulk prec={precision}", flush=True)
+    eng = _engine(ws, precision)
+    got = gpu_eval(eng)
+    eng.close()
+    off = 0
+    for r, w in enumerate(ws):
+        sl = slice(off, off + w.N)
+        _compare(got["energy"][r], got["force"][sl], got["virial"][r], _oracle(w), precision, f"replica {r}")
+        off += w.N
+    assert got["energy"][0, 7] == 0.0 and got["energy"][0, 8] == 0.0
+
+
+def test_set_bonds_errors_and_clear():
+    from paper_2403_08148_amd._binding import GCMeError
+    ws = [W.small_bulk(N=300, seed=28, charged_frac=0.2, box=(5.0, 5.0, 5.0), rc=2.0, grid=(16, 16, 16)),
+          W.slab_system(seed=29)]
+    print("case set_bonds_errors", flush=True)
+    eng = _engine(ws, "fp64")
+    for bad in ([[0, 300]], [[5, 5]], [[0, ws[0].N + ws[1].N]], [[-1, 2]]):
+        with pytest.raises(GCMeError, match="EINVAL"):
+            eng.set_bonds(bad)
+    e1 = gpu_eval(eng)["energy"]
+    assert e1[1, 8] > 0.0
+    eng.set_bonds(np.zeros((0, 2), dtype=np.int32))
+    e0 = gpu_eval(eng)["energy"]
+    eng.close()
+    assert e0[1, 8] == 0.0
+    assert e0[1, 5] == pytest.approx(e1[1, 5] - e1[1, 8], rel=1e-12)
