@@ -25,6 +25,10 @@
  *     adsorption", with the Yeh--Berkowitz reference it cites):
  *     E = 2 pi lB M_z^2 / V, M_z = sum z_i z-coordinate_i.
  *   - Harmonic bonds u = k/2 (r - b)^2 (the bond potential of that section).
+ *   - The method of image charges for perfectly conducting electrodes
+ *     (section "Method of image charges"): the real system in 0 < z < Lz,
+ *     its mirror image in -Lz < z < 0 with opposite charges, one periodic
+ *     box of length 2 Lz; images follow their sources after every drift.
  *   - Velocity-Verlet and BAOAB Langevin steps (the paper integrates the
  *     Langevin equation; the splitting is this oracle's reading), with
  *     Philox4x64-10 (Salmon et al., SC'11) Gaussian noise keyed by
@@ -783,7 +787,25 @@ typedef struct {
     int nbonds;          /* harmonic bonds */
     const int* bonds;    /* [nbonds][2] bead indices */
     double bond_k, bond_b;
+    int nimages;         /* image charges */
+    const int* images;   /* [nimages][2] (image bead, source bead) */
 } gco_extra;
+
+/* Method of image charges (metal electrodes at z = 0 and z = Lz of the real
+ * system, box length 2 Lz along z): each image bead sits at the source's
+ * reflection across z = 0, (x, y, -z), wrapped into the box; its charge is
+ * the source's with the opposite sign and it has no excluded volume (the
+ * caller gives it such a type).  Both electrodes are mirror planes, since
+ * the reflection across z = 0 followed by the period 2 Lz is the reflection
+ * across z = Lz. */
+void gco_mirror_images(double* pos, const double box[3], int nimg, const int* images) {
+    for (int m = 0; m < nimg; ++m) {
+        const int i = images[2 * m], s = images[2 * m + 1];
+        pos[3 * i + 0] = pos[3 * s + 0];
+        pos[3 * i + 1] = pos[3 * s + 1];
+        pos[3 * i + 2] = wrapd(-pos[3 * s + 2], box[2]);
+    }
+}
 
 /* Slab correction for a slab that is periodic in x and y and separated from
  * its periodic images along z by vacuum (the nonmetal-electrode systems,
@@ -866,7 +888,9 @@ int gco_forces_ext(int N, const double* pos, const int* type, const int* z, cons
  * (0-based within this call) draws noise with step counter step0 + s.
  * Positions are wrapped into [0, L) after each drift.  A type of infinite
  * mass is held fixed (the electrode lattices of the slab systems): no kick,
- * no noise, no kinetic energy; its beads must start at rest.  ex may be NULL.
+ * no noise, no kinetic energy; its beads must start at rest.  Image beads
+ * (ex->images, of such a type) are moved to their sources' reflections after
+ * every drift.  ex may be NULL.
  * Per-step potential + kinetic energies go to Elog[n_steps][2] if non-NULL. */
 int gco_md(int N, double* pos, double* vel, double* F, const int* type, const int* z,
            const int* id, const gco_params* p, const gco_recip* rec, const gco_extra* ex,
@@ -892,6 +916,7 @@ int gco_md(int N, double* pos, double* vel, double* F, const int* type, const in
             }
             for (int k = 0; k < 3; ++k) pos[3 * i + k] = wrapd(pos[3 * i + k], p->box[k]);
         }
+        if (ex && ex->nimages > 0) gco_mirror_images(pos, p->box, ex->nimages, ex->images);
         int rc = gco_forces_ext(N, pos, type, z, p, rec, ex, F, E, NULL);
         if (rc) return rc;
         double ke = 0;

@@ -50,7 +50,8 @@ class _Recip(C.Structure):
 
 class _Extra(C.Structure):
     _fields_ = [("slab", C.c_int), ("nbonds", C.c_int), ("bonds", C.POINTER(C.c_int)),
-                ("bond_k", C.c_double), ("bond_b", C.c_double)]
+                ("bond_k", C.c_double), ("bond_b", C.c_double), ("nimages", C.c_int),
+                ("images", C.POINTER(C.c_int))]
 
 
 RECIP_NONE, RECIP_EWALD, RECIP_SPME = 0, 1, 2
@@ -91,6 +92,7 @@ def lib():
                                      C.POINTER(_Extra), dp, dp, dp]
         L.gco_slab.restype = C.c_double
         L.gco_slab.argtypes = [C.c_int, dp, ip, dp, C.c_double, dp, dp]
+        L.gco_mirror_images.argtypes = [dp, dp, C.c_int, ip]
         L.gco_bonds.restype = C.c_double
         L.gco_bonds.argtypes = [C.c_int, dp, dp, C.c_int, ip, C.c_double, C.c_double, dp, dp]
         L.gco_md.argtypes = [C.c_int, dp, dp, dp, ip, ip, ip, C.POINTER(_Params), C.POINTER(_Recip),
@@ -315,18 +317,32 @@ def bonds(pos, box, pairs, k, b):
     return dict(E=E, F=F, W=W)
 
 
-class Extra:
-    """Terms beyond the nonbonded force field: the slab correction and
-    harmonic bonds (bead-index pairs)."""
+def mirror_images(pos, box, images):
+    """Image beads moved to their sources' reflections across z = 0 (see
+    gco_mirror_images); images is [n, 2] of (image, source)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3).copy()
+    images = np.ascontiguousarray(images, dtype=np.int32).reshape(-1, 2)
+    bx = np.ascontiguousarray(box, dtype=np.float64)
+    lib().gco_mirror_images(_d(pos), _d(bx), len(images), _i(images))
+    return pos
 
-    def __init__(self, slab=False, pairs=None, bond_k=0.0, bond_b=0.0):
+
+class Extra:
+    """Terms beyond the nonbonded force field: the slab correction, harmonic
+    bonds (bead-index pairs) and image charges ((image, source) pairs)."""
+
+    def __init__(self, slab=False, pairs=None, bond_k=0.0, bond_b=0.0, images=None):
         self.pairs = np.ascontiguousarray(pairs if pairs is not None else np.zeros((0, 2)),
                                           dtype=np.int32).reshape(-1, 2)
+        self.images = np.ascontiguousarray(images if images is not None else np.zeros((0, 2)),
+                                           dtype=np.int32).reshape(-1, 2)
         self.c = _Extra()
         self.c.slab = 1 if slab else 0
         self.c.nbonds = len(self.pairs)
         self.c.bonds = _i(self.pairs)
         self.c.bond_k, self.c.bond_b = float(bond_k), float(bond_b)
+        self.c.nimages = len(self.images)
+        self.c.images = _i(self.images)
 
 
 def forces_ext(pos, type_, z, p: Params, extra: Extra, recip_mode=RECIP_SPME, kmax=0.0, K=(0, 0, 0),

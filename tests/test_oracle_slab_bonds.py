@@ -14,6 +14,9 @@ polyelectrolyte adsorption at electrodes.
   virial = -dE/d strain.
 - Fixed types: beads of infinite mass keep their positions bit for bit over
   Langevin steps while feeling forces; the kinetic energy stays finite.
+- Image charges (metal electrodes): a charge near the conducting plane feels
+  its image's pull -lB/(2d)^2, approached as the periodic box grows; images
+  stay the exact reflections of their sources through MD steps.
 """
 import numpy as np
 import pytest
@@ -166,3 +169,47 @@ def test_infinite_mass_type_stays_fixed():
     assert np.all(np.isfinite(Elog))
     # the kinetic energy is that of the mobile beads only
     assert Elog[-1, 1] == pytest.approx(0.5 * (v1[t == 0] ** 2).sum(), rel=1e-12)
+
+
+def test_image_charge_attracts_to_the_electrode():
+    """Method of image charges: a charge at height d over a perfectly
+    conducting plane is pulled toward it by its image, F = -lB q^2/(2d)^2
+    (the smeared charges act as points at 2d >= 1.5 to 1e-3); the periodic
+    copies' share falls as the box grows."""
+    ratios = {}
+    for L in (16.0, 32.0):
+        for d in (1.0, 1.5):
+            pos = np.array([[L / 2, L / 2, d], [0.0, 0.0, 0.0]])
+            pos = O.mirror_images(pos, (L, L, L), [[1, 0]])
+            assert pos[1, 2] == L - d and pos[1, 0] == pos[0, 0] and pos[1, 1] == pos[0, 1]
+            p = O.Params(box=(L, L, L), rc=4.0, beta=1.0, lB=1.0, A=np.zeros((2, 2)), sigma=np.array([0.5, 0.5]),
+                         a=np.array([0.5, 0.5]))
+            F = O.forces(pos, np.array([0, 1]), np.array([1, -1]), p, recip_mode=O.RECIP_EWALD, kmax=9.5)["F"]
+            assert abs(F[0, 0]) < 1e-12 and abs(F[0, 1]) < 1e-12
+            ratios[(L, d)] = F[0, 2] / (-1.0 / (2 * d) ** 2)
+    assert abs(ratios[(32.0, 1.0)] - 1.0) < 2e-3
+    assert abs(ratios[(32.0, 1.5)] - 1.0) < 6e-3
+    for d in (1.0, 1.5):
+        assert abs(ratios[(32.0, d)] - 1.0) < abs(ratios[(16.0, d)] - 1.0)
+
+
+def test_images_follow_their_sources_in_md():
+    rng = np.random.default_rng(12)
+    L, H = 6.0, 5.0
+    n = 60
+    pos = np.c_[rng.uniform(0, L, n), rng.uniform(0, L, n), rng.uniform(0.5, H - 0.5, n)]
+    z = np.array([1, -1] * (n // 2), dtype=np.int32)
+    # images of every charged bead, type 1 (no excluded volume, infinite mass)
+    img = np.c_[np.arange(n, 2 * n), np.arange(n)]
+    pos = O.mirror_images(np.vstack([pos, np.zeros((n, 3))]), (L, L, 2 * H), img)
+    t = np.r_[np.zeros(n), np.ones(n)].astype(np.int32)
+    zz = np.r_[z, -z].astype(np.int32)
+    A = np.array([[25.0, 0.0], [0.0, 0.0]])
+    p = O.Params(box=(L, L, 2 * H), rc=2.5, beta=1.2, lB=1.0, A=A, sigma=np.array([0.5, 0.5]), a=np.array([0.5, 0.5]))
+    vel = np.r_[rng.normal(size=(n, 3)), np.zeros((n, 3))]
+    ex = O.Extra(images=img)
+    p1, v1, F1, _ = O.md(pos, vel, t, zz, np.arange(2 * n), p, np.array([1.0, np.inf]), 0.02, 1.0, 1.0, 3, 0, 0, 5,
+                         recip_mode=O.RECIP_EWALD, kmax=6.0, extra=ex)
+    np.testing.assert_array_equal(p1[n:], O.mirror_images(p1, (L, L, 2 * H), img)[n:])
+    assert np.abs(p1[:n] - pos[:n]).max() > 1e-3
+    assert np.all(v1[n:] == 0.0)
