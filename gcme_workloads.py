@@ -158,7 +158,7 @@ def config3():
 
 
 def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, beta=1.2, grid=(24, 24, 64),
-                order=5, gap_factor=3.0, lB=1.0, A=25.0, dt=0.02, gamma=1.0, kT=1.0, name=None):
+                order=5, gap_factor=3.0, lB=1.0, A=25.0, dt=0.02, gamma=1.0, kT=1.0, name=None, metal=False):
     """The nonmetal-electrode slab of the polyelectrolyte adsorption study,
     at a chosen size.  Electrodes: two planes of fixed beads (type 1, half
     the electrolyte radius, infinite mass, neutral) on a triangular lattice
@@ -169,20 +169,29 @@ def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, bet
     counterions (each an ion fraction x_p), the rest neutral solvent; chains
     are random walks of step 0.8 kept inside the slab.  The box is
     gap_factor h long in z (tripled for the slab correction).  Bonds k = 100,
-    b = 0.8 join consecutive monomers (extra["bonds"], concatenated indices)."""
+    b = 0.8 join consecutive monomers (extra["bonds"], concatenated indices).
+
+    metal=True: the perfectly conducting electrodes of the same study,
+    by the method of image charges: electrode planes at z = 0 and z = H =
+    h + 1, the electrolyte between them, the box 2 H long in z, and after
+    the real beads one image bead per charged bead (type 2: infinite mass,
+    no excluded volume, the opposite charge) at the reflection (x, y, -z)
+    on the fixed-point lattice (extra["images"]: (image, source) pairs)."""
     rng = np.random.default_rng(seed)
     sp = 0.5
     Lx, Ly = sp * nx, sp * ny * math.sqrt(3.0) / 2.0
-    Lz = gap_factor * (h + 1.0)
+    H = h + 1.0
+    Lz = 2.0 * H if metal else gap_factor * H
     box = (Lx, Ly, Lz)
+    z_el = (0.0, H) if metal else (0.5, h + 0.5)
     # electrode lattices
     ex, ey = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
     ex = (ex + 0.5 * (ey % 2)) * sp
     ey = ey * sp * math.sqrt(3.0) / 2.0
     plane = np.c_[ex.ravel(), ey.ravel()]
-    elec = np.vstack([np.c_[plane, np.full(len(plane), 0.5)], np.c_[plane, np.full(len(plane), h + 0.5)]])
+    elec = np.vstack([np.c_[plane, np.full(len(plane), z_el[0])], np.c_[plane, np.full(len(plane), z_el[1])]])
     # electrolyte
-    zlo, zhi = 0.8, h + 0.2
+    zlo, zhi = z_el[0] + 0.3, z_el[1] - 0.3
     n_e = int(round(DENSITY * Lx * Ly * h))
     n_chain = max(1, int(round(x_p * n_e / chain_len)))
     n_mono = n_chain * chain_len
@@ -214,16 +223,33 @@ def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, bet
     z[:n_mono] = -1
     z[n_mono:n_mono + n_ci] = 1
     mass = np.array([1.0, np.inf])
+    a = np.array([0.5, 0.25])
+    Am = np.full((2, 2), float(A))
+    images = np.zeros((0, 2), dtype=np.int32)
+    if metal:
+        src = np.nonzero(z)[0]
+        u = np.round(pos[src] / np.asarray(box) * 4294967296.0)
+        u[:, 2] = np.mod(4294967296.0 - u[:, 2], 4294967296.0)
+        ipos = u / 4294967296.0 * np.asarray(box)
+        images = np.c_[np.arange(N, N + len(src)), src].astype(np.int32)
+        pos = np.vstack([pos, ipos])
+        typ = np.r_[typ, np.full(len(src), 2)].astype(np.int32)
+        z = np.r_[z, -z[src]].astype(np.int32)
+        N = len(pos)
+        mass = np.array([1.0, np.inf, np.inf])
+        a = np.array([0.5, 0.25, 0.5])
+        Am = np.zeros((3, 3))
+        Am[:2, :2] = float(A)
     vel = np.zeros((N, 3))
     mob = typ == 0
     vel[mob] = _velocities(rng, int(mob.sum()), np.ones(int(mob.sum())), kT)
     bonds = np.array([[c * chain_len + m, c * chain_len + m + 1] for c in range(n_chain) for m in range(chain_len - 1)],
                      dtype=np.int32).reshape(-1, 2)
-    a = np.array([0.5, 0.25])
-    Am = np.full((2, 2), float(A))
-    return Workload(name or f"slab_N{N}", pos, typ, z, vel, box, rc, beta, lB, Am, a.copy(), a.copy(),
+    kind = "metal" if metal else "slab"
+    return Workload(name or f"{kind}_N{N}", pos, typ, z, vel, box, rc, beta, lB, Am, a.copy(), a.copy(),
                     tuple(grid), order, dt, gamma, kT, mass, seed,
-                    extra=dict(bonds=bonds, bond_k=100.0, bond_b=0.8, slab=True, fixed_type=1))
+                    extra=dict(bonds=bonds, bond_k=100.0, bond_b=0.8, slab=not metal, fixed_type=1,
+                               images=images))
 
 
 def config4():

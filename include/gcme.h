@@ -179,6 +179,25 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
  * The bond forces enter every later evaluation and step. */
 gcme_status gcme_set_bonds(gcme_handle h, int64_t n_bonds, const int32_t* pairs);
 
+/* Method of image charges for perfectly conducting electrodes (section
+ * "Method of image charges"): the real system lies in 0 < z < L2/2 between
+ * electrodes at z = 0 and z = L2/2, and each charged bead has an image bead,
+ * its reflection (x, y, -z) across z = 0 with the opposite charge, in the
+ * other half of the box (the reflection across z = 0 with the period L2 is
+ * also the reflection across z = L2/2).  pairs is host [n_images][2] of
+ * (image, source) concatenated bead indices in one replica; a bead is an
+ * image at most once and never both an image and a source.  Image beads
+ * must be of a type with infinite mass (gcme_params.mass) and, to carry no
+ * excluded volume, zero A; their charge must be the opposite of their
+ * source's (both checked at the next evaluation, GCME_EINVAL).  After every
+ * binning (each evaluation and step) the images are moved to their sources'
+ * reflections, exactly on the fixed-point lattice, so the forces on the real
+ * beads include the images' field; the images' own forces are not used.
+ * Energies and virial are those of the whole doubled box: the real system's
+ * electrostatic energy is half of U_elec of the doubled box.  Replaces the
+ * previous list (n_images = 0 removes them). */
+gcme_status gcme_set_images(gcme_handle h, int64_t n_images, const int32_t* pairs);
+
 /* Load the dynamic state: positions (device [3][N] float64, any real
  * coordinates; wrapped into the box), velocities (device [3][N] float64 or
  * NULL = zero), types (device int32 [N], 0..n_types-1) and charge numbers

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "GCME_OK", 1: "GCME_EINVAL", 2: "GCME_EUNSUPPORTED", 3: "GCME
                 4: "GCME_ENONNEUTRAL", 5: "GCME_ESTATE", 6: "GCME_EDEVICE", 7: "GCME_ENOMEM",
                 8: "GCME_EOVERFLOW"}
 
-EXPORTED = ["gcme_create", "gcme_set_params", "gcme_set_bonds", "gcme_set_state", "gcme_get_state", "gcme_forces_energy",
+EXPORTED = ["gcme_create", "gcme_set_params", "gcme_set_bonds", "gcme_set_images", "gcme_set_state", "gcme_get_state", "gcme_forces_energy",
             "gcme_step", "gcme_sync", "gcme_last_error", "gcme_get_tuning", "gcme_set_tuning",
             "gcme_autotune", "gcme_count_pairs", "gcme_profile_step", "gcme_stage_name", "gcme_destroy"]
 GCME_N_STAGES = 12
@@ -75,6 +75,7 @@ def load():
     L.gcme_create.argtypes = [C.POINTER(gcme_create_info), C.POINTER(H)]
     L.gcme_set_params.argtypes = [H, C.c_int32, C.POINTER(gcme_params)]
     L.gcme_set_bonds.argtypes = [H, C.c_int64, C.POINTER(C.c_int32)]
+    L.gcme_set_images.argtypes = [H, C.c_int64, C.POINTER(C.c_int32)]
     L.gcme_set_state.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.gcme_get_state.argtypes = [H, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]
     L.gcme_forces_energy.argtypes = [H, C.POINTER(gcme_io)]

@@ -46,7 +46,8 @@ __global__ void k_bin(StateView A, const RepDesc* __restrict__ rep, CellView c, 
   const int si = active ? s : 0;
   const uint32_t p = A.param[si];
   const RepDesc& R = rep[param_rep(p)];
-  bin_bead(c, R, A.pos[0][si], A.pos[1][si], A.pos[2][si], p, s, active);
+  const int id = c.slot_a ? A.id[si] : 0;
+  bin_bead(c, R, A.pos[0][si], A.pos[1][si], A.pos[2][si], p, s, id, active);
 }
 
 constexpr int SCAN_THREADS = 256;

@@ -142,7 +142,43 @@ __global__ __launch_bounds__(EX_THREADS) void k_bond(BondLaunch a, StateView B) 
   }
 }
 
+// Method of image charges (metal electrodes at z = 0 and z = Lz of the real
+// system, box 2 Lz long): the reflection (x, y, -z) of the source is, in
+// fractional fixed point, (ux, uy, 2^32 - uz) exactly.  Sources are never
+// images, so the reads and writes of one launch do not overlap.
+__global__ __launch_bounds__(EX_THREADS) void k_images(ImageLaunch a, StateView A, CellView c) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.n) return;
+  const int2 pr = a.pairs[m];
+  const int si = c.slot_a[pr.x], ss = c.slot_a[pr.y];
+  if ((unsigned)si >= (unsigned)a.nbeads || (unsigned)ss >= (unsigned)a.nbeads) {
+    atomicOr(a.status, (unsigned)STATUS_LIST_OVERFLOW);
+    return;
+  }
+  const uint32_t ux = A.pos[0][ss], uy = A.pos[1][ss], uz = 0u - A.pos[2][ss];
+  A.pos[0][si] = ux;
+  A.pos[1][si] = uy;
+  A.pos[2][si] = uz;
+  const uint32_t prm = A.param[si];
+  const int cid = cell_of(a.rep[param_rep(prm)], ux, uy, uz);
+  const int old = c.cell[si];
+  if (cid != old) {
+    c.cell[si] = cid;
+    atomicAdd(&c.counts[old], -1);
+    atomicAdd(&c.counts[cid], 1);
+    if (param_z(prm) != 0) {
+      atomicAdd(&c.qcounts[old], -1);
+      atomicAdd(&c.qcounts[cid], 1);
+    }
+  }
+}
+
 }  // namespace
+
+void launch_images(hipStream_t s, const ImageLaunch& a, StateView A, CellView c) {
+  if (a.n <= 0) return;
+  hipLaunchKernelGGL(k_images, dim3((a.n + EX_THREADS - 1) / EX_THREADS), dim3(EX_THREADS), 0, s, a, A, c);
+}
 
 void launch_slab(hipStream_t s, const SlabLaunch& a, StateView B) {
   if (a.ntiles <= 0) return;

@@ -142,6 +142,11 @@ struct gcme_ctx {
   int ntiles_b = 0;
   std::vector<std::vector<int2>> bonds;  // per replica, original bead indices
   long long nbonds = 0;
+  // image charges: (image, source) pairs; checked against types and charges
+  std::vector<int2> images;
+  DevBuf d_images, slot_a;
+  int nimages = 0;
+  bool images_checked = true;
   // plan sizes
   int ncells = 0;
   long long grid_total = 0, cgrid_total = 0;
@@ -233,6 +238,7 @@ CellView cview(gcme_handle h) {
   c.bsum = h->bsum.as<int>();
   c.step = nullptr;
   c.slot_of = h->nbonds > 0 ? h->slot_of.as<int>() : nullptr;
+  c.slot_a = h->nimages > 0 ? h->slot_a.as<int>() : nullptr;
   c.ncells = h->ncells;
   return c;
 }
@@ -715,6 +721,10 @@ gcme_status build_plan(gcme_handle h) {
     upload(tb, h->d_btiles, s);
     upload(toff_b, h->d_off[SLOT_BOND], s);
     HIPCHK(h, h->part[SLOT_BOND].alloc((size_t)std::max(1, h->ntiles_b) * PART_W * 8));
+    std::vector<int2> im = h->images;
+    h->nimages = (int)im.size();
+    if (im.empty()) im.push_back(int2{0, 0});
+    upload(im, h->d_images, s);
   }
 
   // cells
@@ -933,6 +943,15 @@ void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
   // its scan advances the step counter
   if (!bin) c.step = h->d_step.as<unsigned long long>();
   if (bin) launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
+  if (h->nimages > 0) {
+    ImageLaunch im{};
+    im.rep = h->d_rep.as<RepDesc>();
+    im.pairs = h->d_images.as<int2>();
+    im.n = h->nimages;
+    im.nbeads = h->N;
+    im.status = h->d_status.as<unsigned>();
+    launch_images(s, im, viewA(h), c);
+  }
   launch_scan(s, c);
   launch_scatter(s, c, h->N);
   launch_permute(s, viewA(h), viewB(h), h->b_pk.as<uint4>(), c, qview(h), h->N);
@@ -1054,6 +1073,17 @@ gcme_status check_ready(gcme_handle h) {
   for (int r = 0; r < h->R; ++r)
     if (!h->hp[r].set) return fail(h, GCME_ESTATE, "parameters not set for replica " + std::to_string(r));
   if (!h->have_state) return fail(h, GCME_ESTATE, "state not set (gcme_set_state)");
+  if (!h->images_checked) {
+    // an image bead: immobile type, the opposite charge of its source
+    for (const int2& pr : h->images) {
+      const int r = (int)(std::upper_bound(h->boff.begin(), h->boff.begin() + h->R, pr.x) - h->boff.begin()) - 1;
+      if (!std::isinf(h->hp[r].mass[h->h_type[pr.x]]))
+        return fail(h, GCME_EINVAL, "an image bead's type must have infinite mass");
+      if (h->h_z[pr.x] != -h->h_z[pr.y])
+        return fail(h, GCME_EINVAL, "an image bead's charge must be the opposite of its source's");
+    }
+    h->images_checked = true;
+  }
   if (h->plan_dirty) return build_plan(h);
   return GCME_OK;
 }
@@ -1178,6 +1208,7 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   ok &= h->cell.alloc(N * 4) == hipSuccess;
   ok &= h->tmp.alloc(N * 4) == hipSuccess;
   ok &= h->slot_of.alloc(N * 4) == hipSuccess;
+  ok &= h->slot_a.alloc(N * 4) == hipSuccess;
   ok &= h->F.alloc(N * 24) == hipSuccess;
   ok &= h->d_status.alloc(64) == hipSuccess;
   ok &= h->d_step.alloc(64) == hipSuccess;
@@ -1190,6 +1221,7 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   (void)hipMemsetAsync(h->d_step.p, 0, 64, h->stream);
   (void)hipMemsetAsync(h->F.p, 0, N * 24, h->stream);
   (void)hipMemsetAsync(h->slot_of.p, 0, N * 4, h->stream);
+  (void)hipMemsetAsync(h->slot_a.p, 0, N * 4, h->stream);
   (void)hipStreamSynchronize(h->stream);
   *out = h;
   return GCME_OK;
@@ -1288,6 +1320,7 @@ gcme_status gcme_set_params(gcme_handle h, int32_t replica, const gcme_params* p
   }
   h->plan_dirty = true;
   h->forces_valid = false;
+  h->images_checked = h->images.empty();
   if (h->have_state) {
     // types must stay within the new type count
     for (int r = r0; r < r1; ++r)
@@ -1315,6 +1348,31 @@ gcme_status gcme_set_bonds(gcme_handle h, int64_t n_bonds, const int32_t* pairs)
     by[r].push_back(int2{i, j});
   }
   h->bonds.swap(by);
+  h->plan_dirty = true;
+  h->forces_valid = false;
+  return GCME_OK;
+}
+
+gcme_status gcme_set_images(gcme_handle h, int64_t n_images, const int32_t* pairs) {
+  if (!h) return GCME_EINVAL;
+  if (n_images < 0 || (n_images > 0 && !pairs)) return fail(h, GCME_EINVAL, "n_images must be >= 0, pairs non-null");
+  if (n_images > h->N) return fail(h, GCME_EINVAL, "more images than beads");
+  std::vector<char> role(h->N, 0);  // 1 image, 2 source
+  std::vector<int2> im;
+  im.reserve((size_t)n_images);
+  for (int64_t m = 0; m < n_images; ++m) {
+    const int i = pairs[2 * m], j = pairs[2 * m + 1];
+    if (i < 0 || j < 0 || i >= h->N || j >= h->N || i == j)
+      return fail(h, GCME_EINVAL, "image and source must be distinct beads in 0..N-1");
+    const int r = (int)(std::upper_bound(h->boff.begin(), h->boff.begin() + h->R, i) - h->boff.begin()) - 1;
+    if (j < h->boff[r] || j >= h->boff[r] + h->nb[r]) return fail(h, GCME_EINVAL, "an image in another replica");
+    if (role[i] != 0 || role[j] == 1) return fail(h, GCME_EINVAL, "a bead is an image twice, or an image and a source");
+    role[i] = 1;
+    role[j] = 2;
+    im.push_back(int2{i, j});
+  }
+  h->images.swap(im);
+  h->images_checked = false;
   h->plan_dirty = true;
   h->forces_valid = false;
   return GCME_OK;
@@ -1371,6 +1429,7 @@ gcme_status gcme_set_state(gcme_handle h, const double* pos, const double* vel, 
   // the state is new: rebuild the plan (charged ranges, constants)
   h->plan_dirty = true;
   h->have_state = true;
+  h->images_checked = h->images.empty();
   gcme_status st = build_plan(h);
   if (st != GCME_OK) return st;
   launch_ingest(h->stream, pos, N, N, h->d_rep.as<RepDesc>(), nullptr, viewA(h), h->F.as<long long>(), N);

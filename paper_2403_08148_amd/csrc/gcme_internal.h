@@ -160,6 +160,8 @@ struct CellView {
                              // scan advances by one (one thread); else null
   int* slot_of;      // [N] sorted index of each original bead index, written
                      // by the permute; null when nothing reads it (no bonds)
+  int* slot_a;       // [N] index in the unsorted array of each original bead
+                     // index, written by the binning; null without images
   int ncells;
 };
 
@@ -196,9 +198,10 @@ __device__ inline int run_atomic_add(int* counts, int key, bool active) {
 // Record bead s's cell and count it (and, if charged, among the charged).
 // Every lane of the wavefront must call it (inactive lanes: active false).
 __device__ inline void bin_bead(const CellView& c, const RepDesc& R, uint32_t ux, uint32_t uy, uint32_t uz,
-                                uint32_t prm, int s, bool active) {
+                                uint32_t prm, int s, int id, bool active) {
   const int cid = active ? cell_of(R, ux, uy, uz) : 0;
   if (active) c.cell[s] = cid;
+  if (active && c.slot_a) c.slot_a[id] = s;
   (void)run_atomic_add(c.counts, cid, active);
   (void)run_atomic_add(c.qcounts, cid, active && param_z(prm) != 0);
 }
@@ -236,7 +239,18 @@ struct BondLaunch {
   unsigned int* status;
   double* part;             // SLOT_BOND partials [ntiles][PART_W]
 };
+// Image charges: pairs (image bead, source bead) of original indices.
+struct ImageLaunch {
+  const RepDesc* rep;
+  const int2* pairs;
+  int n;
+  int nbeads;
+  unsigned int* status;
+};
 void launch_slab(hipStream_t s, const SlabLaunch& a, StateView B);
+// After a binning of A: every image bead to its source's reflection across
+// z = 0, with its cell and the cell counts corrected.
+void launch_images(hipStream_t s, const ImageLaunch& a, StateView A, CellView c);
 void launch_bonds(hipStream_t s, const BondLaunch& a, StateView B);
 
 // ---------------------------------------------------------------------------

@@ -96,7 +96,8 @@ __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* 
     v[k] = A.vel[k][s];
     u[k] = A.pos[k][s];
   }
-  first_half(a, R, r, t, *a.step, A.id[s], f, v, u);
+  const int id = A.id[s];
+  first_half(a, R, r, t, *a.step, id, f, v, u);
   if (active) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -104,7 +105,7 @@ __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* 
       A.vel[k][s] = v[k];
     }
   }
-  if (BIN) bin_bead(c, R, u[0], u[1], u[2], prm, s, active);
+  if (BIN) bin_bead(c, R, u[0], u[1], u[2], prm, s, id, active);
 }
 
 // The second half kick of the step just completed (as k_int_last, on the
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(BEAD_THREADS) void k_int_between(IntLaunch a, State
     A.id[s] = id;
     cid = cell_of(R, u[0], u[1], u[2]);
     c.cell[s] = cid;
+    if (c.slot_a) c.slot_a[id] = s;
   }
   // the binning's counts, one atomic per run of equal cells in the wavefront
   (void)run_atomic_add(c.counts, cid, active);

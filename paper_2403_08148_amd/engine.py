@@ -106,6 +106,12 @@ class GCMe:
         pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
         B.check(self.h, self.lib.gcme_set_bonds(self.h, len(pr), pr.ctypes.data_as(C.POINTER(C.c_int32))))
 
+    def set_images(self, pairs):
+        """Image charges: [n, 2] (image bead, source bead) concatenated
+        indices; replaces the previous list."""
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        B.check(self.h, self.lib.gcme_set_images(self.h, len(pr), pr.ctypes.data_as(C.POINTER(C.c_int32))))
+
     def _soa(self, x):
         t = self.torch.as_tensor(x, dtype=self.torch.float64, device=self.device)
         if t.dim() == 2 and t.shape[0] == self.N and t.shape[1] == 3 and self.N != 3:

@@ -1,6 +1,7 @@
 """GPU parity of the slab systems' terms (section on polyelectrolyte
-adsorption at electrodes): the slab correction, harmonic bonds and fixed
-electrode beads, against the FP64 oracle on the same seeded inputs."""
+adsorption at electrodes): the slab correction, harmonic bonds, fixed
+electrode beads and image charges (metal electrodes), against the FP64
+oracle on the same seeded inputs."""
 import numpy as np
 import pytest
 
@@ -17,7 +18,7 @@ def _engine(ws, precision, seed=1, slab=True, bonds=True, tuning=None):
     from paper_2403_08148_amd import GCMe, params_from_workload
     from paper_2403_08148_amd import _binding as B
     eng = GCMe([w.N for w in ws], precision=precision, seed=seed)
-    off, pairs = 0, []
+    off, pairs, images = 0, [], []
     for r, w in enumerate(ws):
         ex = w.extra
         over = dict(flags=B.GCME_FLAG_SLAB_CORRECTION if slab and ex.get("slab") else 0,
@@ -25,11 +26,15 @@ def _engine(ws, precision, seed=1, slab=True, bonds=True, tuning=None):
         eng.set_params(params_from_workload(w, **over), replica=r)
         if bonds and "bonds" in ex:
             pairs.append(ex["bonds"] + off)
+        if len(ex.get("images", ())):
+            images.append(ex["images"] + off)
         off += w.N
     if tuning:
         eng.set_tuning(**tuning)
     if pairs:
         eng.set_bonds(np.concatenate(pairs))
+    if images:
+        eng.set_images(np.concatenate(images))
     eng.set_state(np.concatenate([w.pos for w in ws]), np.concatenate([w.type for w in ws]),
                   np.concatenate([w.z for w in ws]), np.concatenate([w.vel for w in ws]))
     return eng
@@ -38,7 +43,7 @@ def _engine(ws, precision, seed=1, slab=True, bonds=True, tuning=None):
 def _extra(w, slab=True, bonds=True):
     ex = w.extra
     return O.Extra(slab=slab and ex.get("slab", False), pairs=ex.get("bonds") if bonds else None,
-                   bond_k=ex.get("bond_k", 0.0), bond_b=ex.get("bond_b", 0.0))
+                   bond_k=ex.get("bond_k", 0.0), bond_b=ex.get("bond_b", 0.0), images=ex.get("images"))
 
 
 def _oracle(w, pos=None, slab=True, bonds=True):
@@ -185,3 +190,72 @@ def test_set_bonds_errors_and_clear():
     eng.close()
     assert e0[1, 8] == 0.0
     assert e0[1, 5] == pytest.approx(e1[1, 5] - e1[1, 8], rel=1e-12)
+
+
+def _metal(seed):
+    return W.slab_system(seed=seed, metal=True, grid=(24, 24, 48))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_metal_electrodes_parity(precision):
+    w = _metal(31)
+    print(f"case metal_electrodes N={w.N} images={len(w.extra['images'])} prec={precision}", flush=True)
+    eng = _engine([w], precision)
+    got = gpu_eval(eng)
+    eng.close()
+    _compare(got["energy"][0], got["force"], got["virial"][0], _oracle(w), precision, "metal")
+    assert got["energy"][0, 7] == 0.0
+
+
+def test_metal_electrodes_steps():
+    """Ten BAOAB steps: the images follow their sources (the engine moves
+    them after every binning), the trajectory matches the oracle's, and a
+    fresh evaluation at the new positions matches the oracle there."""
+    w = _metal(32)
+    print(f"case metal_steps N={w.N}", flush=True)
+    eng = _engine([w], "fp64", seed=99)
+    eng.step(10)
+    eng.sync()
+    pos, vel, _ = eng.get_state()
+    pos = pos.cpu().numpy().T.copy()
+    got = gpu_eval(eng)
+    eng.close()
+    img = w.extra["images"]
+    L = w.box[2]
+    np.testing.assert_allclose(pos[img[:, 0], :2], pos[img[:, 1], :2], rtol=0, atol=0)
+    np.testing.assert_allclose(np.mod(pos[img[:, 0], 2] + pos[img[:, 1], 2], L), 0.0, rtol=0, atol=1e-12 * L)
+    assert np.abs(pos[img[:, 0]] - w.pos[img[:, 0]]).max() > 1e-3
+    opos, ovel, _, _ = O.md(w.pos, w.vel, w.type, w.z, np.arange(w.N, dtype=np.int32), oracle_params(w), w.mass,
+                            w.dt, w.gamma, w.kT, 99, 0, 0, 10, recip_mode=O.RECIP_SPME, K=w.grid, order=w.order,
+                            extra=_extra(w))
+    dv = rel_rms(vel.cpu().numpy().T, ovel)
+    print(f"  10 steps velocity rel diff {dv:.2e}", flush=True)
+    assert dv < 1e-7
+    _compare(got["energy"][0], got["force"], got["virial"][0], _oracle(w, pos=pos), "fp64", "metal after 10 steps")
+
+
+def test_set_images_errors():
+    from paper_2403_08148_amd._binding import GCMeError
+    w = _metal(33)
+    img = w.extra["images"]
+    print("case set_images_errors", flush=True)
+    eng = _engine([w], "fp64")
+    for bad in ([[img[0, 0], img[0, 1]], [img[0, 0], img[1, 1]]],  # an image twice
+                [[img[0, 0], img[0, 1]], [img[0, 1], img[1, 1]]],  # a source that is an image
+                [[3, 3]], [[0, w.N]]):
+        with pytest.raises(GCMeError, match="EINVAL"):
+            eng.set_images(bad)
+    # a mobile bead as an image, and an image of the wrong charge
+    mobile = int(np.nonzero((w.type == 0) & (w.z == 0))[0][0])
+    eng.set_images([[mobile, int(img[0, 1])]])
+    with pytest.raises(GCMeError, match="EINVAL"):
+        eng.forces_energy()
+    # image of charge +1 (of a -1 monomer) given a +1 counterion as source
+    plus = int(np.nonzero((w.type == 0) & (w.z == 1))[0][0])
+    assert w.z[img[0, 0]] == 1
+    eng.set_images([[int(img[0, 0]), plus]])
+    with pytest.raises(GCMeError, match="EINVAL"):
+        eng.forces_energy()
+    eng.set_images(img)
+    gpu_eval(eng)
+    eng.close()
