@@ -257,10 +257,26 @@ def engine_for(ws, precision, tune=True, kmax=0.0):
     """An engine over the workloads (kmax > 0: the exact reciprocal sum over
     |k| <= kmax in place of the mesh)."""
     from paper_2403_08148_amd import GCMe, params_from_workload
+    from paper_2403_08148_amd import _binding as B
     import numpy as np
     eng = GCMe([x.N for x in ws], precision=precision, seed=12345)
+    off, bonds, images = 0, [], []
     for r, x in enumerate(ws):
-        eng.set_params(params_from_workload(x, kmax=kmax), replica=r)
+        ex = x.extra
+        over = dict(kmax=kmax)
+        if ex.get("slab"):
+            over["flags"] = B.GCME_FLAG_SLAB_CORRECTION
+        if "bonds" in ex:
+            over.update(bond_k=ex["bond_k"], bond_b=ex["bond_b"])
+            bonds.append(ex["bonds"] + off)
+        if len(ex.get("images", ())):
+            images.append(ex["images"] + off)
+        eng.set_params(params_from_workload(x, **over), replica=r)
+        off += x.N
+    if bonds:
+        eng.set_bonds(np.concatenate(bonds))
+    if images:
+        eng.set_images(np.concatenate(images))
     eng.set_state(np.concatenate([x.pos for x in ws]), np.concatenate([x.type for x in ws]),
                   np.concatenate([x.z for x in ws]), np.concatenate([x.vel for x in ws]))
     tuning = eng.autotune() if tune else eng.tuning()
@@ -273,7 +289,8 @@ def extra_workloads(w):
     replica called in sequence, the 200,000-bead system with the
     polyelectrolyte workload's composition and mesh (periodic), and the
     1,536-bead plain-method system with the exact reciprocal sum against its
-    mesh form."""
+    mesh form, and the adsorption study's slab systems (nonmetal and metal
+    electrodes) at its size."""
     import numpy as np
     import gcme_workloads as W
     out = {}
@@ -362,6 +379,24 @@ def extra_workloads(w):
     res["spme_force_rel_rms_vs_exact_fp64"] = float(np.linalg.norm(fr[("fp64", "spme_32")] - fx) / np.linalg.norm(fx))
     res["kmax"] = w1.kmax
     out[w1.name] = res
+
+    # 6. the adsorption study's slab systems at its size: nonmetal electrodes
+    #    (slab correction, box tripled) and metal electrodes (image charges,
+    #    box doubled), both with bonded chains and fixed electrode lattices
+    for metal in (False, True):
+        ws6 = W.paper_slab(metal=metal)
+        res = {"n_beads": ws6.N, "n_mobile": int((ws6.type == 0).sum()), "box": list(ws6.box),
+               "grid": list(ws6.grid), "bonds": int(len(ws6.extra["bonds"])),
+               "images": int(len(ws6.extra["images"]))}
+        for prec in ("mixed", "fp64"):
+            eng, tun = engine_for([ws6], prec)
+            ms = time_steps(eng, 50, 5)
+            pairs = eng.count_pairs()
+            res[prec] = {"ms_per_step": ms, "pair_interactions_per_s": pairs * 1000.0 / ms,
+                         "ns_per_day": 1000.0 / ms * ws6.dt * TAU_PS * 86400.0 / 1000.0,
+                         "pairs_within_cutoff": pairs, "tuning": tun}
+            eng.close()
+        out[ws6.name] = res
     return out
 
 

@@ -252,6 +252,18 @@ def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, bet
                                images=images))
 
 
+def paper_slab(metal=False, x_p=0.05, seed=6):
+    """The adsorption study's system at its size: 96,000 electrolyte beads
+    in a 25 x 25.11 x 61.16 slab between electrode lattices of 50 x 58 sites,
+    chains of 60 monomers at ion fraction x_p; the box tripled along z for
+    the slab correction (nonmetal) or doubled with image charges (metal).
+    rc = 3, beta = 1.1 as for the bulk electrolyte; mesh spacing about 0.4
+    (64 x 64 x 432, or 64 x 64 x 288 for the doubled box)."""
+    return slab_system(nx=50, ny=58, h=61.16, chain_len=60, x_p=x_p, seed=seed, rc=3.0, beta=1.1,
+                       grid=(64, 64, 288) if metal else (64, 64, 432), metal=metal,
+                       name="slab_metal_images" if metal else "slab_nonmetal_corrected")
+
+
 def config4():
     """Large bulk: N = 2^21, three species a = 0.3/0.5/0.7, A ~ U(15, 35)
     symmetric (seeded), 15% charged, rc = 2.5, beta = 1.2, SPME 256^3."""

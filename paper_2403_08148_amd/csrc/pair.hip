@@ -844,7 +844,15 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
 #pragma unroll
           for (int g = 0; g < G; ++g) {
             const int k = k0 + g;
-            try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, pp[g], vi && jl + k * CJ < n && (pp[g].w >> 16) != self);
+            // slots past the last entry of a final drain may never have been
+            // written by this wave (fewer than 64 candidates, as in sparse
+            // regions): their parameter word would index the pair tables out
+            // of range, so it is replaced by 0 (the positions are integers,
+            // always finite, and the pair is masked)
+            const bool live = jl + k * CJ < n;
+            uint4 q = pp[g];
+            q.w = live ? q.w : 0u;
+            try_pair<T, ELEC, EV, ADJ, COUNT>(L, P, mi, q, vi && live && (q.w >> 16) != self);
           }
         }
       }

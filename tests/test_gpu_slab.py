@@ -259,3 +259,38 @@ def test_set_images_errors():
     eng.set_images(img)
     gpu_eval(eng)
     eng.close()
+
+
+@pytest.mark.parametrize("metal", [False, True])
+def test_paper_slab_full_size(metal):
+    """The adsorption study's slab systems at its size (about 10^5 beads), in
+    the launch configuration the benchmark times (mixed precision,
+    autotuned), against the oracle over every bead."""
+    w = W.paper_slab(metal=metal)
+    print(f"case paper_slab metal={metal} N={w.N}", flush=True)
+    eng = _engine([w], "mixed")
+    tun = eng.autotune()
+    print(f"  tuning {tun}", flush=True)
+    got = gpu_eval(eng)
+    eng.close()
+    _compare(got["energy"][0], got["force"], got["virial"][0], _oracle(w), "mixed", w.name)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sparse_image_half_steps(precision):
+    """The metal slab's image half holds only the image charges (about 0.25
+    beads per unit volume), so list-free excluded-volume clusters there have
+    fewer than 64 candidates and are not compact: the final drain of the
+    general path must not read ring slots the wave never wrote.  Thirty steps
+    at the default tuning, then a fresh evaluation against the oracle."""
+    w = W.paper_slab(metal=True)
+    print(f"case sparse_image_half N={w.N} prec={precision}", flush=True)
+    eng = _engine([w], precision, seed=12345)
+    eng.set_tuning(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=4, direct_pairs=3, stream_layout=0)
+    eng.step(30)
+    eng.sync()
+    pos, _, _ = eng.get_state()
+    pos = pos.cpu().numpy().T.copy()
+    got = gpu_eval(eng)
+    eng.close()
+    _compare(got["energy"][0], got["force"], got["virial"][0], _oracle(w, pos=pos), precision, "after 30 steps")
