@@ -19,7 +19,8 @@
  *     -lB beta/sqrt(pi) sum z^2 and the Born self term lB/2 sum z^2/a.
  *   - Forces F = -dE/dr, the virial tensor sum r_ij (x) f_ij (eq. pres_virial
  *     uses its trace) plus the reciprocal-space virial.
- *   - Parameter derivatives dE/dA (per type pair), dE/dsigma_t, dE/da_t.
+ *   - Parameter derivatives dE/dA (per type pair), dE/dsigma_t, dE/da_t, and
+ *     per bead dE/dsigma_i, dE/da_i.
  *   - The slab correction for a slab in a box with a vacuum gap along z
  *     (nonmetal electrodes; section "Image charge effects on polyelectrolyte
  *     adsorption", with the Yeh--Berkowitz reference it cites):
@@ -309,6 +310,51 @@ int gco_real_space(int N, const double* pos, const int* type, const int* z,
     }
     free(wp); free(head); free(next); free(acc); free(ftmp);
     free(ett); free(dsg); free(dea);
+    return 0;
+}
+
+/* Per-bead radius derivatives: the derivative of E with respect to bead i's
+ * own mass radius sigma_i and charge radius a_i, as if every bead had its
+ * own radii (evaluated at the per-type values), written out over all pairs
+ * by brute force (minimum image, r < rc):
+ *   dE/dsigma_i = sum_j du_ex/ds_ij * sigma_i / s_ij,  s_ij^2 = sigma_i^2 + sigma_j^2
+ *     (eq. u_ex: du/ds = u (3 r^2/s^3 - 3/s)),
+ *   dE/da_i = sum_j d/da_ij [lB z_i z_j erf(alpha_ij r)/r] * a_i / a_ij
+ *             - lB z_i^2 / (2 a_i^2)
+ *     (eq. u_elec through the real-space term of eq. ewald, and eq.
+ *     self_energy; the reciprocal and correction terms do not depend on a).
+ * Summed over the beads of a type they give dE/dsigma_t and dE/da_t. */
+int gco_per_bead_adjoint(int N, const double* pos, const int* type, const int* z, const gco_params* p,
+                         double* dsig, double* da) {
+    for (int k = 0; k < 3; ++k)
+        if (p->rc > 0.5 * p->box[k]) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < N; ++i) {
+        const int ti = type[i];
+        double ds = 0.0, dq = 0.0;
+        for (int j = 0; j < N; ++j) {
+            if (j == i) continue;
+            double d[3], r2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                d[k] = min_image(wrapd(pos[3 * i + k], p->box[k]) - wrapd(pos[3 * j + k], p->box[k]), p->box[k]);
+                r2 += d[k] * d[k];
+            }
+            if (r2 >= p->rc * p->rc) continue;
+            const int tj = type[j];
+            const double s2 = p->sigma[ti] * p->sigma[ti] + p->sigma[tj] * p->sigma[tj], s = sqrt(s2);
+            const double u = gco_u_ex(sqrt(r2), p->A[ti * p->nt + tj], s2);
+            ds += u * (3.0 * r2 / (s2 * s) - 3.0 / s) * p->sigma[ti] / s;
+            if (z[i] != 0 && z[j] != 0) {
+                const double aij = sqrt(p->a[ti] * p->a[ti] + p->a[tj] * p->a[tj]);
+                const double alpha = sqrt(M_PI / 2.0) / aij;
+                const double dud = -p->lB * (double)z[i] * (double)z[j] * (2.0 / sqrt(M_PI)) * (alpha / aij) *
+                                   exp(-alpha * alpha * r2);
+                dq += dud * p->a[ti] / aij;
+            }
+        }
+        dsig[i] = ds;
+        da[i] = dq - 0.5 * p->lB * (double)z[i] * (double)z[i] / (p->a[ti] * p->a[ti]);
+    }
     return 0;
 }
 

@@ -93,6 +93,7 @@ def lib():
         L.gco_slab.restype = C.c_double
         L.gco_slab.argtypes = [C.c_int, dp, ip, dp, C.c_double, dp, dp]
         L.gco_mirror_images.argtypes = [dp, dp, C.c_int, ip]
+        L.gco_per_bead_adjoint.argtypes = [C.c_int, dp, ip, ip, C.POINTER(_Params), dp, dp]
         L.gco_bonds.restype = C.c_double
         L.gco_bonds.argtypes = [C.c_int, dp, dp, C.c_int, ip, C.c_double, C.c_double, dp, dp]
         L.gco_md.argtypes = [C.c_int, dp, dp, dp, ip, ip, ip, C.POINTER(_Params), C.POINTER(_Recip),
@@ -315,6 +316,17 @@ def bonds(pos, box, pairs, k, b):
     bx = np.ascontiguousarray(box, dtype=np.float64)
     E = lib().gco_bonds(len(pos), _d(pos), _d(bx), len(pairs), _i(pairs), float(k), float(b), _d(F), _d(W))
     return dict(E=E, F=F, W=W)
+
+
+def per_bead_adjoint(pos, type_, z, p: Params):
+    """dE/dsigma_i and dE/da_i of every bead (see gco_per_bead_adjoint)."""
+    pos, type_, z = _prep(pos, type_, z)
+    N = len(pos)
+    pc = p._c()
+    ds, da = np.zeros(N), np.zeros(N)
+    if lib().gco_per_bead_adjoint(N, _d(pos), _i(type_), _i(z), C.byref(pc), _d(ds), _d(da)) != 0:
+        raise ValueError("oracle: rc must be <= L/2")
+    return dict(dE_dsigma=ds, dE_da=da)
 
 
 def mirror_images(pos, box, images):
