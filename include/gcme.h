@@ -157,6 +157,18 @@ typedef struct {
                             entry (t,u) = dE/dA_tu of the symmetric parameter */
     double* dE_dsigma;   /* device [n_replicas][MAX_TYPES] out, or NULL */
     double* dE_da;       /* device [n_replicas][MAX_TYPES] out, or NULL */
+    double* dE_dsigma_bead;  /* device [N_total] out, or NULL: per bead, the
+                                derivative of E with respect to the bead's own
+                                mass radius sigma_i (eq. u_ex), as if every bead
+                                had its own radii, at the per-type values;
+                                summed over a type it is dE_dsigma */
+    double* dE_da_bead;      /* device [N_total] out, or NULL: the same for the
+                                charge radius a_i (eq. u_elec through the
+                                real-space term of eq. ewald, and eq.
+                                self_energy; the reciprocal and correction
+                                terms do not depend on a).  Original bead order.
+                                gcme_forces_energy only (gcme_step with steps
+                                to take: GCME_EINVAL) */
 } gcme_io;
 
 /* Create a context: allocates every device buffer whose size depends only on

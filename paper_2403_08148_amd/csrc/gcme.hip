@@ -132,6 +132,9 @@ struct gcme_ctx {
   DevBuf part[N_SLOTS], adjp[2];
   DevBuf d_off[N_SLOTS], d_adj_off[2];
   DevBuf d_consts, d_Avals, d_dself;
+  // per-bead radius derivatives (sorted order) and the self term's factor
+  DevBuf dbead_g, dbead_q, d_self_a;
+  bool per_bead = false;
   DevBuf d_imass, d_c1, d_c2s, d_dt, d_lang;
   DevBuf d_status, d_step, d_pairs;
   DevBuf d_ewk, d_ew_items_s, d_ew_items_f, ew_sp;  // exact reciprocal sums
@@ -776,6 +779,12 @@ gcme_status build_plan(gcme_handle h) {
   upload(consts, h->d_consts, s);
   upload(Av, h->d_Avals, s);
   upload(dself, h->d_dself, s);
+  {
+    std::vector<double> sa(R * MAXT, 0.0);
+    for (int r = 0; r < R; ++r)
+      for (int t = 0; t < h->hp[r].nt; ++t) sa[r * MAXT + t] = -0.5 * h->hp[r].lB / (h->hp[r].a[t] * h->hp[r].a[t]);
+    upload(sa, h->d_self_a, s);
+  }
   upload(h->rep, h->d_rep, s);
   HIPCHK(h, hipStreamSynchronize(s));
   h->plan_dirty = false;
@@ -806,6 +815,7 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.qidx = h->q_idx.as<int>();
     a.part = h->part[SLOT_REAL].as<double>();
     a.adj_part = h->adjp[1].as<double>();
+    a.dbead = h->per_bead ? h->dbead_q.as<double>() : nullptr;
   } else {
     a.tiles = h->d_tiles_g.as<Tile>();
     a.ntiles = h->ntiles_g;
@@ -820,6 +830,7 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.start = h->start.as<int>();
     a.part = h->part[SLOT_GCM].as<double>();
     a.adj_part = h->adjp[0].as<double>();
+    a.dbead = h->per_bead ? h->dbead_g.as<double>() : nullptr;
   }
   return a;
 }
@@ -1209,6 +1220,8 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   ok &= h->tmp.alloc(N * 4) == hipSuccess;
   ok &= h->slot_of.alloc(N * 4) == hipSuccess;
   ok &= h->slot_a.alloc(N * 4) == hipSuccess;
+  ok &= h->dbead_g.alloc(N * 8) == hipSuccess;
+  ok &= h->dbead_q.alloc(N * 8) == hipSuccess;
   ok &= h->F.alloc(N * 24) == hipSuccess;
   ok &= h->d_status.alloc(64) == hipSuccess;
   ok &= h->d_step.alloc(64) == hipSuccess;
@@ -1460,7 +1473,7 @@ gcme_status gcme_forces_energy(gcme_handle h, const gcme_io* io) {
   if (!io) return fail(h, GCME_EINVAL, "null io");
   gcme_status st = check_ready(h);
   if (st != GCME_OK) return st;
-  if (io->dE_da)
+  if (io->dE_da || io->dE_da_bead)
     for (int r = 0; r < h->R; ++r)
       if (h->hp[r].flags & GCME_FLAG_ALL_RECIPROCAL)
         return fail(h, GCME_EUNSUPPORTED, "dE/da is not provided with the all-reciprocal splitting");
@@ -1470,10 +1483,18 @@ gcme_status gcme_forces_energy(gcme_handle h, const gcme_io* io) {
     launch_ingest(s, io->pos, h->N, h->N, h->d_rep.as<RepDesc>(), nullptr, viewA(h), h->F.as<long long>(), h->N);
   else
     launch_fill_i64(s, h->F.as<long long>(), 0, 3LL * h->N);
-  bool adj = io->dE_dA || io->dE_dsigma || io->dE_da;
+  const bool pb = io->dE_dsigma_bead || io->dE_da_bead;
+  bool adj = io->dE_dA || io->dE_dsigma || io->dE_da || pb;
   bool ev = io->energy || io->virial || adj;
+  // uncharged beads get no charged-kernel store
+  if (pb) launch_fill_i64(s, h->dbead_q.as<long long>(), 0, h->N);
+  h->per_bead = pb;
   enqueue_eval(h, s, ev, adj);
+  h->per_bead = false;
   enqueue_outputs(h, s, io, false);
+  if (pb)
+    launch_bead_adj_out(s, viewB(h), h->dbead_g.as<double>(), h->dbead_q.as<double>(), h->d_self_a.as<double>(),
+                        io->dE_dsigma_bead, io->dE_da_bead, h->N);
   launch_commit(s, viewB(h), viewA(h), h->N);
   HIPCHK(h, hipGetLastError());
   h->forces_valid = true;
@@ -1484,6 +1505,8 @@ gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe) {
   if (!h) return GCME_EINVAL;
   if (n_steps < 0) return fail(h, GCME_EINVAL, "n_steps must be >= 0");
   if (observe && observe->pos) return fail(h, GCME_EINVAL, "observe->pos must be NULL");
+  if (observe && n_steps > 0 && (observe->dE_dsigma_bead || observe->dE_da_bead))
+    return fail(h, GCME_EINVAL, "per-bead derivatives come from gcme_forces_energy");
   gcme_status st = check_ready(h);
   if (st != GCME_OK) return st;
   HIPCHK(h, hipSetDevice(h->device));

@@ -291,6 +291,9 @@ struct PairLaunch {
   long long* F[3];
   double* part;        // partial sums of this slot, [ntiles][PART_W]
   double* adj_part;    // adjoint partials [ntiles][MAXT * MAXT + 2 * MAXT]
+  double* dbead;       // adjoint, or null: per sorted bead, the derivative of E
+                       // with respect to the bead's own radius (sigma in the
+                       // excluded-volume kernel, a in the charged one)
   unsigned long long* pair_count;  // optional counter
   unsigned int* status;
   double fscale;       // 2^FSHIFT
@@ -408,6 +411,10 @@ void launch_int_last(hipStream_t s, const IntLaunch& a, StateView B, StateView A
                      long long* const F[3], bool kin);
 void launch_forces_out(hipStream_t s, StateView B, long long* const F[3], double* out, long long ld,
                        int N, double fscale_inv);
+// Per-bead radius derivatives to original bead order: dE/dsigma_i from dg,
+// dE/da_i from dq plus the self-energy term self_a[rep][type] z_i^2.
+void launch_bead_adj_out(hipStream_t s, StateView B, const double* dg, const double* dq, const double* self_a,
+                         double* out_sigma, double* out_a, int N);
 void launch_state_out(hipStream_t s, StateView A, const RepDesc* rep, double* pos, double* vel,
                       long long ld, int N);
 struct FinalLaunch {

@@ -213,6 +213,17 @@ __global__ void k_forces_out(StateView B, long long* F0, long long* F1, long lon
   out[2 * ld + id] = (double)F2[n] * sc;
 }
 
+__global__ void k_bead_adj_out(StateView B, const double* dg, const double* dq, const double* self_a,
+                               double* out_s, double* out_a, int N) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int id = B.id[n];
+  const uint32_t prm = B.param[n];
+  const int z = param_z(prm);
+  if (out_s) out_s[id] = dg[n];
+  if (out_a) out_a[id] = dq[n] + self_a[param_rep(prm) * MAXT + param_type(prm)] * (double)(z * z);
+}
+
 __global__ void k_state_out(StateView A, const RepDesc* rep, double* pos, double* vel, long long ld, int N) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N) return;
@@ -343,6 +354,11 @@ void launch_forces_out(hipStream_t s, StateView B, long long* const F[3], double
                        double fscale_inv) {
   hipLaunchKernelGGL(k_forces_out, dim3(nblk(N, 256)), dim3(256), 0, s, B, F[0], F[1], F[2], out, ld, N,
                      fscale_inv);
+}
+
+void launch_bead_adj_out(hipStream_t s, StateView B, const double* dg, const double* dq, const double* self_a,
+                         double* out_sigma, double* out_a, int N) {
+  hipLaunchKernelGGL(k_bead_adj_out, dim3(nblk(N, 256)), dim3(256), 0, s, B, dg, dq, self_a, out_sigma, out_a, N);
 }
 
 void launch_state_out(hipStream_t s, StateView A, const RepDesc* rep, double* pos, double* vel, long long ld,

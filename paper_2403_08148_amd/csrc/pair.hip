@@ -647,6 +647,14 @@ template <typename T, int CI, bool ELEC, bool ADJ>
 __device__ inline void flush_bead(const PairLaunch& a, Lane<T>& L, bool vi, int i, int ti) {
   constexpr int CJ = 64 / CI;
   const int jl = (threadIdx.x & 63) % CJ;
+  if (ADJ && a.dbead) {
+    // the bead's own-radius derivative: every bead is in one cluster, so one
+    // store per bead, summed over its lanes in a fixed order
+    T d = L.di;
+#pragma unroll
+    for (int o = CJ >> 1; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    if (vi && jl == 0) a.dbead[ELEC ? a.qidx[i] : i] = (double)d;
+  }
   if (ADJ && vi) flush_adj<T, ELEC>(L, ti);
   T fx = L.fx, fy = L.fy, fz = L.fz;
 #pragma unroll

@@ -135,11 +135,11 @@ class GCMe:
         return pos, vel, step.value
 
     # -- evaluation -------------------------------------------------------
-    def _io(self, pos=None, force=True, energy=True, virial=True, adjoint=False):
+    def _io(self, pos=None, force=True, energy=True, virial=True, adjoint=False, per_bead=False):
         with self.torch.cuda.stream(self.stream):
-            return self._io_on_stream(pos, force, energy, virial, adjoint)
+            return self._io_on_stream(pos, force, energy, virial, adjoint, per_bead)
 
-    def _io_on_stream(self, pos, force, energy, virial, adjoint):
+    def _io_on_stream(self, pos, force, energy, virial, adjoint, per_bead=False):
         torch = self.torch
         out = {}
         keep = []
@@ -167,10 +167,16 @@ class GCMe:
             io.dE_dA = out["dE_dA"].data_ptr()
             io.dE_dsigma = out["dE_dsigma"].data_ptr()
             io.dE_da = out["dE_da"].data_ptr()
+        if per_bead:
+            # per-bead radius derivatives, original bead order
+            out["dE_dsigma_bead"] = torch.empty(self.N, dtype=torch.float64, device=self.device)
+            out["dE_da_bead"] = torch.empty(self.N, dtype=torch.float64, device=self.device)
+            io.dE_dsigma_bead = out["dE_dsigma_bead"].data_ptr()
+            io.dE_da_bead = out["dE_da_bead"].data_ptr()
         return io, out, keep
 
-    def forces_energy(self, pos=None, force=True, energy=True, virial=True, adjoint=False):
-        io, out, keep = self._io(pos, force, energy, virial, adjoint)
+    def forces_energy(self, pos=None, force=True, energy=True, virial=True, adjoint=False, per_bead=False):
+        io, out, keep = self._io(pos, force, energy, virial, adjoint, per_bead)
         B.check(self.h, self.lib.gcme_forces_energy(self.h, C.byref(io)))
         return out
 
