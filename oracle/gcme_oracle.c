@@ -20,7 +20,8 @@
  *   - Forces F = -dE/dr, the virial tensor sum r_ij (x) f_ij (eq. pres_virial
  *     uses its trace) plus the reciprocal-space virial.
  *   - Parameter derivatives dE/dA (per type pair), dE/dsigma_t, dE/da_t, and
- *     per bead dE/dsigma_i, dE/da_i.
+ *     per bead dE/dsigma_i, dE/da_i, and the forces' vector-Jacobian product
+ *     sum_i v_i . dF_i/dtheta for force matching.
  *   - The slab correction for a slab in a box with a vacuum gap along z
  *     (nonmetal electrodes; section "Image charge effects on polyelectrolyte
  *     adsorption", with the Yeh--Berkowitz reference it cites):
@@ -355,6 +356,78 @@ int gco_per_bead_adjoint(int N, const double* pos, const int* type, const int* z
         dsig[i] = ds;
         da[i] = dq - 0.5 * p->lB * (double)z[i] * (double)z[i] / (p->a[ti] * p->a[ti]);
     }
+    return 0;
+}
+
+/* Force vector-Jacobian product for force matching: for a per-bead vector
+ * v (AoS [N][3]), the derivatives of sum_i v_i . F_i with respect to the
+ * parameters, by brute force over ordered pairs (i, j), r < rc.  The pair
+ * force on i is fs(r) d with d = r_i - r_j, so each ordered pair adds
+ * (v_i . d) dfs/dtheta:
+ *   GCM (eq. u_ex, fs = 3 u / s^2): dfs/dA_ij = fs / A_ij, evaluated as the
+ *     A = 1 value; dfs/ds = (u / s^3)(9 r^2 / s^2 - 15), ds/dsigma_t =
+ *     sigma_t / s for each end of type t;
+ *   real-space electrostatics (eq. ewald's first term, fs = lB z_i z_j g):
+ *     dg/dalpha = 2 (2/sqrt(pi)) alpha^2 exp(-alpha^2 r^2), alpha =
+ *     sqrt(pi/2)/a_ij, dalpha/da_ij = -alpha/a_ij, da_ij/da_t = a_t/a_ij.
+ * The reciprocal term's forces do not depend on A, sigma or a.
+ * dA[nt*nt] is the derivative for the symmetric parameter (both orders of a
+ * type pair), dsig[nt], da[nt]. */
+int gco_force_vjp(int N, const double* pos, const int* type, const int* z, const gco_params* p, const double* v,
+                  double* dA, double* dsig, double* da) {
+    for (int k = 0; k < 3; ++k)
+        if (p->rc > 0.5 * p->box[k]) return -1;
+    const int nt = p->nt;
+    double* M = (double*)calloc((size_t)N * (nt * nt + 2 * nt), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < N; ++i) {
+        double* m = M + (size_t)i * (nt * nt + 2 * nt);
+        const int ti = type[i];
+        for (int j = 0; j < N; ++j) {
+            if (j == i) continue;
+            double d[3], r2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                d[k] = min_image(wrapd(pos[3 * i + k], p->box[k]) - wrapd(pos[3 * j + k], p->box[k]), p->box[k]);
+                r2 += d[k] * d[k];
+            }
+            if (r2 >= p->rc * p->rc) continue;
+            const int tj = type[j];
+            const double vd = v[3 * i] * d[0] + v[3 * i + 1] * d[1] + v[3 * i + 2] * d[2];
+            const double r = sqrt(r2);
+            const double s2 = p->sigma[ti] * p->sigma[ti] + p->sigma[tj] * p->sigma[tj], s = sqrt(s2);
+            const double u1 = gco_u_ex(r, 1.0, s2), u = p->A[ti * nt + tj] * u1;
+            m[ti * nt + tj] += vd * 3.0 * u1 / s2;
+            const double dfds = u / (s2 * s) * (9.0 * r2 / s2 - 15.0);
+            m[nt * nt + ti] += vd * dfds * p->sigma[ti] / s;
+            m[nt * nt + tj] += vd * dfds * p->sigma[tj] / s;
+            if (z[i] != 0 && z[j] != 0) {
+                const double aij = sqrt(p->a[ti] * p->a[ti] + p->a[tj] * p->a[tj]);
+                const double al = sqrt(M_PI / 2.0) / aij;
+                const double dfda = p->lB * (double)z[i] * (double)z[j] * 2.0 * (2.0 / sqrt(M_PI)) * al * al *
+                                    exp(-al * al * r2) * (-al / aij);
+                m[nt * nt + nt + ti] += vd * dfda * p->a[ti] / aij;
+                m[nt * nt + nt + tj] += vd * dfda * p->a[tj] / aij;
+            }
+        }
+    }
+    for (int q = 0; q < nt * nt + 2 * nt; ++q) {
+        double acc = 0.0;
+        for (int i = 0; i < N; ++i) acc += M[(size_t)i * (nt * nt + 2 * nt) + q];
+        if (q < nt * nt) {
+            /* ordered sums first, symmetrised below */
+            dA[q] = acc;
+        } else if (q < nt * nt + nt) {
+            dsig[q - nt * nt] = acc;
+        } else {
+            da[q - nt * nt - nt] = acc;
+        }
+    }
+    for (int t = 0; t < nt; ++t)
+        for (int u2 = t + 1; u2 < nt; ++u2) {
+            const double sym = dA[t * nt + u2] + dA[u2 * nt + t];
+            dA[t * nt + u2] = dA[u2 * nt + t] = sym;
+        }
+    free(M);
     return 0;
 }
 

@@ -94,6 +94,7 @@ def lib():
         L.gco_slab.argtypes = [C.c_int, dp, ip, dp, C.c_double, dp, dp]
         L.gco_mirror_images.argtypes = [dp, dp, C.c_int, ip]
         L.gco_per_bead_adjoint.argtypes = [C.c_int, dp, ip, ip, C.POINTER(_Params), dp, dp]
+        L.gco_force_vjp.argtypes = [C.c_int, dp, ip, ip, C.POINTER(_Params), dp, dp, dp, dp]
         L.gco_bonds.restype = C.c_double
         L.gco_bonds.argtypes = [C.c_int, dp, dp, C.c_int, ip, C.c_double, C.c_double, dp, dp]
         L.gco_md.argtypes = [C.c_int, dp, dp, dp, ip, ip, ip, C.POINTER(_Params), C.POINTER(_Recip),
@@ -327,6 +328,19 @@ def per_bead_adjoint(pos, type_, z, p: Params):
     if lib().gco_per_bead_adjoint(N, _d(pos), _i(type_), _i(z), C.byref(pc), _d(ds), _d(da)) != 0:
         raise ValueError("oracle: rc must be <= L/2")
     return dict(dE_dsigma=ds, dE_da=da)
+
+
+def force_vjp(pos, type_, z, p: Params, v):
+    """sum_i v_i . dF_i/dtheta for theta = A (symmetric, [nt, nt]), sigma
+    and a ([nt] each); v is [N, 3] (see gco_force_vjp)."""
+    pos, type_, z = _prep(pos, type_, z)
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+    nt = len(p.sigma)
+    pc = p._c()
+    dA, ds, da = np.zeros(nt * nt), np.zeros(nt), np.zeros(nt)
+    if lib().gco_force_vjp(len(pos), _d(pos), _i(type_), _i(z), C.byref(pc), _d(v), _d(dA), _d(ds), _d(da)) != 0:
+        raise ValueError("oracle: rc must be <= L/2")
+    return dict(dA=dA.reshape(nt, nt), dsigma=ds, da=da)
 
 
 def mirror_images(pos, box, images):

@@ -1,4 +1,5 @@
-"""Pins of the oracle's per-bead radius derivatives dE/dsigma_i, dE/da_i.
+"""Pins of the oracle's per-bead radius derivatives dE/dsigma_i, dE/da_i and
+of the forces' vector-Jacobian product (force matching).
 
 A bead given a type of its own (with its old type's parameters, so the
 energy is unchanged) has a per-type derivative equal to its per-bead one:
@@ -71,3 +72,38 @@ def test_per_bead_sums_to_per_type():
     for ty in range(2):
         assert pb["dE_dsigma"][t == ty].sum() == pytest.approx(rs["dE_dsigma"][ty], rel=1e-11)
         assert pb["dE_da"][t == ty].sum() == pytest.approx(rs["dE_da"][ty] + c["dE_da_self"][ty], rel=1e-11)
+
+
+def test_force_vjp_matches_finite_differences():
+    """sum_i v_i . dF_i/dtheta against central differences of sum_i v_i . F_i
+    over each parameter (forces from the oracle's evaluation; the
+    reciprocal forces do not depend on these parameters)."""
+    pos, t, z, p = _system(seed=5, N=160)
+    rng = np.random.default_rng(9)
+    v = rng.normal(size=(len(pos), 3))
+    vj = O.force_vjp(pos, t, z, p, v)
+
+    def vF(q):
+        return float((v * O.forces(pos, t, z, q, recip_mode=O.RECIP_NONE)["F"]).sum())
+
+    def with_(A=None, sigma=None, a=None):
+        return O.Params(box=p.box, rc=p.rc, beta=p.beta, lB=p.lB, A=p.A if A is None else A,
+                        sigma=p.sigma if sigma is None else sigma, a=p.a if a is None else a)
+
+    h = 1e-5
+    for (ti, tu) in ((0, 0), (0, 1), (1, 1)):
+        Ap, Am = p.A.copy(), p.A.copy()
+        Ap[ti, tu] += h
+        Am[ti, tu] -= h
+        if ti != tu:
+            Ap[tu, ti] += h
+            Am[tu, ti] -= h
+        fd = (vF(with_(A=Ap)) - vF(with_(A=Am))) / (2 * h)
+        assert vj["dA"][ti, tu] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    for ty in range(2):
+        for name, key in (("sigma", "dsigma"), ("a", "da")):
+            vp, vm = getattr(p, name).copy(), getattr(p, name).copy()
+            vp[ty] += h
+            vm[ty] -= h
+            fd = (vF(with_(**{name: vp})) - vF(with_(**{name: vm}))) / (2 * h)
+            assert vj[key][ty] == pytest.approx(fd, rel=1e-6, abs=1e-8), (name, ty)
