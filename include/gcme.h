@@ -169,6 +169,17 @@ typedef struct {
                                 terms do not depend on a).  Original bead order.
                                 gcme_forces_energy only (gcme_step with steps
                                 to take: GCME_EINVAL) */
+    const double* force_vjp; /* device [3][N_total] in, or NULL: a vector v per
+                                bead.  When set, dE_dA, dE_dsigma and dE_da (at
+                                least one required) receive the forces'
+                                vector-Jacobian product sum_i v_i . dF_i/dtheta
+                                instead of dE/dtheta: the gradient of a
+                                force-matching loss L(F) with v = dL/dF.  Only
+                                the pair terms depend on the parameters (eq.
+                                u_ex, the real-space term of eq. ewald); the
+                                entry for a type pair with A = 0 is 0.  Not
+                                with the per-bead outputs (GCME_EINVAL);
+                                gcme_forces_energy only */
 } gcme_io;
 
 /* Create a context: allocates every device buffer whose size depends only on

@@ -7,6 +7,6 @@ engine does, and raises if the library has not been built.
 """
 from ._binding import GCMeError, load  # noqa: F401
 from .engine import GCMe, ReplicaParams, params_from_workload  # noqa: F401
-from .autograd import GCMeEnergy, gcme_energy  # noqa: F401
+from .autograd import GCMeEnergy, GCMeForces, gcme_energy, gcme_forces  # noqa: F401
 
-__all__ = ["GCMe", "GCMeError", "GCMeEnergy", "ReplicaParams", "gcme_energy", "params_from_workload", "load"]
+__all__ = ["GCMe", "GCMeError", "GCMeEnergy", "GCMeForces", "ReplicaParams", "gcme_energy", "gcme_forces", "params_from_workload", "load"]

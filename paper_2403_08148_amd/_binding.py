@@ -45,7 +45,7 @@ class gcme_params(C.Structure):
 class gcme_io(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("force", C.c_void_p), ("energy", C.c_void_p), ("virial", C.c_void_p),
                 ("dE_dA", C.c_void_p), ("dE_dsigma", C.c_void_p), ("dE_da", C.c_void_p),
-                ("dE_dsigma_bead", C.c_void_p), ("dE_da_bead", C.c_void_p)]
+                ("dE_dsigma_bead", C.c_void_p), ("dE_da_bead", C.c_void_p), ("force_vjp", C.c_void_p)]
 
 
 class gcme_tuning(C.Structure):

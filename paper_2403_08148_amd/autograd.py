@@ -104,4 +104,53 @@ def gcme_energy(engine, params, pos, A, a, sigma=None):
     return GCMeEnergy.apply(pos, A, a, sigma, engine, params)
 
 
-__all__ = ["GCMeEnergy", "gcme_energy", "E_POT"]
+def _set_params(engine, params, A, a, sigma):
+    As = _sym(A.detach()).cpu()
+    ac = a.detach().cpu()
+    sc = ac if sigma is None else sigma.detach().cpu()
+    for r in range(engine.R):
+        engine.set_params(dataclasses.replace(params[r], A=As[r].numpy(), a=ac[r].numpy(), sigma=sc[r].numpy()), r)
+
+
+class GCMeForces(torch.autograd.Function):
+    """forces[N, 3] = GCMeForces.apply(A, a, sigma, engine, params, pos)
+
+    The forces as a function of the pair strengths and radii (same arguments
+    as GCMeEnergy), for force matching: the backward of a loss L(F) passes
+    v = dL/dF to the library's force vector-Jacobian product, the sums
+    sum_i v_i . dF_i/dtheta accumulated in the pair kernels (only the pair
+    terms of eq. u_ex and of eq. ewald's real-space term depend on A and the
+    radii).  The engine keeps the forward's parameters until the backward.
+    """
+
+    @staticmethod
+    def forward(ctx, A, a, sigma, engine, params, pos):
+        _set_params(engine, params, A, a, sigma)
+        out = engine.forces_energy(pos=pos.detach(), force=True, energy=False, virial=False)
+        engine.sync()
+        ctx.engine, ctx.pos, ctx.tied, ctx.nt, ctx.pdev = engine, pos.detach(), sigma is None, A.shape[-1], A.device
+        return out["force"].t().contiguous()
+
+    @staticmethod
+    def backward(ctx, gF):
+        eng = ctx.engine
+        out = eng.forces_energy(pos=ctx.pos, force=False, energy=False, virial=False, adjoint=True,
+                                force_vjp=gF.detach().to(torch.float64).contiguous())
+        eng.sync()
+        nt = ctx.nt
+        dA, da, ds = out["dE_dA"][:, :nt, :nt], out["dE_da"][:, :nt], out["dE_dsigma"][:, :nt]
+        # a type pair's value is for the symmetric parameter: half to each of
+        # the two matrix entries through the symmetrisation
+        eye = torch.eye(nt, dtype=dA.dtype, device=dA.device)
+        g_A = (dA * (0.5 * (1.0 - eye) + eye)).to(ctx.pdev)
+        if ctx.tied:
+            return g_A, (da + ds).to(ctx.pdev), None, None, None, None
+        return g_A, da.to(ctx.pdev), ds.to(ctx.pdev), None, None, None
+
+
+def gcme_forces(engine, params, pos, A, a, sigma=None):
+    """Functional form of GCMeForces.apply (see its docstring)."""
+    return GCMeForces.apply(A, a, sigma, engine, params, pos)
+
+
+__all__ = ["GCMeEnergy", "gcme_energy", "GCMeForces", "gcme_forces", "E_POT"]

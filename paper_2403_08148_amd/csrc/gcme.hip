@@ -135,6 +135,8 @@ struct gcme_ctx {
   // per-bead radius derivatives (sorted order) and the self term's factor
   DevBuf dbead_g, dbead_q, d_self_a;
   bool per_bead = false;
+  DevBuf vjp_sorted;  // force vector-Jacobian product: v in sorted order
+  bool vjp = false;
   DevBuf d_imass, d_c1, d_c2s, d_dt, d_lang;
   DevBuf d_status, d_step, d_pairs;
   DevBuf d_ewk, d_ew_items_s, d_ew_items_f, ew_sp;  // exact reciprocal sums
@@ -816,6 +818,8 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.part = h->part[SLOT_REAL].as<double>();
     a.adj_part = h->adjp[1].as<double>();
     a.dbead = h->per_bead ? h->dbead_q.as<double>() : nullptr;
+    a.vjp = h->vjp ? h->vjp_sorted.as<double>() : nullptr;
+    a.nbeads = h->N;
   } else {
     a.tiles = h->d_tiles_g.as<Tile>();
     a.ntiles = h->ntiles_g;
@@ -831,6 +835,8 @@ PairLaunch pair_args(gcme_handle h, bool charged) {
     a.part = h->part[SLOT_GCM].as<double>();
     a.adj_part = h->adjp[0].as<double>();
     a.dbead = h->per_bead ? h->dbead_g.as<double>() : nullptr;
+    a.vjp = h->vjp ? h->vjp_sorted.as<double>() : nullptr;
+    a.nbeads = h->N;
   }
   return a;
 }
@@ -1075,6 +1081,8 @@ void enqueue_outputs(gcme_handle h, hipStream_t s, const gcme_io* io, bool kin) 
     f.dE_dA = io->dE_dA;
     f.dE_dsigma = io->dE_dsigma;
     f.dE_da = io->dE_da;
+    f.adj_scale = io->force_vjp ? 2.0 : 1.0;
+    f.vjp = io->force_vjp ? 1 : 0;
     launch_finalize(s, f);
   }
 }
@@ -1222,6 +1230,7 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
   ok &= h->slot_a.alloc(N * 4) == hipSuccess;
   ok &= h->dbead_g.alloc(N * 8) == hipSuccess;
   ok &= h->dbead_q.alloc(N * 8) == hipSuccess;
+  ok &= h->vjp_sorted.alloc(N * 24) == hipSuccess;
   ok &= h->F.alloc(N * 24) == hipSuccess;
   ok &= h->d_status.alloc(64) == hipSuccess;
   ok &= h->d_step.alloc(64) == hipSuccess;
@@ -1485,12 +1494,23 @@ gcme_status gcme_forces_energy(gcme_handle h, const gcme_io* io) {
     launch_fill_i64(s, h->F.as<long long>(), 0, 3LL * h->N);
   const bool pb = io->dE_dsigma_bead || io->dE_da_bead;
   bool adj = io->dE_dA || io->dE_dsigma || io->dE_da || pb;
+  if (io->force_vjp && (pb || !adj))
+    return fail(h, GCME_EINVAL, "force_vjp needs dE_dA, dE_dsigma or dE_da and no per-bead outputs");
   bool ev = io->energy || io->virial || adj;
   // uncharged beads get no charged-kernel store
   if (pb) launch_fill_i64(s, h->dbead_q.as<long long>(), 0, h->N);
   h->per_bead = pb;
-  enqueue_eval(h, s, ev, adj);
+  h->vjp = io->force_vjp != nullptr;
+  if (h->vjp) {
+    // v to the sorted order the pair kernels index
+    enqueue_sort(h, s);
+    launch_gather_vjp(s, viewB(h), io->force_vjp, h->vjp_sorted.as<double>(), h->N);
+    enqueue_forces(h, s, ev, adj);
+  } else {
+    enqueue_eval(h, s, ev, adj);
+  }
   h->per_bead = false;
+  h->vjp = false;
   enqueue_outputs(h, s, io, false);
   if (pb)
     launch_bead_adj_out(s, viewB(h), h->dbead_g.as<double>(), h->dbead_q.as<double>(), h->d_self_a.as<double>(),
@@ -1505,8 +1525,8 @@ gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe) {
   if (!h) return GCME_EINVAL;
   if (n_steps < 0) return fail(h, GCME_EINVAL, "n_steps must be >= 0");
   if (observe && observe->pos) return fail(h, GCME_EINVAL, "observe->pos must be NULL");
-  if (observe && n_steps > 0 && (observe->dE_dsigma_bead || observe->dE_da_bead))
-    return fail(h, GCME_EINVAL, "per-bead derivatives come from gcme_forces_energy");
+  if (observe && n_steps > 0 && (observe->dE_dsigma_bead || observe->dE_da_bead || observe->force_vjp))
+    return fail(h, GCME_EINVAL, "per-bead derivatives and force_vjp come from gcme_forces_energy");
   gcme_status st = check_ready(h);
   if (st != GCME_OK) return st;
   HIPCHK(h, hipSetDevice(h->device));

@@ -291,6 +291,9 @@ struct PairLaunch {
   long long* F[3];
   double* part;        // partial sums of this slot, [ntiles][PART_W]
   double* adj_part;    // adjoint partials [ntiles][MAXT * MAXT + 2 * MAXT]
+  const double* vjp;   // adjoint, or null: v per sorted bead, [3][nbeads]; the
+                       // adjoint sums then hold sum_i v_i . dF_i/dtheta
+  int nbeads;
   double* dbead;       // adjoint, or null: per sorted bead, the derivative of E
                        // with respect to the bead's own radius (sigma in the
                        // excluded-volume kernel, a in the charged one)
@@ -411,6 +414,9 @@ void launch_int_last(hipStream_t s, const IntLaunch& a, StateView B, StateView A
                      long long* const F[3], bool kin);
 void launch_forces_out(hipStream_t s, StateView B, long long* const F[3], double* out, long long ld,
                        int N, double fscale_inv);
+// v (original order, [3][N]) to sorted order for the force vector-Jacobian
+// product.
+void launch_gather_vjp(hipStream_t s, StateView B, const double* v, double* vs, int N);
 // Per-bead radius derivatives to original bead order: dE/dsigma_i from dg,
 // dE/da_i from dq plus the self-energy term self_a[rep][type] z_i^2.
 void launch_bead_adj_out(hipStream_t s, StateView B, const double* dg, const double* dq, const double* self_a,
@@ -423,7 +429,7 @@ struct FinalLaunch {
   const double* part[N_SLOTS];
   const int* slot_off[N_SLOTS];  // [R+1] partial ranges per replica
   const double* consts;          // [R][2]: E_corr, E_self
-  double* energy;                // [R][7] or null
+  double* energy;                // [R][N_TERMS] or null
   double* virial;                // [R][6] or null
   int have_kin;
   const double* adj_part[2];     // gcm, real adjoint partials
@@ -433,6 +439,9 @@ struct FinalLaunch {
   double* dE_dA;
   double* dE_dsigma;
   double* dE_da;
+  double adj_scale;              // 1, or 2 for the force vector-Jacobian
+                                 // product (its pair sums are not halved)
+  int vjp;                       // the adjoint holds sum_i v_i . dF_i/dtheta
 };
 void launch_finalize(hipStream_t s, const FinalLaunch& a);
 

@@ -213,6 +213,14 @@ __global__ void k_forces_out(StateView B, long long* F0, long long* F1, long lon
   out[2 * ld + id] = (double)F2[n] * sc;
 }
 
+__global__ void k_gather_vjp(StateView B, const double* v, double* vs, int N) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int id = B.id[n];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) vs[(size_t)k * N + n] = v[(size_t)k * N + id];
+}
+
 __global__ void k_bead_adj_out(StateView B, const double* dg, const double* dq, const double* self_a,
                                double* out_s, double* out_a, int N) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -315,10 +323,11 @@ __global__ __launch_bounds__(256) void k_finalize(FinalLaunch a) {
           // unordered type-pair energy: both visiting orders
           double E = t == u ? ett[t * MAXT + t] : ett[t * MAXT + u] + ett[u * MAXT + t];
           double A = a.Avals[(size_t)r * MAXT * MAXT + t * MAXT + u];
-          if (a.dE_dA) a.dE_dA[(size_t)r * MAXT * MAXT + t * MAXT + u] = A != 0.0 ? E / A : 0.0;
+          if (a.dE_dA) a.dE_dA[(size_t)r * MAXT * MAXT + t * MAXT + u] = A != 0.0 ? a.adj_scale * E / A : 0.0;
         }
-        if (a.dE_dsigma) a.dE_dsigma[(size_t)r * MAXT + t] = dsg[t];
-        if (a.dE_da) a.dE_da[(size_t)r * MAXT + t] = dea[t] + a.dself[(size_t)r * MAXT + t];
+        if (a.dE_dsigma) a.dE_dsigma[(size_t)r * MAXT + t] = a.adj_scale * dsg[t];
+        if (a.dE_da)
+          a.dE_da[(size_t)r * MAXT + t] = a.adj_scale * dea[t] + (a.vjp ? 0.0 : a.dself[(size_t)r * MAXT + t]);
       }
     }
   }
@@ -354,6 +363,10 @@ void launch_forces_out(hipStream_t s, StateView B, long long* const F[3], double
                        double fscale_inv) {
   hipLaunchKernelGGL(k_forces_out, dim3(nblk(N, 256)), dim3(256), 0, s, B, F[0], F[1], F[2], out, ld, N,
                      fscale_inv);
+}
+
+void launch_gather_vjp(hipStream_t s, StateView B, const double* v, double* vs, int N) {
+  hipLaunchKernelGGL(k_gather_vjp, dim3(nblk(N, 256)), dim3(256), 0, s, B, v, vs, N);
 }
 
 void launch_bead_adj_out(hipStream_t s, StateView B, const double* dg, const double* dq, const double* self_a,

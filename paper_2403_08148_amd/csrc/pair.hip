@@ -470,7 +470,8 @@ __device__ inline void lane_zero(Lane<T>& L) {
 // One ordered pair (i, j) with separation d = r_i - r_j, r2 < rc^2.
 template <typename T, bool ELEC, bool EV, bool ADJ, bool COUNT>
 __device__ inline void interact(Lane<T>& L, T dx, T dy, T dz, T r2, uint32_t pj, const GcmPar<T>* grow,
-                                const ElecPar<T>* erow, const AdjPar<T>* arow, T zi, T beta, T beta2, T lB) {
+                                const ElecPar<T>* erow, const AdjPar<T>* arow, T zi, T beta, T beta2, T lB,
+                                T vx = 0, T vy = 0, T vz = 0, bool vjp = false) {
   const int tj = param_type(pj);
   T fs, en;
   if (!ELEC) {
@@ -481,11 +482,20 @@ __device__ inline void interact(Lane<T>& L, T dx, T dy, T dz, T r2, uint32_t pj,
       const AdjPar<T> ap = arow[tj];
       // du/ds = u (3 r^2/s^3 - 3/s), s = s_ij
       T duds = en * ((T)3 * r2 * ap.inv_s2 - (T)3) * ap.s_inv;
+      T eA = en;
+      if (vjp) {
+        // force vector-Jacobian product: (v_i . d) dfs/dtheta with
+        // dfs/dA = fs/A (divided by A with the energies) and
+        // dfs/ds = (u/s^3)(9 r^2/s^2 - 15)
+        const T vd = vx * dx + vy * dy + vz * dz;
+        eA = vd * fs;
+        duds = vd * en * ap.inv_s2 * ap.s_inv * ((T)9 * r2 * ap.inv_s2 - (T)15);
+      }
       L.di += duds * ap.dsig_i;
 #pragma unroll
       for (int t = 0; t < MAXT; ++t) {
         if (t == tj) {
-          L.eA[t] += en;
+          L.eA[t] += eA;
           L.dj[t] += duds * ap.dsig_j;
         }
       }
@@ -516,6 +526,9 @@ __device__ inline void interact(Lane<T>& L, T dx, T dy, T dz, T r2, uint32_t pj,
       const AdjPar<T> ap = arow[tj];
       // d/da_ij of lB zz erf(alpha r)/r = -lB zz (2/sqrt(pi)) (alpha/a_ij) exp(-alpha^2 r^2)
       T dd = -lB * zz * ap.ea * gexp(-p.alpha2 * r2);
+      // force vector-Jacobian product: dg/dalpha = 2 (2/sqrt(pi)) alpha^2
+      // exp(-alpha^2 r^2), so dfs/da_ij = 2 alpha^2 dd
+      if (vjp) dd = (vx * dx + vy * dy + vz * dz) * (T)2 * p.alpha2 * dd;
       L.di += dd * ap.daij_i;
 #pragma unroll
       for (int t = 0; t < MAXT; ++t)
@@ -561,6 +574,8 @@ __device__ inline void flush_adj(Lane<T>& L, int ti) {
 template <typename T>
 struct PairCtx {
   T sx, sy, sz, rc2, beta, beta2, lB, zi;
+  T vx, vy, vz;  // force vector-Jacobian product: v of bead i (adjoint only)
+  bool vjp;
   const GcmPar<T>* grow;
   const ElecPar<T>* erow;
   const AdjPar<T>* arow;
@@ -584,7 +599,8 @@ __device__ inline void stage_tables(Tables<T, ELEC, ADJ>& S, const PairLaunch& a
 }
 
 template <typename T, bool ELEC, bool ADJ>
-__device__ inline PairCtx<T> make_ctx(const Tables<T, ELEC, ADJ>& S, const RepDesc& R, uint32_t pi) {
+__device__ inline PairCtx<T> make_ctx(const Tables<T, ELEC, ADJ>& S, const RepDesc& R, uint32_t pi,
+                                      const PairLaunch& a, int i) {
   const int ti = param_type(pi);
   PairCtx<T> P;
   P.sx = (T)R.scaled[0];
@@ -598,6 +614,15 @@ __device__ inline PairCtx<T> make_ctx(const Tables<T, ELEC, ADJ>& S, const RepDe
   P.grow = S.g + (ELEC ? 0 : ti * MAXT);
   P.erow = S.e + (ELEC ? ti * MAXT : 0);
   P.arow = S.a + (ADJ ? ti * MAXT : 0);
+  P.vjp = false;
+  P.vx = P.vy = P.vz = 0;
+  if (ADJ && a.vjp) {
+    const int fi = ELEC ? a.qidx[i] : i;
+    P.vjp = true;
+    P.vx = (T)a.vjp[fi];
+    P.vy = (T)a.vjp[(size_t)a.nbeads + fi];
+    P.vz = (T)a.vjp[2 * (size_t)a.nbeads + fi];
+  }
   return P;
 }
 
@@ -629,7 +654,8 @@ __device__ inline void pair_at(Lane<T>& L, const PairCtx<T>& P, T dx, T dy, T dz
       L.w5 += fyd * (double)dz;
     }
   } else if (in) {
-    interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pw, P.grow, P.erow, P.arow, P.zi, P.beta, P.beta2, P.lB);
+    interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pw, P.grow, P.erow, P.arow, P.zi, P.beta, P.beta2, P.lB,
+                                      P.vx, P.vy, P.vz, P.vjp);
   }
 }
 
@@ -725,7 +751,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
     const bool vi = il < ni;
     const int i = first + (vi ? il : 0);
     const uint4 mi = a.pk[i];
-    const PairCtx<T> P = make_ctx(S, R, mi.w);
+    const PairCtx<T> P = make_ctx(S, R, mi.w, a, i);
     const int cnt = a.count[c];
     const uint32_t* __restrict__ lst = a.list + (size_t)c * a.cap;
     const uint4* __restrict__ pk = a.pk;
@@ -794,7 +820,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
     Cluster<CI> K;
     make_cluster(K, me, R);
     const bool frame = in_frame(K, R);
-    const PairCtx<T> P = make_ctx(S, R, mi.w);
+    const PairCtx<T> P = make_ctx(S, R, mi.w, a, i);
     // Ring records carry, in place of the replica bits, 1 + the cluster slot
     // of a candidate that is itself a cluster bead (0 otherwise).  In single
     // precision with the cluster in bead 0's frame they hold the candidate's

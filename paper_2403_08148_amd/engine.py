@@ -135,11 +135,11 @@ class GCMe:
         return pos, vel, step.value
 
     # -- evaluation -------------------------------------------------------
-    def _io(self, pos=None, force=True, energy=True, virial=True, adjoint=False, per_bead=False):
+    def _io(self, pos=None, force=True, energy=True, virial=True, adjoint=False, per_bead=False, force_vjp=None):
         with self.torch.cuda.stream(self.stream):
-            return self._io_on_stream(pos, force, energy, virial, adjoint, per_bead)
+            return self._io_on_stream(pos, force, energy, virial, adjoint, per_bead, force_vjp)
 
-    def _io_on_stream(self, pos, force, energy, virial, adjoint, per_bead=False):
+    def _io_on_stream(self, pos, force, energy, virial, adjoint, per_bead=False, force_vjp=None):
         torch = self.torch
         out = {}
         keep = []
@@ -167,6 +167,12 @@ class GCMe:
             io.dE_dA = out["dE_dA"].data_ptr()
             io.dE_dsigma = out["dE_dsigma"].data_ptr()
             io.dE_da = out["dE_da"].data_ptr()
+        if force_vjp is not None:
+            # v = dL/dF per bead: the adjoint outputs then hold sum_i v_i . dF_i/dtheta
+            v = self._soa(force_vjp)
+            v.record_stream(self.stream)
+            keep.append(v)
+            io.force_vjp = v.data_ptr()
         if per_bead:
             # per-bead radius derivatives, original bead order
             out["dE_dsigma_bead"] = torch.empty(self.N, dtype=torch.float64, device=self.device)
@@ -175,8 +181,9 @@ class GCMe:
             io.dE_da_bead = out["dE_da_bead"].data_ptr()
         return io, out, keep
 
-    def forces_energy(self, pos=None, force=True, energy=True, virial=True, adjoint=False, per_bead=False):
-        io, out, keep = self._io(pos, force, energy, virial, adjoint, per_bead)
+    def forces_energy(self, pos=None, force=True, energy=True, virial=True, adjoint=False, per_bead=False,
+                      force_vjp=None):
+        io, out, keep = self._io(pos, force, energy, virial, adjoint, per_bead, force_vjp)
         B.check(self.h, self.lib.gcme_forces_energy(self.h, C.byref(io)))
         return out
 
