@@ -124,14 +124,32 @@ class GCMe:
         vel = self._soa(vel) if vel is not None else None
         type_ = torch.as_tensor(type_, dtype=torch.int32, device=self.device).contiguous()
         z = torch.as_tensor(z, dtype=torch.int32, device=self.device).contiguous()
+        self._engine_waits()
         B.check(self.h, self.lib.gcme_set_state(self.h, _ptr(pos), _ptr(vel), _ptr(type_), _ptr(z)))
+
+    # The library works on its own stream.  Inputs made on torch's current
+    # stream must be complete before it reads them, and its outputs before
+    # torch's stream reads them: two event waits, no host synchronisation.
+    def _engine_waits(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _caller_waits(self, outs=()):
+        cur = self.torch.cuda.current_stream(self.device)
+        cur.wait_stream(self.stream)
+        # outputs made on the library's stream are read on the caller's
+        for t in outs:
+            t.record_stream(cur)
 
     def get_state(self):
         torch = self.torch
         pos = torch.empty((3, self.N), dtype=torch.float64, device=self.device)
         vel = torch.empty((3, self.N), dtype=torch.float64, device=self.device)
+        pos.record_stream(self.stream)
+        vel.record_stream(self.stream)
+        self._engine_waits()
         step = C.c_uint64()
         B.check(self.h, self.lib.gcme_get_state(self.h, _ptr(pos), _ptr(vel), C.byref(step)))
+        self._caller_waits()
         return pos, vel, step.value
 
     # -- evaluation -------------------------------------------------------
@@ -183,16 +201,21 @@ class GCMe:
 
     def forces_energy(self, pos=None, force=True, energy=True, virial=True, adjoint=False, per_bead=False,
                       force_vjp=None):
+        self._engine_waits()
         io, out, keep = self._io(pos, force, energy, virial, adjoint, per_bead, force_vjp)
         B.check(self.h, self.lib.gcme_forces_energy(self.h, C.byref(io)))
+        self._caller_waits(out.values())
         return out
 
     def step(self, n_steps: int, observe: bool = False, **kw):
+        self._engine_waits()
         if observe:
             io, out, keep = self._io(None, **kw)
             B.check(self.h, self.lib.gcme_step(self.h, int(n_steps), C.byref(io)))
+            self._caller_waits(out.values())
             return out
         B.check(self.h, self.lib.gcme_step(self.h, int(n_steps), None))
+        self._caller_waits()
         return None
 
     def sync(self):

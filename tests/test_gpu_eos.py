@@ -53,3 +53,35 @@ def test_gcm_equation_of_state():
     # below the mean-field value, rising towards it with the density
     assert 0.45 < w25 < w50 < 0.5
     assert 0.5 - w50 < 0.015
+
+
+def test_gcm_rdf_first_peak():
+    """The radial distribution function of the same fluid at rho = 2.5 has its
+    first maximum near 0.8 d: the separation the paper takes as the bond
+    length b = 0.8 d because the RDF of the neutral GCMe fluid peaks there.
+    g(r) from 30 snapshots of the engine's MD, histogrammed on the host."""
+    from scipy.spatial import cKDTree
+    rho, N = 2.5, 4000
+    L = (N / rho) ** (1.0 / 3.0)
+    w = W.small_bulk(N=N, seed=33, charged_frac=0.0, a_types=(0.5,), A=[[25.0]], rc=3.0, grid=(16, 16, 16),
+                     box=(L, L, L))
+    print(f"case GCM RDF, N = {N}, rho = {rho}", flush=True)
+    eng = make_engine([w], "mixed", seed=9)
+    eng.step(600)
+    dr, rmax = 0.02, 2.0
+    hist = np.zeros(int(rmax / dr))
+    for _ in range(30):
+        eng.step(25)
+        pos, _, _ = eng.get_state()
+        p = np.mod(pos.cpu().numpy().T, L)
+        d = cKDTree(p, boxsize=L).sparse_distance_matrix(cKDTree(p, boxsize=L), rmax, output_type="ndarray")["v"]
+        hist += np.histogram(d[d > 0], bins=len(hist), range=(0.0, rmax))[0]
+    eng.close()
+    r = (np.arange(len(hist)) + 0.5) * dr
+    shell = 4.0 * np.pi * r * r * dr
+    g = hist / (30 * N * rho * shell)
+    k = int(np.argmax(g))
+    print(f"  first maximum g({r[k]:.2f}) = {g[k]:.3f}; g(0.1) = {g[5]:.3f}; g(1.8) = {g[90]:.3f}", flush=True)
+    assert 0.7 <= r[k] <= 0.9
+    assert g[k] > 1.05 and g[5] < 0.5
+    assert abs(g[85:].mean() - 1.0) < 0.1
