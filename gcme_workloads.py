@@ -148,8 +148,8 @@ def config2():
 
 def config3():
     """The polyelectrolyte-slab workload's composition and mesh as a periodic
-    bulk box (its chains' bonds, the electrodes and the image charges are not
-    part of the nonbonded path): N = 200,000 in 40 x 40 x 50 (rho = 2.5),
+    bulk box (the slab systems themselves, with bonds, electrodes and image
+    charges, are slab_system and paper_slab): N = 200,000 in 40 x 40 x 50 (rho = 2.5),
     50,000 beads at +1 (the charged chain monomers) and 50,000 at -1 (the
     counterions), the rest neutral; one species a = sigma = 0.5, A = 25,
     rc = 3, beta = 1.1, SPME 96 x 96 x 128 order 5."""
