@@ -110,7 +110,7 @@ __global__ __launch_bounds__(EX_THREADS) void k_bond(BondLaunch a, StateView B) 
     int si = a.slot_of[bd.x], sj = a.slot_of[bd.y];
     if ((unsigned)si >= (unsigned)a.nbeads || (unsigned)sj >= (unsigned)a.nbeads) {
       // a bead the sort did not place (inconsistent counts): flagged, skipped
-      atomicOr(a.status, (unsigned)STATUS_LIST_OVERFLOW);
+      atomicOr(a.status, (unsigned)STATUS_SLOT_MAP);
       si = sj = 0;
     }
     double d[3];
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(EX_THREADS) void k_images(ImageLaunch a, StateView 
   const int2 pr = a.pairs[m];
   const int si = c.slot_a[pr.x], ss = c.slot_a[pr.y];
   if ((unsigned)si >= (unsigned)a.nbeads || (unsigned)ss >= (unsigned)a.nbeads) {
-    atomicOr(a.status, (unsigned)STATUS_LIST_OVERFLOW);
+    atomicOr(a.status, (unsigned)STATUS_SLOT_MAP);
     return;
   }
   const uint32_t ux = A.pos[0][ss], uy = A.pos[1][ss], uz = 0u - A.pos[2][ss];

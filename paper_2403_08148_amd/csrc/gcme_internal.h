@@ -129,7 +129,9 @@ constexpr int PART_W = 8;
 constexpr int N_TERMS = 9;
 
 // Device status bits.
-enum { STATUS_FORCE_OVERFLOW = 1, STATUS_MESH_OVERFLOW = 2, STATUS_LIST_OVERFLOW = 4 };
+// STATUS_SLOT_MAP: a bond or image named a bead the sort did not place
+// (inconsistent cell counts); the term was skipped.
+enum { STATUS_FORCE_OVERFLOW = 1, STATUS_MESH_OVERFLOW = 2, STATUS_LIST_OVERFLOW = 4, STATUS_SLOT_MAP = 8 };
 
 // Bead parameter word: bits 0..7 type, 8..15 charge (int8), 16..31 replica.
 __host__ __device__ inline uint32_t pack_param(int t, int z, int rep) {
