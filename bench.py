@@ -50,7 +50,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--workload", default="bulk_N32768", choices=["bulk_N32768", "bulk_N2097152"])
+    ap.add_argument("--workload", default="bulk_N32768",
+                    choices=["bulk_N32768", "bulk_N2097152", "slab_nonmetal", "slab_metal"],
+                    help="the slab systems (adsorption study, its size) time the step loop only")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default="",
                     help="cells_per_cutoff,beads_per_cluster,charges_per_cluster[,direct_pairs[,stream_layout]] "
@@ -88,10 +90,15 @@ def main():
     import gcme_workloads as W
     from paper_2403_08148_amd import GCMe, params_from_workload
 
-    w = W.config2() if args.workload == "bulk_N32768" else W.config4()
-    eng = GCMe([w.N], precision=args.precision, seed=12345)
-    eng.set_params(params_from_workload(w))
-    eng.set_state(w.pos, w.type, w.z, w.vel)
+    slab = args.workload.startswith("slab")
+    if slab:
+        w = W.paper_slab(metal=args.workload == "slab_metal")
+        eng, _ = engine_for([w], args.precision, tune=False)
+    else:
+        w = W.config2() if args.workload == "bulk_N32768" else W.config4()
+        eng = GCMe([w.N], precision=args.precision, seed=12345)
+        eng.set_params(params_from_workload(w))
+        eng.set_state(w.pos, w.type, w.z, w.vel)
     if args.tuning:
         v = [int(x) for x in args.tuning.split(",")]
         eng.set_tuning(cells_per_cutoff=v[0], beads_per_cluster=v[1], charges_per_cluster=v[2],
@@ -122,8 +129,9 @@ def main():
     steps_per_s = 1000.0 / ms_step
     value = pairs * steps_per_s
     ns_day = steps_per_s * w.dt * TAU_PS * 86400.0 / 1000.0
-    if args.steps_only:
-        print(json.dumps({"ms_per_step": ms_step, "pairs": pairs}))
+    if args.steps_only or slab:
+        print(json.dumps({"workload": w.name, "n_beads": w.N, "ms_per_step": ms_step, "pairs": pairs,
+                          "pair_interactions_per_s": value, "tuning": tuning}))
         return
 
     # per-stage device times (HIP events between stages on the engine stream)
