@@ -97,3 +97,24 @@ def test_force_vjp_refusals():
     with pytest.raises(GCMeError, match="EINVAL"):
         eng.step(2, observe=True, adjoint=True, force_vjp=v)
     eng.close()
+
+
+def test_force_vjp_bulk_N32768():
+    """The benchmark workload (N = 32,768, mixed precision, default tuning)
+    against the oracle's brute force."""
+    import torch
+    w = W.config2()
+    print(f"case force_vjp N={w.N} mixed", flush=True)
+    v = np.random.default_rng(8).normal(size=(w.N, 3))
+    eng = make_engine([w], "mixed")
+    out = eng.forces_energy(adjoint=True, force_vjp=torch.as_tensor(v))
+    eng.sync()
+    got = {k: val.cpu().numpy() for k, val in out.items()}
+    eng.close()
+    ref = O.force_vjp(w.pos, w.type, w.z, oracle_params(w), v)
+    nt = w.nt
+    for g, r, tag in ((got["dE_dA"][0, :nt, :nt], ref["dA"], "A"), (got["dE_dsigma"][0, :nt], ref["dsigma"], "sigma"),
+                      (got["dE_da"][0, :nt], ref["da"], "a")):
+        err = np.abs(g - r).max() / np.abs(r).max()
+        print(f"  v.dF/d{tag}: {err:.2e}", flush=True)
+        assert err < 2e-5, tag
