@@ -228,6 +228,7 @@ def main():
                    "cutoff": w.rc, "beta": w.beta, "pme_grid": list(w.grid), "order": w.order, "dt": w.dt,
                    "integrator": "BAOAB Langevin", "precision": args.precision, "tuning": tuning},
         "ns_per_day": ns_day,
+        "tau_per_day": steps_per_s * w.dt * 86400.0,  # simulated time in the paper's reduced unit tau
         "steps_per_s": steps_per_s,
         "pairs_within_cutoff": pairs,
         "wall_s_timed": wall,
