@@ -387,9 +387,19 @@ __device__ inline cplx<T> green_apply(const RepDesc& R, const T* gf0, const T* g
       acc.w[0] += em * (1.0 - c * m0 * m0);
       acc.w[1] += em * (1.0 - c * m1 * m1);
       acc.w[2] += em * (1.0 - c * m2 * m2);
-      acc.w[3] -= em * c * m0 * m1;
-      acc.w[4] -= em * c * m0 * m2;
-      acc.w[5] -= em * c * m1 * m2;
+      // The sum runs over every m with each component in (-K/2, K/2]; an
+      // interior kz plane stands for itself and its conjugate partner
+      // (-m0, -m1, -m2), except that on a Nyquist line (m0 = K0/2 or
+      // m1 = K1/2) the partner keeps +K/2 there.  A term odd in such a
+      // component then cancels between the two instead of doubling.
+      const bool interior = wgt == 2.0;
+      const bool nyx = 2 * mx == R.K[0], nyy = 2 * my == R.K[1];
+      const double sxy = interior && nyx != nyy ? 0.0 : 1.0;
+      const double sxz = interior && nyx ? 0.0 : 1.0;
+      const double syz = interior && nyy ? 0.0 : 1.0;
+      acc.w[3] -= sxy * em * c * m0 * m1;
+      acc.w[4] -= sxz * em * c * m0 * m2;
+      acc.w[5] -= syz * em * c * m1 * m2;
     }
   }
   return {v.x * G, v.y * G};
