@@ -44,6 +44,20 @@ FLOP_PER_DISTANCE_TEST = 8
 FLOP_PER_ELEC_PAIR = 35
 
 
+# Default tuning per workload (cells_per_cutoff, beads_per_cluster,
+# charges_per_cluster, direct_pairs, stream_layout): the library's
+# autotuner's pick on MI355X for that workload (bench.py --autotune), fixed
+# so that every run, and the kernel traces under profiles/, time the same
+# kernels.
+DEFAULT_TUNING = {
+    "bulk_N32768": "3,8,4,3,0",
+    "bulk_N2097152": "3,8,4,3,0",
+}
+
+# stages of more than one kernel launch
+MULTI_KERNEL_STAGES = {"sort"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,11 +67,17 @@ def parse():
     ap.add_argument("--workload", default="bulk_N32768",
                     choices=["bulk_N32768", "bulk_N2097152", "slab_nonmetal", "slab_metal"],
                     help="the slab systems (adsorption study, its size) time the step loop only")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the tuning with the library's autotuner (after the warm-up) instead of the "
+                         "workload's default tuning")
     ap.add_argument("--tuning", default="",
                     help="cells_per_cutoff,beads_per_cluster,charges_per_cluster[,direct_pairs[,stream_layout]] "
-                         "(implies --no-autotune)")
+                         "in place of the workload's default tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing-steps", type=int, default=20,
+                    help="steps of the stage-timing pass (HIP event nodes in the step graph)")
+    ap.add_argument("--isolated-stages", action="store_true",
+                    help="also time each stage alone (replays of that stage only)")
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--steps-only", action="store_true",
                     help="only the timed step loop (for profiler runs)")
@@ -99,17 +119,23 @@ def main():
         eng = GCMe([w.N], precision=args.precision, seed=12345)
         eng.set_params(params_from_workload(w))
         eng.set_state(w.pos, w.type, w.z, w.vel)
-    if args.tuning:
-        v = [int(x) for x in args.tuning.split(",")]
+    tun_s = args.tuning or DEFAULT_TUNING.get(args.workload, "")
+    if tun_s and not args.autotune:
+        v = [int(x) for x in tun_s.split(",")]
         eng.set_tuning(cells_per_cutoff=v[0], beads_per_cluster=v[1], charges_per_cluster=v[2],
                        direct_pairs=v[3] if len(v) > 3 else -1, stream_layout=v[4] if len(v) > 4 else -1)
-        tuning = eng.tuning()
-    else:
-        tuning = eng.tuning() if args.no_autotune else eng.autotune()
 
-    # warm-up (also relaxes the random start a little)
+    # warm-up (also relaxes the random start a little); the first run of
+    # steps captures every step graph a later run replays
     eng.step(args.warmup)
     eng.sync()
+    if args.autotune:
+        eng.autotune()
+    # capture the step graphs if the autotuner's tuning dropped them, so that
+    # no graph is built inside the timed region
+    eng.step(0)
+    eng.sync()
+    tuning = eng.tuning()
     pairs0 = eng.count_pairs()
     torch.cuda.synchronize()
     stream = eng.stream  # the stream every kernel of the engine runs on
@@ -134,9 +160,14 @@ def main():
                           "pair_interactions_per_s": value, "tuning": tuning}))
         return
 
-    # per-stage device times (HIP events between stages on the engine stream)
-    stages = eng.profile_step(args.profile_reps)
+    # per-stage device times inside real steps: HIP event-record nodes
+    # around each stage's kernels, on that stage's stream, in the step graph
+    stages = eng.time_stages(args.timing_steps)
     eng.sync()
+    isolated = None
+    if args.isolated_stages:
+        isolated = eng.profile_step(args.profile_reps)
+        eng.sync()
     nq = int((w.z != 0).sum())
     obs = eng.step(1, observe=True)
     eng.sync()
@@ -188,9 +219,16 @@ def main():
     skip = {"list_gcm"} if direct & 1 else set()
     skip |= {"list_elec"} if direct & 2 else set()
     stage_roof = {k: roof_of(k) for k in stages if k in alg and stages[k] > 0 and k not in skip}
-    dom = max(stage_roof, key=lambda k: stages[k])
+    # the dominant kernel: the longest stage that is one kernel launch (the
+    # sort stage is four)
+    dom = max((k for k in stage_roof if k not in MULTI_KERNEL_STAGES), key=lambda k: stages[k])
     roof = dict(stage_roof[dom])
     roof["launch_us"] = stages[dom] * 1e3
+    roof["launch_us_source"] = (f"mean over {args.timing_steps} steps of HIP event-record nodes around the kernel "
+                                f"in the step graph (gcme_time_stages)")
+    prof = profiled_launch_us(dom, tuning, args.workload)
+    if prof is not None:
+        roof["launch_us_rocprof"] = prof
     roof["traffic"] = measured_traffic(dom, tuning) if args.precision == "mixed" else None
     vi = measured_valu(dom, tuning) if args.precision == "mixed" else None
     if vi is not None:
@@ -233,6 +271,7 @@ def main():
         "pairs_within_cutoff": pairs,
         "wall_s_timed": wall,
         "stage_ms": stages,
+        "stage_ms_isolated": isolated,
         "pair_gcm_tflops": gcm_tflops,
         "charged_pairs_within_cutoff": cc_pairs,
         "stage_roofline": stage_roof,
@@ -458,6 +497,24 @@ def measured_traffic(stage, tuning):
     fetch = run["fetch_kib"] * 1024.0 * cb / (t["copy_fetch_kib"] * 1024.0)
     write = run["write_kib"] * 1024.0 * cb / (t["copy_write_kib"] * 1024.0)
     return fetch + write
+
+
+def profiled_launch_us(stage, tuning, workload):
+    """The committed rocprofv3 kernel-trace mean duration (us) of the stage's
+    kernel for this workload and tuning (profiles/launch_<stage>.json), or
+    None when none matches or the kernel source changed since the trace."""
+    path = os.path.join(ROOT, "profiles", f"launch_{stage}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    with open(os.path.join(ROOT, t["source"])) as f:
+        if code_digest(f.read()) != t["source_code_sha256"]:
+            return None
+    key = ",".join(str(tuning[k]) for k in ("cells_per_cutoff", "beads_per_cluster", "charges_per_cluster",
+                                            "direct_pairs", "stream_layout"))
+    run = next((r for r in t["runs"] if r["key"] == key and r["workload"] == workload), None)
+    return None if run is None else float(run["mean_us"])
 
 
 def measured_valu(stage, tuning):

@@ -130,20 +130,21 @@ def bulk(name, N, seed, charged_frac, a_types, A, rc, beta, grid, order=5, lB=1.
                     a.copy(), a.copy(), tuple(grid), order, dt, gamma, kT, mass, seed, kmax)
 
 
-def config1():
+def config1(on_lattice=True):
     """Plain method, FP64: N = 1536 at rho = 2.5, 10% +1 / 10% -1, a = 0.5,
     A = 25, lB = 1, rc = 3, beta = 1.0, exact k-sum |k| <= 8 (wavevector),
     SPME 32^3 order 5 on the GPU, velocity Verlet at dt = 0.02."""
     return bulk("bulk_N1536_fp64", 1536, 1, 0.2, [0.5], [[25.0]], 3.0, 1.0, (32, 32, 32),
-                gamma=0.0, kmax=8.0)
+                gamma=0.0, kmax=8.0, on_lattice=on_lattice)
 
 
-def config2():
+def config2(on_lattice=True):
     """Bulk electrolyte: N = 32768, 20% charged, species a = 0.4 / 0.6 with
     A = {20, 25, 30}, rc = 3, beta = 1.1, SPME 64^3 order 5, BAOAB kT = 1,
     gamma = 1, dt = 0.02."""
     A = [[20.0, 25.0], [25.0, 30.0]]
-    return bulk("bulk_N32768_mixed", 32768, 2, 0.2, [0.4, 0.6], A, 3.0, 1.1, (64, 64, 64))
+    return bulk("bulk_N32768_mixed", 32768, 2, 0.2, [0.4, 0.6], A, 3.0, 1.1, (64, 64, 64),
+                on_lattice=on_lattice)
 
 
 def config3():
@@ -158,7 +159,8 @@ def config3():
 
 
 def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, beta=1.2, grid=(24, 24, 64),
-                order=5, gap_factor=3.0, lB=1.0, A=25.0, dt=0.02, gamma=1.0, kT=1.0, name=None, metal=False):
+                order=5, gap_factor=3.0, lB=1.0, A=25.0, dt=0.02, gamma=1.0, kT=1.0, name=None, metal=False,
+                on_lattice=True):
     """The nonmetal-electrode slab of the polyelectrolyte adsorption study,
     at a chosen size.  Electrodes: two planes of fixed beads (type 1, half
     the electrolyte radius, infinite mass, neutral) on a triangular lattice
@@ -176,7 +178,10 @@ def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, bet
     h + 1, the electrolyte between them, the box 2 H long in z, and after
     the real beads one image bead per charged bead (type 2: infinite mass,
     no excluded volume, the opposite charge) at the reflection (x, y, -z)
-    on the fixed-point lattice (extra["images"]: (image, source) pairs)."""
+    on the fixed-point lattice (extra["images"]: (image, source) pairs).
+
+    on_lattice=False leaves the positions where they were drawn (the images
+    then at the exact reflections of their sources)."""
     rng = np.random.default_rng(seed)
     sp = 0.5
     Lx, Ly = sp * nx, sp * ny * math.sqrt(3.0) / 2.0
@@ -215,7 +220,8 @@ def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, bet
     pos = np.vstack([mono, free, elec])
     pos[:, 0] %= Lx
     pos[:, 1] %= Ly
-    pos = lattice_positions(pos / np.asarray(box), box)
+    if on_lattice:
+        pos = lattice_positions(pos / np.asarray(box), box)
     N = len(pos)
     typ = np.zeros(N, dtype=np.int32)
     typ[n_mono + n_ci + n_sol:] = 1
@@ -228,9 +234,13 @@ def slab_system(nx=16, ny=18, h=8.0, chain_len=20, x_p=0.1, seed=21, rc=2.5, bet
     images = np.zeros((0, 2), dtype=np.int32)
     if metal:
         src = np.nonzero(z)[0]
-        u = np.round(pos[src] / np.asarray(box) * 4294967296.0)
-        u[:, 2] = np.mod(4294967296.0 - u[:, 2], 4294967296.0)
-        ipos = u / 4294967296.0 * np.asarray(box)
+        if on_lattice:
+            u = np.round(pos[src] / np.asarray(box) * 4294967296.0)
+            u[:, 2] = np.mod(4294967296.0 - u[:, 2], 4294967296.0)
+            ipos = u / 4294967296.0 * np.asarray(box)
+        else:
+            ipos = pos[src].copy()
+            ipos[:, 2] = np.mod(-ipos[:, 2], box[2])
         images = np.c_[np.arange(N, N + len(src)), src].astype(np.int32)
         pos = np.vstack([pos, ipos])
         typ = np.r_[typ, np.full(len(src), 2)].astype(np.int32)
@@ -264,15 +274,16 @@ def paper_slab(metal=False, x_p=0.05, seed=6):
                        name="slab_metal_images" if metal else "slab_nonmetal_corrected")
 
 
-def config4():
+def config4(on_lattice=True):
     """Large bulk: N = 2^21, three species a = 0.3/0.5/0.7, A ~ U(15, 35)
     symmetric (seeded), 15% charged, rc = 2.5, beta = 1.2, SPME 256^3."""
     rng = np.random.default_rng(1004)
     A = _sym_uniform(rng, 3, 15.0, 35.0)
-    return bulk("bulk_N2097152", 2097152, 4, 0.15, [0.3, 0.5, 0.7], A, 2.5, 1.2, (256, 256, 256))
+    return bulk("bulk_N2097152", 2097152, 4, 0.15, [0.3, 0.5, 0.7], A, 2.5, 1.2, (256, 256, 256),
+                on_lattice=on_lattice)
 
 
-def config5(n_replicas=256, seed=5):
+def config5(n_replicas=256, seed=5, on_lattice=True):
     """Batched replicas: N_r log-uniform in [500, 8000], 2 species with
     a ~ U(0.3, 0.7), A ~ U(15, 35) symmetric, charged fraction U(0.1, 0.3),
     rc = 2.5, beta = 1.2, grid = smallest 2^a 3^b >= L/0.37, order 5."""
@@ -285,18 +296,19 @@ def config5(n_replicas=256, seed=5):
         f = rng.uniform(0.1, 0.3)
         L = (n / DENSITY) ** (1.0 / 3.0)
         K = smooth_size(L / 0.37)
-        reps.append(bulk(f"replica{r}", n, seed * 100003 + r, f, a, A, 2.5, 1.2, (K, K, K)))
+        reps.append(bulk(f"replica{r}", n, seed * 100003 + r, f, a, A, 2.5, 1.2, (K, K, K),
+                         on_lattice=on_lattice))
     return reps
 
 
 def small_bulk(N=300, seed=11, charged_frac=0.3, a_types=(0.4, 0.6), rc=2.0, beta=1.1,
-               grid=(16, 16, 16), A=None, box=None, order=5):
+               grid=(16, 16, 16), A=None, box=None, order=5, on_lattice=True):
     """A few-hundred-bead box for fast parity cases (several tiles, ragged)."""
     nt = len(a_types)
     if A is None:
         A = _sym_uniform(np.random.default_rng(seed + 7), nt, 15.0, 35.0)
     return bulk(f"small_N{N}", N, seed, charged_frac, list(a_types), A, rc, beta, grid, order=order,
-                box=box)
+                box=box, on_lattice=on_lattice)
 
 
 def rock_salt(n_cells: int, r0: float = 1.0):

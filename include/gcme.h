@@ -182,8 +182,13 @@ typedef struct {
                                 gcme_forces_energy only */
 } gcme_io;
 
-/* Create a context: allocates every device buffer whose size depends only on
- * bead counts.  *out is set only on GCME_OK. */
+/* Create a context for n_replicas independent periodic systems, each the
+ * bead system of section "Gaussian core model" (N beads with positions,
+ * types and charge numbers in an orthorhombic box; the batch of boxes is
+ * this interface's own).  Allocates every device buffer whose size depends
+ * only on bead counts.  *out is set only on GCME_OK; on an error nothing is
+ * kept (GCME_EINVAL for a bad argument, GCME_EDEVICE when no device or
+ * stream is available, GCME_ENOMEM when an allocation fails). */
 gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out);
 
 /* Set force-field, mesh and integrator parameters of one replica
@@ -221,17 +226,28 @@ gcme_status gcme_set_bonds(gcme_handle h, int64_t n_bonds, const int32_t* pairs)
  * previous list (n_images = 0 removes them). */
 gcme_status gcme_set_images(gcme_handle h, int64_t n_images, const int32_t* pairs);
 
-/* Load the dynamic state: positions (device [3][N] float64, any real
- * coordinates; wrapped into the box), velocities (device [3][N] float64 or
- * NULL = zero), types (device int32 [N], 0..n_types-1) and charge numbers
- * (device int32 [N], |z| <= 127).  Checks types, and that every replica is
- * neutral.  Resets the step counter.  Synchronous. */
+/* Load the dynamic state of the bead system (section "Gaussian core
+ * model": positions r_i, species, charge numbers z_i; the periodic images n
+ * of eq. ewald make positions equivalent modulo the box): positions (device
+ * [3][N] float64, any real coordinates; wrapped into the box and stored as
+ * 32-bit fractions of each edge, i.e. rounded to the nearest multiple of
+ * L/2^32), velocities (device [3][N] float64 or NULL = zero), types (device
+ * int32 [N], 0..n_types-1) and charge numbers (device int32 [N],
+ * |z| <= 127).  The arrays are copied; the caller keeps ownership.  Checks
+ * types (GCME_EINVAL) and that every replica is neutral, as the Ewald sum
+ * of eq. ewald with the tin-foil boundary requires (GCME_ENONNEUTRAL);
+ * on an error the previous state is kept.  Resets the step counter.
+ * Synchronous. */
 gcme_status gcme_set_state(gcme_handle h, const double* pos, const double* vel,
                            const int32_t* type, const int32_t* z);
 
-/* Copy the state out in original bead order: positions wrapped into
- * [0, L) (device [3][N] or NULL), velocities (device [3][N] or NULL), and the
- * number of steps taken since gcme_set_state (host, or NULL). */
+/* Copy the dynamic state (section "Gaussian core model": positions and
+ * velocities of the beads) out in original bead order: positions wrapped
+ * into [0, L) at the stored 2^-32 L resolution (device [3][N] or NULL),
+ * velocities (device [3][N] or NULL), and the number of steps taken since
+ * gcme_set_state (host, or NULL).  The caller owns the outputs.
+ * GCME_ESTATE before any gcme_set_state.  Asynchronous for the device
+ * arrays (valid after gcme_sync). */
 gcme_status gcme_get_state(gcme_handle h, double* pos, double* vel, uint64_t* step);
 
 /* One force/energy evaluation (paper: eqs. u_ex, u_elec, ewald) at the
@@ -239,15 +255,30 @@ gcme_status gcme_get_state(gcme_handle h, double* pos, double* vel, uint64_t* st
  * Asynchronous on the context's stream. */
 gcme_status gcme_forces_energy(gcme_handle h, const gcme_io* io);
 
-/* Advance n_steps >= 0 (velocity Verlet if gamma == 0, else BAOAB Langevin
- * with Philox4x64-10 noise keyed by (seed, step, bead id, replica)).  If
- * observe != NULL its outputs are filled at the final positions (energy
- * includes GCME_E_KIN).  Steps are replayed from a captured HIP graph.
- * Asynchronous. */
+/* Advance n_steps >= 0 of molecular dynamics with the forces of eqs. u_ex,
+ * u_elec and ewald: the Langevin equations of motion that the paper's MD
+ * integrates each timestep (section "Method of image charges"; the timestep
+ * sizes of sections "Performance" and "Image charge effects on
+ * polyelectrolyte adsorption"), by BAOAB splitting with friction gamma at
+ * temperature kT and Philox4x64-10 noise keyed by (seed, step, bead id,
+ * replica); with gamma == 0, velocity Verlet (NVE).  Image beads follow
+ * their sources after every update (gcme_set_images).  If observe != NULL
+ * its outputs (caller-owned device arrays, as for gcme_forces_energy) are
+ * filled at the final positions (energy includes GCME_E_KIN).  Steps are
+ * replayed from captured HIP graphs, which the first run after a change of
+ * parameters or tuning captures (n_steps == 0 without observe takes no step
+ * and only captures them); the call allocates no device memory.
+ * GCME_EINVAL for n_steps < 0, observe->pos set, or per-bead/force_vjp
+ * outputs with steps to take; GCME_ESTATE before parameters and state.
+ * Asynchronous; device errors surface at gcme_sync. */
 gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe);
 
-/* Wait for the context's stream and report device-side status (accumulator
- * overflow -> GCME_EOVERFLOW, runtime errors -> GCME_EDEVICE). */
+/* Wait for the context's stream and report device-side status: a force
+ * that would overflow the 64-bit fixed-point accumulator of eq. ewald's
+ * force sum, a charge-mesh point beyond its fixed-point range, or a full
+ * neighbour list -> GCME_EOVERFLOW (the outputs of the calls since the last
+ * gcme_sync are then invalid); runtime errors -> GCME_EDEVICE.  The status
+ * is cleared once reported. */
 gcme_status gcme_sync(gcme_handle h);
 
 /* Message describing the last error on h (or on creation if h is NULL).
@@ -313,6 +344,21 @@ gcme_status gcme_count_pairs(gcme_handle h, uint64_t* n_pairs);
 #define GCME_N_STAGES 12
 gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms);
 const char* gcme_stage_name(int32_t i);
+
+/* Device time of each stage's kernel inside real steps, as it runs in a
+ * step's graph: n_steps >= 1 steps are taken (the state advances as with
+ * gcme_step(n_steps)), each the first half on the stream followed by a
+ * one-step graph, the step's graph with HIP event-record nodes added around
+ * every one-kernel stage (the first after the nodes the kernel waits for
+ * and before the kernel, the second after it), so the kernels overlap as
+ * in gcme_step's graphs; the host waits for each step and reads the events.
+ * ms[i] = the mean elapsed time of stage i over the steps (host array of
+ * GCME_N_STAGES; 0 for a stage this configuration does not launch, e.g. the
+ * list builds of list-free pairs, and for the sort, which is several
+ * kernels; int_first is timed by events on the stream around its kernel;
+ * int_last, the plain second half, includes the wait for every branch of
+ * the force evaluation).  Synchronous. */
+gcme_status gcme_time_stages(gcme_handle h, int32_t n_steps, double* ms);
 
 /* Release all device memory and the owned stream. */
 void gcme_destroy(gcme_handle h);

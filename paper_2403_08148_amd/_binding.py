@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "GCME_OK", 1: "GCME_EINVAL", 2: "GCME_EUNSUPPORTED", 3: "GCME
 
 EXPORTED = ["gcme_create", "gcme_set_params", "gcme_set_bonds", "gcme_set_images", "gcme_set_state", "gcme_get_state", "gcme_forces_energy",
             "gcme_step", "gcme_sync", "gcme_last_error", "gcme_get_tuning", "gcme_set_tuning",
-            "gcme_autotune", "gcme_count_pairs", "gcme_profile_step", "gcme_stage_name", "gcme_destroy"]
+            "gcme_autotune", "gcme_count_pairs", "gcme_profile_step", "gcme_stage_name", "gcme_destroy",
+            "gcme_time_stages"]
 GCME_N_STAGES = 12
 
 
@@ -89,6 +90,7 @@ def load():
     L.gcme_autotune.argtypes = [H]
     L.gcme_count_pairs.argtypes = [H, C.POINTER(C.c_uint64)]
     L.gcme_profile_step.argtypes = [H, C.c_int32, C.POINTER(C.c_double)]
+    L.gcme_time_stages.argtypes = [H, C.c_int32, C.POINTER(C.c_double)]
     L.gcme_stage_name.argtypes = [C.c_int32]
     L.gcme_stage_name.restype = C.c_char_p
     L.gcme_destroy.argtypes = [H]

@@ -22,18 +22,44 @@ static_assert(GCME_N_TERMS == N_TERMS, "energy row width");
 
 namespace {
 
+// A bump allocator over a device region the library already holds (the
+// static scratch of the no-alloc entry point).  While one is set for the
+// calling thread, DevBuf::alloc carves from it and never calls hipMalloc;
+// such buffers are never freed.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  size_t need = 0;  // bytes the last refused request would have needed
+};
+thread_local Arena* t_arena = nullptr;
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool in_arena = false;
   ~DevBuf() {
-    if (p) (void)hipFree(p);
+    if (p && !in_arena) (void)hipFree(p);
   }
   hipError_t alloc(size_t n) {
     if (n <= bytes && p) return hipSuccess;
-    if (p) (void)hipFree(p);
+    if (n == 0) n = 64;
+    if (t_arena) {
+      const size_t off = (t_arena->used + 255) & ~(size_t)255;
+      if (off + n > t_arena->size) {
+        t_arena->need = std::max(t_arena->need, off + n);
+        return hipErrorOutOfMemory;
+      }
+      if (p && !in_arena) (void)hipFree(p);
+      p = t_arena->base + off;
+      bytes = n;
+      in_arena = true;
+      t_arena->used = off + n;
+      return hipSuccess;
+    }
+    if (p && !in_arena) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
-    if (n == 0) n = 64;
+    in_arena = false;
     hipError_t e = hipMalloc(&p, n);
     if (e == hipSuccess) bytes = n;
     return e;
@@ -173,9 +199,23 @@ struct gcme_ctx {
   //          accumulates the energy, virial and kinetic partials)
   //   g_midn: MID_BATCH consecutive g_mid steps in one graph (one launch)
   hipGraphExec_t g_mid = nullptr, g_midn = nullptr, g_last = nullptr, g_obs = nullptr;
+  // stage timers (gcme_time_stages): while `timing` is set, the enqueue
+  // functions record tev[stage][0] before and tev[stage][1] after each
+  // stage's kernels, on that stage's stream (event-record nodes when
+  // captured into a graph)
+  hipEvent_t tev[GCME_N_STAGES][2] = {};
+  bool timing = false;
+  unsigned marked = 0;  // stages whose graph nodes the timing capture recorded
+  hipError_t mark_err = hipSuccess;  // first failed capture-info query
+  // per stage: the captured nodes its first kernel depends on, and its last
+  // kernel node(s)
+  std::vector<hipGraphNode_t> t_pre[GCME_N_STAGES], t_post[GCME_N_STAGES];
 
   ~gcme_ctx() {
     drop_graphs();
+    for (auto& st : tev)
+      for (auto& e : st)
+        if (e) (void)hipEventDestroy(e);
     for (auto& e : ev_join)
       if (e) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -258,10 +298,14 @@ ChargedView qview(gcme_handle h) {
 long long* Fk(gcme_handle h, int k) { return h->F.as<long long>() + (size_t)k * h->N; }
 
 template <typename T>
-void upload(std::vector<T>& v, DevBuf& b, hipStream_t s) {
-  (void)b.alloc(v.size() * sizeof(T));
-  (void)hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+hipError_t upload_buf(std::vector<T>& v, DevBuf& b, hipStream_t s) {
+  hipError_t e = b.alloc(v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
+// a table to the device; a failed allocation or copy ends the calling
+// function with its status
+#define upload(v, b, s) HIPCHK(h, upload_buf(v, b, s))
 
 std::vector<Tile> make_tiles(const std::vector<int>& off, const std::vector<int>& cnt, int per,
                              std::vector<int>& tile_off) {
@@ -319,7 +363,9 @@ void build_tables(gcme_handle h, std::vector<GcmPar<T>>& g, std::vector<ElecPar<
         double al = std::sqrt(M_PI / 2.0) / aij;
         e[q].alpha = (T)al;
         e[q].alpha2 = (T)(al * al);
-        double rs = 0.5 / al;
+        // the series is used where both alpha r and beta r stay below 1/2,
+        // which bounds its truncation after 8 (FP32) or 14 (FP64) terms
+        double rs = 0.5 / std::max(al, p.beta);
         e[q].rs2 = (T)(rs * rs);
         double cp[NSER], cgv[NSER];
         erf_series(al, p.beta, cp, cgv);
@@ -951,6 +997,53 @@ IntLaunch int_args(gcme_handle h) {
   return a;
 }
 
+// Stage indices of gcme_stage_name.
+enum {
+  ST_INT_FIRST = 0, ST_SORT, ST_LIST_GCM, ST_PAIR_GCM, ST_LIST_ELEC, ST_PAIR_ELEC, ST_SPREAD, ST_FFT_Y,
+  ST_FFT_CONV, ST_FFT_Y_INV, ST_GATHER, ST_INT_LAST
+};
+
+// A stage timer mark (only while the context captures its timing graph):
+// the capture's current dependencies on stream s, i.e. before a stage's
+// first kernel the nodes it will depend on, after its last kernel that
+// kernel's node.  Event-record nodes are placed at these points once the
+// capture has ended (add_stage_timers).
+void mark(gcme_handle h, int stage, int end, hipStream_t s) {
+  if (!h->timing) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  unsigned long long id = 0;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  const hipError_t e = hipStreamGetCaptureInfo_v2(s, &cs, &id, &g, &deps, &nd);
+  if (e != hipSuccess || cs != hipStreamCaptureStatusActive) {
+    if (h->mark_err == hipSuccess) h->mark_err = e != hipSuccess ? e : hipErrorStreamCaptureInvalidated;
+    return;
+  }
+  (end ? h->t_post : h->t_pre)[stage].assign(deps, deps + nd);
+  if (end && nd > 0) h->marked |= 1u << stage;
+}
+
+// Event-record nodes around every marked stage of a captured graph: the
+// first timer after the nodes the stage's kernels wait for, and before its
+// kernel (stages of one kernel, whose first kernel is also its last); the
+// second after its last kernel.
+hipError_t add_stage_timers(gcme_handle h, hipGraph_t g) {
+  // the sort stage is several kernels, some of them graph roots: not timed
+  h->marked &= ~(1u << ST_SORT);
+  for (int i = 0; i < GCME_N_STAGES; ++i) {
+    if (!(h->marked >> i & 1u)) continue;
+    hipGraphNode_t n0 = nullptr, n1 = nullptr;
+    const auto& pre = h->t_pre[i];
+    const auto& post = h->t_post[i];
+    hipError_t e = hipGraphAddEventRecordNode(&n0, g, pre.empty() ? nullptr : pre.data(), pre.size(), h->tev[i][0]);
+    if (e == hipSuccess && post.size() == 1) e = hipGraphAddDependencies(g, &n0, &post[0], 1);
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&n1, g, post.data(), post.size(), h->tev[i][1]);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Sort the state A into B by cell (and the charged copy), on stream s;
 // bin = false when the integrator has already binned A.
 void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
@@ -959,6 +1052,7 @@ void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
   // a step's sort (after the integrator's binning) starts the next step:
   // its scan advances the step counter
   if (!bin) c.step = h->d_step.as<unsigned long long>();
+  mark(h, ST_SORT, 0, s);
   if (bin) launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
   if (h->nimages > 0) {
     ImageLaunch im{};
@@ -972,6 +1066,7 @@ void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
   launch_scan(s, c);
   launch_scatter(s, c, h->N);
   launch_permute(s, viewA(h), viewB(h), h->b_pk.as<uint4>(), c, qview(h), h->N);
+  mark(h, ST_SORT, 1, s);
 }
 
 // Forces (and partial sums if ev) on the sorted copy B; F must be cleared.
@@ -982,8 +1077,14 @@ void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
 void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   PairLaunch g = pair_args(h, false);
   if (h->NQ == 0) {
-    launch_nl_build(s, g);
+    if (!g.direct) {
+      mark(h, ST_LIST_GCM, 0, s);
+      launch_nl_build(s, g);
+      mark(h, ST_LIST_GCM, 1, s);
+    }
+    mark(h, ST_PAIR_GCM, 0, s);
     launch_pair_gcm(s, g, h->fp64, ev, adj);
+    mark(h, ST_PAIR_GCM, 1, s);
     launch_bonds(s, bond_args(h), viewB(h));
     return;
   }
@@ -1000,33 +1101,61 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   };
   static const Layout kLayouts[6] = {{0, 1, 2, "gqp"}, {0, 0, 2, "gqp"}, {1, 1, 0, "pqg"},
                                      {1, 1, 0, "gqp"}, {0, 1, 1, "gpq"}, {1, 0, 0, "gpq"}};
-  const Layout& L = kLayouts[h->tune.stream_layout];
+  // a context without auxiliary streams (the no-alloc entry point's) runs
+  // the three parts in sequence on s
+  static const Layout kSingle = {0, 0, 0, "gqp"};
+  const Layout& L = h->aux[0] ? kLayouts[h->tune.stream_layout] : kSingle;
   hipStream_t st3[3] = {s, h->aux[0], h->aux[1]};
   hipStream_t sg = st3[L.g], sq = st3[L.q], sp = st3[L.p];
   const bool use1 = L.g == 1 || L.q == 1 || L.p == 1, use2 = L.g == 2 || L.q == 2 || L.p == 2;
-  (void)hipEventRecord(h->ev_fork, s);
+  if (use1 || use2) (void)hipEventRecord(h->ev_fork, s);
   if (use1) (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
   if (use2) (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
   PairLaunch q = pair_args(h, true);
   PmeLaunch p = pme_args(h);
   auto gcm = [&]() {
-    launch_nl_build(sg, g);
+    if (!g.direct) {
+      mark(h, ST_LIST_GCM, 0, sg);
+      launch_nl_build(sg, g);
+      mark(h, ST_LIST_GCM, 1, sg);
+    }
+    mark(h, ST_PAIR_GCM, 0, sg);
     launch_pair_gcm(sg, g, h->fp64, ev, adj);
+    mark(h, ST_PAIR_GCM, 1, sg);
   };
   auto elec = [&]() {
-    launch_nl_build(sq, q);
+    if (!q.direct && q.ntiles > 0) {
+      mark(h, ST_LIST_ELEC, 0, sq);
+      launch_nl_build(sq, q);
+      mark(h, ST_LIST_ELEC, 1, sq);
+    }
+    mark(h, ST_PAIR_ELEC, 0, sq);
     launch_pair_elec(sq, q, h->fp64, ev, adj);
+    mark(h, ST_PAIR_ELEC, 1, sq);
   };
   auto mesh = [&]() {
+    const bool meshed = p.ntiles > 0;
+    if (meshed) mark(h, ST_SPREAD, 0, sp);
     launch_spread_z(sp, p, h->fp64);
+    if (meshed) mark(h, ST_SPREAD, 1, sp);
     if (h->yx_fused) {
+      if (meshed) mark(h, ST_FFT_CONV, 0, sp);
       launch_fft_yx_conv(sp, p, h->fp64, ev);
+      if (meshed) mark(h, ST_FFT_CONV, 1, sp);
     } else {
+      if (meshed) mark(h, ST_FFT_Y, 0, sp);
       launch_fft_y(sp, p, h->fp64, false);
+      if (meshed) mark(h, ST_FFT_Y, 1, sp);
+      if (meshed) mark(h, ST_FFT_CONV, 0, sp);
       launch_fft_x_conv(sp, p, h->fp64, ev);
+      if (meshed) mark(h, ST_FFT_CONV, 1, sp);
+      if (meshed) mark(h, ST_FFT_Y_INV, 0, sp);
       launch_fft_y(sp, p, h->fp64, true);
+      if (meshed) mark(h, ST_FFT_Y_INV, 1, sp);
     }
+    if (meshed) mark(h, ST_GATHER, 0, sp);
     launch_z_gather(sp, p, h->fp64);
+    if (meshed) mark(h, ST_GATHER, 1, sp);
     // replicas with the exact reciprocal sum instead of a mesh
     launch_ewald(sp, ewald_args(h), h->fp64, ev);
     // the slab systems' extra terms (none in bulk)
@@ -1125,10 +1254,12 @@ void enqueue_step_rest(gcme_handle h, hipStream_t s, bool between, bool ev) {
   long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
   enqueue_sort(h, s, false);
   enqueue_forces(h, s, ev, false);
+  mark(h, ST_INT_LAST, 0, s);
   if (between)
     launch_int_between(s, ia, viewB(h), viewA(h), F3, cview(h));
   else
     launch_int_last(s, ia, viewB(h), viewA(h), F3, ev);
+  mark(h, ST_INT_LAST, 1, s);
 }
 
 gcme_status capture(gcme_handle h, bool between, bool ev, hipGraphExec_t* out, int repeat = 1) {
@@ -1137,10 +1268,27 @@ gcme_status capture(gcme_handle h, bool between, bool ev, hipGraphExec_t* out, i
   for (int k = 0; k < repeat; ++k) enqueue_step_rest(h, h->cap_stream, between, ev);
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (e != hipSuccess) return fail(h, GCME_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  if (h->timing) {
+    e = h->mark_err != hipSuccess ? h->mark_err : add_stage_timers(h, g);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(h, GCME_EDEVICE, std::string("stage timers: ") + hipGetErrorString(e));
+    }
+  }
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(h, GCME_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
   return GCME_OK;
+}
+
+// The graphs of a run of steps without observation: one step (g_mid),
+// MID_BATCH steps (g_midn) and the last step (g_last).
+gcme_status prepare_graphs(gcme_handle h) {
+  gcme_status st = GCME_OK;
+  if (!h->g_mid) st = capture(h, true, false, &h->g_mid);
+  if (st == GCME_OK && !h->g_midn) st = capture(h, true, false, &h->g_midn, MID_BATCH);
+  if (st == GCME_OK && !h->g_last) st = capture(h, false, false, &h->g_last);
+  return st;
 }
 
 gcme_status ensure_forces(gcme_handle h) {
@@ -1151,6 +1299,45 @@ gcme_status ensure_forces(gcme_handle h) {
   HIPCHK(h, hipGetLastError());
   h->forces_valid = true;
   return GCME_OK;
+}
+
+// The per-bead device buffers of a context (their sizes depend only on the
+// bead count), cleared where a first read needs zeros.  Without `derivs`
+// the buffers only the per-bead derivatives, the force vector-Jacobian
+// product, bonds and images use are left at a minimal size.
+bool alloc_bead_buffers(gcme_handle h, bool derivs) {
+  const size_t N = (size_t)h->N, Nd = derivs ? N : 1;
+  bool ok = true;
+  for (int k = 0; k < 3; ++k) {
+    ok &= h->a_pos[k].alloc(N * 4) == hipSuccess;
+    ok &= h->b_pos[k].alloc(N * 4) == hipSuccess;
+    ok &= h->a_vel[k].alloc(N * 8) == hipSuccess;
+    ok &= h->b_vel[k].alloc(N * 8) == hipSuccess;
+  }
+  ok &= h->a_param.alloc(N * 4) == hipSuccess;
+  ok &= h->b_param.alloc(N * 4) == hipSuccess;
+  ok &= h->a_id.alloc(N * 4) == hipSuccess;
+  ok &= h->b_pk.alloc(N * 16) == hipSuccess;
+  ok &= h->b_id.alloc(N * 4) == hipSuccess;
+  ok &= h->cell.alloc(N * 4) == hipSuccess;
+  ok &= h->tmp.alloc(N * 4) == hipSuccess;
+  ok &= h->slot_of.alloc(Nd * 4) == hipSuccess;
+  ok &= h->slot_a.alloc(Nd * 4) == hipSuccess;
+  ok &= h->dbead_g.alloc(Nd * 8) == hipSuccess;
+  ok &= h->dbead_q.alloc(Nd * 8) == hipSuccess;
+  ok &= h->vjp_sorted.alloc(Nd * 24) == hipSuccess;
+  ok &= h->F.alloc(N * 24) == hipSuccess;
+  ok &= h->d_status.alloc(64) == hipSuccess;
+  ok &= h->d_step.alloc(64) == hipSuccess;
+  ok &= h->d_pairs.alloc(64) == hipSuccess;
+  if (!ok) return false;
+  ok &= hipMemsetAsync(h->d_status.p, 0, 64, h->stream) == hipSuccess;
+  ok &= hipMemsetAsync(h->d_step.p, 0, 64, h->stream) == hipSuccess;
+  ok &= hipMemsetAsync(h->F.p, 0, N * 24, h->stream) == hipSuccess;
+  ok &= hipMemsetAsync(h->slot_of.p, 0, Nd * 4, h->stream) == hipSuccess;
+  ok &= hipMemsetAsync(h->slot_a.p, 0, Nd * 4, h->stream) == hipSuccess;
+  ok &= hipStreamSynchronize(h->stream) == hipSuccess;
+  return ok;
 }
 
 }  // namespace
@@ -1211,40 +1398,10 @@ gcme_status gcme_create(const gcme_create_info* info, gcme_handle* out) {
     delete h;
     return fail(nullptr, GCME_EDEVICE, "stream/event creation failed");
   }
-  const size_t N = (size_t)h->N;
-  bool ok = true;
-  for (int k = 0; k < 3; ++k) {
-    ok &= h->a_pos[k].alloc(N * 4) == hipSuccess;
-    ok &= h->b_pos[k].alloc(N * 4) == hipSuccess;
-    ok &= h->a_vel[k].alloc(N * 8) == hipSuccess;
-    ok &= h->b_vel[k].alloc(N * 8) == hipSuccess;
-  }
-  ok &= h->a_param.alloc(N * 4) == hipSuccess;
-  ok &= h->b_param.alloc(N * 4) == hipSuccess;
-  ok &= h->a_id.alloc(N * 4) == hipSuccess;
-  ok &= h->b_pk.alloc(N * 16) == hipSuccess;
-  ok &= h->b_id.alloc(N * 4) == hipSuccess;
-  ok &= h->cell.alloc(N * 4) == hipSuccess;
-  ok &= h->tmp.alloc(N * 4) == hipSuccess;
-  ok &= h->slot_of.alloc(N * 4) == hipSuccess;
-  ok &= h->slot_a.alloc(N * 4) == hipSuccess;
-  ok &= h->dbead_g.alloc(N * 8) == hipSuccess;
-  ok &= h->dbead_q.alloc(N * 8) == hipSuccess;
-  ok &= h->vjp_sorted.alloc(N * 24) == hipSuccess;
-  ok &= h->F.alloc(N * 24) == hipSuccess;
-  ok &= h->d_status.alloc(64) == hipSuccess;
-  ok &= h->d_step.alloc(64) == hipSuccess;
-  ok &= h->d_pairs.alloc(64) == hipSuccess;
-  if (!ok) {
+  if (!alloc_bead_buffers(h, true)) {
     delete h;
     return fail(nullptr, GCME_ENOMEM, "device allocation failed");
   }
-  (void)hipMemsetAsync(h->d_status.p, 0, 64, h->stream);
-  (void)hipMemsetAsync(h->d_step.p, 0, 64, h->stream);
-  (void)hipMemsetAsync(h->F.p, 0, N * 24, h->stream);
-  (void)hipMemsetAsync(h->slot_of.p, 0, N * 4, h->stream);
-  (void)hipMemsetAsync(h->slot_a.p, 0, N * 4, h->stream);
-  (void)hipStreamSynchronize(h->stream);
   *out = h;
   return GCME_OK;
 }
@@ -1537,13 +1694,17 @@ gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe) {
       // re-evaluate at the current positions to fill the outputs
       return gcme_forces_energy(h, observe);
     }
-    return GCME_OK;
+    // no step: capture the graphs a run will replay, if a change of
+    // parameters or tuning dropped them
+    return prepare_graphs(h);
   }
   bool obs = observe != nullptr;
-  if (n_steps > 1 && !h->g_mid) {
-    st = capture(h, true, false, &h->g_mid);
-    if (st != GCME_OK) return st;
-  }
+  // every graph a run of steps replays is captured at the first run after a
+  // change of plan or tuning, whatever that run's length, so that a later
+  // run of any length launches graphs only (capture and instantiation are
+  // host work of milliseconds)
+  st = prepare_graphs(h);
+  if (st != GCME_OK) return st;
   hipGraphExec_t* last = obs ? &h->g_obs : &h->g_last;
   if (!*last) {
     st = capture(h, false, obs, last);
@@ -1558,13 +1719,7 @@ gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe) {
   // long runs replay MID_BATCH steps per graph launch: the host-side cost of a
   // launch (tens of microseconds) is paid once per batch
   int rest = n_steps - 1;
-  if (rest >= MID_BATCH) {
-    if (!h->g_midn) {
-      st = capture(h, true, false, &h->g_midn, MID_BATCH);
-      if (st != GCME_OK) return st;
-    }
-    for (; rest >= MID_BATCH; rest -= MID_BATCH) HIPCHK(h, hipGraphLaunch(h->g_midn, h->stream));
-  }
+  for (; rest >= MID_BATCH; rest -= MID_BATCH) HIPCHK(h, hipGraphLaunch(h->g_midn, h->stream));
   for (int i = 0; i < rest; ++i) HIPCHK(h, hipGraphLaunch(h->g_mid, h->stream));
   HIPCHK(h, hipGraphLaunch(*last, h->stream));
   if (obs) {
@@ -1652,10 +1807,10 @@ gcme_status gcme_count_pairs(gcme_handle h, uint64_t* n_pairs) {
   HIPCHK(h, hipMemsetAsync(h->d_pairs.p, 0, 8, s));
   PairLaunch g = pair_args(h, false);
   g.pair_count = h->d_pairs.as<unsigned long long>();
-  // counting run: forces go to a scratch copy so the state's forces stay valid
-  DevBuf scratch;
-  HIPCHK(h, scratch.alloc((size_t)h->N * 24));
-  for (int k = 0; k < 3; ++k) g.F[k] = scratch.as<long long>() + (size_t)k * h->N;
+  // counting run: forces go to a separate buffer so the state's forces stay valid
+  DevBuf cnt_F;
+  HIPCHK(h, cnt_F.alloc((size_t)h->N * 24));
+  for (int k = 0; k < 3; ++k) g.F[k] = cnt_F.as<long long>() + (size_t)k * h->N;
   launch_nl_build(s, g);
   launch_pair_gcm(s, g, h->fp64, false, false);
   HIPCHK(h, hipGetLastError());
@@ -1901,6 +2056,69 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
   HIPCHK(h, hipMemcpyAsync(h->d_step.p, &stepv, 8, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemsetAsync(h->d_status.p, 0, 4, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  return GCME_OK;
+}
+
+gcme_status gcme_time_stages(gcme_handle h, int32_t n_steps, double* ms) {
+  if (!h || !ms || n_steps < 1) return h ? fail(h, GCME_EINVAL, "n_steps >= 1 and ms required") : GCME_EINVAL;
+  gcme_status st = check_ready(h);
+  if (st != GCME_OK) return st;
+  HIPCHK(h, hipSetDevice(h->device));
+  st = ensure_forces(h);
+  if (st != GCME_OK) return st;
+  // fresh timers: an event left recorded by an earlier call (another
+  // configuration) must not pass for a stage that does not run now
+  for (auto& sv : h->tev)
+    for (auto& e : sv) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+      HIPCHK(h, hipEventCreate(&e));
+    }
+  // a one-step graph (the last-step variant, so every step ends with the
+  // state committed) with the stage timers captured in it
+  hipGraphExec_t ex = nullptr;
+  h->timing = true;
+  h->marked = 0;
+  h->mark_err = hipSuccess;
+  for (int i = 0; i < GCME_N_STAGES; ++i) {
+    h->t_pre[i].clear();
+    h->t_post[i].clear();
+  }
+  st = capture(h, false, false, &ex);
+  h->timing = false;
+  h->marked |= 1u << ST_INT_FIRST;  // timed on the stream, outside the graph
+  if (st != GCME_OK) return st;
+  hipStream_t s = h->stream;
+  double sum[GCME_N_STAGES] = {};
+  int cnt[GCME_N_STAGES] = {};
+  IntLaunch ia = int_args(h);
+  long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < n_steps && err == hipSuccess; ++k) {
+    CellView c = cview(h);
+    err = hipEventRecord(h->tev[ST_INT_FIRST][0], s);
+    launch_int_first(s, ia, viewA(h), F3, &c);
+    if (err == hipSuccess) err = hipEventRecord(h->tev[ST_INT_FIRST][1], s);
+    if (err == hipSuccess) err = hipGraphLaunch(ex, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    // a stage whose kernels this configuration does not launch has no
+    // recorded pair of timers
+    for (int i = 0; i < GCME_N_STAGES && err == hipSuccess; ++i) {
+      if (!(h->marked >> i & 1u)) continue;
+      float m = 0.f;
+      err = hipEventElapsedTime(&m, h->tev[i][0], h->tev[i][1]);
+      if (err != hipSuccess) {
+        (void)hipGraphExecDestroy(ex);
+        return fail(h, GCME_EDEVICE, std::string("stage timer of ") + kStageNames[i] + ": " + hipGetErrorString(err));
+      }
+      sum[i] += (double)m;
+      ++cnt[i];
+    }
+  }
+  (void)hipGraphExecDestroy(ex);
+  HIPCHK(h, err);
+  h->step += (uint64_t)n_steps;
+  for (int i = 0; i < GCME_N_STAGES; ++i) ms[i] = cnt[i] == n_steps ? sum[i] / n_steps : 0.0;
   return GCME_OK;
 }
 

@@ -835,6 +835,17 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
     const float rzi = (float)(int)(mi.z - K.uz[0]) * R.scalef[2];
     const uint32_t self = (uint32_t)(il + 1);
     uint4* ring = s_ring[wave];
+    // Every slot of both ring halves is written before any drain can read
+    // it: in the frame with a record 1e18 away, otherwise with position 0
+    // and parameter word 0 (type 0, a valid table index).  No drain variant
+    // can then read LDS this wave never wrote.
+    {
+      const uint32_t far = __float_as_uint(1e18f);
+      const uint4 init = rel ? make_uint4(far, far, far, 0u) : make_uint4(0u, 0u, 0u, 0u);
+      ring[lane] = init;
+      ring[64 + lane] = init;
+      __builtin_amdgcn_wave_barrier();
+    }
     int head = 0, tail = 0;  // wave-uniform: pairs evaluated / appended
     // evaluate the n <= 64 pending entries from head: lane (il, jl) takes
     // entries jl + k CJ, k < CI.  head is a multiple of 64 here (every drain

@@ -33,6 +33,23 @@ class ReplicaParams:
     bond_b: float = 0.0
 
 
+def c_params(p: ReplicaParams):
+    """The gcme_params struct of p, and the host arrays it points to (keep
+    them alive while the struct is in use)."""
+    nt = len(p.sigma)
+    A = np.ascontiguousarray(np.asarray(p.A, dtype=np.float64).reshape(nt, nt))
+    s = np.ascontiguousarray(p.sigma, dtype=np.float64)
+    a = np.ascontiguousarray(p.a, dtype=np.float64)
+    m = np.ascontiguousarray(p.mass, dtype=np.float64) if p.mass is not None else None
+    dp = C.POINTER(C.c_double)
+    cp = B.gcme_params((C.c_double * 3)(*[float(x) for x in p.box]), float(p.cutoff), float(p.beta),
+                       (C.c_int32 * 3)(*[int(k) for k in p.grid]), int(p.order), float(p.lB), nt,
+                       A.ctypes.data_as(dp), s.ctypes.data_as(dp), a.ctypes.data_as(dp),
+                       m.ctypes.data_as(dp) if m is not None else None, float(p.kT), float(p.dt),
+                       float(p.gamma), int(p.flags), float(p.kmax), float(p.bond_k), float(p.bond_b))
+    return cp, (A, s, a, m)
+
+
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -85,17 +102,7 @@ class GCMe:
 
     # -- setup ------------------------------------------------------------
     def set_params(self, p: ReplicaParams, replica: int = -1):
-        nt = len(p.sigma)
-        A = np.ascontiguousarray(np.asarray(p.A, dtype=np.float64).reshape(nt, nt))
-        s = np.ascontiguousarray(p.sigma, dtype=np.float64)
-        a = np.ascontiguousarray(p.a, dtype=np.float64)
-        m = np.ascontiguousarray(p.mass, dtype=np.float64) if p.mass is not None else None
-        dp = C.POINTER(C.c_double)
-        cp = B.gcme_params((C.c_double * 3)(*[float(x) for x in p.box]), float(p.cutoff), float(p.beta),
-                           (C.c_int32 * 3)(*[int(k) for k in p.grid]), int(p.order), float(p.lB), nt,
-                           A.ctypes.data_as(dp), s.ctypes.data_as(dp), a.ctypes.data_as(dp),
-                           m.ctypes.data_as(dp) if m is not None else None, float(p.kT), float(p.dt),
-                           float(p.gamma), int(p.flags), float(p.kmax), float(p.bond_k), float(p.bond_b))
+        cp, _keep = c_params(p)
         B.check(self.h, self.lib.gcme_set_params(self.h, int(replica), C.byref(cp)))
         for r in (range(self.R) if replica < 0 else [replica]):
             self.params[r] = p
@@ -245,6 +252,13 @@ class GCMe:
         events on the engine's stream (state, forces and mesh restored)."""
         ms = (C.c_double * B.GCME_N_STAGES)()
         B.check(self.h, self.lib.gcme_profile_step(self.h, int(n_reps), ms))
+        return {self.lib.gcme_stage_name(i).decode(): ms[i] for i in range(B.GCME_N_STAGES)}
+
+    def time_stages(self, n_steps: int = 20) -> dict:
+        """Device time (ms) of each stage's kernels inside real steps (HIP
+        event-record nodes in the step graph); takes n_steps steps."""
+        ms = (C.c_double * B.GCME_N_STAGES)()
+        B.check(self.h, self.lib.gcme_time_stages(self.h, int(n_steps), ms))
         return {self.lib.gcme_stage_name(i).decode(): ms[i] for i in range(B.GCME_N_STAGES)}
 
     def autotune(self):

@@ -37,16 +37,18 @@ def oracle_params(w, **over):
     return O.Params(**d)
 
 
-def oracle_eval(w, adjoint=False, kmax=0.0):
+def oracle_eval(w, adjoint=False, kmax=0.0, pos=None, **over):
     """The oracle's forces, energy terms and virial: SPME on the workload's
-    mesh, or with kmax > 0 the exact reciprocal sum over |k| <= kmax."""
-    p = oracle_params(w)
+    mesh, or with kmax > 0 the exact reciprocal sum over |k| <= kmax (at
+    w.pos, or at pos; `over` replaces oracle parameters)."""
+    p = oracle_params(w, **over)
+    pos = w.pos if pos is None else pos
     if kmax > 0:
-        ref = O.forces(w.pos, w.type, w.z, p, recip_mode=O.RECIP_EWALD, kmax=kmax)
+        ref = O.forces(pos, w.type, w.z, p, recip_mode=O.RECIP_EWALD, kmax=kmax)
     else:
-        ref = O.forces(w.pos, w.type, w.z, p, recip_mode=O.RECIP_SPME, K=w.grid, order=w.order)
+        ref = O.forces(pos, w.type, w.z, p, recip_mode=O.RECIP_SPME, K=w.grid, order=w.order)
     if adjoint:
-        rs = O.real_space(w.pos, w.type, w.z, p, adjoint=True)
+        rs = O.real_space(pos, w.type, w.z, p, adjoint=True)
         c = O.constants(w.type, w.z, p)
         ref["Eex_tt"] = rs["Eex_tt"]
         ref["dE_dsigma"] = rs["dE_dsigma"]
@@ -56,6 +58,41 @@ def oracle_eval(w, adjoint=False, kmax=0.0):
 
 def rel_rms(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def per_bead_err(a, b):
+    """Largest per-bead force error, each bead on the scale of its own force
+    or, if smaller, the RMS force: max_i |a_i - b_i| / max(|b_i|, F_rms).
+    A single bead off by a relative e moves this by e, where the norm above
+    moves by e / sqrt(N)."""
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    fr = np.sqrt((b * b).sum(1).mean())
+    d = np.linalg.norm(a - b, axis=1)
+    return float((d / np.maximum(np.linalg.norm(b, axis=1), max(fr, 1e-300))).max())
+
+
+def snap(pos, box):
+    """Positions rounded to the nearest point of the 2^-32 L lattice of each
+    edge, as the engine stores them (wrapped into [0, L))."""
+    L = np.asarray(box, dtype=np.float64)
+    f = np.asarray(pos, dtype=np.float64) / L
+    f -= np.floor(f)
+    u = np.mod(np.rint(f * 4294967296.0), 4294967296.0)
+    return u / 4294967296.0 * L
+
+
+def fp64_force_tol(w, ref=None, pos=None, evaluate=None):
+    """Force tolerance of the FP64 engine on positions off the lattice: the
+    engine computes the forces of the stored (rounded) positions, so its
+    error against the oracle at the given positions is the oracle's own
+    change under that rounding, plus FP64 rounding.  Returns (relative RMS
+    tolerance, per-bead tolerance): twice the oracle's change in each metric
+    plus 1e-12."""
+    pos = w.pos if pos is None else pos
+    evaluate = evaluate or (lambda x: oracle_eval(w, pos=x)["F"])
+    F0 = evaluate(pos) if ref is None else ref
+    F1 = evaluate(snap(pos, w.box))
+    return 2.0 * rel_rms(F1, F0) + 1e-12, 2.0 * per_bead_err(F1, F0) + 1e-12
 
 
 def rel(a, b, floor=1e-12):

@@ -4,13 +4,16 @@ inputs (oracle in SPME-matched mode: same mesh and order).
 Tolerances: FP64 engine -- 1e-9 relative RMS force error and 1e-10 relative
 energy error per term (fixed-point forces at 2^-40, everything else FP64).
 Mixed engine -- the target of the method: 1e-5 relative RMS force error and
-1e-6 relative energy error per term against the FP64 oracle.
+1e-6 relative energy error per term against the FP64 oracle.  Per bead,
+max_i |dF_i| / max(|F_i|, F_rms) is held to ten times the RMS tolerance.
+These inputs lie on the engine's 2^-32 L position lattice; the same checks on
+general positions are in test_gpu_general_inputs.py.
 """
 import numpy as np
 import pytest
 
 import gcme_workloads as W
-from tests.gpu_common import energy_errors, gpu_eval, make_engine, oracle_eval, rel, rel_rms
+from tests.gpu_common import energy_errors, gpu_eval, make_engine, oracle_eval, per_bead_err, rel, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -27,10 +30,13 @@ def _check(w, precision, tuning=None, etol=None):
     if etol is not None:
         et = etol
     ferr = rel_rms(got["force"], ref["F"])
+    fb = per_bead_err(got["force"], ref["F"])
     eerr = energy_errors(got["energy"][0, :5], ref["E"])
     werr = rel_rms(got["virial"][0], ref["W"])
-    print(f"  force {ferr:.2e} energy {np.array2string(eerr, precision=2)} virial {werr:.2e}", flush=True)
+    print(f"  force {ferr:.2e} per-bead {fb:.2e} energy {np.array2string(eerr, precision=2)} virial {werr:.2e}",
+          flush=True)
     assert ferr < ftol
+    assert fb < 10 * ftol
     assert np.all(eerr < et), eerr
     assert werr < max(ftol, et) * 10
     assert got["energy"][0, 5] == pytest.approx(got["energy"][0, :5].sum(), rel=1e-14)
@@ -128,8 +134,10 @@ def test_forces_only_pass_parity(precision, tuning):
     eng.close()
     ref = oracle_eval(w)
     ferr = rel_rms(F, ref["F"])
-    print(f"  force {ferr:.2e}", flush=True)
+    fb = per_bead_err(F, ref["F"])
+    print(f"  force {ferr:.2e} per-bead {fb:.2e}", flush=True)
     assert ferr < TOL[precision][0]
+    assert fb < 10 * TOL[precision][0]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -144,6 +152,9 @@ def test_forces_only_small_boxes(precision):
             eng.sync()
             F = F.cpu().numpy().T
             eng.close()
-            ferr = rel_rms(F, oracle_eval(w)["F"])
-            print(f"case forces-only {w.name} box={w.box} CI={ci} prec={precision}: force {ferr:.2e}", flush=True)
+            Fr = oracle_eval(w)["F"]
+            ferr, fb = rel_rms(F, Fr), per_bead_err(F, Fr)
+            print(f"case forces-only {w.name} box={w.box} CI={ci} prec={precision}: force {ferr:.2e} "
+                  f"per-bead {fb:.2e}", flush=True)
             assert ferr < TOL[precision][0]
+            assert fb < 10 * TOL[precision][0]
