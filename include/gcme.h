@@ -285,6 +285,40 @@ gcme_status gcme_sync(gcme_handle h);
  * Valid until the next call on h. */
 const char* gcme_last_error(gcme_handle h);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * evaluation of gcme_forces_energy for one periodic replica, with the
+ * creation, parameters and state folded into the call and every device
+ * buffer the evaluation needs (sorted state, cell lists, clusters, tables,
+ * charge mesh, partial sums, status) carved from a static device array of
+ * GCME_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds from
+ * the library's load until the process ends.  The call makes no hipMalloc,
+ * hipFree or other device allocation (its host-side planning uses ordinary
+ * host memory); it runs on `stream` (NULL = the null stream) of the current
+ * device and uses the default tuning, with the three parts of the
+ * evaluation in sequence on that stream.
+ *   p       host, as for gcme_set_params (bonds and images are not
+ *           available here)
+ *   n_beads >= 2; precision: gcme_precision
+ *   pos     device [3][n_beads] float64, type and z device int32 [n_beads]
+ *           (as for gcme_set_state)
+ *   force   device [3][n_beads] out, energy device [GCME_N_TERMS] out,
+ *           virial device [6] out; each may be NULL; caller-owned
+ * Synchronous: returns after the outputs are written, with the device
+ * status of gcme_sync (GCME_EOVERFLOW).  GCME_ENOMEM, before any kernel is
+ * launched, when the system needs more scratch than
+ * GCME_NOALLOC_SCRATCH_BYTES (about 140 bytes per bead plus the mesh and
+ * cell tables: some 3e5 beads at a 64^3 mesh); validation errors as for the
+ * calls it folds in.  gcme_last_error(NULL) gives the message.  Every call
+ * on one GPU uses that GPU's one array and leaves its contents behind (the
+ * call clears what it reads before writing it): calls that overlap on one
+ * GPU, from several host threads or on several streams, race and must be
+ * serialised by the caller. */
+#define GCME_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+gcme_status gcme_forces_energy_noalloc(const gcme_params* p, int32_t n_beads, int32_t precision,
+                                       const double* pos, const int32_t* type, const int32_t* z,
+                                       double* force, double* energy, double* virial, void* stream);
+
 /* Tuning knobs picked by the autotuner (exposed for benchmarks and tests).
  * Any field < 0 means "leave as is".  The pair kernels work on clusters of
  * consecutive cell-sorted beads, either with one neighbour list per cluster

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "GCME_OK", 1: "GCME_EINVAL", 2: "GCME_EUNSUPPORTED", 3: "GCME
 EXPORTED = ["gcme_create", "gcme_set_params", "gcme_set_bonds", "gcme_set_images", "gcme_set_state", "gcme_get_state", "gcme_forces_energy",
             "gcme_step", "gcme_sync", "gcme_last_error", "gcme_get_tuning", "gcme_set_tuning",
             "gcme_autotune", "gcme_count_pairs", "gcme_profile_step", "gcme_stage_name", "gcme_destroy",
-            "gcme_time_stages"]
+            "gcme_forces_energy_noalloc", "gcme_time_stages"]
+GCME_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 GCME_N_STAGES = 12
 
 
@@ -95,6 +96,8 @@ def load():
     L.gcme_stage_name.restype = C.c_char_p
     L.gcme_destroy.argtypes = [H]
     L.gcme_destroy.restype = None
+    L.gcme_forces_energy_noalloc.argtypes = [C.POINTER(gcme_params), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     for name in EXPORTED:
         if name not in ("gcme_last_error", "gcme_destroy", "gcme_stage_name"):
             getattr(L, name).restype = C.c_int

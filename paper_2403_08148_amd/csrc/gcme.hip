@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,14 @@
 using namespace gcme;
 
 static_assert(GCME_N_TERMS == N_TERMS, "energy row width");
+
+// The no-alloc entry point's device memory: one static array per GPU,
+// created with the library's code object on that GPU and held until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[GCME_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1340,6 +1349,25 @@ bool alloc_bead_buffers(gcme_handle h, bool derivs) {
   return ok;
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of the current device's scratch (device `dev`).
+gcme_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(nullptr, GCME_EDEVICE, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, GCME_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GCME_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1676,6 +1704,67 @@ gcme_status gcme_forces_energy(gcme_handle h, const gcme_io* io) {
   HIPCHK(h, hipGetLastError());
   h->forces_valid = true;
   return GCME_OK;
+}
+
+gcme_status gcme_forces_energy_noalloc(const gcme_params* p, int32_t n_beads, int32_t precision,
+                                       const double* pos, const int32_t* type, const int32_t* z, double* force,
+                                       double* energy, double* virial, void* stream) {
+  if (!p || !pos || !type || !z) return fail(nullptr, GCME_EINVAL, "params, pos, type and z are required");
+  if (n_beads < 2) return fail(nullptr, GCME_EINVAL, "n_beads must be >= 2");
+  if (precision != GCME_FP64 && precision != GCME_MIXED)
+    return fail(nullptr, GCME_EINVAL, "precision must be GCME_FP64 or GCME_MIXED");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, GCME_EDEVICE, "no current HIP device");
+  void* base = nullptr;
+  gcme_status st = scratch_address(dev, &base);
+  if (st != GCME_OK) return st;
+  // a transient context on the caller's stream: no streams, events or
+  // graphs of its own, every device buffer carved from the scratch
+  gcme_handle h = new gcme_ctx();
+  h->device = dev;
+  h->stream = (hipStream_t)stream;
+  h->R = 1;
+  h->nb.assign(1, n_beads);
+  h->boff.assign(1, 0);
+  h->N = n_beads;
+  h->fp64 = precision == GCME_FP64;
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+      h->lds_max = lds - 4096;
+  }
+  h->hp.assign(1, HostRep{});
+  h->bonds.assign(1, {});
+  h->nq.assign(1, 0);
+  h->qoff.assign(1, 0);
+  Arena arena;
+  arena.base = (char*)base;
+  arena.size = GCME_NOALLOC_SCRATCH_BYTES;
+  t_arena = &arena;
+  if (!alloc_bead_buffers(h, false)) {
+    st = GCME_ENOMEM;
+    h->err = "device buffers";
+  }
+  if (st == GCME_OK) st = gcme_set_params(h, -1, p);
+  if (st == GCME_OK) st = gcme_set_state(h, pos, nullptr, type, z);
+  if (st == GCME_OK) {
+    gcme_io io{};
+    io.force = force;
+    io.energy = energy;
+    io.virial = virial;
+    st = gcme_forces_energy(h, &io);
+  }
+  if (st == GCME_OK) st = gcme_sync(h);
+  t_arena = nullptr;
+  if (st == GCME_ENOMEM && arena.need > 0) {
+    g_create_err = "the evaluation needs " + std::to_string(arena.need) + " bytes of device scratch, more than the " +
+                   std::to_string((size_t)GCME_NOALLOC_SCRATCH_BYTES) +
+                   " of the no-alloc entry point (use a context from gcme_create)";
+  } else if (st != GCME_OK) {
+    g_create_err = h->err;
+  }
+  delete h;
+  return st;
 }
 
 gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe) {
