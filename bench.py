@@ -160,8 +160,9 @@ def main():
                           "pair_interactions_per_s": value, "tuning": tuning}))
         return
 
-    # per-stage device times inside real steps: HIP event-record nodes
-    # around each stage's kernels, on that stage's stream, in the step graph
+    # per-stage device times inside real steps: each one-kernel stage's
+    # execution span in the step graph, from the kernels' own wavefront
+    # start/end stamps
     stages = eng.time_stages(args.timing_steps)
     eng.sync()
     isolated = None
@@ -224,8 +225,9 @@ def main():
     dom = max((k for k in stage_roof if k not in MULTI_KERNEL_STAGES), key=lambda k: stages[k])
     roof = dict(stage_roof[dom])
     roof["launch_us"] = stages[dom] * 1e3
-    roof["launch_us_source"] = (f"mean over {args.timing_steps} steps of HIP event-record nodes around the kernel "
-                                f"in the step graph (gcme_time_stages)")
+    roof["launch_us_source"] = (f"mean over {args.timing_steps} steps of the kernel's execution span in the step "
+                                f"graph: first wavefront start to last wavefront end on the GPU's real-time counter "
+                                f"(gcme_time_stages)")
     prof = profiled_launch_us(dom, tuning, args.workload)
     if prof is not None:
         roof["launch_us_rocprof"] = prof

@@ -382,16 +382,15 @@ const char* gcme_stage_name(int32_t i);
 /* Device time of each stage's kernel inside real steps, as it runs in a
  * step's graph: n_steps >= 1 steps are taken (the state advances as with
  * gcme_step(n_steps)), each the first half on the stream followed by a
- * one-step graph, the step's graph with HIP event-record nodes added around
- * every one-kernel stage (the first after the nodes the kernel waits for
- * and before the kernel, the second after it), so the kernels overlap as
- * in gcme_step's graphs; the host waits for each step and reads the events.
- * ms[i] = the mean elapsed time of stage i over the steps (host array of
- * GCME_N_STAGES; 0 for a stage this configuration does not launch, e.g. the
- * list builds of list-free pairs, and for the sort, which is several
- * kernels; int_first is timed by events on the stream around its kernel;
- * int_last, the plain second half, includes the wait for every branch of
- * the force evaluation).  Synchronous. */
+ * one-step graph (the step's own kernels, so they overlap as in gcme_step's
+ * graphs).  In these launches the first lane of every wavefront records the
+ * GPU's constant-rate real-time counter at the wavefront's start and end;
+ * the host waits for each step and takes, per launch, the first start to
+ * the last end: the launch's execution span.  ms[i] = the mean span of
+ * stage i's kernel over the steps (host array of GCME_N_STAGES; 0 for a
+ * stage this configuration does not launch, e.g. the list builds of
+ * list-free pairs, and for the sort, which is several kernels; int_last is
+ * the plain second half).  Synchronous. */
 gcme_status gcme_time_stages(gcme_handle h, int32_t n_steps, double* ms);
 
 /* Release all device memory and the owned stream. */

@@ -209,22 +209,15 @@ struct gcme_ctx {
   //   g_midn: MID_BATCH consecutive g_mid steps in one graph (one launch)
   hipGraphExec_t g_mid = nullptr, g_midn = nullptr, g_last = nullptr, g_obs = nullptr;
   // stage timers (gcme_time_stages): while `timing` is set, the enqueue
-  // functions record tev[stage][0] before and tev[stage][1] after each
-  // stage's kernels, on that stage's stream (event-record nodes when
-  // captured into a graph)
-  hipEvent_t tev[GCME_N_STAGES][2] = {};
+  // functions hand every one-kernel stage's launch the stamp slots
+  // stamps + 2 stamp_off[stage] (one pair per wavefront, stamp_nw[stage])
   bool timing = false;
-  unsigned marked = 0;  // stages whose graph nodes the timing capture recorded
-  hipError_t mark_err = hipSuccess;  // first failed capture-info query
-  // per stage: the captured nodes its first kernel depends on, and its last
-  // kernel node(s)
-  std::vector<hipGraphNode_t> t_pre[GCME_N_STAGES], t_post[GCME_N_STAGES];
+  DevBuf stamps;
+  size_t stamp_off[GCME_N_STAGES] = {};
+  int stamp_nw[GCME_N_STAGES] = {};
 
   ~gcme_ctx() {
     drop_graphs();
-    for (auto& st : tev)
-      for (auto& e : st)
-        if (e) (void)hipEventDestroy(e);
     for (auto& e : ev_join)
       if (e) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -1012,45 +1005,10 @@ enum {
   ST_FFT_CONV, ST_FFT_Y_INV, ST_GATHER, ST_INT_LAST
 };
 
-// A stage timer mark (only while the context captures its timing graph):
-// the capture's current dependencies on stream s, i.e. before a stage's
-// first kernel the nodes it will depend on, after its last kernel that
-// kernel's node.  Event-record nodes are placed at these points once the
-// capture has ended (add_stage_timers).
-void mark(gcme_handle h, int stage, int end, hipStream_t s) {
-  if (!h->timing) return;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  unsigned long long id = 0;
-  hipGraph_t g = nullptr;
-  const hipGraphNode_t* deps = nullptr;
-  size_t nd = 0;
-  const hipError_t e = hipStreamGetCaptureInfo_v2(s, &cs, &id, &g, &deps, &nd);
-  if (e != hipSuccess || cs != hipStreamCaptureStatusActive) {
-    if (h->mark_err == hipSuccess) h->mark_err = e != hipSuccess ? e : hipErrorStreamCaptureInvalidated;
-    return;
-  }
-  (end ? h->t_post : h->t_pre)[stage].assign(deps, deps + nd);
-  if (end && nd > 0) h->marked |= 1u << stage;
-}
-
-// Event-record nodes around every marked stage of a captured graph: the
-// first timer after the nodes the stage's kernels wait for, and before its
-// kernel (stages of one kernel, whose first kernel is also its last); the
-// second after its last kernel.
-hipError_t add_stage_timers(gcme_handle h, hipGraph_t g) {
-  // the sort stage is several kernels, some of them graph roots: not timed
-  h->marked &= ~(1u << ST_SORT);
-  for (int i = 0; i < GCME_N_STAGES; ++i) {
-    if (!(h->marked >> i & 1u)) continue;
-    hipGraphNode_t n0 = nullptr, n1 = nullptr;
-    const auto& pre = h->t_pre[i];
-    const auto& post = h->t_post[i];
-    hipError_t e = hipGraphAddEventRecordNode(&n0, g, pre.empty() ? nullptr : pre.data(), pre.size(), h->tev[i][0]);
-    if (e == hipSuccess && post.size() == 1) e = hipGraphAddDependencies(g, &n0, &post[0], 1);
-    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&n1, g, post.data(), post.size(), h->tev[i][1]);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+// The stamp slots of a stage's launch while the context times its stages,
+// else null.
+unsigned long long* stamps_for(gcme_handle h, int stage) {
+  return h->timing ? h->stamps.as<unsigned long long>() + 2 * h->stamp_off[stage] : nullptr;
 }
 
 // Sort the state A into B by cell (and the charged copy), on stream s;
@@ -1061,7 +1019,6 @@ void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
   // a step's sort (after the integrator's binning) starts the next step:
   // its scan advances the step counter
   if (!bin) c.step = h->d_step.as<unsigned long long>();
-  mark(h, ST_SORT, 0, s);
   if (bin) launch_bin(s, viewA(h), h->d_rep.as<RepDesc>(), c, h->N);
   if (h->nimages > 0) {
     ImageLaunch im{};
@@ -1075,7 +1032,6 @@ void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
   launch_scan(s, c);
   launch_scatter(s, c, h->N);
   launch_permute(s, viewA(h), viewB(h), h->b_pk.as<uint4>(), c, qview(h), h->N);
-  mark(h, ST_SORT, 1, s);
 }
 
 // Forces (and partial sums if ev) on the sorted copy B; F must be cleared.
@@ -1086,14 +1042,10 @@ void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
 void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   PairLaunch g = pair_args(h, false);
   if (h->NQ == 0) {
-    if (!g.direct) {
-      mark(h, ST_LIST_GCM, 0, s);
-      launch_nl_build(s, g);
-      mark(h, ST_LIST_GCM, 1, s);
-    }
-    mark(h, ST_PAIR_GCM, 0, s);
+    g.stamps = stamps_for(h, ST_LIST_GCM);
+    launch_nl_build(s, g);
+    g.stamps = stamps_for(h, ST_PAIR_GCM);
     launch_pair_gcm(s, g, h->fp64, ev, adj);
-    mark(h, ST_PAIR_GCM, 1, s);
     launch_bonds(s, bond_args(h), viewB(h));
     return;
   }
@@ -1123,48 +1075,34 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   PairLaunch q = pair_args(h, true);
   PmeLaunch p = pme_args(h);
   auto gcm = [&]() {
-    if (!g.direct) {
-      mark(h, ST_LIST_GCM, 0, sg);
-      launch_nl_build(sg, g);
-      mark(h, ST_LIST_GCM, 1, sg);
-    }
-    mark(h, ST_PAIR_GCM, 0, sg);
+    g.stamps = stamps_for(h, ST_LIST_GCM);
+    launch_nl_build(sg, g);
+    g.stamps = stamps_for(h, ST_PAIR_GCM);
     launch_pair_gcm(sg, g, h->fp64, ev, adj);
-    mark(h, ST_PAIR_GCM, 1, sg);
   };
   auto elec = [&]() {
-    if (!q.direct && q.ntiles > 0) {
-      mark(h, ST_LIST_ELEC, 0, sq);
-      launch_nl_build(sq, q);
-      mark(h, ST_LIST_ELEC, 1, sq);
-    }
-    mark(h, ST_PAIR_ELEC, 0, sq);
+    q.stamps = stamps_for(h, ST_LIST_ELEC);
+    launch_nl_build(sq, q);
+    q.stamps = stamps_for(h, ST_PAIR_ELEC);
     launch_pair_elec(sq, q, h->fp64, ev, adj);
-    mark(h, ST_PAIR_ELEC, 1, sq);
   };
   auto mesh = [&]() {
-    const bool meshed = p.ntiles > 0;
-    if (meshed) mark(h, ST_SPREAD, 0, sp);
+    p.stamps = stamps_for(h, ST_SPREAD);
     launch_spread_z(sp, p, h->fp64);
-    if (meshed) mark(h, ST_SPREAD, 1, sp);
     if (h->yx_fused) {
-      if (meshed) mark(h, ST_FFT_CONV, 0, sp);
+      p.stamps = stamps_for(h, ST_FFT_CONV);
       launch_fft_yx_conv(sp, p, h->fp64, ev);
-      if (meshed) mark(h, ST_FFT_CONV, 1, sp);
     } else {
-      if (meshed) mark(h, ST_FFT_Y, 0, sp);
+      p.stamps = stamps_for(h, ST_FFT_Y);
       launch_fft_y(sp, p, h->fp64, false);
-      if (meshed) mark(h, ST_FFT_Y, 1, sp);
-      if (meshed) mark(h, ST_FFT_CONV, 0, sp);
+      p.stamps = stamps_for(h, ST_FFT_CONV);
       launch_fft_x_conv(sp, p, h->fp64, ev);
-      if (meshed) mark(h, ST_FFT_CONV, 1, sp);
-      if (meshed) mark(h, ST_FFT_Y_INV, 0, sp);
+      p.stamps = stamps_for(h, ST_FFT_Y_INV);
       launch_fft_y(sp, p, h->fp64, true);
-      if (meshed) mark(h, ST_FFT_Y_INV, 1, sp);
     }
-    if (meshed) mark(h, ST_GATHER, 0, sp);
+    p.stamps = stamps_for(h, ST_GATHER);
     launch_z_gather(sp, p, h->fp64);
-    if (meshed) mark(h, ST_GATHER, 1, sp);
+    p.stamps = nullptr;
     // replicas with the exact reciprocal sum instead of a mesh
     launch_ewald(sp, ewald_args(h), h->fp64, ev);
     // the slab systems' extra terms (none in bulk)
@@ -1263,12 +1201,11 @@ void enqueue_step_rest(gcme_handle h, hipStream_t s, bool between, bool ev) {
   long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
   enqueue_sort(h, s, false);
   enqueue_forces(h, s, ev, false);
-  mark(h, ST_INT_LAST, 0, s);
+  ia.stamps = stamps_for(h, ST_INT_LAST);
   if (between)
     launch_int_between(s, ia, viewB(h), viewA(h), F3, cview(h));
   else
     launch_int_last(s, ia, viewB(h), viewA(h), F3, ev);
-  mark(h, ST_INT_LAST, 1, s);
 }
 
 gcme_status capture(gcme_handle h, bool between, bool ev, hipGraphExec_t* out, int repeat = 1) {
@@ -1277,13 +1214,6 @@ gcme_status capture(gcme_handle h, bool between, bool ev, hipGraphExec_t* out, i
   for (int k = 0; k < repeat; ++k) enqueue_step_rest(h, h->cap_stream, between, ev);
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (e != hipSuccess) return fail(h, GCME_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-  if (h->timing) {
-    e = h->mark_err != hipSuccess ? h->mark_err : add_stage_timers(h, g);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return fail(h, GCME_EDEVICE, std::string("stage timers: ") + hipGetErrorString(e));
-    }
-  }
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(h, GCME_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -2155,59 +2085,76 @@ gcme_status gcme_time_stages(gcme_handle h, int32_t n_steps, double* ms) {
   HIPCHK(h, hipSetDevice(h->device));
   st = ensure_forces(h);
   if (st != GCME_OK) return st;
-  // fresh timers: an event left recorded by an earlier call (another
-  // configuration) must not pass for a stage that does not run now
-  for (auto& sv : h->tev)
-    for (auto& e : sv) {
-      if (e) (void)hipEventDestroy(e);
-      e = nullptr;
-      HIPCHK(h, hipEventCreate(&e));
+  int khz = 0;
+  HIPCHK(h, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
+  if (khz <= 0) return fail(h, GCME_EDEVICE, "no wall-clock rate");
+  // stamp slots of every one-kernel stage's launch (wavefronts per launch
+  // from the launch shapes; the sort is several kernels and is not timed)
+  auto waves = [&](int i) -> int {
+    const int wpb = pair_waves_per_block();
+    const int nbead_blk = (h->N + BEAD_THREADS - 1) / BEAD_THREADS * (BEAD_THREADS / 64);
+    const bool dg = h->tune.direct_pairs & 1, dq = (h->tune.direct_pairs >> 1) & 1;
+    const bool mesh = h->NQ > 0 && h->nmtiles > 0;
+    switch (i) {
+      case ST_INT_FIRST: return nbead_blk;
+      case ST_LIST_GCM: return dg ? 0 : (h->ncl_g + wpb - 1) / wpb * wpb;
+      case ST_PAIR_GCM: return h->ntiles_g * wpb;
+      case ST_LIST_ELEC: return dq || h->NQ == 0 ? 0 : (h->ncl_q + wpb - 1) / wpb * wpb;
+      case ST_PAIR_ELEC: return h->NQ == 0 ? 0 : h->ntiles_q * wpb;
+      case ST_SPREAD:
+      case ST_GATHER: return mesh ? h->nmtiles * (FFT_THREADS / 64) : 0;
+      case ST_FFT_Y:
+      case ST_FFT_Y_INV: return mesh && !h->yx_fused ? h->nitems[1] * (FFT_THREADS / 64) : 0;
+      case ST_FFT_CONV:
+        return !mesh ? 0 : h->yx_fused ? h->nitems[0] * (YX_THREADS / 64) : h->nitems[2] * (FFT_THREADS / 64);
+      case ST_INT_LAST: return h->ntiles_256 * (256 / 64);
+      default: return 0;
     }
+  };
+  size_t tot = 0;
+  for (int i = 0; i < GCME_N_STAGES; ++i) {
+    h->stamp_off[i] = tot;
+    h->stamp_nw[i] = waves(i);
+    tot += (size_t)h->stamp_nw[i];
+  }
+  HIPCHK(h, h->stamps.alloc(std::max<size_t>(1, tot) * 16));
   // a one-step graph (the last-step variant, so every step ends with the
-  // state committed) with the stage timers captured in it
+  // state committed) whose launches write the stamps
   hipGraphExec_t ex = nullptr;
   h->timing = true;
-  h->marked = 0;
-  h->mark_err = hipSuccess;
-  for (int i = 0; i < GCME_N_STAGES; ++i) {
-    h->t_pre[i].clear();
-    h->t_post[i].clear();
-  }
   st = capture(h, false, false, &ex);
   h->timing = false;
-  h->marked |= 1u << ST_INT_FIRST;  // timed on the stream, outside the graph
   if (st != GCME_OK) return st;
   hipStream_t s = h->stream;
+  std::vector<unsigned long long> hs(2 * std::max<size_t>(1, tot));
   double sum[GCME_N_STAGES] = {};
-  int cnt[GCME_N_STAGES] = {};
   IntLaunch ia = int_args(h);
+  ia.stamps = h->stamps.as<unsigned long long>() + 2 * h->stamp_off[ST_INT_FIRST];
   long long* const F3[3] = {Fk(h, 0), Fk(h, 1), Fk(h, 2)};
   hipError_t err = hipSuccess;
   for (int k = 0; k < n_steps && err == hipSuccess; ++k) {
     CellView c = cview(h);
-    err = hipEventRecord(h->tev[ST_INT_FIRST][0], s);
+    err = hipMemsetAsync(h->stamps.p, 0, tot * 16, s);
     launch_int_first(s, ia, viewA(h), F3, &c);
-    if (err == hipSuccess) err = hipEventRecord(h->tev[ST_INT_FIRST][1], s);
     if (err == hipSuccess) err = hipGraphLaunch(ex, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(hs.data(), h->stamps.p, tot * 16, hipMemcpyDeviceToHost, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
-    // a stage whose kernels this configuration does not launch has no
-    // recorded pair of timers
+    // each stage's span: its first wavefront's start to its last one's end
+    // (a wavefront that leaves early records no end)
     for (int i = 0; i < GCME_N_STAGES && err == hipSuccess; ++i) {
-      if (!(h->marked >> i & 1u)) continue;
-      float m = 0.f;
-      err = hipEventElapsedTime(&m, h->tev[i][0], h->tev[i][1]);
-      if (err != hipSuccess) {
-        (void)hipGraphExecDestroy(ex);
-        return fail(h, GCME_EDEVICE, std::string("stage timer of ") + kStageNames[i] + ": " + hipGetErrorString(err));
+      unsigned long long t0 = ~0ull, t1 = 0;
+      for (int w = 0; w < h->stamp_nw[i]; ++w) {
+        const unsigned long long a0 = hs[2 * (h->stamp_off[i] + w)], a1 = hs[2 * (h->stamp_off[i] + w) + 1];
+        if (a0) t0 = std::min(t0, a0);
+        if (a1) t1 = std::max(t1, a1);
       }
-      sum[i] += (double)m;
-      ++cnt[i];
+      if (t1 > t0 && t0 != ~0ull) sum[i] += (double)(t1 - t0) / (double)khz;
     }
   }
   (void)hipGraphExecDestroy(ex);
   HIPCHK(h, err);
   h->step += (uint64_t)n_steps;
-  for (int i = 0; i < GCME_N_STAGES; ++i) ms[i] = cnt[i] == n_steps ? sum[i] / n_steps : 0.0;
+  for (int i = 0; i < GCME_N_STAGES; ++i) ms[i] = sum[i] / n_steps;
   return GCME_OK;
 }
 

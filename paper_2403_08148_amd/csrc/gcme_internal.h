@@ -208,6 +208,18 @@ __device__ inline void bin_bead(const CellView& c, const RepDesc& R, uint32_t ux
   (void)run_atomic_add(c.qcounts, cid, active && param_z(prm) != 0);
 }
 
+// Execution span of a launch, for the stage timers (null pointer: off):
+// the first lane of every wavefront writes the GPU's constant-rate real-time
+// counter at the wavefront's start (end = 0) and end (end = 1) into slot
+// 2 w + end of st, w the wavefront's index in the grid.  The host takes the
+// first start and the last end over the launch's wavefronts.
+__device__ inline void wave_stamp(unsigned long long* st, int end) {
+  if (st && (threadIdx.x & 63) == 0) {
+    const unsigned w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    st[2 * (size_t)w + end] = wall_clock64();
+  }
+}
+
 // Packed copy of a sorted bead: x, y, z (fractional fixed point), param.
 struct ChargedView {
   uint4* pk;         // charged beads in cell order
@@ -302,6 +314,7 @@ struct PairLaunch {
   unsigned long long* pair_count;  // optional counter
   unsigned int* status;
   double fscale;       // 2^FSHIFT
+  unsigned long long* stamps;  // wave_stamp slots of this launch, or null
 };
 void launch_nl_build(hipStream_t s, const PairLaunch& a);
 void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint);
@@ -339,6 +352,7 @@ struct PmeLaunch {
   unsigned int* status;
   double fscale;      // force fixed-point scale
   double qscale;      // mesh fixed-point scale
+  unsigned long long* stamps;  // wave_stamp slots of this launch, or null
 };
 void launch_spread_z(hipStream_t s, const PmeLaunch& a, bool fp64);
 void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse);
@@ -402,6 +416,7 @@ struct IntLaunch {
                             // so captured steps can be replayed)
   double fscale_inv;
   double* part;             // kinetic partials [ntiles][PART_W]
+  unsigned long long* stamps;  // wave_stamp slots of this launch, or null
 };
 // First half of a step on A (kick, drift, noise; clears F); with bin != NULL
 // also the binning of the new positions (as launch_bin).

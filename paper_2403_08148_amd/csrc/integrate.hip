@@ -79,6 +79,7 @@ __device__ inline void first_half(const IntLaunch& a, const RepDesc& R, int r, i
 template <bool BIN>
 __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* F1, long long* F2, CellView c,
                             int N) {
+  wave_stamp(a.stamps, 0);
   const int s0 = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = s0 < N;
   if (!BIN && !active) return;
@@ -106,6 +107,7 @@ __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* 
     }
   }
   if (BIN) bin_bead(c, R, u[0], u[1], u[2], prm, s, id, active);
+  wave_stamp(a.stamps, 1);
 }
 
 // The second half kick of the step just completed (as k_int_last, on the
@@ -116,6 +118,7 @@ __global__ void k_int_first(IntLaunch a, StateView A, long long* F0, long long* 
 // step at N = 2,097,152).
 __global__ __launch_bounds__(BEAD_THREADS) void k_int_between(IntLaunch a, StateView B, StateView A, long long* F0,
                                                      long long* F1, long long* F2, CellView c, int N) {
+  wave_stamp(a.stamps, 0);
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned long long step = *a.step;
   const bool active = s < N;
@@ -154,6 +157,7 @@ __global__ __launch_bounds__(BEAD_THREADS) void k_int_between(IntLaunch a, State
   // the binning's counts, one atomic per run of equal cells in the wavefront
   (void)run_atomic_add(c.counts, cid, active);
   (void)run_atomic_add(c.qcounts, cid, active && param_z(prm) != 0);
+  wave_stamp(a.stamps, 1);
 }
 
 __device__ inline double block_sum(double v, double* sh) {
@@ -173,6 +177,7 @@ __device__ inline double block_sum(double v, double* sh) {
 template <bool KIN>
 __global__ __launch_bounds__(256) void k_int_last(IntLaunch a, StateView B, StateView A, long long* F0,
                                                   long long* F1, long long* F2) {
+  wave_stamp(a.stamps, 0);
   __shared__ double sh[4];
   const Tile tile = a.tiles[blockIdx.x];
   const bool active = (int)threadIdx.x < tile.count;
@@ -201,6 +206,7 @@ __global__ __launch_bounds__(256) void k_int_last(IntLaunch a, StateView B, Stat
       for (int k = 1; k < PART_W; ++k) a.part[(size_t)blockIdx.x * PART_W + k] = 0.0;
     }
   }
+  wave_stamp(a.stamps, 1);
 }
 
 __global__ void k_forces_out(StateView B, long long* F0, long long* F1, long long* F2, double* out, long long ld,

@@ -410,6 +410,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
   __shared__ int s_sb[NL_WAVES][NL_SEG];
   __shared__ int s_sl[NL_WAVES][NL_SEG];
   __shared__ int s_cand[NL_WAVES][NL_CAND];
+  wave_stamp(a.stamps, 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = blockIdx.x * NL_WAVES + wave;
   if (c >= a.ncl) return;  // whole wavefront; no block barriers below
@@ -440,6 +441,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
     a.count[c] = min(nent, a.cap);
     if (nent > a.cap) atomicOr(a.status, (unsigned)STATUS_LIST_OVERFLOW);
   }
+  wave_stamp(a.stamps, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -737,6 +739,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
   constexpr int CJ = 64 / CI;
   __shared__ double red[NL_WAVES];
   __shared__ Tables<T, ELEC, ADJ> S;
+  wave_stamp(a.stamps, 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Tile tl = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[tl.rep];
@@ -775,6 +778,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
     flush_bead<T, CI, ELEC, ADJ>(a, L, vi, i, param_type(mi.w));
   }
   block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red);
+  wave_stamp(a.stamps, 1);
 }
 
 // List-free pairs: one wavefront per cluster enumerates the candidates of
@@ -795,6 +799,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
   __shared__ int s_sl[NL_WAVES][NL_SEG];
   __shared__ int s_cand[NL_WAVES][NL_CAND];
   __shared__ uint4 s_ring[NL_WAVES][RING];
+  wave_stamp(a.stamps, 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Tile tl = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[tl.rep];
@@ -927,6 +932,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
     flush_bead<T, CI, ELEC, ADJ>(a, L, vi, i, param_type(mi.w));
   }
   block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red);
+  wave_stamp(a.stamps, 1);
 }
 
 template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>

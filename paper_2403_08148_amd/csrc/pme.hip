@@ -320,6 +320,7 @@ __device__ inline const cplx<T>* stage_twiddles(cplx<T>* dst, const PmeLaunch& a
 
 template <typename T>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse) {
+  wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   const LineItem it = a.items[1][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
@@ -340,6 +341,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse)
     const int k = dnl.div(e), l = e - k * nl;
     base[(long long)k * K2h + l] = res[k * LBP + l];
   }
+  wave_stamp(a.stamps, 1);
 }
 
 template <int NT>
@@ -407,6 +409,7 @@ __device__ inline cplx<T> green_apply(const RepDesc& R, const T* gf0, const T* g
 
 template <typename T, bool EV>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
+  wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[4];
   const LineItem it = a.items[2][blockIdx.x];
@@ -449,6 +452,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
       if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
     }
   }
+  wave_stamp(a.stamps, 1);
 }
 
 // y transform, x transform, Green's function (energy, virial), inverse x,
@@ -458,6 +462,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
 // with x interleaved, the x lines with their points consecutive.
 template <typename T, bool EV, int KC>
 __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
+  wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[YX_THREADS / 64];
   const LineItem it = a.items[0][blockIdx.x];
@@ -598,6 +603,7 @@ __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
       if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
     }
   }
+  wave_stamp(a.stamps, 1);
 }
 
 // Inclusive scan of one int per thread over the block (FFT_THREADS).
@@ -704,6 +710,7 @@ __device__ inline int tile_off(int k0, int t0, int K) {
 
 template <typename T, int P>
 __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
+  wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_cs[FFT_THREADS], s_cp[FFT_THREADS], s_tot, scan_sh[FFT_THREADS / 64];
   const MeshTile mt = a.tiles[blockIdx.x];
@@ -804,10 +811,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
     const int lx = dty.div(l), ly = l - lx * TY;
     if (lx < nxt && ly < nyt) out[mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m)] = res[m * LBP + l];
   }
+  wave_stamp(a.stamps, 1);
 }
 
 template <typename T, int P>
 __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
+  wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_cs[FFT_THREADS], s_cp[FFT_THREADS], s_tot, scan_sh[FFT_THREADS / 64];
   const MeshTile mt = a.tiles[blockIdx.x];
@@ -928,6 +937,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
     atomicAdd((unsigned long long*)&a.F[1][bi], (unsigned long long)iv[1]);
     atomicAdd((unsigned long long*)&a.F[2][bi], (unsigned long long)iv[2]);
   });
+  wave_stamp(a.stamps, 1);
 }
 
 template <typename T>
