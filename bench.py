@@ -65,8 +65,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--workload", default="bulk_N32768",
-                    choices=["bulk_N32768", "bulk_N2097152", "slab_nonmetal", "slab_metal"],
-                    help="the slab systems (adsorption study, its size) time the step loop only")
+                    choices=["bulk_N32768", "bulk_N2097152", "slab_nonmetal", "slab_metal",
+                             "polyelectrolyte_slab_nonmetal", "polyelectrolyte_slab_metal"],
+                    help="the slab systems (the adsorption study's size, and the 200,000-bead "
+                         "polyelectrolyte slab) time the step loop only")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the tuning with the library's autotuner (after the warm-up) instead of the "
                          "workload's default tuning")
@@ -110,9 +112,10 @@ def main():
     import gcme_workloads as W
     from paper_2403_08148_amd import GCMe, params_from_workload
 
-    slab = args.workload.startswith("slab")
+    slab = args.workload.startswith("slab") or args.workload.startswith("polyelectrolyte")
     if slab:
-        w = W.paper_slab(metal=args.workload == "slab_metal")
+        metal = args.workload.endswith("_metal")
+        w = W.paper_slab(metal=metal) if args.workload.startswith("slab") else W.polyelectrolyte_slab(metal=metal)
         eng, _ = engine_for([w], args.precision, tune=False)
     else:
         w = W.config2() if args.workload == "bulk_N32768" else W.config4()
@@ -430,11 +433,13 @@ def extra_workloads(w):
     res["kmax"] = w1.kmax
     out[w1.name] = res
 
-    # 6. the adsorption study's slab systems at its size: nonmetal electrodes
-    #    (slab correction, box tripled) and metal electrodes (image charges,
-    #    box doubled), both with bonded chains and fixed electrode lattices
-    for metal in (False, True):
-        ws6 = W.paper_slab(metal=metal)
+    # 6. the adsorption study's slab systems at its size, and the
+    #    200,000-bead polyelectrolyte slab (2,000 chains of 50, counterions,
+    #    solvent): nonmetal electrodes (slab correction, box tripled) and
+    #    metal electrodes (image charges, box doubled), with bonded chains
+    #    and fixed electrode lattices
+    for ws6 in (W.paper_slab(metal=False), W.paper_slab(metal=True), W.polyelectrolyte_slab(metal=False),
+                W.polyelectrolyte_slab(metal=True)):
         res = {"n_beads": ws6.N, "n_mobile": int((ws6.type == 0).sum()), "box": list(ws6.box),
                "grid": list(ws6.grid), "bonds": int(len(ws6.extra["bonds"])),
                "images": int(len(ws6.extra["images"]))}

@@ -274,6 +274,102 @@ def paper_slab(metal=False, x_p=0.05, seed=6):
                        name="slab_metal_images" if metal else "slab_nonmetal_corrected")
 
 
+def polyelectrolyte_slab(metal=False, n_chains=2000, chain_len=50, n_counter=50000, n_solvent=50000, nx=80, ny=92,
+                         seed=3, rc=3.0, beta=1.1, grid_xy=96, order=5, on_lattice=True):
+    """The polyelectrolyte slab of the adsorption study at the size of the
+    200,000-bead configuration: n_chains linear chains of chain_len beads in
+    which every other bead (the first, third, ...) carries +1, joined by
+    harmonic bonds (k = 100, b = 0.8); n_counter counterions at -1 and
+    n_solvent neutral beads; all electrolyte beads a = sigma = 0.5 with
+    A = 25 (one species, as in the study).  The electrolyte fills
+    Lx x Ly x h at rho = 2.5 between two electrode lattices of fixed beads
+    (type 1, a = sigma = 0.25, neutral, triangular lattice of spacing 0.5:
+    nx sites per row, ny rows, Lx = 0.5 nx = 40, Ly = 0.5 ny sqrt(3)/2 =
+    39.84), h = N_e / (2.5 Lx Ly).  Chains are random walks of step 0.8
+    inside the slab.  Nonmetal electrodes: planes at z = 0.5 and h + 0.5,
+    box tripled along z (H = h + 1, Lz = 3H) for the slab correction, mesh
+    grid_xy^2 x 384 (spacing about 0.4).  Metal electrodes: planes at z = 0
+    and H, box 2H long with one image bead (type 2: infinite mass, no
+    excluded volume, opposite charge) per charged bead at its reflection
+    (x, y, -z), mesh grid_xy^2 x 256.  rc = 3, beta = 1.1, order 5."""
+    rng = np.random.default_rng(seed)
+    sp = 0.5
+    Lx, Ly = sp * nx, sp * ny * math.sqrt(3.0) / 2.0
+    n_mono = n_chains * chain_len
+    n_e = n_mono + n_counter + n_solvent
+    h = n_e / (DENSITY * Lx * Ly)
+    H = h + 1.0
+    Lz = 2.0 * H if metal else 3.0 * H
+    box = (Lx, Ly, Lz)
+    z_el = (0.0, H) if metal else (0.5, h + 0.5)
+    ex, ey = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    ex = (ex + 0.5 * (ey % 2)) * sp
+    ey = ey * sp * math.sqrt(3.0) / 2.0
+    plane = np.c_[ex.ravel(), ey.ravel()]
+    elec = np.vstack([np.c_[plane, np.full(len(plane), z_el[0])], np.c_[plane, np.full(len(plane), z_el[1])]])
+    zlo, zhi = z_el[0] + 0.3, z_el[1] - 0.3
+    # chains: random walks of step 0.8 reflected at the slab faces
+    start = np.c_[rng.uniform(0, Lx, n_chains), rng.uniform(0, Ly, n_chains), rng.uniform(zlo, zhi, n_chains)]
+    steps = rng.standard_normal((n_chains, chain_len - 1, 3))
+    steps *= 0.8 / np.linalg.norm(steps, axis=2, keepdims=True)
+    mono = np.empty((n_chains, chain_len, 3))
+    mono[:, 0] = start
+    for m in range(1, chain_len):
+        x = mono[:, m - 1] + steps[:, m - 1]
+        zz = x[:, 2]
+        zz = np.where(zz < zlo, 2 * zlo - zz, zz)
+        zz = np.where(zz > zhi, 2 * zhi - zz, zz)
+        x[:, 2] = zz
+        mono[:, m] = x
+    mono = mono.reshape(-1, 3)
+    free = np.c_[rng.uniform(0, Lx, n_counter + n_solvent), rng.uniform(0, Ly, n_counter + n_solvent),
+                 rng.uniform(zlo, zhi, n_counter + n_solvent)]
+    pos = np.vstack([mono, free, elec])
+    pos[:, 0] %= Lx
+    pos[:, 1] %= Ly
+    if on_lattice:
+        pos = lattice_positions(pos / np.asarray(box), box)
+    N = len(pos)
+    typ = np.zeros(N, dtype=np.int32)
+    typ[n_e:] = 1
+    z = np.zeros(N, dtype=np.int32)
+    z[:n_mono][np.arange(n_mono) % chain_len % 2 == 0] = 1
+    z[n_mono:n_mono + n_counter] = -1
+    assert z.sum() == 0, "chain charges and counterions must balance"
+    mass = np.array([1.0, np.inf])
+    a = np.array([0.5, 0.25])
+    Am = np.full((2, 2), 25.0)
+    images = np.zeros((0, 2), dtype=np.int32)
+    if metal:
+        src = np.nonzero(z)[0]
+        if on_lattice:
+            u = np.round(pos[src] / np.asarray(box) * 4294967296.0)
+            u[:, 2] = np.mod(4294967296.0 - u[:, 2], 4294967296.0)
+            ipos = u / 4294967296.0 * np.asarray(box)
+        else:
+            ipos = pos[src].copy()
+            ipos[:, 2] = np.mod(-ipos[:, 2], box[2])
+        images = np.c_[np.arange(N, N + len(src)), src].astype(np.int32)
+        pos = np.vstack([pos, ipos])
+        typ = np.r_[typ, np.full(len(src), 2)].astype(np.int32)
+        z = np.r_[z, -z[src]].astype(np.int32)
+        N = len(pos)
+        mass = np.array([1.0, np.inf, np.inf])
+        a = np.array([0.5, 0.25, 0.5])
+        Am = np.zeros((3, 3))
+        Am[:2, :2] = 25.0
+    vel = np.zeros((N, 3))
+    mob = typ == 0
+    vel[mob] = _velocities(rng, int(mob.sum()), np.ones(int(mob.sum())), 1.0)
+    c = np.arange(n_chains)[:, None] * chain_len + np.arange(chain_len - 1)[None, :]
+    bonds = np.c_[c.ravel(), c.ravel() + 1].astype(np.int32)
+    grid = (grid_xy, grid_xy, 256 if metal else 384)
+    return Workload("polyelectrolyte_slab_metal" if metal else "polyelectrolyte_slab_nonmetal", pos, typ, z, vel, box,
+                    rc, beta, 1.0, Am, a.copy(), a.copy(), grid, order, 0.02, 1.0, 1.0, mass, seed,
+                    extra=dict(bonds=bonds, bond_k=100.0, bond_b=0.8, slab=not metal, fixed_type=1, images=images,
+                               n_electrolyte=n_e))
+
+
 def config4(on_lattice=True):
     """Large bulk: N = 2^21, three species a = 0.3/0.5/0.7, A ~ U(15, 35)
     symmetric (seeded), 15% charged, rc = 2.5, beta = 1.2, SPME 256^3."""

@@ -1,16 +1,26 @@
-"""Equation of state of the neutral GCM fluid from the engine's own MD: a
-physics check of the excluded-volume forces and virial at scale.
+"""Equation of state of the neutral GCM fluid from the engine's own MD
+(section "Parametrization": eq. pres_virial, eq. pres_approx and Fig.
+water_p_excess_vs_rho): a physics check of the excluded-volume forces and
+virial at scale.
 
-The excess pressure of Gaussian cores approaches its mean-field value
-(rho^2/2) times the integral of u_ex, that is A rho^2 / 2 (eq. u_ex is a
-normalised Gaussian times A), from below as the density grows: the paper's
-parametrisation section finds omega = (p - rho kT)/(A rho^2) levelling off at
-0.499 at large rho, with rho = 2.5 near the start of the plateau.  The
-correlation hole that keeps omega below 1/2 (a potential with a positive
-Fourier transform lowers g(r) where u is large) shrinks as the density grows.
-Measured here: omega = 0.470 at rho = 2.5 and 0.491 at rho = 5.  A wrong virial
-prefactor or a missing pair class would move omega by tens of percent.
+omega = (p - rho kT)/(A rho^2), with the excess pressure from the virial,
+<sum_pairs r_ij . f_ij>/(3V) (eq. pres_virial; the ideal part rho kT is the
+thermostat's, so the kinetic temperature's O(dt^2) BAOAB bias does not
+enter).
+
+* Parity: at four (rho, A) state points omega equals the FP64 oracle's own
+  MD value (tests/golden/eos_oracle.json, written by eos_oracle.py beside
+  it) within 5 combined standard errors.
+* The scan over rho = 2..6 and A = 15, 25, 35: omega stays below the
+  mean-field value 1/2 (A rho^2/2 is the excess pressure of uncorrelated
+  beads: eq. u_ex integrates to A) and rises towards it with rho and with
+  A; at fixed rho the excess pressure over A is one master curve, within
+  2% across A (Fig. water_p_excess_vs_rho a); at rho = 6 omega is within 2%
+  of the paper's large-rho plateau 0.499 (Fig. water_p_excess_vs_rho b).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -19,40 +29,64 @@ from tests.gpu_common import make_engine
 
 pytestmark = pytest.mark.gpu
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "eos_oracle.json")
+PAPER_PLATEAU = 0.499  # Fig. water_p_excess_vs_rho b, section "Parametrization"
 
-def _omega(rho, N=4000, A=25.0, kT=1.0, seed=31):
+
+def _omega(rho, A, precision="mixed", proto=None):
+    """omega and its block error by the oracle reference's protocol."""
+    pr = proto or json.load(open(GOLDEN))["protocol"]
+    N = pr["N"]
     L = (N / rho) ** (1.0 / 3.0)
-    w = W.small_bulk(N=N, seed=seed, charged_frac=0.0, a_types=(0.5,), A=[[A]], rc=3.0, grid=(16, 16, 16),
-                     box=(L, L, L))
+    w = W.small_bulk(N=N, seed=pr["seed"], charged_frac=0.0, a_types=(pr["a"],), A=[[A]], rc=pr["rc"],
+                     grid=(16, 16, 16), box=(L, L, L))
     V = L ** 3
-    eng = make_engine([w], "mixed", seed=7)
-    eng.step(600)
+    eng = make_engine([w], precision, seed=pr["noise_seed"])
+    eng.step(pr["equil"])
     eng.sync()
-    p, T = [], []
-    for _ in range(60):
-        obs = eng.step(25, observe=True)
+    om, T = [], []
+    for _ in range(pr["nobs"]):
+        obs = eng.step(pr["gap"], observe=True)
         eng.sync()
-        E = obs["energy"].cpu().numpy()[0]
         Wv = obs["virial"].cpu().numpy()[0]
-        kin = E[6]
-        p.append((2.0 * kin / 3.0 + (Wv[0] + Wv[1] + Wv[2]) / 3.0) / V)
-        T.append(2.0 * kin / (3.0 * N))
+        om.append((Wv[0] + Wv[1] + Wv[2]) / (3.0 * V) / (A * rho * rho))
+        T.append(2.0 * obs["energy"].cpu().numpy()[0][6] / (3.0 * N))
     eng.close()
-    p, T = np.array(p), np.array(T)
-    omega = (p.mean() - rho * kT) / (A * rho * rho)
-    err = p.std(ddof=1) / np.sqrt(len(p)) / (A * rho * rho)
-    print(f"  rho = {rho}: <T> = {T.mean():.4f}  omega = {omega:.5f} +- {err:.5f}", flush=True)
-    return omega, T.mean()
+    om = np.array(om)
+    blocks = om.reshape(pr["blocks"], -1).mean(1)
+    return float(om.mean()), float(blocks.std(ddof=1) / np.sqrt(pr["blocks"])), float(np.mean(T))
 
 
-def test_gcm_equation_of_state():
-    print("case GCM EOS, A = 25, a = sigma = 0.5, N = 4000", flush=True)
-    w25, t25 = _omega(2.5)
-    w50, t50 = _omega(5.0)
-    assert abs(t25 - 1.0) < 0.02 and abs(t50 - 1.0) < 0.02
-    # below the mean-field value, rising towards it with the density
-    assert 0.45 < w25 < w50 < 0.5
-    assert 0.5 - w50 < 0.015
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_gcm_eos_matches_oracle_md(precision):
+    ref = json.load(open(GOLDEN))
+    print(f"case GCM EOS against the oracle's MD, prec={precision}", flush=True)
+    for st in ref["states"]:
+        om, err, T = _omega(st["rho"], st["A"], precision, ref["protocol"])
+        tol = 5.0 * np.hypot(err, st["err"])
+        print(f"  A {st['A']:.0f} rho {st['rho']}: engine {om:.5f} +- {err:.5f}, oracle {st['omega']:.5f} +- "
+              f"{st['err']:.5f}; <T> {T:.4f}", flush=True)
+        assert abs(om - st["omega"]) < tol
+        assert abs(T - 1.0) < 0.03
+
+
+def test_gcm_eos_density_scan():
+    print("case GCM EOS scan, rho 2..6, A 15/25/35", flush=True)
+    rhos, As = (2.0, 2.5, 3.0, 4.0, 5.0, 6.0), (15.0, 25.0, 35.0)
+    om = np.zeros((len(As), len(rhos)))
+    er = np.zeros_like(om)
+    for a, A in enumerate(As):
+        for r, rho in enumerate(rhos):
+            om[a, r], er[a, r], _ = _omega(rho, A)
+            print(f"  A {A:.0f} rho {rho}: omega {om[a, r]:.5f} +- {er[a, r]:.5f}", flush=True)
+    assert np.all(om < 0.5)
+    assert np.all(np.diff(om, axis=1) > 0)          # rises with rho
+    assert np.all(np.diff(om, axis=0) > 0)          # and with A
+    excess_over_A = om * np.asarray(rhos) ** 2      # (p - rho kT)/A
+    spread = excess_over_A.max(0) / excess_over_A.min(0) - 1.0
+    print(f"  master curve: largest spread over A {spread.max():.4f}", flush=True)
+    assert np.all(spread < 0.02)
+    assert np.all(np.abs(om[:, -1] / PAPER_PLATEAU - 1.0) < 0.02)
 
 
 def test_gcm_rdf_first_peak():

@@ -51,7 +51,7 @@ def _oracle(w, pos=None, slab=True, bonds=True):
                         recip_mode=O.RECIP_SPME, K=w.grid, order=w.order)
 
 
-def _compare(E, F, Wv, ref, precision, tag):
+def _compare(E, F, Wv, ref, precision, tag, slab_tol=1e-12):
     ftol, et = TOL[precision]
     ferr = rel_rms(F, ref["F"])
     eerr = energy_errors(E[:5], ref["E"][:5])
@@ -64,7 +64,7 @@ def _compare(E, F, Wv, ref, precision, tag):
     assert np.all(eerr < et), eerr
     # both terms are summed in float64 from the fixed-point positions in
     # either precision
-    assert es < 1e-12 and eb < 1e-12
+    assert es < slab_tol and eb < 1e-12
     assert werr < max(ftol, et) * 10
     assert E[5] == pytest.approx(E[:5].sum() + E[7] + E[8], rel=1e-14)
 
@@ -295,3 +295,51 @@ def test_sparse_image_half_steps(precision):
     got = gpu_eval(eng)
     eng.close()
     _compare(got["energy"][0], got["force"], got["virial"][0], _oracle(w, pos=pos), precision, "after 30 steps")
+
+
+@pytest.fixture(scope="module", params=[False, True], ids=["nonmetal", "metal"])
+def polyelectrolyte_200k(request):
+    # the 200,000-bead polyelectrolyte slab (2,000 chains of 50, 50,000
+    # counterions, 50,000 solvent) between electrode lattices: slab
+    # correction in a tripled box, or image charges in a doubled one
+    w = W.polyelectrolyte_slab(metal=request.param)
+    print(f"case {w.name} N={w.N} box={w.box} grid={w.grid} bonds={len(w.extra['bonds'])} "
+          f"images={len(w.extra['images'])}", flush=True)
+    ref = _oracle(w)
+    print("  oracle done", flush=True)
+    return w, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_polyelectrolyte_slab_200k(polyelectrolyte_200k, precision):
+    """Every force, energy term and the virial of the 200,000-bead
+    polyelectrolyte slab against the oracle, both electrode kinds."""
+    from tests.gpu_common import per_bead_err
+    w, ref = polyelectrolyte_200k
+    eng = _engine([w], precision)
+    got = gpu_eval(eng)
+    eng.close()
+    fb = per_bead_err(got["force"], ref["F"])
+    print(f"  {precision}: per-bead {fb:.2e}", flush=True)
+    assert fb < 10 * TOL[precision][0]
+    # the engine sums the slab's dipole M_z = sum z_i zeta_i exactly (integer
+    # fixed point); the oracle adds its N signed terms in FP64, with a
+    # rounding of at most gamma_N sum |z_i zeta_i| (gamma_N = N u / (1 - N u),
+    # u = 2^-53), and E ~ M_z^2 doubles the relative error
+    slab_tol = 1e-12
+    if w.extra.get("slab"):
+        import math
+        zeta = np.mod(w.pos[:, 2], w.box[2])
+        q = np.nonzero(w.z)[0]
+        Mz = math.fsum((w.z[q] * zeta[q]).tolist())  # correctly rounded
+        n, u = len(q), 2.0 ** -53
+        slab_tol = max(slab_tol, 2.0 * n * u / (1.0 - n * u) * float(np.sum(np.abs(zeta[q]))) / abs(Mz))
+        E_exact = 2.0 * math.pi * w.lB * Mz * Mz / float(np.prod(w.box))
+        e_eng = abs(got["energy"][0][7] - E_exact) / E_exact
+        e_ora = abs(ref["E"][5] - E_exact) / E_exact
+        print(f"  slab energy against the correctly rounded definition: engine {e_eng:.2e}, oracle {e_ora:.2e} "
+              f"(oracle's summation bound {slab_tol:.2e})", flush=True)
+        assert e_eng < 2e-12
+        assert e_ora < slab_tol
+    _compare(got["energy"][0], got["force"], got["virial"][0], ref, precision, f"{w.name} {precision}",
+             slab_tol=slab_tol)
