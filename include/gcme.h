@@ -52,7 +52,13 @@ typedef enum {
     GCME_ESTATE = 5,        /* call order (e.g. forces before params/state) */
     GCME_EDEVICE = 6,       /* HIP runtime error */
     GCME_ENOMEM = 7,        /* device allocation failed */
-    GCME_EOVERFLOW = 8      /* fixed-point force/charge accumulator would overflow */
+    GCME_EOVERFLOW = 8      /* fixed-point force accumulator would overflow, or a
+                               neighbour list is full.  The mixed-precision charge
+                               mesh is not checked: a point holds +-128 unit
+                               charges (32-bit integers at 2^-24), reached only
+                               if several hundred unit charges of one sign
+                               (300 at order 3, 600 at order 5) crowd into the
+                               p^3 mesh cells around it */
 } gcme_status;
 
 typedef enum {
@@ -275,8 +281,7 @@ gcme_status gcme_step(gcme_handle h, int32_t n_steps, const gcme_io* observe);
 
 /* Wait for the context's stream and report device-side status: a force
  * that would overflow the 64-bit fixed-point accumulator of eq. ewald's
- * force sum, a charge-mesh point beyond its fixed-point range, or a full
- * neighbour list -> GCME_EOVERFLOW (the outputs of the calls since the last
+ * force sum, or a full neighbour list -> GCME_EOVERFLOW (the outputs of the calls since the last
  * gcme_sync are then invalid); runtime errors -> GCME_EDEVICE.  The status
  * is cleared once reported. */
 gcme_status gcme_sync(gcme_handle h);

@@ -1760,7 +1760,6 @@ gcme_status gcme_sync(gcme_handle h) {
     HIPCHK(h, hipMemset(h->d_status.p, 0, 4));
     if (st & STATUS_LIST_OVERFLOW)
       return fail(h, GCME_EOVERFLOW, "neighbour list capacity exceeded (raise gcme_tuning.list_slack_pct)");
-    if (st & STATUS_MESH_OVERFLOW) return fail(h, GCME_EOVERFLOW, "fixed-point charge mesh overflow");
     if (st & STATUS_SLOT_MAP)
       return fail(h, GCME_EDEVICE, "a bond or image named a bead the sort did not place (inconsistent state)");
     return fail(h, GCME_EOVERFLOW, "fixed-point force accumulator overflow (forces too large)");

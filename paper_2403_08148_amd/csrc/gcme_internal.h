@@ -131,7 +131,14 @@ constexpr int N_TERMS = 9;
 // Device status bits.
 // STATUS_SLOT_MAP: a bond or image named a bead the sort did not place
 // (inconsistent cell counts); the term was skipped.
-enum { STATUS_FORCE_OVERFLOW = 1, STATUS_MESH_OVERFLOW = 2, STATUS_LIST_OVERFLOW = 4, STATUS_SLOT_MAP = 8 };
+// The charge mesh has no status bit: in single precision a point is summed
+// in 32-bit integers at 2^-24 of a unit charge (range +-128 unit charges);
+// it collects z_i w_x w_y w_z from the beads within p mesh cells, each
+// weight product at most (max M_p)^3 (0.42 for p = 3, 0.22 for p = 5), so
+// it wraps only if several hundred unit charges of one sign crowd into a
+// p^3-cell neighbourhood (300 at p = 3, 600 at p = 5).
+// Double precision sums in 64 bits at 2^-40 (range 2^23 unit charges).
+enum { STATUS_FORCE_OVERFLOW = 1, STATUS_LIST_OVERFLOW = 4, STATUS_SLOT_MAP = 8 };
 
 // Bead parameter word: bits 0..7 type, 8..15 charge (int8), 16..31 replica.
 __host__ __device__ inline uint32_t pack_param(int t, int z, int rep) {
