@@ -2105,7 +2105,9 @@ gcme_status gcme_time_stages(gcme_handle h, int32_t n_steps, double* ms) {
       case ST_FFT_Y:
       case ST_FFT_Y_INV: return mesh && !h->yx_fused ? h->nitems[1] * (FFT_THREADS / 64) : 0;
       case ST_FFT_CONV:
-        return !mesh ? 0 : h->yx_fused ? h->nitems[0] * (YX_THREADS / 64) : h->nitems[2] * (FFT_THREADS / 64);
+        return !mesh ? 0
+               : h->yx_fused ? h->nitems[0] * (pme_plane_threads(h->plane_elems) / 64)
+                             : h->nitems[2] * (FFT_THREADS / 64);
       case ST_INT_LAST: return h->ntiles_256 * (256 / 64);
       default: return 0;
     }

@@ -12,6 +12,7 @@ constexpr int NSER = 14;          // small-r series terms stored per type pair
 constexpr int TILE = 256;         // beads per tile of the per-bead kernels
 constexpr int FFT_THREADS = 256;  // threads of a mesh-line work item
 constexpr int YX_THREADS = 1024;  // threads of a fused y/x plane work item
+constexpr int YX_SMALL_THREADS = 256;  // the same for planes up to 48 x 48
 
 // Fixed-point scales (log2) of the force and charge-mesh accumulators.
 constexpr int FSHIFT_MIXED = 32;
@@ -366,6 +367,8 @@ void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse);
 void launch_fft_x_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev);
 void launch_fft_yx_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev);
 size_t pme_plane_lds_bytes(int plane_elems, int maxK0, int maxK1, int maxK2, bool fp64);
+// threads of a fused y/x plane workgroup for planes of plane_elems entries
+int pme_plane_threads(int plane_elems);
 void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64);
 size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64);
 

@@ -460,11 +460,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
 // whose K0 x K1 plane fits twice in a workgroup's LDS).  The plane stays in
 // one layout, (y, x) at y*LY + x (LY = K0 + 1): the y lines are transformed
 // with x interleaved, the x lines with their points consecutive.
-template <typename T, bool EV, int KC>
-__global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
+template <typename T, bool EV, int KC, int NT>
+__global__ __launch_bounds__(NT) void k_fft_yx_conv(PmeLaunch a) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double sh[YX_THREADS / 64];
+  __shared__ double sh[NT / 64];
   const LineItem it = a.items[0][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
   // KC > 0: every replica's plane is KC x KC (compile-time transforms)
@@ -473,7 +473,6 @@ __global__ __launch_bounds__(YX_THREADS) void k_fft_yx_conv(PmeLaunch a) {
   const int LY = K0 + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.plane_elems;
-  constexpr int NT = YX_THREADS;
   cplx<T>* twx = B + (size_t)a.plane_elems;
   cplx<T>* twy = twx + a.maxK[2];
   // per-axis Green's function factors and frequencies of this replica
@@ -1032,25 +1031,35 @@ void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse) {
   }
 }
 
+int pme_plane_threads(int plane_elems) {
+  // planes up to 48 x 48 (49 x 49 with padding; the small meshes of batched
+  // replicas) have few butterflies per stage: four wavefronts per plane, so
+  // that four planes share a compute unit instead of one plane's sixteen
+  // mostly idle wavefronts
+  return plane_elems <= 49 * 49 ? YX_SMALL_THREADS : YX_THREADS;
+}
+
 size_t pme_plane_lds_bytes(int plane_elems, int maxK0, int maxK1, int maxK2, bool fp64) {
   // two plane buffers, x and y twiddles, then six per-axis real tables
   return (2 * (size_t)plane_elems + maxK0 + maxK1) * (fp64 ? 16 : 8) + 2 * (size_t)(maxK0 + maxK1 + maxK2) * (fp64 ? 8 : 4);
 }
 
-template <typename T, bool EV, int KC>
+template <typename T, bool EV, int KC, int NT>
 void fft_yx_conv_k(hipStream_t s, const PmeLaunch& a, size_t sh) {
-  allow_lds((const void*)k_fft_yx_conv<T, EV, KC>, sh);
-  hipLaunchKernelGGL((k_fft_yx_conv<T, EV, KC>), dim3(a.nitems[0]), dim3(YX_THREADS), sh, s, a);
+  allow_lds((const void*)k_fft_yx_conv<T, EV, KC, NT>, sh);
+  hipLaunchKernelGGL((k_fft_yx_conv<T, EV, KC, NT>), dim3(a.nitems[0]), dim3(NT), sh, s, a);
 }
 
 template <typename T, bool EV>
 void fft_yx_conv_t(hipStream_t s, const PmeLaunch& a, size_t sh) {
   if (a.plane_k == 64)
-    fft_yx_conv_k<T, EV, 64>(s, a, sh);
+    fft_yx_conv_k<T, EV, 64, YX_THREADS>(s, a, sh);
   else if (a.plane_k == 32)
-    fft_yx_conv_k<T, EV, 32>(s, a, sh);
+    fft_yx_conv_k<T, EV, 32, YX_SMALL_THREADS>(s, a, sh);
+  else if (pme_plane_threads(a.plane_elems) == YX_SMALL_THREADS)
+    fft_yx_conv_k<T, EV, 0, YX_SMALL_THREADS>(s, a, sh);
   else
-    fft_yx_conv_k<T, EV, 0>(s, a, sh);
+    fft_yx_conv_k<T, EV, 0, YX_THREADS>(s, a, sh);
 }
 
 void launch_fft_yx_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev) {
