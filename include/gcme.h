@@ -353,6 +353,15 @@ typedef struct {
                                     5: the mesh chain then the charged pairs on
                                        the context's stream, the
                                        excluded-volume pairs on a second one */
+    int32_t mesh_tile_x;         /* z lines per mesh tile of the fused spread */
+    int32_t mesh_tile_y;         /* pass along x and y (1..16; 0 = 4): a bead's
+                                    B-splines are evaluated once per tile its
+                                    stencil meets, so larger tiles evaluate them
+                                    fewer times but hold more LDS, and fewer
+                                    workgroups fit a compute unit (halved along
+                                    the longer side until they fit) */
+    int32_t gather_tile_x;       /* the same for the fused gather pass (0 = the */
+    int32_t gather_tile_y;       /* spread's) */
 } gcme_tuning;
 
 gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t);

@@ -150,7 +150,7 @@ struct gcme_ctx {
   std::vector<int> nq, qoff;
   int NQ = 0;
   // tuning
-  gcme_tuning tune{3, 8, 4, 50, 3, 0};  // list-free pairs, three stream branches
+  gcme_tuning tune{3, 8, 4, 50, 3, 0, 0, 0, 0, 0};  // list-free pairs, three stream branches, 4 x 4 mesh tiles
   bool plan_dirty = true;
   // device buffers
   DevBuf a_pos[3], a_vel[3], a_param, a_id;
@@ -158,7 +158,7 @@ struct gcme_ctx {
   DevBuf cell, tmp, counts, qcounts, fill, start, qstart, bsum;
   DevBuf b_pk, q_pk, q_idx;
   DevBuf F;
-  DevBuf Qc, d_mtiles;
+  DevBuf Qc, d_mtiles, d_gtiles;
   DevBuf d_rep, d_gcm, d_elec, d_adj;
   DevBuf d_tw, d_rad, d_bsp, d_freq;
   DevBuf d_items[3];
@@ -192,7 +192,8 @@ struct gcme_ctx {
   long long grid_total = 0, cgrid_total = 0;
   int ncl_g = 0, ncl_q = 0, ntiles_g = 0, ntiles_q = 0, ntiles_256 = 0;
   int cap_g = 64, cap_q = 64;
-  int nmtiles = 0, mtx = 4, mty = 4;
+  int nmtiles = 0, mtx = 4, mty = 4;     // spread tiles
+  int ngtiles = 0, gtx = 4, gty = 4;     // gather tiles
   bool yx_fused = false;  // y and x passes in one LDS plane kernel
   int plane_elems = 0;
   int lds_max = 65536;  // dynamic LDS a workgroup may use
@@ -622,27 +623,40 @@ gcme_status build_plan(gcme_handle h) {
     }
     item_off[R] = (int)items[0].size();
   }
-  // mesh tiles of the fused spread / gather passes: 4 x 4 z lines, fewer if
-  // the two LDS line buffers would not fit
-  h->mtx = 4;
-  h->mty = 4;
-  while (h->mtx * h->mty > 1 && pme_tile_lds_bytes(h->maxK[0], h->mtx, h->mty, h->fp64) > (size_t)h->lds_max) {
-    if (h->mtx >= h->mty)
-      h->mtx /= 2;
-    else
-      h->mty /= 2;
-  }
-  if (pme_tile_lds_bytes(h->maxK[0], h->mtx, h->mty, h->fp64) > (size_t)h->lds_max)
+  // mesh tiles of the fused spread and gather passes, each with its own
+  // shape: the tuning's z lines per tile (4 x 4 by default; the gather's
+  // default is the spread's), halved along the longer side while the two
+  // LDS line buffers would not fit
+  auto tiles_of = [&](int tx, int ty, int& ox, int& oy, std::vector<MeshTile>& t) -> bool {
+    ox = tx;
+    oy = ty;
+    while (ox * oy > 1 && pme_tile_lds_bytes(h->maxK[0], ox, oy, h->fp64) > (size_t)h->lds_max) {
+      if (ox >= oy)
+        ox /= 2;
+      else
+        oy /= 2;
+    }
+    if (pme_tile_lds_bytes(h->maxK[0], ox, oy, h->fp64) > (size_t)h->lds_max) return false;
+    t.clear();
+    for (int r = 0; r < R; ++r) {
+      const RepDesc& d = h->rep[r];
+      for (int x = 0; x < d.K[0]; x += ox)
+        for (int y = 0; y < d.K[1]; y += oy)
+          t.push_back(MeshTile{r, x, y, std::min(ox, d.K[0] - x) | (std::min(oy, d.K[1] - y) << 16)});
+    }
+    return true;
+  };
+  std::vector<MeshTile> mtiles, gtiles;
+  const int stx = h->tune.mesh_tile_x > 0 ? h->tune.mesh_tile_x : 4;
+  const int sty = h->tune.mesh_tile_y > 0 ? h->tune.mesh_tile_y : 4;
+  if (!tiles_of(stx, sty, h->mtx, h->mty, mtiles) ||
+      !tiles_of(h->tune.gather_tile_x > 0 ? h->tune.gather_tile_x : stx,
+                h->tune.gather_tile_y > 0 ? h->tune.gather_tile_y : sty, h->gtx, h->gty, gtiles))
     return fail(h, GCME_EUNSUPPORTED, "mesh z length too large for the LDS of one workgroup");
-  std::vector<MeshTile> mtiles;
-  for (int r = 0; r < R; ++r) {
-    const RepDesc& d = h->rep[r];
-    for (int x = 0; x < d.K[0]; x += h->mtx)
-      for (int y = 0; y < d.K[1]; y += h->mty)
-        mtiles.push_back(MeshTile{r, x, y, std::min(h->mtx, d.K[0] - x) | (std::min(h->mty, d.K[1] - y) << 16)});
-  }
   h->nmtiles = h->NQ > 0 ? (int)mtiles.size() : 0;
+  h->ngtiles = h->NQ > 0 ? (int)gtiles.size() : 0;
   upload(mtiles, h->d_mtiles, s);
+  upload(gtiles, h->d_gtiles, s);
   for (int ps = 0; ps < 3; ++ps) {
     h->nitems[ps] = (int)items[ps].size();
     upload(items[ps], h->d_items[ps], s);
@@ -981,6 +995,15 @@ PmeLaunch pme_args(gcme_handle h) {
   return a;
 }
 
+// The gather's launch: the mesh launch with the gather's own tiles.
+PmeLaunch gather_args(gcme_handle h, PmeLaunch p) {
+  p.tiles = h->d_gtiles.as<MeshTile>();
+  p.ntiles = h->ngtiles;
+  p.tx = h->gtx;
+  p.ty = h->gty;
+  return p;
+}
+
 IntLaunch int_args(gcme_handle h) {
   IntLaunch a{};
   a.rep = h->d_rep.as<RepDesc>();
@@ -1101,7 +1124,7 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
       launch_fft_y(sp, p, h->fp64, true);
     }
     p.stamps = stamps_for(h, ST_GATHER);
-    launch_z_gather(sp, p, h->fp64);
+    launch_z_gather(sp, gather_args(h, p), h->fp64);
     p.stamps = nullptr;
     // replicas with the exact reciprocal sum instead of a mesh
     launch_ewald(sp, ewald_args(h), h->fp64, ev);
@@ -1805,9 +1828,20 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
     n.stream_layout = t->stream_layout;
     h->tune.stream_layout = n.stream_layout;
   }
+  {
+    const int32_t* in[4] = {&t->mesh_tile_x, &t->mesh_tile_y, &t->gather_tile_x, &t->gather_tile_y};
+    int32_t* out[4] = {&n.mesh_tile_x, &n.mesh_tile_y, &n.gather_tile_x, &n.gather_tile_y};
+    for (int k = 0; k < 4; ++k) {
+      if (*in[k] < 0) continue;
+      if (*in[k] > 16) return fail(h, GCME_EINVAL, "mesh and gather tile sizes in 0..16");
+      *out[k] = *in[k];
+    }
+  }
   if (n.cells_per_cutoff != h->tune.cells_per_cutoff || n.beads_per_cluster != h->tune.beads_per_cluster ||
       n.charges_per_cluster != h->tune.charges_per_cluster || n.list_slack_pct != h->tune.list_slack_pct ||
-      n.direct_pairs != h->tune.direct_pairs) {
+      n.direct_pairs != h->tune.direct_pairs || n.mesh_tile_x != h->tune.mesh_tile_x ||
+      n.mesh_tile_y != h->tune.mesh_tile_y || n.gather_tile_x != h->tune.gather_tile_x ||
+      n.gather_tile_y != h->tune.gather_tile_y) {
     h->tune = n;
     h->plan_dirty = true;
     h->drop_graphs();
@@ -1866,7 +1900,7 @@ gcme_status gcme_autotune(gcme_handle h) {
       for (int cq : ci_list)
         for (int dp = 0; dp < 4; ++dp) {
           if (h->NQ == 0 && (cq != ci_list[0] || dp > 1)) continue;
-          gcme_tuning t{ncc, cg, cq, -1, dp, keep_layout};
+          gcme_tuning t{ncc, cg, cq, -1, dp, keep_layout, -1, -1, -1, -1};
           if (gcme_set_tuning(h, &t) != GCME_OK) continue;
           if (build_plan(h) != GCME_OK) continue;
           float ms = 0;
@@ -1885,6 +1919,50 @@ gcme_status gcme_autotune(gcme_handle h) {
   std::sort(cands.begin(), cands.end(),
             [](const std::pair<float, gcme_tuning>& x, const std::pair<float, gcme_tuning>& y) { return x.first < y.first; });
   gcme_tuning best = cands.empty() ? h->tune : cands[0].second;
+  // 1b. the mesh tile shapes, for the best of them, the spread's then the
+  //     gather's: whole evaluations are timed, since the mesh passes run
+  //     beside the pair kernels.  A shape the plan has to shrink to fit LDS
+  //     is the smaller one, not retimed.
+  if (h->NQ > 0) {
+    static const int kShapes[][2] = {{4, 4}, {2, 2}, {2, 4}, {4, 2}, {8, 4}, {4, 8}, {8, 8}, {16, 8}, {16, 16}, {1, 1}};
+    for (int pass = 0; pass < 2; ++pass) {
+      float best_ms = 1e30f;
+      int bx = pass == 0 ? best.mesh_tile_x : best.gather_tile_x, by = pass == 0 ? best.mesh_tile_y : best.gather_tile_y;
+      for (const auto& sh : kShapes) {
+        gcme_tuning t = best;
+        (pass == 0 ? t.mesh_tile_x : t.gather_tile_x) = sh[0];
+        (pass == 0 ? t.mesh_tile_y : t.gather_tile_y) = sh[1];
+        if (gcme_set_tuning(h, &t) != GCME_OK) continue;
+        if (build_plan(h) != GCME_OK) continue;
+        if (h->nmtiles == 0) break;  // no mesh: nothing to choose
+        if ((pass == 0 ? h->mtx : h->gtx) != sh[0] || (pass == 0 ? h->mty : h->gty) != sh[1]) continue;
+        float ms = 0;
+        for (int rep = 0; rep < 3; ++rep) {
+          launch_fill_i64(s, h->F.as<long long>(), 0, 3LL * h->N);
+          (void)hipEventRecord(e0, s);
+          enqueue_eval(h, s, false, false);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          float m = 0;
+          (void)hipEventElapsedTime(&m, e0, e1);
+          if (rep > 0) ms += m;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          bx = sh[0];
+          by = sh[1];
+        }
+      }
+      (pass == 0 ? best.mesh_tile_x : best.gather_tile_x) = bx;
+      (pass == 0 ? best.mesh_tile_y : best.gather_tile_y) = by;
+    }
+    for (auto& c : cands) {
+      c.second.mesh_tile_x = best.mesh_tile_x;
+      c.second.mesh_tile_y = best.mesh_tile_y;
+      c.second.gather_tile_x = best.gather_tile_x;
+      c.second.gather_tile_y = best.gather_tile_y;
+    }
+  }
   // 2. the best few, with every charged-cluster size and stream layout, as
   //    replays of the captured step graph from the saved state: stream
   //    dependencies cost differently in a graph, and only whole steps show
@@ -2028,7 +2106,7 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
       case 9:
         if (!h->yx_fused) launch_fft_y(st2, p, h->fp64, true);
         break;
-      case 10: launch_z_gather(st2, p, h->fp64); break;
+      case 10: launch_z_gather(st2, gather_args(h, p), h->fp64); break;
       default: launch_int_last(st2, ia, viewB(h), viewA(h), F3, false); break;
     }
   };
@@ -2100,8 +2178,8 @@ gcme_status gcme_time_stages(gcme_handle h, int32_t n_steps, double* ms) {
       case ST_PAIR_GCM: return h->ntiles_g * wpb;
       case ST_LIST_ELEC: return dq || h->NQ == 0 ? 0 : (h->ncl_q + wpb - 1) / wpb * wpb;
       case ST_PAIR_ELEC: return h->NQ == 0 ? 0 : h->ntiles_q * wpb;
-      case ST_SPREAD:
-      case ST_GATHER: return mesh ? h->nmtiles * (FFT_THREADS / 64) : 0;
+      case ST_SPREAD: return mesh ? h->nmtiles * (FFT_THREADS / 64) : 0;
+      case ST_GATHER: return mesh ? h->ngtiles * (FFT_THREADS / 64) : 0;
       case ST_FFT_Y:
       case ST_FFT_Y_INV: return mesh && !h->yx_fused ? h->nitems[1] * (FFT_THREADS / 64) : 0;
       case ST_FFT_CONV:

@@ -78,6 +78,18 @@ def test_tunings_parity(precision, tuning):
     _check(w, precision, tuning)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("tile", [(8, 8, 0, 0), (16, 4, 2, 2), (2, 8, 16, 16), (16, 16, 1, 1), (1, 1, 8, 4)])
+def test_mesh_tile_shapes(precision, tile):
+    # the fused spread and gather passes with other z-line tiles (spread x,
+    # y, gather x, y; 0 = the spread's), ragged at the mesh edges (27 and
+    # 36 lines are not multiples of 8 or 16)
+    w = W.small_bulk(N=1001, seed=4, charged_frac=0.25, a_types=(0.3, 0.5, 0.7), box=(7.7, 8.3, 6.5),
+                     rc=2.6, grid=(27, 36, 24), order=4)
+    _check(w, precision, dict(mesh_tile_x=tile[0], mesh_tile_y=tile[1], gather_tile_x=tile[2],
+                              gather_tile_y=tile[3]))
+
+
 @pytest.mark.parametrize("order", [3, 6, 8])
 def test_orders_and_odd_mesh(order):
     w = W.small_bulk(N=512, seed=5, charged_frac=0.5, a_types=(0.45,), box=(6.0, 6.0, 6.0), rc=2.5,
