@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/gcme.h"
@@ -366,6 +367,16 @@ void build_tables(gcme_handle h, std::vector<GcmPar<T>>& g, std::vector<ElecPar<
         double al = std::sqrt(M_PI / 2.0) / aij;
         e[q].alpha = (T)al;
         e[q].alpha2 = (T)(al * al);
+        if constexpr (std::is_same<T, float>::value) {
+          // the same float operations as the kernel's for beta, so that
+          // alpha == beta (as floats) gives equal Gaussians, bit for bit
+          const float af = (float)al;
+          e[q].cexp = -(af * af) * 1.44269504088896341f;
+          e[q].tsa = 1.12837916709551257f * af;
+        } else {
+          e[q].cexp = (T)(-al * al * log2e);
+          e[q].tsa = (T)(2.0 / std::sqrt(M_PI) * al);
+        }
         // the series is used where both alpha r and beta r stay below 1/2,
         // which bounds its truncation after 8 (FP32) or 14 (FP64) terms
         double rs = 0.5 / std::max(al, p.beta);

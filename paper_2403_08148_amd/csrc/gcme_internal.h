@@ -63,7 +63,10 @@ struct GcmPar {
 // For r^2 < rs2 both come from the series in r^2 with coefficients cphi, cg.
 template <typename T>
 struct ElecPar {
-  T alpha, alpha2, rs2, pad;
+  T alpha, alpha2, rs2;
+  T cexp;       // -alpha^2 log2(e): exp(-alpha^2 r^2) = 2^(cexp r^2)
+  T tsa;        // (2/sqrt(pi)) alpha
+  T pad[3];
   T cphi[NSER];
   T cg[NSER];
 };

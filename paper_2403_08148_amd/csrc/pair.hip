@@ -54,6 +54,17 @@ __device__ inline double gerfc(double x) { return erfc(x); }
 __device__ inline float gsqrt(float x) { return sqrtf(x); }
 __device__ inline double gsqrt(double x) { return sqrt(x); }
 
+// erfc(x) e^(x^2), x >= 0, in single precision by the rational
+// approximation of Abramowitz and Stegun (Handbook of Mathematical
+// Functions, 7.1.26): with t = 1/(1 + p x), erfc(x) = (a1 t + a2 t^2 +
+// a3 t^3 + a4 t^4 + a5 t^5) e^(-x^2), absolute error at most 1.5e-7.  The
+// factor e^(-x^2) is left to the caller, who needs it for the force too.
+__device__ inline float erfc_scaled(float x) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  return t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+                  0.254829592f);
+}
+
 template <typename T>
 struct Series;
 template <>
@@ -473,7 +484,7 @@ __device__ inline void lane_zero(Lane<T>& L) {
 template <typename T, bool ELEC, bool EV, bool ADJ, bool COUNT>
 __device__ inline void interact(Lane<T>& L, T dx, T dy, T dz, T r2, uint32_t pj, const GcmPar<T>* grow,
                                 const ElecPar<T>* erow, const AdjPar<T>* arow, T zi, T beta, T beta2, T lB,
-                                T vx = 0, T vy = 0, T vz = 0, bool vjp = false) {
+                                T vx = 0, T vy = 0, T vz = 0, bool vjp = false, T cexpb = 0, T tsb = 0) {
   const int tj = param_type(pj);
   T fs, en;
   if (!ELEC) {
@@ -506,7 +517,7 @@ __device__ inline void interact(Lane<T>& L, T dx, T dy, T dz, T r2, uint32_t pj,
     constexpr T TSP = (T)1.1283791670955126;  // 2/sqrt(pi)
     const ElecPar<T>& p = erow[tj];
     const T zz = zi * (T)param_z(pj);
-    T phi, g;
+    T phi, g, ea = 0;  // ea: exp(-alpha^2 r^2) where computed
     if (r2 < p.rs2) {
       // series in r^2, free of the cancellation near contact
       phi = p.cphi[Series<T>::n - 1];
@@ -516,18 +527,33 @@ __device__ inline void interact(Lane<T>& L, T dx, T dy, T dz, T r2, uint32_t pj,
         phi = phi * r2 + p.cphi[n];
         g = g * r2 + p.cg[n];
       }
+    } else if constexpr (std::is_same<T, float>::value) {
+      // single precision: both error functions from their Gaussians, which
+      // the force needs anyway (one reciprocal square root, two 2^x, two
+      // reciprocals)
+      // each product rounded on its own (no multiply-add fused across a
+      // difference), so that alpha == beta gives exactly zero
+#pragma clang fp contract(off)
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * rinv;
+      ea = gexp2(p.cexp * r2);
+      const float eb = gexp2(cexpb * r2);
+      phi = (erfc_scaled(beta * r) * eb - erfc_scaled(p.alpha * r) * ea) * rinv;
+      g = (phi - (p.tsa * ea - tsb * eb)) * rinv * rinv;
     } else {
       T r = gsqrt(r2);
       T rinv = (T)1 / r;
+      ea = gexp(-p.alpha2 * r2);
       phi = (gerfc(beta * r) - gerfc(p.alpha * r)) * rinv;
-      g = (phi - TSP * (p.alpha * gexp(-p.alpha2 * r2) - beta * gexp(-beta2 * r2))) * rinv * rinv;
+      g = (phi - TSP * (p.alpha * ea - beta * gexp(-beta2 * r2))) * rinv * rinv;
     }
     fs = lB * zz * g;
     en = lB * zz * phi;
     if (ADJ) {
       const AdjPar<T> ap = arow[tj];
       // d/da_ij of lB zz erf(alpha r)/r = -lB zz (2/sqrt(pi)) (alpha/a_ij) exp(-alpha^2 r^2)
-      T dd = -lB * zz * ap.ea * gexp(-p.alpha2 * r2);
+      if (r2 < p.rs2) ea = gexp(-p.alpha2 * r2);
+      T dd = -lB * zz * ap.ea * ea;
       // force vector-Jacobian product: dg/dalpha = 2 (2/sqrt(pi)) alpha^2
       // exp(-alpha^2 r^2), so dfs/da_ij = 2 alpha^2 dd
       if (vjp) dd = (vx * dx + vy * dy + vz * dz) * (T)2 * p.alpha2 * dd;
@@ -576,6 +602,7 @@ __device__ inline void flush_adj(Lane<T>& L, int ti) {
 template <typename T>
 struct PairCtx {
   T sx, sy, sz, rc2, beta, beta2, lB, zi;
+  T cexpb, tsb;  // -beta^2 log2(e), (2/sqrt(pi)) beta
   T vx, vy, vz;  // force vector-Jacobian product: v of bead i (adjoint only)
   bool vjp;
   const GcmPar<T>* grow;
@@ -611,6 +638,15 @@ __device__ inline PairCtx<T> make_ctx(const Tables<T, ELEC, ADJ>& S, const RepDe
   P.rc2 = (T)R.rc2;
   P.beta = (T)R.beta;
   P.beta2 = (T)(R.beta * R.beta);
+  if constexpr (std::is_same<T, float>::value) {
+    // float operations matching the host's for alpha (see build_tables)
+    const float bf = (float)R.beta;
+    P.cexpb = -(bf * bf) * 1.44269504088896341f;
+    P.tsb = 1.12837916709551257f * bf;
+  } else {
+    P.cexpb = -R.beta * R.beta * 1.4426950408889634;
+    P.tsb = 1.1283791670955126 * R.beta;
+  }
   P.lB = (T)R.lB;
   P.zi = (T)param_z(pi);
   P.grow = S.g + (ELEC ? 0 : ti * MAXT);
@@ -657,7 +693,7 @@ __device__ inline void pair_at(Lane<T>& L, const PairCtx<T>& P, T dx, T dy, T dz
     }
   } else if (in) {
     interact<T, ELEC, EV, ADJ, COUNT>(L, dx, dy, dz, r2, pw, P.grow, P.erow, P.arow, P.zi, P.beta, P.beta2, P.lB,
-                                      P.vx, P.vy, P.vz, P.vjp);
+                                      P.vx, P.vy, P.vz, P.vjp, P.cexpb, P.tsb);
   }
 }
 
