@@ -74,8 +74,8 @@ def parse():
                          "workload's default tuning")
     ap.add_argument("--tuning", default="",
                     help="cells_per_cutoff,beads_per_cluster,charges_per_cluster[,direct_pairs[,stream_layout"
-                         "[,mesh_tile_x,mesh_tile_y[,gather_tile_x,gather_tile_y]]]] in place of the workload's "
-                         "default tuning")
+                         "[,mesh_tile_x,mesh_tile_y[,gather_tile_x,gather_tile_y[,half_pairs]]]]] in place of "
+                         "the workload's default tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=20,
                     help="steps of the stage-timing pass (HIP event nodes in the step graph)")
@@ -129,7 +129,8 @@ def main():
         eng.set_tuning(cells_per_cutoff=v[0], beads_per_cluster=v[1], charges_per_cluster=v[2],
                        direct_pairs=v[3] if len(v) > 3 else -1, stream_layout=v[4] if len(v) > 4 else -1,
                        mesh_tile_x=v[5] if len(v) > 6 else -1, mesh_tile_y=v[6] if len(v) > 6 else -1,
-                       gather_tile_x=v[7] if len(v) > 8 else -1, gather_tile_y=v[8] if len(v) > 8 else -1)
+                       gather_tile_x=v[7] if len(v) > 8 else -1, gather_tile_y=v[8] if len(v) > 8 else -1,
+                       half_pairs=v[9] if len(v) > 9 else -1)
 
     # warm-up (also relaxes the random start a little); the first run of
     # steps captures every step graph a later run replays

@@ -54,7 +54,8 @@ class gcme_tuning(C.Structure):
     _fields_ = [("cells_per_cutoff", C.c_int32), ("beads_per_cluster", C.c_int32),
                 ("charges_per_cluster", C.c_int32), ("list_slack_pct", C.c_int32),
                 ("direct_pairs", C.c_int32), ("stream_layout", C.c_int32), ("mesh_tile_x", C.c_int32),
-                ("mesh_tile_y", C.c_int32), ("gather_tile_x", C.c_int32), ("gather_tile_y", C.c_int32)]
+                ("mesh_tile_y", C.c_int32), ("gather_tile_x", C.c_int32), ("gather_tile_y", C.c_int32),
+                ("half_pairs", C.c_int32)]
 
 
 class GCMeError(RuntimeError):

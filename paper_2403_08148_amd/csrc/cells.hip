@@ -299,6 +299,86 @@ __global__ void k_commit(StateView B, StateView A, int N) {
   A.id[s] = B.id[s];
 }
 
+// Column clusters (see ColLaunch).  One block: the columns' cluster counts
+// are staged in LDS (loads spread over the block), each thread then takes a
+// contiguous run of columns, and a block scan of the runs' counts gives every
+// column its first cluster slot, numbered from its replica's first slot.
+// With `fill` the scan's threads write the clusters themselves (one column
+// per thread at most); otherwise each column's first slot goes to colbase
+// and k_col_fill writes them, one thread per column.
+constexpr int COL_THREADS = 1024;
+constexpr int COL_LDS_MAX = 36864;  // columns + replicas staged in LDS (144 KiB)
+
+__global__ __launch_bounds__(COL_THREADS) void k_col_scan(ColLaunch a, bool fill) {
+  __shared__ int sh[COL_THREADS / 64];
+  extern __shared__ int lds[];
+  int* rfirst = lds;            // [nrep]: global cluster count before each replica
+  int* rend = lds + a.nrep;     // [nrep]: ... and after it
+  int* cnt = lds + 2 * a.nrep;  // [ncols]: clusters per column, then their first slot
+  wave_stamp(a.stamps, 0);
+  const int n = a.ncols;
+  const int sh_ci = __ffs(a.ci) - 1;
+  // 1. the counts, four columns per thread in flight
+  for (int c0 = threadIdx.x; c0 < n; c0 += 4 * COL_THREADS) {
+    int lo[4], hi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u * COL_THREADS;
+      lo[u] = c < n ? a.coltab[c].x : 0;
+      hi[u] = c < n ? a.coltab[c + 1].x : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      lo[u] = a.start[lo[u]];
+      hi[u] = a.start[hi[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u * COL_THREADS;
+      if (c < n) cnt[c] = (hi[u] - lo[u] + a.ci - 1) >> sh_ci;
+    }
+  }
+  __syncthreads();
+  // 2. exclusive scan over contiguous runs of columns
+  const int per = (n + COL_THREADS - 1) / COL_THREADS;
+  const int lo = min(n, (int)threadIdx.x * per), hi = min(lo + per, n);
+  int s = 0;
+  for (int c = lo; c < hi; ++c) s += cnt[c];
+  const int inc = block_incl_scan<COL_THREADS>(s, sh);
+  int run = inc - s;
+  for (int c = lo; c < hi; ++c) {
+    const int v = cnt[c];
+    cnt[c] = run;
+    const int r = a.coltab[c].y;
+    if (c == 0 || a.coltab[c - 1].y != r) rfirst[r] = run;
+    run += v;
+    if (c + 1 == n || a.coltab[c + 1].y != r) rend[r] = run;
+  }
+  __syncthreads();
+  // 3. each replica's count, and the columns' first slots (or the clusters)
+  for (int r = threadIdx.x; r < a.nrep; r += COL_THREADS) a.ncl[r] = rend[r] - rfirst[r];
+  for (int c = threadIdx.x; c < n; c += COL_THREADS) {
+    const int2 ct = a.coltab[c];
+    const int slot = a.rep_base[ct.y] + cnt[c] - rfirst[ct.y];
+    if (fill) {
+      const int b = a.start[ct.x], e = a.start[a.coltab[c + 1].x];
+      int sl = slot;
+      for (int f = b; f < e; f += a.ci) a.cl[sl++] = make_int2(f, min(a.ci, e - f));
+    } else {
+      a.colbase[c] = slot;
+    }
+  }
+  wave_stamp(a.stamps, 1);
+}
+
+__global__ void k_col_fill(ColLaunch a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.ncols) return;
+  const int b = a.start[a.coltab[c].x], e = a.start[a.coltab[c + 1].x];
+  int slot = a.colbase[c];
+  for (int f = b; f < e; f += a.ci) a.cl[slot++] = make_int2(f, min(a.ci, e - f));
+}
+
 inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -341,6 +421,18 @@ void launch_scatter(hipStream_t s, CellView c, int N) {
 
 void launch_permute(hipStream_t s, StateView A, StateView B, uint4* bpk, CellView c, ChargedView q, int N) {
   hipLaunchKernelGGL(k_permute, dim3(nblk(N, BEAD_THREADS)), dim3(BEAD_THREADS), 0, s, A, B, bpk, c, q, N);
+}
+
+int col_clusters_max_entries() { return COL_LDS_MAX; }
+
+void launch_col_clusters(hipStream_t s, const ColLaunch& a) {
+  if (a.ncols <= 0) return;
+  const size_t sh = ((size_t)a.ncols + 2 * (size_t)a.nrep) * 4;
+  if (sh > 65536) (void)hipFuncSetAttribute((const void*)k_col_scan, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  // one column per thread of the scan: it writes the clusters itself
+  const bool fill = a.ncols <= COL_THREADS;
+  hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(COL_THREADS), sh, s, a, fill);
+  if (!fill) hipLaunchKernelGGL(k_col_fill, dim3(nblk(a.ncols, 128)), dim3(128), 0, s, a);
 }
 
 void launch_commit(hipStream_t s, StateView B, StateView A, int N) {

@@ -151,7 +151,7 @@ struct gcme_ctx {
   std::vector<int> nq, qoff;
   int NQ = 0;
   // tuning
-  gcme_tuning tune{3, 8, 4, 50, 3, 0, 0, 0, 0, 0};  // list-free pairs, three stream branches, 4 x 4 mesh tiles
+  gcme_tuning tune{3, 8, 4, 50, 3, 0, 0, 0, 0, 0, 0};  // list-free pairs, three stream branches, 4 x 4 mesh tiles
   bool plan_dirty = true;
   // device buffers
   DevBuf a_pos[3], a_vel[3], a_param, a_id;
@@ -164,6 +164,15 @@ struct gcme_ctx {
   DevBuf d_tw, d_rad, d_bsp, d_freq;
   DevBuf d_items[3];
   DevBuf d_cl_g, d_cl_q, d_tiles_g, d_tiles_q, d_tiles_256;
+  // half-shell excluded-volume pairs: cell columns (first cell, replica),
+  // each replica's first cluster slot, the column clusters, their count per
+  // replica, the pair tiles and their partial-sum rows
+  DevBuf d_coltab, d_colbase, d_colbase_q, d_hbase, d_hcl, d_hncl, d_htiles, part_h, d_off_h;
+  int ncols = 0, ntiles_h = 0, hci = 8;
+  // the same for the charged beads' real-space pairs
+  DevBuf d_hqbase, d_hqcl, d_hqncl, d_hqtiles, part_hq, d_off_hq;
+  int ntiles_hq = 0, hqci = 4;
+  int ncols_tmp = 0;  // build_plan's running column count
   DevBuf list_g, list_q, cnt_g, cnt_q;
   DevBuf part[N_SLOTS], adjp[2];
   DevBuf d_off[N_SLOTS], d_adj_off[2];
@@ -510,6 +519,7 @@ gcme_status build_plan(gcme_handle h) {
   const int R = h->R;
   h->rep.assign(R, RepDesc{});
   int cell_off = 0;
+  h->ncols_tmp = 0;
   long long goff = 0, cgoff = 0;
   h->order = h->hp[0].order;
   for (int ax = 0; ax < 3; ++ax) h->maxK[ax] = 0;
@@ -540,6 +550,8 @@ gcme_status build_plan(gcme_handle h) {
     d.lBf = (float)p.lB;
     d.cell_off = cell_off;
     cell_off += d.nc[0] * d.nc[1] * d.nc[2];
+    d.col_off = h->ncols_tmp;
+    h->ncols_tmp += d.nc[0] * d.nc[1];
     d.bead_off = h->boff[r];
     d.n = h->nb[r];
     d.q_off = h->qoff[r];
@@ -766,6 +778,67 @@ gcme_status build_plan(gcme_handle h) {
   HIPCHK(h, h->part[SLOT_EWALD].alloc((size_t)std::max(1, h->nitems_ew_f) * PART_W * 8));
   HIPCHK(h, h->adjp[0].alloc((size_t)std::max(1, h->ntiles_g) * (MAXT * MAXT + 2 * MAXT) * 8));
   HIPCHK(h, h->adjp[1].alloc((size_t)std::max(1, h->ntiles_q) * (MAXT * MAXT + 2 * MAXT) * 8));
+
+  // half-shell pairs: the column table, each replica's cluster slots
+  // (ceil(n / ci) + its column count bounds the column clusters) and tiles
+  // of pair_waves_per_block() slots
+  h->ncols = h->ncols_tmp;
+  h->ntiles_h = h->ntiles_hq = 0;
+  // (beyond what the column pass can stage, the cluster kernels run instead)
+  const bool half_fits = h->ncols + 2 * R <= col_clusters_max_entries();
+  if ((h->tune.half_pairs & 3) && half_fits) {
+    std::vector<int2> coltab;
+    coltab.reserve((size_t)h->ncols + 1);
+    for (int r = 0; r < R; ++r) {
+      const RepDesc& d = h->rep[r];
+      for (int x = 0; x < d.nc[0]; ++x)
+        for (int y = 0; y < d.nc[1]; ++y) coltab.push_back(make_int2(d.cell_off + (x * d.nc[1] + y) * d.nc[2], r));
+    }
+    coltab.push_back(make_int2(h->ncells, R));
+    upload(coltab, h->d_coltab, s);
+    // (one per population: the two column passes may run concurrently)
+    HIPCHK(h, h->d_colbase.alloc((size_t)(h->ncols + 1) * 4));
+    HIPCHK(h, h->d_colbase_q.alloc((size_t)(h->ncols + 1) * 4));
+  }
+  // each population's cluster slots and tiles (n: its beads per replica)
+  auto plan_half = [&](const std::vector<int>& n, int ci, DevBuf& base, DevBuf& cl, DevBuf& ncl, DevBuf& tiles,
+                       DevBuf& part, DevBuf& off, int& ntiles) -> gcme_status {
+    std::vector<int> hbase(R), toff(R + 1);
+    std::vector<Tile> th;
+    const int wpb = pair_waves_per_block();
+    int slots = 0;
+    for (int r = 0; r < R; ++r) {
+      const RepDesc& d = h->rep[r];
+      const int cap = n[r] == 0 ? 0 : (n[r] + ci - 1) / ci + d.nc[0] * d.nc[1];
+      hbase[r] = slots;
+      toff[r] = (int)th.size();
+      for (int c = 0; c < cap; c += wpb) th.push_back(Tile{r, slots + c, std::min(wpb, cap - c), slots});
+      slots += cap;
+    }
+    toff[R] = (int)th.size();
+    ntiles = (int)th.size();
+    if (th.empty()) th.push_back(Tile{0, 0, 0, 0});
+    upload(hbase, base, s);
+    upload(th, tiles, s);
+    upload(toff, off, s);
+    HIPCHK(h, cl.alloc((size_t)std::max(1, slots) * 8));
+    HIPCHK(h, ncl.alloc((size_t)R * 4));
+    HIPCHK(h, hipMemsetAsync(ncl.p, 0, (size_t)R * 4, s));
+    HIPCHK(h, part.alloc((size_t)std::max(1, ntiles) * PART_W * 8));
+    return GCME_OK;
+  };
+  if ((h->tune.half_pairs & 1) && half_fits) {
+    h->hci = h->tune.beads_per_cluster < 4 ? 4 : h->tune.beads_per_cluster;
+    gcme_status e = plan_half(h->nb, h->hci, h->d_hbase, h->d_hcl, h->d_hncl, h->d_htiles, h->part_h, h->d_off_h,
+                              h->ntiles_h);
+    if (e != GCME_OK) return e;
+  }
+  if ((h->tune.half_pairs & 2) && h->NQ > 0 && half_fits) {
+    h->hqci = h->tune.charges_per_cluster < 4 ? 4 : h->tune.charges_per_cluster;
+    gcme_status e = plan_half(h->nq, h->hqci, h->d_hqbase, h->d_hqcl, h->d_hqncl, h->d_hqtiles, h->part_hq,
+                              h->d_off_hq, h->ntiles_hq);
+    if (e != GCME_OK) return e;
+  }
 
   // slab correction (per 256-bead tile) and bonds (per 256-bond tile)
   {
@@ -1045,6 +1118,82 @@ unsigned long long* stamps_for(gcme_handle h, int stage) {
   return h->timing ? h->stamps.as<unsigned long long>() + 2 * h->stamp_off[stage] : nullptr;
 }
 
+// Whether an evaluation's excluded-volume (charged) pairs take the
+// half-shell kernel (not with parameter derivatives, which the cluster
+// kernels provide).
+bool half_gcm(gcme_handle h, bool adj) { return (h->tune.half_pairs & 1) && !adj && h->ntiles_h > 0; }
+bool half_elec(gcme_handle h, bool adj) { return (h->tune.half_pairs & 2) && !adj && h->ntiles_hq > 0; }
+
+PairLaunch pair_args_half(gcme_handle h, bool charged) {
+  PairLaunch a = pair_args(h, charged);
+  if (charged) {
+    a.tiles = h->d_hqtiles.as<Tile>();
+    a.ntiles = h->ntiles_hq;
+    a.cl = h->d_hqcl.as<int2>();
+    a.hncl = h->d_hqncl.as<int>();
+    a.ci = h->hqci;
+    a.part = h->part_hq.as<double>();
+  } else {
+    a.tiles = h->d_htiles.as<Tile>();
+    a.ntiles = h->ntiles_h;
+    a.cl = h->d_hcl.as<int2>();
+    a.hncl = h->d_hncl.as<int>();
+    a.ci = h->hci;
+    a.part = h->part_h.as<double>();
+  }
+  return a;
+}
+
+ColLaunch col_args(gcme_handle h, bool charged) {
+  ColLaunch c{};
+  c.start = charged ? h->qstart.as<int>() : h->start.as<int>();
+  c.coltab = h->d_coltab.as<int2>();
+  c.ncols = h->ncols;
+  c.ci = charged ? h->hqci : h->hci;
+  c.rep_base = charged ? h->d_hqbase.as<int>() : h->d_hbase.as<int>();
+  c.cl = charged ? h->d_hqcl.as<int2>() : h->d_hcl.as<int2>();
+  c.ncl = charged ? h->d_hqncl.as<int>() : h->d_hncl.as<int>();
+  c.colbase = charged ? h->d_colbase_q.as<int>() : h->d_colbase.as<int>();
+  c.nrep = h->R;
+  return c;
+}
+
+// The excluded-volume pairs of an evaluation on stream s.
+void enqueue_gcm_pairs(gcme_handle h, hipStream_t s, bool ev, bool adj) {
+  if (half_gcm(h, adj)) {
+    ColLaunch c = col_args(h, false);
+    c.stamps = stamps_for(h, ST_LIST_GCM);
+    launch_col_clusters(s, c);
+    PairLaunch g = pair_args_half(h, false);
+    g.stamps = stamps_for(h, ST_PAIR_GCM);
+    launch_pair_gcm_half(s, g, h->fp64, ev);
+    return;
+  }
+  PairLaunch g = pair_args(h, false);
+  g.stamps = stamps_for(h, ST_LIST_GCM);
+  launch_nl_build(s, g);
+  g.stamps = stamps_for(h, ST_PAIR_GCM);
+  launch_pair_gcm(s, g, h->fp64, ev, adj);
+}
+
+// The charged beads' real-space pairs of an evaluation on stream s.
+void enqueue_elec_pairs(gcme_handle h, hipStream_t s, bool ev, bool adj) {
+  if (half_elec(h, adj)) {
+    ColLaunch c = col_args(h, true);
+    c.stamps = stamps_for(h, ST_LIST_ELEC);
+    launch_col_clusters(s, c);
+    PairLaunch q = pair_args_half(h, true);
+    q.stamps = stamps_for(h, ST_PAIR_ELEC);
+    launch_pair_elec_half(s, q, h->fp64, ev);
+    return;
+  }
+  PairLaunch q = pair_args(h, true);
+  q.stamps = stamps_for(h, ST_LIST_ELEC);
+  launch_nl_build(s, q);
+  q.stamps = stamps_for(h, ST_PAIR_ELEC);
+  launch_pair_elec(s, q, h->fp64, ev, adj);
+}
+
 // Sort the state A into B by cell (and the charged copy), on stream s;
 // bin = false when the integrator has already binned A.
 void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
@@ -1074,12 +1223,8 @@ void enqueue_sort(gcme_handle h, hipStream_t s, bool bin = true) {
 // they run as three concurrent branches (fork/join with events; captured as
 // parallel graph branches).
 void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
-  PairLaunch g = pair_args(h, false);
   if (h->NQ == 0) {
-    g.stamps = stamps_for(h, ST_LIST_GCM);
-    launch_nl_build(s, g);
-    g.stamps = stamps_for(h, ST_PAIR_GCM);
-    launch_pair_gcm(s, g, h->fp64, ev, adj);
+    enqueue_gcm_pairs(h, s, ev, adj);
     launch_bonds(s, bond_args(h), viewB(h));
     return;
   }
@@ -1106,20 +1251,9 @@ void enqueue_forces(gcme_handle h, hipStream_t s, bool ev, bool adj) {
   if (use1 || use2) (void)hipEventRecord(h->ev_fork, s);
   if (use1) (void)hipStreamWaitEvent(h->aux[0], h->ev_fork, 0);
   if (use2) (void)hipStreamWaitEvent(h->aux[1], h->ev_fork, 0);
-  PairLaunch q = pair_args(h, true);
   PmeLaunch p = pme_args(h);
-  auto gcm = [&]() {
-    g.stamps = stamps_for(h, ST_LIST_GCM);
-    launch_nl_build(sg, g);
-    g.stamps = stamps_for(h, ST_PAIR_GCM);
-    launch_pair_gcm(sg, g, h->fp64, ev, adj);
-  };
-  auto elec = [&]() {
-    q.stamps = stamps_for(h, ST_LIST_ELEC);
-    launch_nl_build(sq, q);
-    q.stamps = stamps_for(h, ST_PAIR_ELEC);
-    launch_pair_elec(sq, q, h->fp64, ev, adj);
-  };
+  auto gcm = [&]() { enqueue_gcm_pairs(h, sg, ev, adj); };
+  auto elec = [&]() { enqueue_elec_pairs(h, sq, ev, adj); };
   auto mesh = [&]() {
     p.stamps = stamps_for(h, ST_SPREAD);
     launch_spread_z(sp, p, h->fp64);
@@ -1169,6 +1303,14 @@ void enqueue_outputs(gcme_handle h, hipStream_t s, const gcme_io* io, bool kin) 
     for (int sl = 0; sl < N_SLOTS; ++sl) {
       f.part[sl] = h->part[sl].as<double>();
       f.slot_off[sl] = h->d_off[sl].as<int>();
+    }
+    if (half_gcm(h, adj)) {
+      f.part[SLOT_GCM] = h->part_h.as<double>();
+      f.slot_off[SLOT_GCM] = h->d_off_h.as<int>();
+    }
+    if (half_elec(h, adj)) {
+      f.part[SLOT_REAL] = h->part_hq.as<double>();
+      f.slot_off[SLOT_REAL] = h->d_off_hq.as<int>();
     }
     if (h->NQ == 0) {
       // no charged beads: the charged kernels did not run, their slots are empty ranges
@@ -1833,6 +1975,10 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
     if (t->direct_pairs > 3) return fail(h, GCME_EINVAL, "direct_pairs in 0..3");
     n.direct_pairs = t->direct_pairs;
   }
+  if (t->half_pairs >= 0) {
+    if (t->half_pairs > 3) return fail(h, GCME_EINVAL, "half_pairs in 0..3");
+    n.half_pairs = t->half_pairs;
+  }
   if (t->stream_layout >= 0) {
     if (t->stream_layout > 5) return fail(h, GCME_EINVAL, "stream_layout in 0..5");
     if (t->stream_layout != h->tune.stream_layout) h->drop_graphs();  // no new plan needed
@@ -1852,7 +1998,7 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
       n.charges_per_cluster != h->tune.charges_per_cluster || n.list_slack_pct != h->tune.list_slack_pct ||
       n.direct_pairs != h->tune.direct_pairs || n.mesh_tile_x != h->tune.mesh_tile_x ||
       n.mesh_tile_y != h->tune.mesh_tile_y || n.gather_tile_x != h->tune.gather_tile_x ||
-      n.gather_tile_y != h->tune.gather_tile_y) {
+      n.gather_tile_y != h->tune.gather_tile_y || n.half_pairs != h->tune.half_pairs) {
     h->tune = n;
     h->plan_dirty = true;
     h->drop_graphs();
@@ -1906,12 +2052,17 @@ gcme_status gcme_autotune(gcme_handle h) {
   std::vector<std::pair<float, gcme_tuning>> cands;
   const int ncc_list[] = {2, 3, 4};
   const int ci_list[] = {2, 4, 8};
+  // per pair type: 0 = neighbour lists, 1 = list-free, 2 = half-shell
+  // (clusters of 4 or 8)
   for (int ncc : ncc_list)
     for (int cg : ci_list)
       for (int cq : ci_list)
-        for (int dp = 0; dp < 4; ++dp) {
-          if (h->NQ == 0 && (cq != ci_list[0] || dp > 1)) continue;
-          gcme_tuning t{ncc, cg, cq, -1, dp, keep_layout, -1, -1, -1, -1};
+        for (int mg = 0; mg < 3; ++mg)
+          for (int mq = 0; mq < 3; ++mq) {
+          if (h->NQ == 0 && (cq != ci_list[0] || mq > 0)) continue;
+          if ((mg == 2 && cg == 2) || (mq == 2 && cq == 2)) continue;
+          const int dp = (mg > 0 ? 1 : 0) | (mq > 0 ? 2 : 0), hp = (mg == 2 ? 1 : 0) | (mq == 2 ? 2 : 0);
+          gcme_tuning t{ncc, cg, cq, -1, dp, keep_layout, -1, -1, -1, -1, hp};
           if (gcme_set_tuning(h, &t) != GCME_OK) continue;
           if (build_plan(h) != GCME_OK) continue;
           float ms = 0;
@@ -2016,7 +2167,8 @@ gcme_status gcme_autotune(gcme_handle h) {
         bool dup = false;
         for (const gcme_tuning& u : second)
           dup = dup || (u.cells_per_cutoff == t.cells_per_cutoff && u.beads_per_cluster == t.beads_per_cluster &&
-                        u.charges_per_cluster == t.charges_per_cluster && u.direct_pairs == t.direct_pairs);
+                        u.charges_per_cluster == t.charges_per_cluster && u.direct_pairs == t.direct_pairs &&
+                        u.half_pairs == t.half_pairs);
         if (!dup) second.push_back(t);
       }
     }
@@ -2100,10 +2252,30 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
     switch (i) {
       case 0: launch_int_first(st2, ia, viewA(h), F3); break;
       case 1: enqueue_sort(h, st2); break;
-      case 2: launch_nl_build(st2, g); break;
-      case 3: launch_pair_gcm(st2, g, h->fp64, false, false); break;
-      case 4: launch_nl_build(st2, q); break;
-      case 5: launch_pair_elec(st2, q, h->fp64, false, false); break;
+      case 2:
+        if (half_gcm(h, false))
+          launch_col_clusters(st2, col_args(h, false));
+        else
+          launch_nl_build(st2, g);
+        break;
+      case 3:
+        if (half_gcm(h, false))
+          launch_pair_gcm_half(st2, pair_args_half(h, false), h->fp64, false);
+        else
+          launch_pair_gcm(st2, g, h->fp64, false, false);
+        break;
+      case 4:
+        if (half_elec(h, false))
+          launch_col_clusters(st2, col_args(h, true));
+        else
+          launch_nl_build(st2, q);
+        break;
+      case 5:
+        if (half_elec(h, false))
+          launch_pair_elec_half(st2, pair_args_half(h, true), h->fp64, false);
+        else
+          launch_pair_elec(st2, q, h->fp64, false, false);
+        break;
       case 6: launch_spread_z(st2, p, h->fp64); break;
       case 7:
         if (!h->yx_fused) launch_fft_y(st2, p, h->fp64, false);
@@ -2185,10 +2357,11 @@ gcme_status gcme_time_stages(gcme_handle h, int32_t n_steps, double* ms) {
     const bool mesh = h->NQ > 0 && h->nmtiles > 0;
     switch (i) {
       case ST_INT_FIRST: return nbead_blk;
-      case ST_LIST_GCM: return dg ? 0 : (h->ncl_g + wpb - 1) / wpb * wpb;
-      case ST_PAIR_GCM: return h->ntiles_g * wpb;
-      case ST_LIST_ELEC: return dq || h->NQ == 0 ? 0 : (h->ncl_q + wpb - 1) / wpb * wpb;
-      case ST_PAIR_ELEC: return h->NQ == 0 ? 0 : h->ntiles_q * wpb;
+      case ST_LIST_GCM: return half_gcm(h, false) ? 16 : dg ? 0 : (h->ncl_g + wpb - 1) / wpb * wpb;
+      case ST_PAIR_GCM: return half_gcm(h, false) ? h->ntiles_h * wpb : h->ntiles_g * wpb;
+      case ST_LIST_ELEC:
+        return h->NQ == 0 ? 0 : half_elec(h, false) ? 16 : dq ? 0 : (h->ncl_q + wpb - 1) / wpb * wpb;
+      case ST_PAIR_ELEC: return h->NQ == 0 ? 0 : half_elec(h, false) ? h->ntiles_hq * wpb : h->ntiles_q * wpb;
       case ST_SPREAD: return mesh ? h->nmtiles * (FFT_THREADS / 64) : 0;
       case ST_GATHER: return mesh ? h->ngtiles * (FFT_THREADS / 64) : 0;
       case ST_FFT_Y:

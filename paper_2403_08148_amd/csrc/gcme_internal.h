@@ -33,6 +33,7 @@ struct RepDesc {
   int reach[3];       // stencil half-width in cells; -1 = take the whole axis
   int nreach[3];      // ceil(rc / cell edge): neighbourhood half-width of a brick
   int cell_off;       // first global cell id
+  int col_off;        // first global cell column (nc[0] nc[1] columns of nc[2] cells)
   int bead_off, n;    // bead range in the concatenated arrays
   int q_off, nq;      // charged-bead range in the compacted charged arrays
   int K[3];
@@ -326,8 +327,43 @@ struct PairLaunch {
   unsigned int* status;
   double fscale;       // 2^FSHIFT
   unsigned long long* stamps;  // wave_stamp slots of this launch, or null
+  const int* hncl;     // half-shell kernels: column clusters in use per replica
 };
 void launch_nl_build(hipStream_t s, const PairLaunch& a);
+
+// Column clusters of the half-shell pair kernels: runs of at most ci
+// consecutive sorted beads (all beads, or the compacted charged beads) that
+// never leave their cell column.  Each replica owns the cluster slots
+// [base, base + capacity) with capacity ceil(n / ci) + its column count (an
+// upper bound); k_col_clusters fills the first ncl[r] of them after every
+// sort, from the cell starts, in column order.
+struct ColLaunch {
+  const int* start;      // cell starts of the population (all or charged beads)
+  const int2* coltab;    // [ncols + 1] (first global cell, replica) per column;
+                         // the last entry is (total cells, replica count)
+  int ncols;
+  int ci;                // beads per cluster (a power of two)
+  const int* rep_base;   // [R] first cluster slot of each replica
+  int2* cl;              // cluster slots: (first bead, bead count)
+  int* ncl;              // [R] clusters in use
+  int* colbase;          // [ncols] first cluster slot of each column (scratch)
+  int nrep;
+  unsigned long long* stamps;
+};
+void launch_col_clusters(hipStream_t s, const ColLaunch& a);
+// Largest ncols + 2 nrep the column pass stages (the plan falls back to the
+// cluster kernels beyond it).
+int col_clusters_max_entries();
+
+// Half-shell pairs (`half_pairs` tuning bit): each unordered pair within rc
+// is evaluated once, by the cluster that owns it, and both beads receive its
+// force.  Tiles hold up to pair_waves_per_block() cluster slots of one
+// replica (Tile.first: first slot; Tile.bead0: the replica's first slot);
+// a.cl / a.hncl are the column clusters and their per-replica counts.
+void launch_pair_gcm_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev);
+// The same for the real-space electrostatics of the charged beads (a.pk:
+// their compacted records, a.start: their cell list, a.qidx: sorted index).
+void launch_pair_elec_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev);
 void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint);
 void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint);
 int pair_waves_per_block();

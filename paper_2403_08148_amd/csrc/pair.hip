@@ -225,81 +225,123 @@ __device__ inline void load_cluster(Cluster<CI>& K, const uint4* __restrict__ pk
   make_cluster(K, pk[first + (lane < ni ? lane : 0)], R);
 }
 
+// Sign of the periodic offset from cell index a to cell index c along an
+// axis of n cells: +1 when c lies less than half the axis ahead of a, -1
+// when less than half behind, 0 when equal; at exactly half the axis the
+// smaller index counts as behind.  ahead(c, a, n) = -ahead(a, c, n).
+__device__ inline int ahead(int c, int a, int n) {
+  int d = c - a;
+  if (d == 0) return 0;
+  if (d < 0) d += n;
+  if (2 * d < n) return 1;
+  if (2 * d > n) return -1;
+  return a < c ? 1 : -1;
+}
+
+// One round of the enumeration: the columns cbase .. cbase + 63 of the
+// cluster's reach, one per lane, culled by the exact box-to-column distance,
+// each z run clipped to the sphere of radius rclm around the box and split
+// at the periodic end into up to two bead ranges; the non-empty ranges go to
+// seg_b / seg_l (wave-level, no block barriers).  Returns their number.
+template <int CI, bool HALF>
+__device__ inline int column_segments(const Cluster<CI>& K, const RepDesc& R, const int* __restrict__ start,
+                                      int first, int cbase, int* seg_b, int* seg_l) {
+  const int lane = threadIdx.x & 63;
+  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
+  const int ncx = K.chi[0] - K.clo[0] + 1, ncy = K.chi[1] - K.clo[1] + 1;
+  const int ncol = ncx * ncy;
+  const float rclm2 = K.rclm * K.rclm;
+  int b0[2] = {0, 0}, ln[2] = {0, 0};
+  const int k = cbase + lane;
+  if (k < ncol) {
+    const int rx = K.clo[0] + k / ncy, ry = K.clo[1] + k % ncy;
+    const float gx = K.whole[0] ? 0.f
+                                : fmaxf(0.f, fmaxf(rx * K.h[0] - (K.p0[0] + K.hi[0]),
+                                                   (K.p0[0] + K.lo[0]) - (rx + 1) * K.h[0]));
+    const float gy = K.whole[1] ? 0.f
+                                : fmaxf(0.f, fmaxf(ry * K.h[1] - (K.p0[1] + K.hi[1]),
+                                                   (K.p0[1] + K.lo[1]) - (ry + 1) * K.h[1]));
+    const float d2 = gx * gx + gy * gy;
+    if (d2 < rclm2) {
+      int cx = K.whole[0] ? rx : K.c0[0] + rx;
+      int cy = K.whole[1] ? ry : K.c0[1] + ry;
+      cx += cx < 0 ? nx : (cx >= nx ? -nx : 0);
+      cy += cy < 0 ? ny : (cy >= ny ? -ny : 0);
+      const int sx = HALF ? ahead(cx, K.c0[0], nx) : 1, sy = HALF ? ahead(cy, K.c0[1], ny) : 1;
+      const bool owned = sx > 0 || (sx == 0 && sy >= 0);
+      int zlo = 0, zhi = nz - 1;
+      if (!K.whole[2]) {
+        const float zr = sqrtf(rclm2 - d2);
+        zlo = K.c0[2] + (int)floorf((K.p0[2] + K.lo[2] - zr) * K.ih[2]);
+        zhi = K.c0[2] + (int)floorf((K.p0[2] + K.hi[2] + zr) * K.ih[2]);
+        if (zhi - zlo + 1 >= nz) {
+          zlo = 0;
+          zhi = nz - 1;
+        }
+      }
+      const int colbase = R.cell_off + (cx * ny + cy) * nz;
+      if (zlo < 0) {
+        b0[0] = start[colbase + zlo + nz];
+        ln[0] = start[colbase + nz] - b0[0];
+        b0[1] = start[colbase];
+        ln[1] = start[colbase + zhi + 1] - b0[1];
+      } else if (zhi >= nz) {
+        b0[0] = start[colbase + zlo];
+        ln[0] = start[colbase + nz] - b0[0];
+        b0[1] = start[colbase];
+        ln[1] = start[colbase + zhi - nz + 1] - b0[1];
+      } else {
+        b0[0] = start[colbase + zlo];
+        ln[0] = start[colbase + zhi + 1] - b0[0];
+      }
+      if (HALF && !owned) ln[0] = ln[1] = 0;
+      if (HALF && sx == 0 && sy == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int e = b0[q] + ln[q], nb = max(b0[q], first);
+          ln[q] = max(0, e - nb);
+          b0[q] = nb;
+        }
+      }
+    }
+  }
+  int nseg = 0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const bool has = ln[q] > 0;
+    const unsigned long long m = __ballot(has);
+    if (has) {
+      const int p = nseg + lanes_below(m);
+      seg_b[p] = b0[q];
+      seg_l[p] = ln[q];
+    }
+    nseg += __popcll(m);
+  }
+  __builtin_amdgcn_wave_barrier();
+  return nseg;
+}
+
 // Every bead of the cells within reach of the cluster: the columns whose
 // distance to the cluster's box is below rclm, each with its z run clipped to
 // the sphere of radius rclm around the box.  The beads are handed over in
 // rounds: a round leaves up to NL_CAND bead indices in cand[0, total) and
 // calls visit(total).  Wavefront-level only (no block barriers); seg_b and
 // seg_l are the wavefront's NL_SEG-entry segment scratch.
-template <int CI, class V>
+// With HALF, only the columns the cluster owns pairs with are enumerated:
+// the cluster's own column (bead 0's; a column cluster never leaves it),
+// clipped to the beads from `first` on, and the columns ahead of it (ahead
+// along x, or level along x and ahead along y).  A column pair is owned by
+// exactly one side, so every unordered pair within rc is visited by one
+// cluster only (within the own column: by the lower sorted index).
+template <int CI, bool HALF = false, class V>
 __device__ inline void for_candidates(const Cluster<CI>& K, const RepDesc& R, const int* __restrict__ start,
-                                      int* seg_b, int* seg_l, int* cand, V&& visit) {
+                                      int* seg_b, int* seg_l, int* cand, V&& visit, int first = 0) {
   const int lane = threadIdx.x & 63;
-  const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
-  const int ncx = K.chi[0] - K.clo[0] + 1, ncy = K.chi[1] - K.clo[1] + 1;
-  const int ncol = ncx * ncy;
-  const float rclm2 = K.rclm * K.rclm;
+  const int ncol = (K.chi[0] - K.clo[0] + 1) * (K.chi[1] - K.clo[1] + 1);
   for (int cbase = 0; cbase < ncol; cbase += 64) {
-    // 1. this lane's column: culled, z run clipped, as up to two bead ranges
-    int b0[2] = {0, 0}, ln[2] = {0, 0};
-    const int k = cbase + lane;
-    if (k < ncol) {
-      const int rx = K.clo[0] + k / ncy, ry = K.clo[1] + k % ncy;
-      const float gx = K.whole[0] ? 0.f
-                                  : fmaxf(0.f, fmaxf(rx * K.h[0] - (K.p0[0] + K.hi[0]),
-                                                     (K.p0[0] + K.lo[0]) - (rx + 1) * K.h[0]));
-      const float gy = K.whole[1] ? 0.f
-                                  : fmaxf(0.f, fmaxf(ry * K.h[1] - (K.p0[1] + K.hi[1]),
-                                                     (K.p0[1] + K.lo[1]) - (ry + 1) * K.h[1]));
-      const float d2 = gx * gx + gy * gy;
-      if (d2 < rclm2) {
-        int cx = K.whole[0] ? rx : K.c0[0] + rx;
-        int cy = K.whole[1] ? ry : K.c0[1] + ry;
-        cx += cx < 0 ? nx : (cx >= nx ? -nx : 0);
-        cy += cy < 0 ? ny : (cy >= ny ? -ny : 0);
-        int zlo = 0, zhi = nz - 1;
-        if (!K.whole[2]) {
-          const float zr = sqrtf(rclm2 - d2);
-          zlo = K.c0[2] + (int)floorf((K.p0[2] + K.lo[2] - zr) * K.ih[2]);
-          zhi = K.c0[2] + (int)floorf((K.p0[2] + K.hi[2] + zr) * K.ih[2]);
-          if (zhi - zlo + 1 >= nz) {
-            zlo = 0;
-            zhi = nz - 1;
-          }
-        }
-        const int colbase = R.cell_off + (cx * ny + cy) * nz;
-        if (zlo < 0) {
-          b0[0] = start[colbase + zlo + nz];
-          ln[0] = start[colbase + nz] - b0[0];
-          b0[1] = start[colbase];
-          ln[1] = start[colbase + zhi + 1] - b0[1];
-        } else if (zhi >= nz) {
-          b0[0] = start[colbase + zlo];
-          ln[0] = start[colbase + nz] - b0[0];
-          b0[1] = start[colbase];
-          ln[1] = start[colbase + zhi - nz + 1] - b0[1];
-        } else {
-          b0[0] = start[colbase + zlo];
-          ln[0] = start[colbase + zhi + 1] - b0[0];
-        }
-      }
-    }
-    // 2. compact the non-empty ranges into the segment list
-    int nseg = 0;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const bool has = ln[q] > 0;
-      const unsigned long long m = __ballot(has);
-      if (has) {
-        const int p = nseg + lanes_below(m);
-        seg_b[p] = b0[q];
-        seg_l[p] = ln[q];
-      }
-      nseg += __popcll(m);
-    }
-    __builtin_amdgcn_wave_barrier();
-    // 3. expand segments into the candidate buffer (a segment too long for
-    //    the room left is split across rounds), then visit the round
+    const int nseg = column_segments<CI, HALF>(K, R, start, first, cbase, seg_b, seg_l);
+    // expand segments into the candidate buffer (a segment too long for the
+    // room left is split across rounds), then visit the round
     int sn = 0, soff = 0;
     while (sn < nseg) {
       const int s = sn + lane;
@@ -480,6 +522,47 @@ __device__ inline void lane_zero(Lane<T>& L) {
   L.cnt = 0;
 }
 
+// The real-space bracket of eq. ewald for one type pair at r^2 = r2 > 0:
+// phi = [erf(alpha r) - erf(beta r)]/r and g = -(1/r) dphi/dr; ea receives
+// exp(-alpha^2 r^2) where the evaluation computes it (left as is in the
+// series branch).  cexpb = -beta^2 log2(e), tsb = (2/sqrt(pi)) beta.
+template <typename T>
+__device__ inline void bracket(const ElecPar<T>& p, T r2, T beta, T beta2, T cexpb, T tsb, T& phi, T& g, T& ea) {
+  constexpr T TSP = (T)1.1283791670955126;  // 2/sqrt(pi)
+  if (r2 < p.rs2) {
+    // series in r^2, free of the cancellation near contact
+    phi = p.cphi[Series<T>::n - 1];
+    g = p.cg[Series<T>::n - 1];
+#pragma unroll
+    for (int n = Series<T>::n - 2; n >= 0; --n) {
+      phi = phi * r2 + p.cphi[n];
+      g = g * r2 + p.cg[n];
+    }
+  } else if constexpr (std::is_same<T, float>::value) {
+    // single precision: both error functions from their Gaussians, which
+    // the force needs anyway (one reciprocal square root, two 2^x, two
+    // reciprocals)
+    // each product rounded on its own (no multiply-add fused across a
+    // difference), so that alpha == beta gives exactly zero
+#pragma clang fp contract(off)
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    ea = gexp2(p.cexp * r2);
+    const float eb = gexp2(cexpb * r2);
+    phi = (erfc_scaled(beta * r) * eb - erfc_scaled(p.alpha * r) * ea) * rinv;
+    g = (phi - (p.tsa * ea - tsb * eb)) * rinv * rinv;
+    (void)beta2;
+  } else {
+    T r = gsqrt(r2);
+    T rinv = (T)1 / r;
+    ea = gexp(-p.alpha2 * r2);
+    phi = (gerfc(beta * r) - gerfc(p.alpha * r)) * rinv;
+    g = (phi - TSP * (p.alpha * ea - beta * gexp(-beta2 * r2))) * rinv * rinv;
+    (void)cexpb;
+    (void)tsb;
+  }
+}
+
 // One ordered pair (i, j) with separation d = r_i - r_j, r2 < rc^2.
 template <typename T, bool ELEC, bool EV, bool ADJ, bool COUNT>
 __device__ inline void interact(Lane<T>& L, T dx, T dy, T dz, T r2, uint32_t pj, const GcmPar<T>* grow,
@@ -514,39 +597,10 @@ __device__ inline void interact(Lane<T>& L, T dx, T dy, T dz, T r2, uint32_t pj,
       }
     }
   } else {
-    constexpr T TSP = (T)1.1283791670955126;  // 2/sqrt(pi)
     const ElecPar<T>& p = erow[tj];
     const T zz = zi * (T)param_z(pj);
     T phi, g, ea = 0;  // ea: exp(-alpha^2 r^2) where computed
-    if (r2 < p.rs2) {
-      // series in r^2, free of the cancellation near contact
-      phi = p.cphi[Series<T>::n - 1];
-      g = p.cg[Series<T>::n - 1];
-#pragma unroll
-      for (int n = Series<T>::n - 2; n >= 0; --n) {
-        phi = phi * r2 + p.cphi[n];
-        g = g * r2 + p.cg[n];
-      }
-    } else if constexpr (std::is_same<T, float>::value) {
-      // single precision: both error functions from their Gaussians, which
-      // the force needs anyway (one reciprocal square root, two 2^x, two
-      // reciprocals)
-      // each product rounded on its own (no multiply-add fused across a
-      // difference), so that alpha == beta gives exactly zero
-#pragma clang fp contract(off)
-      const float rinv = __builtin_amdgcn_rsqf(r2);
-      const float r = r2 * rinv;
-      ea = gexp2(p.cexp * r2);
-      const float eb = gexp2(cexpb * r2);
-      phi = (erfc_scaled(beta * r) * eb - erfc_scaled(p.alpha * r) * ea) * rinv;
-      g = (phi - (p.tsa * ea - tsb * eb)) * rinv * rinv;
-    } else {
-      T r = gsqrt(r2);
-      T rinv = (T)1 / r;
-      ea = gexp(-p.alpha2 * r2);
-      phi = (gerfc(beta * r) - gerfc(p.alpha * r)) * rinv;
-      g = (phi - TSP * (p.alpha * ea - beta * gexp(-beta2 * r2))) * rinv * rinv;
-    }
+    bracket(p, r2, beta, beta2, cexpb, tsb, phi, g, ea);
     fs = lB * zz * g;
     en = lB * zz * phi;
     if (ADJ) {
@@ -971,6 +1025,440 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
   wave_stamp(a.stamps, 1);
 }
 
+// ---------------------------------------------------------------------------
+// Half-shell excluded-volume pairs
+// ---------------------------------------------------------------------------
+//
+// One wavefront per column cluster (at most CI consecutive sorted beads of
+// one cell column).  Its beads are wave-uniform; each lane takes one
+// candidate of the owned columns (for_candidates<HALF>) and evaluates it
+// against every cluster bead, so a pair is evaluated once and both beads
+// get its force: the cluster beads' sums stay in registers until the end
+// (one fixed-order lane reduction), a candidate's goes to the fixed-point
+// accumulator after its chunk.  Integer accumulation keeps reruns
+// bit-identical whatever the order of the atomics.
+
+// Fixed point of a single-precision force component at `scale`, rounded to
+// the nearest integer (ties to even) as llrint would: the fused multiply-add
+// with 1.5 2^52 leaves the integer in the low mantissa bits.  Needs
+// |f| scale < 2^51 (|f| < lim); beyond, or not finite, the status bit is set
+// and 0 returned.
+__device__ inline long long fixed_of(float f, double scale, float lim, unsigned int* status) {
+  if (!(fabsf(f) < lim)) {
+    atomicOr(status, (unsigned)STATUS_FORCE_OVERFLOW);
+    return 0;
+  }
+  return __double_as_longlong(fma((double)f, scale, 6755399441055744.0)) - 0x4338000000000000LL;
+}
+__device__ inline long long fixed_of(double f, double scale, float, unsigned int* status) {
+  return to_fixed(f, scale, status);
+}
+
+// DPP lane moves within rows of 16 lanes (all sources valid).
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp_f(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int DPP_ROW_ROR8 = 0x128, DPP_ROW_HALF_MIRROR = 0x141, DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E;
+
+// a + b after exchanging the upper 32 lanes of a with the lower 32 of b
+// (lanes 0-31: the sum of a over lanes l and l + 32; lanes 32-63: of b).
+__device__ inline float swap32_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// The same within each half for rows of 16 (rows 0, 2: a; rows 1, 3: b).
+__device__ inline float swap16_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline double swap32_sum(double a, double b) {
+  const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+  const double p = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  const double q = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  return p + q;
+}
+__device__ inline double swap16_sum(double a, double b) {
+  const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+  const double p = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  const double q = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  return p + q;
+}
+
+// Sums of V per-lane values over the wavefront, in a fixed order: lanes of
+// row r (lanes 16 r .. 16 r + 15) end with u[m] = the total of
+// v[r V/4 + m], m < V/4.
+template <typename T, int V>
+__device__ inline void reduce_rows(const T (&v)[V], T (&u)[V / 4]) {
+  static_assert(V % 4 == 0, "four rows");
+  T w[V / 2];
+#pragma unroll
+  for (int m = 0; m < V / 2; ++m) w[m] = swap32_sum(v[m], v[m + V / 2]);
+#pragma unroll
+  for (int m = 0; m < V / 4; ++m) {
+    T t = swap16_sum(w[m], w[m + V / 4]);
+    t += dpp_f<DPP_ROW_ROR8>(t);
+    t += dpp_f<DPP_ROW_HALF_MIRROR>(t);
+    t += dpp_f<DPP_XOR1>(t);
+    t += dpp_f<DPP_XOR2>(t);
+    u[m] = t;
+  }
+}
+
+// Pair tables of the half-shell kernel: (-bl, fC) and C per type pair.
+template <typename T>
+struct HalfPar {
+  T nb, fc;
+};
+// Pair tables of the half-shell kernels: excluded volume (-bl, fC) and C per
+// type pair, or the real-space bracket's coefficients.
+template <typename T, bool ELEC>
+struct HalfTab {
+  HalfPar<T> p[ELEC ? 1 : MAXT * MAXT];
+  T c[ELEC ? 1 : MAXT * MAXT];
+  ElecPar<T> e[ELEC ? MAXT * MAXT : 1];
+};
+
+// A cluster bead as the half-shell kernels read it.
+template <typename T>
+struct IBead {
+  T x, y, z;  // relative to bead 0
+  int trow;   // type x MAXT: its row of the pair tables
+  T q;        // charge number
+};
+
+// ELEC: the charged beads (their compacted records and cell list), the
+// real-space bracket of eq. ewald in place of eq. u_ex; forces go to the
+// sorted index of each charged bead.
+//
+// Per cluster: the owned column runs (column_segments<HALF>) are read 64
+// consecutive beads at a time, one per lane; a bead within the list cutoff
+// of the cluster's bounding box joins a 128-entry LDS ring of pending
+// candidates, and every 64 pending candidates are evaluated at once, a lane
+// per candidate against every cluster bead.  In the cluster's frame (bead 0's;
+// every column cluster in bulk) the ring holds the candidate's position
+// relative to bead 0, so a pair costs a subtraction per axis; otherwise the
+// fixed-point record, and each pair takes its own minimum image.
+template <typename T, int CI, bool EV, bool ELEC>
+__global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
+  constexpr int NV = 3 * CI;
+  __shared__ double red[NL_WAVES];
+  __shared__ HalfTab<T, ELEC> S;
+  __shared__ int s_sb[NL_WAVES][NL_SEG];
+  __shared__ int s_sl[NL_WAVES][NL_SEG];
+  __shared__ uint4 s_ring[NL_WAVES][RING];
+  __shared__ int s_rj[NL_WAVES][RING];  // candidate index
+  __shared__ int s_rf[NL_WAVES][RING];  // its force slot (sorted bead index)
+  __shared__ int s_cand[NL_WAVES][NL_CAND];
+  __shared__ IBead<T> s_ib[NL_WAVES][ELEC ? 1 : CI];
+  wave_stamp(a.stamps, 0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const Tile tl = a.tiles[blockIdx.x];
+  const RepDesc& R = a.rep[tl.rep];
+  const uint4* __restrict__ pk = a.pk;
+  const int slot = tl.first + wave;
+  // tl.bead0: the replica's first cluster slot
+  const bool active = wave < tl.count && slot - tl.bead0 < a.hncl[tl.rep];
+  int2 info = make_int2(0, 1);
+  if (active) info = a.cl[slot];
+  const int first = info.x, ni = info.y;
+  uint4 me = make_uint4(0u, 0u, 0u, 0u);
+  if (active) me = pk[first + (lane < ni ? lane : 0)];
+  if (threadIdx.x < MAXT * MAXT) {
+    const size_t tb = (size_t)tl.rep * MAXT * MAXT + threadIdx.x;
+    if (ELEC) {
+      S.e[threadIdx.x] = reinterpret_cast<const ElecPar<T>*>(a.elec)[tb];
+    } else {
+      const GcmPar<T> g = reinterpret_cast<const GcmPar<T>*>(a.gcm)[tb];
+      S.p[threadIdx.x] = HalfPar<T>{-g.bl, g.fC};
+      S.c[threadIdx.x] = g.C;
+    }
+  }
+  __syncthreads();
+  double e = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
+  if (active) {
+    Cluster<CI> K;
+    make_cluster(K, me, R);
+    const bool frame = in_frame(K, R);
+    const T sx = (T)R.scaled[0], sy = (T)R.scaled[1], sz = (T)R.scaled[2];
+    const T rc2 = (T)R.rc2;
+    // the real-space bracket's constants (as the cluster kernels take them)
+    const T beta = (T)R.beta, beta2 = (T)(R.beta * R.beta), lB = (T)R.lB;
+    T cexpb, tsb;
+    if constexpr (std::is_same<T, float>::value) {
+      const float bf = (float)R.beta;
+      cexpb = -(bf * bf) * 1.44269504088896341f;
+      tsb = 1.12837916709551257f * bf;
+    } else {
+      cexpb = -R.beta * R.beta * 1.4426950408889634;
+      tsb = 1.1283791670955126 * R.beta;
+    }
+    // the cluster beads, wave-uniform: positions relative to bead 0, the
+    // type row of the pair tables and the charge (slots beyond ni: far from
+    // everything, so the unrolled pairs need no branch; the general path
+    // masks them)
+    // (excluded volume: in LDS, every lane reading the same entry, which
+    // keeps the kernel within three wavefronts' registers per SIMD; the
+    // charged pairs' branchy bracket keeps them in registers)
+    IBead<T> ib[CI];
+    IBead<T>* ibl = s_ib[wave];
+#pragma unroll
+    for (int k = 0; k < CI; ++k) {
+      const uint32_t wk = read_lane(me.w, k);
+      ib[k].x = k < ni ? (T)(int)(K.ux[k] - K.ux[0]) * sx : (T)1e18f;
+      ib[k].y = k < ni ? (T)(int)(K.uy[k] - K.uy[0]) * sy : (T)1e18f;
+      ib[k].z = k < ni ? (T)(int)(K.uz[k] - K.uz[0]) * sz : (T)1e18f;
+      ib[k].trow = param_type(wk) * MAXT;
+      ib[k].q = (T)param_z(wk);
+      if (!ELEC && lane == k) ibl[k] = ib[k];
+    }
+    T fx[CI], fy[CI], fz[CI];
+#pragma unroll
+    for (int k = 0; k < CI; ++k) fx[k] = fy[k] = fz[k] = 0;
+    const float lim = (float)(2251799813685248.0 / a.fscale);  // 2^51 / scale
+    const bool rel = std::is_same<T, float>::value && frame;
+    uint4* ring = s_ring[wave];
+    int* rj = s_rj[wave];
+    int* rf = s_rf[wave];
+    // every slot of the ring is written before a drain can read it
+    ring[lane] = ring[64 + lane] = make_uint4(0u, 0u, 0u, 0u);
+    rj[lane] = rj[64 + lane] = -1;
+    rf[lane] = rf[64 + lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    int head = 0, tail = 0;  // wave-uniform: candidates evaluated / appended
+    // n <= 64 pending candidates from head, one per lane (head is a multiple
+    // of 64 here: every drain but the last takes exactly 64).  FRAME: ring
+    // positions relative to bead 0; MASK: the drain holds cluster beads,
+    // whose pairs with the cluster count only for k < j - first.
+    auto drain = [&](int n) {
+      const int q = (head & 64) + lane;
+      const bool valid = lane < n;
+      const uint4 rec = ring[q];
+      const int j = valid ? rj[q] : -1;
+      const int fj = rf[q];
+      const unsigned jrel = j < 0 ? 0u : (unsigned)(j - first);
+      const bool intra = __ballot(j >= 0 && jrel < (unsigned)ni) != 0ull;
+      auto eval = [&](auto frame_tag, auto mask_tag) {
+        constexpr bool FR = decltype(frame_tag)::value, MASK = decltype(mask_tag)::value;
+        T Dx = 0, Dy = 0, Dz = 0;
+        if (FR) {
+          if (std::is_same<T, float>::value) {
+            Dx = (T)__uint_as_float(rec.x);
+            Dy = (T)__uint_as_float(rec.y);
+            Dz = (T)__uint_as_float(rec.z);
+          } else {
+            Dx = (T)(int)(rec.x - K.ux[0]) * sx;
+            Dy = (T)(int)(rec.y - K.uy[0]) * sy;
+            Dz = (T)(int)(rec.z - K.uz[0]) * sz;
+          }
+          if (!valid) Dx = Dy = Dz = (T)-1e18f;  // beyond the cutoff of every bead
+        }
+        const int tj = param_type(rec.w);
+        const T qj = (T)param_z(rec.w);
+        T gx = 0, gy = 0, gz = 0;
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < CI; ++k) {
+          const IBead<T> bi = ELEC ? ib[k] : ibl[k];
+          T dx, dy, dz;
+          if (FR) {
+            dx = bi.x - Dx;
+            dy = bi.y - Dy;
+            dz = bi.z - Dz;
+          } else {
+            dx = (T)(int)(K.ux[k] - rec.x) * sx;
+            dy = (T)(int)(K.uy[k] - rec.y) * sy;
+            dz = (T)(int)(K.uz[k] - rec.z) * sz;
+          }
+          const T r2 = dx * dx + dy * dy + dz * dz;
+          bool in = r2 < rc2;
+          if (MASK || !FR) in = in && jrel > (unsigned)k;
+          if (!FR) in = in && k < ni && valid;
+          const int ix = bi.trow + tj;
+          T fs, en;
+          if (ELEC) {
+            // a pair that does not count is evaluated at r = 1 (finite for
+            // every bead, also on itself) and weighted by zero
+            T phi, g, ea;
+            bracket(S.e[ix], in ? r2 : (T)1, beta, beta2, cexpb, tsb, phi, g, ea);
+            const T c = in ? lB * (bi.q * qj) : (T)0;
+            fs = c * g;
+            en = c * phi;
+          } else {
+            const HalfPar<T> hp = S.p[ix];
+            const T ex = gexp2(in ? hp.nb * r2 : -(T)INFINITY);
+            fs = hp.fc * ex;
+            en = EV ? S.c[ix] * ex : (T)0;
+          }
+          // the candidate's sum is kept with the cluster bead's sign and
+          // negated once: two fused multiply-adds per axis
+          fx[k] = fma(fs, dx, fx[k]);
+          fy[k] = fma(fs, dy, fy[k]);
+          fz[k] = fma(fs, dz, fz[k]);
+          gx = fma(fs, dx, gx);
+          gy = fma(fs, dy, gy);
+          gz = fma(fs, dz, gz);
+          any = any || in;
+          if (EV) {
+            const double fxd = (double)(fs * dx), fyd = (double)(fs * dy), fzd = (double)(fs * dz);
+            e += (double)en;
+            w0 += fxd * (double)dx;
+            w1 += fyd * (double)dy;
+            w2 += fzd * (double)dz;
+            w3 += fxd * (double)dy;
+            w4 += fxd * (double)dz;
+            w5 += fyd * (double)dz;
+          }
+        }
+        if (j >= 0 && any) {
+          atomicAdd((unsigned long long*)&a.F[0][fj], (unsigned long long)fixed_of(-gx, a.fscale, lim, a.status));
+          atomicAdd((unsigned long long*)&a.F[1][fj], (unsigned long long)fixed_of(-gy, a.fscale, lim, a.status));
+          atomicAdd((unsigned long long*)&a.F[2][fj], (unsigned long long)fixed_of(-gz, a.fscale, lim, a.status));
+        }
+      };
+      using TT = std::true_type;
+      using FF = std::false_type;
+      if (!frame)
+        eval(FF{}, TT{});
+      else if (intra)
+        eval(TT{}, TT{});
+      else
+        eval(TT{}, FF{});
+      head += n;
+    };
+    // the list cutoff around the cluster's bounding box (relative to bead 0)
+    const float rcl2 = K.rcl * K.rcl;
+    int* cand = s_cand[wave];
+    // the candidates cand[0, total), 64 per chunk (one per lane): those within
+    // the list cutoff of the box join the ring
+    auto filter = [&](int total) {
+      // the records of FB chunks are requested together (one memory latency
+      // for all of them), and the charged beads' sorted indices with them
+      constexpr int FB = 4;
+      for (int p0 = 0; p0 < total; p0 += 64 * FB) {
+        int jj[FB], ff[FB];
+        uint4 pp[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+          const int q = p0 + 64 * u + lane;
+          jj[u] = q < total ? cand[q] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+          pp[u] = pk[jj[u] < 0 ? first : jj[u]];
+          ff[u] = ELEC ? a.qidx[jj[u] < 0 ? first : jj[u]] : jj[u];
+        }
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+          if (p0 + 64 * u >= total) break;
+          const int j = jj[u];
+          const bool valid = j >= 0;
+          const uint4 pj = pp[u];
+          bool hit;
+          uint4 rec = pj;
+          if (frame) {
+            const float Dx = (float)(int)(pj.x - K.ux[0]) * R.scalef[0];
+            const float Dy = (float)(int)(pj.y - K.uy[0]) * R.scalef[1];
+            const float Dz = (float)(int)(pj.z - K.uz[0]) * R.scalef[2];
+            const float bx = fmaxf(0.f, fmaxf(K.lo[0] - Dx, Dx - K.hi[0]));
+            const float by = fmaxf(0.f, fmaxf(K.lo[1] - Dy, Dy - K.hi[1]));
+            const float bz = fmaxf(0.f, fmaxf(K.lo[2] - Dz, Dz - K.hi[2]));
+            hit = valid && bx * bx + by * by + bz * bz < rcl2;
+            if (rel) rec = make_uint4(__float_as_uint(Dx), __float_as_uint(Dy), __float_as_uint(Dz), pj.w);
+          } else {
+            hit = valid && near_exact(K, pj, R);
+          }
+          const unsigned long long m = __ballot(hit);
+          if (hit) {
+            const int q = (tail + lanes_below(m)) & (RING - 1);
+            ring[q] = rec;
+            rj[q] = j;
+            rf[q] = ff[u];
+          }
+          tail += __popcll(m);
+          __builtin_amdgcn_wave_barrier();
+          if (tail - head >= 64) drain(64);
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+    };
+    const int ncol = (K.chi[0] - K.clo[0] + 1) * (K.chi[1] - K.clo[1] + 1);
+    for (int cbase = 0; cbase < ncol; cbase += 64) {
+      const int nseg = column_segments<CI, true>(K, R, a.start, first, cbase, s_sb[wave], s_sl[wave]);
+      // the owned column runs packed into the candidate buffer (filtered
+      // whenever it fills), so that filter chunks are full
+      int pos = 0;
+      for (int sg = 0; sg < nseg; ++sg) {
+        const int sb = __builtin_amdgcn_readfirstlane(s_sb[wave][sg]);
+        const int sl = __builtin_amdgcn_readfirstlane(s_sl[wave][sg]);
+        for (int off = 0; off < sl;) {
+          const int take = min(sl - off, NL_CAND - pos);
+          for (int t = lane; t < take; t += 64) cand[pos + t] = sb + off + t;
+          pos += take;
+          off += take;
+          __builtin_amdgcn_wave_barrier();
+          if (pos == NL_CAND) {
+            filter(pos);
+            pos = 0;
+          }
+        }
+      }
+      if (pos > 0) filter(pos);
+    }
+    if (tail > head) drain(tail - head);
+    // the cluster beads' sums: row r of the wavefront holds beads
+    // r CI/4 .. r CI/4 + CI/4 - 1 (CI/4 beads x 3 axes per row)
+    T v[NV], u[NV / 4];
+#pragma unroll
+    for (int k = 0; k < CI; ++k) {
+      v[3 * k] = fx[k];
+      v[3 * k + 1] = fy[k];
+      v[3 * k + 2] = fz[k];
+    }
+    reduce_rows<T, NV>(v, u);
+    const int row = lane >> 4, t = lane & 15;
+    if (t < CI / 4) {
+      T f3[3] = {0, 0, 0};
+#pragma unroll
+      for (int b = 0; b < CI / 4; ++b)
+        if (t == b) {
+          f3[0] = u[3 * b];
+          f3[1] = u[3 * b + 1];
+          f3[2] = u[3 * b + 2];
+        }
+      const int k = row * (CI / 4) + t;
+      if (k < ni) {
+        const int fi = ELEC ? a.qidx[first + k] : first + k;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          atomicAdd((unsigned long long*)&a.F[c][fi],
+                    (unsigned long long)fixed_of(f3[c], a.fscale, lim, a.status));
+      }
+    }
+  }
+  if (EV) {
+    // every pair once: no halving
+    double v7[7] = {e, w0, w1, w2, w3, w4, w5};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      const double t = block_sum(v7[k], red);
+      if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
+    }
+  }
+  wave_stamp(a.stamps, 1);
+}
+
 template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
 void launch_one(hipStream_t s, const PairLaunch& a) {
   dim3 g(a.ntiles), b(NL_WAVES * 64);
@@ -1029,6 +1517,35 @@ void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bo
   else
     dispatch_ci<float, true>(s, a, ev, adjoint, false);
 }
+
+template <bool ELEC>
+void launch_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev) {
+  if (a.ntiles <= 0) return;
+  dim3 g(a.ntiles), b(NL_WAVES * 64);
+#define GCME_HALF(T, CI)                                                          \
+  do {                                                                             \
+    if (ev)                                                                        \
+      hipLaunchKernelGGL((k_pair_half<T, CI, true, ELEC>), g, b, 0, s, a);        \
+    else                                                                           \
+      hipLaunchKernelGGL((k_pair_half<T, CI, false, ELEC>), g, b, 0, s, a);       \
+  } while (0)
+  if (fp64) {
+    if (a.ci == 8)
+      GCME_HALF(double, 8);
+    else
+      GCME_HALF(double, 4);
+  } else {
+    if (a.ci == 8)
+      GCME_HALF(float, 8);
+    else
+      GCME_HALF(float, 4);
+  }
+#undef GCME_HALF
+}
+
+void launch_pair_gcm_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev) { launch_half<false>(s, a, fp64, ev); }
+
+void launch_pair_elec_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev) { launch_half<true>(s, a, fp64, ev); }
 
 int pair_waves_per_block() { return NL_WAVES; }
 

@@ -239,13 +239,14 @@ class GCMe:
         return dict(cells_per_cutoff=t.cells_per_cutoff, beads_per_cluster=t.beads_per_cluster,
                     charges_per_cluster=t.charges_per_cluster, list_slack_pct=t.list_slack_pct,
                     direct_pairs=t.direct_pairs, stream_layout=t.stream_layout, mesh_tile_x=t.mesh_tile_x,
-                    mesh_tile_y=t.mesh_tile_y, gather_tile_x=t.gather_tile_x, gather_tile_y=t.gather_tile_y)
+                    mesh_tile_y=t.mesh_tile_y, gather_tile_x=t.gather_tile_x, gather_tile_y=t.gather_tile_y,
+                    half_pairs=t.half_pairs)
 
     def set_tuning(self, cells_per_cutoff=-1, beads_per_cluster=-1, charges_per_cluster=-1, list_slack_pct=-1,
                    direct_pairs=-1, stream_layout=-1, mesh_tile_x=-1, mesh_tile_y=-1, gather_tile_x=-1,
-                   gather_tile_y=-1):
+                   gather_tile_y=-1, half_pairs=-1):
         t = B.gcme_tuning(cells_per_cutoff, beads_per_cluster, charges_per_cluster, list_slack_pct, direct_pairs,
-                          stream_layout, mesh_tile_x, mesh_tile_y, gather_tile_x, gather_tile_y)
+                          stream_layout, mesh_tile_x, mesh_tile_y, gather_tile_x, gather_tile_y, half_pairs)
         B.check(self.h, self.lib.gcme_set_tuning(self.h, C.byref(t)))
 
     def profile_step(self, n_reps: int = 10) -> dict:
