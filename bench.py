@@ -184,49 +184,8 @@ def main():
     # charged pairs within the cutoff at the final positions (for the
     # charged-pair stages' algorithmic counts)
     cc_pairs = charged_pairs(eng, w)
-
-    # algorithmic work per launch of each stage: (bound, amount); alu amounts
-    # are FLOP, hbm amounts bytes (kernels table)
-    K = w.grid
-    nch = K[0] * K[1] * (K[2] // 2 + 1)
-    cs = 16 if args.precision == "fp64" else 8
-    peak_alu = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
-    # a list-free pair kernel does its neighbour search itself: its stage
-    # carries the distance tests too (and the list stage is empty)
     direct = tuning.get("direct_pairs", 0)
-    gcm_flop = FLOP_PER_GCM_PAIR + (FLOP_PER_DISTANCE_TEST if direct & 1 else 0)
-    elec_flop = FLOP_PER_ELEC_PAIR + (FLOP_PER_DISTANCE_TEST if direct & 2 else 0)
-    alg = {
-        "int_first": ("hbm", w.N * (12 + 24 + 24 + 12 + 24 + 24)),
-        "sort": ("hbm", w.N * (12 + 4 + 4 + 12 + 24 + 4 + 4 + 12 + 24 + 4 + 4 + 16)),
-        "list_gcm": ("alu", FLOP_PER_DISTANCE_TEST * pairs),
-        "pair_gcm": ("alu", gcm_flop * pairs),
-        "list_elec": ("alu", FLOP_PER_DISTANCE_TEST * cc_pairs),
-        "pair_elec": ("alu", elec_flop * cc_pairs),
-        "spread_z": ("hbm", nq * 16 + nch * cs),
-        "fft_y": ("hbm", 2 * nch * cs),
-        "fft_conv": ("hbm", 2 * nch * cs),
-        "fft_y_inv": ("hbm", 2 * nch * cs),
-        "z_gather": ("hbm", nch * cs + nq * (16 + 4 + 24)),
-        "int_last": ("hbm", w.N * (12 + 24 + 24 + 12 + 24 + 4)),
-    }
-
-    def roof_of(name):
-        bound, amount = alg[name]
-        t = stages[name] * 1e-3
-        if t <= 0:
-            return None
-        if bound == "alu":
-            ach = amount / t / 1e12
-            return {"bound": "alu", "kernel": name, "achieved": ach, "peak": peak_alu, "unit": "TFLOP/s",
-                    "frac": ach / peak_alu}
-        ach = amount / t / 1e9
-        return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS}
-
-    skip = {"list_gcm"} if direct & 1 else set()
-    skip |= {"list_elec"} if direct & 2 else set()
-    stage_roof = {k: roof_of(k) for k in stages if k in alg and stages[k] > 0 and k not in skip}
+    stage_roof = stage_rooflines(w, stages, tuning, pairs, cc_pairs, nq, args.precision)
     # the dominant kernel: the longest stage that is one kernel launch (the
     # sort stage is four)
     dom = max((k for k in stage_roof if k not in MULTI_KERNEL_STAGES), key=lambda k: stages[k])
@@ -293,6 +252,58 @@ def main():
     print(json.dumps(out), flush=True)
     if args.no_extras:
         eng.close()
+
+
+def stage_rooflines(w, stages, tuning, pairs, cc_pairs, nq, precision):
+    """Each one-kernel stage's achieved rate against its bound: algorithmic
+    work per launch (FLOP for the pair kernels, bytes for the others; the
+    kernels table of the design notes) over the stage's measured launch
+    time."""
+    K = w.grid
+    nch = K[0] * K[1] * (K[2] // 2 + 1)
+    cs = 16 if precision == "fp64" else 8
+    peak_alu = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
+    # a list-free pair kernel does its neighbour search itself: its stage
+    # carries the distance tests too (and the list stage is empty)
+    direct = tuning.get("direct_pairs", 0)
+    half = tuning.get("half_pairs", 0)
+    search_g = (direct & 1) or (half & 3)
+    search_q = (direct & 2) or (half >> 2) & 3
+    gcm_flop = FLOP_PER_GCM_PAIR + (FLOP_PER_DISTANCE_TEST if search_g else 0)
+    elec_flop = FLOP_PER_ELEC_PAIR + (FLOP_PER_DISTANCE_TEST if search_q else 0)
+    alg = {
+        "int_first": ("hbm", w.N * (12 + 24 + 24 + 12 + 24 + 24)),
+        "sort": ("hbm", w.N * (12 + 4 + 4 + 12 + 24 + 4 + 4 + 12 + 24 + 4 + 4 + 16)),
+        "list_gcm": ("alu", FLOP_PER_DISTANCE_TEST * pairs),
+        "pair_gcm": ("alu", gcm_flop * pairs),
+        "list_elec": ("alu", FLOP_PER_DISTANCE_TEST * cc_pairs),
+        "pair_elec": ("alu", elec_flop * cc_pairs),
+        "spread_z": ("hbm", nq * 16 + nch * cs),
+        "fft_y": ("hbm", 2 * nch * cs),
+        "fft_conv": ("hbm", 2 * nch * cs),
+        "fft_y_inv": ("hbm", 2 * nch * cs),
+        "z_gather": ("hbm", nch * cs + nq * (16 + 4 + 24)),
+        "int_last": ("hbm", w.N * (12 + 24 + 24 + 12 + 24 + 4)),
+    }
+
+    def roof_of(name):
+        bound, amount = alg[name]
+        t = stages[name] * 1e-3
+        if t <= 0:
+            return None
+        if bound == "alu":
+            ach = amount / t / 1e12
+            return {"bound": "alu", "kernel": name, "achieved": ach, "peak": peak_alu, "unit": "TFLOP/s",
+                    "frac": ach / peak_alu, "launch_us": stages[name] * 1e3}
+        ach = amount / t / 1e9
+        return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "launch_us": stages[name] * 1e3}
+
+    # list stages of list-free pairs are empty; with column clusters the list
+    # stage is the column pass (not an algorithmic step of its own)
+    skip = {"list_gcm"} if search_g else set()
+    skip |= {"list_elec"} if search_q else set()
+    return {k: roof_of(k) for k in stages if k in alg and stages[k] > 0 and k not in skip}
 
 
 def time_steps(eng, steps, warmup):
@@ -381,6 +392,13 @@ def extra_workloads(w):
         res[prec] = {"ms_per_step": ms, "pair_interactions_per_s": pairs * 1000.0 / ms,
                      "ns_per_day": 1000.0 / ms * w4.dt * TAU_PS * 86400.0 / 1000.0, "pairs_within_cutoff": pairs,
                      "tuning": tun}
+        if prec == "mixed":
+            # every kernel of the step against its bound (as for the headline)
+            st = eng.time_stages(3)
+            eng.sync()
+            nq4 = int((w4.z != 0).sum())
+            res[prec]["stage_ms"] = st
+            res[prec]["stage_roofline"] = stage_rooflines(w4, st, tun, pairs, charged_pairs(eng, w4), nq4, prec)
         eng.close()
     res["mixed_force_rel_rms_vs_fp64"] = float(np.linalg.norm(fr["mixed"] - fr["fp64"]) / np.linalg.norm(fr["fp64"]))
     out[w4.name] = res

@@ -362,19 +362,24 @@ typedef struct {
                                     the longer side until they fit) */
     int32_t gather_tile_x;       /* the same for the fused gather pass (0 = the */
     int32_t gather_tile_y;       /* spread's) */
-    int32_t half_pairs;          /* each unordered pair evaluated once (0..3):
-                                    bit 0 excluded volume, bit 1 real-space
-                                    electrostatics.  Clusters are then runs of
+    int32_t half_pairs;          /* column-cluster pair kernels, two bits per
+                                    pair type: bits 0-1 excluded volume, bits
+                                    2-3 real-space electrostatics; 0 = the
+                                    kernels of direct_pairs, 1 = half shell,
+                                    2 = both ends.  Clusters are then runs of
                                     consecutive beads of one cell column
                                     (beads_per_cluster / charges_per_cluster
                                     4 or 8; 2 is taken as 4), rebuilt after
-                                    every sort; a cluster evaluates the beads
-                                    of its own column that follow it and of
-                                    the columns ahead of its own, and both
-                                    beads of a pair receive its force.
+                                    every sort.  Half shell: a cluster
+                                    evaluates the beads of its own column
+                                    that follow it and of the columns ahead
+                                    of its own, each unordered pair once, and
+                                    both beads of a pair receive its force.
+                                    Both ends: every column within reach,
+                                    each pair from both of its beads' clusters.
                                     Evaluations that ask for parameter
                                     derivatives, and pair counting, use the
-                                    list-free or list path of direct_pairs. */
+                                    kernels of direct_pairs. */
 } gcme_tuning;
 
 gcme_status gcme_get_tuning(gcme_handle h, gcme_tuning* t);

@@ -511,6 +511,10 @@ void plan_clusters(gcme_handle h, bool charged, int ci, std::vector<int2>& cl, s
   cap = ((int)std::ceil(cmax) + 63) & ~63;
 }
 
+// The column-cluster mode of the excluded-volume (charged) pairs:
+// 0 = cluster kernels, 1 = half shell, 2 = both ends (tuning half_pairs).
+int col_mode(gcme_handle h, bool charged) { return (h->tune.half_pairs >> (charged ? 2 : 0)) & 3; }
+
 gcme_status build_plan(gcme_handle h) {
   hipStream_t s = h->stream;
   HIPCHK(h, hipSetDevice(h->device));
@@ -786,7 +790,7 @@ gcme_status build_plan(gcme_handle h) {
   h->ntiles_h = h->ntiles_hq = 0;
   // (beyond what the column pass can stage, the cluster kernels run instead)
   const bool half_fits = h->ncols + 2 * R <= col_clusters_max_entries();
-  if ((h->tune.half_pairs & 3) && half_fits) {
+  if ((col_mode(h, false) || col_mode(h, true)) && half_fits) {
     std::vector<int2> coltab;
     coltab.reserve((size_t)h->ncols + 1);
     for (int r = 0; r < R; ++r) {
@@ -827,13 +831,13 @@ gcme_status build_plan(gcme_handle h) {
     HIPCHK(h, part.alloc((size_t)std::max(1, ntiles) * PART_W * 8));
     return GCME_OK;
   };
-  if ((h->tune.half_pairs & 1) && half_fits) {
+  if (col_mode(h, false) && half_fits) {
     h->hci = h->tune.beads_per_cluster < 4 ? 4 : h->tune.beads_per_cluster;
     gcme_status e = plan_half(h->nb, h->hci, h->d_hbase, h->d_hcl, h->d_hncl, h->d_htiles, h->part_h, h->d_off_h,
                               h->ntiles_h);
     if (e != GCME_OK) return e;
   }
-  if ((h->tune.half_pairs & 2) && h->NQ > 0 && half_fits) {
+  if (col_mode(h, true) && h->NQ > 0 && half_fits) {
     h->hqci = h->tune.charges_per_cluster < 4 ? 4 : h->tune.charges_per_cluster;
     gcme_status e = plan_half(h->nq, h->hqci, h->d_hqbase, h->d_hqcl, h->d_hqncl, h->d_hqtiles, h->part_hq,
                               h->d_off_hq, h->ntiles_hq);
@@ -1121,8 +1125,8 @@ unsigned long long* stamps_for(gcme_handle h, int stage) {
 // Whether an evaluation's excluded-volume (charged) pairs take the
 // half-shell kernel (not with parameter derivatives, which the cluster
 // kernels provide).
-bool half_gcm(gcme_handle h, bool adj) { return (h->tune.half_pairs & 1) && !adj && h->ntiles_h > 0; }
-bool half_elec(gcme_handle h, bool adj) { return (h->tune.half_pairs & 2) && !adj && h->ntiles_hq > 0; }
+bool half_gcm(gcme_handle h, bool adj) { return col_mode(h, false) && !adj && h->ntiles_h > 0; }
+bool half_elec(gcme_handle h, bool adj) { return col_mode(h, true) && !adj && h->ntiles_hq > 0; }
 
 PairLaunch pair_args_half(gcme_handle h, bool charged) {
   PairLaunch a = pair_args(h, charged);
@@ -1166,7 +1170,7 @@ void enqueue_gcm_pairs(gcme_handle h, hipStream_t s, bool ev, bool adj) {
     launch_col_clusters(s, c);
     PairLaunch g = pair_args_half(h, false);
     g.stamps = stamps_for(h, ST_PAIR_GCM);
-    launch_pair_gcm_half(s, g, h->fp64, ev);
+    launch_pair_gcm_col(s, g, h->fp64, ev, col_mode(h, false) == 1);
     return;
   }
   PairLaunch g = pair_args(h, false);
@@ -1184,7 +1188,7 @@ void enqueue_elec_pairs(gcme_handle h, hipStream_t s, bool ev, bool adj) {
     launch_col_clusters(s, c);
     PairLaunch q = pair_args_half(h, true);
     q.stamps = stamps_for(h, ST_PAIR_ELEC);
-    launch_pair_elec_half(s, q, h->fp64, ev);
+    launch_pair_elec_col(s, q, h->fp64, ev, col_mode(h, true) == 1);
     return;
   }
   PairLaunch q = pair_args(h, true);
@@ -1976,7 +1980,8 @@ gcme_status gcme_set_tuning(gcme_handle h, const gcme_tuning* t) {
     n.direct_pairs = t->direct_pairs;
   }
   if (t->half_pairs >= 0) {
-    if (t->half_pairs > 3) return fail(h, GCME_EINVAL, "half_pairs in 0..3");
+    if ((t->half_pairs & 3) > 2 || ((t->half_pairs >> 2) & 3) > 2 || t->half_pairs > 15)
+      return fail(h, GCME_EINVAL, "half_pairs: two bits per pair type, each 0..2");
     n.half_pairs = t->half_pairs;
   }
   if (t->stream_layout >= 0) {
@@ -2052,16 +2057,17 @@ gcme_status gcme_autotune(gcme_handle h) {
   std::vector<std::pair<float, gcme_tuning>> cands;
   const int ncc_list[] = {2, 3, 4};
   const int ci_list[] = {2, 4, 8};
-  // per pair type: 0 = neighbour lists, 1 = list-free, 2 = half-shell
-  // (clusters of 4 or 8)
+  // per pair type: 0 = neighbour lists, 1 = list-free, 2 = column clusters
+  // half shell, 3 = column clusters both ends (clusters of 4 or 8)
   for (int ncc : ncc_list)
     for (int cg : ci_list)
       for (int cq : ci_list)
-        for (int mg = 0; mg < 3; ++mg)
-          for (int mq = 0; mq < 3; ++mq) {
+        for (int mg = 0; mg < 4; ++mg)
+          for (int mq = 0; mq < 4; ++mq) {
           if (h->NQ == 0 && (cq != ci_list[0] || mq > 0)) continue;
-          if ((mg == 2 && cg == 2) || (mq == 2 && cq == 2)) continue;
-          const int dp = (mg > 0 ? 1 : 0) | (mq > 0 ? 2 : 0), hp = (mg == 2 ? 1 : 0) | (mq == 2 ? 2 : 0);
+          if ((mg >= 2 && cg == 2) || (mq >= 2 && cq == 2)) continue;
+          const int dp = (mg > 0 ? 1 : 0) | (mq > 0 ? 2 : 0);
+          const int hp = (mg >= 2 ? mg - 1 : 0) | ((mq >= 2 ? mq - 1 : 0) << 2);
           gcme_tuning t{ncc, cg, cq, -1, dp, keep_layout, -1, -1, -1, -1, hp};
           if (gcme_set_tuning(h, &t) != GCME_OK) continue;
           if (build_plan(h) != GCME_OK) continue;
@@ -2260,7 +2266,7 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
         break;
       case 3:
         if (half_gcm(h, false))
-          launch_pair_gcm_half(st2, pair_args_half(h, false), h->fp64, false);
+          launch_pair_gcm_col(st2, pair_args_half(h, false), h->fp64, false, col_mode(h, false) == 1);
         else
           launch_pair_gcm(st2, g, h->fp64, false, false);
         break;
@@ -2272,7 +2278,7 @@ gcme_status gcme_profile_step(gcme_handle h, int32_t n_reps, double* ms) {
         break;
       case 5:
         if (half_elec(h, false))
-          launch_pair_elec_half(st2, pair_args_half(h, true), h->fp64, false);
+          launch_pair_elec_col(st2, pair_args_half(h, true), h->fp64, false, col_mode(h, true) == 1);
         else
           launch_pair_elec(st2, q, h->fp64, false, false);
         break;

@@ -355,15 +355,16 @@ void launch_col_clusters(hipStream_t s, const ColLaunch& a);
 // cluster kernels beyond it).
 int col_clusters_max_entries();
 
-// Half-shell pairs (`half_pairs` tuning bit): each unordered pair within rc
-// is evaluated once, by the cluster that owns it, and both beads receive its
-// force.  Tiles hold up to pair_waves_per_block() cluster slots of one
-// replica (Tile.first: first slot; Tile.bead0: the replica's first slot);
-// a.cl / a.hncl are the column clusters and their per-replica counts.
-void launch_pair_gcm_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev);
-// The same for the real-space electrostatics of the charged beads (a.pk:
-// their compacted records, a.start: their cell list, a.qidx: sorted index).
-void launch_pair_elec_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev);
+// Column-cluster pairs (`half_pairs` tuning field): every unordered pair
+// within rc evaluated once by the cluster that owns it, both beads
+// receiving its force (half), or from both ends with the cluster beads'
+// forces only (!half).  Tiles hold up to pair_waves_per_block() cluster
+// slots of one replica (Tile.first: first slot; Tile.bead0: the replica's
+// first slot); a.cl / a.hncl are the column clusters and their per-replica
+// counts.  The charged variant takes the charged beads' compacted records
+// (a.pk), cell list (a.start) and sorted indices (a.qidx).
+void launch_pair_gcm_col(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool half);
+void launch_pair_elec_col(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool half);
 void launch_pair_gcm(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint);
 void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool adjoint);
 int pair_waves_per_block();

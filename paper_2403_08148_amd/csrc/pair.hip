@@ -36,6 +36,7 @@
 // image is the wrapped 32-bit difference of the fractional fixed-point
 // coordinates (valid because rc <= L/2 is enforced).
 #include <type_traits>
+#include <utility>
 
 #include "gcme_internal.h"
 
@@ -527,7 +528,8 @@ __device__ inline void lane_zero(Lane<T>& L) {
 // exp(-alpha^2 r^2) where the evaluation computes it (left as is in the
 // series branch).  cexpb = -beta^2 log2(e), tsb = (2/sqrt(pi)) beta.
 template <typename T>
-__device__ inline void bracket(const ElecPar<T>& p, T r2, T beta, T beta2, T cexpb, T tsb, T& phi, T& g, T& ea) {
+__device__ __attribute__((always_inline)) inline void bracket(const ElecPar<T>& p, T r2, T beta, T beta2, T cexpb,
+                                                              T tsb, T& phi, T& g, T& ea) {
   constexpr T TSP = (T)1.1283791670955126;  // 2/sqrt(pi)
   if (r2 < p.rs2) {
     // series in r^2, free of the cancellation near contact
@@ -1130,6 +1132,18 @@ struct HalfTab {
   ElecPar<T> e[ELEC ? MAXT * MAXT : 1];
 };
 
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N - 1>) in
+// order: a loop unrolled whatever the size of its body, so that register
+// arrays indexed by the counter stay in registers.
+template <class F, int... I>
+__device__ __attribute__((always_inline)) inline void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __attribute__((always_inline)) inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // A cluster bead as the half-shell kernels read it.
 template <typename T>
 struct IBead {
@@ -1150,8 +1164,12 @@ struct IBead {
 // every column cluster in bulk) the ring holds the candidate's position
 // relative to bead 0, so a pair costs a subtraction per axis; otherwise the
 // fixed-point record, and each pair takes its own minimum image.
-template <typename T, int CI, bool EV, bool ELEC>
-__global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
+//
+// HALF false: every column within reach (both ends of each pair; no
+// candidate atomics, each pair's energy and virial halved), the same ring
+// and evaluation otherwise.
+template <typename T, int CI, bool EV, bool ELEC, bool HALF>
+__global__ __launch_bounds__(NL_WAVES * 64) void k_pair_col(PairLaunch a) {
   constexpr int NV = 3 * CI;
   __shared__ double red[NL_WAVES];
   __shared__ HalfTab<T, ELEC> S;
@@ -1241,7 +1259,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
     // of 64 here: every drain but the last takes exactly 64).  FRAME: ring
     // positions relative to bead 0; MASK: the drain holds cluster beads,
     // whose pairs with the cluster count only for k < j - first.
-    auto drain = [&](int n) {
+    auto drain = [&](int n) __attribute__((always_inline)) {
       const int q = (head & 64) + lane;
       const bool valid = lane < n;
       const uint4 rec = ring[q];
@@ -1249,7 +1267,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
       const int fj = rf[q];
       const unsigned jrel = j < 0 ? 0u : (unsigned)(j - first);
       const bool intra = __ballot(j >= 0 && jrel < (unsigned)ni) != 0ull;
-      auto eval = [&](auto frame_tag, auto mask_tag) {
+      auto eval = [&](auto frame_tag, auto mask_tag) __attribute__((always_inline)) {
         constexpr bool FR = decltype(frame_tag)::value, MASK = decltype(mask_tag)::value;
         T Dx = 0, Dy = 0, Dz = 0;
         if (FR) {
@@ -1268,8 +1286,8 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
         const T qj = (T)param_z(rec.w);
         T gx = 0, gy = 0, gz = 0;
         bool any = false;
-#pragma unroll
-        for (int k = 0; k < CI; ++k) {
+        static_for<CI>([&](auto kc) __attribute__((always_inline)) {
+          constexpr int k = decltype(kc)::value;
           const IBead<T> bi = ELEC ? ib[k] : ibl[k];
           T dx, dy, dz;
           if (FR) {
@@ -1283,18 +1301,20 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
           }
           const T r2 = dx * dx + dy * dy + dz * dz;
           bool in = r2 < rc2;
-          if (MASK || !FR) in = in && jrel > (unsigned)k;
+          // half shell: within the cluster, pairs (k, j) with k < j; both
+          // ends: every cluster bead but the candidate itself
+          if (MASK || !FR) in = in && (HALF ? jrel > (unsigned)k : jrel != (unsigned)k);
           if (!FR) in = in && k < ni && valid;
           const int ix = bi.trow + tj;
-          T fs, en;
+          T fs = 0, en = 0;
           if (ELEC) {
-            // a pair that does not count is evaluated at r = 1 (finite for
-            // every bead, also on itself) and weighted by zero
-            T phi, g, ea;
-            bracket(S.e[ix], in ? r2 : (T)1, beta, beta2, cexpb, tsb, phi, g, ea);
-            const T c = in ? lB * (bi.q * qj) : (T)0;
-            fs = c * g;
-            en = c * phi;
+            if (in) {
+              T phi, g, ea;
+              bracket(S.e[ix], r2, beta, beta2, cexpb, tsb, phi, g, ea);
+              const T c = lB * (bi.q * qj);
+              fs = c * g;
+              en = c * phi;
+            }
           } else {
             const HalfPar<T> hp = S.p[ix];
             const T ex = gexp2(in ? hp.nb * r2 : -(T)INFINITY);
@@ -1320,8 +1340,8 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
             w4 += fxd * (double)dz;
             w5 += fyd * (double)dz;
           }
-        }
-        if (j >= 0 && any) {
+        });
+        if (HALF && j >= 0 && any) {
           atomicAdd((unsigned long long*)&a.F[0][fj], (unsigned long long)fixed_of(-gx, a.fscale, lim, a.status));
           atomicAdd((unsigned long long*)&a.F[1][fj], (unsigned long long)fixed_of(-gy, a.fscale, lim, a.status));
           atomicAdd((unsigned long long*)&a.F[2][fj], (unsigned long long)fixed_of(-gz, a.fscale, lim, a.status));
@@ -1342,7 +1362,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
     int* cand = s_cand[wave];
     // the candidates cand[0, total), 64 per chunk (one per lane): those within
     // the list cutoff of the box join the ring
-    auto filter = [&](int total) {
+    auto filter = [&](int total) __attribute__((always_inline)) {
       // the records of FB chunks are requested together (one memory latency
       // for all of them), and the charged beads' sorted indices with them
       constexpr int FB = 4;
@@ -1395,7 +1415,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
     };
     const int ncol = (K.chi[0] - K.clo[0] + 1) * (K.chi[1] - K.clo[1] + 1);
     for (int cbase = 0; cbase < ncol; cbase += 64) {
-      const int nseg = column_segments<CI, true>(K, R, a.start, first, cbase, s_sb[wave], s_sl[wave]);
+      const int nseg = column_segments<CI, HALF>(K, R, a.start, first, cbase, s_sb[wave], s_sl[wave]);
       // the owned column runs packed into the candidate buffer (filtered
       // whenever it fills), so that filter chunks are full
       int pos = 0;
@@ -1448,12 +1468,12 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_half(PairLaunch a) {
     }
   }
   if (EV) {
-    // every pair once: no halving
+    // half shell: every pair once; both ends: twice, halved
     double v7[7] = {e, w0, w1, w2, w3, w4, w5};
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
       const double t = block_sum(v7[k], red);
-      if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
+      if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = HALF ? t : 0.5 * t;
     }
   }
   wave_stamp(a.stamps, 1);
@@ -1519,33 +1539,45 @@ void launch_pair_elec(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bo
 }
 
 template <bool ELEC>
-void launch_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev) {
+void launch_col(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool half) {
   if (a.ntiles <= 0) return;
   dim3 g(a.ntiles), b(NL_WAVES * 64);
-#define GCME_HALF(T, CI)                                                          \
+#define GCME_COL(T, CI, H)                                                        \
   do {                                                                             \
     if (ev)                                                                        \
-      hipLaunchKernelGGL((k_pair_half<T, CI, true, ELEC>), g, b, 0, s, a);        \
+      hipLaunchKernelGGL((k_pair_col<T, CI, true, ELEC, H>), g, b, 0, s, a);      \
     else                                                                           \
-      hipLaunchKernelGGL((k_pair_half<T, CI, false, ELEC>), g, b, 0, s, a);       \
+      hipLaunchKernelGGL((k_pair_col<T, CI, false, ELEC, H>), g, b, 0, s, a);     \
+  } while (0)
+#define GCME_COL_H(T, CI) \
+  do {                    \
+    if (half)             \
+      GCME_COL(T, CI, true); \
+    else                  \
+      GCME_COL(T, CI, false); \
   } while (0)
   if (fp64) {
     if (a.ci == 8)
-      GCME_HALF(double, 8);
+      GCME_COL_H(double, 8);
     else
-      GCME_HALF(double, 4);
+      GCME_COL_H(double, 4);
   } else {
     if (a.ci == 8)
-      GCME_HALF(float, 8);
+      GCME_COL_H(float, 8);
     else
-      GCME_HALF(float, 4);
+      GCME_COL_H(float, 4);
   }
-#undef GCME_HALF
+#undef GCME_COL_H
+#undef GCME_COL
 }
 
-void launch_pair_gcm_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev) { launch_half<false>(s, a, fp64, ev); }
+void launch_pair_gcm_col(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool half) {
+  launch_col<false>(s, a, fp64, ev, half);
+}
 
-void launch_pair_elec_half(hipStream_t s, const PairLaunch& a, bool fp64, bool ev) { launch_half<true>(s, a, fp64, ev); }
+void launch_pair_elec_col(hipStream_t s, const PairLaunch& a, bool fp64, bool ev, bool half) {
+  launch_col<true>(s, a, fp64, ev, half);
+}
 
 int pair_waves_per_block() { return NL_WAVES; }
 

@@ -1,7 +1,8 @@
-"""GPU parity of the half-shell pair kernels (tuning half_pairs: bit 0 the
-excluded volume, bit 1 the real-space electrostatics): each unordered pair
-within rc evaluated once, by the column cluster that owns it, both beads
-receiving its force.
+"""GPU parity of the column-cluster pair kernels (tuning half_pairs, two bits
+per pair type: bits 0-1 the excluded volume, 2-3 the real-space
+electrostatics; 1 = half shell: each unordered pair within rc evaluated once,
+by the column cluster that owns it, both beads receiving its force; 2 = both
+ends: every pair from both of its beads' clusters).
 
 The bars are those of test_gpu_parity.py (FP64: 1e-9 force RMS, 1e-10 per
 energy term; mixed: 1e-5 and 1e-6; per bead ten times the RMS bar), against
@@ -27,7 +28,7 @@ from tests.test_gpu_parity import _check
 
 pytestmark = pytest.mark.gpu
 
-HALF = dict(half_pairs=3)
+HALF = dict(half_pairs=5)  # both pair types half shell
 
 
 def _t(**kw):
@@ -42,11 +43,19 @@ def _t(**kw):
                                     _t(cells_per_cutoff=2, beads_per_cluster=8, direct_pairs=1, stream_layout=1,
                                        half_pairs=1),
                                     _t(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=2, direct_pairs=2,
-                                       stream_layout=0, half_pairs=2),
+                                       stream_layout=0, half_pairs=4),
                                     _t(cells_per_cutoff=3, beads_per_cluster=2, charges_per_cluster=8, direct_pairs=3,
                                        stream_layout=2),
                                     _t(cells_per_cutoff=4, beads_per_cluster=4, charges_per_cluster=4, direct_pairs=3,
-                                       stream_layout=4)])
+                                       stream_layout=4),
+                                    _t(cells_per_cutoff=1, beads_per_cluster=8, charges_per_cluster=4, direct_pairs=3,
+                                       half_pairs=10),
+                                    _t(cells_per_cutoff=2, beads_per_cluster=4, charges_per_cluster=8, direct_pairs=3,
+                                       half_pairs=6),
+                                    _t(cells_per_cutoff=3, beads_per_cluster=8, charges_per_cluster=4, direct_pairs=3,
+                                       half_pairs=9),
+                                    _t(cells_per_cutoff=4, beads_per_cluster=8, charges_per_cluster=8, direct_pairs=3,
+                                       half_pairs=10, stream_layout=1)])
 def test_half_tunings_parity(precision, tuning):
     w = W.small_bulk(N=1001, seed=4, charged_frac=0.25, a_types=(0.3, 0.5, 0.7), box=(7.7, 8.3, 6.5),
                      rc=2.6, grid=(27, 36, 24), order=4)
@@ -55,27 +64,30 @@ def test_half_tunings_parity(precision, tuning):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("cpc", [1, 2])
-def test_half_two_cells_per_axis(precision, cpc):
+@pytest.mark.parametrize("mode", [5, 10])
+def test_half_two_cells_per_axis(precision, cpc, mode):
     # 5.3 / 2.5: two cells per axis at one cell per cutoff (every column of
     # the other half-axis is exactly half the axis away), four at two
     # (whole axes)
     w = W.small_bulk(N=360, seed=8, charged_frac=0.3, box=(5.3, 5.6, 5.2), rc=2.5, grid=(18, 18, 18))
-    _check(w, precision, _t(cells_per_cutoff=cpc, beads_per_cluster=8))
+    _check(w, precision, _t(cells_per_cutoff=cpc, beads_per_cluster=8, half_pairs=mode))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_half_one_cell_across(precision):
+@pytest.mark.parametrize("mode", [5, 10])
+def test_half_one_cell_across(precision, mode):
     # 3.0 wide at rc = 1.45: one cell along x at one cell per cutoff
     w = W.small_bulk(N=180, seed=9, charged_frac=0.2, box=(3.0, 6.2, 5.9), rc=1.45, grid=(16, 24, 24))
-    _check(w, precision, _t(cells_per_cutoff=1, beads_per_cluster=4))
+    _check(w, precision, _t(cells_per_cutoff=1, beads_per_cluster=4, half_pairs=mode))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("on_lattice", [True, False])
-def test_half_config2_full_size(precision, on_lattice):
+@pytest.mark.parametrize("mode", [5, 10])
+def test_half_config2_full_size(precision, on_lattice, mode):
     w = W.config2(on_lattice=on_lattice)
-    print(f"case config2 N={w.N} prec={precision} on_lattice={on_lattice}", flush=True)
-    eng = make_engine([w], precision, tuning=_t(cells_per_cutoff=2, beads_per_cluster=8))
+    print(f"case config2 N={w.N} prec={precision} on_lattice={on_lattice} mode={mode}", flush=True)
+    eng = make_engine([w], precision, tuning=_t(cells_per_cutoff=2, beads_per_cluster=8, half_pairs=mode))
     got = gpu_eval(eng)
     eng.close()
     ref = oracle_eval(w)
@@ -103,9 +115,10 @@ def test_half_config2_full_size(precision, on_lattice):
                       <= 1e-12 * np.abs(full["energy"][0, :5]) + 1e-9)
 
 
-def test_half_reruns_bit_identical():
+@pytest.mark.parametrize("mode", [5, 10])
+def test_half_reruns_bit_identical(mode):
     w = W.small_bulk(N=2000, seed=12, charged_frac=0.2, box=(9.3, 9.1, 9.5), rc=2.5, grid=(24, 24, 24))
-    eng = make_engine([w], "mixed", tuning=_t(cells_per_cutoff=2, beads_per_cluster=8))
+    eng = make_engine([w], "mixed", tuning=_t(cells_per_cutoff=2, beads_per_cluster=8, half_pairs=mode))
     a = gpu_eval(eng)
     b = gpu_eval(eng)
     eng.close()
@@ -115,9 +128,10 @@ def test_half_reruns_bit_identical():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_half_batched_replicas(precision):
+@pytest.mark.parametrize("mode", [5, 10])
+def test_half_batched_replicas(precision, mode):
     ws = W.config5(n_replicas=6, seed=7)
-    tun = _t(cells_per_cutoff=2, beads_per_cluster=8)
+    tun = _t(cells_per_cutoff=2, beads_per_cluster=8, half_pairs=mode)
     eng = make_engine(ws, precision, tuning=tun)
     got = gpu_eval(eng)
     eng.close()
@@ -136,11 +150,12 @@ def test_half_batched_replicas(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("metal", [False, True])
-def test_half_slab(precision, metal):
+@pytest.mark.parametrize("mode", [5, 10])
+def test_half_slab(precision, metal, mode):
     from tests.test_gpu_slab import _compare, _engine, _oracle
     w = W.slab_system(metal=metal)
-    print(f"case slab_system metal={metal} N={w.N} prec={precision}", flush=True)
-    eng = _engine([w], precision, tuning=_t(cells_per_cutoff=2, beads_per_cluster=8))
+    print(f"case slab_system metal={metal} N={w.N} prec={precision} mode={mode}", flush=True)
+    eng = _engine([w], precision, tuning=_t(cells_per_cutoff=2, beads_per_cluster=8, half_pairs=mode))
     got = gpu_eval(eng)
     eng.close()
     _compare(got["energy"][0], got["force"], got["virial"][0], _oracle(w), precision, "half")
@@ -148,13 +163,14 @@ def test_half_slab(precision, metal):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("gamma", [0.0, 1.0])
-def test_half_fused_steps_equal_single_steps(precision, gamma):
+@pytest.mark.parametrize("mode", [5, 10])
+def test_half_fused_steps_equal_single_steps(precision, gamma, mode):
     w = W.small_bulk(N=900, seed=13, charged_frac=0.2, box=(7.0, 7.3, 7.1), rc=2.5, grid=(24, 24, 24))
     w.gamma = gamma
     print(f"case half fused steps prec={precision} gamma={gamma}", flush=True)
     runs = []
     for split in (False, True):
-        eng = make_engine([w], precision, seed=5, tuning=_t(cells_per_cutoff=2, beads_per_cluster=8))
+        eng = make_engine([w], precision, seed=5, tuning=_t(cells_per_cutoff=2, beads_per_cluster=8, half_pairs=mode))
         if split:
             for _ in range(12):
                 eng.step(1)
