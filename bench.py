@@ -50,8 +50,9 @@ FLOP_PER_ELEC_PAIR = 35
 # so that every run, and the kernel traces under profiles/, time the same
 # kernels.
 DEFAULT_TUNING = {
-    "bulk_N32768": "3,8,4,3,0",
-    "bulk_N2097152": "3,8,4,3,0",
+    "bulk_N32768": "3,8,4,3,1",
+    "bulk_N2097152": "2,8,8,1,0,4,4,4,2",
+    "batched_256": "2,8,8,2,1,16,8,16,8",
 }
 
 # stages of more than one kernel launch
@@ -65,10 +66,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--workload", default="bulk_N32768",
-                    choices=["bulk_N32768", "bulk_N2097152", "slab_nonmetal", "slab_metal",
+                    choices=["bulk_N32768", "bulk_N2097152", "batched_256", "slab_nonmetal", "slab_metal",
                              "polyelectrolyte_slab_nonmetal", "polyelectrolyte_slab_metal"],
                     help="the slab systems (the adsorption study's size, and the 200,000-bead "
-                         "polyelectrolyte slab) time the step loop only")
+                         "polyelectrolyte slab) and the 256 batched replicas time the step loop only")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the tuning with the library's autotuner (after the warm-up) instead of the "
                          "workload's default tuning")
@@ -114,7 +115,12 @@ def main():
     from paper_2403_08148_amd import GCMe, params_from_workload
 
     slab = args.workload.startswith("slab") or args.workload.startswith("polyelectrolyte")
-    if slab:
+    if args.workload == "batched_256":
+        ws = W.config5()
+        eng, _ = engine_for(ws, args.precision, tune=False)
+        w = ws[0]
+        slab = True  # the step loop only
+    elif slab:
         metal = args.workload.endswith("_metal")
         w = W.paper_slab(metal=metal) if args.workload.startswith("slab") else W.polyelectrolyte_slab(metal=metal)
         eng, _ = engine_for([w], args.precision, tune=False)
@@ -163,7 +169,8 @@ def main():
     value = pairs * steps_per_s
     ns_day = steps_per_s * w.dt * TAU_PS * 86400.0 / 1000.0
     if args.steps_only or slab:
-        print(json.dumps({"workload": w.name, "n_beads": w.N, "ms_per_step": ms_step, "pairs": pairs,
+        print(json.dumps({"workload": args.workload if args.workload == "batched_256" else w.name,
+                          "n_beads": eng.N, "ms_per_step": ms_step, "pairs": pairs,
                           "pair_interactions_per_s": value, "tuning": tuning}))
         return
 

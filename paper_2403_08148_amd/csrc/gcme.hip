@@ -561,10 +561,11 @@ gcme_status build_plan(gcme_handle h) {
     d.q_off = h->qoff[r];
     d.nq = h->nq[r];
     d.K2h = p.K[2] > 0 ? p.K[2] / 2 + 1 : 0;  // no mesh: exact reciprocal sum
+    d.K2s = (d.K2h + 7) & ~7;
     d.grid_off = goff;
     d.cgrid_off = cgoff;
     goff += (long long)p.K[0] * p.K[1] * p.K[2];
-    cgoff += (long long)p.K[0] * p.K[1] * d.K2h;
+    cgoff += (long long)p.K[0] * p.K[1] * d.K2s;
     d.order = p.order;
     d.nt = p.nt;
     h->maxK[0] = std::max(h->maxK[0], p.K[2]);  // z pass line length
@@ -631,6 +632,10 @@ gcme_status build_plan(gcme_handle h) {
     // balanced batches of the K2/2+1 strided lines
     int c1 = (d.K2h + h->lb[1] - 1) / h->lb[1], b1 = (d.K2h + c1 - 1) / c1;
     int c2 = (d.K2h + h->lb[2] - 1) / h->lb[2], b2 = (d.K2h + c2 - 1) / c2;
+    // batches of whole 8-line segments where the batch size allows: each
+    // batch then starts on a 64-byte boundary of its rows
+    if (h->lb[1] >= 8) b1 = h->lb[1] / 8 * 8;
+    if (h->lb[2] >= 8) b2 = h->lb[2] / 8 * 8;
     for (int x = 0; x < d.K[0]; ++x)
       for (int kz = 0; kz < d.K2h; kz += b1)
         items[1].push_back(LineItem{r, x * d.K2h + kz, std::min(b1, d.K2h - kz), 0});

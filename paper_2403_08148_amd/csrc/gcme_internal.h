@@ -38,6 +38,9 @@ struct RepDesc {
   int q_off, nq;      // charged-bead range in the compacted charged arrays
   int K[3];
   int K2h;            // K2/2 + 1
+  int K2s;            // row stride of the (x, y, m) mesh layout: K2h rounded up
+                      // to a multiple of 8, so that the line-batched passes'
+                      // 8-line segments start on 64-byte boundaries
   long long grid_off;   // real mesh offset (K0 K1 K2 entries)
   long long cgrid_off;  // half-complex mesh offset (K0 K1 K2h entries)
   int order;

@@ -122,7 +122,7 @@ struct QDiv {
 // Offset of half-complex mesh point (x, y, m) within a replica's mesh, in
 // the layout the launch uses.
 __device__ inline long long mesh_index(const PmeLaunch& a, const RepDesc& R, int x, int y, int m) {
-  return a.plane_major ? ((long long)m * R.K[0] + x) * R.K[1] + y : ((long long)x * R.K[1] + y) * R.K2h + m;
+  return a.plane_major ? ((long long)m * R.K[0] + x) * R.K[1] + y : ((long long)x * R.K[1] + y) * R.K2s + m;
 }
 
 // Radix-RR DFT of v (twiddles already applied): o_q = sum_s v_s
@@ -324,22 +324,22 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse)
   extern __shared__ __align__(16) unsigned char smem[];
   const LineItem it = a.items[1][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
-  const int K = R.K[1], K2h = R.K2h, nl = it.count, LBP = a.lb[1] + 1;
+  const int K = R.K[1], K2h = R.K2h, K2s = R.K2s, nl = it.count, LBP = a.lb[1] + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[1] * LBP;
   const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[1] * LBP, a, R.tw_off[1], K);
   const int x = it.first / K2h, kz0 = it.first % K2h;
-  cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)x * R.K[1] * K2h + kz0;
+  cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)x * R.K[1] * K2s + kz0;
   const FDiv dnl(nl);
   for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
     const int k = dnl.div(e), l = e - k * nl;
-    A[k * LBP + l] = base[(long long)k * K2h + l];
+    A[k * LBP + l] = base[(long long)k * K2s + l];
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[1], R.nrad[1], inverse != 0);
   for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
     const int k = dnl.div(e), l = e - k * nl;
-    base[(long long)k * K2h + l] = res[k * LBP + l];
+    base[(long long)k * K2s + l] = res[k * LBP + l];
   }
   wave_stamp(a.stamps, 1);
 }
@@ -414,13 +414,13 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
   __shared__ double sh[4];
   const LineItem it = a.items[2][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
-  const int K = R.K[0], K1 = R.K[1], K2h = R.K2h, nl = it.count, LBP = a.lb[2] + 1;
+  const int K = R.K[0], K1 = R.K[1], K2h = R.K2h, K2s = R.K2s, nl = it.count, LBP = a.lb[2] + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[2] * LBP;
   const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[2] * LBP, a, R.tw_off[0], K);
   const int y = it.first / K2h, kz0 = it.first % K2h;
-  const long long xstride = (long long)K1 * K2h;
-  cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)y * K2h + kz0;
+  const long long xstride = (long long)K1 * K2s;
+  cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)y * K2s + kz0;
   const FDiv dnl(nl);
   for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
     const int k = dnl.div(e), l = e - k * nl;
