@@ -318,6 +318,30 @@ __device__ inline const cplx<T>* stage_twiddles(cplx<T>* dst, const PmeLaunch& a
   return dst;
 }
 
+// Loads nl lines of K points, point k of line l at src[k * stride + l],
+// into LDS at A[k * LBP + l]: consecutive threads take consecutive lines of
+// one point (consecutive addresses), and each thread issues U loads before
+// it stores any, so their latencies overlap.
+template <typename T, int U>
+__device__ inline void load_lines(cplx<T>* A, const cplx<T>* src, long long stride, int K, int nl, int LBP) {
+  const FDiv dnl(nl);
+  const int n = nl * K;
+  for (int e0 = threadIdx.x; e0 < n; e0 += U * FFT_THREADS) {
+    cplx<T> v[U];
+    int k[U], l[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = min(e0 + u * FFT_THREADS, n - 1);
+      k[u] = dnl.div(e);
+      l[u] = e - k[u] * nl;
+      v[u] = src[(long long)k[u] * stride + l[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * FFT_THREADS < n) A[k[u] * LBP + l[u]] = v[u];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse) {
   wave_stamp(a.stamps, 0);
@@ -331,10 +355,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse)
   const int x = it.first / K2h, kz0 = it.first % K2h;
   cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)x * R.K[1] * K2s + kz0;
   const FDiv dnl(nl);
-  for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
-    const int k = dnl.div(e), l = e - k * nl;
-    A[k * LBP + l] = base[(long long)k * K2s + l];
-  }
+  load_lines<T, 8>(A, base, K2s, K, nl, LBP);
   __syncthreads();
   cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[1], R.nrad[1], inverse != 0);
   for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
@@ -422,10 +443,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
   const long long xstride = (long long)K1 * K2s;
   cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)y * K2s + kz0;
   const FDiv dnl(nl);
-  for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
-    const int k = dnl.div(e), l = e - k * nl;
-    A[k * LBP + l] = base[(long long)k * xstride + l];
-  }
+  load_lines<T, 8>(A, base, xstride, K, nl, LBP);
   __syncthreads();
   cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], false);
   cplx<T>* other = res == A ? B : A;
