@@ -45,10 +45,11 @@ FLOP_PER_ELEC_PAIR = 35
 
 
 # Default tuning per workload (cells_per_cutoff, beads_per_cluster,
-# charges_per_cluster, direct_pairs, stream_layout): the library's
-# autotuner's pick on MI355X for that workload (bench.py --autotune), fixed
-# so that every run, and the kernel traces under profiles/, time the same
-# kernels.
+# charges_per_cluster, direct_pairs, stream_layout, then optionally
+# mesh_tile_x, mesh_tile_y, gather_tile_x, gather_tile_y, half_pairs; the
+# form --tuning takes): the library's autotuner's pick on MI355X for that
+# workload (bench.py --autotune), fixed so that every run, and the kernel
+# traces under profiles/, time the same kernels.
 DEFAULT_TUNING = {
     "bulk_N32768": "3,8,4,3,1",
     "bulk_N2097152": "2,8,8,1,0,4,4,4,2",
@@ -406,6 +407,9 @@ def extra_workloads(w):
             nq4 = int((w4.z != 0).sum())
             res[prec]["stage_ms"] = st
             res[prec]["stage_roofline"] = stage_rooflines(w4, st, tun, pairs, charged_pairs(eng, w4), nq4, prec)
+            prof = profiled_launch_us("pair_gcm", tun, w4.name)
+            if prof is not None and res[prec]["stage_roofline"].get("pair_gcm"):
+                res[prec]["stage_roofline"]["pair_gcm"]["launch_us_rocprof"] = prof
         eng.close()
     res["mixed_force_rel_rms_vs_fp64"] = float(np.linalg.norm(fr["mixed"] - fr["fp64"]) / np.linalg.norm(fr["fp64"]))
     out[w4.name] = res
@@ -509,6 +513,13 @@ def code_digest(text):
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
+def pair_gcm_key(tuning):
+    """What selects the excluded-volume pair kernel: the cell size, the
+    cluster size, the list choice and the column-cluster mode."""
+    return (f"{tuning['cells_per_cutoff']},{tuning['beads_per_cluster']},{tuning.get('direct_pairs', 0) & 1},"
+            f"{tuning.get('half_pairs', 0) & 3}")
+
+
 def measured_traffic(stage, tuning):
     """HBM bytes per launch of a stage from committed rocprofv3 counter runs
     (profiles/traffic_<stage>.json: FETCH_SIZE and WRITE_SIZE in KiB per
@@ -523,9 +534,7 @@ def measured_traffic(stage, tuning):
     with open(os.path.join(ROOT, t["source"])) as f:
         if code_digest(f.read()) != t["source_code_sha256"]:
             return None
-    # the excluded-volume pair kernel is set by the cell size, the cluster
-    # size and the list choice
-    key = f"{tuning['cells_per_cutoff']},{tuning['beads_per_cluster']},{tuning.get('direct_pairs', 0) & 1}"
+    key = pair_gcm_key(tuning)
     run = next((r for r in t["runs"] if r["key"] == key), None)
     if run is None:
         return None
@@ -549,7 +558,7 @@ def profiled_launch_us(stage, tuning, workload):
             return None
     key = ",".join(str(tuning[k]) for k in ("cells_per_cutoff", "beads_per_cluster", "charges_per_cluster",
                                             "direct_pairs", "stream_layout", "mesh_tile_x", "mesh_tile_y",
-                                            "gather_tile_x", "gather_tile_y"))
+                                            "gather_tile_x", "gather_tile_y", "half_pairs"))
     run = next((r for r in t["runs"] if r["key"] == key and r["workload"] == workload), None)
     return None if run is None else float(run["mean_us"])
 
@@ -566,7 +575,7 @@ def measured_valu(stage, tuning):
     with open(os.path.join(ROOT, t["source"])) as f:
         if code_digest(f.read()) != t["source_code_sha256"]:
             return None
-    key = f"{tuning['cells_per_cutoff']},{tuning['beads_per_cluster']},{tuning.get('direct_pairs', 0) & 1}"
+    key = pair_gcm_key(tuning)
     run = next((r for r in t["runs"] if r["key"] == key), None)
     return None if run is None else float(run["valu_instr"])
 
