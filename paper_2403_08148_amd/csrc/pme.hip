@@ -701,10 +701,10 @@ __device__ inline void for_tile_beads(const RepDesc& R, const TileCols& tc, cons
     s_cp[threadIdx.x] = inc - cr.n;
     if (threadIdx.x == NT - 1) *s_tot = inc;
     __syncthreads();
-    const int tot = *s_tot;
+    const int tot = *s_tot, last = min(NT, ncol - cb) - 1;
     for (int e = threadIdx.x; e < tot; e += NT) {
       // the last column whose prefix is <= e holds candidate e
-      int lo = 0, hi = NT - 1;
+      int lo = 0, hi = last;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_cp[mid] <= e)
@@ -733,7 +733,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   const MeshTile mt = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[mt.rep];
   const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h;
-  const int TY = a.ty, NL = a.tx * a.ty, LBP = NL + 1;
+  // the tile's real z lines are transformed two to a complex line: line l
+  // is the real (l even) or imaginary (l odd) part of packed line l / 2
+  const int TY = a.ty, NL = a.tx * a.ty, NP = (NL + 1) >> 1, LBP = NP + 1;
   const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
@@ -801,18 +803,24 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   });
   if (threadIdx.x < K2) tw[threadIdx.x] = tw0;
   for (int e = threadIdx.x + FFT_THREADS; e < K2; e += FFT_THREADS) tw[e] = tws[e];
-  // integer mesh -> complex lines (k, l) at A[k * LBP + l]
+  // integer mesh -> packed lines: real point k of line l at AT[k * 2 LBP + l]
+  // (a line past the tile's last is zero)
   const double inv_qs = 1.0 / qs;
+  T* AT = reinterpret_cast<T*>(A);
   const FDiv dk2(K2), dk2h(K2h);
-  for (int e = threadIdx.x; e < NL * K2; e += FFT_THREADS) {
+  for (int e = threadIdx.x; e < 2 * NP * K2; e += FFT_THREADS) {
     const int l = dk2.div(e), k = e - l * K2;
-    if constexpr (std::is_same<T, float>::value)
-      A[k * LBP + l] = {(float)(int)acc[e] * (1.0f / MeshInt<float>::scale), 0.0f};
-    else
-      A[k * LBP + l] = {(T)((double)(long long)acc[e] * inv_qs), (T)0};
+    T v = 0;
+    if (l < NL) {
+      if constexpr (std::is_same<T, float>::value)
+        v = (float)(int)acc[e] * (1.0f / MeshInt<float>::scale);
+      else
+        v = (T)((double)(long long)acc[e] * inv_qs);
+    }
+    AT[k * 2 * LBP + l] = v;
   }
   __syncthreads();
-  cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], false);
+  const cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NP, tw, a.radix + R.rad_off[2], R.nrad[2], false);
   cplx<T>* out = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off;
   const FDiv dnl(NL), dty(TY);
   for (int e = threadIdx.x; e < NL * K2h; e += FFT_THREADS) {
@@ -826,7 +834,15 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
       m = e - l * K2h;
     }
     const int lx = dty.div(l), ly = l - lx * TY;
-    if (lx < nxt && ly < nyt) out[mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m)] = res[m * LBP + l];
+    if (lx < nxt && ly < nyt) {
+      // packed transform Z = X + i Y of real lines x, y: X_m = (Z_m +
+      // conj Z_-m) / 2, Y_m = (Z_m - conj Z_-m) / 2i
+      const int p = l >> 1;
+      const cplx<T> zm = res[m * LBP + p], zc = res[(m == 0 ? 0 : K2 - m) * LBP + p];
+      const cplx<T> v = (l & 1) ? cplx<T>{(zm.y + zc.y) * (T)0.5, (zc.x - zm.x) * (T)0.5}
+                                : cplx<T>{(zm.x + zc.x) * (T)0.5, (zm.y - zc.y) * (T)0.5};
+      out[mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m)] = v;
+    }
   }
   wave_stamp(a.stamps, 1);
 }
@@ -839,60 +855,75 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   const MeshTile mt = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[mt.rep];
   const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h;
-  const int TY = a.ty, NL = a.tx * a.ty, LBP = NL + 1;
+  // the tile's real z lines come out of the inverse transform two to a
+  // complex line: line l is the real (l even) or imaginary (l odd) part of
+  // packed line l / 2
+  const int TY = a.ty, NL = a.tx * a.ty, NP = (NL + 1) >> 1, LBP = NP + 1;
   const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
   const TileCols tc = tile_columns(R, mt, P);
   const ColRun first = tile_column<FFT_THREADS>(R, tc, a.qstart, 0);
   const cplx<T>* in = reinterpret_cast<const cplx<T>*>(a.Qc) + R.cgrid_off;
-  const FDiv dk2h(K2h), dnl(NL), dty(TY);
-  // point e of the tile's half-complex lines: line l, frequency m, and its
-  // mesh offset (negative outside the tile); consecutive e take consecutive
-  // addresses of either layout
-  auto point = [&](int e, int& l, int& m) -> long long {
-    if (a.plane_major) {
-      m = dnl.div(e);
-      l = e - m * NL;
-    } else {
-      l = dk2h.div(e);
-      m = e - l * K2h;
-    }
+  const FDiv dk2h(K2h), dnp(NP), dty(TY);
+  // mesh offset of frequency m of tile line l (negative outside the tile)
+  auto offset = [&](int l, int m) -> long long {
     const int lx = dty.div(l), ly = l - lx * TY;
-    return lx < nxt && ly < nyt ? mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m) : -1;
+    return l < NL && lx < nxt && ly < nyt ? mesh_index(a, R, mt.x0 + lx, mt.y0 + ly, m) : -1;
   };
-  auto put = [&](int l, int m, cplx<T> v) {
-    A[m * LBP + l] = v;
-    // Hermitian partner of a real field
+  // point e of the packed half-complex lines: packed line p, frequency m;
+  // consecutive e take consecutive addresses of either layout
+  auto point = [&](int e, int& p, int& m) {
+    if (a.plane_major) {
+      m = dnp.div(e);
+      p = e - m * NP;
+    } else {
+      p = dk2h.div(e);
+      m = e - p * K2h;
+    }
+  };
+  // Z = X + i Y over the whole line from the half-complex X, Y of two real
+  // lines (X_-m = conj X_m); at m = 0 and K2 / 2 only the real parts count
+  auto put = [&](int p, int m, cplx<T> x, cplx<T> y) {
     const int mc = K2 - m;
-    if (m > 0 && mc > m && mc < K2) A[mc * LBP + l] = {v.x, -v.y};
+    if (m == 0 || mc == m) {
+      A[m * LBP + p] = {x.x, y.x};
+    } else {
+      A[m * LBP + p] = {x.x - y.y, x.y + y.x};
+      A[mc * LBP + p] = {x.x + y.y, y.x - x.y};
+    }
   };
-  const int ne = NL * K2h;
+  const int ne = NP * K2h;
   // the first PL points per thread are loaded together (one memory latency)
   constexpr int PL = 4;
-  cplx<T> v[PL];
-  int vl[PL], vm[PL];
+  cplx<T> v[PL][2];
+  int vp[PL], vm[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int e = threadIdx.x + u * FFT_THREADS;
-    v[u] = cplx<T>{};
-    vl[u] = vm[u] = 0;
+    v[u][0] = v[u][1] = cplx<T>{};
+    vp[u] = vm[u] = 0;
     if (e < ne) {
-      const long long o = point(e, vl[u], vm[u]);
-      if (o >= 0) v[u] = in[o];
+      point(e, vp[u], vm[u]);
+      const long long o0 = offset(2 * vp[u], vm[u]), o1 = offset(2 * vp[u] + 1, vm[u]);
+      if (o0 >= 0) v[u][0] = in[o0];
+      if (o1 >= 0) v[u][1] = in[o1];
     }
   }
   const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
 #pragma unroll
   for (int u = 0; u < PL; ++u)
-    if (threadIdx.x + u * FFT_THREADS < ne) put(vl[u], vm[u], v[u]);
+    if (threadIdx.x + u * FFT_THREADS < ne) put(vp[u], vm[u], v[u][0], v[u][1]);
   for (int e = threadIdx.x + PL * FFT_THREADS; e < ne; e += FFT_THREADS) {
-    int l, m;
-    const long long o = point(e, l, m);
-    put(l, m, o >= 0 ? in[o] : cplx<T>{});
+    int p, m;
+    point(e, p, m);
+    const long long o0 = offset(2 * p, m), o1 = offset(2 * p + 1, m);
+    put(p, m, o0 >= 0 ? in[o0] : cplx<T>{}, o1 >= 0 ? in[o1] : cplx<T>{});
   }
   __syncthreads();
-  const cplx<T>* phi = fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NL, tw, a.radix + R.rad_off[2], R.nrad[2], true);
+  // real point g of line l at phi[g * 2 LBP + l]
+  const T* phi = reinterpret_cast<const T*>(
+      fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NP, tw, a.radix + R.rad_off[2], R.nrad[2], true));
   const double fx = -R.lB * K0 / R.L[0], fy = -R.lB * K1 / R.L[1], fz = -R.lB * K2 / R.L[2];
   for_tile_beads<FFT_THREADS>(R, tc, a.qstart, first, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
     const uint4 rec = a.qpk[q];
@@ -928,7 +959,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
           T s0 = 0, s2 = 0;
 #pragma unroll
           for (int jz = 0; jz < P; ++jz) {
-            const T ph = phi[g2s[jz] * LBP + l].x;
+            const T ph = phi[g2s[jz] * 2 * LBP + l];
             s0 += w[2][jz] * ph;
             s2 += dw[2][jz] * ph;
           }
@@ -996,7 +1027,8 @@ inline size_t lds_bytes(const PmeLaunch& a, int pass, bool fp64) {
 }  // namespace
 
 size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64) {
-  return (2 * (size_t)maxK2 * (size_t)(tx * ty + 1) + maxK2) * (fp64 ? 16 : 8);
+  // two buffers of (tx ty + 1) / 2 packed lines (+1 padding), and the twiddles
+  return (2 * (size_t)maxK2 * (size_t)((tx * ty + 1) / 2 + 1) + maxK2) * (fp64 ? 16 : 8);
 }
 
 void launch_spread_z(hipStream_t s, const PmeLaunch& a, bool fp64) {
