@@ -662,13 +662,13 @@ gcme_status build_plan(gcme_handle h) {
   auto tiles_of = [&](int tx, int ty, int& ox, int& oy, std::vector<MeshTile>& t) -> bool {
     ox = tx;
     oy = ty;
-    while (ox * oy > 1 && pme_tile_lds_bytes(h->maxK[0], ox, oy, h->fp64) > (size_t)h->lds_max) {
+    while (ox * oy > 1 && pme_tile_lds_bytes(h->maxK[0], ox, oy, h->order, h->fp64) > (size_t)h->lds_max) {
       if (ox >= oy)
         ox /= 2;
       else
         oy /= 2;
     }
-    if (pme_tile_lds_bytes(h->maxK[0], ox, oy, h->fp64) > (size_t)h->lds_max) return false;
+    if (pme_tile_lds_bytes(h->maxK[0], ox, oy, h->order, h->fp64) > (size_t)h->lds_max) return false;
     t.clear();
     for (int r = 0; r < R; ++r) {
       const RepDesc& d = h->rep[r];

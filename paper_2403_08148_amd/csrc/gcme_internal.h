@@ -413,7 +413,7 @@ size_t pme_plane_lds_bytes(int plane_elems, int maxK0, int maxK1, int maxK2, boo
 // threads of a fused y/x plane workgroup for planes of plane_elems entries
 int pme_plane_threads(int plane_elems);
 void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64);
-size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64);
+size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, int order, bool fp64);
 
 // ewald.hip: the reciprocal term of eq. ewald summed exactly over the wave
 // vectors k = 2 pi (n0/L0, n1/L1, n2/L2) != 0 with |k| <= kmax, for the

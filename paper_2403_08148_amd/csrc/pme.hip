@@ -686,13 +686,23 @@ __device__ inline ColRun tile_column(const RepDesc& R, const TileCols& tc, const
   return r;
 }
 
-// Calls f(q) for every charged bead q in the tile's columns (every thread of
-// the block must call this; f runs on the thread that owns q).  first is
-// tile_column(.., 0), which callers load early so that its latency overlaps
-// other work.
-template <int NT, typename F>
+// Calls f(q) for every charged bead q in the tile's columns for which
+// keep(q) holds.  The kept beads are queued per wavefront and handed to f 64
+// at a time, so every lane of a call but those of the last has a bead (the
+// test alone rejects about half the candidates of a small tile).  Every
+// thread of the block must call this; f runs on one lane per bead and uses
+// no cross-lane operation.  work is 4 NT ints of LDS (the column table and
+// the queues); first is tile_column(.., 0), which callers load early so that
+// its latency overlaps other work.  The order in which beads reach f depends
+// on timing: the callers only add integers.
+template <int NT, typename Keep, typename F>
 __device__ inline void for_tile_beads(const RepDesc& R, const TileCols& tc, const int* __restrict__ qstart,
-                                      ColRun first, int* s_cs, int* s_cp, int* s_tot, int* scan_sh, F&& f) {
+                                      ColRun first, int* work, int* s_tot, int* scan_sh, Keep&& keep, F&& f) {
+  int* s_cs = work;
+  int* s_cp = work + NT;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int* que = work + 2 * NT + wv * 128;
+  int qn = 0;  // wavefront-uniform: queued beads
   const int ncol = tc.n[0] * tc.n[1];
   for (int cb = 0; cb < ncol; cb += NT) {
     const ColRun cr = cb == 0 ? first : tile_column<NT>(R, tc, qstart, cb);
@@ -702,20 +712,81 @@ __device__ inline void for_tile_beads(const RepDesc& R, const TileCols& tc, cons
     if (threadIdx.x == NT - 1) *s_tot = inc;
     __syncthreads();
     const int tot = *s_tot, last = min(NT, ncol - cb) - 1;
-    for (int e = threadIdx.x; e < tot; e += NT) {
-      // the last column whose prefix is <= e holds candidate e
-      int lo = 0, hi = last;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_cp[mid] <= e)
-          lo = mid;
-        else
-          hi = mid - 1;
+    for (int e0 = wv * 64; e0 < tot; e0 += NT) {
+      const int e = e0 + lane;
+      int q = -1;
+      if (e < tot) {
+        // the last column whose prefix is <= e holds candidate e
+        int lo = 0, hi = last;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_cp[mid] <= e)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        q = s_cs[lo] + (e - s_cp[lo]);
+        if (!keep(q)) q = -1;
       }
-      f(s_cs[lo] + (e - s_cp[lo]));
+      const unsigned long long m = __ballot(q >= 0);
+      if (q >= 0) que[qn + __popcll(m & ((1ull << lane) - 1ull))] = q;
+      qn += __popcll(m);
+      __builtin_amdgcn_wave_barrier();
+      if (qn >= 64) {
+        f(que[lane]);
+        const int rest = qn - 64;
+        const int v = lane < rest ? que[64 + lane] : 0;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) que[lane] = v;
+        __builtin_amdgcn_wave_barrier();
+        qn = rest;
+      }
     }
+    // the column table is rewritten by the next column block
     __syncthreads();
   }
+  if (lane < qn) f(que[lane]);
+  __syncthreads();
+}
+
+// Complex entries of each of the two LDS line buffers of a tile pass: the
+// packed lines (nl + 1) / 2 (+1 padding) of the longest z line; at least the
+// spread's integer accumulators (nl lines of maxK2 + order - 1 entries, half
+// a complex each) and the 4 FFT_THREADS ints of the bead enumeration, which
+// use a buffer while it is free.
+__host__ __device__ inline int tile_buf_elems(int maxK2, int nl, int order, int cplx_bytes) {
+  int e = maxK2 * ((nl + 1) / 2 + 1);
+  const int acc = (nl * (maxK2 + order - 1) + 1) / 2;
+  const int work = (4 * FFT_THREADS * 4 + cplx_bytes - 1) / cplx_bytes;
+  e = e > acc ? e : acc;
+  return e > work ? e : work;
+}
+
+// w[i] <- w[i + s] for i < P - s (s in [0, P); the rest is not used).
+template <typename T, int P>
+__device__ inline void shift_down(T* w, int s) {
+#pragma unroll
+  for (int b = 1; b < P; b <<= 1) {
+    const bool on = (s & b) != 0;
+#pragma unroll
+    for (int i = 0; i + b < P; ++i) w[i] = on ? w[i + b] : w[i];
+  }
+}
+
+// The stencil offsets j of one axis whose mesh line (o - j mod K) lies in
+// the tile's n lines, o the stencil base's offset from the tile origin (at
+// most n + P - 2).  When the axis is longer than n + P - 2 no stencil point
+// wraps into the tile, and they are the run j0 .. j0 + nv - 1 with
+// line o - j0 - i; else every j is tried (j0 = 0, nv = P) and the caller
+// tests each line.
+struct StencilRun {
+  int j0, nv;
+  bool wrap;
+};
+template <int P>
+__device__ inline StencilRun stencil_run(int o, int n, int K) {
+  if (K >= n + P - 1) return {max(0, o - n + 1), min(P - 1, o) - max(0, o - n + 1) + 1, false};
+  return {0, P, true};
 }
 
 // Offset of a stencil base point from the tile origin (mod K); the bead
@@ -729,7 +800,7 @@ template <typename T, int P>
 __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_cs[FFT_THREADS], s_cp[FFT_THREADS], s_tot, scan_sh[FFT_THREADS / 64];
+  __shared__ int s_tot, scan_sh[FFT_THREADS / 64];
   const MeshTile mt = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[mt.rep];
   const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h;
@@ -737,24 +808,35 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   // is the real (l even) or imaginary (l odd) part of packed line l / 2
   const int TY = a.ty, NL = a.tx * a.ty, NP = (NL + 1) >> 1, LBP = NP + 1;
   const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
+  const int SB = tile_buf_elems(a.maxK[0], NL, P, (int)sizeof(cplx<T>));
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
+  cplx<T>* B = A + SB;
   // the tile's first column run and this thread's twiddle are loaded first;
   // the twiddles go to LDS after the spread, so neither latency is waited
   // for on its own
   const TileCols tc = tile_columns(R, mt, P);
   const ColRun first = tile_column<FFT_THREADS>(R, tc, a.qstart, 0);
-  cplx<T>* tw = B + (size_t)a.maxK[0] * LBP;
+  cplx<T>* tw = B + SB;
   const cplx<T>* tws = reinterpret_cast<const cplx<T>*>(a.tw) + R.tw_off[2];
   const cplx<T> tw0 = threadIdx.x < K2 ? tws[threadIdx.x] : cplx<T>{};
-  // integer accumulators of the tile, line l = lx * TY + ly, point l * K2 + z
-  // (they live in B, which the transform first writes after they are read)
+  // integer accumulators of the tile in B (which the transform first writes
+  // after they are read): line l = lx * TY + ly at l * KP, mesh point z at
+  // z + P - 1, so that a stencil's P points are consecutive (those below
+  // z = 0 are folded onto z + K2 afterwards)
   using U = typename MeshInt<T>::U;
   U* acc = reinterpret_cast<U*>(B);
-  for (int e = threadIdx.x; e < NL * K2; e += FFT_THREADS) acc[e] = 0;
+  const int KP = K2 + P - 1;
+  for (int e = threadIdx.x; e < NL * KP; e += FFT_THREADS) acc[e] = 0;
   __syncthreads();
   const double qs = a.qscale;
-  for_tile_beads<FFT_THREADS>(R, tc, a.qstart, first, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
+  auto keep = [&](int q) {
+    const uint4 rec = a.qpk[q];
+    const int ox = tile_off((int)(((unsigned long long)rec.x * (unsigned)K0) >> 32), mt.x0, K0);
+    const int oy = tile_off((int)(((unsigned long long)rec.y * (unsigned)K1) >> 32), mt.y0, K1);
+    return ox <= nxt + P - 2 && oy <= nyt + P - 2;
+  };
+  // A is free until the transform: the enumeration's tables go there
+  for_tile_beads<FFT_THREADS>(R, tc, a.qstart, first, reinterpret_cast<int*>(A), &s_tot, scan_sh, keep, [&](int q) {
     const uint4 rec = a.qpk[q];
     int k0[3];
     T t[3];
@@ -762,45 +844,62 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
     mesh_coord<T>(rec.y, K1, k0[1], t[1]);
     mesh_coord<T>(rec.z, K2, k0[2], t[2]);
     const int ox = tile_off(k0[0], mt.x0, K0), oy = tile_off(k0[1], mt.y0, K1);
-    if (ox > nxt + P - 2 || oy > nyt + P - 2) return;
     T w[3][P], dw[P];
 #pragma unroll
     for (int d = 0; d < 3; ++d) bspline<T, P>(t[d], w[d], dw);
     const T z = (T)param_z(rec.w);
-    int g2s[P];
+    // only the stencil rows and columns inside the tile: w[0][i], w[1][k]
+    // become the weights of offsets jx0 + i, jy0 + k
+    const StencilRun rx = stencil_run<P>(ox, nxt, K0), ry = stencil_run<P>(oy, nyt, K1);
+    shift_down<T, P>(w[0], rx.j0);
+    shift_down<T, P>(w[1], ry.j0);
+    // the stencil's lowest z point (jz = P - 1) at accumulator offset k0z,
+    // point jz at k0z + P - 1 - jz
+    const int lx0 = ox - rx.j0, ly0 = oy - ry.j0;
+    // at most min(P, n) offsets per axis can be inside (uniform bounds)
+    const int mx = rx.wrap ? P : min(P, nxt), my = ry.wrap ? P : min(P, nyt);
+    int rowy[P];
+    bool oky[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int g = k0[2] - j;
-      g2s[j] = g < 0 ? g + K2 : g;
+    for (int k = 0; k < P; ++k) {
+      int ly = ly0 - k;
+      ly += ly < 0 ? K1 : 0;
+      oky[k] = k < my && k < ry.nv && ly < nyt;
+      rowy[k] = ly * KP + k0[2];
     }
-    // stencil loops unrolled so the weights stay in registers
 #pragma unroll
-    for (int jx = 0; jx < P; ++jx) {
-      int lx = ox - jx;
+    for (int i = 0; i < P; ++i) {
+      int lx = lx0 - i;
       lx += lx < 0 ? K0 : 0;
-      const T ax = z * w[0][jx];
+      if (i >= mx || i >= rx.nv || lx >= nxt) continue;
+      const T ax = z * w[0][i];
+      U* const row = acc + lx * TY * KP;
 #pragma unroll
-      for (int jy = 0; jy < P; ++jy) {
-        int ly = oy - jy;
-        ly += ly < 0 ? K1 : 0;
-        if (lx < nxt && ly < nyt) {
-          const T axy = ax * w[1][jy];
-          U* row = acc + (size_t)(lx * TY + ly) * K2;
+      for (int k = 0; k < P; ++k) {
+        if (oky[k]) {
+          const T axy = ax * w[1][k];
+          U* pt = row + rowy[k];
           if constexpr (std::is_same<T, float>::value) {
             const float axs = axy * MeshInt<float>::scale;  // exact: a power of two
 #pragma unroll
-            for (int jz = 0; jz < P; ++jz) atomicAdd(&row[g2s[jz]], (unsigned)(int)rintf(axs * w[2][jz]));
+            for (int jz = 0; jz < P; ++jz) atomicAdd(&pt[P - 1 - jz], (unsigned)(int)rintf(axs * w[2][jz]));
           } else {
 #pragma unroll
             for (int jz = 0; jz < P; ++jz) {
               const double v = (double)(axy * w[2][jz]) * qs;
-              atomicAdd(&row[g2s[jz]], (unsigned long long)(long long)llrint(v));
+              atomicAdd(&pt[P - 1 - jz], (unsigned long long)(long long)llrint(v));
             }
           }
         }
       }
     }
   });
+  // fold the points below z = 0 onto z + K2 (K2 >= 2P: no double wrap)
+  for (int e = threadIdx.x; e < NL * (P - 1); e += FFT_THREADS) {
+    const int l = e / (P - 1), j = e - l * (P - 1);
+    acc[l * KP + K2 + j] += acc[l * KP + j];
+  }
+  __syncthreads();
   if (threadIdx.x < K2) tw[threadIdx.x] = tw0;
   for (int e = threadIdx.x + FFT_THREADS; e < K2; e += FFT_THREADS) tw[e] = tws[e];
   // integer mesh -> packed lines: real point k of line l at AT[k * 2 LBP + l]
@@ -812,10 +911,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
     const int l = dk2.div(e), k = e - l * K2;
     T v = 0;
     if (l < NL) {
+      const U c = acc[l * KP + P - 1 + k];
       if constexpr (std::is_same<T, float>::value)
-        v = (float)(int)acc[e] * (1.0f / MeshInt<float>::scale);
+        v = (float)(int)c * (1.0f / MeshInt<float>::scale);
       else
-        v = (T)((double)(long long)acc[e] * inv_qs);
+        v = (T)((double)(long long)c * inv_qs);
     }
     AT[k * 2 * LBP + l] = v;
   }
@@ -851,7 +951,7 @@ template <typename T, int P>
 __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_cs[FFT_THREADS], s_cp[FFT_THREADS], s_tot, scan_sh[FFT_THREADS / 64];
+  __shared__ int s_tot, scan_sh[FFT_THREADS / 64];
   const MeshTile mt = a.tiles[blockIdx.x];
   const RepDesc& R = a.rep[mt.rep];
   const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h;
@@ -860,8 +960,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   // packed line l / 2
   const int TY = a.ty, NL = a.tx * a.ty, NP = (NL + 1) >> 1, LBP = NP + 1;
   const int nxt = mt.nxy & 0xffff, nyt = mt.nxy >> 16;
+  const int SB = tile_buf_elems(a.maxK[0], NL, P, (int)sizeof(cplx<T>));
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* B = A + (size_t)a.maxK[0] * LBP;
+  cplx<T>* B = A + SB;
   const TileCols tc = tile_columns(R, mt, P);
   const ColRun first = tile_column<FFT_THREADS>(R, tc, a.qstart, 0);
   const cplx<T>* in = reinterpret_cast<const cplx<T>*>(a.Qc) + R.cgrid_off;
@@ -910,7 +1011,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
       if (o1 >= 0) v[u][1] = in[o1];
     }
   }
-  const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[0] * LBP, a, R.tw_off[2], K2);
+  const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + SB, a, R.tw_off[2], K2);
 #pragma unroll
   for (int u = 0; u < PL; ++u)
     if (threadIdx.x + u * FFT_THREADS < ne) put(vp[u], vm[u], v[u][0], v[u][1]);
@@ -922,10 +1023,18 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   }
   __syncthreads();
   // real point g of line l at phi[g * 2 LBP + l]
-  const T* phi = reinterpret_cast<const T*>(
-      fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NP, tw, a.radix + R.rad_off[2], R.nrad[2], true));
+  const cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NP, tw, a.radix + R.rad_off[2], R.nrad[2], true);
+  const T* phi = reinterpret_cast<const T*>(res);
   const double fx = -R.lB * K0 / R.L[0], fy = -R.lB * K1 / R.L[1], fz = -R.lB * K2 / R.L[2];
-  for_tile_beads<FFT_THREADS>(R, tc, a.qstart, first, s_cs, s_cp, &s_tot, scan_sh, [&](int q) {
+  auto keep = [&](int q) {
+    const uint4 rec = a.qpk[q];
+    const int ox = tile_off((int)(((unsigned long long)rec.x * (unsigned)K0) >> 32), mt.x0, K0);
+    const int oy = tile_off((int)(((unsigned long long)rec.y * (unsigned)K1) >> 32), mt.y0, K1);
+    return ox <= nxt + P - 2 && oy <= nyt + P - 2;
+  };
+  // the buffer the transform did not end in holds the enumeration's tables
+  int* work = reinterpret_cast<int*>(res == A ? B : A);
+  for_tile_beads<FFT_THREADS>(R, tc, a.qstart, first, work, &s_tot, scan_sh, keep, [&](int q) {
     const uint4 rec = a.qpk[q];
     const int bi = a.qidx[q];
     int k0[3];
@@ -934,38 +1043,55 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
     mesh_coord<T>(rec.y, K1, k0[1], t[1]);
     mesh_coord<T>(rec.z, K2, k0[2], t[2]);
     const int ox = tile_off(k0[0], mt.x0, K0), oy = tile_off(k0[1], mt.y0, K1);
-    if (ox > nxt + P - 2 || oy > nyt + P - 2) return;
     T w[3][P], dw[3][P];
 #pragma unroll
     for (int d = 0; d < 3; ++d) bspline<T, P>(t[d], w[d], dw[d]);
-    int g2s[P];
+    // only the stencil rows and columns inside the tile: index i, k stands
+    // for offset jx0 + i, jy0 + k
+    const StencilRun rx = stencil_run<P>(ox, nxt, K0), ry = stencil_run<P>(oy, nyt, K1);
+    shift_down<T, P>(w[0], rx.j0);
+    shift_down<T, P>(dw[0], rx.j0);
+    shift_down<T, P>(w[1], ry.j0);
+    shift_down<T, P>(dw[1], ry.j0);
+    int zo[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int g = k0[2] - j;
-      g2s[j] = g < 0 ? g + K2 : g;
+      zo[j] = (g < 0 ? g + K2 : g) * 2 * LBP;
     }
+    const int lx0 = ox - rx.j0, ly0 = oy - ry.j0;
+    const int mx = rx.wrap ? P : min(P, nxt), my = ry.wrap ? P : min(P, nyt);
     T gx = 0, gy = 0, gz = 0;
     // stencil loops unrolled so the weights stay in registers
+    int rowy[P];
+    bool oky[P];
 #pragma unroll
-    for (int jx = 0; jx < P; ++jx) {
-      int lx = ox - jx;
+    for (int k = 0; k < P; ++k) {
+      int ly = ly0 - k;
+      ly += ly < 0 ? K1 : 0;
+      oky[k] = k < my && k < ry.nv && ly < nyt;
+      rowy[k] = ly;
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      int lx = lx0 - i;
       lx += lx < 0 ? K0 : 0;
+      if (i >= mx || i >= rx.nv || lx >= nxt) continue;
+      const int rowx = lx * TY;
 #pragma unroll
-      for (int jy = 0; jy < P; ++jy) {
-        int ly = oy - jy;
-        ly += ly < 0 ? K1 : 0;
-        if (lx < nxt && ly < nyt) {
-          const int l = lx * TY + ly;
+      for (int k = 0; k < P; ++k) {
+        if (oky[k]) {
+          const int l = rowx + rowy[k];
           T s0 = 0, s2 = 0;
 #pragma unroll
           for (int jz = 0; jz < P; ++jz) {
-            const T ph = phi[g2s[jz] * 2 * LBP + l];
+            const T ph = phi[zo[jz] + l];
             s0 += w[2][jz] * ph;
             s2 += dw[2][jz] * ph;
           }
-          gx += dw[0][jx] * w[1][jy] * s0;
-          gy += w[0][jx] * dw[1][jy] * s0;
-          gz += w[0][jx] * w[1][jy] * s2;
+          gx += dw[0][i] * w[1][k] * s0;
+          gy += w[0][i] * dw[1][k] * s0;
+          gz += w[0][i] * w[1][k] * s2;
         }
       }
     }
@@ -1026,14 +1152,15 @@ inline size_t lds_bytes(const PmeLaunch& a, int pass, bool fp64) {
 
 }  // namespace
 
-size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, bool fp64) {
-  // two buffers of (tx ty + 1) / 2 packed lines (+1 padding), and the twiddles
-  return (2 * (size_t)maxK2 * (size_t)((tx * ty + 1) / 2 + 1) + maxK2) * (fp64 ? 16 : 8);
+size_t pme_tile_lds_bytes(int maxK2, int tx, int ty, int order, bool fp64) {
+  // two line buffers and the twiddles
+  const int cs = fp64 ? 16 : 8;
+  return (2 * (size_t)tile_buf_elems(maxK2, tx * ty, order, cs) + maxK2) * cs;
 }
 
 void launch_spread_z(hipStream_t s, const PmeLaunch& a, bool fp64) {
   if (a.ntiles <= 0) return;
-  const size_t sh = pme_tile_lds_bytes(a.maxK[0], a.tx, a.ty, fp64);
+  const size_t sh = pme_tile_lds_bytes(a.maxK[0], a.tx, a.ty, a.order, fp64);
   const int o = std::min(std::max(a.order, 3), 8) - 3;
   if (fp64) {
     static const void* fns[6] = {(const void*)k_spread_z<double, 3>, (const void*)k_spread_z<double, 4>,
@@ -1052,7 +1179,7 @@ void launch_spread_z(hipStream_t s, const PmeLaunch& a, bool fp64) {
 
 void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64) {
   if (a.ntiles <= 0) return;
-  const size_t sh = pme_tile_lds_bytes(a.maxK[0], a.tx, a.ty, fp64);
+  const size_t sh = pme_tile_lds_bytes(a.maxK[0], a.tx, a.ty, a.order, fp64);
   const int o = std::min(std::max(a.order, 3), 8) - 3;
   if (fp64) {
     static const void* fns[6] = {(const void*)k_z_gather<double, 3>, (const void*)k_z_gather<double, 4>,
