@@ -342,25 +342,60 @@ __device__ inline void load_lines(cplx<T>* A, const cplx<T>* src, long long stri
   }
 }
 
-template <typename T>
+// load_lines with the line count NL of the LDS layout known at compile
+// time (LDS line stride NL + 1); lines count .. NL - 1 are zero.
+template <typename T, int U, int NL>
+__device__ inline void load_lines_c(cplx<T>* A, const cplx<T>* src, long long stride, int K, int count) {
+  const int n = NL * K;
+  for (int e0 = threadIdx.x; e0 < n; e0 += U * FFT_THREADS) {
+    cplx<T> v[U];
+    int k[U], l[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned e = min(e0 + u * FFT_THREADS, n - 1);
+      k[u] = (int)(e / NL);
+      l[u] = (int)(e % NL);
+      v[u] = l[u] < count ? src[(long long)k[u] * stride + l[u]] : cplx<T>{};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * FFT_THREADS < n) A[k[u] * (NL + 1) + l[u]] = v[u];
+  }
+}
+
+// y lines of a batch of kz lines at one x.  KC > 0: every replica's K1 is
+// KC and the batch holds LB lines (the plan's lines per item), so the
+// transform's stages, indices and LDS offsets are compile-time constants.
+template <typename T, int KC, int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   const LineItem it = a.items[1][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
-  const int K = R.K[1], K2h = R.K2h, K2s = R.K2s, nl = it.count, LBP = a.lb[1] + 1;
+  const int K = KC > 0 ? KC : R.K[1], K2h = R.K2h, K2s = R.K2s, nl = it.count;
+  const int LBP = KC > 0 ? LB + 1 : a.lb[1] + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[1] * LBP;
   const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[1] * LBP, a, R.tw_off[1], K);
   const int x = it.first / K2h, kz0 = it.first % K2h;
   cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)x * R.K[1] * K2s + kz0;
-  const FDiv dnl(nl);
-  load_lines<T, 8>(A, base, K2s, K, nl, LBP);
-  __syncthreads();
-  cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[1], R.nrad[1], inverse != 0);
-  for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
-    const int k = dnl.div(e), l = e - k * nl;
-    base[(long long)k * K2s + l] = res[k * LBP + l];
+  if constexpr (KC > 0) {
+    load_lines_c<T, 8, LB>(A, base, K2s, KC, nl);
+    __syncthreads();
+    const cplx<T>* res = fft_lines_c<T, KC, FFT_THREADS, LB + 1, 1, LB>(A, B, tw, inverse != 0);
+    for (int e = threadIdx.x; e < LB * KC; e += FFT_THREADS) {
+      const int k = (unsigned)e / LB, l = (unsigned)e % LB;
+      if (l < nl) base[(long long)k * K2s + l] = res[k * (LB + 1) + l];
+    }
+  } else {
+    const FDiv dnl(nl);
+    load_lines<T, 8>(A, base, K2s, K, nl, LBP);
+    __syncthreads();
+    cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[1], R.nrad[1], inverse != 0);
+    for (int e = threadIdx.x; e < nl * K; e += FFT_THREADS) {
+      const int k = dnl.div(e), l = e - k * nl;
+      base[(long long)k * K2s + l] = res[k * LBP + l];
+    }
   }
   wave_stamp(a.stamps, 1);
 }
@@ -428,39 +463,62 @@ __device__ inline cplx<T> green_apply(const RepDesc& R, const T* gf0, const T* g
   return {v.x * G, v.y * G};
 }
 
-template <typename T, bool EV>
+// x lines of a batch of kz lines at one y: transform, Green's function
+// (energy, virial), inverse transform.  KC, LB as for k_fft_y (K0 = KC).
+template <typename T, bool EV, int KC, int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[4];
   const LineItem it = a.items[2][blockIdx.x];
   const RepDesc& R = a.rep[it.rep];
-  const int K = R.K[0], K1 = R.K[1], K2h = R.K2h, K2s = R.K2s, nl = it.count, LBP = a.lb[2] + 1;
+  const int K = KC > 0 ? KC : R.K[0], K1 = R.K[1], K2h = R.K2h, K2s = R.K2s, nl = it.count;
+  const int LBP = KC > 0 ? LB + 1 : a.lb[2] + 1;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* B = A + (size_t)a.maxK[2] * LBP;
   const cplx<T>* tw = stage_twiddles<T, FFT_THREADS>(B + (size_t)a.maxK[2] * LBP, a, R.tw_off[0], K);
   const int y = it.first / K2h, kz0 = it.first % K2h;
   const long long xstride = (long long)K1 * K2s;
   cplx<T>* base = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off + (long long)y * K2s + kz0;
-  const FDiv dnl(nl);
-  load_lines<T, 8>(A, base, xstride, K, nl, LBP);
-  __syncthreads();
-  cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], false);
-  cplx<T>* other = res == A ? B : A;
-  // Green's function, energy and virial
   const T* gf = reinterpret_cast<const T*>(a.bsp);
   const T* fr = reinterpret_cast<const T*>(a.freq);
   RecipSums acc{};
-  for (int q = threadIdx.x; q < nl * K; q += FFT_THREADS) {
-    const int k = dnl.div(q), l = q - k * nl;
-    res[k * LBP + l] = green_apply<T, EV>(R, gf + R.bsp_off[0], gf + R.bsp_off[1], gf + R.bsp_off[2], fr + R.bsp_off[0],
-                                          fr + R.bsp_off[1], fr + R.bsp_off[2], k, y, kz0 + l, res[k * LBP + l], acc);
-  }
-  __syncthreads();
-  cplx<T>* fin = fft_lines<T, FFT_THREADS>(res, other, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], true);
-  for (int e2 = threadIdx.x; e2 < nl * K; e2 += FFT_THREADS) {
-    const int k = dnl.div(e2), l = e2 - k * nl;
-    base[(long long)k * xstride + l] = fin[k * LBP + l];
+  if constexpr (KC > 0) {
+    load_lines_c<T, 8, LB>(A, base, xstride, KC, nl);
+    __syncthreads();
+    cplx<T>* res = fft_lines_c<T, KC, FFT_THREADS, LB + 1, 1, LB>(A, B, tw, false);
+    cplx<T>* other = res == A ? B : A;
+    for (int q = threadIdx.x; q < LB * KC; q += FFT_THREADS) {
+      const int k = (unsigned)q / LB, l = (unsigned)q % LB;
+      if (l < nl)
+        res[k * (LB + 1) + l] = green_apply<T, EV>(R, gf + R.bsp_off[0], gf + R.bsp_off[1], gf + R.bsp_off[2],
+                                                   fr + R.bsp_off[0], fr + R.bsp_off[1], fr + R.bsp_off[2], k, y,
+                                                   kz0 + l, res[k * (LB + 1) + l], acc);
+    }
+    __syncthreads();
+    const cplx<T>* fin = fft_lines_c<T, KC, FFT_THREADS, LB + 1, 1, LB>(res, other, tw, true);
+    for (int e2 = threadIdx.x; e2 < LB * KC; e2 += FFT_THREADS) {
+      const int k = (unsigned)e2 / LB, l = (unsigned)e2 % LB;
+      if (l < nl) base[(long long)k * xstride + l] = fin[k * (LB + 1) + l];
+    }
+  } else {
+    const FDiv dnl(nl);
+    load_lines<T, 8>(A, base, xstride, K, nl, LBP);
+    __syncthreads();
+    cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], false);
+    cplx<T>* other = res == A ? B : A;
+    for (int q = threadIdx.x; q < nl * K; q += FFT_THREADS) {
+      const int k = dnl.div(q), l = q - k * nl;
+      res[k * LBP + l] = green_apply<T, EV>(R, gf + R.bsp_off[0], gf + R.bsp_off[1], gf + R.bsp_off[2],
+                                            fr + R.bsp_off[0], fr + R.bsp_off[1], fr + R.bsp_off[2], k, y, kz0 + l,
+                                            res[k * LBP + l], acc);
+    }
+    __syncthreads();
+    cplx<T>* fin = fft_lines<T, FFT_THREADS>(res, other, K, LBP, nl, tw, a.radix + R.rad_off[0], R.nrad[0], true);
+    for (int e2 = threadIdx.x; e2 < nl * K; e2 += FFT_THREADS) {
+      const int k = dnl.div(e2), l = e2 - k * nl;
+      base[(long long)k * xstride + l] = fin[k * LBP + l];
+    }
   }
   if (EV) {
     double v[7] = {acc.e, acc.w[0], acc.w[1], acc.w[2], acc.w[3], acc.w[4], acc.w[5]};
@@ -1196,16 +1254,34 @@ void launch_z_gather(hipStream_t s, const PmeLaunch& a, bool fp64) {
   }
 }
 
+// the compile-time line passes: every replica's K0 = K1 = KC (plane_k) and
+// the plan's lines per item equal LINE_LB
+constexpr int LINE_LB = 8;
+
+template <typename T, int KC>
+void fft_y_k(hipStream_t s, const PmeLaunch& a, size_t sh, bool inverse) {
+  allow_lds((const void*)k_fft_y<T, KC, LINE_LB>, sh);
+  hipLaunchKernelGGL((k_fft_y<T, KC, LINE_LB>), dim3(a.nitems[1]), dim3(FFT_THREADS), sh, s, a, (int)inverse);
+}
+
+template <typename T>
+void fft_y_t(hipStream_t s, const PmeLaunch& a, size_t sh, bool inverse) {
+  const bool c = a.lb[1] == LINE_LB && a.maxK[1] == a.plane_k;
+  if (c && a.plane_k == 256)
+    fft_y_k<T, 256>(s, a, sh, inverse);
+  else if (c && a.plane_k == 128)
+    fft_y_k<T, 128>(s, a, sh, inverse);
+  else
+    fft_y_k<T, 0>(s, a, sh, inverse);
+}
+
 void launch_fft_y(hipStream_t s, const PmeLaunch& a, bool fp64, bool inverse) {
   if (a.nitems[1] <= 0) return;
-  size_t sh = lds_bytes(a, 1, fp64);
-  if (fp64) {
-    allow_lds((const void*)k_fft_y<double>, sh);
-    hipLaunchKernelGGL(k_fft_y<double>, dim3(a.nitems[1]), dim3(FFT_THREADS), sh, s, a, (int)inverse);
-  } else {
-    allow_lds((const void*)k_fft_y<float>, sh);
-    hipLaunchKernelGGL(k_fft_y<float>, dim3(a.nitems[1]), dim3(FFT_THREADS), sh, s, a, (int)inverse);
-  }
+  const size_t sh = lds_bytes(a, 1, fp64);
+  if (fp64)
+    fft_y_t<double>(s, a, sh, inverse);
+  else
+    fft_y_t<float>(s, a, sh, inverse);
 }
 
 int pme_plane_threads(int plane_elems) {
@@ -1255,26 +1331,36 @@ void launch_fft_yx_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev) {
   }
 }
 
+template <typename T, bool EV, int KC>
+void fft_x_conv_k(hipStream_t s, const PmeLaunch& a, size_t sh) {
+  allow_lds((const void*)k_fft_x_conv<T, EV, KC, LINE_LB>, sh);
+  hipLaunchKernelGGL((k_fft_x_conv<T, EV, KC, LINE_LB>), dim3(a.nitems[2]), dim3(FFT_THREADS), sh, s, a);
+}
+
+template <typename T, bool EV>
+void fft_x_conv_t(hipStream_t s, const PmeLaunch& a, size_t sh) {
+  const bool c = a.lb[2] == LINE_LB && a.maxK[2] == a.plane_k;
+  if (c && a.plane_k == 256)
+    fft_x_conv_k<T, EV, 256>(s, a, sh);
+  else if (c && a.plane_k == 128)
+    fft_x_conv_k<T, EV, 128>(s, a, sh);
+  else
+    fft_x_conv_k<T, EV, 0>(s, a, sh);
+}
+
 void launch_fft_x_conv(hipStream_t s, const PmeLaunch& a, bool fp64, bool ev) {
   if (a.nitems[2] <= 0) return;
-  size_t sh = lds_bytes(a, 2, fp64);
-  dim3 g(a.nitems[2]), b(FFT_THREADS);
+  const size_t sh = lds_bytes(a, 2, fp64);
   if (fp64) {
-    if (ev) {
-      allow_lds((const void*)k_fft_x_conv<double, true>, sh);
-      hipLaunchKernelGGL((k_fft_x_conv<double, true>), g, b, sh, s, a);
-    } else {
-      allow_lds((const void*)k_fft_x_conv<double, false>, sh);
-      hipLaunchKernelGGL((k_fft_x_conv<double, false>), g, b, sh, s, a);
-    }
+    if (ev)
+      fft_x_conv_t<double, true>(s, a, sh);
+    else
+      fft_x_conv_t<double, false>(s, a, sh);
   } else {
-    if (ev) {
-      allow_lds((const void*)k_fft_x_conv<float, true>, sh);
-      hipLaunchKernelGGL((k_fft_x_conv<float, true>), g, b, sh, s, a);
-    } else {
-      allow_lds((const void*)k_fft_x_conv<float, false>, sh);
-      hipLaunchKernelGGL((k_fft_x_conv<float, false>), g, b, sh, s, a);
-    }
+    if (ev)
+      fft_x_conv_t<float, true>(s, a, sh);
+    else
+      fft_x_conv_t<float, false>(s, a, sh);
   }
 }
 

@@ -90,6 +90,16 @@ def test_mesh_tile_shapes(precision, tile):
                               gather_tile_y=tile[3]))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("grid", [(128, 128, 24), (128, 128, 27), (96, 128, 24)])
+def test_line_batched_mesh_passes(precision, grid):
+    # planes too large for the fused y/x pass: the line-batched y and x
+    # passes, with the transforms fixed at compile time when K0 = K1 = 128
+    # (both precisions), at run time otherwise; odd and even z lengths
+    w = W.small_bulk(N=800, seed=21, charged_frac=0.4, box=(7.4, 7.9, 6.8), rc=2.5, grid=grid)
+    _check(w, precision)
+
+
 @pytest.mark.parametrize("order", [3, 6, 8])
 def test_orders_and_odd_mesh(order):
     w = W.small_bulk(N=512, seed=5, charged_frac=0.5, a_types=(0.45,), box=(6.0, 6.0, 6.0), rc=2.5,
