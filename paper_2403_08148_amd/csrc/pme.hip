@@ -537,13 +537,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
 // one layout, (y, x) at y*LY + x (LY = K0 + 1): the y lines are transformed
 // with x interleaved, the x lines with their points consecutive.
 template <typename T, bool EV, int KC, int NT>
-__global__ __launch_bounds__(NT) void k_fft_yx_conv(PmeLaunch a) {
-  wave_stamp(a.stamps, 0);
+__device__ __attribute__((always_inline)) inline void yx_plane(const PmeLaunch& a, const LineItem& it,
+                                                                const RepDesc& R) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[NT / 64];
-  const LineItem it = a.items[0][blockIdx.x];
-  const RepDesc& R = a.rep[it.rep];
-  // KC > 0: every replica's plane is KC x KC (compile-time transforms)
+  // KC > 0: this plane is KC x KC (compile-time transforms)
   const int K0 = KC > 0 ? KC : R.K[0], K1 = KC > 0 ? KC : R.K[1], K2h = R.K2h;
   const int kz = it.first;
   const int LY = K0 + 1;
@@ -676,6 +674,30 @@ __global__ __launch_bounds__(NT) void k_fft_yx_conv(PmeLaunch a) {
     for (int k = 0; k < 7; ++k) {
       double t = block_sum_fft<NT>(v[k], sh);
       if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
+    }
+  }
+}
+
+// KC > 0: every replica's plane is KC x KC.  KC == 0: each workgroup takes
+// the compile-time transforms of its replica's plane when that is square
+// with one of the sides the batched workloads use, else the run-time plan.
+template <typename T, bool EV, int KC, int NT>
+__global__ __launch_bounds__(NT) void k_fft_yx_conv(PmeLaunch a) {
+  wave_stamp(a.stamps, 0);
+  const LineItem it = a.items[0][blockIdx.x];
+  const RepDesc& R = a.rep[it.rep];
+  if constexpr (KC > 0) {
+    yx_plane<T, EV, KC, NT>(a, it, R);
+  } else {
+    switch (R.K[0] == R.K[1] ? R.K[0] : 0) {
+      case 16: yx_plane<T, EV, 16, NT>(a, it, R); break;
+      case 18: yx_plane<T, EV, 18, NT>(a, it, R); break;
+      case 24: yx_plane<T, EV, 24, NT>(a, it, R); break;
+      case 27: yx_plane<T, EV, 27, NT>(a, it, R); break;
+      case 32: yx_plane<T, EV, 32, NT>(a, it, R); break;
+      case 36: yx_plane<T, EV, 36, NT>(a, it, R); break;
+      case 48: yx_plane<T, EV, 48, NT>(a, it, R); break;
+      default: yx_plane<T, EV, 0, NT>(a, it, R); break;
     }
   }
   wave_stamp(a.stamps, 1);
