@@ -869,6 +869,20 @@ __device__ inline StencilRun stencil_run(int o, int n, int K) {
   return {0, P, true};
 }
 
+// The packed z lines of a tile pass (np lines of K2 points, line stride
+// LBP = np + 1): compile-time transforms for the z lengths and tile shapes
+// of the bulk workloads (64-point lines in 4 x 4 tiles, 256-point lines in
+// 4 x 4 and 8 x 4 tiles), the run-time plan otherwise.
+template <typename T>
+__device__ __attribute__((always_inline)) inline cplx<T>* z_lines(cplx<T>* A, cplx<T>* B, int K2, int np,
+                                                                  const cplx<T>* tw, const int* rad, int nrad,
+                                                                  bool inverse) {
+  if (K2 == 64 && np == 8) return fft_lines_c<T, 64, FFT_THREADS, 9, 1, 8>(A, B, tw, inverse);
+  if (K2 == 256 && np == 8) return fft_lines_c<T, 256, FFT_THREADS, 9, 1, 8>(A, B, tw, inverse);
+  if (K2 == 256 && np == 16) return fft_lines_c<T, 256, FFT_THREADS, 17, 1, 16>(A, B, tw, inverse);
+  return fft_lines<T, FFT_THREADS>(A, B, K2, np + 1, np, tw, rad, nrad, inverse);
+}
+
 // Offset of a stencil base point from the tile origin (mod K); the bead
 // meets the tile iff it is at most n + P - 2.
 __device__ inline int tile_off(int k0, int t0, int K) {
@@ -1000,7 +1014,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
     AT[k * 2 * LBP + l] = v;
   }
   __syncthreads();
-  const cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NP, tw, a.radix + R.rad_off[2], R.nrad[2], false);
+  const cplx<T>* res = z_lines<T>(A, B, K2, NP, tw, a.radix + R.rad_off[2], R.nrad[2], false);
   cplx<T>* out = reinterpret_cast<cplx<T>*>(a.Qc) + R.cgrid_off;
   const FDiv dnl(NL), dty(TY);
   for (int e = threadIdx.x; e < NL * K2h; e += FFT_THREADS) {
@@ -1103,7 +1117,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   }
   __syncthreads();
   // real point g of line l at phi[g * 2 LBP + l]
-  const cplx<T>* res = fft_lines<T, FFT_THREADS>(A, B, K2, LBP, NP, tw, a.radix + R.rad_off[2], R.nrad[2], true);
+  const cplx<T>* res = z_lines<T>(A, B, K2, NP, tw, a.radix + R.rad_off[2], R.nrad[2], true);
   const T* phi = reinterpret_cast<const T*>(res);
   const double fx = -R.lB * K0 / R.L[0], fy = -R.lB * K1 / R.L[1], fz = -R.lB * K2 / R.L[2];
   auto keep = [&](int q) {
