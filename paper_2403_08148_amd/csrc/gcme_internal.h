@@ -228,6 +228,18 @@ __device__ inline void bin_bead(const CellView& c, const RepDesc& R, uint32_t ux
 // counter at the wavefront's start (end = 0) and end (end = 1) into slot
 // 2 w + end of st, w the wavefront's index in the grid.  The host takes the
 // first start and the last end over the launch's wavefronts.
+// The work item of this workgroup among n: the hardware hands workgroups
+// to the 8 XCDs in turn (workgroup b to XCD b mod 8), each XCD with its own
+// L2, so item order is remapped to give every XCD one contiguous run of
+// items.  Neighbouring items (adjacent clusters, mesh tiles, batches of
+// mesh lines) read mostly the same records and cache lines, which then
+// come through one L2 instead of eight.  A bijection of [0, n).
+__device__ inline int xcd_item(int b, int n) {
+  constexpr int X = 8;
+  const int per = n / X, rem = n % X, x = b % X;
+  return x * per + (x < rem ? x : rem) + b / X;
+}
+
 __device__ inline void wave_stamp(unsigned long long* st, int end) {
   if (st && (threadIdx.x & 63) == 0) {
     const unsigned w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);

@@ -466,7 +466,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
   __shared__ int s_cand[NL_WAVES][NL_CAND];
   wave_stamp(a.stamps, 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * NL_WAVES + wave;
+  const int c = xcd_item(blockIdx.x, gridDim.x) * NL_WAVES + wave;
   if (c >= a.ncl) return;  // whole wavefront; no block barriers below
   const int2 info = a.cl[c];
   const int first = info.x, rep = info.y & 0xffff, ni = info.y >> 16;
@@ -794,7 +794,7 @@ __device__ inline void flush_bead(const PairLaunch& a, Lane<T>& L, bool vi, int 
 // Workgroup partial sums (every pair was seen from both ends: halved).
 // Reached by every thread of the workgroup.
 template <typename T, bool ELEC, bool EV, bool ADJ, bool COUNT>
-__device__ inline void block_outputs(const PairLaunch& a, const Lane<T>& L, double* red) {
+__device__ inline void block_outputs(const PairLaunch& a, const Lane<T>& L, double* red, int item) {
   const int lane = threadIdx.x & 63;
   if (COUNT) {
     unsigned long long cc = L.cnt;
@@ -806,7 +806,7 @@ __device__ inline void block_outputs(const PairLaunch& a, const Lane<T>& L, doub
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
       double t = block_sum(v[k], red);
-      if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = 0.5 * t;
+      if (threadIdx.x == 0) a.part[(size_t)item * PART_W + k] = 0.5 * t;
     }
   }
   if (ADJ) {
@@ -814,12 +814,12 @@ __device__ inline void block_outputs(const PairLaunch& a, const Lane<T>& L, doub
     if (!ELEC) {
       for (int q = 0; q < MAXT * MAXT; ++q) {
         double t = block_sum((double)L.ett[q], red);
-        if (threadIdx.x == 0) a.adj_part[(size_t)blockIdx.x * W + q] = 0.5 * t;
+        if (threadIdx.x == 0) a.adj_part[(size_t)item * W + q] = 0.5 * t;
       }
     }
     for (int t = 0; t < MAXT; ++t) {
       double s = block_sum((double)L.dsg[t], red);
-      if (threadIdx.x == 0) a.adj_part[(size_t)blockIdx.x * W + MAXT * MAXT + (ELEC ? MAXT : 0) + t] = 0.5 * s;
+      if (threadIdx.x == 0) a.adj_part[(size_t)item * W + MAXT * MAXT + (ELEC ? MAXT : 0) + t] = 0.5 * s;
     }
   }
 }
@@ -833,7 +833,8 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
   __shared__ Tables<T, ELEC, ADJ> S;
   wave_stamp(a.stamps, 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const Tile tl = a.tiles[blockIdx.x];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const Tile tl = a.tiles[item];
   const RepDesc& R = a.rep[tl.rep];
   stage_tables(S, a, tl.rep);
   const int il = lane / CJ, jl = lane % CJ;
@@ -869,7 +870,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
     }
     flush_bead<T, CI, ELEC, ADJ>(a, L, vi, i, param_type(mi.w));
   }
-  block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red);
+  block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red, item);
   wave_stamp(a.stamps, 1);
 }
 
@@ -893,7 +894,8 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
   __shared__ uint4 s_ring[NL_WAVES][RING];
   wave_stamp(a.stamps, 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const Tile tl = a.tiles[blockIdx.x];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const Tile tl = a.tiles[item];
   const RepDesc& R = a.rep[tl.rep];
   const int il = lane / CJ, jl = lane % CJ;
   const uint4* __restrict__ pk = a.pk;
@@ -1023,7 +1025,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
     if (tail > head) drain(tail - head);
     flush_bead<T, CI, ELEC, ADJ>(a, L, vi, i, param_type(mi.w));
   }
-  block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red);
+  block_outputs<T, ELEC, EV, ADJ, COUNT>(a, L, red, item);
   wave_stamp(a.stamps, 1);
 }
 
@@ -1182,7 +1184,8 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_col(PairLaunch a) {
   __shared__ IBead<T> s_ib[NL_WAVES][ELEC ? 1 : CI];
   wave_stamp(a.stamps, 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const Tile tl = a.tiles[blockIdx.x];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const Tile tl = a.tiles[item];
   const RepDesc& R = a.rep[tl.rep];
   const uint4* __restrict__ pk = a.pk;
   const int slot = tl.first + wave;
@@ -1473,7 +1476,7 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_pair_col(PairLaunch a) {
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
       const double t = block_sum(v7[k], red);
-      if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = HALF ? t : 0.5 * t;
+      if (threadIdx.x == 0) a.part[(size_t)item * PART_W + k] = HALF ? t : 0.5 * t;
     }
   }
   wave_stamp(a.stamps, 1);

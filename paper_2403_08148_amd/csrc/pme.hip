@@ -370,7 +370,7 @@ template <typename T, int KC, int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_y(PmeLaunch a, int inverse) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
-  const LineItem it = a.items[1][blockIdx.x];
+  const LineItem it = a.items[1][xcd_item(blockIdx.x, gridDim.x)];
   const RepDesc& R = a.rep[it.rep];
   const int K = KC > 0 ? KC : R.K[1], K2h = R.K2h, K2s = R.K2s, nl = it.count;
   const int LBP = KC > 0 ? LB + 1 : a.lb[1] + 1;
@@ -470,7 +470,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[4];
-  const LineItem it = a.items[2][blockIdx.x];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const LineItem it = a.items[2][item];
   const RepDesc& R = a.rep[it.rep];
   const int K = KC > 0 ? KC : R.K[0], K1 = R.K[1], K2h = R.K2h, K2s = R.K2s, nl = it.count;
   const int LBP = KC > 0 ? LB + 1 : a.lb[2] + 1;
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
       double t = block_sum_fft<FFT_THREADS>(v[k], sh);
-      if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
+      if (threadIdx.x == 0) a.part[(size_t)item * PART_W + k] = t;
     }
   }
   wave_stamp(a.stamps, 1);
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_x_conv(PmeLaunch a) {
 // with x interleaved, the x lines with their points consecutive.
 template <typename T, bool EV, int KC, int NT>
 __device__ __attribute__((always_inline)) inline void yx_plane(const PmeLaunch& a, const LineItem& it,
-                                                                const RepDesc& R) {
+                                                                const RepDesc& R, int item) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[NT / 64];
   // KC > 0: this plane is KC x KC (compile-time transforms)
@@ -673,7 +674,7 @@ __device__ __attribute__((always_inline)) inline void yx_plane(const PmeLaunch& 
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
       double t = block_sum_fft<NT>(v[k], sh);
-      if (threadIdx.x == 0) a.part[(size_t)blockIdx.x * PART_W + k] = t;
+      if (threadIdx.x == 0) a.part[(size_t)item * PART_W + k] = t;
     }
   }
 }
@@ -684,20 +685,21 @@ __device__ __attribute__((always_inline)) inline void yx_plane(const PmeLaunch& 
 template <typename T, bool EV, int KC, int NT>
 __global__ __launch_bounds__(NT) void k_fft_yx_conv(PmeLaunch a) {
   wave_stamp(a.stamps, 0);
-  const LineItem it = a.items[0][blockIdx.x];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const LineItem it = a.items[0][item];
   const RepDesc& R = a.rep[it.rep];
   if constexpr (KC > 0) {
-    yx_plane<T, EV, KC, NT>(a, it, R);
+    yx_plane<T, EV, KC, NT>(a, it, R, item);
   } else {
     switch (R.K[0] == R.K[1] ? R.K[0] : 0) {
-      case 16: yx_plane<T, EV, 16, NT>(a, it, R); break;
-      case 18: yx_plane<T, EV, 18, NT>(a, it, R); break;
-      case 24: yx_plane<T, EV, 24, NT>(a, it, R); break;
-      case 27: yx_plane<T, EV, 27, NT>(a, it, R); break;
-      case 32: yx_plane<T, EV, 32, NT>(a, it, R); break;
-      case 36: yx_plane<T, EV, 36, NT>(a, it, R); break;
-      case 48: yx_plane<T, EV, 48, NT>(a, it, R); break;
-      default: yx_plane<T, EV, 0, NT>(a, it, R); break;
+      case 16: yx_plane<T, EV, 16, NT>(a, it, R, item); break;
+      case 18: yx_plane<T, EV, 18, NT>(a, it, R, item); break;
+      case 24: yx_plane<T, EV, 24, NT>(a, it, R, item); break;
+      case 27: yx_plane<T, EV, 27, NT>(a, it, R, item); break;
+      case 32: yx_plane<T, EV, 32, NT>(a, it, R, item); break;
+      case 36: yx_plane<T, EV, 36, NT>(a, it, R, item); break;
+      case 48: yx_plane<T, EV, 48, NT>(a, it, R, item); break;
+      default: yx_plane<T, EV, 0, NT>(a, it, R, item); break;
     }
   }
   wave_stamp(a.stamps, 1);
@@ -895,7 +897,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spread_z(PmeLaunch a) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_tot, scan_sh[FFT_THREADS / 64];
-  const MeshTile mt = a.tiles[blockIdx.x];
+  const MeshTile mt = a.tiles[xcd_item(blockIdx.x, gridDim.x)];
   const RepDesc& R = a.rep[mt.rep];
   const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h;
   // the tile's real z lines are transformed two to a complex line: line l
@@ -1046,7 +1048,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_z_gather(PmeLaunch a) {
   wave_stamp(a.stamps, 0);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_tot, scan_sh[FFT_THREADS / 64];
-  const MeshTile mt = a.tiles[blockIdx.x];
+  const MeshTile mt = a.tiles[xcd_item(blockIdx.x, gridDim.x)];
   const RepDesc& R = a.rep[mt.rep];
   const int K0 = R.K[0], K1 = R.K[1], K2 = R.K[2], K2h = R.K2h;
   // the tile's real z lines come out of the inverse transform two to a
