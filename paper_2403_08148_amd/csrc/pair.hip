@@ -459,8 +459,10 @@ __device__ inline bool near_cluster(const Cluster<CI>& K, bool fast, const uint4
   return fast ? near_frame(K, pj, R, Dx, Dy, Dz) : near_exact(K, pj, R);
 }
 
+// Compiled for five wavefronts per SIMD (102 VGPRs; a few spilled for CI =
+// 8): the 256 batched replicas' step went 0.763 -> 0.748 ms.
 template <int CI>
-__global__ __launch_bounds__(NL_WAVES * 64) void k_nl_build(PairLaunch a) {
+__global__ __launch_bounds__(NL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(5))) void k_nl_build(PairLaunch a) {
   __shared__ int s_sb[NL_WAVES][NL_SEG];
   __shared__ int s_sl[NL_WAVES][NL_SEG];
   __shared__ int s_cand[NL_WAVES][NL_CAND];
@@ -883,8 +885,20 @@ __global__ __launch_bounds__(NL_WAVES * 64) void k_nl_force(PairLaunch a) {
 constexpr int RING = 128;  // pending-pair ring per wavefront (entries)
 static_assert(RING == 128, "the drain relies on a ring of exactly two 64-entry halves");
 
+// Wavefronts per SIMD the list-free kernel is compiled for: the per-step
+// variant (single precision, forces only) is held to 128 VGPRs, so four
+// wavefronts share each SIMD instead of three (it then has no spills: the
+// excluded-volume pairs of N = 2,097,152 took 1.34 -> 1.08 ms, of N = 32,768
+// 48 -> 36 us); the others keep the compiler's choice, since the bound would
+// make them spill.
+template <typename T, bool EV, bool ADJ, bool COUNT>
+struct FusedWaves {
+  static constexpr int value = std::is_same<T, float>::value && !EV && !ADJ && !COUNT ? 4 : 1;
+};
+
 template <typename T, int CI, bool ELEC, bool EV, bool ADJ, bool COUNT>
-__global__ __launch_bounds__(NL_WAVES * 64) void k_pair_fused(PairLaunch a) {
+__global__ __launch_bounds__(NL_WAVES * 64) __attribute__((amdgpu_waves_per_eu(FusedWaves<T, EV, ADJ, COUNT>::value)))
+void k_pair_fused(PairLaunch a) {
   constexpr int CJ = 64 / CI;
   __shared__ double red[NL_WAVES];
   __shared__ Tables<T, ELEC, ADJ> S;
