@@ -100,6 +100,16 @@ def test_line_batched_mesh_passes(precision, grid):
     _check(w, precision)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("order,tile", [(3, (2, 4)), (8, (4, 2)), (6, (3, 5))])
+def test_line_layout_orders_and_gather_tiles(precision, order, tile):
+    # a mesh in line layout (its plane does not fit LDS) with other orders,
+    # an odd z length and gather tiles ragged at the mesh edges
+    w = W.small_bulk(N=700, seed=23, charged_frac=0.4, box=(7.4, 7.9, 6.8), rc=2.5, grid=(96, 128, 27),
+                     order=order)
+    _check(w, precision, dict(gather_tile_x=tile[0], gather_tile_y=tile[1]))
+
+
 @pytest.mark.parametrize("order", [3, 6, 8])
 def test_orders_and_odd_mesh(order):
     w = W.small_bulk(N=512, seed=5, charged_frac=0.5, a_types=(0.45,), box=(6.0, 6.0, 6.0), rc=2.5,
