@@ -53,7 +53,7 @@ FLOP_PER_ELEC_PAIR = 35
 # beat it), fixed so that every run, and the kernel traces under profiles/,
 # time the same kernels.
 DEFAULT_TUNING = {
-    "bulk_N32768": "3,8,4,3,1",
+    "bulk_N32768": "3,8,4,3,2",
     "bulk_N2097152": "2,8,8,1,0,4,4,8,4",
     "batched_256": "2,8,4,1,3,16,8,16,8",
 }
