@@ -53,6 +53,9 @@ __global__ void k_bin(StateView A, const RepDesc* __restrict__ rep, CellView c, 
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PER_THREAD = 4;
 constexpr int SCAN_BLOCK = SCAN_THREADS * SCAN_PER_THREAD;
+// up to this many scan blocks, each adds up the block sums before it itself
+// (at most 2 SCAN_SUMS_MAX ints per block) instead of a k_scan_top launch
+constexpr int SCAN_SUMS_MAX = 1024;
 
 // Inclusive scan of one int per thread over a block of NT threads (a
 // multiple of 64, at most 1024); sh holds NT / 64 ints.
@@ -184,10 +187,33 @@ __global__ void k_scan_top(CellView c, int nb) {
   }
 }
 
+// Last pass: each block's scan plus its offset.  With SUMS the block adds up
+// the block sums before it itself (the raw ones of k_scan_reduce; cheap
+// while there are few blocks), writes the totals from the last block and
+// advances the step counter, so that k_scan_top is not launched; otherwise
+// k_scan_top has turned the block sums into offsets.
+template <bool SUMS>
 __global__ void k_scan_apply(CellView c, int nb) {
   __shared__ int sh[8];
+  __shared__ int off_sh[2];
   int b = blockIdx.x;
   int base = b * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
+  if constexpr (SUMS) {
+    if (c.step && b == 0 && threadIdx.x == 0) *c.step += 1ULL;
+    int s0 = 0, s1 = 0;
+    for (int k = threadIdx.x; k < b; k += SCAN_THREADS) {
+      s0 += c.bsum[k];
+      s1 += c.bsum[nb + k];
+    }
+    const int t0 = block_incl_scan<SCAN_THREADS>(s0, sh);
+    __syncthreads();
+    const int t1 = block_incl_scan<SCAN_THREADS>(s1, sh);
+    if (threadIdx.x == SCAN_THREADS - 1) {
+      off_sh[0] = t0;
+      off_sh[1] = t1;
+    }
+    __syncthreads();
+  }
   for (int arr = 0; arr < 2; ++arr) {
     const int* cnt = arr == 0 ? c.counts : c.qcounts;
     int* st = arr == 0 ? c.start : c.qstart;
@@ -200,7 +226,9 @@ __global__ void k_scan_apply(CellView c, int nb) {
       tot += v[k];
     }
     int inc = block_incl_scan<SCAN_THREADS>(tot, sh);
-    int run = c.bsum[arr * nb + b] + inc - tot;
+    const int off = SUMS ? off_sh[arr] : c.bsum[arr * nb + b];
+    if (SUMS && b == nb - 1 && threadIdx.x == SCAN_THREADS - 1) st[c.ncells] = off + inc;
+    int run = off + inc - tot;
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k) {
       int i = base + k;
@@ -411,8 +439,12 @@ void launch_scan(hipStream_t s, CellView c) {
   }
   int nb = nblk(c.ncells, SCAN_BLOCK);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, c, nb);
+  if (nb <= SCAN_SUMS_MAX) {
+    hipLaunchKernelGGL(k_scan_apply<true>, dim3(nb), dim3(SCAN_THREADS), 0, s, c, nb);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, c, nb);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_THREADS), 0, s, c, nb);
+  hipLaunchKernelGGL(k_scan_apply<false>, dim3(nb), dim3(SCAN_THREADS), 0, s, c, nb);
 }
 
 void launch_scatter(hipStream_t s, CellView c, int N) {
