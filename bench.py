@@ -413,7 +413,7 @@ def extra_workloads(w):
         if prec == "mixed":
             tun = apply_tuning(eng, DEFAULT_TUNING["bulk_N2097152"])
         fr[prec] = forces(eng)
-        ms = time_steps(eng, 10, 3)
+        ms = time_steps(eng, 40, 5)
         pairs = eng.count_pairs()
         res[prec] = {"ms_per_step": ms, "pair_interactions_per_s": pairs * 1000.0 / ms,
                      "ns_per_day": 1000.0 / ms * w4.dt * TAU_PS * 86400.0 / 1000.0, "pairs_within_cutoff": pairs,
